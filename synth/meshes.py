@@ -1,0 +1,265 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module only builds *inputs*: polygonal meshes of the unit square or of a
+basin section (vertex coordinates, CCW vertex lists, a fluid/solid flag per cell)
+and piecewise-constant material fields.  It holds none of the discretisation's
+arithmetic (no bases, no quadrature, no operators), so that both the FP64
+oracle and the HIP path can consume the very same meshes.
+
+Mesh conventions (paper Sec. 3.1): cells are polygons with planar faces aligned
+with the fluid/solid partition; hanging nodes are kept as ordinary polygon
+vertices, so a square next to two refined squares becomes a pentagon and a
+triangle next to one becomes a quadrilateral.
+
+Returned meshes are dicts with
+    xy        float64 [n_vertices, 2]
+    cell_ptr  int32   [n_cells + 1]   CSR offsets into cell_vtx
+    cell_vtx  int32   [cell_ptr[-1]]  counter-clockwise vertex ids
+    medium    uint8   [n_cells]       0 = fluid (acoustic), 1 = solid (elastic)
+and, after ``with_materials``, rho, a, b (float64 [n_cells]): fluid a = c
+(sound speed), b unused (0); solid a = lambda, b = mu.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+FLUID = 0
+SOLID = 1
+
+
+def _lattice_mesh(nx, ny, x0, x1, y0, y1, refine, p_split, rng):
+    """Build a 2:1 refined square lattice, optionally split into triangles.
+
+    The lattice works in integer half-step coordinates so that the midpoint of
+    any coarse edge is an exact lattice point.  ``refine`` is a bool array
+    [nx, ny] (coarse square (i, j) refined into four children) or None.
+    Each leaf square is kept with probability 1 - p_split, otherwise it is cut
+    along one of its two diagonals, chosen at random.
+    """
+    if refine is None:
+        refine = np.zeros((nx, ny), dtype=bool)
+    hx = (x1 - x0) / nx
+    hy = (y1 - y0) / ny
+    # leaf squares in half-step lattice coordinates: (I, J, size) with size 1 or 2
+    leaves = []
+    for j in range(ny):
+        for i in range(nx):
+            if refine[i, j]:
+                for b in (0, 1):
+                    for a in (0, 1):
+                        leaves.append((2 * i + a, 2 * j + b, 1))
+            else:
+                leaves.append((2 * i, 2 * j, 2))
+    nl = len(leaves)
+    split_u = rng.random(nl) if p_split > 0 else np.ones(nl)
+    diag_u = rng.random(nl) if p_split > 0 else np.zeros(nl)
+    polys = []
+    for idx, (I, J, s) in enumerate(leaves):
+        c00, c10, c11, c01 = (I, J), (I + s, J), (I + s, J + s), (I, J + s)
+        if split_u[idx] < p_split:
+            if diag_u[idx] < 0.5:   # diagonal c00 - c11
+                polys.append([c00, c10, c11])
+                polys.append([c00, c11, c01])
+            else:                   # diagonal c10 - c01
+                polys.append([c00, c10, c01])
+                polys.append([c10, c11, c01])
+        else:
+            polys.append([c00, c10, c11, c01])
+    used = set()
+    for P in polys:
+        used.update(P)
+    # insert hanging nodes: used lattice points strictly inside axis-aligned edges of length 2
+    cells = []
+    for P in polys:
+        out = []
+        n = len(P)
+        for t in range(n):
+            a = P[t]
+            b = P[(t + 1) % n]
+            out.append(a)
+            dI, dJ = b[0] - a[0], b[1] - a[1]
+            if (abs(dI) == 2 and dJ == 0) or (abs(dJ) == 2 and dI == 0):
+                m = (a[0] + dI // 2, a[1] + dJ // 2)
+                if m in used:
+                    out.append(m)
+        cells.append(out)
+    ids = {}
+    order = sorted(used, key=lambda q: (q[1], q[0]))
+    for q in order:
+        ids[q] = len(ids)
+    xy = np.empty((len(order), 2))
+    for q, v in ids.items():
+        xy[v, 0] = x0 + q[0] * hx / 2
+        xy[v, 1] = y0 + q[1] * hy / 2
+    cell_ptr = np.zeros(len(cells) + 1, dtype=np.int32)
+    cell_ptr[1:] = np.cumsum([len(c) for c in cells])
+    cell_vtx = np.fromiter((ids[q] for c in cells for q in c), dtype=np.int32,
+                           count=int(cell_ptr[-1]))
+    return dict(xy=xy, cell_ptr=cell_ptr, cell_vtx=cell_vtx, h=hx)
+
+
+def _barycentres(mesh):
+    xy, ptr, vtx = mesh["xy"], mesh["cell_ptr"], mesh["cell_vtx"]
+    cnt = np.diff(ptr)
+    sx = np.add.reduceat(xy[vtx, 0], ptr[:-1])
+    sy = np.add.reduceat(xy[vtx, 1], ptr[:-1])
+    return np.stack([sx / cnt, sy / cnt], axis=1)   # vertex average: only used to classify media
+
+
+def unit_square(n, p_split=0.0, seed=0, interface_y=0.5, refine=None):
+    """n x n squares on [0,1]^2, solid below y = interface_y, fluid above.
+
+    ``p_split`` = probability that a square is cut into two triangles (the
+    hybrid meshes of the benchmark workloads use 0.5).  ``refine`` is an
+    optional [n, n] bool mask of squares refined 2:1 (hanging nodes).
+    """
+    rng = np.random.default_rng(seed)
+    m = _lattice_mesh(n, n, 0.0, 1.0, 0.0, 1.0, refine, p_split, rng)
+    bc = _barycentres(m)
+    m["medium"] = np.where(bc[:, 1] > interface_y, FLUID, SOLID).astype(np.uint8)
+    return m
+
+
+def single_medium(n, medium, p_split=0.0, seed=0, refine=None):
+    """n x n squares on [0,1]^2 filled with one medium (pure acoustic / elastic)."""
+    rng = np.random.default_rng(seed)
+    m = _lattice_mesh(n, n, 0.0, 1.0, 0.0, 1.0, refine, p_split, rng)
+    m["medium"] = np.full(len(m["cell_ptr"]) - 1, medium, dtype=np.uint8)
+    return m
+
+
+def bilayer_vertical(n, p_split=0.0, seed=0):
+    """The CFL test geometry: solid (-1,0)x(0,1), fluid (0,1)x(0,1), interface x = 0.
+
+    Uses 2n x n squares of side 1/n.
+    """
+    rng = np.random.default_rng(seed)
+    m = _lattice_mesh(2 * n, n, -1.0, 1.0, 0.0, 1.0, None, p_split, rng)
+    bc = _barycentres(m)
+    m["medium"] = np.where(bc[:, 0] > 0.0, FLUID, SOLID).astype(np.uint8)
+    return m
+
+
+def with_materials(mesh, rho_f=1.0, c_f=1.0, rho_s=1.0, cp_s=np.sqrt(3.0), cs_s=1.0,
+                   perturb=0.0, seed=None):
+    """Attach per-cell (rho, a, b).  Each physical parameter (rho, c for fluid
+    cells; rho, cP, cS for solid cells) is multiplied by 1 + U[-perturb, perturb]
+    independently per cell; solid Lame parameters follow from
+    mu = rho cS^2 and lambda = rho cP^2 - 2 mu."""
+    nc = len(mesh["cell_ptr"]) - 1
+    med = mesh["medium"]
+    rng = np.random.default_rng(seed)
+    f = (lambda: 1.0 + rng.uniform(-perturb, perturb, nc)) if perturb > 0 else (lambda: np.ones(nc))
+    rho = np.where(med == FLUID, rho_f, rho_s) * f()
+    c1 = np.where(med == FLUID, c_f, cp_s) * f()
+    c2 = np.where(med == FLUID, 0.0, cs_s) * f()
+    mu = rho * c2 ** 2
+    lam = rho * c1 ** 2 - 2.0 * mu
+    a = np.where(med == FLUID, c1, lam)
+    b = np.where(med == FLUID, 0.0, mu)
+    out = dict(mesh)
+    out.update(rho=rho.astype(np.float64), a=a.astype(np.float64), b=b.astype(np.float64))
+    return out
+
+
+def max_wave_speed(mesh):
+    """Largest wave speed over the cells (c for fluid, cP for solid)."""
+    med, rho, a, b = mesh["medium"], mesh["rho"], mesh["a"], mesh["b"]
+    cp = np.where(med == FLUID, a, np.sqrt(np.maximum(a + 2.0 * b, 0.0) / rho))
+    return float(cp.max())
+
+
+# --------------------------------------------------------------------------------------
+# Named workloads (sizes and seeds of the benchmark configurations)
+# --------------------------------------------------------------------------------------
+
+def manufactured_square(n=16):
+    """Unit square, 16 x 16 quads, fluid rho = 1, c = 1 above y = 1/2; solid rho = 1,
+    cP = sqrt(3), cS = 1 below (lambda = mu = 1)."""
+    return with_materials(unit_square(n))
+
+
+def hybrid_square(n=256, mesh_seed=2001, mat_seed=2002, perturb=0.10):
+    """n x n squares, each kept or cut along a random diagonal with probability 1/2,
+    per-cell materials perturbed by U[-10 %, +10 %]."""
+    return with_materials(unit_square(n, p_split=0.5, seed=mesh_seed),
+                          perturb=perturb, seed=mat_seed)
+
+
+def hanging_square(n=8, seed=7, p_split=0.5, frac=0.25):
+    """Hybrid unit-square mesh where a random set of squares is refined 2:1,
+    producing pentagons, hexagons and quadrilaterals with hanging nodes."""
+    rng = np.random.default_rng(seed + 1)
+    refine = rng.random((n, n)) < frac
+    return with_materials(unit_square(n, p_split=p_split, seed=seed, refine=refine))
+
+
+def basin(nx=1120, ny=280, seed=3001, p_split=0.5):
+    """Synthetic sedimentary basin: x in [0, 20] km, y in [-4, 1] km, water above
+    y = 0 (c = 1500 m/s, rho = 1000), layered solid below with a Gaussian-profile
+    low-velocity basin (depth 1 km * exp(-((x - 12 km)/2.5 km)^2)); the squares
+    intersecting the basin plus a one-square margin are refined 2:1."""
+    L, y0, y1 = 20000.0, -4000.0, 1000.0
+    hx = L / nx
+    xs = (np.arange(nx) + 0.5) * hx
+    ys = y0 + (np.arange(ny) + 0.5) * (y1 - y0) / ny
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    d = 1000.0 * np.exp(-((X - 12000.0) / 2500.0) ** 2)
+    inside = (Y < 0) & (-Y < d + hx)
+    refine = inside.copy()
+    refine[1:, :] |= inside[:-1, :]
+    refine[:-1, :] |= inside[1:, :]
+    refine[:, 1:] |= inside[:, :-1]
+    refine[:, :-1] |= inside[:, 1:]
+    refine &= (Y < 0)
+    rng = np.random.default_rng(seed)
+    m = _lattice_mesh(nx, ny, 0.0, L, y0, y1, refine, p_split, rng)
+    bc = _barycentres(m)
+    med = np.where(bc[:, 1] > 0.0, FLUID, SOLID).astype(np.uint8)
+    z = -bc[:, 1]
+    cs = np.select([z < 500, z < 1500, z < 2500], [1200.0, 1800.0, 2400.0], 3000.0)
+    rho = np.select([z < 500, z < 1500, z < 2500], [2100.0, 2300.0, 2500.0], 2700.0)
+    db = 1000.0 * np.exp(-((bc[:, 0] - 12000.0) / 2500.0) ** 2)
+    inb = (z > 0) & (z < db)
+    cs = np.where(inb, 300.0 + 600.0 * z / np.maximum(db, 1e-9), cs)
+    rho = np.where(inb, 1800.0 + 200.0 * z / np.maximum(db, 1e-9), rho)
+    cp = np.sqrt(3.0) * cs
+    mu = rho * cs ** 2
+    lam = rho * cp ** 2 - 2.0 * mu
+    m["medium"] = med
+    m["rho"] = np.where(med == FLUID, 1000.0, rho)
+    m["a"] = np.where(med == FLUID, 1500.0, lam)
+    m["b"] = np.where(med == FLUID, 0.0, mu)
+    return m
+
+
+def batch_meshes(n_meshes=16, c_min=2.0e4, c_max=3.0e5):
+    """Sizes of the multi-mesh batch: target cell counts log-spaced between
+    c_min and c_max, n_i = round(sqrt(C_i / 1.5)) squares per side, split seed
+    4000 + i, degree k_i = 1 + (i mod 3)."""
+    out = []
+    for i in range(n_meshes):
+        ci = c_min * (c_max / c_min) ** (i / max(n_meshes - 1, 1))
+        n = int(round(np.sqrt(ci / 1.5)))
+        n += n % 2
+        out.append(dict(n=n, seed=4000 + i, k=1 + (i % 3)))
+    return out
+
+
+def shot_positions(n, seed, box=(0.1, 0.9, 0.1, 0.4)):
+    """Seeded source positions, uniform in the given box of the solid part."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(box[0], box[1], n)
+    y = rng.uniform(box[2], box[3], n)
+    return np.stack([x, y], axis=1)
+
+
+def receiver_line(n, y, x0=0.05, x1=0.95):
+    """n receivers equally spaced on the horizontal line at height y."""
+    return np.stack([np.linspace(x0, x1, n), np.full(n, y)], axis=1)
+
+
+def random_state(ndof_per_cell, seed, scale=1.0):
+    """Seeded random cell coefficients (one value per cell degree of freedom)."""
+    rng = np.random.default_rng(seed)
+    return scale * rng.standard_normal(int(np.sum(ndof_per_cell)))

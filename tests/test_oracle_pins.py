@@ -1,0 +1,377 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each check is a closed form, an
+exact identity of the discrete scheme, a value printed in the paper, or a
+convergence rate, chosen so that a dropped term, a wrong sign, a wrong index or
+a transposed block in the oracle makes at least one of them fail.
+
+Paper references are to arXiv 2505.15771.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Oracle, ERK_TABLEAUX
+from synth import meshes as M
+
+FLUID, SOLID = 0, 1
+
+
+# ----------------------------------------------------------------------------- helpers
+class Poly:
+    """Random bivariate polynomial of total degree <= k with seeded coefficients."""
+
+    def __init__(self, k, rng):
+        self.terms = [(a, d - a, rng.standard_normal()) for d in range(k + 1) for a in range(d + 1)]
+
+    def __call__(self, x, y):
+        return sum(c * x ** a * y ** b for a, b, c in self.terms)
+
+    def dx(self, x, y):
+        return sum(c * a * x ** (a - 1) * y ** b for a, b, c in self.terms if a > 0) + 0 * x
+
+    def dy(self, x, y):
+        return sum(c * b * x ** a * y ** (b - 1) for a, b, c in self.terms if b > 0) + 0 * x
+
+
+def zero(x, y):
+    return np.zeros_like(x)
+
+
+def interior_cells(o):
+    fv, fc, tag = o.face_info()
+    touching = set(fc[fc[:, 1] < 0, 0].tolist())
+    return np.array([c for c in range(o.nc) if c not in touching], dtype=int)
+
+
+def cell_blocks(o, cells):
+    idx = []
+    for c in cells:
+        idx.extend(range(o.offsets[c], o.offsets[c + 1]))
+    return np.array(idx, dtype=int)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# ----------------------------------------------------------------------------- P8 DOF layout
+def test_dof_counts_k1():
+    """Sec. 3.2 worked example: 9 cell unknowns per fluid cell, 15 per solid cell,
+    2 / 4 / 6 unknowns on fluid / solid / interface faces at k = 1."""
+    mesh = M.manufactured_square(4)
+    o = Oracle(mesh, 1)
+    nd = o.ndof_cell()
+    assert set(nd[o.medium == FLUID].tolist()) == {9}
+    assert set(nd[o.medium == SOLID].tolist()) == {15}
+    fv, fc, tag = o.face_info()
+    w = np.diff(o.face_offsets())
+    assert set(w[tag == 0].tolist()) == {2}
+    assert set(w[tag == 1].tolist()) == {4}
+    assert set(w[tag == 2].tolist()) == {6}
+    assert set(w[tag >= 3].tolist()) == {0}
+
+
+def test_face_counts_16x16():
+    """Unit square 16 x 16, interface y = 1/2: 544 edges, 64 on the boundary, 16 on the interface."""
+    o = Oracle(M.manufactured_square(16), 1)
+    fv, fc, tag = o.face_info()
+    assert o.nfaces == 544
+    assert int(np.sum(tag >= 3)) == 64
+    assert int(np.sum(tag == 2)) == 16
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_face_dof_share_table(k):
+    """Table tab::DOFS (2D, equal order): the share of face unknowns tends to 1/(k+3)
+    (acoustic) and 6/(5k+16) (elastic) on large triangle meshes."""
+    n = 48
+    for medium, expect in ((FLUID, 1.0 / (k + 3)), (SOLID, 6.0 / (5 * k + 16))):
+        mesh = M.with_materials(M.single_medium(n, medium, p_split=1.0, seed=3))
+        o = Oracle(mesh, k)
+        fv, fc, tag = o.face_info()
+        nface_dofs = int(np.diff(o.face_offsets()).sum())
+        share = nface_dofs / (nface_dofs + o.ndof)
+        # boundary faces carry no unknowns; the asymptotic formula neglects them (O(1/n))
+        assert abs(share - expect) < 2.0 / n, (share, expect)
+
+
+# ----------------------------------------------------------------------------- P1 polynomial consistency
+MESHES = {
+    "quads": lambda: M.unit_square(6),
+    "triangles": lambda: M.unit_square(6, p_split=1.0, seed=5),
+    "hanging": lambda: M.unit_square(6, p_split=0.5, seed=9,
+                                     refine=np.random.default_rng(4).random((6, 6)) < 0.35),
+}
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("shape", list(MESHES))
+def test_consistency_acoustic(k, shape):
+    """eq. rec_a / eq. stab: for a global polynomial p of degree k (m = 0) every interior
+    face value equals the trace of p, so rho dm/dt = grad p and dp/dt = 0 exactly; for a
+    polynomial m (p = 0) the face values vanish and dp/dt = kappa div m, dm/dt = 0."""
+    rng = np.random.default_rng(10 + k)
+    base = MESHES[shape]()
+    base["medium"] = np.zeros_like(base["medium"])
+    mesh = M.with_materials(base, rho_f=1.7, c_f=0.9)
+    o = Oracle(mesh, k)
+    cells = interior_cells(o)
+    assert len(cells) > 0
+    idx = cell_blocks(o, cells)
+    rho, kap = 1.7, 1.7 * 0.81
+    p = Poly(k, rng)
+    U = o.project([p, zero, zero], [zero] * 5)
+    dU = o.rhs(U)
+    ex = o.project([zero, lambda x, y: p.dx(x, y) / rho, lambda x, y: p.dy(x, y) / rho], [zero] * 5)
+    assert rel(dU[idx], ex[idx]) < 1e-11
+    mx, my = Poly(k, rng), Poly(k, rng)
+    U = o.project([zero, mx, my], [zero] * 5)
+    dU = o.rhs(U)
+    ex = o.project([lambda x, y: kap * (mx.dx(x, y) + my.dy(x, y)), zero, zero], [zero] * 5)
+    assert rel(dU[idx], ex[idx]) < 1e-11
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("shape", list(MESHES))
+def test_consistency_elastic(k, shape):
+    """eq. rec_e / eq. stab: polynomial v (s = 0) gives C^{-1} ds/dt = grad_sym v and
+    dv/dt = 0; polynomial s (v = 0) gives rho dv/dt = div s and ds/dt = 0 (interior cells).
+    The stress uses the orthonormal tensor basis E1 = e1e1, E2 = e2e2, E3 = (e1e2+e2e1)/sqrt2."""
+    rng = np.random.default_rng(20 + k)
+    base = MESHES[shape]()
+    base["medium"] = np.ones_like(base["medium"])
+    rho, cp, cs = 1.3, 2.1, 1.1
+    mesh = M.with_materials(base, rho_s=rho, cp_s=cp, cs_s=cs)
+    mu = rho * cs ** 2
+    lam = rho * cp ** 2 - 2 * mu
+    o = Oracle(mesh, k)
+    idx = cell_blocks(o, interior_cells(o))
+    r2 = math.sqrt(2.0)
+    vx, vy = Poly(k, rng), Poly(k, rng)
+    U = o.project([zero] * 3, [vx, vy, zero, zero, zero])
+    dU = o.rhs(U)
+
+    def sig(x, y):
+        exx, eyy = vx.dx(x, y), vy.dy(x, y)
+        exy = 0.5 * (vx.dy(x, y) + vy.dx(x, y))
+        tr = exx + eyy
+        return lam * tr + 2 * mu * exx, lam * tr + 2 * mu * eyy, 2 * mu * exy
+
+    ex = o.project([zero] * 3, [zero, zero, lambda x, y: sig(x, y)[0], lambda x, y: sig(x, y)[1],
+                                lambda x, y: r2 * sig(x, y)[2]])
+    assert rel(dU[idx], ex[idx]) < 1e-11
+    sxx, syy, sxy = Poly(k, rng), Poly(k, rng), Poly(k, rng)
+    U = o.project([zero] * 3, [zero, zero, sxx, syy, lambda x, y: r2 * sxy(x, y)])
+    dU = o.rhs(U)
+    ex = o.project([zero] * 3, [lambda x, y: (sxx.dx(x, y) + sxy.dy(x, y)) / rho,
+                                lambda x, y: (sxy.dx(x, y) + syy.dy(x, y)) / rho, zero, zero, zero])
+    assert rel(dU[idx], ex[idx]) < 1e-11
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_interface_steady_state(k):
+    """eq. continuous_coupling imposed weakly (eq. HHO1 / HHO2): the constant state
+    p = P, m = (0, W) in the fluid and v = (0, W), s = P Id in the solid satisfies
+    v.n = m.n and s n = p n on the interface y = 1/2 and solves the PDEs, so the
+    semi-discrete time derivative vanishes on every cell away from the outer boundary."""
+    mesh = M.with_materials(M.unit_square(8, p_split=0.5, seed=2))
+    o = Oracle(mesh, k)
+    P, W = 0.7, -1.3
+    r2 = math.sqrt(2.0)
+    c = lambda v: (lambda x, y: np.full_like(x, v))
+    U = o.project([c(P), c(0.0), c(W)], [c(0.0), c(W), c(P), c(P), c(0.0)])
+    dU = o.rhs(U)
+    idx = cell_blocks(o, interior_cells(o))
+    assert np.max(np.abs(dU[idx])) < 1e-12
+    # sanity: the interface is really crossed by the chosen interior cells
+    fv, fc, tag = o.face_info()
+    assert np.sum(tag == 2) == 8
+    # a shear stress violates s n = p n and must produce a response
+    U2 = o.project([c(P), c(0.0), c(W)], [c(0.0), c(W), c(P), c(P), c(0.3 * r2)])
+    assert np.max(np.abs(o.rhs(U2)[idx])) > 1e-3
+
+
+def _shift(poly, dy):
+    """poly evaluated in (x, y - dy), with derivatives."""
+    class S:
+        def __call__(self, x, y): return poly(x, y - dy)
+        def dx(self, x, y): return poly.dx(x, y - dy)
+        def dy(self, x, y): return poly.dy(x, y - dy)
+    return S()
+
+
+def _matched(k, rng, base):
+    """Random polynomial of degree k whose restriction to y = 0 equals that of ``base``
+    (the terms without a power of y are copied, the others drawn afresh)."""
+    q = Poly(k, rng)
+    keep = {(a, b): c for a, b, c in base.terms if b == 0}
+    q.terms = [(a, b, keep[(a, b)] if b == 0 else c) for a, b, c in q.terms]
+    return q
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_interface_polynomial_consistency(k):
+    """Polynomial fields of degree k that satisfy the coupling conditions eq. continuous_coupling
+    on the interface y = 1/2 (v_y = m_y, s_xy = 0, s_yy = p there) are reproduced exactly:
+    the interface face values equal the traces, so on every cell away from the outer boundary
+    the semi-discrete time derivatives equal rho^{-1} grad p, kappa div m, C grad_sym v and
+    rho^{-1} div s.  This pins the coupling block and its sign on both sides of the interface."""
+    rng = np.random.default_rng(40 + k)
+    rho_f, c_f, rho_s, cp, cs = 1.2, 0.8, 1.4, 1.9, 1.0
+    mesh = M.with_materials(M.unit_square(8, p_split=0.5, seed=6), rho_f=rho_f, c_f=c_f,
+                            rho_s=rho_s, cp_s=cp, cs_s=cs)
+    kap = rho_f * c_f ** 2
+    mu = rho_s * cs ** 2
+    lam = rho_s * cp ** 2 - 2 * mu
+    o = Oracle(mesh, k)
+    r2 = math.sqrt(2.0)
+    p0, mx0, my0 = Poly(k, rng), Poly(k, rng), Poly(k, rng)
+    syy0 = _matched(k, rng, p0)
+    vy0 = _matched(k, rng, my0)
+    sxy0 = Poly(k, rng)
+    sxy0.terms = [(a, b, c if b > 0 else 0.0) for a, b, c in sxy0.terms]
+    vx0, sxx0 = Poly(k, rng), Poly(k, rng)
+    p, mx, my, syy, vy, sxy, vx, sxx = (_shift(q, 0.5) for q in (p0, mx0, my0, syy0, vy0, sxy0, vx0, sxx0))
+    U = o.project([p, mx, my], [vx, vy, sxx, syy, lambda x, y: r2 * sxy(x, y)])
+    dU = o.rhs(U)
+
+    def sig(x, y):
+        exx, eyy = vx.dx(x, y), vy.dy(x, y)
+        exy = 0.5 * (vx.dy(x, y) + vy.dx(x, y))
+        tr = exx + eyy
+        return lam * tr + 2 * mu * exx, lam * tr + 2 * mu * eyy, 2 * mu * exy
+
+    ex = o.project([lambda x, y: kap * (mx.dx(x, y) + my.dy(x, y)),
+                    lambda x, y: p.dx(x, y) / rho_f, lambda x, y: p.dy(x, y) / rho_f],
+                   [lambda x, y: (sxx.dx(x, y) + sxy.dy(x, y)) / rho_s,
+                    lambda x, y: (sxy.dx(x, y) + syy.dy(x, y)) / rho_s,
+                    lambda x, y: sig(x, y)[0], lambda x, y: sig(x, y)[1], lambda x, y: r2 * sig(x, y)[2]])
+    idx = cell_blocks(o, interior_cells(o))
+    assert rel(dU[idx], ex[idx]) < 1e-11
+
+
+# ----------------------------------------------------------------------------- P5 energy identity
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_energy_balance_identity(k):
+    """With no source, dE/dt = U^T M dU/dt = -U^T K_eff U, and eliminating the face unknowns
+    makes U^T K_eff U equal to the stabilisation energy sum_T eta tau_T ||S_dT||^2 at
+    (U_T, U_F(U_T)): the skew parts (the reconstructions and the coupling block) cancel."""
+    mesh = M.hanging_square(6, seed=11)
+    o = Oracle(mesh, k)
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        U = rng.standard_normal(o.ndof)
+        lhs = o.mass_dot(U, o.rhs(U))
+        S = o.stab_energy(U)
+        assert S > 0
+        assert abs(lhs + S) < 1e-11 * S
+
+
+def test_energy_nonincreasing_lossless():
+    """Sec. 5.1: with zero source and dt below the CFL limit the discrete energy decays
+    (it can only lose the stabilisation dissipation), step after step."""
+    mesh = M.manufactured_square(8)
+    o = Oracle(mesh, 2)
+    U = np.random.default_rng(1).standard_normal(o.ndof)
+    dt = 0.5 * 0.138 * (1 / 8) / math.sqrt(3.0)
+    U1, E = o.erk(U, 0.0, dt, 40, s=4, energies=True)
+    E0 = o.energy(U)
+    seq = np.concatenate([[E0], E])
+    assert np.all(np.diff(seq) <= 1e-14 * seq[:-1])
+    assert seq[-1] < seq[0]
+
+
+# ----------------------------------------------------------------------------- P4 RK closed form
+@pytest.mark.parametrize("s", [2, 3, 4])
+def test_erk_matches_taylor_polynomial(s):
+    """eq. ERK: the s-stage, order-s explicit tableaux applied to the linear system
+    dU/dt = L U give U^{n+1} = sum_{j<=s} (dt L)^j / j! U^n exactly."""
+    mesh = M.with_materials(M.unit_square(3, p_split=0.5, seed=1))
+    o = Oracle(mesh, 1)
+    L = o.dense_operator()
+    rng = np.random.default_rng(s)
+    U = rng.standard_normal(o.ndof)
+    dt = 0.01
+    ex = U.copy()
+    term = U.copy()
+    for j in range(1, s + 1):
+        term = dt * (L @ term) / j
+        ex = ex + term
+    got = o.erk(U, 0.0, dt, 1, s=s)
+    assert rel(got, ex) < 1e-13
+
+
+def test_tableaux_orders():
+    """The printed tableaux eq. ERK have order s: sum b = 1, sum b c = 1/2, and for s >= 3
+    sum b c^2 = 1/3, b A c = 1/6; for s = 4 the four fourth-order conditions too."""
+    for s, (A, b, c) in ERK_TABLEAUX.items():
+        assert abs(b.sum() - 1) < 1e-15
+        assert abs(b @ c - 0.5) < 1e-15
+        assert np.allclose(A.sum(axis=1), c)
+        if s >= 3:
+            assert abs(b @ c ** 2 - 1 / 3) < 1e-15
+            assert abs(b @ A @ c - 1 / 6) < 1e-15
+        if s == 4:
+            assert abs(b @ c ** 3 - 1 / 4) < 1e-15
+            assert abs(b @ (c * (A @ c)) - 1 / 8) < 1e-15
+            assert abs(b @ A @ c ** 2 - 1 / 12) < 1e-15
+            assert abs(b @ A @ A @ c - 1 / 24) < 1e-15
+
+
+# ----------------------------------------------------------------------------- sources / receivers
+def test_point_source_load_and_point_values():
+    """eq. rhs read as a load vector: a point force d R(t) delta_{x_s} tested with a
+    polynomial w gives R(t) d.w(x_s); R is the Ricker wavelet (1 - 2a^2) exp(-a^2),
+    a = pi f0 (t - t0).  Point values of a projected polynomial are exact."""
+    mesh = M.with_materials(M.unit_square(4, p_split=0.5, seed=3))
+    o = Oracle(mesh, 2)
+    rng = np.random.default_rng(8)
+    xs = np.array([0.37, 0.21])
+    d = np.array([0.3, -1.0])
+    f0, t0, amp = 10.0, 0.12, 2.5
+    o.set_point_sources(xs, d, f0, t0, amp)
+    t = 0.093
+    a = math.pi * f0 * (t - t0)
+    R = amp * (1 - 2 * a * a) * math.exp(-a * a)
+    wx, wy = Poly(2, rng), Poly(2, rng)
+    Wc = o.project([zero] * 3, [wx, wy, zero, zero, zero])
+    dU = o.rhs(np.zeros(o.ndof), t)
+    # dU = M^{-1} F with M = rho M0 on the v rows -> F = rho M0 dU; F . Wc = R d . w(x_s)
+    c = o.locate(*xs)
+    rho = mesh["rho"][c]
+    off = o.offsets[c]
+    M0 = o.cell_ops(c)["M0"]
+    F = np.concatenate([rho * M0 @ dU[off + i * o.N: off + (i + 1) * o.N] for i in range(2)])
+    got = F @ Wc[off: off + 2 * o.N]
+    assert abs(got - R * (d[0] * wx(*xs) + d[1] * wy(*xs))) < 1e-12 * abs(R)
+    # point values
+    cc, vals = o.point_values(Wc, 0.61, 0.13)
+    assert abs(vals[0] - wx(0.61, 0.13)) < 1e-12 and abs(vals[1] - wy(0.61, 0.13)) < 1e-12
+
+
+# ----------------------------------------------------------------------------- P6 convergence
+@pytest.mark.slow
+@pytest.mark.parametrize("k", [1, 2])
+def test_manufactured_convergence(k):
+    """Sec. 5.1 sinusoidal solution (eq. non_poly_sol), adapted to the unit square with the
+    interface at y = 1/2 and omega odd so that the coupling and Dirichlet conditions hold
+    exactly: the L2 error of the cell unknowns at T decreases at a rate close to k + 1."""
+    from oracle.manufactured import Manufactured
+    ms = Manufactured(omega=1, theta=math.sqrt(2.0), phase=0.7)
+    errs = []
+    for n in (8, 16, 32):
+        o = Oracle(M.manufactured_square(n), k)
+        fl, so = ms.fields(0.0)
+        U0 = o.project(fl, so)
+        terms, om, ph = ms.forcing_terms()
+        o.set_dense_load(np.stack([o.load_vector(*tm) for tm in terms]), om, ph)
+        T = 0.25
+        dt = 0.1 * 0.087 / n / math.sqrt(3.0)
+        ns = int(math.ceil(T / dt))
+        U = o.erk(U0, 0.0, T / ns, ns)
+        Ue = o.project(*ms.fields(T))
+        errs.append(math.sqrt(o.mass_dot(U - Ue, U - Ue) / o.mass_dot(Ue, Ue)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates[-1] > k + 0.5, (errs, rates)
