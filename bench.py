@@ -1,0 +1,174 @@
+"""Benchmark of the HHO elasto-acoustic explicit Runge-Kutta path on one MI355X.
+
+Workload: the unit square with the two-material split (elastic below y = 1/2:
+rho = 1, cP = sqrt(3), cS = 1; acoustic above: rho = 1, c = 1), a 256 x 256 hybrid
+mesh (each square kept or cut along a random diagonal with probability 1/2, seed
+2001), per-cell materials perturbed by U[-10 %, +10 %] (seed 2002), HHO k = 2,
+classical RK4 at dt = 0.5 CFL* h / c_max.  A step is one RK4 step (four fused stage
+launches) over the whole mesh; inputs are resident in HBM before timing starts.
+
+The headline value is float32 stepping of one shot; float64, k = 3 and batched
+(several shots per launch) variants are reported next to it.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from synth import meshes as M  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+CFL_SQUARE = {1: 0.282, 2: 0.138, 3: 0.087}   # Table tab::ratio_ERK, s = 4
+CFL_TRI = {1: 0.265, 2: 0.147, 3: 0.100}      # Table tab::ratio_geo, s = 4
+METRIC = "HHO DOF-stage updates/s, FP64 vs FP32/batched, % of HBM roofline"
+
+
+def algorithmic_bytes_per_step(mesh, k, word, shots):
+    """Minimum HBM traffic of one RK4 step: 17 state words per cell unknown per shot
+    (read U^n, Y_i and the accumulator, write Y_{i+1}, accumulator and U^{n+1}),
+    plus per stage the mesh metadata in 4-byte words: per cell one face id per face and
+    its material scalars (3 fluid, 5 solid), per interior face one coefficient."""
+    N = (k + 1) * (k + 2) // 2
+    med = np.asarray(mesh["medium"])
+    nf = np.diff(mesh["cell_ptr"])
+    ndof = int(np.sum(np.where(med == 0, 3, 5))) * N
+    state = word * 17 * ndof * shots
+    meta_cells = int(np.sum(4 * nf + 4 * np.where(med == 0, 3, 5)))
+    # interior faces: every interior face is seen by two cells -> count unique via edge keys
+    vtx, ptr = mesh["cell_vtx"], mesh["cell_ptr"]
+    a = vtx
+    b = np.empty_like(vtx)
+    for c in range(len(ptr) - 1):
+        s, e = ptr[c], ptr[c + 1]
+        b[s:e] = np.roll(vtx[s:e], -1)
+    keys = np.minimum(a, b).astype(np.int64) * (1 << 32) + np.maximum(a, b)
+    _, cnt = np.unique(keys, return_counts=True)
+    n_faces_int = int(np.sum(cnt == 2))
+    meta = 4 * (meta_cells + 4 * n_faces_int)
+    return state + meta, ndof
+
+
+def run_variant(mesh, k, dtype, shots, steps, warmup):
+    import torch
+    from paper_2505_15771_amd import Engine
+    eng = Engine(mesh, k, dtype=dtype, n_shots=shots)
+    rng = np.random.default_rng(7)
+    for sh in range(shots):
+        eng.set_state(1e-3 * rng.standard_normal(eng.n_dof), shot=sh)
+        eng.set_sources(sh, [[0.5, 0.25 + 0.01 * sh]], [[0.0, 1.0]], 10.0, 0.12, 1.0)
+    h = 1.0 / 256
+    dt = 0.5 * min(CFL_SQUARE[k], CFL_TRI[k]) * h / M.max_wave_speed(mesh)
+    eng.erk_step(0.0, dt, warmup)
+    eng.synchronize()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    eng.erk_step(warmup * dt, dt, steps)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    torch.cuda.synchronize()
+    word = 8 if dtype == "f64" else 4
+    bstep, ndof = algorithmic_bytes_per_step(mesh, k, word, shots)
+    secs = ms / 1e3
+    updates = ndof * shots * 4 * steps
+    launch_us = ms * 1e3 / (4 * steps)
+    gbs = (bstep / 4) / (launch_us * 1e-6) / 1e9
+    E = eng.energy()
+    eng.close()
+    return dict(k=k, dtype=dtype, shots=shots, steps=steps, ms=ms, ms_per_step=ms / steps,
+                value=updates / secs, launch_us=launch_us, bytes_per_launch=bstep / 4, gbs=gbs,
+                frac=gbs / HBM_PEAK_GBS, finite=bool(np.all(np.isfinite(E))), ndof=ndof)
+
+
+def cpu_baseline(mesh, k, budget_s=12.0):
+    """The FP64 oracle as it stands, on the host cores, for a bounded number of steps."""
+    from oracle import Oracle
+    o = Oracle(mesh, k)
+    U = 1e-3 * np.random.default_rng(7).standard_normal(o.ndof)
+    h = 1.0 / 256
+    dt = 0.5 * min(CFL_SQUARE[k], CFL_TRI[k]) * h / M.max_wave_speed(mesh)
+    U = o.erk(U, 0.0, dt, 1)  # warm-up
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        U = o.erk(U, n * dt, dt, 1)
+        n += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or n >= 200:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=o.ndof * 4 * n / el, unit="DOF-stage updates/s", cores=cores, kind="oracle",
+                sample="%d RK4 steps of the full 256x256 hybrid mesh, k=%d, float64, %.1f s" % (n, k, el))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--k", type=int, default=2)
+    ap.add_argument("--dtype", default="f32")
+    ap.add_argument("--shots", type=int, default=1)
+    ap.add_argument("--variants", type=int, default=1, help="also time the float64 / k=3 / batched variants")
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (the data-parallel "
+              "decomposition is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    mesh = M.hybrid_square(256)
+    head = run_variant(mesh, args.k, args.dtype, args.shots, args.steps, args.warmup)
+    print("headline", json.dumps(head), file=sys.stderr, flush=True)
+    variants = []
+    if args.variants:
+        for (k, dt, sh) in ((2, "f64", 1), (3, "f32", 1), (3, "f64", 1), (2, "f32", 8), (3, "f32", 8)):
+            if (k, dt, sh) == (args.k, args.dtype, args.shots):
+                continue
+            v = run_variant(mesh, k, dt, sh, max(args.steps // 2, 10), 5)
+            print("variant", json.dumps(v), file=sys.stderr, flush=True)
+            variants.append({key: v[key] for key in ("k", "dtype", "shots", "value", "ms_per_step", "launch_us",
+                                                       "gbs", "frac")})
+    cpu = cpu_baseline(mesh, args.k) if args.cpu_baseline else None
+    out = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "DOF-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head["dtype"],
+        "data": "synthetic",
+        "config": {"workload": "two-material unit square, 256x256 hybrid quad/triangle mesh (seed 2001), "
+                               "materials +-10% (seed 2002), HHO k=%d, RK4, Ricker point source" % args.k,
+                   "cells": int(len(mesh["cell_ptr"]) - 1), "cell_dofs": head["ndof"], "shots": args.shots},
+        "roofline": {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": head["frac"], "traffic": None, "kernel": "stage_kernel",
+                     "launch_us": head["launch_us"], "bytes_per_launch": head["bytes_per_launch"]},
+        "cpu_baseline": cpu,
+        "variants": variants,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

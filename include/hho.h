@@ -1,0 +1,166 @@
+/*
+ * hho.h - C ABI of the MI355X HHO elasto-acoustic explicit Runge-Kutta engine.
+ *
+ * The engine advances the first-order hybrid high-order (HHO) semi-discretisation
+ * of coupled acoustic / elastic waves (arXiv 2505.15771) with an explicit
+ * Runge-Kutta method, eliminating the face unknowns at every stage so that every
+ * solve is block-diagonal:
+ *   model     Sec. 2.1, eq. continuous_acoustic (p, m), eq. continuous_elastic_eq (v, s),
+ *             coupling eq. continuous_coupling imposed weakly (Sec. 2.2);
+ *   space     Sec. 3.3, eq. HHO1 / HHO2 with the reconstructions eq. rec_a / rec_e, the
+ *             least-squares stabilisation eq. stab (alpha = 0, equal order k' = k) scaled
+ *             by the weights eta^f, eta^s of Sec. 5.1, and the face-local coupling block;
+ *   time      Sec. 4.2, eq. ERK_compact / eq. ex_solve: K_F U_F = -K_FT U_T, then
+ *             M U_T^{n,i} = M U_T^{n-1} + dt sum_j a_ij (F_T - K_T U_T - K_TF U_F)^{n,j},
+ *             with the ERK(s) tableaux of eq. ERK (s = 2, 3, 4);
+ *   energy    Sec. 5.1 (cell unknowns only).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns hho_status; no C++ exception crosses the ABI.  After an
+ *     error hho_last_error(ctx) returns a message (valid until the next call on ctx).
+ *   - The caller owns every pointer it passes.  Input arrays are copied during the
+ *     call and never retained.  "on_device" pointers are HIP device pointers (e.g.
+ *     torch.Tensor.data_ptr() of a contiguous float64 cuda tensor); they are only
+ *     accessed during the call, on params.stream.
+ *   - A context is not thread-safe: use one context per host thread / stream.
+ *   - State layout (external, "per cell contiguous", cells in input order, float64):
+ *       fluid cell  [p (N) | m_x (N) | m_y (N)]
+ *       solid cell  [v_x (N) | v_y (N) | s_1 (N) | s_2 (N) | s_3 (N)]
+ *     N = (k+1)(k+2)/2 coefficients in the cell basis: the graded monomials
+ *     ((x-x_T)/h_T)^a ((y-y_T)/h_T)^b (degree-major, decreasing power of x within a
+ *     degree; x_T the centroid, h_T the largest vertex distance) orthonormalised in
+ *     L2(T) by the inverse Cholesky factor of their Gram matrix (Sec. 3.3 uses
+ *     barycentre-centred monomials; the orthonormal combination spans the same space).
+ *     Stress coefficients refer to E_1 = e1 e1^T, E_2 = e2 e2^T, E_3 = (e1 e2^T + e2 e1^T)/sqrt(2),
+ *     so s_3 = sqrt(2) * s_xy.
+ */
+#ifndef HHO_H
+#define HHO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hho_ctx hho_ctx; /* opaque; owns every device buffer it allocates */
+
+typedef enum {
+    HHO_OK = 0,
+    HHO_ERR_ARG = 1,      /* invalid argument (null pointer, out-of-range value)            */
+    HHO_ERR_MESH = 2,     /* non-conforming / inconsistent mesh, clockwise or degenerate cell */
+    HHO_ERR_SINGULAR = 3, /* a local Gram or face block is not invertible                 */
+    HHO_ERR_DEVICE = 4,   /* HIP runtime or kernel launch failure                            */
+    HHO_ERR_OOM = 5,      /* device allocation failed                                        */
+    HHO_ERR_UNSTABLE = 6  /* recorded energy grew by more than 5 % or became non-finite
+                             (energy criterion of Algorithm algo_CFL, Sec. 5.1)              */
+} hho_status;
+
+/* Polygonal mesh aligned with the fluid / solid partition (Sec. 3.1).
+ *   xy[2*n_vertices]          vertex coordinates (x, y)
+ *   cell_ptr[n_cells+1]       CSR offsets into cell_vtx
+ *   cell_vtx[cell_ptr[n]]     counter-clockwise vertex ids of every cell; hanging nodes
+ *                             are ordinary (collinear) vertices, so a face is one edge
+ *   medium[n_cells]           0 = fluid (acoustic), 1 = solid (elastic)
+ *   rho, a, b [n_cells]       piecewise-constant materials: fluid a = sound speed c
+ *                             (kappa = rho c^2), b ignored; solid a = lambda, b = mu.
+ * Every edge must be shared by at most two cells, traversed in opposite directions. */
+typedef struct {
+    int32_t n_vertices;
+    const double *xy;
+    int32_t n_cells;
+    const int32_t *cell_ptr;
+    const int32_t *cell_vtx;
+    const uint8_t *medium;
+    const double *rho;
+    const double *a;
+    const double *b;
+} hho_mesh;
+
+/* Discretisation and run parameters.
+ *   k            polynomial degree, 1..3 (k >= 1 is needed in the solid, Sec. 3.2)
+ *   rk_stages    ERK(s) of eq. ERK: 2 (midpoint), 3 (Kutta), 4 (classical)
+ *   eta_f, eta_s stabilisation weights (0.8 and 1.5 in Sec. 5.1)
+ *   stab_speed   speed c^s in tau^s = eta^s rho c^s: 0 = P-wave, 1 = S-wave speed
+ *   dtype        0 = float64 stepping; 1 = float32 stepping (float32 matvecs and
+ *                accumulation, factors formed in float64 and rounded, float64 energy)
+ *   n_shots      number of independent right-hand sides advanced together (1..256)
+ *   record_energy 1 = record the float64 energy of every shot after every step
+ *   device       HIP device ordinal
+ *   stream       hipStream_t to run on (NULL = the null stream) */
+typedef struct {
+    int32_t k;
+    int32_t rk_stages;
+    double eta_f, eta_s;
+    int32_t stab_speed;
+    int32_t dtype;
+    int32_t n_shots;
+    int32_t record_energy;
+    int32_t device;
+    void *stream;
+} hho_params;
+
+/* Build the discretisation on the device: face extraction and tagging (Sec. 3.1),
+ * local operators in float64 (Sec. 3.3), grouping of cells by (medium, shape class),
+ * upload of SoA buffers.  State starts at zero.  Errors: ARG, MESH, SINGULAR, OOM, DEVICE. */
+hho_status hho_setup(const hho_mesh *mesh, const hho_params *params, hho_ctx **out);
+
+/* Release every device buffer and the context (NULL is ignored). */
+void hho_destroy(hho_ctx *ctx);
+
+/* Message of the last error on ctx ("" if none); ctx NULL gives the last setup error. */
+const char *hho_last_error(const hho_ctx *ctx);
+
+/* Sizes: cell unknowns per shot (external layout), number of cells and faces. */
+hho_status hho_sizes(const hho_ctx *ctx, int64_t *n_dof, int32_t *n_cells, int32_t *n_faces);
+
+/* Copy one shot's state in / out (external layout above, float64, n_dof values).
+ * on_device = 1: U is a device pointer.  Synchronous with respect to the host. */
+hho_status hho_set_state(hho_ctx *ctx, int32_t shot, const double *U, int32_t on_device);
+hho_status hho_get_state(hho_ctx *ctx, int32_t shot, double *U, int32_t on_device);
+
+/* Point sources of one shot (replaces earlier ones of that shot).  Source i is the load
+ * vector of eq. rhs for the point force  amp_i R_i(t) d_i delta(x - x_i):  on the v rows of
+ * the solid cell containing x_i (direction d_i = (dir[2i], dir[2i+1])), or on the p rows
+ * of a fluid cell with weight dir[2i].  R_i is the Ricker wavelet
+ * (1 - 2 a^2) exp(-a^2), a = pi f0_i (t - t0_i).  The containing cell is the lowest-id
+ * cell whose closed polygon holds x_i.  Errors: ARG (point outside the mesh). */
+hho_status hho_set_sources(hho_ctx *ctx, int32_t shot, int32_t n, const double *xy, const double *dir,
+                           const double *f0, const double *t0, const double *amp);
+
+/* Separable dense loads shared by every shot: F_T(t) += sum_m sin(omega_m t + phase_m) g_m,
+ * g[m * n_dof + i] in the external layout (load vectors (f_m, phi_a)_T of eq. rhs).
+ * At most 4 terms; n_terms = 0 removes them. */
+hho_status hho_set_loads(hho_ctx *ctx, int32_t n_terms, const double *g, const double *omega,
+                         const double *phase);
+
+/* Register receivers (replaces earlier ones): field 0 records p (point must lie in the
+ * fluid), field 1 records (v_x, v_y) (solid).  Values are point evaluations of the cell
+ * polynomials (sensors of Sec. 5.2), recorded after every step of hho_erk_step. */
+hho_status hho_receivers(hho_ctx *ctx, int32_t n, const double *xy, const int32_t *field);
+
+/* Advance every shot by n_steps steps of ERK(rk_stages) from time t0 with step dt.
+ * Enqueued on params.stream; returns before completion unless record_energy = 1, in
+ * which case it synchronises and returns HHO_ERR_UNSTABLE if the energy of a shot grew
+ * by more than 5 % over its initial value, or over the previous step, or is not finite. */
+hho_status hho_erk_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps);
+
+/* Wait for all work enqueued by ctx. */
+hho_status hho_synchronize(hho_ctx *ctx);
+
+/* Receiver traces of the last hho_erk_step call for one shot: out[n_steps][n_rec][2]
+ * (second slot 0 for p receivers), float64. */
+hho_status hho_get_traces(hho_ctx *ctx, int32_t shot, double *out);
+
+/* Energy of the current state of every shot, float64: E[n_shots]. */
+hho_status hho_energy(hho_ctx *ctx, double *E);
+
+/* Energies recorded after each step of the last hho_erk_step call (record_energy = 1):
+ * out[n_steps] for one shot. */
+hho_status hho_energy_history(hho_ctx *ctx, int32_t shot, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HHO_H */

@@ -1,0 +1,51 @@
+/*
+ * hho_inspect.h - host-only inspection of the execution plan that hho_setup builds
+ * (no device is touched).  Meant for tests and tools that check the local operators,
+ * the cell grouping and the face links on a machine without a GPU.
+ *
+ * Plan contents (float64, structure of arrays over "internal cells" ic, which are the
+ * input cells regrouped by (medium, shape class) and padded per group):
+ *   tables   per shape class: B_x, B_y, S (N x N each, row-major), then for every local
+ *            face j (counter-clockwise order, face j runs from vertex j to vertex j+1):
+ *            G_j (N x F), then the outward unit normals n_j (2 values per face).
+ *            B_c = D_c - sum_j n_{j,c} E_j with D_c[a][b] = (d_c phi_b, phi_a)_T,
+ *            E_j[a][b] = (phi_b, phi_a)_F, S = sum_j E_j, G_j[a][i] = (phi_a, psi_i)_F.
+ *            phi: orthonormal cell basis (see hho.h); psi_i = sqrt((2i+1)/|F|) P_i(xi),
+ *            xi in [-1, 1] running along the counter-clockwise direction of the cell.
+ *            These are the blocks of eq. rec_a / rec_e / stab (Sec. 3.3) in that basis.
+ *   groups   [n_groups][6]: medium, n_faces, table offset, first ic, cells, first block
+ *   link     [max_nf][n_ic]: (ic' << 4) | (interface << 3) | j' of the neighbour across
+ *            local face j, -1 on the boundary
+ *   c0       [max_nf][n_ic]: 1 / (tau_T + tau_T') on same-medium faces,
+ *            1 / (tau_f + 1 / tau_s) on interface faces (tau = eta * tau_T of eq. stab)
+ *   mat      [6][n_ic]: 1/rho, kappa or lambda + 2 mu, eta tau, lambda, 2 mu, 1/(eta tau)
+ *   ic_of_cell [n_cells]
+ * Errors as hho_setup (ARG, MESH, SINGULAR).
+ */
+#ifndef HHO_INSPECT_H
+#define HHO_INSPECT_H
+
+#include "hho.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hho_inspect hho_inspect;
+
+hho_status hho_inspect_create(const hho_mesh *mesh, const hho_params *params, hho_inspect **out);
+void hho_inspect_destroy(hho_inspect *p);
+
+/* sizes[0..9] = N, F, n_ic, max_nf, n_groups, n_table_values, n_cells, n_faces, cpb, n_blocks */
+hho_status hho_inspect_sizes(const hho_inspect *p, int64_t *sizes);
+
+/* Copy the plan arrays out (caller-allocated, sizes from hho_inspect_sizes); any
+ * pointer may be NULL to skip that array. */
+hho_status hho_inspect_arrays(const hho_inspect *p, double *tables, int32_t *groups, int32_t *link, double *c0,
+                              double *mat, int32_t *ic_of_cell);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HHO_INSPECT_H */

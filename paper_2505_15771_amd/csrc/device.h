@@ -1,0 +1,88 @@
+// Device-side argument blocks of the HHO ERK kernels and their host launchers.
+// Shared by kernels.hip (device code) and api.cpp (host runtime); plain structs only.
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime_api.h>
+
+namespace hho {
+
+struct GroupDev {
+    int medium, nF, tab_off, ic_begin, ncells, blk_begin;
+};
+
+constexpr int kMaxN = 10;  // (k+1)(k+2)/2 for k = 3
+
+// Point source entry (sorted by internal cell; `next` chains the entries of one cell).
+struct SrcDev {
+    int ic, shot, next, pad;
+    double dirx, diry, f0, t0, amp;
+    double phi[kMaxN];
+};
+
+// Receiver entry (sorted by internal cell; `next` chains the entries of one cell).
+struct RecDev {
+    int ic, field, r, next;
+    double phi[kMaxN];
+};
+
+template <typename R>
+struct StageArgs {
+    const R *Yin;   // stage input Y_i            [rows][LT]
+    R *Yout;        // stage output Y_{i+1}        [rows][LT]  (unused on the last stage)
+    R *U;           // U^n (read), U^{n+1} (written on the last stage)
+    R *acc;         // running sum of b_i k_i
+    const R *Tin;   // face-trace contributions of Y_i     [trace rows][LT]
+    R *Tout;        // face-trace contributions of the output state
+    const int32_t *link;  // [max_nf][n_ic]
+    const R *c0;          // [max_nf][n_ic]
+    const R *mat;         // [kNumMat][n_ic]
+    const R *tab;         // class tables
+    const GroupDev *groups;
+    const int32_t *blk_group;
+    int n_ic, S, cpb;
+    long long LT;         // lanes = n_ic * S
+    double t;             // stage time t_n + c_i dt
+    R dt;
+    R cU, cY, ck, cb;     // Y_{i+1} = cU U + cY Y_i + ck dt k_i ; acc = acc + cb k_i
+    int first, last;
+    // point sources
+    const int32_t *src_first;  // [n_ic], -1 = none
+    const SrcDev *src;
+    // separable dense loads, [term][rows][n_ic]
+    int nterms;
+    const R *gload;
+    R wterm[4];
+    // last-stage diagnostics
+    double *e_part;            // energy partials [n_blocks][S] (null = off)
+    const double *emat;        // [4][n_ic]
+    const int32_t *rec_first;  // [n_ic], -1 = none (null = off)
+    const RecDev *rec;
+    double *rec_out;           // [S][rec_steps][nrec][2]
+    int step, nrec, rec_steps;
+};
+
+// Launchers (kernels.hip).  K = polynomial degree, R = double or float.
+template <int K, typename R>
+hipError_t launch_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st);
+
+template <int K, typename R>
+hipError_t launch_traces(const StageArgs<R> &a, int n_blocks, hipStream_t st);
+
+template <int K, typename R>
+hipError_t launch_energy(const StageArgs<R> &a, const R *state, int n_blocks, hipStream_t st);
+
+// Sum energy partials over blocks: out[s] = sum_b part[b * S + s].
+hipError_t launch_energy_reduce(const double *part, int n_blocks, int S, double *out, hipStream_t st);
+
+// External (per-cell contiguous, float64) <-> internal ([rows][lanes], R) state copies
+// for one shot.  map[e] = internal row-major index (row * LT + ic * S) of external dof e.
+template <typename R>
+hipError_t launch_scatter(const double *ext, const int64_t *map, long long n, int shot, R *state,
+                          hipStream_t st);
+template <typename R>
+hipError_t launch_gather(const R *state, const int64_t *map, long long n, int shot, double *ext,
+                         hipStream_t st);
+
+}  // namespace hho

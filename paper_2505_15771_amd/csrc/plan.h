@@ -1,0 +1,95 @@
+// Host-side execution plan of the HHO elasto-acoustic ERK engine: the mesh turned
+// into shape classes, cell groups and structure-of-arrays metadata, all in float64.
+// Built once by hho_setup (Sec. 3.1 mesh and faces, Sec. 3.3 local operators).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace hho {
+
+constexpr int kMaxFaces = 8;     // faces per cell (hanging nodes raise the count)
+constexpr int kBlock = 256;      // lanes per workgroup (4 wavefronts of 64)
+
+enum Medium : int { kFluid = 0, kSolid = 1 };
+
+// Per-class table layout (float64 on the host, rounded for float32 runs):
+//   Bx, By, S   N x N each, row-major  (B_c = D_c - sum_j n_{j,c} E_j, S = sum_j E_j)
+//   G_j         N x F for each local face j
+//   n_j         2 values for each local face j (outward unit normal)
+struct ClassInfo {
+    int nF = 0;
+    int offset = 0;  // into Plan::tables
+    int rep_cell = 0;
+};
+
+struct Group {
+    int medium = 0;
+    int cls = 0;
+    int nF = 0;
+    int tab_off = 0;
+    int ic_begin = 0;  // first internal cell of the group
+    int ncells = 0;    // real cells
+    int blk_begin = 0;
+    int nblk = 0;
+};
+
+// Material slots of Plan::mat (per internal cell, structure of arrays).
+enum MatSlot : int {
+    kInvRho = 0,  // 1 / rho
+    kStiff = 1,   // fluid: kappa ; solid: lambda + 2 mu
+    kTau = 2,     // eta * tau_T
+    kLam = 3,     // solid: lambda
+    kTwoMu = 4,   // solid: 2 mu
+    kInvTau = 5,  // 1 / (eta * tau_T)
+    kNumMat = 6
+};
+
+// Energy weights per internal cell (float64): fluid (rho, 1/kappa, 0, 0),
+// solid (rho, a, b, c) with the compliance in the E basis [[a, b, 0], [b, a, 0], [0, 0, c]].
+constexpr int kNumEnergyMat = 4;
+
+struct Plan {
+    int k = 1, N = 3, F = 2, S = 1;
+    int n_cells = 0, n_faces = 0, n_vertices = 0;
+    int max_nf = 0;
+    int cpb = 256;           // cells per block
+    int n_ic = 0;            // padded internal cells
+    int64_t n_ext = 0;       // external dofs per shot
+    std::vector<int64_t> ext_off;   // [n_cells+1]
+    std::vector<int> ic_of_cell;    // [n_cells]
+    std::vector<int> cell_of_ic;    // [n_ic], -1 = padding
+    std::vector<uint8_t> medium;    // input media
+    std::vector<ClassInfo> classes;
+    std::vector<double> tables;
+    std::vector<Group> groups;
+    std::vector<int> blk_group;
+    // per (j, ic): link = (ic' << 4) | (interface << 3) | j', -1 = boundary face
+    std::vector<int32_t> link;  // [max_nf][n_ic]
+    std::vector<double> c0;     // [max_nf][n_ic] face-solve coefficient
+    std::vector<double> mat;    // [kNumMat][n_ic]
+    std::vector<double> emat;   // [kNumEnergyMat][n_ic]
+    // geometry needed for point location / evaluation
+    std::vector<double> xy;
+    std::vector<int32_t> cell_ptr, cell_vtx;
+    std::vector<double> centroid;  // [2*n_cells]
+    std::vector<double> hT;        // [n_cells]
+    std::vector<double> basisC;    // [n_classes][N][N] orthonormal basis coefficients (lower)
+    std::vector<int> cell_class;   // [n_cells]
+};
+
+// Returns "" on success, otherwise an error message; *code receives the status code.
+std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr, const int32_t *cell_vtx,
+                       const uint8_t *medium, const double *rho, const double *a, const double *b, int k,
+                       double eta_f, double eta_s, int stab_speed, int n_shots, Plan &plan, int *code);
+
+// Orthonormal cell basis of input cell c at (x, y) -> phi[N].
+void eval_basis(const Plan &plan, int c, double x, double y, double *phi);
+
+// Lowest-id cell whose closed polygon contains (x, y), -1 if none.
+int locate_cell(const Plan &plan, double x, double y);
+
+int trace_rows(const Plan &plan);  // rows of a trace buffer: max_nf * 2 * F
+
+}  // namespace hho

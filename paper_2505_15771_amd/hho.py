@@ -1,0 +1,273 @@
+"""ctypes binding of libhho.so (C ABI in include/hho.h and include/hho_inspect.h).
+
+Argument marshalling only: every step of the explicit Runge-Kutta path runs in the
+HIP kernels of the library.  If the library is not built this module raises; there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhho.so")
+
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_MESH", 3: "ERR_SINGULAR", 4: "ERR_DEVICE", 5: "ERR_OOM",
+          6: "ERR_UNSTABLE"}
+
+
+class HHOError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class Unstable(HHOError):
+    pass
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("xy", C.c_void_p), ("n_cells", C.c_int32),
+                ("cell_ptr", C.c_void_p), ("cell_vtx", C.c_void_p), ("medium", C.c_void_p),
+                ("rho", C.c_void_p), ("a", C.c_void_p), ("b", C.c_void_p)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("k", C.c_int32), ("rk_stages", C.c_int32), ("eta_f", C.c_double), ("eta_s", C.c_double),
+                ("stab_speed", C.c_int32), ("dtype", C.c_int32), ("n_shots", C.c_int32),
+                ("record_energy", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p)]
+
+
+EXPORTS = {
+    # name: (restype, argtypes)
+    "hho_setup": (C.c_int, [C.POINTER(_Mesh), C.POINTER(_Params), C.POINTER(C.c_void_p)]),
+    "hho_destroy": (None, [C.c_void_p]),
+    "hho_last_error": (C.c_char_p, [C.c_void_p]),
+    "hho_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "hho_set_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
+    "hho_get_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
+    "hho_set_sources": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32] + [C.c_void_p] * 5),
+    "hho_set_loads": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hho_receivers": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "hho_erk_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int32]),
+    "hho_synchronize": (C.c_int, [C.c_void_p]),
+    "hho_get_traces": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "hho_energy": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "hho_energy_history": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "hho_inspect_create": (C.c_int, [C.POINTER(_Mesh), C.POINTER(_Params), C.POINTER(C.c_void_p)]),
+    "hho_inspect_destroy": (None, [C.c_void_p]),
+    "hho_inspect_sizes": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "hho_inspect_arrays": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libhho.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libhho.so is not built (%s): run `python -m paper_2505_15771_amd.build`" % path)
+    lib = C.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _mesh_struct(mesh, keep):
+    xy = np.ascontiguousarray(mesh["xy"], np.float64).reshape(-1)
+    arrs = dict(xy=xy,
+                cell_ptr=np.ascontiguousarray(mesh["cell_ptr"], np.int32),
+                cell_vtx=np.ascontiguousarray(mesh["cell_vtx"], np.int32),
+                medium=np.ascontiguousarray(mesh["medium"], np.uint8),
+                rho=np.ascontiguousarray(mesh["rho"], np.float64),
+                a=np.ascontiguousarray(mesh["a"], np.float64),
+                b=np.ascontiguousarray(mesh["b"], np.float64))
+    keep.update(arrs)
+    m = _Mesh()
+    m.n_vertices = len(xy) // 2
+    m.n_cells = len(arrs["cell_ptr"]) - 1
+    for name in ("xy", "cell_ptr", "cell_vtx", "medium", "rho", "a", "b"):
+        setattr(m, name, arrs[name].ctypes.data)
+    return m
+
+
+def _params(k, rk_stages, eta_f, eta_s, stab_speed, dtype, n_shots, record_energy, device, stream):
+    p = _Params()
+    p.k, p.rk_stages, p.eta_f, p.eta_s = int(k), int(rk_stages), float(eta_f), float(eta_s)
+    p.stab_speed = int(stab_speed)
+    p.dtype = {"f64": 0, "float64": 0, 0: 0, "f32": 1, "float32": 1, 1: 1}[dtype]
+    p.n_shots, p.record_energy, p.device = int(n_shots), int(bool(record_energy)), int(device)
+    p.stream = stream
+    return p
+
+
+def _check(lib, code, h):
+    if code != 0:
+        msg = lib.hho_last_error(h).decode()
+        raise (Unstable if code == 6 else HHOError)(code, msg)
+
+
+class Engine:
+    """One discretisation on one GPU (hho_setup); see include/hho.h for the semantics.
+
+    State arrays are float64 in the per-cell layout of hho.h, either numpy arrays
+    (host) or contiguous float64 torch cuda tensors (device)."""
+
+    def __init__(self, mesh, k, rk_stages=4, eta_f=0.8, eta_s=1.5, stab_speed=0, dtype="f64", n_shots=1,
+                 record_energy=False, device=0, stream=None):
+        lib = load_library()
+        self.lib = lib
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    stream = torch.cuda.current_stream(device).cuda_stream
+            except Exception:
+                stream = None
+        self.stream = stream
+        keep = {}
+        m = _mesh_struct(mesh, keep)
+        p = _params(k, rk_stages, eta_f, eta_s, stab_speed, dtype, n_shots, record_energy, device, stream)
+        h = C.c_void_p()
+        _check(lib, lib.hho_setup(C.byref(m), C.byref(p), C.byref(h)), None)
+        self._h = h
+        self.k, self.n_shots, self.record_energy = k, n_shots, record_energy
+        self.medium = keep["medium"].copy()
+        nd, nc, nf = C.c_int64(), C.c_int32(), C.c_int32()
+        self._call(lib.hho_sizes, C.byref(nd), C.byref(nc), C.byref(nf))
+        self.n_dof, self.n_cells, self.n_faces = nd.value, nc.value, nf.value
+        self.n_rec = 0
+        self.last_steps = 0
+
+    def _call(self, fn, *args):
+        _check(self.lib, fn(self._h, *args), self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.hho_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _dev_ptr(t):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            return None
+        if t.dtype != torch.float64 or not t.is_contiguous():
+            raise TypeError("device state must be a contiguous float64 cuda tensor")
+        return C.c_void_p(t.data_ptr())
+
+    def set_state(self, U, shot=0):
+        try:
+            dp = self._dev_ptr(U)
+        except ImportError:
+            dp = None
+        if dp is not None:
+            if U.numel() != self.n_dof:
+                raise ValueError("state has %d values, expected %d" % (U.numel(), self.n_dof))
+            self._call(self.lib.hho_set_state, int(shot), dp, 1)
+            return
+        U = np.ascontiguousarray(U, np.float64).reshape(-1)
+        if U.size != self.n_dof:
+            raise ValueError("state has %d values, expected %d" % (U.size, self.n_dof))
+        self._call(self.lib.hho_set_state, int(shot), _ptr(U), 0)
+
+    def get_state(self, shot=0, out=None):
+        if out is not None:
+            dp = self._dev_ptr(out)
+            if dp is not None:
+                self._call(self.lib.hho_get_state, int(shot), dp, 1)
+                return out
+        U = np.zeros(self.n_dof)
+        self._call(self.lib.hho_get_state, int(shot), _ptr(U), 0)
+        return U
+
+    def set_sources(self, shot, xy, direction, f0, t0, amp):
+        xy = np.ascontiguousarray(np.asarray(xy, np.float64).reshape(-1))
+        n = len(xy) // 2
+        d = np.ascontiguousarray(np.broadcast_to(np.asarray(direction, np.float64), (n, 2)).reshape(-1))
+        arr = lambda v: np.ascontiguousarray(np.broadcast_to(np.asarray(v, np.float64), (n,)))
+        f0, t0, amp = arr(f0), arr(t0), arr(amp)
+        self._call(self.lib.hho_set_sources, int(shot), n, _ptr(xy), _ptr(d), _ptr(f0), _ptr(t0), _ptr(amp))
+
+    def set_loads(self, g, omega, phase):
+        g = np.ascontiguousarray(np.asarray(g, np.float64).reshape(-1))
+        om = np.ascontiguousarray(np.atleast_1d(np.asarray(omega, np.float64)))
+        ph = np.ascontiguousarray(np.atleast_1d(np.asarray(phase, np.float64)))
+        if g.size != len(om) * self.n_dof:
+            raise ValueError("load vectors must hold n_terms * n_dof values")
+        self._call(self.lib.hho_set_loads, len(om), _ptr(g), _ptr(om), _ptr(ph))
+
+    def set_receivers(self, xy, field):
+        xy = np.ascontiguousarray(np.asarray(xy, np.float64).reshape(-1))
+        fld = np.ascontiguousarray(np.asarray(field, np.int32).reshape(-1))
+        self._call(self.lib.hho_receivers, len(fld), _ptr(xy), _ptr(fld))
+        self.n_rec = len(fld)
+
+    def erk_step(self, t0, dt, n_steps):
+        self._call(self.lib.hho_erk_step, float(t0), float(dt), int(n_steps))
+        self.last_steps = int(n_steps)
+
+    def synchronize(self):
+        self._call(self.lib.hho_synchronize)
+
+    def traces(self, shot=0):
+        out = np.zeros((self.last_steps, self.n_rec, 2))
+        if self.n_rec and self.last_steps:
+            self._call(self.lib.hho_get_traces, int(shot), _ptr(out))
+        return out
+
+    def energy(self):
+        E = np.zeros(self.n_shots)
+        self._call(self.lib.hho_energy, _ptr(E))
+        return E
+
+    def energy_history(self, shot=0):
+        E = np.zeros(max(self.last_steps, 1))
+        self._call(self.lib.hho_energy_history, int(shot), _ptr(E))
+        return E[:self.last_steps]
+
+
+class Inspect:
+    """Host-only view of the execution plan (include/hho_inspect.h)."""
+
+    def __init__(self, mesh, k, eta_f=0.8, eta_s=1.5, stab_speed=0, n_shots=1):
+        lib = load_library()
+        self.lib = lib
+        keep = {}
+        m = _mesh_struct(mesh, keep)
+        p = _params(k, 4, eta_f, eta_s, stab_speed, "f64", n_shots, False, 0, None)
+        h = C.c_void_p()
+        _check(lib, lib.hho_inspect_create(C.byref(m), C.byref(p), C.byref(h)), None)
+        self._h = h
+        sz = np.zeros(10, np.int64)
+        lib.hho_inspect_sizes(h, _ptr(sz))
+        (self.N, self.F, self.n_ic, self.max_nf, self.n_groups, ntab, self.n_cells, self.n_faces, self.cpb,
+         self.n_blocks) = (int(v) for v in sz)
+        self.tables = np.zeros(ntab)
+        self.groups = np.zeros((self.n_groups, 6), np.int32)
+        self.link = np.zeros((self.max_nf, self.n_ic), np.int32)
+        self.c0 = np.zeros((self.max_nf, self.n_ic))
+        self.mat = np.zeros((6, self.n_ic))
+        self.ic_of_cell = np.zeros(self.n_cells, np.int32)
+        lib.hho_inspect_arrays(h, _ptr(self.tables), _ptr(self.groups), _ptr(self.link), _ptr(self.c0),
+                               _ptr(self.mat), _ptr(self.ic_of_cell))
+        lib.hho_inspect_destroy(h)
+        self._h = None

@@ -1,0 +1,210 @@
+"""GPU parity of the HIP path (libhho.so through its C ABI) against the FP64 oracle.
+
+Tolerances (relative L2 of the cell unknowns, and of energies and receiver traces):
+1e-12 when stepping in float64, 1e-5 when stepping in float32 (factors formed in
+float64 and rounded, energy in float64).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from synth import meshes as M
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def engine(mesh, k, **kw):
+    from paper_2505_15771_amd import Engine
+    return Engine(mesh, k, **kw)
+
+
+def oracle(mesh, k, **kw):
+    from oracle import Oracle
+    return Oracle(mesh, k, **kw)
+
+
+def test_manufactured_16x16_k1_200_steps():
+    """Unit square 16 x 16 quads, interface y = 1/2, k = 1, RK4, dt = 0.5 * 0.282 * h / sqrt(3),
+    200 steps from the projected manufactured solution with its separable forcing."""
+    from oracle.manufactured import Manufactured
+    say("case: manufactured 16x16 k=1 200 steps fp64")
+    mesh = M.manufactured_square(16)
+    o = oracle(mesh, 1)
+    ms = Manufactured(omega=1, theta=math.sqrt(2.0), phase=float(np.random.default_rng(1001).uniform(0, 2 * np.pi)))
+    U0 = o.project(*ms.fields(0.0))
+    terms, om, ph = ms.forcing_terms()
+    g = np.stack([o.load_vector(*tm) for tm in terms])
+    o.set_dense_load(g, om, ph)
+    dt = 0.5 * 0.282 * (1.0 / 16) / math.sqrt(3.0)
+    ref = o.erk(U0, 0.0, dt, 200)
+    e = engine(mesh, 1)
+    e.set_loads(g, om, ph)
+    e.set_state(U0)
+    e.erk_step(0.0, dt, 200)
+    got = e.get_state()
+    err = rel(got, ref)
+    say("rel L2 =", err)
+    assert err < TOL64
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("s", [2, 3, 4])
+def test_random_state_hanging_hybrid(k, s):
+    """Hybrid mesh with 2:1 hanging nodes (pentagons, quadrilateral triangles) and the
+    interface, perturbed materials, random state: ERK(s) steps match the oracle."""
+    say("case: hanging hybrid k=%d s=%d fp64" % (k, s))
+    mesh = M.with_materials(M.unit_square(10, p_split=0.5, seed=7,
+                                          refine=np.random.default_rng(8).random((10, 10)) < 0.3),
+                            perturb=0.1, seed=9)
+    o = oracle(mesh, k)
+    U0 = np.random.default_rng(k * 10 + s).standard_normal(o.ndof)
+    dt = 0.3 * 0.087 * 0.05 / math.sqrt(3.0)
+    ref = o.erk(U0, 0.0, dt, 7, s=s)
+    e = engine(mesh, k, rk_stages=s)
+    e.set_state(U0)
+    e.erk_step(0.0, dt, 7)
+    err = rel(e.get_state(), ref)
+    say("rel L2 =", err)
+    assert err < TOL64
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_float32_stepping(k):
+    """float32 matvecs and accumulation against the float64 oracle."""
+    say("case: fp32 k=%d" % k)
+    mesh = M.with_materials(M.unit_square(12, p_split=0.5, seed=3), perturb=0.1, seed=4)
+    o = oracle(mesh, k)
+    U0 = o.project([lambda x, y: np.sin(3 * x) * np.cos(2 * y), lambda x, y: x * y, lambda x, y: np.cos(x)],
+                   [lambda x, y: np.sin(2 * y), lambda x, y: x - y, lambda x, y: x * x, lambda x, y: y,
+                    lambda x, y: np.sin(x + y)])
+    dt = 0.4 * 0.087 / 12 / math.sqrt(3.0)
+    ref = o.erk(U0, 0.0, dt, 50)
+    e = engine(mesh, k, dtype="f32")
+    e.set_state(U0)
+    e.erk_step(0.0, dt, 50)
+    err = rel(e.get_state(), ref)
+    say("rel L2 =", err)
+    assert err < TOL32
+
+
+def test_multishot_sources_receivers_energy():
+    """Three shots (a lane count that is not a power of two) with different initial states and
+    Ricker point sources; receivers record p in the fluid and v in the solid after every step;
+    energies per step; all against the oracle shot by shot."""
+    say("case: 3 shots, sources, receivers, energy")
+    k = 2
+    mesh = M.with_materials(M.unit_square(8, p_split=0.5, seed=11), perturb=0.1, seed=12)
+    rx = np.array([[0.31, 0.77], [0.62, 0.91], [0.45, 0.21], [0.83, 0.33]])
+    fld = np.array([0, 0, 1, 1], np.int32)
+    srcs = [np.array([[0.5, 0.25]]), np.array([[0.3, 0.7]]), np.array([[0.71, 0.12], [0.2, 0.3]])]
+    dirs = [np.array([[0.0, 1.0]]), np.array([[1.0, 0.0]]), np.array([[0.6, -0.8], [1.0, 0.0]])]
+    dt = 0.5 * 0.138 / 8 / math.sqrt(3.0)
+    nsteps = 30
+    e = engine(mesh, k, n_shots=3, record_energy=True)
+    e.set_receivers(rx, fld)
+    refs = []
+    for sh in range(3):
+        o = oracle(mesh, k)
+        U0 = 0.1 * np.random.default_rng(50 + sh).standard_normal(o.ndof)
+        o.set_point_sources(srcs[sh], dirs[sh], 10.0, 0.12, 1.0 + sh)
+        e.set_sources(sh, srcs[sh], dirs[sh], 10.0, 0.12, 1.0 + sh)
+        e.set_state(U0, shot=sh)
+        U = U0.copy()
+        tr = np.zeros((nsteps, 4, 2))
+        En = np.zeros(nsteps)
+        for n in range(nsteps):
+            U = o.erk(U, n * dt, dt, 1)
+            En[n] = o.energy(U)
+            for r in range(4):
+                c, vals = o.point_values(U, *rx[r])
+                tr[n, r, :(1 if fld[r] == 0 else 2)] = vals[:1] if fld[r] == 0 else vals[:2]
+        refs.append((U, tr, En))
+    e.erk_step(0.0, dt, nsteps)
+    E_now = e.energy()
+    for sh in range(3):
+        U, tr, En = refs[sh]
+        err_u = rel(e.get_state(sh), U)
+        err_t = rel(e.traces(sh), tr)
+        err_e = rel(e.energy_history(sh), En)
+        say("shot", sh, "state", err_u, "traces", err_t, "energy", err_e)
+        assert err_u < TOL64 and err_t < TOL64 and err_e < TOL64
+        assert abs(E_now[sh] - En[-1]) < TOL64 * En[-1]
+
+
+def test_single_cell_and_zero_steps():
+    """Degenerate inputs: one fluid triangle (all faces on the boundary), zero steps."""
+    say("case: single cell")
+    mesh = M.with_materials(dict(xy=np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]]),
+                                 cell_ptr=np.array([0, 3], np.int32), cell_vtx=np.array([0, 1, 2], np.int32),
+                                 medium=np.array([0], np.uint8)))
+    o = oracle(mesh, 3)
+    U0 = np.random.default_rng(2).standard_normal(o.ndof)
+    e = engine(mesh, 3)
+    e.set_state(U0)
+    e.erk_step(0.0, 1e-3, 0)
+    assert rel(e.get_state(), U0) == 0.0
+    e.erk_step(0.0, 1e-3, 5)
+    assert rel(e.get_state(), o.erk(U0, 0.0, 1e-3, 5)) < TOL64
+
+
+def test_device_pointer_state():
+    """State handed over as float64 torch cuda tensors (device pointers through the C ABI)."""
+    import torch
+    say("case: device pointers")
+    mesh = M.with_materials(M.unit_square(6, p_split=0.5, seed=1))
+    o = oracle(mesh, 2)
+    U0 = np.random.default_rng(3).standard_normal(o.ndof)
+    e = engine(mesh, 2)
+    e.set_state(torch.tensor(U0, device="cuda:0"))
+    e.erk_step(0.0, 1e-3, 3)
+    out = torch.zeros(o.ndof, dtype=torch.float64, device="cuda:0")
+    e.get_state(out=out)
+    torch.cuda.synchronize()
+    assert rel(out.cpu().numpy(), o.erk(U0, 0.0, 1e-3, 3)) < TOL64
+
+
+def test_unstable_time_step_is_reported():
+    """Energy criterion of Algorithm algo_CFL: a time step far above the CFL limit makes the
+    lossless run blow up and hho_erk_step returns HHO_ERR_UNSTABLE."""
+    from paper_2505_15771_amd import Unstable
+    say("case: unstable dt")
+    mesh = M.manufactured_square(8)
+    e = engine(mesh, 1, record_energy=True)
+    e.set_state(np.random.default_rng(5).standard_normal(e.n_dof))
+    with pytest.raises(Unstable):
+        e.erk_step(0.0, 3.0 * 0.282 / 8 / math.sqrt(3.0), 200)
+
+
+@pytest.mark.parametrize("k,dtype", [(2, "f64"), (2, "f32"), (3, "f64")])
+def test_full_size_hybrid_256(k, dtype):
+    """The 256 x 256 hybrid workload (random quads / split triangles, materials +-10 %)
+    in the launch configuration the benchmark times: a few RK4 steps from a smooth state,
+    compared with the oracle on the whole mesh."""
+    say("case: full-size hybrid 256 k=%d %s" % (k, dtype))
+    mesh = M.hybrid_square(256)
+    o = oracle(mesh, k)
+    U0 = np.random.default_rng(2002).standard_normal(o.ndof)
+    cmax = M.max_wave_speed(mesh)
+    cfl = {1: 0.265, 2: 0.138, 3: 0.087}[k]
+    dt = 0.5 * cfl * (1.0 / 256) / cmax
+    ref = o.erk(U0, 0.0, dt, 3)
+    e = engine(mesh, k, dtype=dtype)
+    e.set_state(U0)
+    e.erk_step(0.0, dt, 3)
+    err = rel(e.get_state(), ref)
+    say("rel L2 =", err)
+    assert err < (TOL64 if dtype == "f64" else TOL32)
