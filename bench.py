@@ -159,7 +159,7 @@ def main():
         "dtype": head["dtype"],
         "data": "synthetic",
         "config": {"workload": "two-material unit square, 256x256 hybrid quad/triangle mesh (seed 2001), "
-                               "materials +-10% (seed 2002), HHO k=%d, RK4, Ricker point source" % args.k,
+                               "materials +-10 percent (seed 2002), HHO k=%d, RK4, Ricker point source" % args.k,
                    "cells": int(len(mesh["cell_ptr"]) - 1), "cell_dofs": head["ndof"], "shots": args.shots},
         "roofline": {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": head["frac"], "traffic": None, "kernel": "stage_kernel",

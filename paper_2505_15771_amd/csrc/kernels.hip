@@ -1,10 +1,11 @@
 // HIP kernels (gfx950) of one explicit Runge-Kutta stage of the HHO elasto-acoustic
 // semi-discretisation with the face unknowns eliminated (Sec. 4.2, eq. ex_solve).
 //
-// One lane = one (cell, shot).  Cells are grouped by (medium, shape class) so that a
-// workgroup reads one class table (uniform addresses -> scalar loads) and runs one code
-// path.  The state is structure-of-arrays, [row][lane], so every row load and store of
-// a wavefront is coalesced.
+// One lane = one (cell, shot).  Cells are grouped by (medium, shape class): a workgroup
+// holds cells of one group, so its class table has uniform addresses and is read with
+// scalar loads through the constant address space, and the (medium, face count) code
+// path is uniform.  The state is structure-of-arrays, [row][lane], so every row load and
+// store of a wavefront is coalesced.
 //
 // Fused stage, for every cell T of the group (bases orthonormal, so the cell and face
 // mass matrices are identities):
@@ -24,6 +25,8 @@
 #include "device.h"
 #include "plan.h"
 
+#define HHO_CONST __attribute__((address_space(4)))
+
 namespace hho {
 
 namespace {
@@ -33,6 +36,13 @@ struct Dim {
     static constexpr int N = (K + 1) * (K + 2) / 2;
     static constexpr int F = K + 1;
 };
+
+// Read-only data with wavefront-uniform addresses: the constant address space lets the
+// compiler use scalar loads.
+template <typename T>
+__device__ __forceinline__ const HHO_CONST T *uni(const T *p) {
+    return (const HHO_CONST T *)p;
+}
 
 template <typename R>
 __device__ __forceinline__ R sgn(int i) {
@@ -44,29 +54,46 @@ __device__ __forceinline__ double ricker(double t, double f0, double t0) {
     return (1.0 - 2.0 * a * a) * exp(-a * a);
 }
 
+struct LaneInfo {
+    int ic, shot;
+    long long lane;
+    bool active;
+};
+
 template <typename R>
-__device__ __forceinline__ void decode_lane(const StageArgs<R> &a, GroupDev &G, int &ic, int &shot, long long &lane,
-                                            bool &active) {
-    G = a.groups[a.blk_group[blockIdx.x]];
+__device__ __forceinline__ LaneInfo decode_lane(const StageArgs<R> &a, GroupDev &G) {
+    const int g = uni(a.blk_group)[blockIdx.x];
+    const HHO_CONST GroupDev *gd = uni(a.groups) + g;
+    G.medium = gd->medium;
+    G.nF = gd->nF;
+    G.tab_off = gd->tab_off;
+    G.ic_begin = gd->ic_begin;
+    G.ncells = gd->ncells;
+    G.blk_begin = gd->blk_begin;
+    LaneInfo L;
     const int tid = threadIdx.x;
     const int cl = tid / a.S;
-    shot = tid - cl * a.S;
+    L.shot = tid - cl * a.S;
     const int l = (blockIdx.x - G.blk_begin) * a.cpb + cl;
-    active = l < G.ncells;
-    ic = G.ic_begin + l;
-    lane = (long long)ic * a.S + shot;
+    L.active = l < G.ncells;
+    L.ic = G.ic_begin + l;
+    L.lane = (long long)L.ic * a.S + L.shot;
+    return L;
 }
 
-// ------------------------------------------------------------------------- fluid cells
-template <int K, typename R>
-__device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const GroupDev &G, int ic, long long lane,
-                                             const R *p, const R *mx, const R *my, R tau) {
+constexpr double kRsqrt2 = 0.70710678118654752440;
+
+// ------------------------------------------------------------------------- traces
+// Own trace contributions of a fluid state on every non-boundary face.
+template <int K, int NF, typename R>
+__device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const HHO_CONST R *tb, int nF,
+                                             const int *lk, long long lane, const R *p, const R *mx, const R *my, R tau) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
-    const R *Gt = a.tab + G.tab_off + 3 * N * N;
-    const R *nr = Gt + G.nF * N * F;
-    for (int j = 0; j < G.nF; ++j) {
-        if (a.link[(long long)j * a.n_ic + ic] < 0) continue;
-        const R *Gj = Gt + j * N * F;
+    const HHO_CONST R *Gt = tb + 3 * N * N;
+    const HHO_CONST R *nr = Gt + nF * N * F;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        if (lk[j] < 0) continue;
         const R nx = nr[2 * j], ny = nr[2 * j + 1];
         R r[F];
 #pragma unroll
@@ -75,24 +102,101 @@ __device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const GroupD
         for (int b = 0; b < N; ++b) {
             const R q = tau * p[b] - (nx * mx[b] + ny * my[b]);
 #pragma unroll
-            for (int i = 0; i < F; ++i) r[i] += Gj[b * F + i] * q;
+            for (int i = 0; i < F; ++i) r[i] += Gt[(j * N + b) * F + i] * q;
         }
 #pragma unroll
         for (int i = 0; i < F; ++i) a.Tout[((long long)(j * 2) * F + i) * a.LT + lane] = r[i];
     }
 }
 
-template <int K, typename R>
-__device__ void fluid_stage(const StageArgs<R> &a, const GroupDev &G, int ic, int shot, long long lane,
-                            double *energy) {
+template <int K, int NF, typename R>
+__device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const HHO_CONST R *tb, int nF,
+                                             const int *lk, long long lane, const R *vx, const R *vy, const R *s1, const R *s2,
+                                             const R *s3, R tau) {
+    constexpr int N = Dim<K>::N, F = Dim<K>::F;
+    const R r2 = R(kRsqrt2);
+    const HHO_CONST R *Gt = tb + 3 * N * N;
+    const HHO_CONST R *nr = Gt + nF * N * F;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        if (lk[j] < 0) continue;
+        const R nx = nr[2 * j], ny = nr[2 * j + 1];
+        R rx[F], ry[F];
+#pragma unroll
+        for (int i = 0; i < F; ++i) rx[i] = ry[i] = R(0);
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            const R qx = tau * vx[b] - (nx * s1[b] + r2 * ny * s3[b]);
+            const R qy = tau * vy[b] - (r2 * nx * s3[b] + ny * s2[b]);
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                rx[i] += Gt[(j * N + b) * F + i] * qx;
+                ry[i] += Gt[(j * N + b) * F + i] * qy;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < F; ++i) {
+            a.Tout[((long long)(j * 2) * F + i) * a.LT + lane] = rx[i];
+            a.Tout[((long long)(j * 2 + 1) * F + i) * a.LT + lane] = ry[i];
+        }
+    }
+}
+
+// Links of every local face and the neighbour trace contributions (both components;
+// the second only where it is needed), issued before any arithmetic.
+// The link and coefficient arrays hold one row per face of the largest cell of the mesh:
+// rows j >= nF of this group are never read (their links count as -1).
+template <int K, int NF, typename R>
+__device__ __forceinline__ void load_faces(const StageArgs<R> &a, int medium, int nF, int ic, int shot, int *lk,
+                                           R *cc, R (*rn)[2][Dim<K>::F], R *its) {
+    constexpr int F = Dim<K>::F;
+    const int nic = a.n_ic;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        lk[j] = -1;
+        cc[j] = R(0);
+        if (j < nF) {
+            lk[j] = a.link[(long long)j * nic + ic];
+            cc[j] = a.c0[(long long)j * nic + ic];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        its[j] = R(0);
+#pragma unroll
+        for (int i = 0; i < F; ++i) rn[j][0][i] = rn[j][1][i] = R(0);
+        if (lk[j] < 0) continue;
+        const int icn = lk[j] >> 4, jn = lk[j] & 7;
+        const bool iface = (lk[j] >> 3) & 1;
+        const long long nl = (long long)icn * a.S + shot;
+        const R *t0 = a.Tin + (long long)(jn * 2) * F * a.LT + nl;
+#pragma unroll
+        for (int i = 0; i < F; ++i) rn[j][0][i] = sgn<R>(i) * t0[(long long)i * a.LT];
+        // second component: solid neighbours (same-medium solid face, or interface seen from the fluid)
+        if (medium == kSolid ? !iface : iface) {
+            const R *t1 = t0 + (long long)F * a.LT;
+#pragma unroll
+            for (int i = 0; i < F; ++i) rn[j][1][i] = sgn<R>(i) * t1[(long long)i * a.LT];
+        }
+        if (iface && medium == kFluid) its[j] = a.mat[(long long)kInvTau * nic + icn];
+    }
+}
+
+// ------------------------------------------------------------------------- fluid cells
+template <int K, int NF, typename R>
+__device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const HHO_CONST R *tb, int nF, int ic, int shot,
+                                            long long lane, double *energy) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
     const long long LT = a.LT;
     const int nic = a.n_ic;
-    const R *Bx = a.tab + G.tab_off;
-    const R *By = Bx + N * N;
-    const R *Sm = By + N * N;
-    const R *Gt = Sm + N * N;
-    const R *nr = Gt + G.nF * N * F;
+    const HHO_CONST R *Bx = tb;
+    const HHO_CONST R *By = tb + N * N;
+    const HHO_CONST R *Sm = tb + 2 * N * N;
+    const HHO_CONST R *Gt = tb + 3 * N * N;
+    const HHO_CONST R *nr = Gt + nF * N * F;
+    int lk[NF];
+    R cc[NF], its[NF], rn[NF][2][F];
+    load_faces<K, NF, R>(a, kFluid, nF, ic, shot, lk, cc, rn, its);
     R p[N], mx[N], my[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
@@ -101,24 +205,26 @@ __device__ void fluid_stage(const StageArgs<R> &a, const GroupDev &G, int ic, in
         my[b] = a.Yin[(long long)(2 * N + b) * LT + lane];
     }
     const R tau = a.mat[(long long)kTau * nic + ic];
+    const R kap = a.mat[(long long)kStiff * nic + ic];
+    const R irho = a.mat[(long long)kInvRho * nic + ic];
     R rp[N], rmx[N], rmy[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-        R sx = 0, sy = 0, sp = 0;
+        R sx = 0, sy = 0, sd = 0, ss = 0;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             sx += Bx[r * N + b] * p[b];
             sy += By[r * N + b] * p[b];
-            sp += Bx[b * N + r] * mx[b] + By[b * N + r] * my[b] + tau * Sm[r * N + b] * p[b];
+            sd += Bx[b * N + r] * mx[b] + By[b * N + r] * my[b];
+            ss += Sm[r * N + b] * p[b];
         }
         rmx[r] = sx;
         rmy[r] = sy;
-        rp[r] = -sp;
+        rp[r] = -(sd + tau * ss);
     }
-    for (int j = 0; j < G.nF; ++j) {
-        const int lk = a.link[(long long)j * nic + ic];
-        if (lk < 0) continue;  // boundary face: p_F = 0 (homogeneous Dirichlet)
-        const R *Gj = Gt + j * N * F;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        if (lk[j] < 0) continue;  // boundary face: p_F = 0 (homogeneous Dirichlet)
         const R nx = nr[2 * j], ny = nr[2 * j + 1];
         R r[F];
 #pragma unroll
@@ -127,31 +233,22 @@ __device__ void fluid_stage(const StageArgs<R> &a, const GroupDev &G, int ic, in
         for (int b = 0; b < N; ++b) {
             const R q = tau * p[b] - (nx * mx[b] + ny * my[b]);
 #pragma unroll
-            for (int i = 0; i < F; ++i) r[i] += Gj[b * F + i] * q;
+            for (int i = 0; i < F; ++i) r[i] += Gt[(j * N + b) * F + i] * q;
         }
-        const int icn = lk >> 4, jn = lk & 7;
-        const long long nl = (long long)icn * a.S + shot;
-        const R cc = a.c0[(long long)j * nic + ic];
         R pF[F];
-        if (!((lk >> 3) & 1)) {
+        if (!((lk[j] >> 3) & 1)) {
 #pragma unroll
-            for (int i = 0; i < F; ++i)
-                pF[i] = (r[i] + sgn<R>(i) * a.Tin[((long long)(jn * 2) * F + i) * LT + nl]) * cc;
+            for (int i = 0; i < F; ++i) pF[i] = (r[i] + rn[j][0][i]) * cc[j];
         } else {
-            // interface: neighbour is solid, n_G = -n_T; eliminate v_F
-            const R its = a.mat[(long long)kInvTau * nic + icn];
+            // interface, neighbour solid: n_G = -n_T, eliminate v_F
 #pragma unroll
-            for (int i = 0; i < F; ++i) {
-                const R rsx = sgn<R>(i) * a.Tin[((long long)(jn * 2) * F + i) * LT + nl];
-                const R rsy = sgn<R>(i) * a.Tin[((long long)(jn * 2 + 1) * F + i) * LT + nl];
-                pF[i] = (r[i] + (nx * rsx + ny * rsy) * its) * cc;
-            }
+            for (int i = 0; i < F; ++i) pF[i] = (r[i] + (nx * rn[j][0][i] + ny * rn[j][1][i]) * its[j]) * cc[j];
         }
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             R w = 0;
 #pragma unroll
-            for (int i = 0; i < F; ++i) w += Gj[b * F + i] * pF[i];
+            for (int i = 0; i < F; ++i) w += Gt[(j * N + b) * F + i] * pF[i];
             rmx[b] += nx * w;
             rmy[b] += ny * w;
             rp[b] += tau * w;
@@ -180,8 +277,6 @@ __device__ void fluid_stage(const StageArgs<R> &a, const GroupDev &G, int ic, in
         }
     }
     // k = M^{-1} R and the Runge-Kutta combine
-    const R kap = a.mat[(long long)kStiff * nic + ic];
-    const R irho = a.mat[(long long)kInvRho * nic + ic];
     R np[N], nmx[N], nmy[N];
 #pragma unroll
     for (int row = 0; row < 3 * N; ++row) {
@@ -204,7 +299,7 @@ __device__ void fluid_stage(const StageArgs<R> &a, const GroupDev &G, int ic, in
         else if (blk == 1) nmx[b] = out;
         else nmy[b] = out;
     }
-    fluid_traces<K, R>(a, G, ic, lane, np, nmx, nmy, tau);
+    fluid_traces<K, NF, R>(a, tb, nF, lk, lane, np, nmx, nmy, tau);
     if (a.last) {
         if (energy) {
             double sp = 0, sm = 0;
@@ -231,53 +326,21 @@ __device__ void fluid_stage(const StageArgs<R> &a, const GroupDev &G, int ic, in
 }
 
 // ------------------------------------------------------------------------- solid cells
-constexpr double kRsqrt2 = 0.70710678118654752440;
-
-template <int K, typename R>
-__device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const GroupDev &G, int ic, long long lane,
-                                             const R *vx, const R *vy, const R *s1, const R *s2, const R *s3,
-                                             R tau) {
-    constexpr int N = Dim<K>::N, F = Dim<K>::F;
-    const R r2 = R(kRsqrt2);
-    const R *Gt = a.tab + G.tab_off + 3 * N * N;
-    const R *nr = Gt + G.nF * N * F;
-    for (int j = 0; j < G.nF; ++j) {
-        if (a.link[(long long)j * a.n_ic + ic] < 0) continue;
-        const R *Gj = Gt + j * N * F;
-        const R nx = nr[2 * j], ny = nr[2 * j + 1];
-        R rx[F], ry[F];
-#pragma unroll
-        for (int i = 0; i < F; ++i) rx[i] = ry[i] = R(0);
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-            const R qx = tau * vx[b] - (nx * s1[b] + r2 * ny * s3[b]);
-            const R qy = tau * vy[b] - (r2 * nx * s3[b] + ny * s2[b]);
-#pragma unroll
-            for (int i = 0; i < F; ++i) {
-                rx[i] += Gj[b * F + i] * qx;
-                ry[i] += Gj[b * F + i] * qy;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < F; ++i) {
-            a.Tout[((long long)(j * 2) * F + i) * a.LT + lane] = rx[i];
-            a.Tout[((long long)(j * 2 + 1) * F + i) * a.LT + lane] = ry[i];
-        }
-    }
-}
-
-template <int K, typename R>
-__device__ void solid_stage(const StageArgs<R> &a, const GroupDev &G, int ic, int shot, long long lane,
-                            double *energy) {
+template <int K, int NF, typename R>
+__device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const HHO_CONST R *tb, int nF, int ic, int shot,
+                                            long long lane, double *energy) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
     const long long LT = a.LT;
     const int nic = a.n_ic;
     const R r2 = R(kRsqrt2);
-    const R *Bx = a.tab + G.tab_off;
-    const R *By = Bx + N * N;
-    const R *Sm = By + N * N;
-    const R *Gt = Sm + N * N;
-    const R *nr = Gt + G.nF * N * F;
+    const HHO_CONST R *Bx = tb;
+    const HHO_CONST R *By = tb + N * N;
+    const HHO_CONST R *Sm = tb + 2 * N * N;
+    const HHO_CONST R *Gt = tb + 3 * N * N;
+    const HHO_CONST R *nr = Gt + nF * N * F;
+    int lk[NF];
+    R cc[NF], its[NF], rn[NF][2][F];
+    load_faces<K, NF, R>(a, kSolid, nF, ic, shot, lk, cc, rn, its);
     R vx[N], vy[N], s1[N], s2[N], s3[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
@@ -289,10 +352,14 @@ __device__ void solid_stage(const StageArgs<R> &a, const GroupDev &G, int ic, in
     }
     const R tau = a.mat[(long long)kTau * nic + ic];
     const R itau = a.mat[(long long)kInvTau * nic + ic];
+    const R irho = a.mat[(long long)kInvRho * nic + ic];
+    const R l2m = a.mat[(long long)kStiff * nic + ic];
+    const R lam = a.mat[(long long)kLam * nic + ic];
+    const R tmu = a.mat[(long long)kTwoMu * nic + ic];
     R rvx[N], rvy[N], rs1[N], rs2[N], rs3[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-        R a1 = 0, a2 = 0, a3 = 0, bx = 0, by = 0;
+        R a1 = 0, a2 = 0, a3 = 0, bx = 0, by = 0, sx = 0, sy = 0;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             const R bxrb = Bx[r * N + b], byrb = By[r * N + b];
@@ -300,19 +367,20 @@ __device__ void solid_stage(const StageArgs<R> &a, const GroupDev &G, int ic, in
             a1 += bxrb * vx[b];
             a2 += byrb * vy[b];
             a3 += byrb * vx[b] + bxrb * vy[b];
-            bx += bxbr * s1[b] + r2 * bybr * s3[b] + tau * srb * vx[b];
-            by += bybr * s2[b] + r2 * bxbr * s3[b] + tau * srb * vy[b];
+            bx += bxbr * s1[b] + bybr * (r2 * s3[b]);
+            by += bybr * s2[b] + bxbr * (r2 * s3[b]);
+            sx += srb * vx[b];
+            sy += srb * vy[b];
         }
         rs1[r] = a1;
         rs2[r] = a2;
         rs3[r] = r2 * a3;
-        rvx[r] = -bx;
-        rvy[r] = -by;
+        rvx[r] = -(bx + tau * sx);
+        rvy[r] = -(by + tau * sy);
     }
-    for (int j = 0; j < G.nF; ++j) {
-        const int lk = a.link[(long long)j * nic + ic];
-        if (lk < 0) continue;  // boundary face: v_F = 0 (homogeneous Dirichlet)
-        const R *Gj = Gt + j * N * F;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        if (lk[j] < 0) continue;  // boundary face: v_F = 0 (homogeneous Dirichlet)
         const R nx = nr[2 * j], ny = nr[2 * j + 1];
         R rx[F], ry[F];
 #pragma unroll
@@ -323,26 +391,22 @@ __device__ void solid_stage(const StageArgs<R> &a, const GroupDev &G, int ic, in
             const R qy = tau * vy[b] - (r2 * nx * s3[b] + ny * s2[b]);
 #pragma unroll
             for (int i = 0; i < F; ++i) {
-                rx[i] += Gj[b * F + i] * qx;
-                ry[i] += Gj[b * F + i] * qy;
+                rx[i] += Gt[(j * N + b) * F + i] * qx;
+                ry[i] += Gt[(j * N + b) * F + i] * qy;
             }
         }
-        const int icn = lk >> 4, jn = lk & 7;
-        const long long nl = (long long)icn * a.S + shot;
-        const R cc = a.c0[(long long)j * nic + ic];
         R vFx[F], vFy[F];
-        if (!((lk >> 3) & 1)) {
+        if (!((lk[j] >> 3) & 1)) {
 #pragma unroll
             for (int i = 0; i < F; ++i) {
-                vFx[i] = (rx[i] + sgn<R>(i) * a.Tin[((long long)(jn * 2) * F + i) * LT + nl]) * cc;
-                vFy[i] = (ry[i] + sgn<R>(i) * a.Tin[((long long)(jn * 2 + 1) * F + i) * LT + nl]) * cc;
+                vFx[i] = (rx[i] + rn[j][0][i]) * cc[j];
+                vFy[i] = (ry[i] + rn[j][1][i]) * cc[j];
             }
         } else {
-            // interface: neighbour is fluid, n_G = n_T; eliminate p_F then v_F
+            // interface, neighbour fluid: n_G = n_T, eliminate p_F then v_F
 #pragma unroll
             for (int i = 0; i < F; ++i) {
-                const R rf = sgn<R>(i) * a.Tin[((long long)(jn * 2) * F + i) * LT + nl];
-                const R pF = (rf - (nx * rx[i] + ny * ry[i]) * itau) * cc;
+                const R pF = (rn[j][0][i] - (nx * rx[i] + ny * ry[i]) * itau) * cc[j];
                 vFx[i] = (rx[i] + nx * pF) * itau;
                 vFy[i] = (ry[i] + ny * pF) * itau;
             }
@@ -352,8 +416,8 @@ __device__ void solid_stage(const StageArgs<R> &a, const GroupDev &G, int ic, in
             R wx = 0, wy = 0;
 #pragma unroll
             for (int i = 0; i < F; ++i) {
-                wx += Gj[b * F + i] * vFx[i];
-                wy += Gj[b * F + i] * vFy[i];
+                wx += Gt[(j * N + b) * F + i] * vFx[i];
+                wy += Gt[(j * N + b) * F + i] * vFy[i];
             }
             rs1[b] += nx * wx;
             rs2[b] += ny * wy;
@@ -389,10 +453,6 @@ __device__ void solid_stage(const StageArgs<R> &a, const GroupDev &G, int ic, in
             e = s.next;
         }
     }
-    const R irho = a.mat[(long long)kInvRho * nic + ic];
-    const R l2m = a.mat[(long long)kStiff * nic + ic];
-    const R lam = a.mat[(long long)kLam * nic + ic];
-    const R tmu = a.mat[(long long)kTwoMu * nic + ic];
     R nvx[N], nvy[N], ns1[N], ns2[N], ns3[N];
 #pragma unroll
     for (int row = 0; row < 5 * N; ++row) {
@@ -425,17 +485,17 @@ __device__ void solid_stage(const StageArgs<R> &a, const GroupDev &G, int ic, in
             default: ns3[b] = out; break;
         }
     }
-    solid_traces<K, R>(a, G, ic, lane, nvx, nvy, ns1, ns2, ns3, tau);
+    solid_traces<K, NF, R>(a, tb, nF, lk, lane, nvx, nvy, ns1, ns2, ns3, tau);
     if (a.last) {
         if (energy) {
             const double ca = a.emat[(long long)1 * nic + ic], cb = a.emat[(long long)2 * nic + ic];
-            const double cc = a.emat[(long long)3 * nic + ic];
+            const double c3 = a.emat[(long long)3 * nic + ic];
             double sv = 0, ss = 0;
 #pragma unroll
             for (int b = 0; b < N; ++b) {
                 const double x1 = ns1[b], x2 = ns2[b], x3 = ns3[b];
                 sv += (double)nvx[b] * (double)nvx[b] + (double)nvy[b] * (double)nvy[b];
-                ss += ca * (x1 * x1 + x2 * x2) + 2.0 * cb * x1 * x2 + cc * x3 * x3;
+                ss += ca * (x1 * x1 + x2 * x2) + 2.0 * cb * x1 * x2 + c3 * x3 * x3;
             }
             *energy = 0.5 * (a.emat[ic] * sv + ss);
         }
@@ -469,52 +529,58 @@ __device__ void block_energy(double e, int S, int cpb, double *out) {
     }
 }
 
+template <int K, int NF, typename R>
+__device__ __forceinline__ void stage_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L, double *e) {
+    const HHO_CONST R *tb = uni(a.tab) + G.tab_off;
+    if (G.medium == kFluid)
+        fluid_stage<K, NF, R>(a, tb, G.nF, L.ic, L.shot, L.lane, e);
+    else
+        solid_stage<K, NF, R>(a, tb, G.nF, L.ic, L.shot, L.lane, e);
+}
+
 template <int K, typename R>
 __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<R> a) {
     GroupDev G;
-    int ic, shot;
-    long long lane;
-    bool active;
-    decode_lane(a, G, ic, shot, lane, active);
+    const LaneInfo L = decode_lane(a, G);
     const bool want_e = a.last && a.e_part;
     double e = 0.0;
-    if (active) {
-        if (G.medium == kFluid)
-            fluid_stage<K, R>(a, G, ic, shot, lane, want_e ? &e : nullptr);
-        else
-            solid_stage<K, R>(a, G, ic, shot, lane, want_e ? &e : nullptr);
+    double *ep = want_e ? &e : nullptr;
+    if (L.active) {
+        // faces beyond a cell's count carry link -1 and are skipped like boundary faces
+        if (G.nF <= 4) stage_body<K, 4, R>(a, G, L, ep);
+        else stage_body<K, kMaxFaces, R>(a, G, L, ep);
     }
     if (want_e) block_energy(e, a.S, a.cpb, a.e_part);
 }
 
 // Trace contributions of the state in a.Yin (used once after the state is set).
+template <int K, int NF, typename R>
+__device__ __forceinline__ void traces_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L) {
+    constexpr int N = Dim<K>::N;
+    const HHO_CONST R *tb = uni(a.tab) + G.tab_off;
+    int lk[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) lk[j] = j < G.nF ? a.link[(long long)j * a.n_ic + L.ic] : -1;
+    const R tau = a.mat[(long long)kTau * a.n_ic + L.ic];
+    R v[5][N];
+    const int nb = G.medium == kFluid ? 3 : 5;
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+        for (int b = 0; b < N; ++b) v[q][b] = q < nb ? a.Yin[(long long)(q * N + b) * a.LT + L.lane] : R(0);
+    if (G.medium == kFluid)
+        fluid_traces<K, NF, R>(a, tb, G.nF, lk, L.lane, v[0], v[1], v[2], tau);
+    else
+        solid_traces<K, NF, R>(a, tb, G.nF, lk, L.lane, v[0], v[1], v[2], v[3], v[4], tau);
+}
+
 template <int K, typename R>
 __global__ __launch_bounds__(kBlock) void trace_kernel(StageArgs<R> a) {
-    constexpr int N = Dim<K>::N;
     GroupDev G;
-    int ic, shot;
-    long long lane;
-    bool active;
-    decode_lane(a, G, ic, shot, lane, active);
-    if (!active) return;
-    const R tau = a.mat[(long long)kTau * a.n_ic + ic];
-    if (G.medium == kFluid) {
-        R p[N], mx[N], my[N];
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-            p[b] = a.Yin[(long long)b * a.LT + lane];
-            mx[b] = a.Yin[(long long)(N + b) * a.LT + lane];
-            my[b] = a.Yin[(long long)(2 * N + b) * a.LT + lane];
-        }
-        fluid_traces<K, R>(a, G, ic, lane, p, mx, my, tau);
-    } else {
-        R v[5][N];
-#pragma unroll
-        for (int q = 0; q < 5; ++q)
-#pragma unroll
-            for (int b = 0; b < N; ++b) v[q][b] = a.Yin[(long long)(q * N + b) * a.LT + lane];
-        solid_traces<K, R>(a, G, ic, lane, v[0], v[1], v[2], v[3], v[4], tau);
-    }
+    const LaneInfo L = decode_lane(a, G);
+    if (!L.active) return;
+    if (G.nF <= 4) traces_body<K, 4, R>(a, G, L);
+    else traces_body<K, kMaxFaces, R>(a, G, L);
 }
 
 // Energy of the state in a.Yin (Sec. 5.1), float64 partials per block and shot.
@@ -522,14 +588,11 @@ template <int K, typename R>
 __global__ __launch_bounds__(kBlock) void energy_kernel(StageArgs<R> a) {
     constexpr int N = Dim<K>::N;
     GroupDev G;
-    int ic, shot;
-    long long lane;
-    bool active;
-    decode_lane(a, G, ic, shot, lane, active);
+    const LaneInfo L = decode_lane(a, G);
     double e = 0.0;
-    if (active) {
-        const int nic = a.n_ic;
-        auto ld = [&](int row) { return (double)a.Yin[(long long)row * a.LT + lane]; };
+    if (L.active) {
+        const int nic = a.n_ic, ic = L.ic;
+        auto ld = [&](int row) { return (double)a.Yin[(long long)row * a.LT + L.lane]; };
         if (G.medium == kFluid) {
             double sp = 0, sm = 0;
             for (int b = 0; b < N; ++b) {
@@ -539,12 +602,12 @@ __global__ __launch_bounds__(kBlock) void energy_kernel(StageArgs<R> a) {
             e = 0.5 * (a.emat[(long long)nic + ic] * sp + a.emat[ic] * sm);
         } else {
             const double ca = a.emat[(long long)nic + ic], cb = a.emat[(long long)2 * nic + ic];
-            const double cc = a.emat[(long long)3 * nic + ic];
+            const double c3 = a.emat[(long long)3 * nic + ic];
             double sv = 0, ss = 0;
             for (int b = 0; b < N; ++b) {
                 const double x1 = ld(2 * N + b), x2 = ld(3 * N + b), x3 = ld(4 * N + b);
                 sv += ld(b) * ld(b) + ld(N + b) * ld(N + b);
-                ss += ca * (x1 * x1 + x2 * x2) + 2.0 * cb * x1 * x2 + cc * x3 * x3;
+                ss += ca * (x1 * x1 + x2 * x2) + 2.0 * cb * x1 * x2 + c3 * x3 * x3;
             }
             e = 0.5 * (a.emat[ic] * sv + ss);
         }

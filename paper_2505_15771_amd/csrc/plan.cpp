@@ -388,7 +388,7 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
     }
 
     // groups (medium, class) in order of first appearance; cells of a group in input order
-    P.cpb = kBlock / P.S;
+    P.cpb = std::max(1, kLanesTarget / P.S);
     std::map<std::pair<int, int>, int> gid;
     std::vector<std::vector<int>> members;
     for (int c = 0; c < nc; ++c) {

@@ -10,7 +10,8 @@
 namespace hho {
 
 constexpr int kMaxFaces = 8;     // faces per cell (hanging nodes raise the count)
-constexpr int kBlock = 256;      // lanes per workgroup (4 wavefronts of 64)
+constexpr int kBlock = 256;      // largest workgroup (lanes)
+constexpr int kLanesTarget = 64; // preferred lanes per workgroup: one wavefront
 
 enum Medium : int { kFluid = 0, kSolid = 1 };
 
