@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--shots", type=int, default=1)
     ap.add_argument("--variants", type=int, default=1, help="also time the float64 / k=3 / batched variants")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the data-parallel "
@@ -132,6 +134,14 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_mb > 0:
+        n = args.copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copy calibration: %d MiB read + %d MiB written" % (args.copy_mb, args.copy_mb), file=sys.stderr)
+        del src, dst
     mesh = M.hybrid_square(256)
     head = run_variant(mesh, args.k, args.dtype, args.shots, args.steps, args.warmup)
     print("headline", json.dumps(head), file=sys.stderr, flush=True)

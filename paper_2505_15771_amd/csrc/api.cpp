@@ -28,6 +28,8 @@ struct hho_ctx {
     void *U = nullptr, *Y[2] = {nullptr, nullptr}, *acc = nullptr, *T[3] = {nullptr, nullptr, nullptr};
     int tcur = 0;
     bool traces_valid = false;
+    void *arena = nullptr;  // state, stage, trace, link, c0 and mat arrays (one buffer resource)
+    size_t arena_bytes = 0;
     int32_t *link = nullptr;
     void *c0 = nullptr, *mat = nullptr, *tab = nullptr;
     double *emat = nullptr;
@@ -95,6 +97,20 @@ hho_status upload(hho_ctx *ctx, T **dst, const std::vector<T> &src) {
     return HHO_OK;
 }
 
+// copy host data into an existing device array
+template <typename T>
+hho_status copy_in(hho_ctx *ctx, void *dst, const std::vector<T> &src) {
+    if (!src.empty()) HCK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+    HCK(hipStreamSynchronize(ctx->stream));
+    return HHO_OK;
+}
+
+hho_status copy_in_real(hho_ctx *ctx, void *dst, const std::vector<double> &src) {
+    if (ctx->dtype == 0) return copy_in(ctx, dst, src);
+    std::vector<float> f(src.begin(), src.end());
+    return copy_in(ctx, dst, f);
+}
+
 // real-typed upload of float64 host data
 hho_status upload_real(hho_ctx *ctx, void **dst, const std::vector<double> &src) {
     if (ctx->dtype == 0) return upload(ctx, (double **)dst, src);
@@ -155,6 +171,20 @@ bool erk_coefficients(int s, std::vector<StageCoef> &out) {
     return true;
 }
 
+unsigned arena_off(const hho_ctx *ctx, const void *p) {
+    return p ? (unsigned)((const char *)p - (const char *)ctx->arena) : 0u;
+}
+
+template <typename R>
+void set_stage_offsets(hho_ctx *ctx, StageArgs<R> &a) {
+    a.o_yin = arena_off(ctx, a.Yin);
+    a.o_yout = arena_off(ctx, a.Yout);
+    a.o_u = arena_off(ctx, a.U);
+    a.o_acc = arena_off(ctx, a.acc);
+    a.o_tin = arena_off(ctx, a.Tin);
+    a.o_tout = arena_off(ctx, a.Tout);
+}
+
 template <typename R>
 StageArgs<R> base_args(hho_ctx *ctx) {
     StageArgs<R> a;
@@ -170,6 +200,11 @@ StageArgs<R> base_args(hho_ctx *ctx) {
     a.cpb = ctx->plan.cpb;
     a.LT = ctx->LT;
     a.emat = ctx->emat;
+    a.arena = ctx->arena;
+    a.arena_bytes = (unsigned)ctx->arena_bytes;
+    a.o_link = arena_off(ctx, ctx->link);
+    a.o_c0 = arena_off(ctx, ctx->c0);
+    a.o_mat = arena_off(ctx, ctx->mat);
     return a;
 }
 
@@ -178,6 +213,7 @@ hho_status compute_traces(hho_ctx *ctx) {
     StageArgs<R> a = base_args<R>(ctx);
     a.Yin = (const R *)ctx->U;
     a.Tout = (R *)ctx->T[ctx->tcur];
+    set_stage_offsets(ctx, a);
     HCK((launch_traces<K, R>(a, ctx->n_blocks, ctx->stream)));
     ctx->traces_valid = true;
     return HHO_OK;
@@ -187,6 +223,8 @@ template <int K, typename R>
 hho_status energy_now(hho_ctx *ctx, double *out_dev) {
     StageArgs<R> a = base_args<R>(ctx);
     a.e_part = ctx->e_part;
+    a.Yin = (const R *)ctx->U;
+    set_stage_offsets(ctx, a);
     HCK((launch_energy<K, R>(a, (const R *)ctx->U, ctx->n_blocks, ctx->stream)));
     HCK(launch_energy_reduce(ctx->e_part, ctx->n_blocks, ctx->plan.S, out_dev, ctx->stream));
     return HHO_OK;
@@ -237,6 +275,7 @@ hho_status run_steps(hho_ctx *ctx, double t0, double dt, int n_steps) {
             a.rec_first = (a.last && ctx->nrec > 0) ? ctx->rec_first : nullptr;
             a.rec = ctx->rec;
             a.step = n;
+            set_stage_offsets(ctx, a);
             HCK((launch_stage<K, R>(a, ctx->n_blocks, ctx->stream)));
         }
         if (ctx->record_energy)
@@ -336,11 +375,35 @@ hho_status hho_setup(const hho_mesh *mesh, const hho_params *prm, hho_ctx **out)
     ctx->n_blocks = (int)P.blk_group.size();
     const size_t sbytes = (size_t)ctx->rows * ctx->LT * ctx->rsize;
     const size_t tbytes = (size_t)ctx->trows * ctx->LT * ctx->rsize;
-    if ((s = dalloc(ctx, &ctx->U, sbytes)) || (s = dalloc(ctx, &ctx->Y[0], sbytes)) ||
-        (s = dalloc(ctx, &ctx->Y[1], sbytes)) || (s = dalloc(ctx, &ctx->acc, sbytes)) ||
-        (s = dalloc(ctx, &ctx->T[0], tbytes)) || (s = dalloc(ctx, &ctx->T[1], tbytes)) ||
-        (s = dalloc(ctx, &ctx->T[2], tbytes)))
-        return fail(s);
+    const size_t lbytes = (size_t)P.max_nf * P.n_ic * 4;
+    const size_t cbytes = (size_t)P.max_nf * P.n_ic * ctx->rsize;
+    const size_t mbytes = (size_t)kNumMat * P.n_ic * ctx->rsize;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t total = 4 * al(sbytes) + 3 * al(tbytes) + al(lbytes) + al(cbytes) + al(mbytes);
+    // the kernels address the arena through one buffer resource with 32-bit byte offsets
+    if (total >= (1ull << 32)) {
+        ctx->err = "cells x shots too large for one context (arena of " + std::to_string(total) +
+                   " bytes exceeds 4 GiB)";
+        return fail(HHO_ERR_ARG);
+    }
+    if ((s = dalloc(ctx, &ctx->arena, total))) return fail(s);
+    ctx->arena_bytes = total;
+    {
+        char *p = (char *)ctx->arena;
+        auto take = [&](size_t b) {
+            void *q = p;
+            p += al(b);
+            return q;
+        };
+        ctx->U = take(sbytes);
+        ctx->Y[0] = take(sbytes);
+        ctx->Y[1] = take(sbytes);
+        ctx->acc = take(sbytes);
+        for (int i = 0; i < 3; ++i) ctx->T[i] = take(tbytes);
+        ctx->link = (int32_t *)take(lbytes);
+        ctx->c0 = take(cbytes);
+        ctx->mat = take(mbytes);
+    }
     std::vector<GroupDev> gd;
     for (const Group &g : P.groups) gd.push_back({g.medium, g.nF, g.tab_off, g.ic_begin, g.ncells, g.blk_begin});
     std::vector<int64_t> map(P.n_ext);
@@ -349,8 +412,8 @@ hho_status hho_setup(const hho_mesh *mesh, const hho_params *prm, hho_ctx **out)
         for (int r = 0; r < nr; ++r)
             map[P.ext_off[c] + r] = (int64_t)r * ctx->LT + (int64_t)P.ic_of_cell[c] * P.S;
     }
-    if ((s = upload(ctx, &ctx->link, P.link)) || (s = upload_real(ctx, &ctx->c0, P.c0)) ||
-        (s = upload_real(ctx, &ctx->mat, P.mat)) || (s = upload_real(ctx, &ctx->tab, P.tables)) ||
+    if ((s = copy_in(ctx, ctx->link, P.link)) || (s = copy_in_real(ctx, ctx->c0, P.c0)) ||
+        (s = copy_in_real(ctx, ctx->mat, P.mat)) || (s = upload_real(ctx, &ctx->tab, P.tables)) ||
         (s = upload(ctx, &ctx->emat, P.emat)) || (s = upload(ctx, &ctx->groups, gd)) ||
         (s = upload(ctx, &ctx->blk_group, P.blk_group)) || (s = upload(ctx, &ctx->map, map)) ||
         (s = dalloc(ctx, (void **)&ctx->staging, std::max<size_t>(1, P.n_ext) * 4 * sizeof(double))) ||

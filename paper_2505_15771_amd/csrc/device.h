@@ -61,6 +61,11 @@ struct StageArgs {
     const RecDev *rec;
     double *rec_out;           // [S][rec_steps][nrec][2]
     int step, nrec, rec_steps;
+    // Every per-lane and per-cell array above except gload lives in one device arena that the
+    // kernels address through a single buffer resource: byte offsets of each array in it.
+    const void *arena;
+    unsigned arena_bytes;
+    unsigned o_yin, o_yout, o_u, o_acc, o_tin, o_tout, o_link, o_c0, o_mat;
 };
 
 // Launchers (kernels.hip).  K = polynomial degree, R = double or float.

@@ -3,23 +3,29 @@
 //
 // One lane = one (cell, shot).  Cells are grouped by (medium, shape class): a workgroup
 // holds cells of one group, so its class table has uniform addresses and is read with
-// scalar loads through the constant address space, and the (medium, face count) code
-// path is uniform.  The state is structure-of-arrays, [row][lane], so every row load and
-// store of a wavefront is coalesced.
+// scalar loads through the constant address space, and the code path is uniform.  All
+// per-lane arrays are structure-of-arrays, [row][lane], read and written through buffer
+// resources: the uniform row offset sits in a scalar register and each lane adds a 32-bit
+// byte offset, so accesses are coalesced, need no 64-bit address arithmetic, and are
+// range-checked by the hardware.
 //
 // Fused stage, for every cell T of the group (bases orthonormal, so the cell and face
 // mass matrices are identities):
 //   1. face solves (eq. ex_solve, first line) for every non-boundary face F of T:
 //        r_T = tau_T G^T u_T - G^T (flux_T . n)       (own trace contribution)
-//        r_T' read from the neighbour's trace buffer  (written by the previous stage,
-//                                                      in the neighbour's face basis:
-//                                                      mode i changes sign as (-1)^i)
+//        r_T'                                          (the neighbour's, read from T's own
+//                                                      incoming slots)
 //        same medium:  u_F = (r_T + r_T') / (tau_T + tau_T')
 //        interface:    tau_f p_F + n_G.v_F = r_f,  -n_G p_F + tau_s v_F = r_s   (3f x 3f)
 //   2. cell residual (eq. ex_solve, second line) R = F_T - K_T u_T - K_TF u_F,
 //   3. k = M^{-1} R (1/rho, kappa, or the stiffness C in the E basis),
-//   4. Runge-Kutta combine (eq. ERK), and the trace contributions of the new stage state
-//      for the neighbours (written once, read once by the cell across each face).
+//   4. Runge-Kutta combine (eq. ERK); then T computes the trace contributions of its new
+//      stage state and stores each one directly into the incoming slot of the neighbour
+//      across that face, already in the neighbour's face basis (mode i flips sign as
+//      (-1)^i between the two orientations of a face; a solid cell writing across the
+//      interface also divides by its tau_s, which the fluid side needs).  So the next stage
+//      reads its incoming contributions at its own lane, coalesced and independent of the
+//      face links; the scattered accesses are stores.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -44,6 +50,69 @@ __device__ __forceinline__ const HHO_CONST T *uni(const T *p) {
     return (const HHO_CONST T *)p;
 }
 
+// Per-lane arrays are addressed through buffer resources: the uniform row offset goes in a
+// scalar register, the lane's byte offset in a vector register, and the hardware range check
+// against the array size turns a stray access into a zero load or a dropped store.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kRsrcWord3 = 0x00020000;  // 32-bit data format, raw (untyped) access
+
+template <typename T>
+__device__ __forceinline__ Rsrc rsrc(const T *p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, 0, (int)bytes, kRsrcWord3);
+}
+
+template <typename T>
+__device__ __forceinline__ T bld(Rsrc r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ float bld<float>(Rsrc r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ int bld<int>(Rsrc r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(int, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ double bld<double>(Rsrc r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bst(Rsrc r, unsigned voff, unsigned soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bst(Rsrc r, unsigned voff, unsigned soff, double v) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, 0);
+}
+
+// Buffer addressing of one stage launch (uniform): one resource over the arena, and the
+// byte offset of each array in it.
+template <typename R>
+struct Bufs {
+    Rsrc r;
+    unsigned yin, yout, u, acc, tin, tout, link, c0, mat;
+    unsigned rowb;   // bytes of one [lane] row: LT * sizeof(R)
+    unsigned crowb;  // bytes of one [cell] row of reals: n_ic * sizeof(R)
+    unsigned irowb;  // bytes of one [cell] row of int32: n_ic * 4
+};
+
+template <typename R>
+__device__ __forceinline__ Bufs<R> make_bufs(const StageArgs<R> &a) {
+    Bufs<R> b;
+    b.r = rsrc(a.arena, a.arena_bytes);
+    b.yin = a.o_yin;
+    b.yout = a.o_yout;
+    b.u = a.o_u;
+    b.acc = a.o_acc;
+    b.tin = a.o_tin;
+    b.tout = a.o_tout;
+    b.link = a.o_link;
+    b.c0 = a.o_c0;
+    b.mat = a.o_mat;
+    b.rowb = (unsigned)a.LT * (unsigned)sizeof(R);
+    b.crowb = (unsigned)a.n_ic * (unsigned)sizeof(R);
+    b.irowb = (unsigned)a.n_ic * 4u;
+    return b;
+}
+
 template <typename R>
 __device__ __forceinline__ R sgn(int i) {
     return (i & 1) ? R(-1) : R(1);
@@ -54,9 +123,12 @@ __device__ __forceinline__ double ricker(double t, double f0, double t0) {
     return (1.0 - 2.0 * a * a) * exp(-a * a);
 }
 
+constexpr double kRsqrt2 = 0.70710678118654752440;
+
 struct LaneInfo {
     int ic, shot;
-    long long lane;
+    unsigned boff;   // byte offset of this lane in a [row][lane] array of reals
+    unsigned coff;   // byte offset of this cell in a [row][cell] array of reals
     bool active;
 };
 
@@ -77,20 +149,66 @@ __device__ __forceinline__ LaneInfo decode_lane(const StageArgs<R> &a, GroupDev 
     const int l = (blockIdx.x - G.blk_begin) * a.cpb + cl;
     L.active = l < G.ncells;
     L.ic = G.ic_begin + l;
-    L.lane = (long long)L.ic * a.S + L.shot;
+    L.boff = (unsigned)(L.ic * a.S + L.shot) * (unsigned)sizeof(R);
+    L.coff = (unsigned)L.ic * (unsigned)sizeof(R);
     return L;
 }
 
-constexpr double kRsqrt2 = 0.70710678118654752440;
+// Per-cell face data: links (rows j >= nF of this group are never read; their links count
+// as -1, like boundary faces) and face-solve coefficients.
+template <int NF, typename R>
+__device__ __forceinline__ void load_links(const Bufs<R> &B, int nF, int ic, int *lk, R *cc) {
+    const unsigned ioff = (unsigned)ic * 4u, roff = (unsigned)ic * (unsigned)sizeof(R);
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        lk[j] = -1;
+        if (cc) cc[j] = R(0);
+        if (j < nF) {
+            lk[j] = bld<int>(B.r, ioff, B.link + j * B.irowb);
+            if (cc) cc[j] = bld<R>(B.r, roff, B.c0 + j * B.crowb);
+        }
+    }
+}
 
-// ------------------------------------------------------------------------- traces
-// Own trace contributions of a fluid state on every non-boundary face.
+// Incoming neighbour contributions.  Rows of every face of the group are loaded without
+// waiting for the links (a boundary face's slot is never written and its value is unused);
+// only a fluid cell's second component, present across the interface, depends on the link.
 template <int K, int NF, typename R>
-__device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const HHO_CONST R *tb, int nF,
-                                             const int *lk, long long lane, const R *p, const R *mx, const R *my, R tau) {
+__device__ __forceinline__ void load_incoming(const Bufs<R> &B, int medium, int nF, const int *lk, unsigned boff,
+                                              R (*rn)[2][Dim<K>::F]) {
+    constexpr int F = Dim<K>::F;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+#pragma unroll
+        for (int i = 0; i < F; ++i) rn[j][0][i] = rn[j][1][i] = R(0);
+        if (j >= nF) continue;
+#pragma unroll
+        for (int i = 0; i < F; ++i) rn[j][0][i] = bld<R>(B.r, boff, B.tin + ((j * 2) * F + i) * B.rowb);
+        if (medium == kSolid) {
+#pragma unroll
+            for (int i = 0; i < F; ++i) rn[j][1][i] = bld<R>(B.r, boff, B.tin + ((j * 2 + 1) * F + i) * B.rowb);
+        }
+    }
+    if (medium == kFluid) {
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            if (lk[j] < 0 || !((lk[j] >> 3) & 1)) continue;
+#pragma unroll
+            for (int i = 0; i < F; ++i) rn[j][1][i] = bld<R>(B.r, boff, B.tin + ((j * 2 + 1) * F + i) * B.rowb);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------- outgoing traces
+template <int K, int NF, typename R>
+__device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
+                                             const int *lk, int shot, const R *p, const R *mx, const R *my, R tau) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
     const HHO_CONST R *Gt = tb + 3 * N * N;
     const HHO_CONST R *nr = Gt + nF * N * F;
+    R tp[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) tp[b] = tau * p[b];
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         if (lk[j] < 0) continue;
@@ -100,23 +218,32 @@ __device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const HHO_CO
         for (int i = 0; i < F; ++i) r[i] = R(0);
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            const R q = tau * p[b] - (nx * mx[b] + ny * my[b]);
+            const R q = tp[b] - nx * mx[b] - ny * my[b];
 #pragma unroll
             for (int i = 0; i < F; ++i) r[i] += Gt[(j * N + b) * F + i] * q;
         }
+        const int icn = lk[j] >> 4, jn = lk[j] & 7;
+        const unsigned nb = (unsigned)(icn * a.S + shot) * (unsigned)sizeof(R);
 #pragma unroll
-        for (int i = 0; i < F; ++i) a.Tout[((long long)(j * 2) * F + i) * a.LT + lane] = r[i];
+        for (int i = 0; i < F; ++i) bst(B.r, nb, B.tout + ((jn * 2) * F + i) * B.rowb, sgn<R>(i) * r[i]);
     }
 }
 
 template <int K, int NF, typename R>
-__device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const HHO_CONST R *tb, int nF,
-                                             const int *lk, long long lane, const R *vx, const R *vy, const R *s1, const R *s2,
-                                             const R *s3, R tau) {
+__device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
+                                             const int *lk, int shot, const R *vx, const R *vy, const R *s1, const R *s2,
+                                             const R *s3, R tau, R itau) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
     const R r2 = R(kRsqrt2);
     const HHO_CONST R *Gt = tb + 3 * N * N;
     const HHO_CONST R *nr = Gt + nF * N * F;
+    R tvx[N], tvy[N], hs3[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        tvx[b] = tau * vx[b];
+        tvy[b] = tau * vy[b];
+        hs3[b] = r2 * s3[b];
+    }
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         if (lk[j] < 0) continue;
@@ -126,101 +253,104 @@ __device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const HHO_CO
         for (int i = 0; i < F; ++i) rx[i] = ry[i] = R(0);
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            const R qx = tau * vx[b] - (nx * s1[b] + r2 * ny * s3[b]);
-            const R qy = tau * vy[b] - (r2 * nx * s3[b] + ny * s2[b]);
+            const R qx = tvx[b] - nx * s1[b] - ny * hs3[b];
+            const R qy = tvy[b] - nx * hs3[b] - ny * s2[b];
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 rx[i] += Gt[(j * N + b) * F + i] * qx;
                 ry[i] += Gt[(j * N + b) * F + i] * qy;
             }
         }
+        const int icn = lk[j] >> 4, jn = lk[j] & 7;
+        const unsigned nb = (unsigned)(icn * a.S + shot) * (unsigned)sizeof(R);
+        // across the interface the fluid side needs r_s / tau_s
+        const R w = ((lk[j] >> 3) & 1) ? itau : R(1);
 #pragma unroll
         for (int i = 0; i < F; ++i) {
-            a.Tout[((long long)(j * 2) * F + i) * a.LT + lane] = rx[i];
-            a.Tout[((long long)(j * 2 + 1) * F + i) * a.LT + lane] = ry[i];
+            bst(B.r, nb, B.tout + ((jn * 2) * F + i) * B.rowb, sgn<R>(i) * w * rx[i]);
+            bst(B.r, nb, B.tout + ((jn * 2 + 1) * F + i) * B.rowb, sgn<R>(i) * w * ry[i]);
         }
     }
 }
 
-// Links of every local face and the neighbour trace contributions (both components;
-// the second only where it is needed), issued before any arithmetic.
-// The link and coefficient arrays hold one row per face of the largest cell of the mesh:
-// rows j >= nF of this group are never read (their links count as -1).
-template <int K, int NF, typename R>
-__device__ __forceinline__ void load_faces(const StageArgs<R> &a, int medium, int nF, int ic, int shot, int *lk,
-                                           R *cc, R (*rn)[2][Dim<K>::F], R *its) {
-    constexpr int F = Dim<K>::F;
-    const int nic = a.n_ic;
+// Runge-Kutta combine of all ND rows of a lane (eq. ERK): out = new stage state, stored to
+// Y_{i+1} (and the accumulator) or to U^{n+1} on the last stage.  Every load is issued before
+// the first store: the arrays share one buffer resource, so the compiler cannot move a load
+// above an earlier store and would otherwise pay one memory round trip per row.
+template <int ND, typename R>
+__device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, const R *y,
+                                          const R *kv, R *out) {
+    R u[ND], ac[ND];
+    if (a.first) {
 #pragma unroll
-    for (int j = 0; j < NF; ++j) {
-        lk[j] = -1;
-        cc[j] = R(0);
-        if (j < nF) {
-            lk[j] = a.link[(long long)j * nic + ic];
-            cc[j] = a.c0[(long long)j * nic + ic];
+        for (int r = 0; r < ND; ++r) {
+            u[r] = y[r];
+            ac[r] = R(0);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < ND; ++r) {
+            u[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
+            ac[r] = bld<R>(B.r, boff, B.acc + r * B.rowb);
         }
     }
+    if (!a.last) {
 #pragma unroll
-    for (int j = 0; j < NF; ++j) {
-        its[j] = R(0);
-#pragma unroll
-        for (int i = 0; i < F; ++i) rn[j][0][i] = rn[j][1][i] = R(0);
-        if (lk[j] < 0) continue;
-        const int icn = lk[j] >> 4, jn = lk[j] & 7;
-        const bool iface = (lk[j] >> 3) & 1;
-        const long long nl = (long long)icn * a.S + shot;
-        const R *t0 = a.Tin + (long long)(jn * 2) * F * a.LT + nl;
-#pragma unroll
-        for (int i = 0; i < F; ++i) rn[j][0][i] = sgn<R>(i) * t0[(long long)i * a.LT];
-        // second component: solid neighbours (same-medium solid face, or interface seen from the fluid)
-        if (medium == kSolid ? !iface : iface) {
-            const R *t1 = t0 + (long long)F * a.LT;
-#pragma unroll
-            for (int i = 0; i < F; ++i) rn[j][1][i] = sgn<R>(i) * t1[(long long)i * a.LT];
+        for (int r = 0; r < ND; ++r) {
+            out[r] = a.cU * u[r] + a.cY * y[r] + a.ck * a.dt * kv[r];
+            bst(B.r, boff, B.yout + r * B.rowb, out[r]);
+            bst(B.r, boff, B.acc + r * B.rowb, ac[r] + a.cb * kv[r]);
         }
-        if (iface && medium == kFluid) its[j] = a.mat[(long long)kInvTau * nic + icn];
+    } else {
+#pragma unroll
+        for (int r = 0; r < ND; ++r) {
+            out[r] = u[r] + a.dt * (ac[r] + a.cb * kv[r]);
+            bst(B.r, boff, B.u + r * B.rowb, out[r]);
+        }
     }
 }
 
 // ------------------------------------------------------------------------- fluid cells
 template <int K, int NF, typename R>
-__device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const HHO_CONST R *tb, int nF, int ic, int shot,
-                                            long long lane, double *energy) {
+__device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
+                                            const LaneInfo &L, double *energy) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
-    const long long LT = a.LT;
-    const int nic = a.n_ic;
+    const int nic = a.n_ic, ic = L.ic, shot = L.shot;
+    const unsigned boff = L.boff, coff = L.coff;
     const HHO_CONST R *Bx = tb;
     const HHO_CONST R *By = tb + N * N;
     const HHO_CONST R *Sm = tb + 2 * N * N;
     const HHO_CONST R *Gt = tb + 3 * N * N;
     const HHO_CONST R *nr = Gt + nF * N * F;
     int lk[NF];
-    R cc[NF], its[NF], rn[NF][2][F];
-    load_faces<K, NF, R>(a, kFluid, nF, ic, shot, lk, cc, rn, its);
+    R cc[NF], rn[NF][2][F];
+    load_links<NF, R>(B, nF, ic, lk, cc);
     R p[N], mx[N], my[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-        p[b] = a.Yin[(long long)b * LT + lane];
-        mx[b] = a.Yin[(long long)(N + b) * LT + lane];
-        my[b] = a.Yin[(long long)(2 * N + b) * LT + lane];
+        p[b] = bld<R>(B.r, boff, B.yin + (b) * B.rowb);
+        mx[b] = bld<R>(B.r, boff, B.yin + (N + b) * B.rowb);
+        my[b] = bld<R>(B.r, boff, B.yin + (2 * N + b) * B.rowb);
     }
-    const R tau = a.mat[(long long)kTau * nic + ic];
-    const R kap = a.mat[(long long)kStiff * nic + ic];
-    const R irho = a.mat[(long long)kInvRho * nic + ic];
-    R rp[N], rmx[N], rmy[N];
+    load_incoming<K, NF, R>(B, kFluid, nF, lk, boff, rn);
+    const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
+    const R kap = bld<R>(B.r, coff, B.mat + kStiff * B.crowb);
+    const R irho = bld<R>(B.r, coff, B.mat + kInvRho * B.crowb);
+    R rp[N], rmx[N], rmy[N], tp[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) tp[b] = tau * p[b];
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-        R sx = 0, sy = 0, sd = 0, ss = 0;
+        R sx = 0, sy = 0, sd = 0;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             sx += Bx[r * N + b] * p[b];
             sy += By[r * N + b] * p[b];
-            sd += Bx[b * N + r] * mx[b] + By[b * N + r] * my[b];
-            ss += Sm[r * N + b] * p[b];
+            sd += Bx[b * N + r] * mx[b] + By[b * N + r] * my[b] + Sm[r * N + b] * tp[b];
         }
         rmx[r] = sx;
         rmy[r] = sy;
-        rp[r] = -(sd + tau * ss);
+        rp[r] = -sd;
     }
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
@@ -231,7 +361,7 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const HHO_CON
         for (int i = 0; i < F; ++i) r[i] = R(0);
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            const R q = tau * p[b] - (nx * mx[b] + ny * my[b]);
+            const R q = tp[b] - nx * mx[b] - ny * my[b];
 #pragma unroll
             for (int i = 0; i < F; ++i) r[i] += Gt[(j * N + b) * F + i] * q;
         }
@@ -240,9 +370,10 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const HHO_CON
 #pragma unroll
             for (int i = 0; i < F; ++i) pF[i] = (r[i] + rn[j][0][i]) * cc[j];
         } else {
-            // interface, neighbour solid: n_G = -n_T, eliminate v_F
+            // interface, neighbour solid (its contribution arrives divided by tau_s):
+            // n_G = -n_T, eliminate v_F
 #pragma unroll
-            for (int i = 0; i < F; ++i) pF[i] = (r[i] + (nx * rn[j][0][i] + ny * rn[j][1][i]) * its[j]) * cc[j];
+            for (int i = 0; i < F; ++i) pF[i] = (r[i] + nx * rn[j][0][i] + ny * rn[j][1][i]) * cc[j];
         }
 #pragma unroll
         for (int b = 0; b < N; ++b) {
@@ -257,12 +388,12 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const HHO_CON
     // loads F_T(t)
     for (int m = 0; m < a.nterms; ++m) {
         const R w = a.wterm[m];
-        const R *g = a.gload + (long long)m * 5 * N * nic + ic;
+        const int gr = m * 5 * N;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            rp[b] += w * g[(long long)b * nic];
-            rmx[b] += w * g[(long long)(N + b) * nic];
-            rmy[b] += w * g[(long long)(2 * N + b) * nic];
+            rp[b] += w * a.gload[(long long)(gr + b) * nic + ic];
+            rmx[b] += w * a.gload[(long long)(gr + N + b) * nic + ic];
+            rmy[b] += w * a.gload[(long long)(gr + 2 * N + b) * nic + ic];
         }
     }
     if (a.src_first) {
@@ -277,29 +408,19 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const HHO_CON
         }
     }
     // k = M^{-1} R and the Runge-Kutta combine
-    R np[N], nmx[N], nmy[N];
+    R y[3 * N], kv[3 * N], nw[3 * N];
 #pragma unroll
-    for (int row = 0; row < 3 * N; ++row) {
-        const int b = row % N, blk = row / N;
-        const R kv = blk == 0 ? kap * rp[b] : irho * (blk == 1 ? rmx[b] : rmy[b]);
-        const R y = blk == 0 ? p[b] : (blk == 1 ? mx[b] : my[b]);
-        const long long ix = (long long)row * LT + lane;
-        R out;
-        if (!a.last) {
-            const R u = a.first ? y : a.U[ix];
-            out = a.cU * u + a.cY * y + a.ck * a.dt * kv;
-            a.Yout[ix] = out;
-            a.acc[ix] = (a.first ? R(0) : a.acc[ix]) + a.cb * kv;
-        } else {
-            const R u = a.first ? y : a.U[ix];
-            out = u + a.dt * ((a.first ? R(0) : a.acc[ix]) + a.cb * kv);
-            a.U[ix] = out;
-        }
-        if (blk == 0) np[b] = out;
-        else if (blk == 1) nmx[b] = out;
-        else nmy[b] = out;
+    for (int b = 0; b < N; ++b) {
+        y[b] = p[b];
+        y[N + b] = mx[b];
+        y[2 * N + b] = my[b];
+        kv[b] = kap * rp[b];
+        kv[N + b] = irho * rmx[b];
+        kv[2 * N + b] = irho * rmy[b];
     }
-    fluid_traces<K, NF, R>(a, tb, nF, lk, lane, np, nmx, nmy, tau);
+    rk_update<3 * N, R>(a, B, boff, y, kv, nw);
+    const R *np = nw, *nmx = nw + N, *nmy = nw + 2 * N;
+    fluid_traces<K, NF, R>(a, B, tb, nF, lk, shot, np, nmx, nmy, tau);
     if (a.last) {
         if (energy) {
             double sp = 0, sm = 0;
@@ -327,11 +448,11 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const HHO_CON
 
 // ------------------------------------------------------------------------- solid cells
 template <int K, int NF, typename R>
-__device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const HHO_CONST R *tb, int nF, int ic, int shot,
-                                            long long lane, double *energy) {
+__device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
+                                            const LaneInfo &L, double *energy) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
-    const long long LT = a.LT;
-    const int nic = a.n_ic;
+    const int nic = a.n_ic, ic = L.ic, shot = L.shot;
+    const unsigned boff = L.boff, coff = L.coff;
     const R r2 = R(kRsqrt2);
     const HHO_CONST R *Bx = tb;
     const HHO_CONST R *By = tb + N * N;
@@ -339,27 +460,34 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const HHO_CON
     const HHO_CONST R *Gt = tb + 3 * N * N;
     const HHO_CONST R *nr = Gt + nF * N * F;
     int lk[NF];
-    R cc[NF], its[NF], rn[NF][2][F];
-    load_faces<K, NF, R>(a, kSolid, nF, ic, shot, lk, cc, rn, its);
+    R cc[NF], rn[NF][2][F];
+    load_links<NF, R>(B, nF, ic, lk, cc);
     R vx[N], vy[N], s1[N], s2[N], s3[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-        vx[b] = a.Yin[(long long)b * LT + lane];
-        vy[b] = a.Yin[(long long)(N + b) * LT + lane];
-        s1[b] = a.Yin[(long long)(2 * N + b) * LT + lane];
-        s2[b] = a.Yin[(long long)(3 * N + b) * LT + lane];
-        s3[b] = a.Yin[(long long)(4 * N + b) * LT + lane];
+        vx[b] = bld<R>(B.r, boff, B.yin + (b) * B.rowb);
+        vy[b] = bld<R>(B.r, boff, B.yin + (N + b) * B.rowb);
+        s1[b] = bld<R>(B.r, boff, B.yin + (2 * N + b) * B.rowb);
+        s2[b] = bld<R>(B.r, boff, B.yin + (3 * N + b) * B.rowb);
+        s3[b] = bld<R>(B.r, boff, B.yin + (4 * N + b) * B.rowb);
     }
-    const R tau = a.mat[(long long)kTau * nic + ic];
-    const R itau = a.mat[(long long)kInvTau * nic + ic];
-    const R irho = a.mat[(long long)kInvRho * nic + ic];
-    const R l2m = a.mat[(long long)kStiff * nic + ic];
-    const R lam = a.mat[(long long)kLam * nic + ic];
-    const R tmu = a.mat[(long long)kTwoMu * nic + ic];
-    R rvx[N], rvy[N], rs1[N], rs2[N], rs3[N];
+    load_incoming<K, NF, R>(B, kSolid, nF, lk, boff, rn);
+    const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
+    const R itau = bld<R>(B.r, coff, B.mat + kInvTau * B.crowb);
+    const R irho = bld<R>(B.r, coff, B.mat + kInvRho * B.crowb);
+    const R l2m = bld<R>(B.r, coff, B.mat + kStiff * B.crowb);
+    const R lam = bld<R>(B.r, coff, B.mat + kLam * B.crowb);
+    const R tmu = bld<R>(B.r, coff, B.mat + kTwoMu * B.crowb);
+    R rvx[N], rvy[N], rs1[N], rs2[N], rs3[N], tvx[N], tvy[N], hs3[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        tvx[b] = tau * vx[b];
+        tvy[b] = tau * vy[b];
+        hs3[b] = r2 * s3[b];
+    }
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-        R a1 = 0, a2 = 0, a3 = 0, bx = 0, by = 0, sx = 0, sy = 0;
+        R a1 = 0, a2 = 0, a3 = 0, bx = 0, by = 0;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             const R bxrb = Bx[r * N + b], byrb = By[r * N + b];
@@ -367,16 +495,14 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const HHO_CON
             a1 += bxrb * vx[b];
             a2 += byrb * vy[b];
             a3 += byrb * vx[b] + bxrb * vy[b];
-            bx += bxbr * s1[b] + bybr * (r2 * s3[b]);
-            by += bybr * s2[b] + bxbr * (r2 * s3[b]);
-            sx += srb * vx[b];
-            sy += srb * vy[b];
+            bx += bxbr * s1[b] + bybr * hs3[b] + srb * tvx[b];
+            by += bybr * s2[b] + bxbr * hs3[b] + srb * tvy[b];
         }
         rs1[r] = a1;
         rs2[r] = a2;
         rs3[r] = r2 * a3;
-        rvx[r] = -(bx + tau * sx);
-        rvy[r] = -(by + tau * sy);
+        rvx[r] = -bx;
+        rvy[r] = -by;
     }
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
@@ -387,8 +513,8 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const HHO_CON
         for (int i = 0; i < F; ++i) rx[i] = ry[i] = R(0);
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            const R qx = tau * vx[b] - (nx * s1[b] + r2 * ny * s3[b]);
-            const R qy = tau * vy[b] - (r2 * nx * s3[b] + ny * s2[b]);
+            const R qx = tvx[b] - nx * s1[b] - ny * hs3[b];
+            const R qy = tvy[b] - nx * hs3[b] - ny * s2[b];
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 rx[i] += Gt[(j * N + b) * F + i] * qx;
@@ -428,14 +554,14 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const HHO_CON
     }
     for (int m = 0; m < a.nterms; ++m) {
         const R w = a.wterm[m];
-        const R *g = a.gload + (long long)m * 5 * N * nic + ic;
+        const int gr = m * 5 * N;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            rvx[b] += w * g[(long long)b * nic];
-            rvy[b] += w * g[(long long)(N + b) * nic];
-            rs1[b] += w * g[(long long)(2 * N + b) * nic];
-            rs2[b] += w * g[(long long)(3 * N + b) * nic];
-            rs3[b] += w * g[(long long)(4 * N + b) * nic];
+            rvx[b] += w * a.gload[(long long)(gr + b) * nic + ic];
+            rvy[b] += w * a.gload[(long long)(gr + N + b) * nic + ic];
+            rs1[b] += w * a.gload[(long long)(gr + 2 * N + b) * nic + ic];
+            rs2[b] += w * a.gload[(long long)(gr + 3 * N + b) * nic + ic];
+            rs3[b] += w * a.gload[(long long)(gr + 4 * N + b) * nic + ic];
         }
     }
     if (a.src_first) {
@@ -453,39 +579,23 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const HHO_CON
             e = s.next;
         }
     }
-    R nvx[N], nvy[N], ns1[N], ns2[N], ns3[N];
+    R y[5 * N], kv[5 * N], nw[5 * N];
 #pragma unroll
-    for (int row = 0; row < 5 * N; ++row) {
-        const int b = row % N, blk = row / N;
-        R kv, y;
-        switch (blk) {
-            case 0: kv = irho * rvx[b]; y = vx[b]; break;
-            case 1: kv = irho * rvy[b]; y = vy[b]; break;
-            case 2: kv = l2m * rs1[b] + lam * rs2[b]; y = s1[b]; break;
-            case 3: kv = lam * rs1[b] + l2m * rs2[b]; y = s2[b]; break;
-            default: kv = tmu * rs3[b]; y = s3[b]; break;
-        }
-        const long long ix = (long long)row * LT + lane;
-        R out;
-        if (!a.last) {
-            const R u = a.first ? y : a.U[ix];
-            out = a.cU * u + a.cY * y + a.ck * a.dt * kv;
-            a.Yout[ix] = out;
-            a.acc[ix] = (a.first ? R(0) : a.acc[ix]) + a.cb * kv;
-        } else {
-            const R u = a.first ? y : a.U[ix];
-            out = u + a.dt * ((a.first ? R(0) : a.acc[ix]) + a.cb * kv);
-            a.U[ix] = out;
-        }
-        switch (blk) {
-            case 0: nvx[b] = out; break;
-            case 1: nvy[b] = out; break;
-            case 2: ns1[b] = out; break;
-            case 3: ns2[b] = out; break;
-            default: ns3[b] = out; break;
-        }
+    for (int b = 0; b < N; ++b) {
+        y[b] = vx[b];
+        y[N + b] = vy[b];
+        y[2 * N + b] = s1[b];
+        y[3 * N + b] = s2[b];
+        y[4 * N + b] = s3[b];
+        kv[b] = irho * rvx[b];
+        kv[N + b] = irho * rvy[b];
+        kv[2 * N + b] = l2m * rs1[b] + lam * rs2[b];
+        kv[3 * N + b] = lam * rs1[b] + l2m * rs2[b];
+        kv[4 * N + b] = tmu * rs3[b];
     }
-    solid_traces<K, NF, R>(a, tb, nF, lk, lane, nvx, nvy, ns1, ns2, ns3, tau);
+    rk_update<5 * N, R>(a, B, boff, y, kv, nw);
+    const R *nvx = nw, *nvy = nw + N, *ns1 = nw + 2 * N, *ns2 = nw + 3 * N, *ns3 = nw + 4 * N;
+    solid_traces<K, NF, R>(a, B, tb, nF, lk, shot, nvx, nvy, ns1, ns2, ns3, tau, itau);
     if (a.last) {
         if (energy) {
             const double ca = a.emat[(long long)1 * nic + ic], cb = a.emat[(long long)2 * nic + ic];
@@ -532,10 +642,11 @@ __device__ void block_energy(double e, int S, int cpb, double *out) {
 template <int K, int NF, typename R>
 __device__ __forceinline__ void stage_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L, double *e) {
     const HHO_CONST R *tb = uni(a.tab) + G.tab_off;
+    const Bufs<R> B = make_bufs(a);
     if (G.medium == kFluid)
-        fluid_stage<K, NF, R>(a, tb, G.nF, L.ic, L.shot, L.lane, e);
+        fluid_stage<K, NF, R>(a, B, tb, G.nF, L, e);
     else
-        solid_stage<K, NF, R>(a, tb, G.nF, L.ic, L.shot, L.lane, e);
+        solid_stage<K, NF, R>(a, B, tb, G.nF, L, e);
 }
 
 template <int K, typename R>
@@ -553,25 +664,26 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<R> a) {
     if (want_e) block_energy(e, a.S, a.cpb, a.e_part);
 }
 
-// Trace contributions of the state in a.Yin (used once after the state is set).
+// Outgoing trace contributions of the state in a.Yin (used once after the state is set).
 template <int K, int NF, typename R>
 __device__ __forceinline__ void traces_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L) {
     constexpr int N = Dim<K>::N;
     const HHO_CONST R *tb = uni(a.tab) + G.tab_off;
+    const Bufs<R> B = make_bufs(a);
     int lk[NF];
-#pragma unroll
-    for (int j = 0; j < NF; ++j) lk[j] = j < G.nF ? a.link[(long long)j * a.n_ic + L.ic] : -1;
-    const R tau = a.mat[(long long)kTau * a.n_ic + L.ic];
+    load_links<NF, R>(B, G.nF, L.ic, lk, (R *)nullptr);
+    const R tau = bld<R>(B.r, L.coff, B.mat + kTau * B.crowb);
+    const R itau = bld<R>(B.r, L.coff, B.mat + kInvTau * B.crowb);
     R v[5][N];
     const int nb = G.medium == kFluid ? 3 : 5;
 #pragma unroll
     for (int q = 0; q < 5; ++q)
 #pragma unroll
-        for (int b = 0; b < N; ++b) v[q][b] = q < nb ? a.Yin[(long long)(q * N + b) * a.LT + L.lane] : R(0);
+        for (int b = 0; b < N; ++b) v[q][b] = q < nb ? bld<R>(B.r, L.boff, B.yin + (q * N + b) * B.rowb) : R(0);
     if (G.medium == kFluid)
-        fluid_traces<K, NF, R>(a, tb, G.nF, lk, L.lane, v[0], v[1], v[2], tau);
+        fluid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.shot, v[0], v[1], v[2], tau);
     else
-        solid_traces<K, NF, R>(a, tb, G.nF, lk, L.lane, v[0], v[1], v[2], v[3], v[4], tau);
+        solid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.shot, v[0], v[1], v[2], v[3], v[4], tau, itau);
 }
 
 template <int K, typename R>
@@ -592,22 +704,31 @@ __global__ __launch_bounds__(kBlock) void energy_kernel(StageArgs<R> a) {
     double e = 0.0;
     if (L.active) {
         const int nic = a.n_ic, ic = L.ic;
-        auto ld = [&](int row) { return (double)a.Yin[(long long)row * a.LT + L.lane]; };
+        const int nb = G.medium == kFluid ? 3 : 5;
+        const Bufs<R> B = make_bufs(a);
+        double v[5][N];
+#pragma unroll
+        for (int q = 0; q < 5; ++q)
+#pragma unroll
+            for (int b = 0; b < N; ++b)
+                v[q][b] = q < nb ? (double)bld<R>(B.r, L.boff, B.yin + (q * N + b) * B.rowb) : 0.0;
         if (G.medium == kFluid) {
             double sp = 0, sm = 0;
+#pragma unroll
             for (int b = 0; b < N; ++b) {
-                sp += ld(b) * ld(b);
-                sm += ld(N + b) * ld(N + b) + ld(2 * N + b) * ld(2 * N + b);
+                sp += v[0][b] * v[0][b];
+                sm += v[1][b] * v[1][b] + v[2][b] * v[2][b];
             }
             e = 0.5 * (a.emat[(long long)nic + ic] * sp + a.emat[ic] * sm);
         } else {
             const double ca = a.emat[(long long)nic + ic], cb = a.emat[(long long)2 * nic + ic];
             const double c3 = a.emat[(long long)3 * nic + ic];
             double sv = 0, ss = 0;
+#pragma unroll
             for (int b = 0; b < N; ++b) {
-                const double x1 = ld(2 * N + b), x2 = ld(3 * N + b), x3 = ld(4 * N + b);
-                sv += ld(b) * ld(b) + ld(N + b) * ld(N + b);
-                ss += ca * (x1 * x1 + x2 * x2) + 2.0 * cb * x1 * x2 + c3 * x3 * x3;
+                sv += v[0][b] * v[0][b] + v[1][b] * v[1][b];
+                ss += ca * (v[2][b] * v[2][b] + v[3][b] * v[3][b]) + 2.0 * cb * v[2][b] * v[3][b] +
+                      c3 * v[4][b] * v[4][b];
             }
             e = 0.5 * (a.emat[ic] * sv + ss);
         }
