@@ -139,8 +139,10 @@ hho_status hho_set_loads(hho_ctx *ctx, int32_t n_terms, const double *g, const d
  * polynomials (sensors of Sec. 5.2), recorded after every step of hho_erk_step. */
 hho_status hho_receivers(hho_ctx *ctx, int32_t n, const double *xy, const int32_t *field);
 
-/* Advance every shot by n_steps steps of ERK(rk_stages) from time t0 with step dt.
- * Enqueued on params.stream; returns before completion unless record_energy = 1, in
+/* Advance every shot by n_steps steps of ERK(rk_stages) from time t0 with step dt.  Steps are
+ * launched in groups of 32 as one captured graph (replayed while the configuration is unchanged),
+ * the remainder directly.  Enqueued on params.stream; returns before completion unless
+ * record_energy = 1, in
  * which case it synchronises and returns HHO_ERR_UNSTABLE if the energy of a shot grew
  * by more than 5 % over its initial value, or over the previous step, or is not finite. */
 hho_status hho_erk_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps);
@@ -158,6 +160,35 @@ hho_status hho_energy(hho_ctx *ctx, double *E);
 /* Energies recorded after each step of the last hho_erk_step call (record_energy = 1):
  * out[n_steps] for one shot. */
 hho_status hho_energy_history(hho_ctx *ctx, int32_t shot, double *out);
+
+/* Launch shape.  The stage kernel can run with workgroups of 64, 128 or 256 lanes (one lane per
+ * cell and shot).  hho_autotune times one stage in every shape on the current state, keeps the
+ * fastest and returns its lane count; it changes no state.  hho_set_launch selects a shape by
+ * lane count (ARG if none matches).  Results do not depend on the shape except for the summation
+ * order of energies. */
+hho_status hho_autotune(hho_ctx *ctx, int32_t *lanes);
+hho_status hho_set_launch(hho_ctx *ctx, int32_t lanes);
+
+/* Time step from the CFL condition (eq. CFL, Sec. 5.1): dt = factor * min over cells of
+ * CFL*(s, k, shape) h_T / c_T.  CFL* is the paper's Table tab::ratio_geo value for the cell's
+ * shape (triangle, square; five or more faces use the hexagon column), c_T the largest wave speed
+ * of the cell (c, or c_P in the solid) and h_T the side of the generating square (sqrt of the area,
+ * sqrt of twice the area for triangles). */
+hho_status hho_dt_cfl(const hho_ctx *ctx, double factor, double *dt);
+
+/* Batched stepping: several contexts (meshes of different sizes and degrees, each with its own
+ * shots) advanced together.  Every group of 32 steps of all contexts is one graph launch in which
+ * the contexts' step chains are independent branches; remaining steps are launched directly.
+ * All contexts must live on one device; the batch launches on the first context's stream and
+ * synchronises before returning.  t0[i], dt[i] per context.  The per-context results (state,
+ * traces, energy history) are read with the per-context calls; HHO_ERR_UNSTABLE as hho_erk_step
+ * for any context (message in hho_batch_last_error).  A batch does not own its contexts; destroy
+ * it before them. */
+typedef struct hho_batch hho_batch;
+hho_status hho_batch_create(hho_ctx *const *ctxs, int32_t n, hho_batch **out);
+void hho_batch_destroy(hho_batch *b);
+const char *hho_batch_last_error(const hho_batch *b);
+hho_status hho_batch_erk_step(hho_batch *b, const double *t0, const double *dt, int32_t n_steps);
 
 #ifdef __cplusplus
 }

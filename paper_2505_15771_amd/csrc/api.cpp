@@ -24,7 +24,6 @@ struct hho_ctx {
     size_t rsize = 8;          // bytes per real
     long long LT = 0;          // lanes
     int rows = 0, trows = 0;   // state rows (5N), trace rows
-    int n_blocks = 0;
     void *U = nullptr, *Y[2] = {nullptr, nullptr}, *acc = nullptr, *T[3] = {nullptr, nullptr, nullptr};
     int tcur = 0;
     bool traces_valid = false;
@@ -33,8 +32,16 @@ struct hho_ctx {
     int32_t *link = nullptr;
     void *c0 = nullptr, *mat = nullptr, *tab = nullptr;
     double *emat = nullptr;
-    GroupDev *groups = nullptr;
-    int32_t *blk_group = nullptr;
+    // launch shapes (Plan::launches) and the one in use
+    struct LaunchDev {
+        GroupDev *groups = nullptr;
+        int32_t *blk_group = nullptr;
+        int n_blocks = 0, cpb = 0, lanes = 0;
+    };
+    std::vector<LaunchDev> launch;
+    int shape = 0;
+    int n_blocks() const { return launch[shape].n_blocks; }
+    int max_blocks = 0;
     int64_t *map = nullptr;
     double *staging = nullptr;
     // point sources
@@ -56,6 +63,22 @@ struct hho_ctx {
     // energy
     double *e_part = nullptr, *e_hist = nullptr, *e_now = nullptr;
     size_t e_hist_cap = 0;
+    // device clock and the cached graph of kGraphSteps steps
+    Clock *clock = nullptr;
+    Clock h_clock{};
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    unsigned version = 1, graph_version = 0;  // graph is valid when graph_version == version
+    double cfl_dt = 0.0;                       // CFL-limited time step at factor 1
+};
+
+struct hho_batch {
+    std::vector<hho_ctx *> ctxs;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<unsigned> versions;  // context versions the graph was captured with
+    std::string err;
 };
 
 namespace {
@@ -193,11 +216,12 @@ StageArgs<R> base_args(hho_ctx *ctx) {
     a.c0 = (const R *)ctx->c0;
     a.mat = (const R *)ctx->mat;
     a.tab = (const R *)ctx->tab;
-    a.groups = ctx->groups;
-    a.blk_group = ctx->blk_group;
+    a.groups = ctx->launch[ctx->shape].groups;
+    a.blk_group = ctx->launch[ctx->shape].blk_group;
     a.n_ic = ctx->plan.n_ic;
     a.S = ctx->plan.S;
-    a.cpb = ctx->plan.cpb;
+    a.cpb = ctx->launch[ctx->shape].cpb;
+    a.clock = ctx->clock;
     a.LT = ctx->LT;
     a.emat = ctx->emat;
     a.arena = ctx->arena;
@@ -214,7 +238,7 @@ hho_status compute_traces(hho_ctx *ctx) {
     a.Yin = (const R *)ctx->U;
     a.Tout = (R *)ctx->T[ctx->tcur];
     set_stage_offsets(ctx, a);
-    HCK((launch_traces<K, R>(a, ctx->n_blocks, ctx->stream)));
+    HCK((launch_traces<K, R>(a, ctx->n_blocks(), ctx->stream)));
     ctx->traces_valid = true;
     return HHO_OK;
 }
@@ -225,38 +249,41 @@ hho_status energy_now(hho_ctx *ctx, double *out_dev) {
     a.e_part = ctx->e_part;
     a.Yin = (const R *)ctx->U;
     set_stage_offsets(ctx, a);
-    HCK((launch_energy<K, R>(a, (const R *)ctx->U, ctx->n_blocks, ctx->stream)));
-    HCK(launch_energy_reduce(ctx->e_part, ctx->n_blocks, ctx->plan.S, out_dev, ctx->stream));
+    HCK((launch_energy<K, R>(a, (const R *)ctx->U, ctx->n_blocks(), ctx->stream)));
+    HCK(launch_energy_reduce(ctx->e_part, ctx->n_blocks(), ctx->plan.S, out_dev, nullptr, 0, ctx->stream));
     return HHO_OK;
 }
 
+// Enqueue n_steps steps on stream st.  Every launch argument is the same for every step (the
+// stage time and step index come from the device clock, advanced by a tick after each step),
+// so the sequence can be captured once into a graph and replayed.
 template <int K, typename R>
-hho_status run_steps(hho_ctx *ctx, double t0, double dt, int n_steps) {
+hho_status enqueue_steps(hho_ctx *ctx, hipStream_t st, int n_steps) {
     std::vector<StageCoef> co;
     if (!erk_coefficients(ctx->stages, co)) {
         ctx->err = "unsupported ERK stage count";
         return HHO_ERR_ARG;
     }
-    if (!ctx->traces_valid) {
-        hho_status s = compute_traces<K, R>(ctx);
-        if (s != HHO_OK) return s;
-    }
     const int s = ctx->stages, S = ctx->plan.S;
     StageArgs<R> a = base_args<R>(ctx);
     a.U = (R *)ctx->U;
     a.acc = (R *)ctx->acc;
-    a.dt = (R)dt;
     a.src_first = ctx->h_src.empty() ? nullptr : ctx->src_first;
     a.src = ctx->src;
     a.nterms = ctx->nterms;
     a.gload = (const R *)ctx->gload;
+    for (int m = 0; m < ctx->nterms; ++m) {
+        a.omega[m] = ctx->omega[m];
+        a.phase[m] = ctx->phase[m];
+    }
     a.nrec = ctx->nrec;
-    a.rec_steps = n_steps;
+    a.rec_steps = ctx->nrec > 0 ? (int)(ctx->rec_cap / ((size_t)S * ctx->nrec * 2)) : 0;
     a.rec_out = ctx->rec_out;
+    a.rec = ctx->rec;
+    const int ecap = ctx->record_energy ? (int)(ctx->e_hist_cap / S) : 0;
     const int Tc = ctx->tcur, Ta = (Tc + 1) % 3, Tb = (Tc + 2) % 3;
     const int Tbuf[2] = {Ta, Tb};
     for (int n = 0; n < n_steps; ++n) {
-        const double tn = t0 + n * dt;
         for (int i = 0; i < s; ++i) {
             const StageCoef &q = co[i];
             a.first = i == 0;
@@ -265,21 +292,19 @@ hho_status run_steps(hho_ctx *ctx, double t0, double dt, int n_steps) {
             a.Yout = a.last ? nullptr : (R *)ctx->Y[i % 2];
             a.Tin = (const R *)ctx->T[i == 0 ? Tc : Tbuf[(i - 1) % 2]];
             a.Tout = (R *)ctx->T[a.last ? Tc : Tbuf[i % 2]];
-            a.t = tn + q.c * dt;
+            a.c = q.c;
             a.cU = (R)q.cU;
             a.cY = (R)q.cY;
             a.ck = (R)q.ck;
             a.cb = (R)q.cb;
-            for (int m = 0; m < ctx->nterms; ++m) a.wterm[m] = (R)std::sin(ctx->omega[m] * a.t + ctx->phase[m]);
             a.e_part = (a.last && ctx->record_energy) ? ctx->e_part : nullptr;
             a.rec_first = (a.last && ctx->nrec > 0) ? ctx->rec_first : nullptr;
-            a.rec = ctx->rec;
-            a.step = n;
             set_stage_offsets(ctx, a);
-            HCK((launch_stage<K, R>(a, ctx->n_blocks, ctx->stream)));
+            HCK((launch_stage<K, R>(a, ctx->n_blocks(), st)));
         }
         if (ctx->record_energy)
-            HCK(launch_energy_reduce(ctx->e_part, ctx->n_blocks, S, ctx->e_hist + (size_t)n * S, ctx->stream));
+            HCK(launch_energy_reduce(ctx->e_part, ctx->n_blocks(), S, ctx->e_hist, ctx->clock, ecap, st));
+        HCK(launch_tick(ctx->clock, st));
     }
     return HHO_OK;
 }
@@ -295,6 +320,201 @@ hho_status dispatch(hho_ctx *ctx, Fn &&fn) {
     if (k == 1) return fn(std::integral_constant<int, 1>(), (float *)nullptr);
     if (k == 2) return fn(std::integral_constant<int, 2>(), (float *)nullptr);
     return fn(std::integral_constant<int, 3>(), (float *)nullptr);
+}
+
+
+// Steps captured per graph: a call advances full graphs, then launches the remainder directly.
+constexpr int kGraphSteps = 32;
+
+template <int K, typename R>
+hho_status autotune_shape(hho_ctx *ctx);
+
+// Common start of a stepping call: output capacities, device clock, initial energy, traces.
+hho_status begin_steps(hho_ctx *ctx, double t0, double dt, int n_steps, std::vector<double> &E0) {
+    const int S = ctx->plan.S;
+    hho_status s;
+    if (ctx->nrec > 0) {
+        const size_t need = (size_t)S * std::max(n_steps, 1) * ctx->nrec * 2;
+        if (need > ctx->rec_cap) {
+            if ((s = dalloc(ctx, (void **)&ctx->rec_out, need * sizeof(double)))) return s;
+            ctx->rec_cap = need;
+            ctx->version++;
+        }
+    }
+    if (ctx->record_energy) {
+        const size_t need = (size_t)S * std::max(n_steps, 1);
+        if (need > ctx->e_hist_cap) {
+            if ((s = dalloc(ctx, (void **)&ctx->e_hist, need * sizeof(double)))) return s;
+            ctx->e_hist_cap = need;
+            ctx->version++;
+        }
+    }
+    ctx->h_clock.t0 = t0;
+    ctx->h_clock.dt = dt;
+    ctx->h_clock.step = 0;
+    HCK(hipMemcpyAsync(ctx->clock, &ctx->h_clock, sizeof(Clock), hipMemcpyHostToDevice, ctx->stream));
+    ctx->last_steps = n_steps;
+    E0.assign(S, 0.0);
+    if (ctx->record_energy) {
+        s = dispatch(ctx, [&](auto kc, auto *r) {
+            using R = std::remove_pointer_t<decltype(r)>;
+            return energy_now<decltype(kc)::value, R>(ctx, ctx->e_now);
+        });
+        if (s != HHO_OK) return s;
+        HCK(hipMemcpyAsync(E0.data(), ctx->e_now, S * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HCK(hipStreamSynchronize(ctx->stream));
+    }
+    if (!ctx->traces_valid) {
+        s = dispatch(ctx, [&](auto kc, auto *r) {
+            using R = std::remove_pointer_t<decltype(r)>;
+            return compute_traces<decltype(kc)::value, R>(ctx);
+        });
+        if (s != HHO_OK) return s;
+    }
+    return HHO_OK;
+}
+
+// Energy criterion of Algorithm algo_CFL (Sec. 5.1) on the recorded history: growth above
+// 5 % over the initial or the previous energy of an undriven run, or a non-finite energy.
+hho_status end_steps(hho_ctx *ctx, int n_steps, const std::vector<double> &E0) {
+    if (!ctx->record_energy || n_steps == 0) return HHO_OK;
+    const int S = ctx->plan.S;
+    std::vector<double> E((size_t)n_steps * S);
+    HCK(hipMemcpyAsync(E.data(), ctx->e_hist, E.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HCK(hipStreamSynchronize(ctx->stream));
+    const bool driven = !ctx->h_src.empty() || ctx->nterms > 0;
+    for (int sh = 0; sh < S; ++sh) {
+        double prev = E0[sh];
+        for (int n = 0; n < n_steps; ++n) {
+            const double e = E[(size_t)n * S + sh];
+            if (!std::isfinite(e) || (!driven && (e > 1.05 * E0[sh] + 1e-300 || e > 1.05 * prev + 1e-300))) {
+                ctx->err = "energy of shot " + std::to_string(sh) +
+                           " grew by more than 5 % (or is not finite) at step " + std::to_string(n);
+                return HHO_ERR_UNSTABLE;
+            }
+            prev = e;
+        }
+    }
+    return HHO_OK;
+}
+
+// Capture kGraphSteps steps of one context into a graph (cached until the configuration changes).
+hho_status ensure_graph(hho_ctx *ctx) {
+    if (ctx->gexec && ctx->graph_version == ctx->version) return HHO_OK;
+    if (ctx->gexec) HCK(hipGraphExecDestroy(ctx->gexec));
+    ctx->gexec = nullptr;
+    HCK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    hho_status s = dispatch(ctx, [&](auto kc, auto *r) {
+        using R = std::remove_pointer_t<decltype(r)>;
+        return enqueue_steps<decltype(kc)::value, R>(ctx, ctx->cap_stream, kGraphSteps);
+    });
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (s != HHO_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    HCK(e);
+    const hipError_t ei = hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HCK(ei);
+    ctx->graph_version = ctx->version;
+    return HHO_OK;
+}
+
+// One graph advancing every context of a batch by `steps` steps: the contexts' step chains are
+// independent branches that fork from and join to one origin stream.
+hho_status capture_batch(hho_batch *b, int steps, hipGraphExec_t *out) {
+    const int n = (int)b->ctxs.size();
+    hipStream_t origin = b->streams[n];
+    auto fail = [&](const std::string &m, hho_status st) {
+        b->err = m;
+        return st;
+    };
+    if (hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail("batch: hipStreamBeginCapture failed", HHO_ERR_DEVICE);
+    hho_status s = HHO_OK;
+    if (hipEventRecord(b->events[n], origin) != hipSuccess) s = HHO_ERR_DEVICE;
+    for (int i = 0; i < n && s == HHO_OK; ++i) {
+        hho_ctx *ctx = b->ctxs[i];
+        if (hipStreamWaitEvent(b->streams[i], b->events[n], 0) != hipSuccess) {
+            s = HHO_ERR_DEVICE;
+            break;
+        }
+        s = dispatch(ctx, [&](auto kc, auto *r) {
+            using R = std::remove_pointer_t<decltype(r)>;
+            return enqueue_steps<decltype(kc)::value, R>(ctx, b->streams[i], steps);
+        });
+        if (s != HHO_OK) {
+            b->err = ctx->err;
+            break;
+        }
+        if (hipEventRecord(b->events[i], b->streams[i]) != hipSuccess ||
+            hipStreamWaitEvent(origin, b->events[i], 0) != hipSuccess)
+            s = HHO_ERR_DEVICE;
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(origin, &graph);
+    if (s != HHO_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s != HHO_OK ? s : fail("batch: hipStreamEndCapture failed", HHO_ERR_DEVICE);
+    }
+    const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail(std::string("batch: hipGraphInstantiate: ") + hipGetErrorString(ei), HHO_ERR_DEVICE);
+    return HHO_OK;
+}
+
+// Autotuner: time the stage kernel in each launch shape (stage-1 form: it reads U and the current
+// traces and writes only scratch stage buffers) and keep the fastest.
+template <int K, typename R>
+hho_status autotune_shape(hho_ctx *ctx) {
+    if (ctx->launch.size() < 2) return HHO_OK;
+    if (!ctx->traces_valid) {
+        hho_status s = compute_traces<K, R>(ctx);
+        if (s != HHO_OK) return s;
+    }
+    ctx->h_clock = Clock{0.0, 0.0, 0, 0};
+    HCK(hipMemcpyAsync(ctx->clock, &ctx->h_clock, sizeof(Clock), hipMemcpyHostToDevice, ctx->stream));
+    hipEvent_t e0, e1;
+    HCK(hipEventCreate(&e0));
+    HCK(hipEventCreate(&e1));
+    const int keep = ctx->shape;
+    int best = keep;
+    float best_ms = 1e30f;
+    hho_status st = HHO_OK;
+    for (size_t sh = 0; sh < ctx->launch.size() && st == HHO_OK; ++sh) {
+        ctx->shape = (int)sh;
+        StageArgs<R> a = base_args<R>(ctx);
+        a.U = (R *)ctx->U;
+        a.acc = (R *)ctx->acc;
+        a.Yin = (const R *)ctx->U;
+        a.Yout = (R *)ctx->Y[0];
+        a.Tin = (const R *)ctx->T[ctx->tcur];
+        a.Tout = (R *)ctx->T[(ctx->tcur + 1) % 3];
+        a.first = 1;
+        a.last = 0;
+        a.cU = R(1);
+        set_stage_offsets(ctx, a);
+        float ms = 0.f;
+        for (int rep = 0; rep < 8 && st == HHO_OK; ++rep) {
+            if (rep == 3 && hipEventRecord(e0, ctx->stream) != hipSuccess) st = HHO_ERR_DEVICE;
+            if (launch_stage<K, R>(a, ctx->n_blocks(), ctx->stream) != hipSuccess) st = HHO_ERR_DEVICE;
+        }
+        if (st == HHO_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = HHO_ERR_DEVICE;
+        if (st == HHO_OK && ms < best_ms) {
+            best_ms = ms;
+            best = (int)sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->shape = best;
+    if (best != keep) ctx->version++;
+    if (st != HHO_OK) ctx->err = "autotune: kernel launch or timing failed";
+    return st;
 }
 
 hho_status rebuild_sources(hho_ctx *ctx) {
@@ -320,6 +540,32 @@ hho_status rebuild_sources(hho_ctx *ctx) {
         HCK(hipMemcpyAsync(ctx->src, v.data(), v.size() * sizeof(SrcDev), hipMemcpyHostToDevice, ctx->stream));
     HCK(hipStreamSynchronize(ctx->stream));
     return HHO_OK;
+}
+
+
+// CFL-limited time step (eq. CFL, Sec. 5.1): min over cells of CFL*(s, k, shape) h_T / c_T, with
+// CFL* from Table tab::ratio_geo (triangles, squares, hexagons; polygons with five or more faces
+// use the hexagon value), c_T the largest wave speed of the cell and h_T the side of the
+// generating square (sqrt(area) for quadrilaterals and polygons, sqrt(2 area) for triangles).
+double cfl_time_step(const Plan &P, const hho_mesh *mesh, int stages) {
+    static const double table[3][3][3] = {
+        // s = 2: triangle, square, hexagon for k = 1, 2, 3
+        {{0.191, 0.106, 0.072}, {0.205, 0.099, 0.063}, {0.264, 0.136, 0.082}},
+        // s = 3
+        {{0.238, 0.133, 0.090}, {0.253, 0.123, 0.079}, {0.329, 0.170, 0.102}},
+        // s = 4
+        {{0.265, 0.147, 0.100}, {0.282, 0.138, 0.087}, {0.363, 0.188, 0.115}},
+    };
+    double dt = 1e300;
+    for (int c = 0; c < P.n_cells; ++c) {
+        const int nF = P.cell_ptr[c + 1] - P.cell_ptr[c];
+        const int shape = nF == 3 ? 0 : (nF == 4 ? 1 : 2);
+        const double h = std::sqrt(P.area[c] * (nF == 3 ? 2.0 : 1.0));
+        const double speed = P.medium[c] == kFluid ? mesh->a[c]
+                                                   : std::sqrt((mesh->a[c] + 2.0 * mesh->b[c]) / mesh->rho[c]);
+        dt = std::min(dt, table[stages - 2][shape][P.k - 1] * h / speed);
+    }
+    return dt;
 }
 
 }  // namespace
@@ -372,7 +618,6 @@ hho_status hho_setup(const hho_mesh *mesh, const hho_params *prm, hho_ctx **out)
     ctx->LT = (long long)P.n_ic * P.S;
     ctx->rows = 5 * P.N;
     ctx->trows = trace_rows(P);
-    ctx->n_blocks = (int)P.blk_group.size();
     const size_t sbytes = (size_t)ctx->rows * ctx->LT * ctx->rsize;
     const size_t tbytes = (size_t)ctx->trows * ctx->LT * ctx->rsize;
     const size_t lbytes = (size_t)P.max_nf * P.n_ic * 4;
@@ -404,8 +649,6 @@ hho_status hho_setup(const hho_mesh *mesh, const hho_params *prm, hho_ctx **out)
         ctx->c0 = take(cbytes);
         ctx->mat = take(mbytes);
     }
-    std::vector<GroupDev> gd;
-    for (const Group &g : P.groups) gd.push_back({g.medium, g.nF, g.tab_off, g.ic_begin, g.ncells, g.blk_begin});
     std::vector<int64_t> map(P.n_ext);
     for (int c = 0; c < P.n_cells; ++c) {
         const int nr = (P.medium[c] == kFluid ? 3 : 5) * P.N;
@@ -414,12 +657,34 @@ hho_status hho_setup(const hho_mesh *mesh, const hho_params *prm, hho_ctx **out)
     }
     if ((s = copy_in(ctx, ctx->link, P.link)) || (s = copy_in_real(ctx, ctx->c0, P.c0)) ||
         (s = copy_in_real(ctx, ctx->mat, P.mat)) || (s = upload_real(ctx, &ctx->tab, P.tables)) ||
-        (s = upload(ctx, &ctx->emat, P.emat)) || (s = upload(ctx, &ctx->groups, gd)) ||
-        (s = upload(ctx, &ctx->blk_group, P.blk_group)) || (s = upload(ctx, &ctx->map, map)) ||
+        (s = upload(ctx, &ctx->emat, P.emat)) || (s = upload(ctx, &ctx->map, map)) ||
         (s = dalloc(ctx, (void **)&ctx->staging, std::max<size_t>(1, P.n_ext) * 4 * sizeof(double))) ||
-        (s = dalloc(ctx, (void **)&ctx->e_part, (size_t)ctx->n_blocks * P.S * sizeof(double))) ||
-        (s = dalloc(ctx, (void **)&ctx->e_now, (size_t)P.S * sizeof(double))))
+        (s = dalloc(ctx, (void **)&ctx->e_now, (size_t)P.S * sizeof(double))) ||
+        (s = dalloc(ctx, (void **)&ctx->clock, sizeof(Clock))))
         return fail(s);
+    for (const Plan::Launch &L : P.launches) {
+        std::vector<GroupDev> gd;
+        for (size_t g = 0; g < P.groups.size(); ++g) {
+            const Group &G = P.groups[g];
+            gd.push_back({G.medium, G.nF, G.tab_off, G.ic_begin, G.ncells, L.blk_begin[g]});
+        }
+        hho_ctx::LaunchDev d;
+        d.n_blocks = (int)L.blk_group.size();
+        d.cpb = L.cpb;
+        d.lanes = L.lanes;
+        if ((s = upload(ctx, &d.groups, gd)) || (s = upload(ctx, &d.blk_group, L.blk_group))) return fail(s);
+        ctx->launch.push_back(d);
+        ctx->max_blocks = std::max(ctx->max_blocks, d.n_blocks);
+    }
+    if ((s = dalloc(ctx, (void **)&ctx->e_part, (size_t)ctx->max_blocks * P.S * sizeof(double)))) return fail(s);
+    ctx->cfl_dt = cfl_time_step(P, mesh, prm->rk_stages);
+    {
+        hipError_t e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            ctx->err = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+            return fail(HHO_ERR_DEVICE);
+        }
+    }
     *out = ctx;
     return HHO_OK;
 }
@@ -429,6 +694,8 @@ void hho_destroy(hho_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (void *p : ctx->allocs) (void)hipFree(p);
     delete ctx;
 }
@@ -510,6 +777,7 @@ hho_status hho_set_sources(hho_ctx *ctx, int32_t shot, int32_t n, const double *
         keep.push_back(e);
     }
     ctx->h_src = keep;
+    ctx->version++;
     return rebuild_sources(ctx);
 }
 
@@ -524,6 +792,7 @@ hho_status hho_set_loads(hho_ctx *ctx, int32_t n_terms, const double *g, const d
     if (s != HHO_OK) return s;
     const Plan &P = ctx->plan;
     ctx->nterms = 0;
+    ctx->version++;
     if (n_terms == 0) return HHO_OK;
     const int rows = 5 * P.N;
     std::vector<double> h((size_t)n_terms * rows * P.n_ic, 0.0);
@@ -593,6 +862,7 @@ hho_status hho_receivers(hho_ctx *ctx, int32_t n, const double *xy, const int32_
                        ctx->stream));
     HCK(hipStreamSynchronize(ctx->stream));
     ctx->nrec = n;
+    ctx->version++;
     return HHO_OK;
 }
 
@@ -604,56 +874,156 @@ hho_status hho_erk_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps) {
     }
     hho_status s = set_device(ctx);
     if (s != HHO_OK) return s;
-    const int S = ctx->plan.S;
-    if (ctx->nrec > 0) {
-        const size_t need = (size_t)S * std::max(n_steps, 1) * ctx->nrec * 2;
-        if (need > ctx->rec_cap) {
-            if ((s = dalloc(ctx, (void **)&ctx->rec_out, need * sizeof(double)))) return s;
-            ctx->rec_cap = need;
-        }
+    std::vector<double> E0;
+    if ((s = begin_steps(ctx, t0, dt, n_steps, E0))) return s;
+    const int full = n_steps / kGraphSteps, rem = n_steps % kGraphSteps;
+    if (full > 0) {
+        if ((s = ensure_graph(ctx))) return s;
+        for (int g = 0; g < full; ++g) HCK(hipGraphLaunch(ctx->gexec, ctx->stream));
     }
-    if (ctx->record_energy) {
-        const size_t need = (size_t)S * (std::max(n_steps, 1) + 1);
-        if (need > ctx->e_hist_cap) {
-            if ((s = dalloc(ctx, (void **)&ctx->e_hist, need * sizeof(double)))) return s;
-            ctx->e_hist_cap = need;
-        }
-    }
-    ctx->last_steps = n_steps;
-    std::vector<double> E0(S);
-    if (ctx->record_energy) {
+    if (rem > 0) {
         s = dispatch(ctx, [&](auto kc, auto *r) {
             using R = std::remove_pointer_t<decltype(r)>;
-            return energy_now<decltype(kc)::value, R>(ctx, ctx->e_now);
+            return enqueue_steps<decltype(kc)::value, R>(ctx, ctx->stream, rem);
         });
         if (s != HHO_OK) return s;
-        HCK(hipMemcpyAsync(E0.data(), ctx->e_now, S * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     }
+    return end_steps(ctx, n_steps, E0);
+}
+
+hho_status hho_autotune(hho_ctx *ctx, int32_t *lanes) {
+    if (!ctx) return HHO_ERR_ARG;
+    hho_status s = set_device(ctx);
+    if (s != HHO_OK) return s;
     s = dispatch(ctx, [&](auto kc, auto *r) {
         using R = std::remove_pointer_t<decltype(r)>;
-        return run_steps<decltype(kc)::value, R>(ctx, t0, dt, n_steps);
+        return autotune_shape<decltype(kc)::value, R>(ctx);
     });
     if (s != HHO_OK) return s;
-    if (ctx->record_energy && n_steps > 0) {
-        std::vector<double> E((size_t)n_steps * S);
-        HCK(hipMemcpyAsync(E.data(), ctx->e_hist, E.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-        HCK(hipStreamSynchronize(ctx->stream));
-        const bool driven = !ctx->h_src.empty() || ctx->nterms > 0;
-        for (int sh = 0; sh < S; ++sh) {
-            double prev = E0[sh];
-            for (int n = 0; n < n_steps; ++n) {
-                const double e = E[(size_t)n * S + sh];
-                if (!std::isfinite(e) ||
-                    (!driven && (e > 1.05 * E0[sh] + 1e-300 || e > 1.05 * prev + 1e-300))) {
-                    ctx->err = "energy of shot " + std::to_string(sh) + " grew by more than 5 % (or is not finite) at step " +
-                               std::to_string(n);
-                    return HHO_ERR_UNSTABLE;
-                }
-                prev = e;
+    if (lanes) *lanes = ctx->launch[ctx->shape].lanes;
+    return HHO_OK;
+}
+
+hho_status hho_set_launch(hho_ctx *ctx, int32_t lanes) {
+    if (!ctx) return HHO_ERR_ARG;
+    for (size_t i = 0; i < ctx->launch.size(); ++i)
+        if (ctx->launch[i].lanes == lanes || ctx->launch[i].lanes == lanes / ctx->plan.S * ctx->plan.S) {
+            if ((int)i != ctx->shape) {
+                ctx->shape = (int)i;
+                ctx->version++;
             }
+            return HHO_OK;
+        }
+    ctx->err = "set_launch: no launch shape with " + std::to_string(lanes) + " lanes";
+    return HHO_ERR_ARG;
+}
+
+hho_status hho_dt_cfl(const hho_ctx *ctx, double factor, double *dt) {
+    if (!ctx || !dt || !(factor > 0.0)) return HHO_ERR_ARG;
+    *dt = factor * ctx->cfl_dt;
+    return HHO_OK;
+}
+
+hho_status hho_batch_create(hho_ctx *const *ctxs, int32_t n, hho_batch **out) {
+    if (!ctxs || n <= 0 || !out) return HHO_ERR_ARG;
+    *out = nullptr;
+    for (int i = 0; i < n; ++i)
+        if (!ctxs[i] || ctxs[i]->device != ctxs[0]->device) {
+            g_setup_error = "batch: contexts must be non-null and on one device";
+            return HHO_ERR_ARG;
+        }
+    hho_batch *b = new hho_batch();
+    b->ctxs.assign(ctxs, ctxs + n);
+    (void)hipSetDevice(ctxs[0]->device);
+    for (int i = 0; i <= n; ++i) {
+        hipStream_t st;
+        hipEvent_t ev;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            g_setup_error = "batch: stream or event creation failed";
+            hho_batch_destroy(b);
+            return HHO_ERR_DEVICE;
+        }
+        b->streams.push_back(st);
+        b->events.push_back(ev);
+    }
+    *out = b;
+    return HHO_OK;
+}
+
+void hho_batch_destroy(hho_batch *b) {
+    if (!b) return;
+    if (!b->ctxs.empty()) (void)hipSetDevice(b->ctxs[0]->device);
+    for (hipStream_t st : b->streams) (void)hipStreamSynchronize(st);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    for (hipStream_t st : b->streams) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : b->events) (void)hipEventDestroy(ev);
+    delete b;
+}
+
+const char *hho_batch_last_error(const hho_batch *b) { return b ? b->err.c_str() : g_setup_error.c_str(); }
+
+hho_status hho_batch_erk_step(hho_batch *b, const double *t0, const double *dt, int32_t n_steps) {
+    if (!b || !t0 || !dt || n_steps < 0) return HHO_ERR_ARG;
+    const int n = (int)b->ctxs.size();
+    hho_ctx *c0 = b->ctxs[0];
+    hipStream_t launch_st = c0->stream;
+    if (hipSetDevice(c0->device) != hipSuccess) return HHO_ERR_DEVICE;
+    std::vector<std::vector<double>> E0(n);
+    for (int i = 0; i < n; ++i) {
+        hho_ctx *ctx = b->ctxs[i];
+        if (!(dt[i] > 0.0)) {
+            b->err = "batch_erk_step: dt must be positive";
+            return HHO_ERR_ARG;
+        }
+        hho_status s = begin_steps(ctx, t0[i], dt[i], n_steps, E0[i]);
+        if (s != HHO_OK) {
+            b->err = ctx->err;
+            return s;
+        }
+        // the batch launches on the first context's stream
+        if (ctx->stream != launch_st) {
+            if (hipStreamSynchronize(ctx->stream) != hipSuccess) return HHO_ERR_DEVICE;
         }
     }
-    return HHO_OK;
+    if (hipStreamSynchronize(launch_st) != hipSuccess) return HHO_ERR_DEVICE;
+    const int full = n_steps / kGraphSteps, rem = n_steps % kGraphSteps;
+    bool fresh = b->gexec && (int)b->versions.size() == n;
+    for (int i = 0; fresh && i < n; ++i) fresh = b->versions[i] == b->ctxs[i]->version;
+    if (full > 0 && !fresh) {
+        if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+        hho_status s = capture_batch(b, kGraphSteps, &b->gexec);
+        if (s != HHO_OK) return s;
+        b->versions.clear();
+        for (hho_ctx *ctx : b->ctxs) b->versions.push_back(ctx->version);
+    }
+    for (int g = 0; g < full; ++g)
+        if (hipGraphLaunch(b->gexec, launch_st) != hipSuccess) {
+            b->err = "batch: hipGraphLaunch failed";
+            return HHO_ERR_DEVICE;
+        }
+    for (int i = 0; i < n && rem > 0; ++i) {
+        hho_ctx *ctx = b->ctxs[i];
+        hho_status s = dispatch(ctx, [&](auto kc, auto *r) {
+            using R = std::remove_pointer_t<decltype(r)>;
+            return enqueue_steps<decltype(kc)::value, R>(ctx, launch_st, rem);
+        });
+        if (s != HHO_OK) {
+            b->err = ctx->err;
+            return s;
+        }
+    }
+    if (hipStreamSynchronize(launch_st) != hipSuccess) return HHO_ERR_DEVICE;
+    hho_status worst = HHO_OK;
+    for (int i = 0; i < n; ++i) {
+        hho_status s = end_steps(b->ctxs[i], n_steps, E0[i]);
+        if (s != HHO_OK && worst == HHO_OK) {
+            worst = s;
+            b->err = "context " + std::to_string(i) + ": " + b->ctxs[i]->err;
+        }
+    }
+    return worst;
 }
 
 hho_status hho_synchronize(hho_ctx *ctx) {

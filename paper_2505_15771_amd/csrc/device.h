@@ -27,6 +27,14 @@ struct RecDev {
     double phi[kMaxN];
 };
 
+// Device-resident time keeping of one context: the stage kernels derive the stage time, the
+// time step and the step index from it, so a captured multi-step graph replays unchanged.
+struct Clock {
+    double t0, dt;  // start time and time step of the current hho_erk_step call
+    int step;       // steps completed since t0
+    int pad;
+};
+
 template <typename R>
 struct StageArgs {
     const R *Yin;   // stage input Y_i            [rows][LT]
@@ -43,24 +51,24 @@ struct StageArgs {
     const int32_t *blk_group;
     int n_ic, S, cpb;
     long long LT;         // lanes = n_ic * S
-    double t;             // stage time t_n + c_i dt
-    R dt;
+    const Clock *clock;   // t_n = t0 + step * dt
+    double c;             // stage node: the stage time is t_n + c dt
     R cU, cY, ck, cb;     // Y_{i+1} = cU U + cY Y_i + ck dt k_i ; acc = acc + cb k_i
     int first, last;
     // point sources
     const int32_t *src_first;  // [n_ic], -1 = none
     const SrcDev *src;
-    // separable dense loads, [term][rows][n_ic]
+    // separable dense loads, [term][rows][n_ic], time factors sin(omega t + phase)
     int nterms;
     const R *gload;
-    R wterm[4];
+    double omega[4], phase[4];
     // last-stage diagnostics
     double *e_part;            // energy partials [n_blocks][S] (null = off)
     const double *emat;        // [4][n_ic]
     const int32_t *rec_first;  // [n_ic], -1 = none (null = off)
     const RecDev *rec;
-    double *rec_out;           // [S][rec_steps][nrec][2]
-    int step, nrec, rec_steps;
+    double *rec_out;           // [S][rec_steps][nrec][2]; steps beyond rec_steps are not recorded
+    int nrec, rec_steps;
     // Every per-lane and per-cell array above except gload lives in one device arena that the
     // kernels address through a single buffer resource: byte offsets of each array in it.
     const void *arena;
@@ -78,8 +86,13 @@ hipError_t launch_traces(const StageArgs<R> &a, int n_blocks, hipStream_t st);
 template <int K, typename R>
 hipError_t launch_energy(const StageArgs<R> &a, const R *state, int n_blocks, hipStream_t st);
 
-// Sum energy partials over blocks: out[s] = sum_b part[b * S + s].
-hipError_t launch_energy_reduce(const double *part, int n_blocks, int S, double *out, hipStream_t st);
+// Sum energy partials over blocks: out[s] = sum_b part[b * S + s]; with a clock, the sums go
+// to out[clock->step * S + s] (an energy history), skipped past `cap` steps.
+hipError_t launch_energy_reduce(const double *part, int n_blocks, int S, double *out, const Clock *clock, int cap,
+                                hipStream_t st);
+
+// clock->step += 1 (one thread), after the last stage of a step.
+hipError_t launch_tick(Clock *clock, hipStream_t st);
 
 // External (per-cell contiguous, float64) <-> internal ([rows][lanes], R) state copies
 // for one shot.  map[e] = internal row-major index (row * LT + ic * S) of external dof e.

@@ -114,6 +114,12 @@ __device__ __forceinline__ Bufs<R> make_bufs(const StageArgs<R> &a) {
 }
 
 template <typename R>
+__device__ __forceinline__ double stage_time(const StageArgs<R> &a) {
+    const HHO_CONST Clock *c = uni(a.clock);
+    return c->t0 + ((double)c->step + a.c) * c->dt;
+}
+
+template <typename R>
 __device__ __forceinline__ R sgn(int i) {
     return (i & 1) ? R(-1) : R(1);
 }
@@ -280,6 +286,7 @@ __device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R
 template <int ND, typename R>
 __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, const R *y,
                                           const R *kv, R *out) {
+    const R dt = R(uni(a.clock)->dt);
     R u[ND], ac[ND];
     if (a.first) {
 #pragma unroll
@@ -297,14 +304,14 @@ __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &
     if (!a.last) {
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
-            out[r] = a.cU * u[r] + a.cY * y[r] + a.ck * a.dt * kv[r];
+            out[r] = a.cU * u[r] + a.cY * y[r] + a.ck * dt * kv[r];
             bst(B.r, boff, B.yout + r * B.rowb, out[r]);
             bst(B.r, boff, B.acc + r * B.rowb, ac[r] + a.cb * kv[r]);
         }
     } else {
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
-            out[r] = u[r] + a.dt * (ac[r] + a.cb * kv[r]);
+            out[r] = u[r] + dt * (ac[r] + a.cb * kv[r]);
             bst(B.r, boff, B.u + r * B.rowb, out[r]);
         }
     }
@@ -387,7 +394,7 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
     }
     // loads F_T(t)
     for (int m = 0; m < a.nterms; ++m) {
-        const R w = a.wterm[m];
+        const R w = R(sin(a.omega[m] * stage_time(a) + a.phase[m]));
         const int gr = m * 5 * N;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
@@ -400,7 +407,7 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
         for (int e = a.src_first[ic]; e >= 0;) {
             const SrcDev &s = a.src[e];
             if (s.shot == shot) {
-                const R w = R(s.amp * ricker(a.t, s.f0, s.t0) * s.dirx);
+                const R w = R(s.amp * ricker(stage_time(a), s.f0, s.t0) * s.dirx);
 #pragma unroll
                 for (int b = 0; b < N; ++b) rp[b] += w * R(s.phi[b]);
             }
@@ -437,9 +444,12 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
                 double v = 0;
 #pragma unroll
                 for (int b = 0; b < N; ++b) v += rc.phi[b] * (double)np[b];
-                double *o = a.rec_out + (((long long)shot * a.rec_steps + a.step) * a.nrec + rc.r) * 2;
-                o[0] = v;
-                o[1] = 0.0;
+                const int step = uni(a.clock)->step;
+                if (step < a.rec_steps) {
+                    double *o = a.rec_out + (((long long)shot * a.rec_steps + step) * a.nrec + rc.r) * 2;
+                    o[0] = v;
+                    o[1] = 0.0;
+                }
                 e = rc.next;
             }
         }
@@ -553,7 +563,7 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
         }
     }
     for (int m = 0; m < a.nterms; ++m) {
-        const R w = a.wterm[m];
+        const R w = R(sin(a.omega[m] * stage_time(a) + a.phase[m]));
         const int gr = m * 5 * N;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
@@ -568,7 +578,7 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
         for (int e = a.src_first[ic]; e >= 0;) {
             const SrcDev &s = a.src[e];
             if (s.shot == shot) {
-                const double w = s.amp * ricker(a.t, s.f0, s.t0);
+                const double w = s.amp * ricker(stage_time(a), s.f0, s.t0);
                 const R wx = R(w * s.dirx), wy = R(w * s.diry);
 #pragma unroll
                 for (int b = 0; b < N; ++b) {
@@ -618,9 +628,12 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
                     v0 += rc.phi[b] * (double)nvx[b];
                     v1 += rc.phi[b] * (double)nvy[b];
                 }
-                double *o = a.rec_out + (((long long)shot * a.rec_steps + a.step) * a.nrec + rc.r) * 2;
-                o[0] = v0;
-                o[1] = v1;
+                const int step = uni(a.clock)->step;
+                if (step < a.rec_steps) {
+                    double *o = a.rec_out + (((long long)shot * a.rec_steps + step) * a.nrec + rc.r) * 2;
+                    o[0] = v0;
+                    o[1] = v1;
+                }
                 e = rc.next;
             }
         }
@@ -736,7 +749,10 @@ __global__ __launch_bounds__(kBlock) void energy_kernel(StageArgs<R> a) {
     block_energy(e, a.S, a.cpb, a.e_part);
 }
 
-__global__ void energy_reduce_kernel(const double *part, int n_blocks, int S, double *out) {
+__global__ void tick_kernel(Clock *clock) { clock->step += 1; }
+
+__global__ void energy_reduce_kernel(const double *part, int n_blocks, int S, double *out, const Clock *clock,
+                                     int cap) {
     __shared__ double buf[kBlock];
     const int s = blockIdx.x;
     double acc = 0;
@@ -747,7 +763,10 @@ __global__ void energy_reduce_kernel(const double *part, int n_blocks, int S, do
         if ((int)threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[s] = buf[0];
+    if (threadIdx.x == 0) {
+        if (!clock) out[s] = buf[0];
+        else if (clock->step < cap) out[(long long)clock->step * S + s] = buf[0];
+    }
 }
 
 template <typename R>
@@ -784,8 +803,14 @@ hipError_t launch_energy(const StageArgs<R> &a, const R *state, int n_blocks, hi
     return hipGetLastError();
 }
 
-hipError_t launch_energy_reduce(const double *part, int n_blocks, int S, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(energy_reduce_kernel, dim3(S), dim3(kBlock), 0, st, part, n_blocks, S, out);
+hipError_t launch_energy_reduce(const double *part, int n_blocks, int S, double *out, const Clock *clock, int cap,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(energy_reduce_kernel, dim3(S), dim3(kBlock), 0, st, part, n_blocks, S, out, clock, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_tick(Clock *clock, hipStream_t st) {
+    hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(1), 0, st, clock);
     return hipGetLastError();
 }
 

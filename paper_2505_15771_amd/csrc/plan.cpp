@@ -185,6 +185,7 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
     std::vector<CellGeom> geo(nc);
     P.centroid.resize(2 * nc);
     P.hT.resize(nc);
+    P.area.resize(nc);
     double hsum = 0.0;
     for (int c = 0; c < nc; ++c) {
         const int s = cell_ptr[c], n = cell_ptr[c + 1] - s;
@@ -209,6 +210,7 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
         P.centroid[2 * c] = geo[c].cx;
         P.centroid[2 * c + 1] = geo[c].cy;
         P.hT[c] = h;
+        P.area[c] = 0.5 * A2;
         hsum += h;
     }
 
@@ -388,7 +390,6 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
     }
 
     // groups (medium, class) in order of first appearance; cells of a group in input order
-    P.cpb = std::max(1, kLanesTarget / P.S);
     std::map<std::pair<int, int>, int> gid;
     std::vector<std::vector<int>> members;
     for (int c = 0; c < nc; ++c) {
@@ -410,20 +411,44 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
         }
         members[g].push_back(c);
     }
-    int ic = 0, blk = 0;
+    // launch shapes: 64, 128 and 256 lanes per workgroup (one shape when shots fill a block)
+    for (int lanes : {kLanesTarget, 2 * kLanesTarget, kBlock}) {
+        const int cpb = std::max(1, lanes / P.S);
+        bool dup = false;
+        for (const auto &L : P.launches) dup |= L.cpb == cpb;
+        if (dup) continue;
+        Plan::Launch L;
+        L.cpb = cpb;
+        L.lanes = cpb * P.S;
+        P.launches.push_back(L);
+    }
+    int cpb_max = 1;
+    for (const auto &L : P.launches) cpb_max = std::max(cpb_max, L.cpb);
+    int ic = 0;
     P.ic_of_cell.assign(nc, -1);
     for (size_t g = 0; g < P.groups.size(); ++g) {
         Group &G = P.groups[g];
         G.ic_begin = ic;
         G.ncells = (int)members[g].size();
-        G.nblk = (G.ncells + P.cpb - 1) / P.cpb;
-        G.blk_begin = blk;
         for (int l = 0; l < G.ncells; ++l) P.ic_of_cell[members[g][l]] = ic + l;
-        ic += G.nblk * P.cpb;
-        blk += G.nblk;
-        for (int b = 0; b < G.nblk; ++b) P.blk_group.push_back((int)g);
+        ic += (G.ncells + cpb_max - 1) / cpb_max * cpb_max;
     }
     P.n_ic = ic;
+    for (auto &L : P.launches) {
+        int blk = 0;
+        for (size_t g = 0; g < P.groups.size(); ++g) {
+            const int nblk = (P.groups[g].ncells + L.cpb - 1) / L.cpb;
+            L.blk_begin.push_back(blk);
+            for (int b = 0; b < nblk; ++b) L.blk_group.push_back((int)g);
+            blk += nblk;
+        }
+    }
+    P.cpb = P.launches[0].cpb;
+    P.blk_group = P.launches[0].blk_group;
+    for (size_t g = 0; g < P.groups.size(); ++g) {
+        P.groups[g].blk_begin = P.launches[0].blk_begin[g];
+        P.groups[g].nblk = (P.groups[g].ncells + P.cpb - 1) / P.cpb;
+    }
     P.cell_of_ic.assign(P.n_ic, -1);
     for (int c = 0; c < nc; ++c) P.cell_of_ic[P.ic_of_cell[c]] = c;
 

@@ -55,7 +55,7 @@ struct Plan {
     int k = 1, N = 3, F = 2, S = 1;
     int n_cells = 0, n_faces = 0, n_vertices = 0;
     int max_nf = 0;
-    int cpb = 256;           // cells per block
+    int cpb = 256;           // cells per block of the default launch shape
     int n_ic = 0;            // padded internal cells
     int64_t n_ext = 0;       // external dofs per shot
     std::vector<int64_t> ext_off;   // [n_cells+1]
@@ -65,7 +65,15 @@ struct Plan {
     std::vector<ClassInfo> classes;
     std::vector<double> tables;
     std::vector<Group> groups;
-    std::vector<int> blk_group;
+    std::vector<int> blk_group;  // default launch shape
+    // Launch shapes the autotuner can choose from: workgroups of `lanes` lanes, `cpb` cells
+    // each; groups are padded to a multiple of the largest cpb so every shape fits.
+    struct Launch {
+        int lanes = 64, cpb = 64;
+        std::vector<int> blk_group;  // group of every block
+        std::vector<int> blk_begin;  // first block of every group
+    };
+    std::vector<Launch> launches;
     // per (j, ic): link = (ic' << 4) | (interface << 3) | j', -1 = boundary face
     std::vector<int32_t> link;  // [max_nf][n_ic]
     std::vector<double> c0;     // [max_nf][n_ic] face-solve coefficient
@@ -76,6 +84,7 @@ struct Plan {
     std::vector<int32_t> cell_ptr, cell_vtx;
     std::vector<double> centroid;  // [2*n_cells]
     std::vector<double> hT;        // [n_cells]
+    std::vector<double> area;      // [n_cells]
     std::vector<double> basisC;    // [n_classes][N][N] orthonormal basis coefficients (lower)
     std::vector<int> cell_class;   // [n_cells]
 };

@@ -56,6 +56,13 @@ EXPORTS = {
     "hho_get_traces": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "hho_energy": (C.c_int, [C.c_void_p, C.c_void_p]),
     "hho_energy_history": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "hho_autotune": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "hho_set_launch": (C.c_int, [C.c_void_p, C.c_int32]),
+    "hho_dt_cfl": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double)]),
+    "hho_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
+    "hho_batch_destroy": (None, [C.c_void_p]),
+    "hho_batch_last_error": (C.c_char_p, [C.c_void_p]),
+    "hho_batch_erk_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "hho_inspect_create": (C.c_int, [C.POINTER(_Mesh), C.POINTER(_Params), C.POINTER(C.c_void_p)]),
     "hho_inspect_destroy": (None, [C.c_void_p]),
     "hho_inspect_sizes": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -239,6 +246,21 @@ class Engine:
         self._call(self.lib.hho_energy, _ptr(E))
         return E
 
+    def autotune(self):
+        """Time the stage kernel in every launch shape, keep the fastest; returns its lanes."""
+        lanes = C.c_int32()
+        self._call(self.lib.hho_autotune, C.byref(lanes))
+        return lanes.value
+
+    def set_launch(self, lanes):
+        self._call(self.lib.hho_set_launch, int(lanes))
+
+    def dt_cfl(self, factor=1.0):
+        """CFL-limited time step (eq. CFL with the paper's CFL* per cell shape) times factor."""
+        dt = C.c_double()
+        self._call(self.lib.hho_dt_cfl, float(factor), C.byref(dt))
+        return dt.value
+
     def energy_history(self, shot=0):
         E = np.zeros(max(self.last_steps, 1))
         self._call(self.lib.hho_energy_history, int(shot), _ptr(E))
@@ -271,3 +293,40 @@ class Inspect:
                                _ptr(self.mat), _ptr(self.ic_of_cell))
         lib.hho_inspect_destroy(h)
         self._h = None
+
+
+class Batch:
+    """Several engines advanced together, 32 steps per graph launch (hho_batch_*)."""
+
+    def __init__(self, engines):
+        lib = load_library()
+        self.lib = lib
+        self.engines = list(engines)
+        arr = (C.c_void_p * len(self.engines))(*[e._h.value for e in self.engines])
+        h = C.c_void_p()
+        code = lib.hho_batch_create(arr, len(self.engines), C.byref(h))
+        if code != 0:
+            raise HHOError(code, lib.hho_last_error(None).decode())
+        self._h = h
+
+    def erk_step(self, t0, dt, n_steps):
+        n = len(self.engines)
+        t0 = np.ascontiguousarray(np.broadcast_to(np.asarray(t0, np.float64), (n,)))
+        dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, np.float64), (n,)))
+        code = self.lib.hho_batch_erk_step(self._h, _ptr(t0), _ptr(dt), int(n_steps))
+        for e in self.engines:
+            e.last_steps = int(n_steps)
+        if code != 0:
+            msg = self.lib.hho_batch_last_error(self._h).decode()
+            raise (Unstable if code == 6 else HHOError)(code, msg)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.hho_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

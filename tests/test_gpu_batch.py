@@ -1,0 +1,126 @@
+"""GPU tests of the stepping driver around the stage kernel: graph replay of the step loop,
+launch-shape autotuning, the CFL time step, and batched multi-mesh / multi-shot stepping,
+each against the FP64 oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from synth import meshes as M
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_graph_replay_with_receivers_and_energy():
+    """75 steps = two replays of the 32-step graph plus 11 direct steps, called twice in a row so the
+    cached graph is reused with a new start time; state, receiver traces and energies vs the oracle."""
+    from oracle import Oracle
+    from paper_2505_15771_amd import Engine
+    say("case: graph replay 2 x 75 steps k=2")
+    mesh = M.with_materials(M.unit_square(8, p_split=0.5, seed=21), perturb=0.1, seed=22)
+    o = Oracle(mesh, 2)
+    o.set_point_sources([[0.45, 0.3]], [[0.0, 1.0]], 10.0, 0.12, 1.0)
+    rx = np.array([[0.3, 0.8], [0.6, 0.2]])
+    fld = np.array([0, 1], np.int32)
+    e = Engine(mesh, 2, record_energy=True)
+    e.set_sources(0, [[0.45, 0.3]], [[0.0, 1.0]], 10.0, 0.12, 1.0)
+    e.set_receivers(rx, fld)
+    U = 0.05 * np.random.default_rng(4).standard_normal(o.ndof)
+    e.set_state(U)
+    dt = 0.4 * 0.138 / 8 / math.sqrt(3.0)
+    t = 0.0
+    for call in range(2):
+        tr = np.zeros((75, 2, 2))
+        En = np.zeros(75)
+        for n in range(75):
+            U = o.erk(U, t + n * dt, dt, 1)
+            En[n] = o.energy(U)
+            for r in range(2):
+                c, vals = o.point_values(U, *rx[r])
+                tr[n, r, :1 + fld[r]] = vals[:1 + fld[r]]
+        e.erk_step(t, dt, 75)
+        t += 75 * dt
+        eu, et, ee = rel(e.get_state(), U), rel(e.traces(), tr), rel(e.energy_history(), En)
+        say("call", call, "state", eu, "traces", et, "energy", ee)
+        assert eu < 1e-12 and et < 1e-12 and ee < 1e-12
+
+
+def test_autotune_keeps_results():
+    """The autotuner picks a launch shape; stepping in any shape gives the same float64 state."""
+    from oracle import Oracle
+    from paper_2505_15771_amd import Engine
+    say("case: autotune k=3 f64")
+    mesh = M.with_materials(M.unit_square(20, p_split=0.5, seed=23), perturb=0.1, seed=24)
+    o = Oracle(mesh, 3)
+    U0 = np.random.default_rng(5).standard_normal(o.ndof)
+    ref = o.erk(U0, 0.0, 1e-4, 40)
+    outs = []
+    for lanes in (64, 128, 256, None):
+        e = Engine(mesh, 3)
+        if lanes is None:
+            got = e.autotune()
+            say("autotune chose", got, "lanes")
+            assert got in (64, 128, 256)
+        else:
+            e.set_launch(lanes)
+        e.set_state(U0)
+        e.erk_step(0.0, 1e-4, 40)
+        outs.append(e.get_state())
+        assert rel(outs[-1], ref) < 1e-12
+    for u in outs[1:]:
+        assert np.array_equal(u, outs[0])
+
+
+def test_dt_cfl_matches_table():
+    """hho_dt_cfl: the CFL condition eq. CFL with Table tab::ratio_geo on a hybrid mesh of squares
+    and half-square triangles (side h), c_max = sqrt(3): dt = min(0.265, 0.282) * h / sqrt(3) at k = 1."""
+    from paper_2505_15771_amd import Engine
+    mesh = M.with_materials(M.unit_square(16, p_split=0.5, seed=25))
+    for k, s, cfl in ((1, 4, 0.265), (2, 4, 0.138), (3, 3, 0.079)):
+        e = Engine(mesh, k, rk_stages=s)
+        assert abs(e.dt_cfl(0.5) - 0.5 * cfl / 16 / math.sqrt(3.0)) < 1e-15
+
+
+def test_batch_of_meshes_and_shots():
+    """Three meshes of different sizes and degrees (k = 1, 2, 3), float32 and float64, several shots
+    each, advanced by one batch (graph branches per mesh) for 70 steps; every shot vs the oracle."""
+    from oracle import Oracle
+    from paper_2505_15771_amd import Batch, Engine
+    say("case: batch of 3 meshes")
+    specs = [(6, 1, "f64", 2), (9, 2, "f32", 3), (5, 3, "f64", 1)]
+    engines, refs, dts = [], [], []
+    for i, (n, k, dtype, S) in enumerate(specs):
+        mesh = M.with_materials(M.unit_square(n, p_split=0.5, seed=30 + i), perturb=0.1, seed=40 + i)
+        e = Engine(mesh, k, dtype=dtype, n_shots=S)
+        dt = e.dt_cfl(0.5)
+        dts.append(dt)
+        shots = []
+        for sh in range(S):
+            o = Oracle(mesh, k)
+            xs = [[0.2 + 0.3 * sh, 0.3]]
+            o.set_point_sources(xs, [[0.0, 1.0]], 10.0, 0.12, 1.0)
+            e.set_sources(sh, xs, [[0.0, 1.0]], 10.0, 0.12, 1.0)
+            U0 = 0.01 * np.random.default_rng(50 + 10 * i + sh).standard_normal(o.ndof)
+            e.set_state(U0, shot=sh)
+            shots.append(o.erk(U0, 0.1, dt, 70))
+        engines.append(e)
+        refs.append(shots)
+    b = Batch(engines)
+    b.erk_step([0.1] * 3, dts, 70)
+    for i, e in enumerate(engines):
+        tol = 1e-12 if specs[i][2] == "f64" else 1e-5
+        for sh, ref in enumerate(refs[i]):
+            err = rel(e.get_state(sh), ref)
+            say("mesh", i, "shot", sh, err)
+            assert err < tol
+    b.close()
