@@ -1,0 +1,101 @@
+"""Receiver misfit and its discrete adjoint gradient for the explicit Runge-Kutta path.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Plain and slow: every stage state of
+every step is kept in memory, so it is meant for small meshes and short runs.
+
+Forward (Sec. 4.2, eq. ERK / eq. ex_solve): U^{n+1} = U^n + dt sum_i b_i k_i, k_i = L Y_i + M^{-1} F(t_i),
+Y_1 = U^n, Y_{i+1} = U^n + dt a_{i+1,i} k_i (tableaux whose matrix is subdiagonal: ERK(2), ERK(4)).
+Misfit J = 1/2 dt sum_{n=1..N} sum_r |R_r U^n - d_r^n|^2, R_r the point evaluation of p (fluid) or
+v (solid) at receiver r (the sensors of Sec. 5.2).
+Reverse sweep of each step from lambda = lambda^{n+1}:
+  mu_s = dt b_s lambda,  mu_i = dt b_i lambda + dt a_{i+1,i} L^T mu_{i+1}  (i = s-1 .. 1),
+  lambda^n = lambda + sum_i L^T mu_i + dJ/dU^n,
+  dJ/dtheta += sum_i mu_i^T (d/dtheta)(L Y_i + M^{-1} F(t_i)).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .oracle import ERK_TABLEAUX
+
+
+class Receivers:
+    """Point evaluation R_r of p (field 0, fluid) or (v_x, v_y) (field 1, solid) in the cell basis."""
+
+    def __init__(self, o, xy, field):
+        self.o = o
+        self.items = []
+        for (x, y), f in zip(np.asarray(xy, float), np.asarray(field)):
+            c = o.locate(x, y)
+            if c < 0:
+                raise ValueError("receiver outside the mesh")
+            if int(f) != int(o.medium[c]):
+                raise ValueError("receiver field does not match the medium of its cell")
+            phi = o.basis(c, x, y)[0]
+            idx = [o.offsets[c] + comp * o.N + np.arange(o.N) for comp in range(1 + int(f))]
+            self.items.append((idx, phi))
+
+    def apply(self, U):
+        out = np.zeros((len(self.items), 2))
+        for r, (idx, phi) in enumerate(self.items):
+            for comp, ix in enumerate(idx):
+                out[r, comp] = phi @ U[ix]
+        return out
+
+    def apply_T(self, res):
+        out = np.zeros(self.o.ndof)
+        for r, (idx, phi) in enumerate(self.items):
+            for comp, ix in enumerate(idx):
+                out[ix] += res[r, comp] * phi
+        return out
+
+
+def forward(o, U0, t0, dt, nsteps, s=4):
+    """Stage states Y_i and stage derivatives k_i of every step, and U^0..U^N."""
+    A, b, c = ERK_TABLEAUX[s]
+    U = np.array(U0, float, copy=True)
+    Us, stages = [U], []
+    for n in range(nsteps):
+        Ys, ks = [], []
+        for i in range(s):
+            Y = U + dt * sum(A[i, j] * ks[j] for j in range(i)) if i else U
+            ks.append(o.rhs(Y, t0 + (n + c[i]) * dt))
+            Ys.append(Y)
+        U = U + dt * sum(b[i] * ks[i] for i in range(s))
+        Us.append(U)
+        stages.append((Ys, ks))
+    return Us, stages
+
+
+def misfit(rec, Us, d_obs, dt):
+    """J = 1/2 dt sum_{n>=1} |R U^n - d^n|^2 (d_obs[n-1] holds the data of step n)."""
+    return 0.5 * dt * sum(float(np.sum((rec.apply(Us[n]) - d_obs[n - 1]) ** 2)) for n in range(1, len(Us)))
+
+
+def misfit_gradient(o, U0, t0, dt, nsteps, rec, d_obs, s=4):
+    """J and dJ/dtheta [n_cells, 3] (fluid: rho, c, 0; solid: rho, lambda, mu)."""
+    A, b, c = ERK_TABLEAUX[s]
+    for i in range(s):
+        for j in range(i - 1):
+            if A[i, j] != 0.0:
+                raise ValueError("the reverse sweep here assumes a subdiagonal Runge-Kutta matrix")
+    Us, stages = forward(o, U0, t0, dt, nsteps, s)
+    J = misfit(rec, Us, d_obs, dt)
+    lam = dt * rec.apply_T(rec.apply(Us[nsteps]) - d_obs[nsteps - 1])
+    grad = np.zeros((o.nc, 3))
+    for n in reversed(range(nsteps)):
+        Ys, ks = stages[n]
+        total = lam.copy()
+        ybar_next = None
+        for i in reversed(range(s)):
+            mu = dt * b[i] * lam
+            if i < s - 1:
+                mu = mu + dt * A[i + 1, i] * ybar_next
+            ybar = o.rhs_T(mu)
+            o.grad_terms(Ys[i], ks[i], mu, grad)
+            total += ybar
+            ybar_next = ybar
+        if n >= 1:
+            total += dt * rec.apply_T(rec.apply(Us[n]) - d_obs[n - 1])
+        lam = total
+    return J, grad

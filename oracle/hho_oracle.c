@@ -84,6 +84,9 @@ typedef struct {
     double *domega, *dphase;
     /* workspace */
     double *UF;
+    /* explicit local blocks of the weak form (built on demand for the adjoint) */
+    double *KT, *KTF, *KF, *KFT;
+    size_t *kt_off, *ktf_off, *kf_off, *kft_off;
 } orc_t;
 
 /* ---------------------------------------------------------------- small dense algebra */
@@ -510,7 +513,8 @@ void orc_destroy(orc_t *o)
     void *p[] = {o->xy, o->cptr, o->cvtx, o->med, o->rho, o->pa, o->pb, o->fv, o->fc, o->fj, o->ftag, o->cf,
                  o->flen, o->fmid, o->ftan, o->fC, o->MF, o->area, o->bary, o->hT, o->C, o->M0, o->L0, o->D,
                  o->E, o->G, o->nrm, o->tau, o->Cinv, o->Cinv_iv, o->off, o->foff, o->src_cell, o->src_phi,
-                 o->src_par, o->dload, o->domega, o->dphase, o->UF};
+                 o->src_par, o->dload, o->domega, o->dphase, o->UF, o->KT, o->KTF, o->KF, o->KFT,
+                 o->kt_off, o->ktf_off, o->kf_off, o->kft_off};
     for (size_t i = 0; i < sizeof(p) / sizeof(p[0]); ++i) free(p[i]);
     free(o);
 }
@@ -638,67 +642,78 @@ static double ricker(double t, double f0, double t0)
 
 /* ---------------------------------------------------------------- operator */
 
-/* Face solves K_F U_F = -K_FT U_T for every non-boundary face (eq. ex_solve, first line). */
-void orc_face_values(orc_t *o, const double *U, double *UF)
+/* Face system of face f (eq. ex_solve, first line): A = K_F (n x n, the face block of the weak
+ * form), r = -K_FT U_T built from the dofs of the adjacent cells (u_side[0], u_side[1]).
+ * Returns n = number of face unknowns (0 on the boundary). */
+static int face_system(const orc_t *o, int f, const double *const *u_side, double *A, double *r)
 {
     int N = o->N, nf = o->nf;
-#pragma omp parallel for schedule(static)
-    for (int f = 0; f < o->nfc; ++f) {
-        int tag = o->ftag[f];
-        if (tag == T_BND_F || tag == T_BND_S) continue;
-        int w = tag == T_INT_F ? 1 : tag == T_INT_S ? 2 : 3, n = w * nf;
-        double A[576], r[24];
-        memset(A, 0, sizeof(double) * n * n);
-        memset(r, 0, sizeof(double) * n);
-        const double *MF = o->MF + (size_t)f * nf * nf;
-        for (int side = 0; side < 2; ++side) {
-            int c = o->fc[2 * f + side];
-            int e = o->cptr[c] + o->fj[2 * f + side];
-            const double *G = o->G + (size_t)e * N * nf, *nv = o->nrm + 2 * e, *u = U + o->off[c];
-            double tau = o->tau[c];
-            if (o->med[c] == FLUID) {
-                /* rows q_F: tau (p_T - p_F, q_F)_F - (m_T . n_T, q_F)_F   (eq. stab_a, rec_a tested with q_F) */
-                int r0 = 0;  /* fluid face unknowns first */
+    int tag = o->ftag[f];
+    if (tag == T_BND_F || tag == T_BND_S) return 0;
+    int w = tag == T_INT_F ? 1 : tag == T_INT_S ? 2 : 3, n = w * nf;
+    memset(A, 0, sizeof(double) * n * n);
+    memset(r, 0, sizeof(double) * n);
+    const double *MF = o->MF + (size_t)f * nf * nf;
+    for (int side = 0; side < 2; ++side) {
+        int c = o->fc[2 * f + side];
+        int e = o->cptr[c] + o->fj[2 * f + side];
+        const double *G = o->G + (size_t)e * N * nf, *nv = o->nrm + 2 * e, *u = u_side[side];
+        double tau = o->tau[c];
+        if (o->med[c] == FLUID) {
+            /* rows q_F: tau (p_T - p_F, q_F)_F - (m_T . n_T, q_F)_F   (eq. stab_a, rec_a tested with q_F) */
+            int r0 = 0;  /* fluid face unknowns first */
+            for (int i = 0; i < nf; ++i) {
+                double t = 0, q = 0;
+                for (int a = 0; a < N; ++a) {
+                    t += G[a * nf + i] * u[a];
+                    q += G[a * nf + i] * (nv[0] * u[N + a] + nv[1] * u[2 * N + a]);
+                }
+                r[r0 + i] += tau * t - q;
+                for (int l = 0; l < nf; ++l) A[(r0 + i) * n + r0 + l] += tau * MF[i * nf + l];
+            }
+        } else {
+            int r0 = (tag == T_GAMMA) ? nf : 0;
+            for (int cc = 0; cc < 2; ++cc)
                 for (int i = 0; i < nf; ++i) {
                     double t = 0, q = 0;
                     for (int a = 0; a < N; ++a) {
-                        t += G[a * nf + i] * u[a];
-                        q += G[a * nf + i] * (nv[0] * u[N + a] + nv[1] * u[2 * N + a]);
+                        t += G[a * nf + i] * u[cc * N + a];
+                        double sn = 0;  /* (s n)_cc = sum_al (E_al n)_cc s_al */
+                        for (int al = 0; al < 3; ++al)
+                            sn += (Eten(al, cc, 0) * nv[0] + Eten(al, cc, 1) * nv[1]) * u[(2 + al) * N + a];
+                        q += G[a * nf + i] * sn;
                     }
-                    r[r0 + i] += tau * t - q;
-                    for (int l = 0; l < nf; ++l) A[(r0 + i) * n + r0 + l] += tau * MF[i * nf + l];
+                    r[r0 + cc * nf + i] += tau * t - q;
+                    for (int l = 0; l < nf; ++l) A[(r0 + cc * nf + i) * n + r0 + cc * nf + l] += tau * MF[i * nf + l];
                 }
-            } else {
-                int r0 = (tag == T_GAMMA) ? nf : 0;
-                for (int cc = 0; cc < 2; ++cc)
-                    for (int i = 0; i < nf; ++i) {
-                        double t = 0, q = 0;
-                        for (int a = 0; a < N; ++a) {
-                            t += G[a * nf + i] * u[cc * N + a];
-                            double sn = 0;  /* (s n)_cc = sum_al (E_al n)_cc s_al */
-                            for (int al = 0; al < 3; ++al)
-                                sn += (Eten(al, cc, 0) * nv[0] + Eten(al, cc, 1) * nv[1]) * u[(2 + al) * N + a];
-                            q += G[a * nf + i] * sn;
-                        }
-                        r[r0 + cc * nf + i] += tau * t - q;
-                        for (int l = 0; l < nf; ++l) A[(r0 + cc * nf + i) * n + r0 + cc * nf + l] += tau * MF[i * nf + l];
-                    }
-            }
         }
-        if (tag == T_GAMMA) {
-            /* coupling block C[i][(c,l)] = (n_G,c psi_l, psi_i)_F with n_G pointing from solid to fluid:
-             * fluid rows +C v_F, solid rows -C^T p_F (eq. HHO1 / HHO2 coupling terms) */
-            int cs = o->med[o->fc[2 * f]] == SOLID ? 0 : 1;
-            int es = o->cptr[o->fc[2 * f + cs]] + o->fj[2 * f + cs];
-            const double *ng = o->nrm + 2 * es;
-            for (int i = 0; i < nf; ++i)
-                for (int cc = 0; cc < 2; ++cc)
-                    for (int l = 0; l < nf; ++l) {
-                        double Cv = ng[cc] * MF[i * nf + l];
-                        A[i * n + nf + cc * nf + l] += Cv;
-                        A[(nf + cc * nf + l) * n + i] -= Cv;
-                    }
-        }
+    }
+    if (tag == T_GAMMA) {
+        /* coupling block C[i][(c,l)] = (n_G,c psi_l, psi_i)_F with n_G pointing from solid to fluid:
+         * fluid rows +C v_F, solid rows -C^T p_F (eq. HHO1 / HHO2 coupling terms) */
+        int cs = o->med[o->fc[2 * f]] == SOLID ? 0 : 1;
+        int es = o->cptr[o->fc[2 * f + cs]] + o->fj[2 * f + cs];
+        const double *ng = o->nrm + 2 * es;
+        for (int i = 0; i < nf; ++i)
+            for (int cc = 0; cc < 2; ++cc)
+                for (int l = 0; l < nf; ++l) {
+                    double Cv = ng[cc] * MF[i * nf + l];
+                    A[i * n + nf + cc * nf + l] += Cv;
+                    A[(nf + cc * nf + l) * n + i] -= Cv;
+                }
+    }
+    return n;
+}
+
+/* Face solves K_F U_F = -K_FT U_T for every non-boundary face (eq. ex_solve, first line). */
+void orc_face_values(orc_t *o, const double *U, double *UF)
+{
+#pragma omp parallel for schedule(static)
+    for (int f = 0; f < o->nfc; ++f) {
+        double A[576], r[24];
+        const double *us[2] = {U + o->off[o->fc[2 * f]], o->fc[2 * f + 1] >= 0 ? U + o->off[o->fc[2 * f + 1]] : NULL};
+        int n = face_system(o, f, us, A, r);
+        if (!n) continue;
         if (lu_solve(n, A, r)) fprintf(stderr, "oracle: singular face block %d\n", f);
         memcpy(UF + o->foff[f], r, sizeof(double) * n);
     }
@@ -713,101 +728,139 @@ static const double *face_slice(const orc_t *o, const double *UF, int f, int med
     return UF + o->foff[f];
 }
 
+/* Cell residual without loads, R = -(K_T u + K_TF u_F) (eq. ex_solve, second line, weak form of
+ * eq. HHO1 / HHO2): u = the cell's dofs, uf[t] = its face unknowns on local face t (the fluid slice
+ * for a fluid cell, the solid slice for a solid cell; zeros on boundary faces). */
+static void cell_residual(const orc_t *o, int c, const double *u, const double *const *uf, double *R)
+{
+    int N = o->N, nf = o->nf;
+    const double *Dx = o->D + (size_t)c * 2 * N * N, *Dd[2] = {Dx, Dx + N * N};
+    int s = o->cptr[c], m = o->cptr[c + 1] - s;
+    double tau = o->tau[c];
+    int nd = o->off[c + 1] - o->off[c];
+    memset(R, 0, sizeof(double) * nd);
+    if (o->med[c] == FLUID) {
+        const double *p = u, *mc[2] = {u + N, u + 2 * N};
+        for (int a = 0; a < N; ++a) {
+            /* m rows: (grad p_T, r)_T - (p_T - p_F, r . n)_dT      (eq. rec_a) */
+            for (int cc = 0; cc < 2; ++cc) {
+                double v = 0;
+                for (int b = 0; b < N; ++b) v += Dd[cc][a * N + b] * p[b];
+                R[(1 + cc) * N + a] = v;
+            }
+            /* p row: -(m, g_T(q_T, 0))_T = -(grad q, m)_T + (q, m . n)_dT */
+            double v = 0;
+            for (int cc = 0; cc < 2; ++cc)
+                for (int b = 0; b < N; ++b) v -= Dd[cc][b * N + a] * mc[cc][b];
+            R[a] = v;
+        }
+        for (int t2 = 0; t2 < m; ++t2) {
+            int e = s + t2, f = o->cf[e];
+            const double *E = o->E + (size_t)e * N * N, *G = o->G + (size_t)e * N * nf, *nv = o->nrm + 2 * e;
+            const double *pF = uf[t2];
+            for (int a = 0; a < N; ++a) {
+                double jump = 0, mn = 0;  /* (p_T - p_F, phi_a)_F and (m . n, phi_a)_F */
+                for (int b = 0; b < N; ++b) { jump += E[a * N + b] * p[b]; mn += E[a * N + b] * (nv[0] * mc[0][b] + nv[1] * mc[1][b]); }
+                for (int i = 0; i < nf; ++i) jump -= G[a * nf + i] * pF[i];
+                R[N + a] -= nv[0] * jump;
+                R[2 * N + a] -= nv[1] * jump;
+                R[a] += mn - tau * jump;   /* + (q, m.n)_F - tau (p_T - p_F, q)_F */
+            }
+        }
+    } else {
+        const double *vc[2] = {u, u + N}, *sa[3] = {u + 2 * N, u + 3 * N, u + 4 * N};
+        for (int a = 0; a < N; ++a) {
+            /* s rows: (grad_sym v_T, E_al phi_a)_T */
+            for (int al = 0; al < 3; ++al) {
+                double v = 0;
+                for (int cc = 0; cc < 2; ++cc)
+                    for (int d = 0; d < 2; ++d) {
+                        double q = Eten(al, cc, d);
+                        if (q == 0) continue;
+                        for (int b = 0; b < N; ++b) v += q * Dd[d][a * N + b] * vc[cc][b];
+                    }
+                R[(2 + al) * N + a] = v;
+            }
+            /* v rows: -(s, grad_sym(e_cc phi_a))_T */
+            for (int cc = 0; cc < 2; ++cc) {
+                double v = 0;
+                for (int al = 0; al < 3; ++al)
+                    for (int d = 0; d < 2; ++d) {
+                        double q = Eten(al, cc, d);
+                        if (q == 0) continue;
+                        for (int b = 0; b < N; ++b) v -= q * Dd[d][b * N + a] * sa[al][b];
+                    }
+                R[cc * N + a] = v;
+            }
+        }
+        for (int t2 = 0; t2 < m; ++t2) {
+            int e = s + t2, f = o->cf[e];
+            const double *E = o->E + (size_t)e * N * N, *G = o->G + (size_t)e * N * nf, *nv = o->nrm + 2 * e;
+            const double *vF = uf[t2];
+            for (int a = 0; a < N; ++a) {
+                double jump[2], sn[2] = {0, 0};
+                for (int cc = 0; cc < 2; ++cc) {
+                    double j = 0;
+                    for (int b = 0; b < N; ++b) j += E[a * N + b] * vc[cc][b];
+                    for (int i = 0; i < nf; ++i) j -= G[a * nf + i] * vF[cc * nf + i];
+                    jump[cc] = j;
+                    for (int al = 0; al < 3; ++al) {
+                        double En = Eten(al, cc, 0) * nv[0] + Eten(al, cc, 1) * nv[1];
+                        if (En == 0) continue;
+                        for (int b = 0; b < N; ++b) sn[cc] += En * E[a * N + b] * sa[al][b];
+                    }
+                }
+                /* s rows: - (v_T - v_F, E_al n)_F */
+                for (int al = 0; al < 3; ++al) {
+                    double v = 0;
+                    for (int cc = 0; cc < 2; ++cc) v += (Eten(al, cc, 0) * nv[0] + Eten(al, cc, 1) * nv[1]) * jump[cc];
+                    R[(2 + al) * N + a] -= v;
+                }
+                /* v rows: + (s n, w)_F - tau (v_T - v_F, w)_F */
+                for (int cc = 0; cc < 2; ++cc) R[cc * N + a] += sn[cc] - tau * jump[cc];
+            }
+        }
+    }
+}
+
+/* out = M_T^{-1} R: rho M0 for m / v, (1/kappa) M0 for p, (Cinv (x) M0) for s (eq. mass). */
+static void cell_inv_mass(const orc_t *o, int c, const double *R, double *out)
+{
+    int N = o->N;
+    /* inverse mass: rho M0 for m / v, (1/kappa) M0 for p, (Cinv (x) M0) for s */
+    const double *L0 = o->L0 + (size_t)c * N * N;
+    if (o->med[c] == FLUID) {
+        double kap = o->rho[c] * o->pa[c] * o->pa[c];
+        for (int a = 0; a < N; ++a) { out[a] = kap * R[a]; out[N + a] = R[N + a] / o->rho[c]; out[2 * N + a] = R[2 * N + a] / o->rho[c]; }
+        for (int bl = 0; bl < 3; ++bl) chol_solve(N, L0, out + bl * N);
+    } else {
+        const double *Ci = o->Cinv_iv + (size_t)c * 9;
+        for (int a = 0; a < N; ++a) {
+            out[a] = R[a] / o->rho[c];
+            out[N + a] = R[N + a] / o->rho[c];
+            for (int al = 0; al < 3; ++al) {
+                double v = 0;
+                for (int be = 0; be < 3; ++be) v += Ci[al * 3 + be] * R[(2 + be) * N + a];
+                out[(2 + al) * N + a] = v;
+            }
+        }
+        for (int bl = 0; bl < 5; ++bl) chol_solve(N, L0, out + bl * N);
+    }
+}
+
 /* Cell residual R = F_T - K_T U_T - K_TF U_F and dU = M^{-1} R (eq. ex_solve, second line). */
 static void cell_update(orc_t *o, const double *U, const double *UF, double t, double *dU)
 {
-    int N = o->N, nf = o->nf;
+    int N = o->N;
 #pragma omp parallel for schedule(static)
     for (int c = 0; c < o->nc; ++c) {
         static const double zero[64] = {0};
         const double *u = U + o->off[c];
-        const double *Dx = o->D + (size_t)c * 2 * N * N, *Dd[2] = {Dx, Dx + N * N};
-        int s = o->cptr[c], m = o->cptr[c + 1] - s;
-        double tau = o->tau[c], R[5 * 64];
-        int nd = o->off[c + 1] - o->off[c];
-        memset(R, 0, sizeof(double) * nd);
-        if (o->med[c] == FLUID) {
-            const double *p = u, *mc[2] = {u + N, u + 2 * N};
-            for (int a = 0; a < N; ++a) {
-                /* m rows: (grad p_T, r)_T - (p_T - p_F, r . n)_dT      (eq. rec_a) */
-                for (int cc = 0; cc < 2; ++cc) {
-                    double v = 0;
-                    for (int b = 0; b < N; ++b) v += Dd[cc][a * N + b] * p[b];
-                    R[(1 + cc) * N + a] = v;
-                }
-                /* p row: -(m, g_T(q_T, 0))_T = -(grad q, m)_T + (q, m . n)_dT */
-                double v = 0;
-                for (int cc = 0; cc < 2; ++cc)
-                    for (int b = 0; b < N; ++b) v -= Dd[cc][b * N + a] * mc[cc][b];
-                R[a] = v;
-            }
-            for (int t2 = 0; t2 < m; ++t2) {
-                int e = s + t2, f = o->cf[e];
-                const double *E = o->E + (size_t)e * N * N, *G = o->G + (size_t)e * N * nf, *nv = o->nrm + 2 * e;
-                const double *pF = face_slice(o, UF, f, FLUID, zero);
-                for (int a = 0; a < N; ++a) {
-                    double jump = 0, mn = 0;  /* (p_T - p_F, phi_a)_F and (m . n, phi_a)_F */
-                    for (int b = 0; b < N; ++b) { jump += E[a * N + b] * p[b]; mn += E[a * N + b] * (nv[0] * mc[0][b] + nv[1] * mc[1][b]); }
-                    for (int i = 0; i < nf; ++i) jump -= G[a * nf + i] * pF[i];
-                    R[N + a] -= nv[0] * jump;
-                    R[2 * N + a] -= nv[1] * jump;
-                    R[a] += mn - tau * jump;   /* + (q, m.n)_F - tau (p_T - p_F, q)_F */
-                }
-            }
-        } else {
-            const double *vc[2] = {u, u + N}, *sa[3] = {u + 2 * N, u + 3 * N, u + 4 * N};
-            for (int a = 0; a < N; ++a) {
-                /* s rows: (grad_sym v_T, E_al phi_a)_T */
-                for (int al = 0; al < 3; ++al) {
-                    double v = 0;
-                    for (int cc = 0; cc < 2; ++cc)
-                        for (int d = 0; d < 2; ++d) {
-                            double q = Eten(al, cc, d);
-                            if (q == 0) continue;
-                            for (int b = 0; b < N; ++b) v += q * Dd[d][a * N + b] * vc[cc][b];
-                        }
-                    R[(2 + al) * N + a] = v;
-                }
-                /* v rows: -(s, grad_sym(e_cc phi_a))_T */
-                for (int cc = 0; cc < 2; ++cc) {
-                    double v = 0;
-                    for (int al = 0; al < 3; ++al)
-                        for (int d = 0; d < 2; ++d) {
-                            double q = Eten(al, cc, d);
-                            if (q == 0) continue;
-                            for (int b = 0; b < N; ++b) v -= q * Dd[d][b * N + a] * sa[al][b];
-                        }
-                    R[cc * N + a] = v;
-                }
-            }
-            for (int t2 = 0; t2 < m; ++t2) {
-                int e = s + t2, f = o->cf[e];
-                const double *E = o->E + (size_t)e * N * N, *G = o->G + (size_t)e * N * nf, *nv = o->nrm + 2 * e;
-                const double *vF = face_slice(o, UF, f, SOLID, zero);
-                for (int a = 0; a < N; ++a) {
-                    double jump[2], sn[2] = {0, 0};
-                    for (int cc = 0; cc < 2; ++cc) {
-                        double j = 0;
-                        for (int b = 0; b < N; ++b) j += E[a * N + b] * vc[cc][b];
-                        for (int i = 0; i < nf; ++i) j -= G[a * nf + i] * vF[cc * nf + i];
-                        jump[cc] = j;
-                        for (int al = 0; al < 3; ++al) {
-                            double En = Eten(al, cc, 0) * nv[0] + Eten(al, cc, 1) * nv[1];
-                            if (En == 0) continue;
-                            for (int b = 0; b < N; ++b) sn[cc] += En * E[a * N + b] * sa[al][b];
-                        }
-                    }
-                    /* s rows: - (v_T - v_F, E_al n)_F */
-                    for (int al = 0; al < 3; ++al) {
-                        double v = 0;
-                        for (int cc = 0; cc < 2; ++cc) v += (Eten(al, cc, 0) * nv[0] + Eten(al, cc, 1) * nv[1]) * jump[cc];
-                        R[(2 + al) * N + a] -= v;
-                    }
-                    /* v rows: + (s n, w)_F - tau (v_T - v_F, w)_F */
-                    for (int cc = 0; cc < 2; ++cc) R[cc * N + a] += sn[cc] - tau * jump[cc];
-                }
-            }
-        }
+        int s = o->cptr[c], m = o->cptr[c + 1] - s, nd = o->off[c + 1] - o->off[c];
+        const double *uf[16];
+        for (int t2 = 0; t2 < m; ++t2) uf[t2] = face_slice(o, UF, o->cf[s + t2], o->med[c], zero);
+        double R[5 * 64];
+        cell_residual(o, c, u, uf, R);
         /* loads F_T (eq. rhs, load-vector reading): point sources and separable dense terms */
         for (int q = 0; q < o->nsrc; ++q) {
             if (o->src_cell[q] != c) continue;
@@ -821,26 +874,7 @@ static void cell_update(orc_t *o, const double *U, const double *UF, double t, d
             const double *g = o->dload + (size_t)q * o->off[o->nc] + o->off[c];
             for (int i = 0; i < nd; ++i) R[i] += w * g[i];
         }
-        /* inverse mass: rho M0 for m / v, (1/kappa) M0 for p, (Cinv (x) M0) for s */
-        const double *L0 = o->L0 + (size_t)c * N * N;
-        double *out = dU + o->off[c];
-        if (o->med[c] == FLUID) {
-            double kap = o->rho[c] * o->pa[c] * o->pa[c];
-            for (int a = 0; a < N; ++a) { out[a] = kap * R[a]; out[N + a] = R[N + a] / o->rho[c]; out[2 * N + a] = R[2 * N + a] / o->rho[c]; }
-            for (int bl = 0; bl < 3; ++bl) chol_solve(N, L0, out + bl * N);
-        } else {
-            const double *Ci = o->Cinv_iv + (size_t)c * 9;
-            for (int a = 0; a < N; ++a) {
-                out[a] = R[a] / o->rho[c];
-                out[N + a] = R[N + a] / o->rho[c];
-                for (int al = 0; al < 3; ++al) {
-                    double v = 0;
-                    for (int be = 0; be < 3; ++be) v += Ci[al * 3 + be] * R[(2 + be) * N + a];
-                    out[(2 + al) * N + a] = v;
-                }
-            }
-            for (int bl = 0; bl < 5; ++bl) chol_solve(N, L0, out + bl * N);
-        }
+        cell_inv_mass(o, c, R, dU + o->off[c]);
     }
 }
 
@@ -987,4 +1021,310 @@ int orc_point_values(const orc_t *o, const double *U, double x, double y, double
         vals[bl] = v;
     }
     return c;
+}
+
+/* ================================================================ discrete adjoint support
+ *
+ * The adjoint of the explicit Runge-Kutta path needs the transpose of the condensed operator
+ * L = -M^{-1} K_eff, K_eff = K_T - K_TF K_F^{-1} K_FT (eq. compact_AR, eq. ex_solve).  The oracle
+ * builds the blocks of K explicitly, cell by cell and face by face, by applying the residual
+ * routines above to unit vectors (they are linear), and then applies transposes with plain
+ * loops.  Parameter derivatives follow from the blocks that depend on the materials: the mass
+ * matrices (eq. mass) and the stabilisation weight tau_T (eq. stab); the reconstructions and the
+ * coupling block do not depend on them.
+ */
+
+/* face unknowns of a cell's slice on one face: fluid nf (p_F), solid 2 nf (v_F) */
+static int cell_face_width(const orc_t *o, int c) { return (o->med[c] == FLUID ? 1 : 2) * o->nf; }
+
+/* offset of a cell's slice inside the face unknown block of face f */
+static int face_slice_offset(const orc_t *o, int f, int c)
+{
+    return (o->ftag[f] == T_GAMMA && o->med[c] == SOLID) ? o->nf : 0;
+}
+
+static int face_width(const orc_t *o, int f) { return o->foff[f + 1] - o->foff[f]; }
+
+void orc_build_blocks(orc_t *o)
+{
+    if (o->KT) return;
+    int nc = o->nc, nfc = o->nfc;
+    o->kt_off = malloc(sizeof(size_t) * (nc + 1));
+    o->ktf_off = malloc(sizeof(size_t) * (nc + 1));
+    o->kf_off = malloc(sizeof(size_t) * (nfc + 1));
+    o->kft_off = malloc(sizeof(size_t) * (nfc + 1));
+    o->kt_off[0] = o->ktf_off[0] = 0;
+    for (int c = 0; c < nc; ++c) {
+        size_t nd = o->off[c + 1] - o->off[c], m = o->cptr[c + 1] - o->cptr[c];
+        o->kt_off[c + 1] = o->kt_off[c] + nd * nd;
+        o->ktf_off[c + 1] = o->ktf_off[c] + nd * m * cell_face_width(o, c);
+    }
+    o->kf_off[0] = o->kft_off[0] = 0;
+    for (int f = 0; f < nfc; ++f) {
+        size_t n = face_width(o, f), nd = 0;
+        if (n) for (int side = 0; side < 2; ++side) nd += o->off[o->fc[2 * f + side] + 1] - o->off[o->fc[2 * f + side]];
+        o->kf_off[f + 1] = o->kf_off[f] + n * n;
+        o->kft_off[f + 1] = o->kft_off[f] + n * nd;
+    }
+    o->KT = calloc(o->kt_off[nc] + 1, sizeof(double));
+    o->KTF = calloc(o->ktf_off[nc] + 1, sizeof(double));
+    o->KF = calloc(o->kf_off[nfc] + 1, sizeof(double));
+    o->KFT = calloc(o->kft_off[nfc] + 1, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int c = 0; c < nc; ++c) {
+        static const double zero[64] = {0};
+        int nd = o->off[c + 1] - o->off[c], m = o->cptr[c + 1] - o->cptr[c], w = cell_face_width(o, c);
+        double u[5 * 64], R[5 * 64], e[64];
+        const double *uf[16];
+        /* K_T[:, j] = -R(u = e_j, u_F = 0) */
+        for (int t = 0; t < m; ++t) uf[t] = zero;
+        double *KT = o->KT + o->kt_off[c];
+        for (int j = 0; j < nd; ++j) {
+            memset(u, 0, sizeof(double) * nd);
+            u[j] = 1.0;
+            cell_residual(o, c, u, uf, R);
+            for (int a = 0; a < nd; ++a) KT[a * nd + j] = -R[a];
+        }
+        /* K_TF[:, (t, i)] = -R(u = 0, u_F on face t = e_i); boundary faces have no unknowns */
+        double *KTF = o->KTF + o->ktf_off[c];
+        memset(u, 0, sizeof(double) * nd);
+        int ncol = m * w;
+        for (int t = 0; t < m; ++t) {
+            int f = o->cf[o->cptr[c] + t];
+            if (!face_width(o, f)) continue;
+            for (int i = 0; i < w; ++i) {
+                memset(e, 0, sizeof(double) * w);
+                e[i] = 1.0;
+                uf[t] = e;
+                cell_residual(o, c, u, uf, R);
+                uf[t] = zero;
+                for (int a = 0; a < nd; ++a) KTF[a * ncol + t * w + i] = -R[a];
+            }
+        }
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int f = 0; f < nfc; ++f) {
+        int n = face_width(o, f);
+        if (!n) continue;
+        int c0 = o->fc[2 * f], c1 = o->fc[2 * f + 1];
+        int nd0 = o->off[c0 + 1] - o->off[c0], nd1 = o->off[c1 + 1] - o->off[c1], nd = nd0 + nd1;
+        double u0[5 * 64], u1[5 * 64], A[576], r[24];
+        const double *us[2] = {u0, u1};
+        double *KFT = o->KFT + o->kft_off[f];
+        for (int j = 0; j < nd; ++j) {
+            memset(u0, 0, sizeof(double) * nd0);
+            memset(u1, 0, sizeof(double) * nd1);
+            if (j < nd0) u0[j] = 1.0;
+            else u1[j - nd0] = 1.0;
+            face_system(o, f, us, A, r);
+            for (int i = 0; i < n; ++i) KFT[i * nd + j] = -r[i];  /* r = -K_FT u */
+        }
+        memcpy(o->KF + o->kf_off[f], A, sizeof(double) * n * n);
+    }
+}
+
+/* K_eff z from the explicit blocks: K_T z + K_TF U_F, U_F = -K_F^{-1} K_FT z. */
+void orc_keff(orc_t *o, const double *z, double *out)
+{
+    orc_build_blocks(o);
+    double *UF = calloc(o->foff[o->nfc] + 1, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int f = 0; f < o->nfc; ++f) {
+        int n = face_width(o, f);
+        if (!n) continue;
+        int c0 = o->fc[2 * f], c1 = o->fc[2 * f + 1];
+        int nd0 = o->off[c0 + 1] - o->off[c0], nd = nd0 + o->off[c1 + 1] - o->off[c1];
+        const double *KFT = o->KFT + o->kft_off[f];
+        double A[576], r[24];
+        for (int i = 0; i < n; ++i) {
+            double v = 0;
+            for (int j = 0; j < nd; ++j) v -= KFT[i * nd + j] * (j < nd0 ? z[o->off[c0] + j] : z[o->off[c1] + j - nd0]);
+            r[i] = v;
+        }
+        memcpy(A, o->KF + o->kf_off[f], sizeof(double) * n * n);
+        lu_solve(n, A, r);
+        memcpy(UF + o->foff[f], r, sizeof(double) * n);
+    }
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < o->nc; ++c) {
+        int nd = o->off[c + 1] - o->off[c], m = o->cptr[c + 1] - o->cptr[c], w = cell_face_width(o, c);
+        const double *KT = o->KT + o->kt_off[c], *KTF = o->KTF + o->ktf_off[c], *zc = z + o->off[c];
+        for (int a = 0; a < nd; ++a) {
+            double v = 0;
+            for (int j = 0; j < nd; ++j) v += KT[a * nd + j] * zc[j];
+            for (int t = 0; t < m; ++t) {
+                int f = o->cf[o->cptr[c] + t];
+                if (!face_width(o, f)) continue;
+                const double *uf = UF + o->foff[f] + face_slice_offset(o, f, c);
+                for (int i = 0; i < w; ++i) v += KTF[a * m * w + t * w + i] * uf[i];
+            }
+            out[o->off[c] + a] = v;
+        }
+    }
+    free(UF);
+}
+
+/* K_eff^T z = K_T^T z + K_FT^T W_F with the adjoint face values W_F = -K_F^{-T} K_TF^T z
+ * (written to WF in the face unknown layout if WF is not NULL). */
+void orc_keff_T(orc_t *o, const double *z, double *out, double *WF)
+{
+    orc_build_blocks(o);
+    double *W = calloc(o->foff[o->nfc] + 1, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int f = 0; f < o->nfc; ++f) {
+        int n = face_width(o, f);
+        if (!n) continue;
+        double a[24], A[576], At[576];
+        memset(a, 0, sizeof(a));
+        for (int side = 0; side < 2; ++side) {
+            int c = o->fc[2 * f + side];
+            int t = o->fj[2 * f + side], m = o->cptr[c + 1] - o->cptr[c], w = cell_face_width(o, c);
+            int nd = o->off[c + 1] - o->off[c], so = face_slice_offset(o, f, c);
+            const double *KTF = o->KTF + o->ktf_off[c], *zc = z + o->off[c];
+            for (int i = 0; i < w; ++i) {
+                double v = 0;
+                for (int r = 0; r < nd; ++r) v += KTF[r * m * w + t * w + i] * zc[r];
+                a[so + i] += v;
+            }
+        }
+        memcpy(A, o->KF + o->kf_off[f], sizeof(double) * n * n);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) At[i * n + j] = A[j * n + i];
+        lu_solve(n, At, a);
+        for (int i = 0; i < n; ++i) W[o->foff[f] + i] = -a[i];
+    }
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < o->nc; ++c) {
+        int nd = o->off[c + 1] - o->off[c], m = o->cptr[c + 1] - o->cptr[c];
+        const double *KT = o->KT + o->kt_off[c], *zc = z + o->off[c];
+        double *oc = out + o->off[c];
+        for (int j = 0; j < nd; ++j) {
+            double v = 0;
+            for (int a = 0; a < nd; ++a) v += KT[a * nd + j] * zc[a];
+            oc[j] = v;
+        }
+        for (int t = 0; t < m; ++t) {
+            int f = o->cf[o->cptr[c] + t], n = face_width(o, f);
+            if (!n) continue;
+            int c0 = o->fc[2 * f], nd0 = o->off[c0 + 1] - o->off[c0];
+            int cnd = nd0 + o->off[o->fc[2 * f + 1] + 1] - o->off[o->fc[2 * f + 1]];
+            int col0 = (c == c0) ? 0 : nd0;
+            const double *KFT = o->KFT + o->kft_off[f], *Wf = W + o->foff[f];
+            for (int j = 0; j < nd; ++j) {
+                double v = 0;
+                for (int i = 0; i < n; ++i) v += KFT[i * cnd + col0 + j] * Wf[i];
+                oc[j] += v;
+            }
+        }
+    }
+    if (WF) memcpy(WF, W, sizeof(double) * o->foff[o->nfc]);
+    free(W);
+}
+
+/* M^{-1} x for every cell (eq. mass). */
+void orc_inv_mass(orc_t *o, const double *x, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < o->nc; ++c) cell_inv_mass(o, c, x + o->off[c], out + o->off[c]);
+}
+
+/* L^T x = -K_eff^T M^{-1} x (the transpose of the condensed operator). */
+void orc_rhs_T(orc_t *o, const double *x, double *out)
+{
+    int nd = o->off[o->nc];
+    double *z = malloc(sizeof(double) * (nd + 1));
+    orc_inv_mass(o, x, z);
+    orc_keff_T(o, z, out, NULL);
+    for (int i = 0; i < nd; ++i) out[i] = -out[i];
+    free(z);
+}
+
+/* Parameter derivatives of one stage, accumulated per cell into grad[c][3]:
+ *   grad -= w^T (dM/dtheta) k + (d tau_T / dtheta) sum_{F in dT} (Y_T - Y_F, w_T - W_F)_F
+ * with w = M^{-1} mu, Y_F = forward face values of Y, W_F = adjoint face values of w
+ * (mu^T (dL/dtheta) Y with L = -M^{-1} K_eff, the Schur-complement derivative written as a
+ * bilinear form on the full cell-and-face system).  Parameters: fluid (rho, c, -), solid
+ * (rho, lambda, mu); kappa = rho c^2, tau^f = eta^f / (rho c), tau^s = eta^s rho c^s. */
+void orc_grad_terms(orc_t *o, const double *Y, const double *k, const double *mu, double *grad)
+{
+    int N = o->N, nf = o->nf, nd = o->off[o->nc];
+    double *w = malloc(sizeof(double) * (nd + 1)), *tmp = malloc(sizeof(double) * (nd + 1));
+    double *YF = calloc(o->foff[o->nfc] + 1, sizeof(double)), *WF = calloc(o->foff[o->nfc] + 1, sizeof(double));
+    orc_inv_mass(o, mu, w);
+    orc_face_values(o, Y, YF);
+    orc_keff_T(o, w, tmp, WF);
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < o->nc; ++c) {
+        static const double zero[64] = {0};
+        const double *M0 = o->M0 + (size_t)c * N * N;
+        const double *yc = Y + o->off[c], *kc = k + o->off[c], *wc = w + o->off[c];
+        double rho = o->rho[c], g[3] = {0, 0, 0};
+        /* block b of w paired through M0 with block b' of k */
+        #define MDOT(bw, bk) ({ double s_ = 0; for (int a_ = 0; a_ < N; ++a_) for (int b_ = 0; b_ < N; ++b_) \
+                                s_ += wc[(bw) * N + a_] * M0[a_ * N + b_] * kc[(bk) * N + b_]; s_; })
+        int ncomp;
+        if (o->med[c] == FLUID) {
+            double cf = o->pa[c], kap = rho * cf * cf;
+            double wp = MDOT(0, 0), wm = MDOT(1, 1) + MDOT(2, 2);
+            g[0] -= -wp / (rho * kap) + wm;       /* d(1/kappa)/drho = -1/(rho kappa), d rho/d rho = 1 */
+            g[1] -= -2.0 * wp / (cf * kap);       /* d(1/kappa)/dc = -2/(c kappa) */
+            ncomp = 1;
+        } else {
+            double lam = o->pa[c], muL = o->pb[c], lpm = lam + muL;
+            double wv = MDOT(0, 0) + MDOT(1, 1);
+            double dl[9] = {-1.0 / (4 * lpm * lpm), -1.0 / (4 * lpm * lpm), 0, -1.0 / (4 * lpm * lpm),
+                            -1.0 / (4 * lpm * lpm), 0, 0, 0, 0};
+            double dA = -(lam * lam + 2 * lam * muL + 2 * muL * muL) / (4 * muL * muL * lpm * lpm);
+            double dB = lam * (lam + 2 * muL) / (4 * muL * muL * lpm * lpm);
+            double dm[9] = {dA, dB, 0, dB, dA, 0, 0, 0, -1.0 / (2 * muL * muL)};
+            double sl = 0, sm = 0;
+            for (int al = 0; al < 3; ++al)
+                for (int be = 0; be < 3; ++be) {
+                    double v = MDOT(2 + al, 2 + be);
+                    sl += dl[al * 3 + be] * v;
+                    sm += dm[al * 3 + be] * v;
+                }
+            g[0] -= wv;
+            g[1] -= sl;
+            g[2] -= sm;
+            ncomp = 2;
+        }
+        #undef MDOT
+        /* stabilisation: sum over faces of (Y_T - Y_F, w_T - W_F)_F, primal components */
+        double stab = 0;
+        int s = o->cptr[c], m = o->cptr[c + 1] - s;
+        for (int t = 0; t < m; ++t) {
+            int e = s + t, f = o->cf[e];
+            const double *E = o->E + (size_t)e * N * N, *G = o->G + (size_t)e * N * nf, *MF = o->MF + (size_t)f * nf * nf;
+            const double *yf = face_slice(o, YF, f, o->med[c], zero), *wf = face_slice(o, WF, f, o->med[c], zero);
+            for (int cc = 0; cc < ncomp; ++cc) {
+                const double *yt = yc + cc * N, *wt = wc + cc * N, *yfc = yf + cc * nf, *wfc = wf + cc * nf;
+                double v = 0;
+                for (int a = 0; a < N; ++a)
+                    for (int b = 0; b < N; ++b) v += yt[a] * E[a * N + b] * wt[b];
+                for (int a = 0; a < N; ++a)
+                    for (int i = 0; i < nf; ++i) v -= yt[a] * G[a * nf + i] * wfc[i] + wt[a] * G[a * nf + i] * yfc[i];
+                for (int i = 0; i < nf; ++i)
+                    for (int l = 0; l < nf; ++l) v += yfc[i] * MF[i * nf + l] * wfc[l];
+                stab += v;
+            }
+        }
+        double tau = o->tau[c];
+        if (o->med[c] == FLUID) {
+            g[0] -= (-tau / rho) * stab;
+            g[1] -= (-tau / o->pa[c]) * stab;
+        } else {
+            double l2m = o->pa[c] + 2 * o->pb[c];
+            if (o->stab_speed == 0) {
+                g[0] -= tau / (2 * rho) * stab;
+                g[1] -= tau / (2 * l2m) * stab;
+                g[2] -= tau / l2m * stab;
+            } else {
+                g[0] -= tau / (2 * rho) * stab;
+                g[2] -= tau / (2 * o->pb[c]) * stab;
+            }
+        }
+        for (int q = 0; q < 3; ++q) grad[3 * c + q] += g[q];
+    }
+    free(w); free(tmp); free(YF); free(WF);
 }

@@ -73,6 +73,12 @@ def _load():
             "orc_mass_dot": (D, [P, dp, dp]),
             "orc_stab_energy": (D, [P, dp]),
             "orc_point_values": (I, [P, dp, D, D, dp]),
+            "orc_build_blocks": (V, [P]),
+            "orc_keff": (V, [P, dp, dp]),
+            "orc_keff_T": (V, [P, dp, dp, P]),
+            "orc_inv_mass": (V, [P, dp, dp]),
+            "orc_rhs_T": (V, [P, dp, dp]),
+            "orc_grad_terms": (V, [P, dp, dp, dp, dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -286,6 +292,37 @@ class Oracle:
             raise ValueError("point outside the mesh")
         nb = 3 if self.medium[c] == 0 else 5
         return c, vals[:nb]
+
+    # ---------------------------------------------------------------- adjoint support
+    def keff(self, z):
+        """K_eff z from the explicit local blocks (K_T z + K_TF U_F, U_F = -K_F^{-1} K_FT z)."""
+        out = np.zeros(self.ndof)
+        self.lib.orc_keff(self._h, np.ascontiguousarray(z, np.float64), out)
+        return out
+
+    def keff_T(self, z):
+        """K_eff^T z and the adjoint face values W_F = -K_F^{-T} K_TF^T z."""
+        out = np.zeros(self.ndof)
+        W = np.zeros(max(self.lib.orc_nface_dofs(self._h), 1))
+        self.lib.orc_keff_T(self._h, np.ascontiguousarray(z, np.float64), out, W.ctypes.data_as(C.c_void_p))
+        return out, W
+
+    def inv_mass(self, x):
+        out = np.zeros(self.ndof)
+        self.lib.orc_inv_mass(self._h, np.ascontiguousarray(x, np.float64), out)
+        return out
+
+    def rhs_T(self, x):
+        """L^T x for the condensed operator L = -M^{-1} K_eff."""
+        out = np.zeros(self.ndof)
+        self.lib.orc_rhs_T(self._h, np.ascontiguousarray(x, np.float64), out)
+        return out
+
+    def grad_terms(self, Y, k, mu, grad):
+        """Accumulate mu^T (dL/dtheta) Y (+ the source part through k) into grad[n_cells, 3]."""
+        assert grad.shape == (self.nc, 3) and grad.flags.c_contiguous
+        self.lib.orc_grad_terms(self._h, np.ascontiguousarray(Y, np.float64), np.ascontiguousarray(k, np.float64),
+                                np.ascontiguousarray(mu, np.float64), grad.reshape(-1))
 
     def dense_operator(self):
         """Columns of the condensed operator L = -M^{-1} K_eff (no loads), for tiny meshes."""

@@ -25,8 +25,11 @@ def _cell_tables(ins, g):
     return med, nF, Bx, By, Sm, G, nrm
 
 
-def rhs(ins, mesh, U):
-    """k = M^{-1}(-K_eff U) for the external state U (no loads)."""
+def rhs(ins, mesh, U, adjoint=False):
+    """k = M^{-1}(-K_eff U) for the external state U (no loads).
+
+    adjoint=True models the adjoint stage instead: L^T x = D R_c(D M^{-1} x), where D flips the
+    sign of the dual unknowns (m, s) and R_c = -K_eff with the interface coupling reversed."""
     N, F = ins.N, ins.F
     med_in = np.asarray(mesh["medium"])
     nb = np.where(med_in == 0, 3, 5)
@@ -39,7 +42,16 @@ def rhs(ins, mesh, U):
         group_of_ic[b:b + n] = g
     state = {}
     for c in range(len(med_in)):
-        state[ins.ic_of_cell[c]] = U[ext_off[c]:ext_off[c + 1]].reshape(nb[c], N)
+        u = U[ext_off[c]:ext_off[c + 1]].reshape(nb[c], N).copy()
+        if adjoint:
+            ic = ins.ic_of_cell[c]
+            irho, stiff, lam, tmu = ins.mat[0, ic], ins.mat[1, ic], ins.mat[3, ic], ins.mat[4, ic]
+            if med_in[c] == 0:
+                u = np.stack([stiff * u[0], -irho * u[1], -irho * u[2]])
+            else:
+                u = np.stack([irho * u[0], irho * u[1], -(stiff * u[2] + lam * u[3]), -(lam * u[2] + stiff * u[3]),
+                              -tmu * u[4]])
+        state[ins.ic_of_cell[c]] = u
     tau = ins.mat[2]
     itau = ins.mat[5]
     # trace contributions of every cell and face
@@ -78,10 +90,11 @@ def rhs(ins, mesh, U):
             cc = ins.c0[j, ic]
             own, nbr = tr[(ic, j)], tr[(icn, jn)] * sg[None, :]
             if med == 0:
+                sc = -1.0 if adjoint else 1.0
                 if not iface:
                     pF = (own[0] + nbr[0]) * cc
                 else:
-                    pF = (own[0] + (nx * nbr[0] + ny * nbr[1]) * itau[icn]) * cc
+                    pF = (own[0] + sc * (nx * nbr[0] + ny * nbr[1]) * itau[icn]) * cc
                 w = G[j] @ pF
                 rmx += nx * w
                 rmy += ny * w
@@ -90,8 +103,9 @@ def rhs(ins, mesh, U):
                 if not iface:
                     vFx, vFy = (own[0] + nbr[0]) * cc, (own[1] + nbr[1]) * cc
                 else:
-                    pF = (nbr[0] - (nx * own[0] + ny * own[1]) * itau[ic]) * cc
-                    vFx, vFy = (own[0] + nx * pF) * itau[ic], (own[1] + ny * pF) * itau[ic]
+                    sc = -1.0 if adjoint else 1.0
+                    pF = (nbr[0] - sc * (nx * own[0] + ny * own[1]) * itau[ic]) * cc
+                    vFx, vFy = (own[0] + sc * nx * pF) * itau[ic], (own[1] + sc * ny * pF) * itau[ic]
                 wx, wy = G[j] @ vFx, G[j] @ vFy
                 rs1 += nx * wx
                 rs2 += ny * wy
@@ -100,7 +114,9 @@ def rhs(ins, mesh, U):
                 rvy += t * wy
         c = cell_of_ic[ic]
         irho, stiff, lam, tmu = ins.mat[0, ic], ins.mat[1, ic], ins.mat[3, ic], ins.mat[4, ic]
-        if med == 0:
+        if adjoint:
+            k = np.concatenate([rp, -rmx, -rmy]) if med == 0 else np.concatenate([rvx, rvy, -rs1, -rs2, -rs3])
+        elif med == 0:
             k = np.concatenate([stiff * rp, irho * rmx, irho * rmy])
         else:
             k = np.concatenate([irho * rvx, irho * rvy, stiff * rs1 + lam * rs2, lam * rs1 + stiff * rs2,

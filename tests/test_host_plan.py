@@ -92,3 +92,20 @@ def test_rejects_bad_input():
     with pytest.raises(HHOError) as e:
         Inspect(neg, 1)
     assert e.value.code == 1
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_plan_adjoint_operator(k):
+    """The transpose of the condensed operator in the form the adjoint stage kernel computes it,
+    L^T x = D R_c(D M^{-1} x) (D flips the dual unknowns, R_c reverses the interface coupling),
+    built from the host plan, equals the oracle's explicitly transposed operator."""
+    from oracle import Oracle
+    from paper_2505_15771_amd import Inspect
+    import kernel_model
+    mesh = M.hanging_square(6, seed=5)
+    ins = Inspect(mesh, k)
+    o = Oracle(mesh, k)
+    x = np.random.default_rng(k).standard_normal(o.ndof)
+    got = kernel_model.rhs(ins, mesh, x, adjoint=True)
+    ref = o.rhs_T(x)
+    assert np.linalg.norm(got - ref) < 1e-12 * np.linalg.norm(ref)
