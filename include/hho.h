@@ -176,6 +176,25 @@ hho_status hho_set_launch(hho_ctx *ctx, int32_t lanes);
  * sqrt of twice the area for triangles). */
 hho_status hho_dt_cfl(const hho_ctx *ctx, double factor, double *dt);
 
+/* Receiver misfit and its gradient with respect to the cell materials, by the discrete adjoint
+ * of the ERK time stepping of eq. ERK applied to the condensed semi-discretisation of eq. ex_solve
+ * (the sensors of Sec. 5.2 as observations).  From the current state U^0 of every shot (time t0,
+ * step dt, the sources and loads set on ctx), the call advances n_steps steps, recording the
+ * receivers, and returns
+ *   J = 1/2 dt sum_shots sum_{n=1..n_steps} sum_r |R_r U^n - d_obs[shot][n-1][r]|^2,
+ *   grad[c][0..2] = dJ/d(rho, c, -) on fluid cells, dJ/d(rho, lambda, mu) on solid cells
+ * (input cell order, float64, summed over shots; slot 2 is 0 on fluid cells).
+ * d_obs[shot][n_steps][n_rec][2] (float64, host) in the layout of hho_get_traces; may be NULL
+ * when no receivers are set (then J = 0 and grad = 0).  The reverse sweep keeps checkpoints of
+ * the state every ckpt_every steps (0: about sqrt(n_steps)) and recomputes one segment of
+ * stage data at a time, so device memory grows as n_steps / ckpt_every states plus
+ * ckpt_every * rk_stages stage records; the workspace is kept for later calls.
+ * On return (synchronised) the state is U^{n_steps}, and hho_get_traces / hho_energy_history
+ * report the forward run, as after hho_erk_step.  Only rk_stages 2 and 4 (subdiagonal
+ * Runge-Kutta matrices) are supported: ARG otherwise; UNSTABLE as hho_erk_step. */
+hho_status hho_adjoint_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps, int32_t ckpt_every,
+                            const double *d_obs, double *J, double *grad);
+
 /* Batched stepping: several contexts (meshes of different sizes and degrees, each with its own
  * shots) advanced together.  Every group of 32 steps of all contexts is one graph launch in which
  * the contexts' step chains are independent branches; remaining steps are launched directly.

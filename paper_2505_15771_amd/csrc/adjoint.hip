@@ -1,0 +1,580 @@
+// HIP kernels (gfx950) of the discrete adjoint of the explicit Runge-Kutta path, and the
+// receiver-misfit gradient with respect to the per-cell materials.
+//
+// Forward stage (Sec. 4.2, eq. ex_solve): k_i = L Y_i + M^{-1} F(t_i), L = -M^{-1} K_eff.
+// Reverse sweep of a step (subdiagonal tableaux of eq. ERK), from lambda = lambda^{n+1}:
+//   mu_s = dt b_s lambda,  mu_i = dt b_i lambda + dt a_{i+1,i} Ybar_{i+1},  Ybar_i = L^T mu_i,
+//   lambda^n = lambda + sum_i Ybar_i + dJ/dU^n.
+// L^T is applied with the forward machinery: K is a skew part (reconstructions eq. rec_a /
+// rec_e, the interface coupling) plus the symmetric stabilisation (eq. stab), so
+// K^T = D K_c D, where D flips the sign of the dual unknowns (m, s) and K_c is K with the
+// interface coupling reversed; hence L^T mu = D R_c(z) with z = D M^{-1} mu and R_c = -K_c,eff
+// evaluated by the same face-condensed cell residual as the forward stage.  The lanes keep
+// z between stages (and exchange its trace contributions exactly as the forward stage does).
+//
+// Gradient: mu^T (dL/dtheta) Y = -w^T (dM/dtheta) k - (dtau_T/dtheta) sum_{F in dT}
+// (Y_T - Y_F, w_T - W_F)_F with w = M^{-1} mu = D z, Y_F the forward face values of Y (stored
+// by the recompute) and W_F the face values of the adjoint face solve: the Schur-complement
+// derivative is a bilinear form on the cell-and-face system, and only the mass matrices
+// (eq. mass) and the stabilisation weight tau_T depend on the materials.  Accumulated per
+// lane in float64.
+#include <hip/hip_runtime.h>
+
+#include "stage_common.h"
+
+namespace hho {
+namespace {
+
+// Parameter-derivative slots of StageArgs::gm ([8][n_ic]).
+//   fluid: 0 d(1/kappa)/drho, 1 d(1/kappa)/dc, 2 dtau/drho, 3 dtau/dc
+//   solid: 0 dtau/drho, 1 dtau/dlambda, 2 dtau/dmu, 3 dA/dlambda (= dB/dlambda),
+//          4 dA/dmu, 5 dB/dmu, 6 dC/dmu   (compliance [[A, B, 0], [B, A, 0], [0, 0, C]])
+
+template <typename R>
+__device__ __forceinline__ double gmv(const StageArgs<R> &a, int slot, int ic) {
+    return a.gm[(long long)slot * a.n_ic + ic];
+}
+
+__device__ __forceinline__ void add_grad(double *g, long long LT, long long lane, double g0, double g1, double g2) {
+    g[lane] += g0;
+    g[LT + lane] += g1;
+    g[2 * LT + lane] += g2;
+}
+
+// ------------------------------------------------------------------------- fluid cells
+template <int K, int NF, typename R>
+__device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
+                                              const LaneInfo &L) {
+    constexpr int N = Dim<K>::N, F = Dim<K>::F;
+    const int nic = a.n_ic, ic = L.ic, shot = L.shot;
+    const unsigned boff = L.boff, coff = L.coff;
+    const long long lane = boff / sizeof(R), LT = a.LT;
+    const HHO_CONST R *Bx = tb;
+    const HHO_CONST R *By = tb + N * N;
+    const HHO_CONST R *Sm = tb + 2 * N * N;
+    const HHO_CONST R *Gt = tb + 3 * N * N;
+    const HHO_CONST R *nr = Gt + nF * N * F;
+    int lk[NF];
+    R cc[NF], rn[NF][2][F];
+    load_links<NF, R>(B, nF, ic, lk, cc);
+    R p[N], mx[N], my[N];  // z = D M^{-1} mu
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        p[b] = bld<R>(B.r, boff, B.yin + (b)*B.rowb);
+        mx[b] = bld<R>(B.r, boff, B.yin + (N + b) * B.rowb);
+        my[b] = bld<R>(B.r, boff, B.yin + (2 * N + b) * B.rowb);
+    }
+    load_incoming<K, NF, R>(B, kFluid, nF, lk, boff, rn);
+    const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
+    const R kap = bld<R>(B.r, coff, B.mat + kStiff * B.crowb);
+    const R irho = bld<R>(B.r, coff, B.mat + kInvRho * B.crowb);
+    // stored forward data of this stage: primal rows of Y, the derivative k, the face values
+    R yp[N], yf[NF][F];
+    double wk_p = 0, wk_m = 0;
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        yp[b] = a.yfwd[(long long)b * LT + lane];
+        const R kp = a.kfwd[(long long)b * LT + lane];
+        const R kmx = a.kfwd[(long long)(N + b) * LT + lane], kmy = a.kfwd[(long long)(2 * N + b) * LT + lane];
+        // w = D z: w_p = p, w_m = -m
+        wk_p += (double)p[b] * (double)kp;
+        wk_m -= (double)mx[b] * (double)kmx + (double)my[b] * (double)kmy;
+    }
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+#pragma unroll
+        for (int i = 0; i < F; ++i) yf[j][i] = lk[j] < 0 ? R(0) : a.ffwd[(long long)((j * 2) * F + i) * LT + lane];
+    // adjoint residual R_c(z) (interface coupling reversed) and the stabilisation pairing
+    R rp[N], rmx[N], rmy[N], tp[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) tp[b] = tau * p[b];
+    double stab = 0;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        R sx = 0, sy = 0, sd = 0;
+        double ys = 0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            sx += Bx[r * N + b] * p[b];
+            sy += By[r * N + b] * p[b];
+            sd += Bx[b * N + r] * mx[b] + By[b * N + r] * my[b] + Sm[r * N + b] * tp[b];
+            ys += (double)Sm[r * N + b] * (double)p[b];
+        }
+        rmx[r] = sx;
+        rmy[r] = sy;
+        rp[r] = -sd;
+        stab += (double)yp[r] * ys;  // Y_T^T S w_T  (S = sum over all faces of E_j)
+    }
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        if (lk[j] < 0) continue;  // boundary face: face values 0
+        const R nx = nr[2 * j], ny = nr[2 * j + 1];
+        R r[F];
+#pragma unroll
+        for (int i = 0; i < F; ++i) r[i] = R(0);
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            const R q = tp[b] - nx * mx[b] - ny * my[b];
+#pragma unroll
+            for (int i = 0; i < F; ++i) r[i] += Gt[(j * N + b) * F + i] * q;
+        }
+        R pF[F];
+        if (!((lk[j] >> 3) & 1)) {
+#pragma unroll
+            for (int i = 0; i < F; ++i) pF[i] = (r[i] + rn[j][0][i]) * cc[j];
+        } else {
+            // interface with the coupling reversed: n_G -> -n_G
+#pragma unroll
+            for (int i = 0; i < F; ++i) pF[i] = (r[i] - nx * rn[j][0][i] - ny * rn[j][1][i]) * cc[j];
+        }
+        double sj = 0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            R w = 0;
+            double gy = 0, gw = 0;
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                w += Gt[(j * N + b) * F + i] * pF[i];
+                gy += (double)Gt[(j * N + b) * F + i] * (double)pF[i];
+                gw += (double)Gt[(j * N + b) * F + i] * (double)yf[j][i];
+            }
+            rmx[b] += nx * w;
+            rmy[b] += ny * w;
+            rp[b] += tau * w;
+            sj += (double)yp[b] * gy + (double)p[b] * gw;  // Y_T^T G W_F + w_T^T G Y_F
+        }
+#pragma unroll
+        for (int i = 0; i < F; ++i) sj -= (double)yf[j][i] * (double)pF[i];  // - Y_F . W_F
+        stab -= sj;
+    }
+    // Ybar = D R_c(z)
+    R yb[3 * N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        yb[b] = rp[b];
+        yb[N + b] = -rmx[b];
+        yb[2 * N + b] = -rmy[b];
+    }
+    // epilogue: every load before the first store
+    R lam[3 * N], lac[3 * N];
+#pragma unroll
+    for (int r = 0; r < 3 * N; ++r) {
+        lam[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
+        lac[r] = a.first ? R(0) : bld<R>(B.r, boff, B.acc + r * B.rowb);
+    }
+    double g0 = a.gacc[lane], g1 = a.gacc[LT + lane];
+    g0 -= gmv(a, 0, ic) * wk_p + wk_m + gmv(a, 2, ic) * stab;
+    g1 -= gmv(a, 1, ic) * wk_p + gmv(a, 3, ic) * stab;
+    a.gacc[lane] = g0;
+    a.gacc[LT + lane] = g1;
+    R mu[3 * N];
+    if (!a.last) {
+#pragma unroll
+        for (int r = 0; r < 3 * N; ++r) {
+            const R acc = lac[r] + yb[r];
+            bst(B.r, boff, B.acc + r * B.rowb, acc);
+            mu[r] = a.mu_b * lam[r] + a.mu_a * yb[r];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 3 * N; ++r) lam[r] += lac[r] + yb[r];
+        if (a.inject >= 1 && a.rec_first) {
+            for (int e = a.rec_first[ic]; e >= 0;) {
+                const RecDev &rc = a.rec[e];
+                double v = 0;
+#pragma unroll
+                for (int b = 0; b < N; ++b) v += rc.phi[b] * (double)yp[b];
+                const double d = a.dobs[(((long long)shot * a.nobs + a.inject - 1) * a.nrec + rc.r) * 2];
+                const double w = uni(a.clock)->dt * (v - d);
+#pragma unroll
+                for (int b = 0; b < N; ++b) lam[b] += R(w * rc.phi[b]);
+                e = rc.next;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 3 * N; ++r) {
+            bst(B.r, boff, B.u + r * B.rowb, lam[r]);
+            mu[r] = a.zs_b * lam[r];
+        }
+    }
+    // next adjoint stage input z = D M^{-1} mu and its outgoing traces
+    R zp[N], zx[N], zy[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        zp[b] = kap * mu[b];
+        zx[b] = -irho * mu[N + b];
+        zy[b] = -irho * mu[2 * N + b];
+        bst(B.r, boff, B.yout + b * B.rowb, zp[b]);
+        bst(B.r, boff, B.yout + (N + b) * B.rowb, zx[b]);
+        bst(B.r, boff, B.yout + (2 * N + b) * B.rowb, zy[b]);
+    }
+    fluid_traces<K, NF, R>(a, B, tb, nF, lk, shot, zp, zx, zy, tau);
+}
+
+// ------------------------------------------------------------------------- solid cells
+template <int K, int NF, typename R>
+__device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
+                                              const LaneInfo &L) {
+    constexpr int N = Dim<K>::N, F = Dim<K>::F;
+    const int nic = a.n_ic, ic = L.ic, shot = L.shot;
+    const unsigned boff = L.boff, coff = L.coff;
+    const long long lane = boff / sizeof(R), LT = a.LT;
+    const R r2 = R(kRsqrt2);
+    const HHO_CONST R *Bx = tb;
+    const HHO_CONST R *By = tb + N * N;
+    const HHO_CONST R *Sm = tb + 2 * N * N;
+    const HHO_CONST R *Gt = tb + 3 * N * N;
+    const HHO_CONST R *nr = Gt + nF * N * F;
+    int lk[NF];
+    R cc[NF], rn[NF][2][F];
+    load_links<NF, R>(B, nF, ic, lk, cc);
+    R vx[N], vy[N], s1[N], s2[N], s3[N];  // z = D M^{-1} mu
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        vx[b] = bld<R>(B.r, boff, B.yin + (b)*B.rowb);
+        vy[b] = bld<R>(B.r, boff, B.yin + (N + b) * B.rowb);
+        s1[b] = bld<R>(B.r, boff, B.yin + (2 * N + b) * B.rowb);
+        s2[b] = bld<R>(B.r, boff, B.yin + (3 * N + b) * B.rowb);
+        s3[b] = bld<R>(B.r, boff, B.yin + (4 * N + b) * B.rowb);
+    }
+    load_incoming<K, NF, R>(B, kSolid, nF, lk, boff, rn);
+    const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
+    const R itau = bld<R>(B.r, coff, B.mat + kInvTau * B.crowb);
+    const R irho = bld<R>(B.r, coff, B.mat + kInvRho * B.crowb);
+    const R l2m = bld<R>(B.r, coff, B.mat + kStiff * B.crowb);
+    const R lam_ = bld<R>(B.r, coff, B.mat + kLam * B.crowb);
+    const R tmu = bld<R>(B.r, coff, B.mat + kTwoMu * B.crowb);
+    R yx[N], yy[N], yf[NF][2][F];
+    double wk_v = 0, P11 = 0, P12 = 0, P21 = 0, P22 = 0, P33 = 0;
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        yx[b] = a.yfwd[(long long)b * LT + lane];
+        yy[b] = a.yfwd[(long long)(N + b) * LT + lane];
+        const double k0 = a.kfwd[(long long)b * LT + lane], k1 = a.kfwd[(long long)(N + b) * LT + lane];
+        const double k2 = a.kfwd[(long long)(2 * N + b) * LT + lane];
+        const double k3 = a.kfwd[(long long)(3 * N + b) * LT + lane];
+        const double k4 = a.kfwd[(long long)(4 * N + b) * LT + lane];
+        // w = D z: w_v = v, w_s = -s
+        wk_v += (double)vx[b] * k0 + (double)vy[b] * k1;
+        P11 -= (double)s1[b] * k2;
+        P12 -= (double)s1[b] * k3;
+        P21 -= (double)s2[b] * k2;
+        P22 -= (double)s2[b] * k3;
+        P33 -= (double)s3[b] * k4;
+    }
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int i = 0; i < F; ++i)
+                yf[j][c][i] = lk[j] < 0 ? R(0) : a.ffwd[(long long)((j * 2 + c) * F + i) * LT + lane];
+    R rvx[N], rvy[N], rs1[N], rs2[N], rs3[N], tvx[N], tvy[N], hs3[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        tvx[b] = tau * vx[b];
+        tvy[b] = tau * vy[b];
+        hs3[b] = r2 * s3[b];
+    }
+    double stab = 0;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        R a1 = 0, a2 = 0, a3 = 0, bx = 0, by = 0;
+        double yx_s = 0, yy_s = 0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            const R bxrb = Bx[r * N + b], byrb = By[r * N + b];
+            const R bxbr = Bx[b * N + r], bybr = By[b * N + r], srb = Sm[r * N + b];
+            a1 += bxrb * vx[b];
+            a2 += byrb * vy[b];
+            a3 += byrb * vx[b] + bxrb * vy[b];
+            bx += bxbr * s1[b] + bybr * hs3[b] + srb * tvx[b];
+            by += bybr * s2[b] + bxbr * hs3[b] + srb * tvy[b];
+            yx_s += (double)srb * (double)vx[b];
+            yy_s += (double)srb * (double)vy[b];
+        }
+        rs1[r] = a1;
+        rs2[r] = a2;
+        rs3[r] = r2 * a3;
+        rvx[r] = -bx;
+        rvy[r] = -by;
+        stab += (double)yx[r] * yx_s + (double)yy[r] * yy_s;
+    }
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        if (lk[j] < 0) continue;
+        const R nx = nr[2 * j], ny = nr[2 * j + 1];
+        R rx[F], ry[F];
+#pragma unroll
+        for (int i = 0; i < F; ++i) rx[i] = ry[i] = R(0);
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            const R qx = tvx[b] - nx * s1[b] - ny * hs3[b];
+            const R qy = tvy[b] - nx * hs3[b] - ny * s2[b];
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                rx[i] += Gt[(j * N + b) * F + i] * qx;
+                ry[i] += Gt[(j * N + b) * F + i] * qy;
+            }
+        }
+        R vFx[F], vFy[F];
+        if (!((lk[j] >> 3) & 1)) {
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                vFx[i] = (rx[i] + rn[j][0][i]) * cc[j];
+                vFy[i] = (ry[i] + rn[j][1][i]) * cc[j];
+            }
+        } else {
+            // interface with the coupling reversed: n_G -> -n_G
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                const R pF = (rn[j][0][i] + (nx * rx[i] + ny * ry[i]) * itau) * cc[j];
+                vFx[i] = (rx[i] - nx * pF) * itau;
+                vFy[i] = (ry[i] - ny * pF) * itau;
+            }
+        }
+        double sj = 0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            R wx = 0, wy = 0;
+            double gyx = 0, gyy = 0, gwx = 0, gwy = 0;
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                const R g = Gt[(j * N + b) * F + i];
+                wx += g * vFx[i];
+                wy += g * vFy[i];
+                gyx += (double)g * (double)vFx[i];
+                gyy += (double)g * (double)vFy[i];
+                gwx += (double)g * (double)yf[j][0][i];
+                gwy += (double)g * (double)yf[j][1][i];
+            }
+            rs1[b] += nx * wx;
+            rs2[b] += ny * wy;
+            rs3[b] += r2 * (ny * wx + nx * wy);
+            rvx[b] += tau * wx;
+            rvy[b] += tau * wy;
+            sj += (double)yx[b] * gyx + (double)yy[b] * gyy + (double)vx[b] * gwx + (double)vy[b] * gwy;
+        }
+#pragma unroll
+        for (int i = 0; i < F; ++i) sj -= (double)yf[j][0][i] * (double)vFx[i] + (double)yf[j][1][i] * (double)vFy[i];
+        stab -= sj;
+    }
+    R yb[5 * N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        yb[b] = rvx[b];
+        yb[N + b] = rvy[b];
+        yb[2 * N + b] = -rs1[b];
+        yb[3 * N + b] = -rs2[b];
+        yb[4 * N + b] = -rs3[b];
+    }
+    R lam[5 * N], lac[5 * N];
+#pragma unroll
+    for (int r = 0; r < 5 * N; ++r) {
+        lam[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
+        lac[r] = a.first ? R(0) : bld<R>(B.r, boff, B.acc + r * B.rowb);
+    }
+    double g0 = a.gacc[lane], g1 = a.gacc[LT + lane], g2 = a.gacc[2 * LT + lane];
+    g0 -= wk_v + gmv(a, 0, ic) * stab;
+    g1 -= gmv(a, 3, ic) * (P11 + P12 + P21 + P22) + gmv(a, 1, ic) * stab;
+    g2 -= gmv(a, 4, ic) * (P11 + P22) + gmv(a, 5, ic) * (P12 + P21) + gmv(a, 6, ic) * P33 + gmv(a, 2, ic) * stab;
+    a.gacc[lane] = g0;
+    a.gacc[LT + lane] = g1;
+    a.gacc[2 * LT + lane] = g2;
+    R mu[5 * N];
+    if (!a.last) {
+#pragma unroll
+        for (int r = 0; r < 5 * N; ++r) {
+            bst(B.r, boff, B.acc + r * B.rowb, lac[r] + yb[r]);
+            mu[r] = a.mu_b * lam[r] + a.mu_a * yb[r];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 5 * N; ++r) lam[r] += lac[r] + yb[r];
+        if (a.inject >= 1 && a.rec_first) {
+            for (int e = a.rec_first[ic]; e >= 0;) {
+                const RecDev &rc = a.rec[e];
+                double v0 = 0, v1 = 0;
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    v0 += rc.phi[b] * (double)yx[b];
+                    v1 += rc.phi[b] * (double)yy[b];
+                }
+                const double *d = a.dobs + (((long long)shot * a.nobs + a.inject - 1) * a.nrec + rc.r) * 2;
+                const double dt = uni(a.clock)->dt;
+                const double w0 = dt * (v0 - d[0]), w1 = dt * (v1 - d[1]);
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    lam[b] += R(w0 * rc.phi[b]);
+                    lam[N + b] += R(w1 * rc.phi[b]);
+                }
+                e = rc.next;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 5 * N; ++r) {
+            bst(B.r, boff, B.u + r * B.rowb, lam[r]);
+            mu[r] = a.zs_b * lam[r];
+        }
+    }
+    R zx[N], zy[N], z1[N], z2[N], z3[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        zx[b] = irho * mu[b];
+        zy[b] = irho * mu[N + b];
+        z1[b] = -(l2m * mu[2 * N + b] + lam_ * mu[3 * N + b]);
+        z2[b] = -(lam_ * mu[2 * N + b] + l2m * mu[3 * N + b]);
+        z3[b] = -tmu * mu[4 * N + b];
+        bst(B.r, boff, B.yout + b * B.rowb, zx[b]);
+        bst(B.r, boff, B.yout + (N + b) * B.rowb, zy[b]);
+        bst(B.r, boff, B.yout + (2 * N + b) * B.rowb, z1[b]);
+        bst(B.r, boff, B.yout + (3 * N + b) * B.rowb, z2[b]);
+        bst(B.r, boff, B.yout + (4 * N + b) * B.rowb, z3[b]);
+    }
+    solid_traces<K, NF, R>(a, B, tb, nF, lk, shot, zx, zy, z1, z2, z3, tau, itau);
+}
+
+template <int K, int NF, typename R>
+__device__ __forceinline__ void adjoint_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L) {
+    const HHO_CONST R *tb = uni(a.tab) + G.tab_off;
+    const Bufs<R> B = make_bufs(a);
+    if (G.medium == kFluid)
+        fluid_adjoint<K, NF, R>(a, B, tb, G.nF, L);
+    else
+        solid_adjoint<K, NF, R>(a, B, tb, G.nF, L);
+}
+
+template <int K, typename R>
+__global__ __launch_bounds__(kBlock) void adjoint_kernel(StageArgs<R> a) {
+    GroupDev G;
+    const LaneInfo L = decode_lane(a, G);
+    if (!L.active) return;
+    if (G.nF <= 4) adjoint_body<K, 4, R>(a, G, L);
+    else adjoint_body<K, kMaxFaces, R>(a, G, L);
+}
+
+// Start of the reverse sweep: lambda += dt R^T (R U - d^n) (primal rows of U read from a.yfwd,
+// n = a.inject; receivers of the lane's cell), then z = D M^{-1}(zs_b lambda) and its outgoing traces.
+template <int K, int NF, typename R>
+__device__ __forceinline__ void start_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L) {
+    constexpr int N = Dim<K>::N;
+    const HHO_CONST R *tb = uni(a.tab) + G.tab_off;
+    const Bufs<R> B = make_bufs(a);
+    const int ic = L.ic, nb = G.medium == kFluid ? 3 : 5, ncomp = G.medium == kFluid ? 1 : 2;
+    const unsigned boff = L.boff, coff = L.coff;
+    int lk[NF];
+    load_links<NF, R>(B, G.nF, ic, lk, (R *)nullptr);
+    R u[2][N], lam[5 * N];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < N; ++b) u[c][b] = c < ncomp ? a.yfwd[(long long)(c * N + b) * a.LT + L.ic * a.S + L.shot] : R(0);
+#pragma unroll
+    for (int r = 0; r < 5 * N; ++r) lam[r] = r < nb * N ? bld<R>(B.r, boff, B.u + r * B.rowb) : R(0);
+    const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
+    const R itau = bld<R>(B.r, coff, B.mat + kInvTau * B.crowb);
+    const R irho = bld<R>(B.r, coff, B.mat + kInvRho * B.crowb);
+    const R stiff = bld<R>(B.r, coff, B.mat + kStiff * B.crowb);
+    const R lamL = bld<R>(B.r, coff, B.mat + kLam * B.crowb);
+    const R tmu = bld<R>(B.r, coff, B.mat + kTwoMu * B.crowb);
+    if (a.inject >= 1 && a.rec_first) {
+        for (int e = a.rec_first[ic]; e >= 0;) {
+            const RecDev &rc = a.rec[e];
+            const double *d = a.dobs + (((long long)L.shot * a.nobs + a.inject - 1) * a.nrec + rc.r) * 2;
+            const double dt = uni(a.clock)->dt;
+            for (int c = 0; c < ncomp; ++c) {
+                double v = 0;
+#pragma unroll
+                for (int b = 0; b < N; ++b) v += rc.phi[b] * (double)u[c][b];
+                const double w = dt * (v - d[c]);
+#pragma unroll
+                for (int b = 0; b < N; ++b) lam[c * N + b] += R(w * rc.phi[b]);
+            }
+            e = rc.next;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 5 * N; ++r)
+        if (r < nb * N) bst(B.r, boff, B.u + r * B.rowb, lam[r]);
+    R z[5][N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        if (G.medium == kFluid) {
+            z[0][b] = stiff * a.zs_b * lam[b];
+            z[1][b] = -irho * a.zs_b * lam[N + b];
+            z[2][b] = -irho * a.zs_b * lam[2 * N + b];
+            z[3][b] = z[4][b] = R(0);
+        } else {
+            z[0][b] = irho * a.zs_b * lam[b];
+            z[1][b] = irho * a.zs_b * lam[N + b];
+            z[2][b] = -a.zs_b * (stiff * lam[2 * N + b] + lamL * lam[3 * N + b]);
+            z[3][b] = -a.zs_b * (lamL * lam[2 * N + b] + stiff * lam[3 * N + b]);
+            z[4][b] = -a.zs_b * tmu * lam[4 * N + b];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+            if (q < nb) bst(B.r, boff, B.yout + (q * N + b) * B.rowb, z[q][b]);
+    if (G.medium == kFluid)
+        fluid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.shot, z[0], z[1], z[2], tau);
+    else
+        solid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.shot, z[0], z[1], z[2], z[3], z[4], tau, itau);
+}
+
+template <int K, typename R>
+__global__ __launch_bounds__(kBlock) void adjoint_start_kernel(StageArgs<R> a) {
+    GroupDev G;
+    const LaneInfo L = decode_lane(a, G);
+    if (!L.active) return;
+    if (G.nF <= 4) start_body<K, 4, R>(a, G, L);
+    else start_body<K, kMaxFaces, R>(a, G, L);
+}
+
+// grad[c][q] = sum over shots of the lane accumulators of cell c (input cell order).
+__global__ __launch_bounds__(256) void grad_reduce_kernel(const double *gacc, long long LT, int S,
+                                                         const int32_t *ic_of_cell, int n_cells, double *out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    const long long base = (long long)ic_of_cell[c] * S;
+    for (int q = 0; q < 3; ++q) {
+        double v = 0;
+        for (int sh = 0; sh < S; ++sh) v += gacc[q * LT + base + sh];
+        out[3 * c + q] = v;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_grad_reduce(const double *gacc, long long LT, int S, const int32_t *ic_of_cell, int n_cells,
+                              double *out, hipStream_t st) {
+    if (n_cells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3((n_cells + 255) / 256), dim3(256), 0, st, gacc, LT, S, ic_of_cell,
+                       n_cells, out);
+    return hipGetLastError();
+}
+
+template <int K, typename R>
+hipError_t launch_adjoint_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
+    hipLaunchKernelGGL((adjoint_kernel<K, R>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int K, typename R>
+hipError_t launch_adjoint_start(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
+    hipLaunchKernelGGL((adjoint_start_kernel<K, R>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    return hipGetLastError();
+}
+
+#define HHO_ADJ_INST(K, R)                                                                      \
+    template hipError_t launch_adjoint_stage<K, R>(const StageArgs<R> &, int, hipStream_t);    \
+    template hipError_t launch_adjoint_start<K, R>(const StageArgs<R> &, int, hipStream_t);
+HHO_ADJ_INST(1, double)
+HHO_ADJ_INST(2, double)
+HHO_ADJ_INST(3, double)
+HHO_ADJ_INST(1, float)
+HHO_ADJ_INST(2, float)
+HHO_ADJ_INST(3, float)
+
+}  // namespace hho

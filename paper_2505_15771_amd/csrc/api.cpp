@@ -15,6 +15,28 @@
 
 using namespace hho;
 
+// Workspace of the discrete adjoint (allocated by the first hho_adjoint_step, grown on demand).
+struct AdjWork {
+    // adjoint arena, addressed by the kernels through one buffer resource like the forward one:
+    // lambda, z (two stage buffers), the running sum of L^T mu, two trace buffers, and copies of
+    // the link / face-coefficient / material arrays
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+    void *lam = nullptr, *Z[2] = {nullptr, nullptr}, *acc = nullptr, *T[2] = {nullptr, nullptr};
+    int32_t *link = nullptr;
+    void *c0 = nullptr, *mat = nullptr;
+    // forward data of one checkpoint segment: per (step, stage) slot the primal rows of Y_i
+    // ([2N][LT]), k_i ([5N][LT]) and the primal face values of Y_i ([trace rows][LT])
+    size_t slot_elems = 0, k_off = 0, f_off = 0;
+    void *store = nullptr;
+    size_t store_slots = 0;
+    void *ckpt = nullptr;  // checkpoints U^{g * every} and U^N, [n + 1][5N][LT]
+    size_t ckpt_states = 0;
+    double *gacc = nullptr, *gm = nullptr, *grad = nullptr, *dobs = nullptr;
+    size_t dobs_cap = 0;
+    int32_t *ic_of_cell = nullptr;
+};
+
 struct hho_ctx {
     Plan plan;
     int dtype = 0, stages = 4, record_energy = 0, device = 0;
@@ -70,6 +92,7 @@ struct hho_ctx {
     hipGraphExec_t gexec = nullptr;
     unsigned version = 1, graph_version = 0;  // graph is valid when graph_version == version
     double cfl_dt = 0.0;                       // CFL-limited time step at factor 1
+    AdjWork adj;
 };
 
 struct hho_batch {
@@ -109,6 +132,14 @@ hho_status dalloc(hho_ctx *ctx, void **p, size_t bytes) {
         return HHO_ERR_DEVICE;
     }
     return HHO_OK;
+}
+
+// free an allocation made by dalloc (null-safe)
+void dfree(hho_ctx *ctx, void *p) {
+    if (!p) return;
+    auto it = std::find(ctx->allocs.begin(), ctx->allocs.end(), p);
+    if (it != ctx->allocs.end()) ctx->allocs.erase(it);
+    (void)hipFree(p);
 }
 
 template <typename T>
@@ -194,18 +225,19 @@ bool erk_coefficients(int s, std::vector<StageCoef> &out) {
     return true;
 }
 
-unsigned arena_off(const hho_ctx *ctx, const void *p) {
-    return p ? (unsigned)((const char *)p - (const char *)ctx->arena) : 0u;
+unsigned arena_off(const void *arena, const void *p) {
+    return p ? (unsigned)((const char *)p - (const char *)arena) : 0u;
 }
 
+// byte offsets of the per-stage arrays inside the arena the arguments address (a.arena)
 template <typename R>
-void set_stage_offsets(hho_ctx *ctx, StageArgs<R> &a) {
-    a.o_yin = arena_off(ctx, a.Yin);
-    a.o_yout = arena_off(ctx, a.Yout);
-    a.o_u = arena_off(ctx, a.U);
-    a.o_acc = arena_off(ctx, a.acc);
-    a.o_tin = arena_off(ctx, a.Tin);
-    a.o_tout = arena_off(ctx, a.Tout);
+void set_stage_offsets(hho_ctx *, StageArgs<R> &a) {
+    a.o_yin = arena_off(a.arena, a.Yin);
+    a.o_yout = arena_off(a.arena, a.Yout);
+    a.o_u = arena_off(a.arena, a.U);
+    a.o_acc = arena_off(a.arena, a.acc);
+    a.o_tin = arena_off(a.arena, a.Tin);
+    a.o_tout = arena_off(a.arena, a.Tout);
 }
 
 template <typename R>
@@ -226,9 +258,9 @@ StageArgs<R> base_args(hho_ctx *ctx) {
     a.emat = ctx->emat;
     a.arena = ctx->arena;
     a.arena_bytes = (unsigned)ctx->arena_bytes;
-    a.o_link = arena_off(ctx, ctx->link);
-    a.o_c0 = arena_off(ctx, ctx->c0);
-    a.o_mat = arena_off(ctx, ctx->mat);
+    a.o_link = arena_off(ctx->arena, ctx->link);
+    a.o_c0 = arena_off(ctx->arena, ctx->c0);
+    a.o_mat = arena_off(ctx->arena, ctx->mat);
     return a;
 }
 
@@ -257,8 +289,12 @@ hho_status energy_now(hho_ctx *ctx, double *out_dev) {
 // Enqueue n_steps steps on stream st.  Every launch argument is the same for every step (the
 // stage time and step index come from the device clock, advanced by a tick after each step),
 // so the sequence can be captured once into a graph and replayed.
+//
+// With `store` non-null (the adjoint's forward recompute), step n, stage i additionally writes the
+// primal rows of Y_i, k_i and the face values of Y_i to slot n * s + i of `store`
+// (AdjWork::slot_elems reals per slot); receivers and energy are not recorded then.
 template <int K, typename R>
-hho_status enqueue_steps(hho_ctx *ctx, hipStream_t st, int n_steps) {
+hho_status enqueue_steps(hho_ctx *ctx, hipStream_t st, int n_steps, R *store = nullptr) {
     std::vector<StageCoef> co;
     if (!erk_coefficients(ctx->stages, co)) {
         ctx->err = "unsupported ERK stage count";
@@ -297,12 +333,21 @@ hho_status enqueue_steps(hho_ctx *ctx, hipStream_t st, int n_steps) {
             a.cY = (R)q.cY;
             a.ck = (R)q.ck;
             a.cb = (R)q.cb;
-            a.e_part = (a.last && ctx->record_energy) ? ctx->e_part : nullptr;
-            a.rec_first = (a.last && ctx->nrec > 0) ? ctx->rec_first : nullptr;
+            a.e_part = (a.last && ctx->record_energy && !store) ? ctx->e_part : nullptr;
+            a.rec_first = (a.last && ctx->nrec > 0 && !store) ? ctx->rec_first : nullptr;
             set_stage_offsets(ctx, a);
-            HCK((launch_stage<K, R>(a, ctx->n_blocks(), st)));
+            if (store) {
+                const AdjWork &w = ctx->adj;
+                R *slot = store + (size_t)(n * s + i) * w.slot_elems;
+                a.ystore = slot;
+                a.kstore = slot + w.k_off;
+                a.fstore = slot + w.f_off;
+                HCK((launch_stage_store<K, R>(a, ctx->n_blocks(), st)));
+            } else {
+                HCK((launch_stage<K, R>(a, ctx->n_blocks(), st)));
+            }
         }
-        if (ctx->record_energy)
+        if (ctx->record_energy && !store)
             HCK(launch_energy_reduce(ctx->e_part, ctx->n_blocks(), S, ctx->e_hist, ctx->clock, ecap, st));
         HCK(launch_tick(ctx->clock, st));
     }
@@ -566,6 +611,139 @@ double cfl_time_step(const Plan &P, const hho_mesh *mesh, int stages) {
         dt = std::min(dt, table[stages - 2][shape][P.k - 1] * h / speed);
     }
     return dt;
+}
+
+// ----------------------------------------------------------------------------- discrete adjoint
+
+// Allocate (or grow) the adjoint workspace for segments of `every` steps and n_seg checkpoints.
+hho_status ensure_adjoint(hho_ctx *ctx, int every, int n_seg) {
+    AdjWork &w = ctx->adj;
+    const Plan &P = ctx->plan;
+    const size_t LT = (size_t)ctx->LT, rs = ctx->rsize;
+    const size_t sbytes = (size_t)ctx->rows * LT * rs;
+    hho_status s;
+    if (!w.arena) {
+        const size_t tbytes = (size_t)ctx->trows * LT * rs;
+        const size_t lbytes = (size_t)P.max_nf * P.n_ic * 4;
+        const size_t cbytes = (size_t)P.max_nf * P.n_ic * rs;
+        const size_t mbytes = (size_t)kNumMat * P.n_ic * rs;
+        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        const size_t total = 4 * al(sbytes) + 2 * al(tbytes) + al(lbytes) + al(cbytes) + al(mbytes);
+        if ((s = dalloc(ctx, &w.arena, total))) return s;
+        w.arena_bytes = total;
+        char *p = (char *)w.arena;
+        auto take = [&](size_t b) {
+            void *q = p;
+            p += al(b);
+            return q;
+        };
+        w.lam = take(sbytes);
+        w.Z[0] = take(sbytes);
+        w.Z[1] = take(sbytes);
+        w.acc = take(sbytes);
+        w.T[0] = take(tbytes);
+        w.T[1] = take(tbytes);
+        w.link = (int32_t *)take(lbytes);
+        w.c0 = take(cbytes);
+        w.mat = take(mbytes);
+        HCK(hipMemcpyAsync(w.link, ctx->link, lbytes, hipMemcpyDeviceToDevice, ctx->stream));
+        HCK(hipMemcpyAsync(w.c0, ctx->c0, cbytes, hipMemcpyDeviceToDevice, ctx->stream));
+        HCK(hipMemcpyAsync(w.mat, ctx->mat, mbytes, hipMemcpyDeviceToDevice, ctx->stream));
+        const size_t N = P.N;
+        w.k_off = 2 * N * LT;
+        w.f_off = 7 * N * LT;
+        w.slot_elems = (7 * N + ctx->trows) * LT;
+        std::vector<int32_t> ic(P.ic_of_cell.begin(), P.ic_of_cell.end());
+        if ((s = dalloc(ctx, (void **)&w.gacc, 3 * LT * sizeof(double))) || (s = upload(ctx, &w.gm, P.gm)) ||
+            (s = dalloc(ctx, (void **)&w.grad, 3 * (size_t)std::max(1, P.n_cells) * sizeof(double))) ||
+            (s = upload(ctx, &w.ic_of_cell, ic)))
+            return s;
+    }
+    const size_t slots = (size_t)every * ctx->stages;
+    if (slots > w.store_slots) {
+        dfree(ctx, w.store);
+        w.store = nullptr;
+        w.store_slots = 0;
+        if ((s = dalloc(ctx, &w.store, slots * w.slot_elems * rs))) return s;
+        w.store_slots = slots;
+    }
+    if ((size_t)n_seg + 1 > w.ckpt_states) {
+        dfree(ctx, w.ckpt);
+        w.ckpt = nullptr;
+        w.ckpt_states = 0;
+        if ((s = dalloc(ctx, &w.ckpt, ((size_t)n_seg + 1) * sbytes))) return s;
+        w.ckpt_states = (size_t)n_seg + 1;
+    }
+    return HHO_OK;
+}
+
+// Reverse sweep (see adjoint.hip): terminal misfit derivative, then for every checkpoint segment
+// from the last, the forward recompute with stores and the adjoint stages of its steps in reverse.
+template <int K, typename R>
+hho_status adjoint_sweep(hho_ctx *ctx, const std::vector<StageCoef> &co, int every, int n_seg, int n_steps,
+                         double t0, double dt, std::vector<Clock> &clocks) {
+    AdjWork &w = ctx->adj;
+    const int s = ctx->stages;
+    const size_t sbytes = (size_t)ctx->rows * ctx->LT * ctx->rsize;
+    StageArgs<R> a = base_args<R>(ctx);
+    a.arena = w.arena;
+    a.arena_bytes = (unsigned)w.arena_bytes;
+    a.link = w.link;
+    a.c0 = (const R *)w.c0;
+    a.mat = (const R *)w.mat;
+    a.o_link = arena_off(w.arena, w.link);
+    a.o_c0 = arena_off(w.arena, w.c0);
+    a.o_mat = arena_off(w.arena, w.mat);
+    a.U = (R *)w.lam;
+    a.acc = (R *)w.acc;
+    a.gacc = w.gacc;
+    a.gm = w.gm;
+    a.rec_first = ctx->nrec > 0 ? ctx->rec_first : nullptr;
+    a.rec = ctx->rec;
+    a.nrec = ctx->nrec;
+    a.dobs = w.dobs;
+    a.nobs = n_steps;
+    a.zs_b = (R)(dt * co[s - 1].cb);
+    // lambda^N = dJ/dU^N, z for the last stage of the last step
+    a.yfwd = (const R *)ctx->U;
+    a.Yout = (R *)w.Z[0];
+    a.Tout = (R *)w.T[0];
+    a.inject = n_steps;
+    set_stage_offsets(ctx, a);
+    HCK((launch_adjoint_start<K, R>(a, ctx->n_blocks(), ctx->stream)));
+    int cur = 0;
+    R *store = (R *)w.store;
+    for (int g = n_seg - 1; g >= 0; --g) {
+        const int n0 = g * every, len = std::min(every, n_steps - n0);
+        HCK(hipMemcpyAsync(ctx->U, (char *)w.ckpt + (size_t)g * sbytes, sbytes, hipMemcpyDeviceToDevice,
+                           ctx->stream));
+        hho_status st = compute_traces<K, R>(ctx);
+        if (st != HHO_OK) return st;
+        clocks[g] = Clock{t0, dt, n0, 0};
+        HCK(hipMemcpyAsync(ctx->clock, &clocks[g], sizeof(Clock), hipMemcpyHostToDevice, ctx->stream));
+        if ((st = enqueue_steps<K, R>(ctx, ctx->stream, len, store))) return st;
+        for (int n = len - 1; n >= 0; --n) {
+            for (int i = s - 1; i >= 0; --i) {
+                const R *slot = store + (size_t)(n * s + i) * w.slot_elems;
+                a.yfwd = slot;
+                a.kfwd = slot + w.k_off;
+                a.ffwd = slot + w.f_off;
+                a.Yin = (const R *)w.Z[cur];
+                a.Yout = (R *)w.Z[1 - cur];
+                a.Tin = (const R *)w.T[cur];
+                a.Tout = (R *)w.T[1 - cur];
+                a.first = i == s - 1;
+                a.last = i == 0;
+                a.mu_b = i > 0 ? (R)(dt * co[i - 1].cb) : R(0);
+                a.mu_a = i > 0 ? (R)(dt * co[i - 1].ck) : R(0);
+                a.inject = i == 0 ? n0 + n : 0;
+                set_stage_offsets(ctx, a);
+                HCK((launch_adjoint_stage<K, R>(a, ctx->n_blocks(), ctx->stream)));
+                cur ^= 1;
+            }
+        }
+    }
+    return HHO_OK;
 }
 
 }  // namespace
@@ -891,6 +1069,91 @@ hho_status hho_erk_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps) {
     return end_steps(ctx, n_steps, E0);
 }
 
+hho_status hho_adjoint_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps, int32_t ckpt_every,
+                            const double *d_obs, double *J, double *grad) {
+    if (!ctx) return HHO_ERR_ARG;
+    if (n_steps < 1 || !(dt > 0.0) || !std::isfinite(t0) || ckpt_every < 0 || !J || !grad ||
+        (ctx->nrec > 0 && !d_obs)) {
+        ctx->err = "adjoint_step: n_steps >= 1, dt > 0, ckpt_every >= 0, J, grad (and d_obs with receivers) required";
+        return HHO_ERR_ARG;
+    }
+    std::vector<StageCoef> co;
+    if (!erk_coefficients(ctx->stages, co)) return HHO_ERR_ARG;
+    for (const StageCoef &q : co)
+        if (q.cY != 0.0) {
+            ctx->err = "adjoint_step: the reverse sweep needs a subdiagonal Runge-Kutta matrix (rk_stages 2 or 4)";
+            return HHO_ERR_ARG;
+        }
+    hho_status s = set_device(ctx);
+    if (s != HHO_OK) return s;
+    const int every = ckpt_every > 0 ? std::min<int>(ckpt_every, n_steps)
+                                     : std::max(1, (int)std::ceil(std::sqrt((double)n_steps)));
+    const int n_seg = (n_steps + every - 1) / every;
+    if ((s = ensure_adjoint(ctx, every, n_seg))) return s;
+    AdjWork &w = ctx->adj;
+    const Plan &P = ctx->plan;
+    const int S = P.S;
+    const size_t sbytes = (size_t)ctx->rows * ctx->LT * ctx->rsize;
+    // forward pass with checkpoints U^{g * every}, then U^N
+    std::vector<double> E0;
+    if ((s = begin_steps(ctx, t0, dt, n_steps, E0))) return s;
+    for (int g = 0; g < n_seg; ++g) {
+        HCK(hipMemcpyAsync((char *)w.ckpt + (size_t)g * sbytes, ctx->U, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+        const int len = std::min(every, n_steps - g * every);
+        s = dispatch(ctx, [&](auto kc, auto *r) {
+            using R = std::remove_pointer_t<decltype(r)>;
+            return enqueue_steps<decltype(kc)::value, R>(ctx, ctx->stream, len);
+        });
+        if (s != HHO_OK) return s;
+    }
+    if ((s = end_steps(ctx, n_steps, E0))) return s;
+    void *uN = (char *)w.ckpt + (size_t)n_seg * sbytes;
+    HCK(hipMemcpyAsync(uN, ctx->U, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+    // misfit J = 1/2 dt sum_shots sum_n sum_r |R_r U^n - d_r^n|^2 from the recorded traces
+    double Jv = 0.0;
+    const size_t per_shot = (size_t)n_steps * ctx->nrec * 2;
+    if (ctx->nrec > 0) {
+        const size_t stride = ctx->rec_cap / (size_t)S;
+        std::vector<double> tr(stride * S);
+        HCK(hipMemcpyAsync(tr.data(), ctx->rec_out, tr.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HCK(hipStreamSynchronize(ctx->stream));
+        for (int sh = 0; sh < S; ++sh)
+            for (size_t e = 0; e < per_shot; ++e) {
+                const double d = tr[sh * stride + e] - d_obs[sh * per_shot + e];
+                Jv += d * d;
+            }
+        Jv *= 0.5 * dt;
+        const size_t need = per_shot * S;
+        if (need > w.dobs_cap) {
+            dfree(ctx, w.dobs);
+            w.dobs = nullptr;
+            w.dobs_cap = 0;
+            if ((s = dalloc(ctx, (void **)&w.dobs, need * sizeof(double)))) return s;
+            w.dobs_cap = need;
+        }
+        HCK(hipMemcpyAsync(w.dobs, d_obs, need * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    }
+    // reverse sweep
+    HCK(hipMemsetAsync(w.lam, 0, sbytes, ctx->stream));
+    HCK(hipMemsetAsync(w.gacc, 0, 3 * (size_t)ctx->LT * sizeof(double), ctx->stream));
+    std::vector<Clock> clocks(n_seg);
+    s = dispatch(ctx, [&](auto kc, auto *r) {
+        using R = std::remove_pointer_t<decltype(r)>;
+        return adjoint_sweep<decltype(kc)::value, R>(ctx, co, every, n_seg, n_steps, t0, dt, clocks);
+    });
+    if (s != HHO_OK) return s;
+    HCK(launch_grad_reduce(w.gacc, ctx->LT, S, w.ic_of_cell, P.n_cells, w.grad, ctx->stream));
+    HCK(hipMemcpyAsync(grad, w.grad, 3 * (size_t)P.n_cells * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    // leave the context at U^N, as after hho_erk_step
+    HCK(hipMemcpyAsync(ctx->U, uN, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->h_clock = Clock{t0, dt, n_steps, 0};
+    HCK(hipMemcpyAsync(ctx->clock, &ctx->h_clock, sizeof(Clock), hipMemcpyHostToDevice, ctx->stream));
+    HCK(hipStreamSynchronize(ctx->stream));
+    ctx->traces_valid = false;
+    *J = Jv;
+    return HHO_OK;
+}
+
 hho_status hho_autotune(hho_ctx *ctx, int32_t *lanes) {
     if (!ctx) return HHO_ERR_ARG;
     hho_status s = set_device(ctx);
@@ -1043,8 +1306,10 @@ hho_status hho_get_traces(hho_ctx *ctx, int32_t shot, double *out) {
     if (ctx->nrec == 0 || ctx->last_steps == 0) return HHO_OK;
     hho_status s = set_device(ctx);
     if (s != HHO_OK) return s;
+    // shots are strided by the recording capacity, which may exceed the last call's steps
     const size_t n = (size_t)ctx->last_steps * ctx->nrec * 2;
-    HCK(hipMemcpyAsync(out, ctx->rec_out + (size_t)shot * n, n * sizeof(double), hipMemcpyDeviceToHost,
+    const size_t stride = ctx->rec_cap / (size_t)ctx->plan.S;
+    HCK(hipMemcpyAsync(out, ctx->rec_out + (size_t)shot * stride, n * sizeof(double), hipMemcpyDeviceToHost,
                        ctx->stream));
     HCK(hipStreamSynchronize(ctx->stream));
     return HHO_OK;
@@ -1140,6 +1405,12 @@ hho_status hho_inspect_arrays(const hho_inspect *p, double *tables, int32_t *gro
     if (c0) std::copy(P.c0.begin(), P.c0.end(), c0);
     if (mat) std::copy(P.mat.begin(), P.mat.end(), mat);
     if (ic_of_cell) std::copy(P.ic_of_cell.begin(), P.ic_of_cell.end(), ic_of_cell);
+    return HHO_OK;
+}
+
+hho_status hho_inspect_grad_coefs(const hho_inspect *p, double *gm) {
+    if (!p || !gm) return HHO_ERR_ARG;
+    std::copy(p->plan.gm.begin(), p->plan.gm.end(), gm);
     return HHO_OK;
 }
 

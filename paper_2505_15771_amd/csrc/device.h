@@ -74,6 +74,18 @@ struct StageArgs {
     const void *arena;
     unsigned arena_bytes;
     unsigned o_yin, o_yout, o_u, o_acc, o_tin, o_tout, o_link, o_c0, o_mat;
+    // forward recompute for the adjoint: the stage input Y_i, its derivative k_i ([rows][LT])
+    // and its face values ([trace rows][LT], own faces) are stored when non-null
+    R *ystore, *kstore, *fstore;
+    // adjoint stage (adjoint.hip): Yin = z_i = D M^{-1} mu_i, Yout = z_{i-1}, U = lambda,
+    // acc = the running sum of L^T mu_j, stored forward data of the same stage (read)
+    const R *yfwd, *kfwd, *ffwd;
+    double *gacc;              // gradient accumulator [3][LT], float64
+    const double *gm;          // per-cell parameter derivative coefficients [8][n_ic], float64
+    R mu_b, mu_a, zs_b;        // dt b_{i-1}, dt a_{i,i-1}, dt b_s
+    int inject;                // step n whose misfit derivative enters lambda^n (-1 = none)
+    const double *dobs;        // observed data [S][nobs][nrec][2]
+    int nobs;
 };
 
 // Launchers (kernels.hip).  K = polynomial degree, R = double or float.
@@ -90,6 +102,24 @@ hipError_t launch_energy(const StageArgs<R> &a, const R *state, int n_blocks, hi
 // to out[clock->step * S + s] (an energy history), skipped past `cap` steps.
 hipError_t launch_energy_reduce(const double *part, int n_blocks, int S, double *out, const Clock *clock, int cap,
                                 hipStream_t st);
+
+// Forward stage with the recompute stores (ystore / kstore / fstore non-null).
+template <int K, typename R>
+hipError_t launch_stage_store(const StageArgs<R> &a, int n_blocks, hipStream_t st);
+
+// Adjoint stage (adjoint.hip): from z_i and its incoming traces, Ybar_i = L^T mu_i, the gradient
+// contributions mu_i^T (dL/dtheta) Y_i, and z_{i-1} (or lambda^n and the next z on the last stage).
+template <int K, typename R>
+hipError_t launch_adjoint_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st);
+
+// lambda += dt R^T (R U - d^n) at the receivers (U = a.yfwd, lambda = a.U, step a.inject), then
+// z = D M^{-1} (a.zs_b lambda) and its outgoing traces (z = a.Yout, traces = a.Tout).
+template <int K, typename R>
+hipError_t launch_adjoint_start(const StageArgs<R> &a, int n_blocks, hipStream_t st);
+
+// grad[c][q] = sum_shots gacc[q][ic_of_cell[c] * S + shot]  (adjoint.hip)
+hipError_t launch_grad_reduce(const double *gacc, long long LT, int S, const int32_t *ic_of_cell, int n_cells,
+                              double *out, hipStream_t st);
 
 // clock->step += 1 (one thread), after the last stage of a step.
 hipError_t launch_tick(Clock *clock, hipStream_t st);

@@ -28,256 +28,10 @@
 //      face links; the scattered accesses are stores.
 #include <hip/hip_runtime.h>
 
-#include "device.h"
-#include "plan.h"
-
-#define HHO_CONST __attribute__((address_space(4)))
+#include "stage_common.h"
 
 namespace hho {
-
 namespace {
-
-template <int K>
-struct Dim {
-    static constexpr int N = (K + 1) * (K + 2) / 2;
-    static constexpr int F = K + 1;
-};
-
-// Read-only data with wavefront-uniform addresses: the constant address space lets the
-// compiler use scalar loads.
-template <typename T>
-__device__ __forceinline__ const HHO_CONST T *uni(const T *p) {
-    return (const HHO_CONST T *)p;
-}
-
-// Per-lane arrays are addressed through buffer resources: the uniform row offset goes in a
-// scalar register, the lane's byte offset in a vector register, and the hardware range check
-// against the array size turns a stray access into a zero load or a dropped store.
-typedef __amdgpu_buffer_rsrc_t Rsrc;
-constexpr int kRsrcWord3 = 0x00020000;  // 32-bit data format, raw (untyped) access
-
-template <typename T>
-__device__ __forceinline__ Rsrc rsrc(const T *p, unsigned bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc((void *)p, 0, (int)bytes, kRsrcWord3);
-}
-
-template <typename T>
-__device__ __forceinline__ T bld(Rsrc r, unsigned voff, unsigned soff);
-template <>
-__device__ __forceinline__ float bld<float>(Rsrc r, unsigned voff, unsigned soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-}
-template <>
-__device__ __forceinline__ int bld<int>(Rsrc r, unsigned voff, unsigned soff) {
-    return __builtin_bit_cast(int, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-}
-template <>
-__device__ __forceinline__ double bld<double>(Rsrc r, unsigned voff, unsigned soff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-}
-__device__ __forceinline__ void bst(Rsrc r, unsigned voff, unsigned soff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
-}
-__device__ __forceinline__ void bst(Rsrc r, unsigned voff, unsigned soff, double v) {
-    typedef unsigned u2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, 0);
-}
-
-// Buffer addressing of one stage launch (uniform): one resource over the arena, and the
-// byte offset of each array in it.
-template <typename R>
-struct Bufs {
-    Rsrc r;
-    unsigned yin, yout, u, acc, tin, tout, link, c0, mat;
-    unsigned rowb;   // bytes of one [lane] row: LT * sizeof(R)
-    unsigned crowb;  // bytes of one [cell] row of reals: n_ic * sizeof(R)
-    unsigned irowb;  // bytes of one [cell] row of int32: n_ic * 4
-};
-
-template <typename R>
-__device__ __forceinline__ Bufs<R> make_bufs(const StageArgs<R> &a) {
-    Bufs<R> b;
-    b.r = rsrc(a.arena, a.arena_bytes);
-    b.yin = a.o_yin;
-    b.yout = a.o_yout;
-    b.u = a.o_u;
-    b.acc = a.o_acc;
-    b.tin = a.o_tin;
-    b.tout = a.o_tout;
-    b.link = a.o_link;
-    b.c0 = a.o_c0;
-    b.mat = a.o_mat;
-    b.rowb = (unsigned)a.LT * (unsigned)sizeof(R);
-    b.crowb = (unsigned)a.n_ic * (unsigned)sizeof(R);
-    b.irowb = (unsigned)a.n_ic * 4u;
-    return b;
-}
-
-template <typename R>
-__device__ __forceinline__ double stage_time(const StageArgs<R> &a) {
-    const HHO_CONST Clock *c = uni(a.clock);
-    return c->t0 + ((double)c->step + a.c) * c->dt;
-}
-
-template <typename R>
-__device__ __forceinline__ R sgn(int i) {
-    return (i & 1) ? R(-1) : R(1);
-}
-
-__device__ __forceinline__ double ricker(double t, double f0, double t0) {
-    const double a = 3.14159265358979323846 * f0 * (t - t0);
-    return (1.0 - 2.0 * a * a) * exp(-a * a);
-}
-
-constexpr double kRsqrt2 = 0.70710678118654752440;
-
-struct LaneInfo {
-    int ic, shot;
-    unsigned boff;   // byte offset of this lane in a [row][lane] array of reals
-    unsigned coff;   // byte offset of this cell in a [row][cell] array of reals
-    bool active;
-};
-
-template <typename R>
-__device__ __forceinline__ LaneInfo decode_lane(const StageArgs<R> &a, GroupDev &G) {
-    const int g = uni(a.blk_group)[blockIdx.x];
-    const HHO_CONST GroupDev *gd = uni(a.groups) + g;
-    G.medium = gd->medium;
-    G.nF = gd->nF;
-    G.tab_off = gd->tab_off;
-    G.ic_begin = gd->ic_begin;
-    G.ncells = gd->ncells;
-    G.blk_begin = gd->blk_begin;
-    LaneInfo L;
-    const int tid = threadIdx.x;
-    const int cl = tid / a.S;
-    L.shot = tid - cl * a.S;
-    const int l = (blockIdx.x - G.blk_begin) * a.cpb + cl;
-    L.active = l < G.ncells;
-    L.ic = G.ic_begin + l;
-    L.boff = (unsigned)(L.ic * a.S + L.shot) * (unsigned)sizeof(R);
-    L.coff = (unsigned)L.ic * (unsigned)sizeof(R);
-    return L;
-}
-
-// Per-cell face data: links (rows j >= nF of this group are never read; their links count
-// as -1, like boundary faces) and face-solve coefficients.
-template <int NF, typename R>
-__device__ __forceinline__ void load_links(const Bufs<R> &B, int nF, int ic, int *lk, R *cc) {
-    const unsigned ioff = (unsigned)ic * 4u, roff = (unsigned)ic * (unsigned)sizeof(R);
-#pragma unroll
-    for (int j = 0; j < NF; ++j) {
-        lk[j] = -1;
-        if (cc) cc[j] = R(0);
-        if (j < nF) {
-            lk[j] = bld<int>(B.r, ioff, B.link + j * B.irowb);
-            if (cc) cc[j] = bld<R>(B.r, roff, B.c0 + j * B.crowb);
-        }
-    }
-}
-
-// Incoming neighbour contributions.  Rows of every face of the group are loaded without
-// waiting for the links (a boundary face's slot is never written and its value is unused);
-// only a fluid cell's second component, present across the interface, depends on the link.
-template <int K, int NF, typename R>
-__device__ __forceinline__ void load_incoming(const Bufs<R> &B, int medium, int nF, const int *lk, unsigned boff,
-                                              R (*rn)[2][Dim<K>::F]) {
-    constexpr int F = Dim<K>::F;
-#pragma unroll
-    for (int j = 0; j < NF; ++j) {
-#pragma unroll
-        for (int i = 0; i < F; ++i) rn[j][0][i] = rn[j][1][i] = R(0);
-        if (j >= nF) continue;
-#pragma unroll
-        for (int i = 0; i < F; ++i) rn[j][0][i] = bld<R>(B.r, boff, B.tin + ((j * 2) * F + i) * B.rowb);
-        if (medium == kSolid) {
-#pragma unroll
-            for (int i = 0; i < F; ++i) rn[j][1][i] = bld<R>(B.r, boff, B.tin + ((j * 2 + 1) * F + i) * B.rowb);
-        }
-    }
-    if (medium == kFluid) {
-#pragma unroll
-        for (int j = 0; j < NF; ++j) {
-            if (lk[j] < 0 || !((lk[j] >> 3) & 1)) continue;
-#pragma unroll
-            for (int i = 0; i < F; ++i) rn[j][1][i] = bld<R>(B.r, boff, B.tin + ((j * 2 + 1) * F + i) * B.rowb);
-        }
-    }
-}
-
-// ------------------------------------------------------------------------- outgoing traces
-template <int K, int NF, typename R>
-__device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
-                                             const int *lk, int shot, const R *p, const R *mx, const R *my, R tau) {
-    constexpr int N = Dim<K>::N, F = Dim<K>::F;
-    const HHO_CONST R *Gt = tb + 3 * N * N;
-    const HHO_CONST R *nr = Gt + nF * N * F;
-    R tp[N];
-#pragma unroll
-    for (int b = 0; b < N; ++b) tp[b] = tau * p[b];
-#pragma unroll
-    for (int j = 0; j < NF; ++j) {
-        if (lk[j] < 0) continue;
-        const R nx = nr[2 * j], ny = nr[2 * j + 1];
-        R r[F];
-#pragma unroll
-        for (int i = 0; i < F; ++i) r[i] = R(0);
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-            const R q = tp[b] - nx * mx[b] - ny * my[b];
-#pragma unroll
-            for (int i = 0; i < F; ++i) r[i] += Gt[(j * N + b) * F + i] * q;
-        }
-        const int icn = lk[j] >> 4, jn = lk[j] & 7;
-        const unsigned nb = (unsigned)(icn * a.S + shot) * (unsigned)sizeof(R);
-#pragma unroll
-        for (int i = 0; i < F; ++i) bst(B.r, nb, B.tout + ((jn * 2) * F + i) * B.rowb, sgn<R>(i) * r[i]);
-    }
-}
-
-template <int K, int NF, typename R>
-__device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
-                                             const int *lk, int shot, const R *vx, const R *vy, const R *s1, const R *s2,
-                                             const R *s3, R tau, R itau) {
-    constexpr int N = Dim<K>::N, F = Dim<K>::F;
-    const R r2 = R(kRsqrt2);
-    const HHO_CONST R *Gt = tb + 3 * N * N;
-    const HHO_CONST R *nr = Gt + nF * N * F;
-    R tvx[N], tvy[N], hs3[N];
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-        tvx[b] = tau * vx[b];
-        tvy[b] = tau * vy[b];
-        hs3[b] = r2 * s3[b];
-    }
-#pragma unroll
-    for (int j = 0; j < NF; ++j) {
-        if (lk[j] < 0) continue;
-        const R nx = nr[2 * j], ny = nr[2 * j + 1];
-        R rx[F], ry[F];
-#pragma unroll
-        for (int i = 0; i < F; ++i) rx[i] = ry[i] = R(0);
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-            const R qx = tvx[b] - nx * s1[b] - ny * hs3[b];
-            const R qy = tvy[b] - nx * hs3[b] - ny * s2[b];
-#pragma unroll
-            for (int i = 0; i < F; ++i) {
-                rx[i] += Gt[(j * N + b) * F + i] * qx;
-                ry[i] += Gt[(j * N + b) * F + i] * qy;
-            }
-        }
-        const int icn = lk[j] >> 4, jn = lk[j] & 7;
-        const unsigned nb = (unsigned)(icn * a.S + shot) * (unsigned)sizeof(R);
-        // across the interface the fluid side needs r_s / tau_s
-        const R w = ((lk[j] >> 3) & 1) ? itau : R(1);
-#pragma unroll
-        for (int i = 0; i < F; ++i) {
-            bst(B.r, nb, B.tout + ((jn * 2) * F + i) * B.rowb, sgn<R>(i) * w * rx[i]);
-            bst(B.r, nb, B.tout + ((jn * 2 + 1) * F + i) * B.rowb, sgn<R>(i) * w * ry[i]);
-        }
-    }
-}
 
 // Runge-Kutta combine of all ND rows of a lane (eq. ERK): out = new stage state, stored to
 // Y_{i+1} (and the accumulator) or to U^{n+1} on the last stage.  Every load is issued before
@@ -317,8 +71,30 @@ __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &
     }
 }
 
+// Recompute stores of one lane for the adjoint: stage input, stage derivative, face values
+// (after the combine, so these stores do not hold back the combine's loads).
+// NC = primal components (1: p, 2: v); only the primal rows of Y and of the face values are kept.
+template <int K, int NF, int ND, typename R, int NFV, int NC>
+__device__ __forceinline__ void store_recompute(const StageArgs<R> &a, const int *lk, unsigned boff, const R *y,
+                                                const R *kv, const R (*fv)[2][Dim<K>::F]) {
+    constexpr int F = Dim<K>::F, N = Dim<K>::N;
+    const long long lane = boff / sizeof(R);
+#pragma unroll
+    for (int r = 0; r < NC * N; ++r) a.ystore[(long long)r * a.LT + lane] = y[r];
+#pragma unroll
+    for (int r = 0; r < ND; ++r) a.kstore[(long long)r * a.LT + lane] = kv[r];
+#pragma unroll
+    for (int j = 0; j < NFV; ++j) {
+        if (lk[j] < 0) continue;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int i = 0; i < F; ++i) a.fstore[(long long)((j * 2 + c) * F + i) * a.LT + lane] = fv[j][c][i];
+    }
+}
+
 // ------------------------------------------------------------------------- fluid cells
-template <int K, int NF, typename R>
+template <int K, int NF, typename R, bool STORE>
 __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
                                             const LaneInfo &L, double *energy) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
@@ -331,6 +107,7 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
     const HHO_CONST R *nr = Gt + nF * N * F;
     int lk[NF];
     R cc[NF], rn[NF][2][F];
+    R fv[STORE ? NF : 1][2][F];  // face values, kept for the recompute stores
     load_links<NF, R>(B, nF, ic, lk, cc);
     R p[N], mx[N], my[N];
 #pragma unroll
@@ -382,6 +159,10 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
 #pragma unroll
             for (int i = 0; i < F; ++i) pF[i] = (r[i] + nx * rn[j][0][i] + ny * rn[j][1][i]) * cc[j];
         }
+        if (STORE) {
+#pragma unroll
+            for (int i = 0; i < F; ++i) fv[j][0][i] = pF[i];
+        }
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             R w = 0;
@@ -427,6 +208,7 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
     }
     rk_update<3 * N, R>(a, B, boff, y, kv, nw);
     const R *np = nw, *nmx = nw + N, *nmy = nw + 2 * N;
+    if (STORE) store_recompute<K, NF, 3 * N, R, NF, 1>(a, lk, boff, y, kv, fv);
     fluid_traces<K, NF, R>(a, B, tb, nF, lk, shot, np, nmx, nmy, tau);
     if (a.last) {
         if (energy) {
@@ -457,7 +239,7 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
 }
 
 // ------------------------------------------------------------------------- solid cells
-template <int K, int NF, typename R>
+template <int K, int NF, typename R, bool STORE>
 __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
                                             const LaneInfo &L, double *energy) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
@@ -471,6 +253,7 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
     const HHO_CONST R *nr = Gt + nF * N * F;
     int lk[NF];
     R cc[NF], rn[NF][2][F];
+    R fv[STORE ? NF : 1][2][F];  // face values, kept for the recompute stores
     load_links<NF, R>(B, nF, ic, lk, cc);
     R vx[N], vy[N], s1[N], s2[N], s3[N];
 #pragma unroll
@@ -547,6 +330,13 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
                 vFy[i] = (ry[i] + ny * pF) * itau;
             }
         }
+        if (STORE) {
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                fv[j][0][i] = vFx[i];
+                fv[j][1][i] = vFy[i];
+            }
+        }
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             R wx = 0, wy = 0;
@@ -605,6 +395,7 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
     }
     rk_update<5 * N, R>(a, B, boff, y, kv, nw);
     const R *nvx = nw, *nvy = nw + N, *ns1 = nw + 2 * N, *ns2 = nw + 3 * N, *ns3 = nw + 4 * N;
+    if (STORE) store_recompute<K, NF, 5 * N, R, NF, 2>(a, lk, boff, y, kv, fv);
     solid_traces<K, NF, R>(a, B, tb, nF, lk, shot, nvx, nvy, ns1, ns2, ns3, tau, itau);
     if (a.last) {
         if (energy) {
@@ -640,29 +431,17 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
     }
 }
 
-// Block reduction of per-lane energies into one partial per shot.
-__device__ void block_energy(double e, int S, int cpb, double *out) {
-    __shared__ double buf[kBlock];
-    buf[threadIdx.x] = e;
-    __syncthreads();
-    if ((int)threadIdx.x < S) {
-        double s = 0;
-        for (int m = 0; m < cpb; ++m) s += buf[threadIdx.x + m * S];
-        out[(long long)blockIdx.x * S + threadIdx.x] = s;
-    }
-}
-
-template <int K, int NF, typename R>
+template <int K, int NF, typename R, bool STORE>
 __device__ __forceinline__ void stage_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L, double *e) {
     const HHO_CONST R *tb = uni(a.tab) + G.tab_off;
     const Bufs<R> B = make_bufs(a);
     if (G.medium == kFluid)
-        fluid_stage<K, NF, R>(a, B, tb, G.nF, L, e);
+        fluid_stage<K, NF, R, STORE>(a, B, tb, G.nF, L, e);
     else
-        solid_stage<K, NF, R>(a, B, tb, G.nF, L, e);
+        solid_stage<K, NF, R, STORE>(a, B, tb, G.nF, L, e);
 }
 
-template <int K, typename R>
+template <int K, typename R, bool STORE>
 __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<R> a) {
     GroupDev G;
     const LaneInfo L = decode_lane(a, G);
@@ -671,8 +450,8 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<R> a) {
     double *ep = want_e ? &e : nullptr;
     if (L.active) {
         // faces beyond a cell's count carry link -1 and are skipped like boundary faces
-        if (G.nF <= 4) stage_body<K, 4, R>(a, G, L, ep);
-        else stage_body<K, kMaxFaces, R>(a, G, L, ep);
+        if (G.nF <= 4) stage_body<K, 4, R, STORE>(a, G, L, ep);
+        else stage_body<K, kMaxFaces, R, STORE>(a, G, L, ep);
     }
     if (want_e) block_energy(e, a.S, a.cpb, a.e_part);
 }
@@ -785,7 +564,13 @@ __global__ void gather_kernel(const R *state, const int64_t *map, long long n, i
 
 template <int K, typename R>
 hipError_t launch_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
-    hipLaunchKernelGGL((stage_kernel<K, R>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    hipLaunchKernelGGL((stage_kernel<K, R, false>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int K, typename R>
+hipError_t launch_stage_store(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
+    hipLaunchKernelGGL((stage_kernel<K, R, true>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     return hipGetLastError();
 }
 
@@ -832,6 +617,7 @@ hipError_t launch_gather(const R *state, const int64_t *map, long long n, int sh
 
 #define HHO_INST(K, R)                                                                              \
     template hipError_t launch_stage<K, R>(const StageArgs<R> &, int, hipStream_t);                \
+    template hipError_t launch_stage_store<K, R>(const StageArgs<R> &, int, hipStream_t);          \
     template hipError_t launch_traces<K, R>(const StageArgs<R> &, int, hipStream_t);               \
     template hipError_t launch_energy<K, R>(const StageArgs<R> &, const R *, int, hipStream_t);
 HHO_INST(1, double)

@@ -458,6 +458,7 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
     P.c0.assign((size_t)P.max_nf * nic, 0.0);
     P.mat.assign((size_t)kNumMat * nic, 0.0);
     P.emat.assign((size_t)kNumEnergyMat * nic, 0.0);
+    P.gm.assign((size_t)kNumGradCoef * nic, 0.0);
     for (int c = 0; c < nc; ++c) {
         const int i = P.ic_of_cell[c], s = cell_ptr[c], n = cell_ptr[c + 1] - s;
         for (int j = 0; j < n; ++j) {
@@ -479,18 +480,33 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
         m(kTau) = tau[c];
         m(kInvTau) = 1.0 / tau[c];
         em(0) = rho[c];
+        auto gd = [&](int slot) -> double & { return P.gm[(size_t)slot * nic + i]; };
+        const double t = tau[c];
         if (medium[c] == kFluid) {
             const double kap = rho[c] * pa[c] * pa[c];
             m(kStiff) = kap;
             em(1) = 1.0 / kap;
+            // kappa = rho c^2, tau = eta / (rho c)
+            gd(0) = -1.0 / (rho[c] * kap);
+            gd(1) = -2.0 / (pa[c] * kap);
+            gd(2) = -t / rho[c];
+            gd(3) = -t / pa[c];
         } else {
-            const double lam = pa[c], mu = pb[c];
-            m(kStiff) = lam + 2.0 * mu;
+            const double lam = pa[c], mu = pb[c], lpm = lam + mu, l2m = lam + 2.0 * mu;
+            m(kStiff) = l2m;
             m(kLam) = lam;
             m(kTwoMu) = 2.0 * mu;
-            em(1) = (lam + 2.0 * mu) / (4.0 * mu * (lam + mu));
-            em(2) = -lam / (4.0 * mu * (lam + mu));
+            em(1) = l2m / (4.0 * mu * lpm);
+            em(2) = -lam / (4.0 * mu * lpm);
             em(3) = 1.0 / (2.0 * mu);
+            // tau = eta rho c_P = eta sqrt(rho (lam + 2 mu))  or  eta rho c_S = eta sqrt(rho mu)
+            gd(0) = t / (2.0 * rho[c]);
+            gd(1) = stab_speed == 0 ? t / (2.0 * l2m) : 0.0;
+            gd(2) = stab_speed == 0 ? t / l2m : t / (2.0 * mu);
+            gd(3) = -1.0 / (4.0 * lpm * lpm);
+            gd(4) = -(lam * lam + 2.0 * lam * mu + 2.0 * mu * mu) / (4.0 * mu * mu * lpm * lpm);
+            gd(5) = lam * l2m / (4.0 * mu * mu * lpm * lpm);
+            gd(6) = -1.0 / (2.0 * mu * mu);
         }
     }
     P.ext_off.assign(nc + 1, 0);

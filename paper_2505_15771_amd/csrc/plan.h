@@ -50,6 +50,7 @@ enum MatSlot : int {
 // Energy weights per internal cell (float64): fluid (rho, 1/kappa, 0, 0),
 // solid (rho, a, b, c) with the compliance in the E basis [[a, b, 0], [b, a, 0], [0, 0, c]].
 constexpr int kNumEnergyMat = 4;
+constexpr int kNumGradCoef = 8;
 
 struct Plan {
     int k = 1, N = 3, F = 2, S = 1;
@@ -79,6 +80,11 @@ struct Plan {
     std::vector<double> c0;     // [max_nf][n_ic] face-solve coefficient
     std::vector<double> mat;    // [kNumMat][n_ic]
     std::vector<double> emat;   // [kNumEnergyMat][n_ic]
+    // Material derivatives for the adjoint gradient, [kNumGradCoef][n_ic] (float64):
+    //   fluid (rho, c):        d(1/kappa)/drho, d(1/kappa)/dc, dtau/drho, dtau/dc
+    //   solid (rho, lam, mu):  dtau/drho, dtau/dlam, dtau/dmu, dA/dlam (= dB/dlam), dA/dmu, dB/dmu, dC/dmu
+    // with tau the stabilisation weight and [[A, B, 0], [B, A, 0], [0, 0, C]] the compliance.
+    std::vector<double> gm;
     // geometry needed for point location / evaluation
     std::vector<double> xy;
     std::vector<int32_t> cell_ptr, cell_vtx;

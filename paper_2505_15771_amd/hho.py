@@ -59,6 +59,8 @@ EXPORTS = {
     "hho_autotune": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "hho_set_launch": (C.c_int, [C.c_void_p, C.c_int32]),
     "hho_dt_cfl": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double)]),
+    "hho_adjoint_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_void_p,
+                                   C.POINTER(C.c_double), C.c_void_p]),
     "hho_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
     "hho_batch_destroy": (None, [C.c_void_p]),
     "hho_batch_last_error": (C.c_char_p, [C.c_void_p]),
@@ -67,6 +69,7 @@ EXPORTS = {
     "hho_inspect_destroy": (None, [C.c_void_p]),
     "hho_inspect_sizes": (C.c_int, [C.c_void_p, C.c_void_p]),
     "hho_inspect_arrays": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
+    "hho_inspect_grad_coefs": (C.c_int, [C.c_void_p, C.c_void_p]),
 }
 
 _lib = None
@@ -232,6 +235,24 @@ class Engine:
         self._call(self.lib.hho_erk_step, float(t0), float(dt), int(n_steps))
         self.last_steps = int(n_steps)
 
+    def adjoint(self, t0, dt, n_steps, d_obs=None, ckpt_every=0):
+        """Misfit J and dJ/d(materials) [n_cells, 3] by the discrete adjoint (hho_adjoint_step).
+
+        d_obs: [n_shots, n_steps, n_rec, 2] (or [n_steps, n_rec, 2] for one shot).  Leaves the
+        state at U^{n_steps} and the forward traces readable, like erk_step."""
+        if self.n_rec:
+            d = np.ascontiguousarray(np.asarray(d_obs, np.float64))
+            if d.size != self.n_shots * n_steps * self.n_rec * 2:
+                raise ValueError("d_obs must hold n_shots * n_steps * n_rec * 2 values")
+        else:
+            d = None
+        J = C.c_double()
+        grad = np.zeros((self.n_cells, 3))
+        self._call(self.lib.hho_adjoint_step, float(t0), float(dt), int(n_steps), int(ckpt_every), _ptr(d),
+                   C.byref(J), _ptr(grad))
+        self.last_steps = int(n_steps)
+        return J.value, grad
+
     def synchronize(self):
         self._call(self.lib.hho_synchronize)
 
@@ -291,6 +312,8 @@ class Inspect:
         self.ic_of_cell = np.zeros(self.n_cells, np.int32)
         lib.hho_inspect_arrays(h, _ptr(self.tables), _ptr(self.groups), _ptr(self.link), _ptr(self.c0),
                                _ptr(self.mat), _ptr(self.ic_of_cell))
+        self.gm = np.zeros((8, self.n_ic))
+        lib.hho_inspect_grad_coefs(h, _ptr(self.gm))
         lib.hho_inspect_destroy(h)
         self._h = None
 

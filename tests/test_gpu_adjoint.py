@@ -1,0 +1,183 @@
+"""GPU parity of the discrete adjoint (hho_adjoint_step through the C ABI) against the oracle's
+plain reverse sweep (oracle.adjoint.misfit_gradient): misfit J and its gradient with respect
+to the per-cell materials (fluid rho, c; solid rho, lambda, mu).
+
+Tolerances: float64 relative 1e-11 on J and relative L2 1e-11 on the gradient (the gradient is a
+sum over every stage of every step of products whose terms partly cancel, so it carries up to a
+few hundred times the rounding of the state; measured <= 3e-13); float32 relative 2e-5 on J and
+5e-5 on the gradient (stage data stored and combined in float32, products accumulated in float64;
+measured 3e-6 and 7e-6 on the k = 2 case).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from synth import meshes as M
+
+pytestmark = pytest.mark.gpu
+
+SRC = [[0.45, 0.3]]
+REC_XY = np.array([[0.3, 0.8], [0.7, 0.65], [0.25, 0.2], [0.8, 0.35]])
+REC_F = np.array([0, 0, 1, 1], np.int32)
+F0, T0 = 20.0, 0.02  # Ricker source: peak frequency and delay
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def small_mesh(seed=5):
+    refine = np.random.default_rng(seed).random((6, 6)) < 0.25
+    return M.with_materials(M.unit_square(6, p_split=0.5, seed=seed, refine=refine), perturb=0.1, seed=seed + 1)
+
+
+def time_step(mesh, k, s=4):
+    """Half the CFL-limited step of the paper's CFL* table (a stable run)."""
+    from paper_2505_15771_amd import Engine
+    return Engine(mesh, k, rk_stages=s).dt_cfl(0.5)
+
+
+def initial_state(mesh, k, seed=3):
+    from oracle import Oracle
+    return 0.05 * np.random.default_rng(seed).standard_normal(Oracle(mesh, k).ndof)
+
+
+def observed(mesh, k, nsteps, dt, src, amp, U0, s=4, seed=77):
+    """Receiver data of a +-5 % perturbed model from the same initial state, computed by the oracle."""
+    from oracle import Oracle
+    from oracle.adjoint import Receivers, forward
+    true = dict(mesh)
+    rng = np.random.default_rng(seed)
+    for key in ("rho", "a", "b"):
+        true[key] = np.asarray(mesh[key]) * (1 + rng.uniform(-0.05, 0.05, len(mesh["rho"])))
+    ot = Oracle(true, k)
+    ot.set_point_sources(src, [[0.0, 1.0]] * len(src), F0, T0, amp)
+    Us, _ = forward(ot, U0, 0.0, dt, nsteps, s)
+    rt = Receivers(ot, REC_XY, REC_F)
+    return np.array([rt.apply(Us[n]) for n in range(1, nsteps + 1)])
+
+
+def oracle_gradient(mesh, k, nsteps, dt, src, amp, d_obs, U0, s=4):
+    from oracle import Oracle
+    from oracle.adjoint import Receivers, misfit_gradient
+    o = Oracle(mesh, k)
+    o.set_point_sources(src, [[0.0, 1.0]] * len(src), F0, T0, amp)
+    J, g = misfit_gradient(o, U0, 0.0, dt, nsteps, Receivers(o, REC_XY, REC_F), d_obs, s)
+    U = o.erk(U0, 0.0, dt, nsteps, s=s)
+    return J, g, U
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_adjoint_gradient_rk4(k):
+    """RK4, 25 steps, default checkpoint spacing (5), source in the solid, receivers in both
+    media, on a hybrid mesh with hanging nodes and the interface."""
+    say("case: adjoint k=%d rk4 25 steps fp64" % k)
+    from paper_2505_15771_amd import Engine
+    nsteps = 25
+    mesh = small_mesh()
+    dt = time_step(mesh, k)
+    U0 = initial_state(mesh, k)
+    d = observed(mesh, k, nsteps, dt, SRC, 1.0, U0)
+    J0, g0, UN = oracle_gradient(mesh, k, nsteps, dt, SRC, 1.0, d, U0)
+    e = Engine(mesh, k)
+    e.set_sources(0, SRC, [[0.0, 1.0]], F0, T0, 1.0)
+    e.set_receivers(REC_XY, REC_F)
+    e.set_state(U0)
+    J, g = e.adjoint(0.0, dt, nsteps, d)
+    say("J", J, J0, "rel", abs(J - J0) / J0, "grad rel L2", rel(g, g0), "state", rel(e.get_state(), UN))
+    assert abs(J - J0) < 1e-11 * J0
+    assert rel(g, g0) < 1e-11
+    assert rel(e.get_state(), UN) < 1e-12
+    assert np.all(g[np.asarray(mesh["medium"]) == 0, 2] == 0.0)
+
+
+def test_adjoint_rk2_ragged_segments_and_repeat():
+    """ERK(2), 25 steps in checkpoint segments of 7 (7, 7, 7, 4), a non-zero initial state; the
+    same call twice gives the same result (workspace reuse), and the forward traces stay readable."""
+    say("case: adjoint k=2 rk2 ckpt 7 fp64")
+    from paper_2505_15771_amd import Engine
+    k, nsteps = 2, 25
+    mesh = small_mesh()
+    dt = time_step(mesh, k, 2)
+    U0 = initial_state(mesh, k, seed=4)
+    d = observed(mesh, k, nsteps, dt, SRC, 1.0, U0, s=2)
+    J0, g0, UN = oracle_gradient(mesh, k, nsteps, dt, SRC, 1.0, d, U0, s=2)
+    e = Engine(mesh, k, rk_stages=2)
+    e.set_sources(0, SRC, [[0.0, 1.0]], F0, T0, 1.0)
+    e.set_receivers(REC_XY, REC_F)
+    for rep in range(2):
+        e.set_state(U0)
+        J, g = e.adjoint(0.0, dt, nsteps, d, ckpt_every=7)
+        say("rep", rep, "J rel", abs(J - J0) / J0, "grad rel L2", rel(g, g0))
+        assert abs(J - J0) < 1e-11 * J0
+        assert rel(g, g0) < 1e-11
+        assert rel(e.get_state(), UN) < 1e-12
+    # J from the returned traces
+    tr = e.traces(0)
+    assert abs(0.5 * dt * np.sum((tr - d) ** 2) - J) < 1e-12 * J
+
+
+def test_adjoint_multishot():
+    """Three shots with their own sources and data: J and the gradient are sums over shots."""
+    say("case: adjoint 3 shots k=2 fp64")
+    from paper_2505_15771_amd import Engine
+    k, nsteps = 2, 20
+    mesh = small_mesh()
+    shots = [([[0.45, 0.3]], 1.0), ([[0.2, 0.75]], 0.7), ([[0.7, 0.2], [0.35, 0.4]], 1.3)]
+    dt = time_step(mesh, k)
+    e = Engine(mesh, k, n_shots=3)
+    e.set_receivers(REC_XY, REC_F)
+    J0, g0, ds = 0.0, 0.0, []
+    for sh, (src, amp) in enumerate(shots):
+        U0 = initial_state(mesh, k, seed=20 + sh)
+        d = observed(mesh, k, nsteps, dt, src, amp, U0, seed=80 + sh)
+        ds.append(d)
+        Jr, gr, _ = oracle_gradient(mesh, k, nsteps, dt, src, amp, d, U0)
+        J0, g0 = J0 + Jr, g0 + gr
+        e.set_sources(sh, src, [[0.0, 1.0]] * len(src), F0, T0, amp)
+        e.set_state(U0, shot=sh)
+    J, g = e.adjoint(0.0, dt, nsteps, np.stack(ds), ckpt_every=6)
+    say("J rel", abs(J - J0) / J0, "grad rel L2", rel(g, g0))
+    assert abs(J - J0) < 1e-11 * J0
+    assert rel(g, g0) < 1e-11
+
+
+def test_adjoint_float32():
+    say("case: adjoint k=2 rk4 fp32")
+    from paper_2505_15771_amd import Engine
+    k, nsteps = 2, 25
+    mesh = small_mesh()
+    dt = time_step(mesh, k)
+    U0 = initial_state(mesh, k)
+    d = observed(mesh, k, nsteps, dt, SRC, 1.0, U0)
+    J0, g0, _ = oracle_gradient(mesh, k, nsteps, dt, SRC, 1.0, d, U0)
+    e = Engine(mesh, k, dtype="f32")
+    e.set_sources(0, SRC, [[0.0, 1.0]], F0, T0, 1.0)
+    e.set_receivers(REC_XY, REC_F)
+    e.set_state(U0)
+    J, g = e.adjoint(0.0, dt, nsteps, d)
+    say("J rel", abs(J - J0) / J0, "grad rel L2", rel(g, g0))
+    assert abs(J - J0) < 2e-5 * J0
+    assert rel(g, g0) < 5e-5
+
+
+def test_adjoint_argument_errors_and_no_receivers():
+    from paper_2505_15771_amd import Engine, HHOError
+    mesh = small_mesh()
+    dt = time_step(mesh, 1)
+    e3 = Engine(mesh, 1, rk_stages=3)
+    with pytest.raises(HHOError) as ex:
+        e3.adjoint(0.0, dt, 4)
+    assert ex.value.code == 1
+    e = Engine(mesh, 1)
+    with pytest.raises(HHOError):
+        e.adjoint(0.0, dt, 0)
+    J, g = e.adjoint(0.0, dt, 3)  # no receivers: J = 0, gradient 0
+    assert J == 0.0 and not np.any(g)

@@ -109,3 +109,24 @@ def test_plan_adjoint_operator(k):
     got = kernel_model.rhs(ins, mesh, x, adjoint=True)
     ref = o.rhs_T(x)
     assert np.linalg.norm(got - ref) < 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("stab_speed", [0, 1])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_plan_gradient_terms(k, stab_speed):
+    """The per-stage parameter derivatives in the form the adjoint stage kernel computes them
+    (stored forward face values, adjoint face values of z, the plan's material-derivative
+    coefficients) equal the oracle's gradient terms, on a mesh with hanging nodes and the
+    fluid-solid interface, for both stabilisation speeds."""
+    from oracle import Oracle
+    from paper_2505_15771_amd import Inspect
+    import kernel_model
+    mesh = M.hanging_square(6, seed=5)
+    ins = Inspect(mesh, k, stab_speed=stab_speed)
+    o = Oracle(mesh, k, stab_speed=stab_speed)
+    rng = np.random.default_rng(10 + k)
+    Y, kk, mu = (rng.standard_normal(o.ndof) for _ in range(3))
+    ref = np.zeros((o.nc, 3))
+    o.grad_terms(Y, kk, mu, ref)
+    got = kernel_model.grad_terms(ins, mesh, Y, kk, mu)
+    assert np.linalg.norm(got - ref) < 1e-12 * np.linalg.norm(ref)
