@@ -85,7 +85,7 @@ struct hho_ctx {
     // energy
     double *e_part = nullptr, *e_hist = nullptr, *e_now = nullptr;
     size_t e_hist_cap = 0;
-    // device clock and the cached graph of kGraphSteps steps
+    // device clocks (two, alternating by step parity) and the cached graph of kGraphSteps steps
     Clock *clock = nullptr;
     Clock h_clock{};
     hipStream_t cap_stream = nullptr;
@@ -179,8 +179,13 @@ hho_status set_device(hho_ctx *ctx) {
 
 // Coefficients of the stage recurrence Y_{i+1} = cU U + cY Y_i + ck dt k_i for the
 // explicit tableaux of eq. ERK: row i+1 of A must be lam * (row i of A) on j < i.
+//
+// The stage buffers hold increments D_i = Y_{i+1} - U; U^{n+1} is formed without an accumulator:
+// stage 1 (for s >= 3) stores Q = qa D_0 + qb D_1, and the last stage adds Q + cd D_{s-2} + b_s dt k_s.
 struct StageCoef {
     double cU, cY, ck, cb, c;
+    double qa, qb, cd;
+    int q_write, q_read;
 };
 
 bool erk_coefficients(int s, std::vector<StageCoef> &out) {
@@ -201,7 +206,7 @@ bool erk_coefficients(int s, std::vector<StageCoef> &out) {
     } else {
         return false;
     }
-    out.assign(s, StageCoef{0, 0, 0, 0, 0});
+    out.assign(s, StageCoef{0, 0, 0, 0, 0, 0, 0, 0, 0, 0});
     for (int i = 0; i < s; ++i) {
         StageCoef &q = out[i];
         q.cb = b[i];
@@ -222,6 +227,26 @@ bool erk_coefficients(int s, std::vector<StageCoef> &out) {
         q.cU = 1.0 - lam;
         q.cY = lam;
     }
+    // increments D_i = Y_{i+1} - U (stage i, 0-based) satisfy D_i = cY_i D_{i-1} + ck_i dt k_i, so
+    // dt k_i = (D_i - cY_i D_{i-1}) / ck_i and U^{n+1} = U + sum_m beta_m D_m + b_{s-1} dt k_{s-1}
+    double beta[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int m = 0; m + 1 < s; ++m) {
+        if (out[m].ck == 0.0) return false;
+        beta[m] += out[m].cb / out[m].ck;
+        if (m + 2 < s) beta[m] -= out[m + 1].cb * out[m + 1].cY / out[m + 1].ck;
+    }
+    StageCoef &L = out[s - 1];
+    if (s >= 3) {
+        // stage 1 folds D_0 and D_1 into Q; for s = 3 D_1 is also the last stage's input
+        out[1].q_write = 1;
+        out[1].qa = beta[0];
+        out[1].qb = beta[1];
+        L.q_read = 1;
+        L.cd = s == 4 ? beta[2] : 0.0;
+    } else {
+        L.cd = beta[0];
+    }
+    if (s > 4) return false;
     return true;
 }
 
@@ -238,6 +263,7 @@ void set_stage_offsets(hho_ctx *, StageArgs<R> &a) {
     a.o_acc = arena_off(a.arena, a.acc);
     a.o_tin = arena_off(a.arena, a.Tin);
     a.o_tout = arena_off(a.arena, a.Tout);
+    a.o_yq = arena_off(a.arena, a.Yq);
 }
 
 template <typename R>
@@ -287,14 +313,15 @@ hho_status energy_now(hho_ctx *ctx, double *out_dev) {
 }
 
 // Enqueue n_steps steps on stream st.  Every launch argument is the same for every step (the
-// stage time and step index come from the device clock, advanced by a tick after each step),
+// stage time and step index come from the device clock, advanced by the last stage of each step),
 // so the sequence can be captured once into a graph and replayed.
 //
 // With `store` non-null (the adjoint's forward recompute), step n, stage i additionally writes the
 // primal rows of Y_i, k_i and the face values of Y_i to slot n * s + i of `store`
 // (AdjWork::slot_elems reals per slot); receivers and energy are not recorded then.
+// Step n reads clock slot (parity + n) % 2; the caller names the slot that holds the current clock.
 template <int K, typename R>
-hho_status enqueue_steps(hho_ctx *ctx, hipStream_t st, int n_steps, R *store = nullptr) {
+hho_status enqueue_steps(hho_ctx *ctx, hipStream_t st, int n_steps, R *store = nullptr, int parity = 0) {
     std::vector<StageCoef> co;
     if (!erk_coefficients(ctx->stages, co)) {
         ctx->err = "unsupported ERK stage count";
@@ -319,13 +346,21 @@ hho_status enqueue_steps(hho_ctx *ctx, hipStream_t st, int n_steps, R *store = n
     const int ecap = ctx->record_energy ? (int)(ctx->e_hist_cap / S) : 0;
     const int Tc = ctx->tcur, Ta = (Tc + 1) % 3, Tb = (Tc + 2) % 3;
     const int Tbuf[2] = {Ta, Tb};
+    // stage increments D_0 .. D_{s-2} in three buffers, kept until the last stage
+    void *stg[3] = {ctx->Y[0], ctx->Y[1], ctx->acc};
     for (int n = 0; n < n_steps; ++n) {
         for (int i = 0; i < s; ++i) {
             const StageCoef &q = co[i];
             a.first = i == 0;
             a.last = i == s - 1;
-            a.Yin = i == 0 ? (const R *)ctx->U : (const R *)ctx->Y[(i - 1) % 2];
-            a.Yout = a.last ? nullptr : (R *)ctx->Y[i % 2];
+            a.Yin = i == 0 ? (const R *)ctx->U : (const R *)stg[i - 1];
+            a.Yout = a.last ? nullptr : (R *)stg[i];
+            a.qa = (R)q.qa;
+            a.qb = (R)q.qb;
+            a.cd = (R)q.cd;
+            a.q_write = q.q_write;
+            a.q_read = q.q_read;
+            a.Yq = (q.q_write || q.q_read) ? (R *)stg[0] : nullptr;  // Q replaces D_0
             a.Tin = (const R *)ctx->T[i == 0 ? Tc : Tbuf[(i - 1) % 2]];
             a.Tout = (R *)ctx->T[a.last ? Tc : Tbuf[i % 2]];
             a.c = q.c;
@@ -335,6 +370,8 @@ hho_status enqueue_steps(hho_ctx *ctx, hipStream_t st, int n_steps, R *store = n
             a.cb = (R)q.cb;
             a.e_part = (a.last && ctx->record_energy && !store) ? ctx->e_part : nullptr;
             a.rec_first = (a.last && ctx->nrec > 0 && !store) ? ctx->rec_first : nullptr;
+            a.clock = ctx->clock + ((parity + n) & 1);
+            a.clock_next = ctx->clock + ((parity + n + 1) & 1);
             set_stage_offsets(ctx, a);
             if (store) {
                 const AdjWork &w = ctx->adj;
@@ -348,8 +385,8 @@ hho_status enqueue_steps(hho_ctx *ctx, hipStream_t st, int n_steps, R *store = n
             }
         }
         if (ctx->record_energy && !store)
-            HCK(launch_energy_reduce(ctx->e_part, ctx->n_blocks(), S, ctx->e_hist, ctx->clock, ecap, st));
-        HCK(launch_tick(ctx->clock, st));
+            HCK(launch_energy_reduce(ctx->e_part, ctx->n_blocks(), S, ctx->e_hist, ctx->clock + ((parity + n) & 1),
+                                     ecap, st));
     }
     return HHO_OK;
 }
@@ -370,6 +407,7 @@ hho_status dispatch(hho_ctx *ctx, Fn &&fn) {
 
 // Steps captured per graph: a call advances full graphs, then launches the remainder directly.
 constexpr int kGraphSteps = 32;
+static_assert(kGraphSteps % 2 == 0, "graph replays must start and end on the same clock slot");
 
 template <int K, typename R>
 hho_status autotune_shape(hho_ctx *ctx);
@@ -838,7 +876,7 @@ hho_status hho_setup(const hho_mesh *mesh, const hho_params *prm, hho_ctx **out)
         (s = upload(ctx, &ctx->emat, P.emat)) || (s = upload(ctx, &ctx->map, map)) ||
         (s = dalloc(ctx, (void **)&ctx->staging, std::max<size_t>(1, P.n_ext) * 4 * sizeof(double))) ||
         (s = dalloc(ctx, (void **)&ctx->e_now, (size_t)P.S * sizeof(double))) ||
-        (s = dalloc(ctx, (void **)&ctx->clock, sizeof(Clock))))
+        (s = dalloc(ctx, (void **)&ctx->clock, 2 * sizeof(Clock))))
         return fail(s);
     for (const Plan::Launch &L : P.launches) {
         std::vector<GroupDev> gd;
@@ -1102,7 +1140,7 @@ hho_status hho_adjoint_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps,
         const int len = std::min(every, n_steps - g * every);
         s = dispatch(ctx, [&](auto kc, auto *r) {
             using R = std::remove_pointer_t<decltype(r)>;
-            return enqueue_steps<decltype(kc)::value, R>(ctx, ctx->stream, len);
+            return enqueue_steps<decltype(kc)::value, R>(ctx, ctx->stream, len, (R *)nullptr, (g * every) & 1);
         });
         if (s != HHO_OK) return s;
     }

@@ -29,6 +29,8 @@ struct RecDev {
 
 // Device-resident time keeping of one context: the stage kernels derive the stage time, the
 // time step and the step index from it, so a captured multi-step graph replays unchanged.
+// Two clocks alternate: the steps of even index read the first and the last stage of such a
+// step writes the advanced clock into the second, and the other way round.
 struct Clock {
     double t0, dt;  // start time and time step of the current hho_erk_step call
     int step;       // steps completed since t0
@@ -37,10 +39,10 @@ struct Clock {
 
 template <typename R>
 struct StageArgs {
-    const R *Yin;   // stage input Y_i            [rows][LT]
-    R *Yout;        // stage output Y_{i+1}        [rows][LT]  (unused on the last stage)
+    const R *Yin;   // stage input: U^n (first stage) or the increment D_{i-1}  [rows][LT]
+    R *Yout;        // stage output: the increment D_i   [rows][LT]  (unused on the last stage)
     R *U;           // U^n (read), U^{n+1} (written on the last stage)
-    R *acc;         // running sum of b_i k_i
+    R *acc;         // adjoint stage: running sum of L^T mu_j (unused by the forward stages)
     const R *Tin;   // face-trace contributions of Y_i     [trace rows][LT]
     R *Tout;        // face-trace contributions of the output state
     const int32_t *link;  // [max_nf][n_ic]
@@ -52,8 +54,16 @@ struct StageArgs {
     int n_ic, S, cpb;
     long long LT;         // lanes = n_ic * S
     const Clock *clock;   // t_n = t0 + step * dt
+    Clock *clock_next;    // last stage: written with step + 1 (the clock the next step reads)
     double c;             // stage node: the stage time is t_n + c dt
-    R cU, cY, ck, cb;     // Y_{i+1} = cU U + cY Y_i + ck dt k_i ; acc = acc + cb k_i
+    // The stage buffers hold increments D_i = Y_{i+1} - U (Yin = D_{i-1}, Yout = D_i; Yin = U on
+    // the first stage).  Before the last stage D_i = cY D_{i-1} + ck dt k_i (cU = 1 - cY unused),
+    // and with q_write the partial sum Q = qa D_{i-1} + qb D_i is stored to Yq; last stage:
+    // U^{n+1} = U + [q_read] Q + cd D_{s-2} + cb dt k_s with Q read from Yq.
+    R cU, cY, ck, cb;
+    R qa, qb, cd;
+    int q_write, q_read;
+    R *Yq;
     int first, last;
     // point sources
     const int32_t *src_first;  // [n_ic], -1 = none
@@ -73,7 +83,7 @@ struct StageArgs {
     // kernels address through a single buffer resource: byte offsets of each array in it.
     const void *arena;
     unsigned arena_bytes;
-    unsigned o_yin, o_yout, o_u, o_acc, o_tin, o_tout, o_link, o_c0, o_mat;
+    unsigned o_yin, o_yout, o_u, o_acc, o_tin, o_tout, o_link, o_c0, o_mat, o_yq;
     // forward recompute for the adjoint: the stage input Y_i, its derivative k_i ([rows][LT])
     // and its face values ([trace rows][LT], own faces) are stored when non-null
     R *ystore, *kstore, *fstore;
@@ -120,9 +130,6 @@ hipError_t launch_adjoint_start(const StageArgs<R> &a, int n_blocks, hipStream_t
 // grad[c][q] = sum_shots gacc[q][ic_of_cell[c] * S + shot]  (adjoint.hip)
 hipError_t launch_grad_reduce(const double *gacc, long long LT, int S, const int32_t *ic_of_cell, int n_cells,
                               double *out, hipStream_t st);
-
-// clock->step += 1 (one thread), after the last stage of a step.
-hipError_t launch_tick(Clock *clock, hipStream_t st);
 
 // External (per-cell contiguous, float64) <-> internal ([rows][lanes], R) state copies
 // for one shot.  map[e] = internal row-major index (row * LT + ic * S) of external dof e.

@@ -33,39 +33,85 @@
 namespace hho {
 namespace {
 
-// Runge-Kutta combine of all ND rows of a lane (eq. ERK): out = new stage state, stored to
-// Y_{i+1} (and the accumulator) or to U^{n+1} on the last stage.  Every load is issued before
-// the first store: the arrays share one buffer resource, so the compiler cannot move a load
-// above an earlier store and would otherwise pay one memory round trip per row.
+// Stage state of one lane.  The stage buffers hold increments D_i = Y_{i+1} - U^n rather than
+// the stage states: the stage input is Y_i = U^n + D_{i-1} (U^n itself on the first stage).
+// Kept as increments, the values that the final combination below sums keep their full
+// relative precision in float32 (a stored Y_i would round away the low bits of dt k_i).
+template <int ND, typename R>
+__device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, R *y) {
+    if (a.first) {
+#pragma unroll
+        for (int r = 0; r < ND; ++r) y[r] = bld<R>(B.r, boff, B.yin + r * B.rowb);
+    } else {
+        R d[ND], u[ND];
+#pragma unroll
+        for (int r = 0; r < ND; ++r) {
+            d[r] = bld<R>(B.r, boff, B.yin + r * B.rowb);
+            u[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
+        }
+#pragma unroll
+        for (int r = 0; r < ND; ++r) y[r] = u[r] + d[r];
+    }
+}
+
+// Runge-Kutta combine of all ND rows of a lane (eq. ERK).  Before the last stage:
+// D_i = cY D_{i-1} + ck dt k_i (so that Y_{i+1} = cU U + cY Y_i + ck dt k_i with cU + cY = 1).
+// For i < s, dt k_i = (D_i - cY_i D_{i-1}) / ck_i, so U^{n+1} = U^n + dt sum_i b_i k_i is U^n plus
+// a fixed combination of the increments and b_s dt k_s.  One middle stage folds the earlier
+// increments into a partial sum Q (stored in place of its input), and the last stage forms
+// U^{n+1} = U^n + Q + cd D_{s-2} + b_s dt k_s.  No accumulator of b_i k_i is kept: a step of
+// ERK(4) moves 13 words per unknown instead of 17.  U^n and D_{i-1} were read at the start of
+// this stage and are read again here (cache hits) rather than held in registers through the
+// residual.  out = the new stage state (Y_{i+1} or U^{n+1}), from which the outgoing traces are
+// formed.  Every load is issued before the first store: the arrays share one buffer resource,
+// so the compiler cannot move a load above an earlier store.
 template <int ND, typename R>
 __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, const R *y,
                                           const R *kv, R *out) {
     const R dt = R(uni(a.clock)->dt);
-    R u[ND], ac[ND];
+    R u[ND], din[ND];
+    const bool need_d = a.last ? a.cd != R(0) : (a.cY != R(0) || a.q_write);
     if (a.first) {
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
             u[r] = y[r];
-            ac[r] = R(0);
+            din[r] = R(0);
+        }
+    } else if (need_d) {
+#pragma unroll
+        for (int r = 0; r < ND; ++r) {
+            u[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
+            din[r] = bld<R>(B.r, boff, B.yin + r * B.rowb);
         }
     } else {
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
             u[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
-            ac[r] = bld<R>(B.r, boff, B.acc + r * B.rowb);
+            din[r] = R(0);
         }
     }
     if (!a.last) {
+        const R ckdt = a.ck * dt;
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
-            out[r] = a.cU * u[r] + a.cY * y[r] + a.ck * dt * kv[r];
-            bst(B.r, boff, B.yout + r * B.rowb, out[r]);
-            bst(B.r, boff, B.acc + r * B.rowb, ac[r] + a.cb * kv[r]);
+            const R d = a.cY * din[r] + ckdt * kv[r];
+            bst(B.r, boff, B.yout + r * B.rowb, d);
+            if (a.q_write) bst(B.r, boff, B.yq + r * B.rowb, a.qa * din[r] + a.qb * d);
+            out[r] = u[r] + d;
         }
     } else {
+        R q[ND];
+        if (a.q_read) {
+#pragma unroll
+            for (int r = 0; r < ND; ++r) q[r] = bld<R>(B.r, boff, B.yq + r * B.rowb);
+        } else {
+#pragma unroll
+            for (int r = 0; r < ND; ++r) q[r] = R(0);
+        }
+        const R cb = a.cb * dt;
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
-            out[r] = u[r] + dt * (ac[r] + a.cb * kv[r]);
+            out[r] = u[r] + (q[r] + a.cd * din[r] + cb * kv[r]);
             bst(B.r, boff, B.u + r * B.rowb, out[r]);
         }
     }
@@ -109,13 +155,9 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
     R cc[NF], rn[NF][2][F];
     R fv[STORE ? NF : 1][2][F];  // face values, kept for the recompute stores
     load_links<NF, R>(B, nF, ic, lk, cc);
-    R p[N], mx[N], my[N];
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-        p[b] = bld<R>(B.r, boff, B.yin + (b) * B.rowb);
-        mx[b] = bld<R>(B.r, boff, B.yin + (N + b) * B.rowb);
-        my[b] = bld<R>(B.r, boff, B.yin + (2 * N + b) * B.rowb);
-    }
+    R y[3 * N];
+    load_state<3 * N, R>(a, B, boff, y);
+    const R *p = y, *mx = y + N, *my = y + 2 * N;
     load_incoming<K, NF, R>(B, kFluid, nF, lk, boff, rn);
     const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
     const R kap = bld<R>(B.r, coff, B.mat + kStiff * B.crowb);
@@ -196,12 +238,9 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
         }
     }
     // k = M^{-1} R and the Runge-Kutta combine
-    R y[3 * N], kv[3 * N], nw[3 * N];
+    R kv[3 * N], nw[3 * N];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-        y[b] = p[b];
-        y[N + b] = mx[b];
-        y[2 * N + b] = my[b];
         kv[b] = kap * rp[b];
         kv[N + b] = irho * rmx[b];
         kv[2 * N + b] = irho * rmy[b];
@@ -255,15 +294,9 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
     R cc[NF], rn[NF][2][F];
     R fv[STORE ? NF : 1][2][F];  // face values, kept for the recompute stores
     load_links<NF, R>(B, nF, ic, lk, cc);
-    R vx[N], vy[N], s1[N], s2[N], s3[N];
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-        vx[b] = bld<R>(B.r, boff, B.yin + (b) * B.rowb);
-        vy[b] = bld<R>(B.r, boff, B.yin + (N + b) * B.rowb);
-        s1[b] = bld<R>(B.r, boff, B.yin + (2 * N + b) * B.rowb);
-        s2[b] = bld<R>(B.r, boff, B.yin + (3 * N + b) * B.rowb);
-        s3[b] = bld<R>(B.r, boff, B.yin + (4 * N + b) * B.rowb);
-    }
+    R y[5 * N];
+    load_state<5 * N, R>(a, B, boff, y);
+    const R *vx = y, *vy = y + N, *s1 = y + 2 * N, *s2 = y + 3 * N, *s3 = y + 4 * N;
     load_incoming<K, NF, R>(B, kSolid, nF, lk, boff, rn);
     const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
     const R itau = bld<R>(B.r, coff, B.mat + kInvTau * B.crowb);
@@ -379,14 +412,9 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
             e = s.next;
         }
     }
-    R y[5 * N], kv[5 * N], nw[5 * N];
+    R kv[5 * N], nw[5 * N];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-        y[b] = vx[b];
-        y[N + b] = vy[b];
-        y[2 * N + b] = s1[b];
-        y[3 * N + b] = s2[b];
-        y[4 * N + b] = s3[b];
         kv[b] = irho * rvx[b];
         kv[N + b] = irho * rvy[b];
         kv[2 * N + b] = l2m * rs1[b] + lam * rs2[b];
@@ -443,6 +471,11 @@ __device__ __forceinline__ void stage_body(const StageArgs<R> &a, const GroupDev
 
 template <int K, typename R, bool STORE>
 __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<R> a) {
+    if (a.last && a.clock_next && blockIdx.x == 0 && threadIdx.x == 0) {
+        Clock c = *a.clock;
+        c.step += 1;
+        *a.clock_next = c;
+    }
     GroupDev G;
     const LaneInfo L = decode_lane(a, G);
     const bool want_e = a.last && a.e_part;
@@ -528,7 +561,6 @@ __global__ __launch_bounds__(kBlock) void energy_kernel(StageArgs<R> a) {
     block_energy(e, a.S, a.cpb, a.e_part);
 }
 
-__global__ void tick_kernel(Clock *clock) { clock->step += 1; }
 
 __global__ void energy_reduce_kernel(const double *part, int n_blocks, int S, double *out, const Clock *clock,
                                      int cap) {
@@ -594,10 +626,6 @@ hipError_t launch_energy_reduce(const double *part, int n_blocks, int S, double 
     return hipGetLastError();
 }
 
-hipError_t launch_tick(Clock *clock, hipStream_t st) {
-    hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(1), 0, st, clock);
-    return hipGetLastError();
-}
 
 template <typename R>
 hipError_t launch_scatter(const double *ext, const int64_t *map, long long n, int shot, R *state, hipStream_t st) {

@@ -64,7 +64,7 @@ __device__ __forceinline__ void bst(Rsrc r, unsigned voff, unsigned soff, double
 template <typename R>
 struct Bufs {
     Rsrc r;
-    unsigned yin, yout, u, acc, tin, tout, link, c0, mat;
+    unsigned yin, yout, u, acc, tin, tout, link, c0, mat, yq;
     unsigned rowb;   // bytes of one [lane] row: LT * sizeof(R)
     unsigned crowb;  // bytes of one [cell] row of reals: n_ic * sizeof(R)
     unsigned irowb;  // bytes of one [cell] row of int32: n_ic * 4
@@ -83,6 +83,7 @@ __device__ __forceinline__ Bufs<R> make_bufs(const StageArgs<R> &a) {
     b.link = a.o_link;
     b.c0 = a.o_c0;
     b.mat = a.o_mat;
+    b.yq = a.o_yq;
     b.rowb = (unsigned)a.LT * (unsigned)sizeof(R);
     b.crowb = (unsigned)a.n_ic * (unsigned)sizeof(R);
     b.irowb = (unsigned)a.n_ic * 4u;
