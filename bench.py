@@ -113,6 +113,38 @@ def run_variant(mesh, k, dtype, shots, steps, warmup):
                 frac=gbs / HBM_PEAK_GBS, finite=bool(np.all(np.isfinite(E))), ndof=ndof)
 
 
+def run_adjoint(k, dtype, steps=1000, ckpt=50):
+    """The adjoint workload: 128 x 128 hybrid mesh (seed 5001), k = 2, one Ricker source, 32
+    receivers; misfit gradient by hho_adjoint_step over `steps` steps with checkpoints every
+    `ckpt`, against the same number of forward steps."""
+    import torch
+    from paper_2505_15771_amd import Engine
+    mesh = M.adjoint_square(128)
+    rec_xy, rec_f = M.adjoint_receivers()
+    eng = Engine(mesh, k, dtype=dtype)
+    eng.set_sources(0, [[0.5, 0.25]], [[0.0, 1.0]], 10.0, 0.12, 1.0)
+    eng.set_receivers(rec_xy, rec_f)
+    dt = eng.dt_cfl(0.5)
+    d_obs = np.zeros((1, steps, len(rec_f), 2))
+    eng.adjoint(0.0, dt, 20, d_obs[:, :20], ckpt)  # warm-up (workspace allocation)
+    eng.set_state(np.zeros(eng.n_dof))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, _ = eng.adjoint(0.0, dt, steps, d_obs, ckpt)
+    t_adj = time.perf_counter() - t0
+    eng.set_state(np.zeros(eng.n_dof))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eng.erk_step(0.0, dt, steps)
+    eng.synchronize()
+    t_fwd = time.perf_counter() - t0
+    cells = int(len(mesh["cell_ptr"]) - 1)
+    eng.close()
+    return dict(workload="adjoint 128x128 hybrid, k=%d, %d steps, checkpoints every %d" % (k, steps, ckpt),
+                dtype=dtype, cells=cells, adjoint_ms=t_adj * 1e3, forward_ms=t_fwd * 1e3,
+                ratio=t_adj / t_fwd, finite=bool(np.isfinite(J)))
+
+
 def cpu_baseline(mesh, k, budget_s=12.0):
     """The FP64 oracle as it stands, on the host cores, for a bounded number of steps."""
     from oracle import Oracle
@@ -178,6 +210,12 @@ def main():
             print("variant", json.dumps(v), file=sys.stderr, flush=True)
             variants.append({key: v[key] for key in ("k", "dtype", "shots", "value", "ms_per_step", "launch_us",
                                                        "gbs", "frac")})
+    adjoint = []
+    if args.variants:
+        for dt_ in ("f64", "f32"):
+            v = run_adjoint(2, dt_)
+            print("adjoint", json.dumps(v), file=sys.stderr, flush=True)
+            adjoint.append(v)
     cpu = cpu_baseline(mesh, args.k) if args.cpu_baseline else None
     traffic = None
     if (stage_sources_digest() == MEASURED_TRAFFIC["sources_sha256"]
@@ -205,6 +243,7 @@ def main():
                      "traffic_unit": "HBM bytes per launch"},
         "cpu_baseline": cpu,
         "variants": variants,
+        "adjoint": adjoint,
     }
     print(json.dumps(out), flush=True)
 

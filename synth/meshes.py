@@ -233,6 +233,29 @@ def basin(nx=1120, ny=280, seed=3001, p_split=0.5):
     return m
 
 
+def adjoint_square(n=128, mesh_seed=5001):
+    """The adjoint workload: n x n hybrid squares (random diagonal cuts, p = 1/2) with the
+    unperturbed two-material setting as the model being evaluated."""
+    return with_materials(unit_square(n, p_split=0.5, seed=mesh_seed))
+
+
+def adjoint_receivers(n_each=16):
+    """Receivers of the adjoint workload: n_each recording p at y = 0.75 (fluid) and n_each
+    recording v at y = 0.40 (solid)."""
+    xy = np.concatenate([receiver_line(n_each, 0.75), receiver_line(n_each, 0.40)])
+    field = np.concatenate([np.zeros(n_each, np.int32), np.ones(n_each, np.int32)])
+    return xy, field
+
+
+def perturbed_model(mesh, seed=5002, amount=0.05):
+    """Copy of mesh with every per-cell parameter times (1 + U[-amount, amount])."""
+    out = dict(mesh)
+    rng = np.random.default_rng(seed)
+    for key in ("rho", "a", "b"):
+        out[key] = np.asarray(mesh[key], float) * (1 + rng.uniform(-amount, amount, len(mesh["rho"])))
+    return out
+
+
 def batch_meshes(n_meshes=16, c_min=2.0e4, c_max=3.0e5):
     """Sizes of the multi-mesh batch: target cell counts log-spaced between
     c_min and c_max, n_i = round(sqrt(C_i / 1.5)) squares per side, split seed

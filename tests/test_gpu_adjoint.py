@@ -181,3 +181,77 @@ def test_adjoint_argument_errors_and_no_receivers():
         e.adjoint(0.0, dt, 0)
     J, g = e.adjoint(0.0, dt, 3)  # no receivers: J = 0, gradient 0
     assert J == 0.0 and not np.any(g)
+
+
+def _fd_workload(nsteps):
+    """The adjoint workload (128 x 128 hybrid, k = 2, 32 receivers, Ricker source) with seeded
+    noise as observed data (the property checked does not depend on the data)."""
+    mesh = M.adjoint_square(128)
+    rec_xy, rec_f = M.adjoint_receivers()
+    d_obs = 1e-3 * np.random.default_rng(5003).standard_normal((1, nsteps, len(rec_f), 2))
+    d_obs[0, :, rec_f == 0, 1] = 0.0
+    return mesh, rec_xy, rec_f, d_obs
+
+
+def _misfit_forward(mesh, k, dt, nsteps, rec_xy, rec_f, d_obs):
+    from paper_2505_15771_amd import Engine
+    e = Engine(mesh, k)
+    e.set_sources(0, [[0.5, 0.25]], [[0.0, 1.0]], 10.0, 0.06, 1.0)
+    e.set_receivers(rec_xy, rec_f)
+    e.erk_step(0.0, dt, nsteps)
+    J = 0.5 * dt * float(np.sum((e.traces(0) - d_obs[0]) ** 2))
+    e.close()
+    return J
+
+
+def test_adjoint_workload_finite_differences_and_autograd():
+    """At the adjoint workload's size (24.6k cells, k = 2, float64, checkpoints every 50 steps):
+    the adjoint gradient agrees with central finite differences of J computed by forward runs,
+    on seeded fluid and solid cells for every parameter; the torch.autograd.Function returns the
+    same J and gradient, and a small step against the gradient lowers J."""
+    import torch
+    from paper_2505_15771_amd import Engine
+    from paper_2505_15771_amd.autograd import MisfitProblem, misfit
+    say("case: adjoint workload 128x128 k=2, FD + autograd")
+    k, nsteps = 2, 600
+    mesh, rec_xy, rec_f, d_obs = _fd_workload(nsteps)
+    dt = Engine(mesh, k).dt_cfl(0.5)
+    prob = MisfitProblem(mesh=mesh, k=k, dt=dt, n_steps=nsteps, rec_xy=rec_xy, rec_field=rec_f, d_obs=d_obs,
+                         sources=[([[0.5, 0.25]], [[0.0, 1.0]], 10.0, 0.06, 1.0)], ckpt_every=50)
+    rho = torch.tensor(np.asarray(mesh["rho"], float), requires_grad=True)
+    a = torch.tensor(np.asarray(mesh["a"], float), requires_grad=True)
+    b = torch.tensor(np.asarray(mesh["b"], float), requires_grad=True)
+    J = misfit(rho, a, b, prob)
+    J.backward()
+    grad = np.stack([rho.grad.numpy(), a.grad.numpy(), b.grad.numpy()], axis=1)
+    J0 = _misfit_forward(mesh, k, dt, nsteps, rec_xy, rec_f, d_obs)
+    say("J", float(J), J0)
+    assert abs(float(J) - J0) < 1e-12 * J0
+    med = np.asarray(mesh["medium"])
+    # cells near the source and receivers, where the gradient is not negligible
+    bc = np.array([np.mean(np.asarray(mesh["xy"]).reshape(-1, 2)[mesh["cell_vtx"][mesh["cell_ptr"][c]:
+                                                                                 mesh["cell_ptr"][c + 1]]], axis=0)
+                   for c in range(len(med))])
+    rng = np.random.default_rng(5004)
+    near = np.where((np.abs(bc[:, 0] - 0.5) < 0.3) & (bc[:, 1] > 0.2) & (bc[:, 1] < 0.8))[0]
+    cells = list(rng.choice(near[med[near] == 0], 3, replace=False)) + \
+        list(rng.choice(near[med[near] == 1], 3, replace=False))
+    gmax = np.max(np.abs(grad))
+    for c in cells:
+        params = [("rho", 0), ("a", 1)] if med[c] == 0 else [("rho", 0), ("a", 1), ("b", 2)]
+        for key, q in params:
+            h = 1e-5 * abs(mesh[key][c])
+            vals = []
+            for sgn in (1, -1):
+                m2 = dict(mesh)
+                m2[key] = np.array(mesh[key], float, copy=True)
+                m2[key][c] += sgn * h
+                vals.append(_misfit_forward(m2, k, dt, nsteps, rec_xy, rec_f, d_obs))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            say("cell", c, key, "adjoint", grad[c, q], "fd", fd)
+            assert abs(grad[c, q] - fd) < 1e-5 * max(abs(fd), 1e-3 * gmax), (c, key, grad[c, q], fd)
+    # descent: J(theta - s g) < J(theta) for a small step s
+    s = 1e-3 * float(np.max(np.abs(np.asarray(mesh["rho"])))) / gmax
+    m3 = dict(mesh)
+    m3["rho"] = np.asarray(mesh["rho"], float) - s * grad[:, 0]
+    assert _misfit_forward(m3, k, dt, nsteps, rec_xy, rec_f, d_obs) < J0
