@@ -37,11 +37,21 @@ namespace {
 // the stage states: the stage input is Y_i = U^n + D_{i-1} (U^n itself on the first stage).
 // Kept as increments, the values that the final combination below sums keep their full
 // relative precision in float32 (a stored Y_i would round away the low bits of dt k_i).
-template <int ND, typename R>
-__device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, R *y) {
+// With KEEP, U^n and D_{i-1} stay in registers (uk, dk) for the combine; otherwise the combine
+// reads them again (cache hits), which keeps the register count of the larger degrees down.
+template <int ND, typename R, bool KEEP>
+__device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, R *y, R *uk,
+                                           R *dk) {
     if (a.first) {
 #pragma unroll
         for (int r = 0; r < ND; ++r) y[r] = bld<R>(B.r, boff, B.yin + r * B.rowb);
+        if (KEEP) {
+#pragma unroll
+            for (int r = 0; r < ND; ++r) {
+                uk[r] = y[r];
+                dk[r] = R(0);
+            }
+        }
     } else {
         R d[ND], u[ND];
 #pragma unroll
@@ -51,6 +61,13 @@ __device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> 
         }
 #pragma unroll
         for (int r = 0; r < ND; ++r) y[r] = u[r] + d[r];
+        if (KEEP) {
+#pragma unroll
+            for (int r = 0; r < ND; ++r) {
+                uk[r] = u[r];
+                dk[r] = d[r];
+            }
+        }
     }
 }
 
@@ -65,13 +82,19 @@ __device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> 
 // residual.  out = the new stage state (Y_{i+1} or U^{n+1}), from which the outgoing traces are
 // formed.  Every load is issued before the first store: the arrays share one buffer resource,
 // so the compiler cannot move a load above an earlier store.
-template <int ND, typename R>
+template <int ND, typename R, bool KEEP>
 __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, const R *y,
-                                          const R *kv, R *out) {
+                                          const R *kv, R *out, const R *uk, const R *dk) {
     const R dt = R(uni(a.clock)->dt);
     R u[ND], din[ND];
     const bool need_d = a.last ? a.cd != R(0) : (a.cY != R(0) || a.q_write);
-    if (a.first) {
+    if (KEEP) {
+#pragma unroll
+        for (int r = 0; r < ND; ++r) {
+            u[r] = uk[r];
+            din[r] = dk[r];
+        }
+    } else if (a.first) {
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
             u[r] = y[r];
@@ -155,8 +178,9 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
     R cc[NF], rn[NF][2][F];
     R fv[STORE ? NF : 1][2][F];  // face values, kept for the recompute stores
     load_links<NF, R>(B, nF, ic, lk, cc);
-    R y[3 * N];
-    load_state<3 * N, R>(a, B, boff, y);
+    constexpr bool KEEP = sizeof(R) == 4 ? K <= 2 : K <= 1;
+    R y[3 * N], uk[KEEP ? 3 * N : 1], dk[KEEP ? 3 * N : 1];
+    load_state<3 * N, R, KEEP>(a, B, boff, y, uk, dk);
     const R *p = y, *mx = y + N, *my = y + 2 * N;
     load_incoming<K, NF, R>(B, kFluid, nF, lk, boff, rn);
     const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
@@ -245,7 +269,7 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
         kv[N + b] = irho * rmx[b];
         kv[2 * N + b] = irho * rmy[b];
     }
-    rk_update<3 * N, R>(a, B, boff, y, kv, nw);
+    rk_update<3 * N, R, KEEP>(a, B, boff, y, kv, nw, uk, dk);
     const R *np = nw, *nmx = nw + N, *nmy = nw + 2 * N;
     if (STORE) store_recompute<K, NF, 3 * N, R, NF, 1>(a, lk, boff, y, kv, fv);
     fluid_traces<K, NF, R>(a, B, tb, nF, lk, shot, np, nmx, nmy, tau);
@@ -294,8 +318,9 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
     R cc[NF], rn[NF][2][F];
     R fv[STORE ? NF : 1][2][F];  // face values, kept for the recompute stores
     load_links<NF, R>(B, nF, ic, lk, cc);
-    R y[5 * N];
-    load_state<5 * N, R>(a, B, boff, y);
+    constexpr bool KEEP = sizeof(R) == 4 ? K <= 2 : K <= 1;
+    R y[5 * N], uk[KEEP ? 5 * N : 1], dk[KEEP ? 5 * N : 1];
+    load_state<5 * N, R, KEEP>(a, B, boff, y, uk, dk);
     const R *vx = y, *vy = y + N, *s1 = y + 2 * N, *s2 = y + 3 * N, *s3 = y + 4 * N;
     load_incoming<K, NF, R>(B, kSolid, nF, lk, boff, rn);
     const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
@@ -421,7 +446,7 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
         kv[3 * N + b] = lam * rs1[b] + l2m * rs2[b];
         kv[4 * N + b] = tmu * rs3[b];
     }
-    rk_update<5 * N, R>(a, B, boff, y, kv, nw);
+    rk_update<5 * N, R, KEEP>(a, B, boff, y, kv, nw, uk, dk);
     const R *nvx = nw, *nvy = nw + N, *ns1 = nw + 2 * N, *ns2 = nw + 3 * N, *ns3 = nw + 4 * N;
     if (STORE) store_recompute<K, NF, 5 * N, R, NF, 2>(a, lk, boff, y, kv, fv);
     solid_traces<K, NF, R>(a, B, tb, nF, lk, shot, nvx, nvy, ns1, ns2, ns3, tau, itau);
