@@ -145,6 +145,67 @@ def run_adjoint(k, dtype, steps=1000, ckpt=50):
                 ratio=t_adj / t_fwd, finite=bool(np.isfinite(J)))
 
 
+def run_basin(dtype, steps=100, warmup=5):
+    """The synthetic basin (20 km x 5 km, water over a layered half-space with a Gaussian basin,
+    2:1 refinement with hanging nodes, ~543k cells), k = 2, ERK(4), Ricker f0 = 2 Hz 1 km below
+    the seafloor, 64 receivers of v just below the seafloor."""
+    import torch
+    from paper_2505_15771_amd import Engine
+    mesh = M.basin()
+    eng = Engine(mesh, 2, dtype=dtype)
+    eng.set_sources(0, [[8000.0, -1000.0]], [[0.0, 1.0]], 2.0, 0.6, 1.0e9)
+    h0 = 20000.0 / 1120
+    eng.set_receivers(np.stack([np.linspace(1000.0, 19000.0, 64), np.full(64, -0.25 * h0)], axis=1),
+                      np.ones(64, np.int32))
+    dt = eng.dt_cfl(0.5)
+    eng.erk_step(0.0, dt, warmup)
+    eng.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    eng.erk_step(warmup * dt, dt, steps)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    tr = eng.traces(0)
+    out = dict(workload="basin 543k cells (hanging nodes), k=2, 64 receivers", dtype=dtype, steps=steps,
+               cells=int(len(mesh["cell_ptr"]) - 1), dofs=int(eng.n_dof), ms_per_step=ms / steps,
+               value=eng.n_dof * 4 * steps / (ms / 1e3), finite=bool(np.all(np.isfinite(tr))))
+    eng.close()
+    return out
+
+
+def run_batch(steps=200, warmup=4):
+    """Sixteen hybrid meshes of 20k-300k cells (k = 1, 2, 3 in turn), four Ricker shots each at
+    seeded positions, float32 stepping with the float64 energy check, all advanced by one batch
+    (graph branches per mesh)."""
+    from paper_2505_15771_amd import Batch, Engine
+    engines, dts = [], []
+    for i, d in enumerate(M.batch_meshes()):
+        mesh = M.with_materials(M.unit_square(d["n"], p_split=0.5, seed=d["seed"]))
+        e = Engine(mesh, d["k"], dtype="f32", n_shots=4, record_energy=True)
+        pos = M.shot_positions(4, 4100 + i)
+        for sh in range(4):
+            e.set_sources(sh, [pos[sh]], [[0.0, 1.0]], 10.0, 0.12, 1.0)
+        dts.append(e.dt_cfl(0.5))
+        engines.append(e)
+    b = Batch(engines)
+    b.erk_step([0.0] * len(engines), dts, warmup)
+    t0 = time.perf_counter()
+    b.erk_step([warmup * dt for dt in dts], dts, steps)
+    secs = time.perf_counter() - t0
+    shot_dofs = sum(e.n_dof * 4 for e in engines)
+    E = [e.energy() for e in engines]
+    out = dict(workload="16 hybrid meshes (%d cells in total), k = 1/2/3, 4 shots each, one batch" %
+               sum(e.n_cells for e in engines), dtype="f32", steps=steps, shot_dofs=int(shot_dofs),
+               ms_per_step=secs * 1e3 / steps, value=shot_dofs * 4 * steps / secs,
+               finite=bool(all(np.all(np.isfinite(x)) for x in E)))
+    b.close()
+    for e in engines:
+        e.close()
+    return out
+
+
 def cpu_baseline(mesh, k, budget_s=12.0):
     """The FP64 oracle as it stands, on the host cores, for a bounded number of steps."""
     from oracle import Oracle
@@ -210,12 +271,19 @@ def main():
             print("variant", json.dumps(v), file=sys.stderr, flush=True)
             variants.append({key: v[key] for key in ("k", "dtype", "shots", "value", "ms_per_step", "launch_us",
                                                        "gbs", "frac")})
-    adjoint = []
+    adjoint, workloads = [], []
     if args.variants:
         for dt_ in ("f64", "f32"):
             v = run_adjoint(2, dt_)
             print("adjoint", json.dumps(v), file=sys.stderr, flush=True)
             adjoint.append(v)
+        for dt_ in ("f32", "f64"):
+            v = run_basin(dt_)
+            print("workload", json.dumps(v), file=sys.stderr, flush=True)
+            workloads.append(v)
+        v = run_batch()
+        print("workload", json.dumps(v), file=sys.stderr, flush=True)
+        workloads.append(v)
     cpu = cpu_baseline(mesh, args.k) if args.cpu_baseline else None
     traffic = None
     if (stage_sources_digest() == MEASURED_TRAFFIC["sources_sha256"]
@@ -244,6 +312,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
         "adjoint": adjoint,
+        "workloads": workloads,
     }
     print(json.dumps(out), flush=True)
 

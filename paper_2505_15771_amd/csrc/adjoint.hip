@@ -95,9 +95,12 @@ __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<
         double ys = 0;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            sx += Bx[r * N + b] * p[b];
-            sy += By[r * N + b] * p[b];
-            sd += Bx[b * N + r] * mx[b] + By[b * N + r] * my[b] + Sm[r * N + b] * tp[b];
+            if (b_nonzero(r, b)) {
+                sx += Bx[r * N + b] * p[b];
+                sy += By[r * N + b] * p[b];
+            }
+            if (b_nonzero(b, r)) sd += Bx[b * N + r] * mx[b] + By[b * N + r] * my[b];
+            sd += Sm[r * N + b] * tp[b];
             ys += (double)Sm[r * N + b] * (double)p[b];
         }
         rmx[r] = sx;
@@ -116,7 +119,8 @@ __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<
         for (int b = 0; b < N; ++b) {
             const R q = tp[b] - nx * mx[b] - ny * my[b];
 #pragma unroll
-            for (int i = 0; i < F; ++i) r[i] += Gt[(j * N + b) * F + i] * q;
+            for (int i = 0; i < F; ++i)
+                if (g_nonzero(b, i)) r[i] += Gt[(j * N + b) * F + i] * q;
         }
         R pF[F];
         if (!((lk[j] >> 3) & 1)) {
@@ -134,6 +138,7 @@ __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<
             double gy = 0, gw = 0;
 #pragma unroll
             for (int i = 0; i < F; ++i) {
+                if (!g_nonzero(b, i)) continue;
                 w += Gt[(j * N + b) * F + i] * pF[i];
                 gy += (double)Gt[(j * N + b) * F + i] * (double)pF[i];
                 gw += (double)Gt[(j * N + b) * F + i] * (double)yf[j][i];
@@ -283,13 +288,20 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
         double yx_s = 0, yy_s = 0;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            const R bxrb = Bx[r * N + b], byrb = By[r * N + b];
-            const R bxbr = Bx[b * N + r], bybr = By[b * N + r], srb = Sm[r * N + b];
-            a1 += bxrb * vx[b];
-            a2 += byrb * vy[b];
-            a3 += byrb * vx[b] + bxrb * vy[b];
-            bx += bxbr * s1[b] + bybr * hs3[b] + srb * tvx[b];
-            by += bybr * s2[b] + bxbr * hs3[b] + srb * tvy[b];
+            const R srb = Sm[r * N + b];
+            if (b_nonzero(r, b)) {
+                const R bxrb = Bx[r * N + b], byrb = By[r * N + b];
+                a1 += bxrb * vx[b];
+                a2 += byrb * vy[b];
+                a3 += byrb * vx[b] + bxrb * vy[b];
+            }
+            if (b_nonzero(b, r)) {
+                const R bxbr = Bx[b * N + r], bybr = By[b * N + r];
+                bx += bxbr * s1[b] + bybr * hs3[b];
+                by += bybr * s2[b] + bxbr * hs3[b];
+            }
+            bx += srb * tvx[b];
+            by += srb * tvy[b];
             yx_s += (double)srb * (double)vx[b];
             yy_s += (double)srb * (double)vy[b];
         }
@@ -313,6 +325,7 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
             const R qy = tvy[b] - nx * hs3[b] - ny * s2[b];
 #pragma unroll
             for (int i = 0; i < F; ++i) {
+                if (!g_nonzero(b, i)) continue;
                 rx[i] += Gt[(j * N + b) * F + i] * qx;
                 ry[i] += Gt[(j * N + b) * F + i] * qy;
             }
@@ -340,6 +353,7 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
             double gyx = 0, gyy = 0, gwx = 0, gwy = 0;
 #pragma unroll
             for (int i = 0; i < F; ++i) {
+                if (!g_nonzero(b, i)) continue;
                 const R g = Gt[(j * N + b) * F + i];
                 wx += g * vFx[i];
                 wy += g * vFy[i];

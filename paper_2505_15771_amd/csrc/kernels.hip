@@ -194,9 +194,12 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
         R sx = 0, sy = 0, sd = 0;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            sx += Bx[r * N + b] * p[b];
-            sy += By[r * N + b] * p[b];
-            sd += Bx[b * N + r] * mx[b] + By[b * N + r] * my[b] + Sm[r * N + b] * tp[b];
+            if (b_nonzero(r, b)) {
+                sx += Bx[r * N + b] * p[b];
+                sy += By[r * N + b] * p[b];
+            }
+            if (b_nonzero(b, r)) sd += Bx[b * N + r] * mx[b] + By[b * N + r] * my[b];
+            sd += Sm[r * N + b] * tp[b];
         }
         rmx[r] = sx;
         rmy[r] = sy;
@@ -213,7 +216,8 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
         for (int b = 0; b < N; ++b) {
             const R q = tp[b] - nx * mx[b] - ny * my[b];
 #pragma unroll
-            for (int i = 0; i < F; ++i) r[i] += Gt[(j * N + b) * F + i] * q;
+            for (int i = 0; i < F; ++i)
+                if (g_nonzero(b, i)) r[i] += Gt[(j * N + b) * F + i] * q;
         }
         R pF[F];
         if (!((lk[j] >> 3) & 1)) {
@@ -233,7 +237,8 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
         for (int b = 0; b < N; ++b) {
             R w = 0;
 #pragma unroll
-            for (int i = 0; i < F; ++i) w += Gt[(j * N + b) * F + i] * pF[i];
+            for (int i = 0; i < F; ++i)
+                if (g_nonzero(b, i)) w += Gt[(j * N + b) * F + i] * pF[i];
             rmx[b] += nx * w;
             rmy[b] += ny * w;
             rp[b] += tau * w;
@@ -341,13 +346,20 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
         R a1 = 0, a2 = 0, a3 = 0, bx = 0, by = 0;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            const R bxrb = Bx[r * N + b], byrb = By[r * N + b];
-            const R bxbr = Bx[b * N + r], bybr = By[b * N + r], srb = Sm[r * N + b];
-            a1 += bxrb * vx[b];
-            a2 += byrb * vy[b];
-            a3 += byrb * vx[b] + bxrb * vy[b];
-            bx += bxbr * s1[b] + bybr * hs3[b] + srb * tvx[b];
-            by += bybr * s2[b] + bxbr * hs3[b] + srb * tvy[b];
+            const R srb = Sm[r * N + b];
+            if (b_nonzero(r, b)) {
+                const R bxrb = Bx[r * N + b], byrb = By[r * N + b];
+                a1 += bxrb * vx[b];
+                a2 += byrb * vy[b];
+                a3 += byrb * vx[b] + bxrb * vy[b];
+            }
+            if (b_nonzero(b, r)) {
+                const R bxbr = Bx[b * N + r], bybr = By[b * N + r];
+                bx += bxbr * s1[b] + bybr * hs3[b];
+                by += bybr * s2[b] + bxbr * hs3[b];
+            }
+            bx += srb * tvx[b];
+            by += srb * tvy[b];
         }
         rs1[r] = a1;
         rs2[r] = a2;
@@ -368,6 +380,7 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
             const R qy = tvy[b] - nx * hs3[b] - ny * s2[b];
 #pragma unroll
             for (int i = 0; i < F; ++i) {
+                if (!g_nonzero(b, i)) continue;
                 rx[i] += Gt[(j * N + b) * F + i] * qx;
                 ry[i] += Gt[(j * N + b) * F + i] * qy;
             }
@@ -400,6 +413,7 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
             R wx = 0, wy = 0;
 #pragma unroll
             for (int i = 0; i < F; ++i) {
+                if (!g_nonzero(b, i)) continue;
                 wx += Gt[(j * N + b) * F + i] * vFx[i];
                 wy += Gt[(j * N + b) * F + i] * vFy[i];
             }

@@ -369,6 +369,36 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
                 Ssum[q] += E[q];
             }
         }
+        // B_c = -D_c^T vanishes where deg(b) >= deg(r) (the derivative of a graded orthonormal basis
+        // function is orthogonal to all functions of its degree and above): store exact zeros there,
+        // after checking that the computed values are round-off
+        {
+            const int deg[10] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3};
+            double bmax = 0.0, zmax = 0.0;
+            for (int q = 0; q < N * N; ++q) bmax = std::max({bmax, std::fabs(Bx[q]), std::fabs(By[q])});
+            for (int r = 0; r < N; ++r)
+                for (int b = 0; b < N; ++b)
+                    if (deg[b] >= deg[r]) {
+                        zmax = std::max({zmax, std::fabs(Bx[r * N + b]), std::fabs(By[r * N + b])});
+                        Bx[r * N + b] = By[r * N + b] = 0.0;
+                    }
+            // G_j[a][i] = (phi_a, psi_i)_F vanishes where i > deg(a)
+            double gmax = 0.0, gzero = 0.0;
+            for (double v : G) gmax = std::max(gmax, std::fabs(v));
+            for (int j = 0; j < n; ++j)
+                for (int a2 = 0; a2 < N; ++a2)
+                    for (int i = 0; i < F; ++i)
+                        if (i > deg[a2]) {
+                            double &g = G[(j * N + a2) * F + i];
+                            gzero = std::max(gzero, std::fabs(g));
+                            g = 0.0;
+                        }
+            if (zmax > 1e-9 * bmax || gzero > 1e-9 * gmax) {
+                *code = 3;  // HHO_ERR_SINGULAR
+                return "cell " + std::to_string(c) + ": local gradient operator lost its degree structure "
+                       "(ill-conditioned cell basis)";
+            }
+        }
         ci.offset = (int)P.tables.size();
         P.tables.insert(P.tables.end(), Bx.begin(), Bx.end());
         P.tables.insert(P.tables.end(), By.begin(), By.end());

@@ -108,6 +108,20 @@ __device__ __forceinline__ double ricker(double t, double f0, double t0) {
 
 constexpr double kRsqrt2 = 0.70710678118654752440;
 
+// Total degree of the i-th function of the graded cell basis (degree-major order, k <= 3).
+constexpr int kBasisDegree[10] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3};
+
+// B_c = D_c - sum_j n_{j,c} E_j equals -D_c^T (integration by parts), and in the orthonormal
+// graded basis the derivative of a basis function is orthogonal to every basis function of equal
+// or higher degree, so B_c[r][b] can be nonzero only when deg(b) < deg(r).  The host plan stores
+// exact zeros there; the kernels skip those products at compile time.
+__device__ constexpr bool b_nonzero(int r, int b) { return kBasisDegree[b] < kBasisDegree[r]; }
+
+// G_j[a][i] = (phi_a, psi_i)_F: the trace of phi_a on a straight face is a polynomial of degree
+// deg(a), orthogonal to the face Legendre polynomial psi_i of higher degree, so G_j[a][i] can be
+// nonzero only when i <= deg(a) (exact zeros in the host plan as well).
+__device__ constexpr bool g_nonzero(int a, int i) { return i <= kBasisDegree[a]; }
+
 struct LaneInfo {
     int ic, shot;
     unsigned boff;   // byte offset of this lane in a [row][lane] array of reals
@@ -203,7 +217,8 @@ __device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const Bufs<R
         for (int b = 0; b < N; ++b) {
             const R q = tp[b] - nx * mx[b] - ny * my[b];
 #pragma unroll
-            for (int i = 0; i < F; ++i) r[i] += Gt[(j * N + b) * F + i] * q;
+            for (int i = 0; i < F; ++i)
+                if (g_nonzero(b, i)) r[i] += Gt[(j * N + b) * F + i] * q;
         }
         const int icn = lk[j] >> 4, jn = lk[j] & 7;
         const unsigned nb = (unsigned)(icn * a.S + shot) * (unsigned)sizeof(R);
@@ -240,6 +255,7 @@ __device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R
             const R qy = tvy[b] - nx * hs3[b] - ny * s2[b];
 #pragma unroll
             for (int i = 0; i < F; ++i) {
+                if (!g_nonzero(b, i)) continue;
                 rx[i] += Gt[(j * N + b) * F + i] * qx;
                 ry[i] += Gt[(j * N + b) * F + i] * qy;
             }

@@ -208,3 +208,22 @@ def test_full_size_hybrid_256(k, dtype):
     err = rel(e.get_state(), ref)
     say("rel L2 =", err)
     assert err < (TOL64 if dtype == "f64" else TOL32)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_size_basin(dtype):
+    """The synthetic basin at full size (543k cells: triangles, quadrilaterals and 2:1 hanging-node
+    polygons, water over a layered half-space, physical units), k = 2, ERK(4) at half the CFL step,
+    two steps from a random state, on the whole mesh against the oracle."""
+    say("case: full-size basin k=2 %s" % dtype)
+    mesh = M.basin()
+    o = oracle(mesh, 2)
+    U0 = np.random.default_rng(3001).standard_normal(o.ndof)
+    e = engine(mesh, 2, dtype=dtype)
+    dt = e.dt_cfl(0.5)
+    ref = o.erk(U0, 0.0, dt, 2)
+    e.set_state(U0)
+    e.erk_step(0.0, dt, 2)
+    err = rel(e.get_state(), ref)
+    say("rel L2 =", err)
+    assert err < (TOL64 if dtype == "f64" else TOL32)
