@@ -82,6 +82,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libhho.so is not built (%s): run `python -m paper_2505_15771_amd.build`" % path)
+    # PyTorch ships its own HIP runtime under the same soname (libamdhip64.so.7).  Loading torch
+    # first makes libhho.so bind to that runtime, so one HIP runtime serves both and device
+    # pointers and streams taken from torch tensors are valid in the library's calls.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     for name, (res, args) in EXPORTS.items():
         f = getattr(lib, name)

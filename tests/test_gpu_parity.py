@@ -227,3 +227,33 @@ def test_full_size_basin(dtype):
     err = rel(e.get_state(), ref)
     say("rel L2 =", err)
     assert err < (TOL64 if dtype == "f64" else TOL32)
+
+
+def test_full_size_float32_error_growth():
+    """The 256 x 256 hybrid workload, k = 2, with its Ricker point source and receivers, stepped
+    200 steps in float32 at half the CFL step: the relative L2 error against the float64 oracle
+    (state and receiver traces) is reported every 50 steps and stays below 1e-5."""
+    say("case: full-size hybrid 256 k=2 f32, 200 steps, error growth")
+    mesh = M.hybrid_square(256)
+    o = oracle(mesh, 2)
+    src, dirs = [[0.5, 0.25]], [[0.0, 1.0]]
+    o.set_point_sources(src, dirs, 10.0, 0.12, 1.0)
+    rx = M.receiver_line(8, 0.75)
+    U = 1e-3 * np.random.default_rng(2003).standard_normal(o.ndof)
+    e = engine(mesh, 2, dtype="f32")
+    e.set_sources(0, src, dirs, 10.0, 0.12, 1.0)
+    e.set_receivers(rx, np.zeros(8, np.int32))
+    e.set_state(U)
+    dt = e.dt_cfl(0.5)
+    t = 0.0
+    for block in range(4):
+        tr = np.zeros((50, 8, 2))
+        for n in range(50):
+            U = o.erk(U, t + n * dt, dt, 1)
+            for r in range(8):
+                tr[n, r, 0] = o.point_values(U, *rx[r])[1][0]
+        e.erk_step(t, dt, 50)
+        t += 50 * dt
+        eu, et = rel(e.get_state(), U), rel(e.traces(), tr)
+        say("steps", 50 * (block + 1), "state", eu, "traces", et)
+        assert eu < TOL32 and et < TOL32
