@@ -25,7 +25,9 @@
 //      (-1)^i between the two orientations of a face; a solid cell writing across the
 //      interface also divides by its tau_s, which the fluid side needs).  So the next stage
 //      reads its incoming contributions at its own lane, coalesced and independent of the
-//      face links; the scattered accesses are stores.
+//      face links; the scattered accesses are stores.  Trace buffers are [slot][lane][mode]
+//      (slot = local face and component): the F modes of one contribution are contiguous, so
+//      a scattered store writes one 12- or 16-byte piece instead of F separate words.
 #include <hip/hip_runtime.h>
 
 #include "stage_common.h"

@@ -59,6 +59,71 @@ __device__ __forceinline__ void bst(Rsrc r, unsigned voff, unsigned soff, double
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, 0);
 }
 
+// D contiguous dwords of one lane in the widest buffer accesses (16, 12, 8, 4 bytes).
+typedef unsigned Dw2 __attribute__((ext_vector_type(2)));
+typedef unsigned Dw3 __attribute__((ext_vector_type(3)));
+typedef unsigned Dw4 __attribute__((ext_vector_type(4)));
+template <int D, int O = 0>
+__device__ __forceinline__ void bld_dw(Rsrc r, unsigned voff, unsigned soff, unsigned *w) {
+    if constexpr (D - O >= 4) {
+        const Dw4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)(soff + 4 * O), 0);
+        w[O] = v.x, w[O + 1] = v.y, w[O + 2] = v.z, w[O + 3] = v.w;
+        bld_dw<D, O + 4>(r, voff, soff, w);
+    } else if constexpr (D - O == 3) {
+        const Dw3 v = __builtin_amdgcn_raw_buffer_load_b96(r, (int)voff, (int)(soff + 4 * O), 0);
+        w[O] = v.x, w[O + 1] = v.y, w[O + 2] = v.z;
+    } else if constexpr (D - O == 2) {
+        const Dw2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)(soff + 4 * O), 0);
+        w[O] = v.x, w[O + 1] = v.y;
+    } else if constexpr (D - O == 1) {
+        w[O] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)(soff + 4 * O), 0);
+    }
+}
+template <int D, int O = 0>
+__device__ __forceinline__ void bst_dw(Rsrc r, unsigned voff, unsigned soff, const unsigned *w) {
+    if constexpr (D - O >= 4) {
+        const Dw4 v = {w[O], w[O + 1], w[O + 2], w[O + 3]};
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)(soff + 4 * O), 0);
+        bst_dw<D, O + 4>(r, voff, soff, w);
+    } else if constexpr (D - O == 3) {
+        const Dw3 v = {w[O], w[O + 1], w[O + 2]};
+        __builtin_amdgcn_raw_buffer_store_b96(v, r, (int)voff, (int)(soff + 4 * O), 0);
+    } else if constexpr (D - O == 2) {
+        const Dw2 v = {w[O], w[O + 1]};
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)(soff + 4 * O), 0);
+    } else if constexpr (D - O == 1) {
+        __builtin_amdgcn_raw_buffer_store_b32(w[O], r, (int)voff, (int)(soff + 4 * O), 0);
+    }
+}
+// F contiguous reals of one lane: v[i] at byte soff + i sizeof(R) (plus the lane's voff).
+template <int F, typename R>
+__device__ __forceinline__ void bldv(Rsrc r, unsigned voff, unsigned soff, R *v) {
+    constexpr int D = F * (int)sizeof(R) / 4;
+    unsigned w[D];
+    bld_dw<D>(r, voff, soff, w);
+#pragma unroll
+    for (int i = 0; i < F; ++i) {
+        if constexpr (sizeof(R) == 4) v[i] = __builtin_bit_cast(R, w[i]);
+        else v[i] = __builtin_bit_cast(R, ((unsigned long long)w[2 * i + 1] << 32) | w[2 * i]);
+    }
+}
+template <int F, typename R>
+__device__ __forceinline__ void bstv(Rsrc r, unsigned voff, unsigned soff, const R *v) {
+    constexpr int D = F * (int)sizeof(R) / 4;
+    unsigned w[D];
+#pragma unroll
+    for (int i = 0; i < F; ++i) {
+        if constexpr (sizeof(R) == 4) {
+            w[i] = __builtin_bit_cast(unsigned, v[i]);
+        } else {
+            const unsigned long long b = __builtin_bit_cast(unsigned long long, v[i]);
+            w[2 * i] = (unsigned)b;
+            w[2 * i + 1] = (unsigned)(b >> 32);
+        }
+    }
+    bst_dw<D>(r, voff, soff, w);
+}
+
 // Buffer addressing of one stage launch (uniform): one resource over the arena, and the
 // byte offset of each array in it.
 template <typename R>
@@ -167,7 +232,8 @@ __device__ __forceinline__ void load_links(const Bufs<R> &B, int nF, int ic, int
     }
 }
 
-// Incoming neighbour contributions.  Rows of every face of the group are loaded without
+// Incoming neighbour contributions (trace buffers [slot = 2 j + c][lane][mode i], byte offset
+// ((2 j + c) LT + lane) F sizeof(R) + i sizeof(R)).  Rows of every face of the group are loaded without
 // waiting for the links (a boundary face's slot is never written and its value is unused);
 // only a fluid cell's second component, present across the interface, depends on the link.
 template <int K, int NF, typename R>
@@ -179,19 +245,14 @@ __device__ __forceinline__ void load_incoming(const Bufs<R> &B, int medium, int 
 #pragma unroll
         for (int i = 0; i < F; ++i) rn[j][0][i] = rn[j][1][i] = R(0);
         if (j >= nF) continue;
-#pragma unroll
-        for (int i = 0; i < F; ++i) rn[j][0][i] = bld<R>(B.r, boff, B.tin + ((j * 2) * F + i) * B.rowb);
-        if (medium == kSolid) {
-#pragma unroll
-            for (int i = 0; i < F; ++i) rn[j][1][i] = bld<R>(B.r, boff, B.tin + ((j * 2 + 1) * F + i) * B.rowb);
-        }
+        bldv<F, R>(B.r, F * boff, B.tin + (j * 2) * F * B.rowb, rn[j][0]);
+        if (medium == kSolid) bldv<F, R>(B.r, F * boff, B.tin + (j * 2 + 1) * F * B.rowb, rn[j][1]);
     }
     if (medium == kFluid) {
 #pragma unroll
         for (int j = 0; j < NF; ++j) {
             if (lk[j] < 0 || !((lk[j] >> 3) & 1)) continue;
-#pragma unroll
-            for (int i = 0; i < F; ++i) rn[j][1][i] = bld<R>(B.r, boff, B.tin + ((j * 2 + 1) * F + i) * B.rowb);
+            bldv<F, R>(B.r, F * boff, B.tin + (j * 2 + 1) * F * B.rowb, rn[j][1]);
         }
     }
 }
@@ -222,8 +283,10 @@ __device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const Bufs<R
         }
         const int icn = lk[j] >> 4, jn = lk[j] & 7;
         const unsigned nb = (unsigned)(icn * a.S + shot) * (unsigned)sizeof(R);
+        R o[F];
 #pragma unroll
-        for (int i = 0; i < F; ++i) bst(B.r, nb, B.tout + ((jn * 2) * F + i) * B.rowb, sgn<R>(i) * r[i]);
+        for (int i = 0; i < F; ++i) o[i] = sgn<R>(i) * r[i];
+        bstv<F, R>(B.r, F * nb, B.tout + (jn * 2) * F * B.rowb, o);
     }
 }
 
@@ -264,11 +327,14 @@ __device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R
         const unsigned nb = (unsigned)(icn * a.S + shot) * (unsigned)sizeof(R);
         // across the interface the fluid side needs r_s / tau_s
         const R w = ((lk[j] >> 3) & 1) ? itau : R(1);
+        R ox[F], oy[F];
 #pragma unroll
         for (int i = 0; i < F; ++i) {
-            bst(B.r, nb, B.tout + ((jn * 2) * F + i) * B.rowb, sgn<R>(i) * w * rx[i]);
-            bst(B.r, nb, B.tout + ((jn * 2 + 1) * F + i) * B.rowb, sgn<R>(i) * w * ry[i]);
+            ox[i] = sgn<R>(i) * w * rx[i];
+            oy[i] = sgn<R>(i) * w * ry[i];
         }
+        bstv<F, R>(B.r, F * nb, B.tout + (jn * 2) * F * B.rowb, ox);
+        bstv<F, R>(B.r, F * nb, B.tout + (jn * 2 + 1) * F * B.rowb, oy);
     }
 }
 
