@@ -33,9 +33,9 @@ HBM_PEAK_GBS = 8000.0
 # elementwise kernel of known size (factors 2.0 and 1.0); valid only for the kernel sources with
 # this digest (otherwise the traffic is reported as null).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "e6df1748961a32d9c336eae1052963434be52231537f153764e056292f3c64e4",
+    "sources_sha256": "d1f95c3613f59be4331030b84acff84f0d9a92e065f9447614ae364456e3195d",
     "config": (2, "f32", 1),
-    "bytes_per_launch": (2.0 * 14774.1 + 1.0 * 24893.8) * 1024,
+    "bytes_per_launch": (2.0 * 14767.4 + 1.0 * 22307.7) * 1024,
 }
 STAGE_SOURCES = ("kernels.hip", "stage_common.h", "device.h")
 
@@ -237,6 +237,9 @@ def main():
     ap.add_argument("--shots", type=int, default=1)
     ap.add_argument("--variants", type=int, default=1, help="also time the float64 / k=3 / batched variants")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--only", choices=("adjoint", "basin", "batch"), default=None,
+                    help="run one extra workload alone and print its JSON line (for profiling)")
+    ap.add_argument("--only-steps", type=int, default=200)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -259,6 +262,12 @@ def main():
         print("copy calibration: neg kernel, %d MiB read + %d MiB written" % (args.copy_mb, args.copy_mb),
               file=sys.stderr)
         del src, dst
+    if args.only:
+        fn = {"adjoint": lambda: run_adjoint(2, args.dtype, steps=args.only_steps, ckpt=50),
+              "basin": lambda: run_basin(args.dtype, steps=args.only_steps),
+              "batch": lambda: run_batch(steps=args.only_steps)}[args.only]
+        print(json.dumps(fn()), flush=True)
+        return
     mesh = M.hybrid_square(256)
     head = run_variant(mesh, args.k, args.dtype, args.shots, args.steps, args.warmup)
     print("headline", json.dumps(head), file=sys.stderr, flush=True)
