@@ -225,7 +225,7 @@ def test_adjoint_workload_finite_differences_and_autograd():
     J.backward()
     grad = np.stack([rho.grad.numpy(), a.grad.numpy(), b.grad.numpy()], axis=1)
     J0 = _misfit_forward(mesh, k, dt, nsteps, rec_xy, rec_f, d_obs)
-    say("J", float(J), J0)
+    say("J", float(J.detach()), J0)
     assert abs(float(J) - J0) < 1e-12 * J0
     med = np.asarray(mesh["medium"])
     # cells near the source and receivers, where the gradient is not negligible
@@ -250,6 +250,15 @@ def test_adjoint_workload_finite_differences_and_autograd():
             fd = (vals[0] - vals[1]) / (2 * h)
             say("cell", c, key, "adjoint", grad[c, q], "fd", fd)
             assert abs(grad[c, q] - fd) < 1e-5 * max(abs(fd), 1e-3 * gmax), (c, key, grad[c, q], fd)
+    # float32 stepping of the same adjoint: gradient close to the float64 one
+    prob32 = MisfitProblem(mesh=mesh, k=k, dt=dt, n_steps=nsteps, rec_xy=rec_xy, rec_field=rec_f, d_obs=d_obs,
+                           sources=prob.sources, ckpt_every=50, dtype="f32")
+    r32, a32, b32 = (torch.tensor(np.asarray(mesh[key], float), requires_grad=True) for key in ("rho", "a", "b"))
+    J32 = misfit(r32, a32, b32, prob32)
+    J32.backward()
+    g32 = np.stack([r32.grad.numpy(), a32.grad.numpy(), b32.grad.numpy()], axis=1)
+    say("float32: J rel", abs(float(J32) - J0) / J0, "grad rel L2", rel(g32, grad))
+    assert abs(float(J32) - J0) < 1e-4 * J0 and rel(g32, grad) < 1e-4
     # descent: J(theta - s g) < J(theta) for a small step s
     s = 1e-3 * float(np.max(np.abs(np.asarray(mesh["rho"])))) / gmax
     m3 = dict(mesh)

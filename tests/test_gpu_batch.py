@@ -124,3 +124,39 @@ def test_batch_of_meshes_and_shots():
             say("mesh", i, "shot", sh, err)
             assert err < tol
     b.close()
+
+
+def test_full_size_batch_sampled():
+    """The 16-mesh batch in the launch configuration the benchmark times (hybrid meshes of 20k-300k
+    cells, k = 1, 2, 3 in turn, 4 Ricker shots each, float32 with the energy check, one batch):
+    after 5 steps, sampled meshes and shots (the smallest, a middle one and the largest mesh) are
+    compared with the oracle on the whole mesh."""
+    from oracle import Oracle
+    from paper_2505_15771_amd import Batch, Engine
+    say("case: full-size 16-mesh batch, sampled vs oracle")
+    specs = M.batch_meshes()
+    engines, dts, meshes = [], [], []
+    for i, d in enumerate(specs):
+        mesh = M.with_materials(M.unit_square(d["n"], p_split=0.5, seed=d["seed"]))
+        e = Engine(mesh, d["k"], dtype="f32", n_shots=4, record_energy=True)
+        pos = M.shot_positions(4, 4100 + i)
+        for sh in range(4):
+            e.set_sources(sh, [pos[sh]], [[0.0, 1.0]], 10.0, 0.12, 1.0)
+            e.set_state(0.01 * np.random.default_rng(7000 + 4 * i + sh).standard_normal(e.n_dof), shot=sh)
+        dts.append(e.dt_cfl(0.5))
+        engines.append(e)
+        meshes.append(mesh)
+    b = Batch(engines)
+    b.erk_step([0.1] * len(engines), dts, 5)
+    for i, sh in ((0, 0), (7, 2), (15, 3)):
+        o = Oracle(meshes[i], specs[i]["k"])
+        pos = M.shot_positions(4, 4100 + i)
+        o.set_point_sources([pos[sh]], [[0.0, 1.0]], 10.0, 0.12, 1.0)
+        U0 = 0.01 * np.random.default_rng(7000 + 4 * i + sh).standard_normal(o.ndof)
+        ref = o.erk(U0, 0.1, dts[i], 5)
+        err = rel(engines[i].get_state(sh), ref)
+        say("mesh", i, "k", specs[i]["k"], "cells", engines[i].n_cells, "shot", sh, "rel L2", err)
+        assert err < 1e-5
+    b.close()
+    for e in engines:
+        e.close()
