@@ -1,0 +1,40 @@
+"""CPU checks of the benchmark's bookkeeping (no GPU): the algorithmic byte count of one ERK(4)
+step and the unknown count on a mesh small enough to count by hand, and the refusal of more
+than one GPU."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def _bench():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    return b
+
+
+def test_algorithmic_bytes_two_squares():
+    """Two unit squares side by side, one fluid and one solid, k = 1 (N = 3): 9 + 15 = 24 cell
+    unknowns; per step 13 words per unknown; in each of the 4 stages one 4-byte face id per cell
+    face (8), the 4-byte material scalars (3 + 5) and one coefficient for the single interior face."""
+    b = _bench()
+    mesh = dict(xy=np.array([[0, 0], [1, 0], [2, 0], [2, 1], [1, 1], [0, 1]], float).reshape(-1),
+                cell_ptr=np.array([0, 4, 8], np.int32), cell_vtx=np.array([0, 1, 4, 5, 1, 2, 3, 4], np.int32),
+                medium=np.array([0, 1], np.uint8))
+    for word in (4, 8):
+        for shots in (1, 3):
+            got, ndof = b.algorithmic_bytes_per_step(mesh, 1, word, shots)
+            assert ndof == 24
+            assert got == word * 13 * 24 * shots + 4 * (4 * (8 + 8) + 4 * 1)
+
+
+def test_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2 and "one GPU" in r.stderr
