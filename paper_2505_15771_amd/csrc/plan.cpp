@@ -441,6 +441,33 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
         }
         members[g].push_back(c);
     }
+    // within a group, cells in Z (Morton) order of their centroids: the cells of one workgroup
+    // are close in space, so the neighbour slots their face contributions are written to fall
+    // in few cache lines
+    {
+        double x0 = P.centroid[0], x1 = x0, y0 = P.centroid[1], y1 = y0;
+        for (int c = 0; c < nc; ++c) {
+            x0 = std::min(x0, P.centroid[2 * c]), x1 = std::max(x1, P.centroid[2 * c]);
+            y0 = std::min(y0, P.centroid[2 * c + 1]), y1 = std::max(y1, P.centroid[2 * c + 1]);
+        }
+        const double sx = 65535.0 / std::max(x1 - x0, 1e-300), sy = 65535.0 / std::max(y1 - y0, 1e-300);
+        auto spread = [](uint32_t v) {  // 16 bits -> even bits of 32
+            v &= 0xffffu;
+            v = (v | (v << 8)) & 0x00ff00ffu;
+            v = (v | (v << 4)) & 0x0f0f0f0fu;
+            v = (v | (v << 2)) & 0x33333333u;
+            v = (v | (v << 1)) & 0x55555555u;
+            return v;
+        };
+        std::vector<uint32_t> key(nc);
+        for (int c = 0; c < nc; ++c) {
+            const uint32_t qx = (uint32_t)std::lround((P.centroid[2 * c] - x0) * sx);
+            const uint32_t qy = (uint32_t)std::lround((P.centroid[2 * c + 1] - y0) * sy);
+            key[c] = spread(qx) | (spread(qy) << 1);
+        }
+        for (auto &m : members)
+            std::stable_sort(m.begin(), m.end(), [&](int a, int b) { return key[a] < key[b]; });
+    }
     // launch shapes: 64, 128 and 256 lanes per workgroup (one shape when shots fill a block)
     for (int lanes : {kLanesTarget, 2 * kLanesTarget, kBlock}) {
         const int cpb = std::max(1, lanes / P.S);
