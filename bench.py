@@ -30,14 +30,14 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per stage launch of the headline workload (k = 2, float32, one shot) from the
 # rocprofv3 FETCH_SIZE / WRITE_SIZE counters, each scaled by what the counter reads for a plain
-# elementwise kernel of known size (factors 2.0 and 1.0); valid only for the kernel sources with
-# this digest (otherwise the traffic is reported as null).
+# elementwise kernel of known size (factors 2.0 and 1.0); valid only for the kernel and host-plan
+# sources with this digest (otherwise the traffic is reported as null).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "d1f95c3613f59be4331030b84acff84f0d9a92e065f9447614ae364456e3195d",
+    "sources_sha256": "b4bc29d8357e20db6ae4a2ba50d400ccf1855708240bb04f7291209201120db7",
     "config": (2, "f32", 1),
-    "bytes_per_launch": (2.0 * 14767.4 + 1.0 * 22307.7) * 1024,
+    "bytes_per_launch": (2.0 * 14774.5 + 1.0 * 22913.8) * 1024,
 }
-STAGE_SOURCES = ("kernels.hip", "stage_common.h", "device.h")
+STAGE_SOURCES = ("kernels.hip", "stage_common.h", "device.h", "plan.cpp", "api.cpp")
 
 
 def stage_sources_digest():
