@@ -22,6 +22,8 @@
  *     K_F U_F = -K_FT U_T, then M dU_T/dt = F_T - K_T U_T - K_TF U_F.
  *   - ERK(s) Butcher tableaux of eq. ERK (s = 2, 3, 4).
  *   - Energy of Sec. 5.1 (cell unknowns only).
+ *   - Point sources: load vectors (eq. rhs) of a point force with a Ricker time factor; the
+ *     time factor is parity unpinned (no values in the paper for a time-domain wavelet).
  * Bases (Sec. 3.3 "local modal basis composed of monomials centred at the
  * barycentre"): graded monomials ((x-xT)/hT)^a ((y-yT)/hT)^b, degree-major and,
  * within a degree, decreasing power of x, orthonormalised in L2(T) by the
@@ -633,7 +635,10 @@ void orc_set_dense_load(orc_t *o, int nterm, const double *g, const double *omeg
     }
 }
 
-/* Ricker wavelet (second derivative of a Gaussian) with peak frequency f0, delay t0 */
+/* Ricker wavelet (second derivative of a Gaussian) with peak frequency f0, delay t0, as the time
+ * factor of a point force.  Parity unpinned: the paper's "Ricker" is a spatial initial field
+ * (eq. ricker_ic), it prints no values for a time-domain wavelet; the formula is the textbook
+ * (1 - 2a^2) exp(-a^2), a = pi f0 (t - t0). */
 static double ricker(double t, double f0, double t0)
 {
     double a = M_PI * f0 * (t - t0);
