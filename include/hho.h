@@ -162,10 +162,11 @@ hho_status hho_energy(hho_ctx *ctx, double *E);
 hho_status hho_energy_history(hho_ctx *ctx, int32_t shot, double *out);
 
 /* Launch shape.  The stage kernel can run with workgroups of 64, 128 or 256 lanes (one lane per
- * cell and shot).  hho_autotune times one stage in every shape on the current state, keeps the
- * fastest and returns its lane count; it changes no state.  hho_set_launch selects a shape by
- * lane count (ARG if none matches).  Results do not depend on the shape except for the summation
- * order of energies. */
+ * cell and shot), and can store its outputs with the default or the non-temporal (streaming)
+ * cache policy.  hho_autotune times one stage in every shape and policy on the current state,
+ * keeps the fastest and returns its lane count; it changes no state.  hho_set_launch selects a
+ * shape by lane count (ARG if none matches) and keeps the policy.  Results do not depend on the
+ * shape or the policy except for the summation order of energies. */
 hho_status hho_autotune(hho_ctx *ctx, int32_t *lanes);
 hho_status hho_set_launch(hho_ctx *ctx, int32_t lanes);
 

@@ -53,6 +53,13 @@ hho_status hho_inspect_arrays(const hho_inspect *p, double *tables, int32_t *gro
  *   (the stress mass matrix of eq. mass); padding cells hold zeros. */
 hho_status hho_inspect_grad_coefs(const hho_inspect *p, double *gm);
 
+/* Coefficients the stage kernel uses for ERK(stages) of eq. ERK (stages 2, 3, 4; ARG otherwise),
+ * coefs[stages][9] = c, cY, ck, cb, qa, qb, cd, q_write, q_read.  The stage buffers hold increments
+ * D_i = Y_{i+1} - U^n: D_i = cY D_{i-1} + ck dt k_i before the last stage (with q_write, also
+ * Q = qa D_{i-1} + qb D_i); the last stage forms U^{n+1} = U^n + [q_read] Q + cd D_{s-2} + cb dt k_s.
+ * c is the stage node (stage time t_n + c dt). */
+hho_status hho_inspect_erk(int32_t stages, double *coefs);
+
 #ifdef __cplusplus
 }
 #endif

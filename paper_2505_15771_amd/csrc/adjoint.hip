@@ -41,6 +41,30 @@ __device__ __forceinline__ void add_grad(double *g, long long LT, long long lane
     g[2 * LT + lane] += g2;
 }
 
+// lambda and the running sum of L^T mu of one lane (the sum starts at zero on the first
+// adjoint stage of a step)
+template <int ND, typename R>
+__device__ __forceinline__ void load_lambda(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, R *lam, R *lac) {
+    if (a.first) {
+#pragma unroll
+        for (int r = 0; r < ND; ++r) {
+            lam[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
+            lac[r] = R(0);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < ND; ++r) {
+            lam[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
+            lac[r] = bld<R>(B.r, boff, B.acc + r * B.rowb);
+        }
+    }
+}
+
+// Read lambda, the running sum and the gradient accumulators at the start of the stage (their
+// latency then overlaps the residual) where registers allow; otherwise after the residual.
+template <int K, typename R>
+constexpr bool kEarlyLambda = sizeof(R) == 4 && K <= 2;
+
 // ------------------------------------------------------------------------- fluid cells
 template <int K, int NF, typename R>
 __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
@@ -68,6 +92,12 @@ __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<
     const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
     const R kap = bld<R>(B.r, coff, B.mat + kStiff * B.crowb);
     const R irho = bld<R>(B.r, coff, B.mat + kInvRho * B.crowb);
+    R lam[3 * N], lac[3 * N];
+    double g0 = 0, g1 = 0;
+    if constexpr (kEarlyLambda<K, R>) {
+        load_lambda<3 * N, R>(a, B, boff, lam, lac);
+        g0 = a.gacc[lane], g1 = a.gacc[LT + lane];
+    }
     // stored forward data of this stage: primal rows of Y, the derivative k, the face values
     R yp[N], yf[NF][F];
     double wk_p = 0, wk_m = 0;
@@ -160,14 +190,11 @@ __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<
         yb[N + b] = -rmx[b];
         yb[2 * N + b] = -rmy[b];
     }
-    // epilogue: every load before the first store
-    R lam[3 * N], lac[3 * N];
-#pragma unroll
-    for (int r = 0; r < 3 * N; ++r) {
-        lam[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
-        lac[r] = a.first ? R(0) : bld<R>(B.r, boff, B.acc + r * B.rowb);
+    if constexpr (!kEarlyLambda<K, R>) {
+        // every load before the first store
+        load_lambda<3 * N, R>(a, B, boff, lam, lac);
+        g0 = a.gacc[lane], g1 = a.gacc[LT + lane];
     }
-    double g0 = a.gacc[lane], g1 = a.gacc[LT + lane];
     g0 -= gmv(a, 0, ic) * wk_p + wk_m + gmv(a, 2, ic) * stab;
     g1 -= gmv(a, 1, ic) * wk_p + gmv(a, 3, ic) * stab;
     a.gacc[lane] = g0;
@@ -249,6 +276,12 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
     const R l2m = bld<R>(B.r, coff, B.mat + kStiff * B.crowb);
     const R lam_ = bld<R>(B.r, coff, B.mat + kLam * B.crowb);
     const R tmu = bld<R>(B.r, coff, B.mat + kTwoMu * B.crowb);
+    R lam[5 * N], lac[5 * N];
+    double g0 = 0, g1 = 0, g2 = 0;
+    if constexpr (kEarlyLambda<K, R>) {
+        load_lambda<5 * N, R>(a, B, boff, lam, lac);
+        g0 = a.gacc[lane], g1 = a.gacc[LT + lane], g2 = a.gacc[2 * LT + lane];
+    }
     R yx[N], yy[N], yf[NF][2][F];
     double wk_v = 0, P11 = 0, P12 = 0, P21 = 0, P22 = 0, P33 = 0;
 #pragma unroll
@@ -382,13 +415,11 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
         yb[3 * N + b] = -rs2[b];
         yb[4 * N + b] = -rs3[b];
     }
-    R lam[5 * N], lac[5 * N];
-#pragma unroll
-    for (int r = 0; r < 5 * N; ++r) {
-        lam[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
-        lac[r] = a.first ? R(0) : bld<R>(B.r, boff, B.acc + r * B.rowb);
+    if constexpr (!kEarlyLambda<K, R>) {
+        // every load before the first store
+        load_lambda<5 * N, R>(a, B, boff, lam, lac);
+        g0 = a.gacc[lane], g1 = a.gacc[LT + lane], g2 = a.gacc[2 * LT + lane];
     }
-    double g0 = a.gacc[lane], g1 = a.gacc[LT + lane], g2 = a.gacc[2 * LT + lane];
     g0 -= wk_v + gmv(a, 0, ic) * stab;
     g1 -= gmv(a, 3, ic) * (P11 + P12 + P21 + P22) + gmv(a, 1, ic) * stab;
     g2 -= gmv(a, 4, ic) * (P11 + P22) + gmv(a, 5, ic) * (P12 + P21) + gmv(a, 6, ic) * P33 + gmv(a, 2, ic) * stab;

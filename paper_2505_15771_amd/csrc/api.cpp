@@ -92,6 +92,9 @@ struct hho_ctx {
     hipGraphExec_t gexec = nullptr;
     unsigned version = 1, graph_version = 0;  // graph is valid when graph_version == version
     double cfl_dt = 0.0;                       // CFL-limited time step at factor 1
+    // Stage outputs stored with the non-temporal cache policy (chosen by hho_autotune: faster
+    // for some large working sets, slower when the stage data stays in the last-level cache).
+    int nt_stores = 0;
     AdjWork adj;
 };
 
@@ -287,6 +290,7 @@ StageArgs<R> base_args(hho_ctx *ctx) {
     a.o_link = arena_off(ctx->arena, ctx->link);
     a.o_c0 = arena_off(ctx->arena, ctx->c0);
     a.o_mat = arena_off(ctx->arena, ctx->mat);
+    a.nt_stores = ctx->nt_stores;
     return a;
 }
 
@@ -552,7 +556,6 @@ hho_status capture_batch(hho_batch *b, int steps, hipGraphExec_t *out) {
 // traces and writes only scratch stage buffers) and keep the fastest.
 template <int K, typename R>
 hho_status autotune_shape(hho_ctx *ctx) {
-    if (ctx->launch.size() < 2) return HHO_OK;
     if (!ctx->traces_valid) {
         hho_status s = compute_traces<K, R>(ctx);
         if (s != HHO_OK) return s;
@@ -562,40 +565,46 @@ hho_status autotune_shape(hho_ctx *ctx) {
     hipEvent_t e0, e1;
     HCK(hipEventCreate(&e0));
     HCK(hipEventCreate(&e1));
-    const int keep = ctx->shape;
-    int best = keep;
+    const int keep = ctx->shape, keep_nt = ctx->nt_stores;
+    int best = keep, best_nt = keep_nt;
     float best_ms = 1e30f;
     hho_status st = HHO_OK;
-    for (size_t sh = 0; sh < ctx->launch.size() && st == HHO_OK; ++sh) {
-        ctx->shape = (int)sh;
-        StageArgs<R> a = base_args<R>(ctx);
-        a.U = (R *)ctx->U;
-        a.acc = (R *)ctx->acc;
-        a.Yin = (const R *)ctx->U;
-        a.Yout = (R *)ctx->Y[0];
-        a.Tin = (const R *)ctx->T[ctx->tcur];
-        a.Tout = (R *)ctx->T[(ctx->tcur + 1) % 3];
-        a.first = 1;
-        a.last = 0;
-        a.cU = R(1);
-        set_stage_offsets(ctx, a);
-        float ms = 0.f;
-        for (int rep = 0; rep < 8 && st == HHO_OK; ++rep) {
-            if (rep == 3 && hipEventRecord(e0, ctx->stream) != hipSuccess) st = HHO_ERR_DEVICE;
-            if (launch_stage<K, R>(a, ctx->n_blocks(), ctx->stream) != hipSuccess) st = HHO_ERR_DEVICE;
-        }
-        if (st == HHO_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            st = HHO_ERR_DEVICE;
-        if (st == HHO_OK && ms < best_ms) {
-            best_ms = ms;
-            best = (int)sh;
+    for (int nt = 0; nt < 2 && st == HHO_OK; ++nt) {
+        ctx->nt_stores = nt;
+        for (size_t sh = 0; sh < ctx->launch.size() && st == HHO_OK; ++sh) {
+            ctx->shape = (int)sh;
+            StageArgs<R> a = base_args<R>(ctx);
+            a.U = (R *)ctx->U;
+            a.acc = (R *)ctx->acc;
+            a.Yin = (const R *)ctx->U;
+            a.Yout = (R *)ctx->Y[0];
+            a.Tin = (const R *)ctx->T[ctx->tcur];
+            a.Tout = (R *)ctx->T[(ctx->tcur + 1) % 3];
+            a.first = 1;
+            a.last = 0;
+            a.cU = R(1);
+            set_stage_offsets(ctx, a);
+            float ms = 0.f;
+            for (int rep = 0; rep < 8 && st == HHO_OK; ++rep) {
+                if (rep == 3 && hipEventRecord(e0, ctx->stream) != hipSuccess) st = HHO_ERR_DEVICE;
+                if (launch_stage<K, R>(a, ctx->n_blocks(), ctx->stream) != hipSuccess) st = HHO_ERR_DEVICE;
+            }
+            if (st == HHO_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess ||
+                                 hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                st = HHO_ERR_DEVICE;
+            if (st == HHO_OK && ms < best_ms) {
+                best_ms = ms;
+                best = (int)sh;
+                best_nt = nt;
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx->shape = best;
-    if (best != keep) ctx->version++;
+    ctx->nt_stores = best_nt;
+    if (best != keep || best_nt != keep_nt) ctx->version++;
     if (st != HHO_OK) ctx->err = "autotune: kernel launch or timing failed";
     return st;
 }
@@ -1443,6 +1452,17 @@ hho_status hho_inspect_arrays(const hho_inspect *p, double *tables, int32_t *gro
     if (c0) std::copy(P.c0.begin(), P.c0.end(), c0);
     if (mat) std::copy(P.mat.begin(), P.mat.end(), mat);
     if (ic_of_cell) std::copy(P.ic_of_cell.begin(), P.ic_of_cell.end(), ic_of_cell);
+    return HHO_OK;
+}
+
+hho_status hho_inspect_erk(int32_t stages, double *coefs) {
+    std::vector<StageCoef> co;
+    if (!coefs || !erk_coefficients(stages, co)) return HHO_ERR_ARG;
+    for (int i = 0; i < stages; ++i) {
+        const StageCoef &q = co[i];
+        const double v[9] = {q.c, q.cY, q.ck, q.cb, q.qa, q.qb, q.cd, (double)q.q_write, (double)q.q_read};
+        std::memcpy(coefs + 9 * i, v, sizeof(v));
+    }
     return HHO_OK;
 }
 

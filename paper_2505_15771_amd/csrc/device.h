@@ -65,6 +65,7 @@ struct StageArgs {
     int q_write, q_read;
     R *Yq;
     int first, last;
+    int nt_stores;        // stage outputs with the non-temporal cache policy (large working sets)
     // point sources
     const int32_t *src_first;  // [n_ic], -1 = none
     const SrcDev *src;

@@ -84,7 +84,7 @@ __device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> 
 // residual.  out = the new stage state (Y_{i+1} or U^{n+1}), from which the outgoing traces are
 // formed.  Every load is issued before the first store: the arrays share one buffer resource,
 // so the compiler cannot move a load above an earlier store.
-template <int ND, typename R, bool KEEP>
+template <int ND, typename R, bool KEEP, int POL>
 __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, const R *y,
                                           const R *kv, R *out, const R *uk, const R *dk) {
     const R dt = R(uni(a.clock)->dt);
@@ -120,8 +120,8 @@ __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
             const R d = a.cY * din[r] + ckdt * kv[r];
-            bst(B.r, boff, B.yout + r * B.rowb, d);
-            if (a.q_write) bst(B.r, boff, B.yq + r * B.rowb, a.qa * din[r] + a.qb * d);
+            bst<POL>(B.r, boff, B.yout + r * B.rowb, d);
+            if (a.q_write) bst<POL>(B.r, boff, B.yq + r * B.rowb, a.qa * din[r] + a.qb * d);
             out[r] = u[r] + d;
         }
     } else {
@@ -137,7 +137,7 @@ __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
             out[r] = u[r] + (q[r] + a.cd * din[r] + cb * kv[r]);
-            bst(B.r, boff, B.u + r * B.rowb, out[r]);
+            bst<POL>(B.r, boff, B.u + r * B.rowb, out[r]);
         }
     }
 }
@@ -165,7 +165,7 @@ __device__ __forceinline__ void store_recompute(const StageArgs<R> &a, const int
 }
 
 // ------------------------------------------------------------------------- fluid cells
-template <int K, int NF, typename R, bool STORE>
+template <int K, int NF, typename R, bool STORE, int POL>
 __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
                                             const LaneInfo &L, double *energy) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
@@ -276,10 +276,10 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
         kv[N + b] = irho * rmx[b];
         kv[2 * N + b] = irho * rmy[b];
     }
-    rk_update<3 * N, R, KEEP>(a, B, boff, y, kv, nw, uk, dk);
+    rk_update<3 * N, R, KEEP, POL>(a, B, boff, y, kv, nw, uk, dk);
     const R *np = nw, *nmx = nw + N, *nmy = nw + 2 * N;
     if (STORE) store_recompute<K, NF, 3 * N, R, NF, 1>(a, lk, boff, y, kv, fv);
-    fluid_traces<K, NF, R>(a, B, tb, nF, lk, shot, np, nmx, nmy, tau);
+    fluid_traces<K, NF, R, POL>(a, B, tb, nF, lk, shot, np, nmx, nmy, tau);
     if (a.last) {
         if (energy) {
             double sp = 0, sm = 0;
@@ -309,7 +309,7 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
 }
 
 // ------------------------------------------------------------------------- solid cells
-template <int K, int NF, typename R, bool STORE>
+template <int K, int NF, typename R, bool STORE, int POL>
 __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
                                             const LaneInfo &L, double *energy) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
@@ -462,10 +462,10 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
         kv[3 * N + b] = lam * rs1[b] + l2m * rs2[b];
         kv[4 * N + b] = tmu * rs3[b];
     }
-    rk_update<5 * N, R, KEEP>(a, B, boff, y, kv, nw, uk, dk);
+    rk_update<5 * N, R, KEEP, POL>(a, B, boff, y, kv, nw, uk, dk);
     const R *nvx = nw, *nvy = nw + N, *ns1 = nw + 2 * N, *ns2 = nw + 3 * N, *ns3 = nw + 4 * N;
     if (STORE) store_recompute<K, NF, 5 * N, R, NF, 2>(a, lk, boff, y, kv, fv);
-    solid_traces<K, NF, R>(a, B, tb, nF, lk, shot, nvx, nvy, ns1, ns2, ns3, tau, itau);
+    solid_traces<K, NF, R, POL>(a, B, tb, nF, lk, shot, nvx, nvy, ns1, ns2, ns3, tau, itau);
     if (a.last) {
         if (energy) {
             const double ca = a.emat[(long long)1 * nic + ic], cb = a.emat[(long long)2 * nic + ic];
@@ -500,17 +500,17 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
     }
 }
 
-template <int K, int NF, typename R, bool STORE>
+template <int K, int NF, typename R, bool STORE, int POL>
 __device__ __forceinline__ void stage_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L, double *e) {
     const HHO_CONST R *tb = uni(a.tab) + G.tab_off;
     const Bufs<R> B = make_bufs(a);
     if (G.medium == kFluid)
-        fluid_stage<K, NF, R, STORE>(a, B, tb, G.nF, L, e);
+        fluid_stage<K, NF, R, STORE, POL>(a, B, tb, G.nF, L, e);
     else
-        solid_stage<K, NF, R, STORE>(a, B, tb, G.nF, L, e);
+        solid_stage<K, NF, R, STORE, POL>(a, B, tb, G.nF, L, e);
 }
 
-template <int K, typename R, bool STORE>
+template <int K, typename R, bool STORE, int POL>
 __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<R> a) {
     if (a.last && a.clock_next && blockIdx.x == 0 && threadIdx.x == 0) {
         Clock c = *a.clock;
@@ -524,8 +524,8 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<R> a) {
     double *ep = want_e ? &e : nullptr;
     if (L.active) {
         // faces beyond a cell's count carry link -1 and are skipped like boundary faces
-        if (G.nF <= 4) stage_body<K, 4, R, STORE>(a, G, L, ep);
-        else stage_body<K, kMaxFaces, R, STORE>(a, G, L, ep);
+        if (G.nF <= 4) stage_body<K, 4, R, STORE, POL>(a, G, L, ep);
+        else stage_body<K, kMaxFaces, R, STORE, POL>(a, G, L, ep);
     }
     if (want_e) block_energy(e, a.S, a.cpb, a.e_part);
 }
@@ -637,13 +637,16 @@ __global__ void gather_kernel(const R *state, const int64_t *map, long long n, i
 
 template <int K, typename R>
 hipError_t launch_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
-    hipLaunchKernelGGL((stage_kernel<K, R, false>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    if (a.nt_stores)
+        hipLaunchKernelGGL((stage_kernel<K, R, false, kNonTemporal>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    else
+        hipLaunchKernelGGL((stage_kernel<K, R, false, 0>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     return hipGetLastError();
 }
 
 template <int K, typename R>
 hipError_t launch_stage_store(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
-    hipLaunchKernelGGL((stage_kernel<K, R, true>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    hipLaunchKernelGGL((stage_kernel<K, R, true, 0>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     return hipGetLastError();
 }
 

@@ -51,12 +51,18 @@ template <>
 __device__ __forceinline__ double bld<double>(Rsrc r, unsigned voff, unsigned soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
+// Stores take a cache policy POL: 0 = default, kNonTemporal = streaming (used when the working
+// set of a context is larger than the last-level cache, so that stage outputs go through to
+// memory while the launch runs instead of in one write-back at its end).
+constexpr int kNonTemporal = 2;
+template <int POL = 0>
 __device__ __forceinline__ void bst(Rsrc r, unsigned voff, unsigned soff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, POL);
 }
+template <int POL = 0>
 __device__ __forceinline__ void bst(Rsrc r, unsigned voff, unsigned soff, double v) {
     typedef unsigned u2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, POL);
 }
 
 // D contiguous dwords of one lane in the widest buffer accesses (16, 12, 8, 4 bytes).
@@ -79,20 +85,20 @@ __device__ __forceinline__ void bld_dw(Rsrc r, unsigned voff, unsigned soff, uns
         w[O] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)(soff + 4 * O), 0);
     }
 }
-template <int D, int O = 0>
+template <int D, int O = 0, int POL = 0>
 __device__ __forceinline__ void bst_dw(Rsrc r, unsigned voff, unsigned soff, const unsigned *w) {
     if constexpr (D - O >= 4) {
         const Dw4 v = {w[O], w[O + 1], w[O + 2], w[O + 3]};
-        __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)(soff + 4 * O), 0);
-        bst_dw<D, O + 4>(r, voff, soff, w);
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)(soff + 4 * O), POL);
+        bst_dw<D, O + 4, POL>(r, voff, soff, w);
     } else if constexpr (D - O == 3) {
         const Dw3 v = {w[O], w[O + 1], w[O + 2]};
-        __builtin_amdgcn_raw_buffer_store_b96(v, r, (int)voff, (int)(soff + 4 * O), 0);
+        __builtin_amdgcn_raw_buffer_store_b96(v, r, (int)voff, (int)(soff + 4 * O), POL);
     } else if constexpr (D - O == 2) {
         const Dw2 v = {w[O], w[O + 1]};
-        __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)(soff + 4 * O), 0);
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)(soff + 4 * O), POL);
     } else if constexpr (D - O == 1) {
-        __builtin_amdgcn_raw_buffer_store_b32(w[O], r, (int)voff, (int)(soff + 4 * O), 0);
+        __builtin_amdgcn_raw_buffer_store_b32(w[O], r, (int)voff, (int)(soff + 4 * O), POL);
     }
 }
 // F contiguous reals of one lane: v[i] at byte soff + i sizeof(R) (plus the lane's voff).
@@ -107,7 +113,7 @@ __device__ __forceinline__ void bldv(Rsrc r, unsigned voff, unsigned soff, R *v)
         else v[i] = __builtin_bit_cast(R, ((unsigned long long)w[2 * i + 1] << 32) | w[2 * i]);
     }
 }
-template <int F, typename R>
+template <int F, typename R, int POL = 0>
 __device__ __forceinline__ void bstv(Rsrc r, unsigned voff, unsigned soff, const R *v) {
     constexpr int D = F * (int)sizeof(R) / 4;
     unsigned w[D];
@@ -121,7 +127,7 @@ __device__ __forceinline__ void bstv(Rsrc r, unsigned voff, unsigned soff, const
             w[2 * i + 1] = (unsigned)(b >> 32);
         }
     }
-    bst_dw<D>(r, voff, soff, w);
+    bst_dw<D, 0, POL>(r, voff, soff, w);
 }
 
 // Buffer addressing of one stage launch (uniform): one resource over the arena, and the
@@ -258,7 +264,7 @@ __device__ __forceinline__ void load_incoming(const Bufs<R> &B, int medium, int 
 }
 
 // ------------------------------------------------------------------------- outgoing traces
-template <int K, int NF, typename R>
+template <int K, int NF, typename R, int POL = 0>
 __device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
                                              const int *lk, int shot, const R *p, const R *mx, const R *my, R tau) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
@@ -286,11 +292,11 @@ __device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const Bufs<R
         R o[F];
 #pragma unroll
         for (int i = 0; i < F; ++i) o[i] = sgn<R>(i) * r[i];
-        bstv<F, R>(B.r, F * nb, B.tout + (jn * 2) * F * B.rowb, o);
+        bstv<F, R, POL>(B.r, F * nb, B.tout + (jn * 2) * F * B.rowb, o);
     }
 }
 
-template <int K, int NF, typename R>
+template <int K, int NF, typename R, int POL = 0>
 __device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
                                              const int *lk, int shot, const R *vx, const R *vy, const R *s1, const R *s2,
                                              const R *s3, R tau, R itau) {
@@ -333,8 +339,8 @@ __device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R
             ox[i] = sgn<R>(i) * w * rx[i];
             oy[i] = sgn<R>(i) * w * ry[i];
         }
-        bstv<F, R>(B.r, F * nb, B.tout + (jn * 2) * F * B.rowb, ox);
-        bstv<F, R>(B.r, F * nb, B.tout + (jn * 2 + 1) * F * B.rowb, oy);
+        bstv<F, R, POL>(B.r, F * nb, B.tout + (jn * 2) * F * B.rowb, ox);
+        bstv<F, R, POL>(B.r, F * nb, B.tout + (jn * 2 + 1) * F * B.rowb, oy);
     }
 }
 

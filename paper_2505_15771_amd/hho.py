@@ -70,6 +70,7 @@ EXPORTS = {
     "hho_inspect_sizes": (C.c_int, [C.c_void_p, C.c_void_p]),
     "hho_inspect_arrays": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
     "hho_inspect_grad_coefs": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "hho_inspect_erk": (C.c_int, [C.c_int32, C.c_void_p]),
 }
 
 _lib = None
@@ -290,6 +291,15 @@ class Engine:
         E = np.zeros(max(self.last_steps, 1))
         self._call(self.lib.hho_energy_history, int(shot), _ptr(E))
         return E[:self.last_steps]
+
+
+def erk_coefficients(stages):
+    """Stage-combine coefficients of the stage kernel (hho_inspect_erk): [stages, 9] array of
+    c, cY, ck, cb, qa, qb, cd, q_write, q_read."""
+    lib = load_library()
+    out = np.zeros((stages, 9))
+    _check(lib, lib.hho_inspect_erk(int(stages), _ptr(out)), None)
+    return out
 
 
 class Inspect:

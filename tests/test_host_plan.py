@@ -130,3 +130,34 @@ def test_plan_gradient_terms(k, stab_speed):
     o.grad_terms(Y, kk, mu, ref)
     got = kernel_model.grad_terms(ins, mesh, Y, kk, mu)
     assert np.linalg.norm(got - ref) < 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("s", [2, 3, 4])
+def test_erk_increment_form_reproduces_tableau(s):
+    """The stage combine as the kernel performs it (increments D_i, the partial sum Q, the last
+    stage's combination), driven by the host's coefficients, applied to the linear system
+    y' = A y: one step equals the Taylor polynomial sum_{j<=s} (dt A)^j / j! y (the stability
+    polynomial of the tableaux of eq. ERK, all of order s), and the stage nodes are the tableau's."""
+    from math import factorial
+    from paper_2505_15771_amd.hho import erk_coefficients
+    co = erk_coefficients(s)
+    rng = np.random.default_rng(s)
+    A = rng.standard_normal((5, 5))
+    U = rng.standard_normal(5)
+    dt = 0.1
+    D_prev, Q = None, None
+    for i in range(s):
+        c, cY, ck, cb, qa, qb, cd, qw, qr = co[i]
+        Y = U if i == 0 else U + D_prev
+        k = A @ Y
+        if i < s - 1:
+            D = (cY * D_prev if i > 0 else 0.0) + ck * dt * k
+            if qw:
+                Q = qa * D_prev + qb * D
+            D_prev = D
+        else:
+            Unew = U + ((Q if qr else 0.0) + cd * D_prev + cb * dt * k)
+    ref = sum(np.linalg.matrix_power(dt * A, j) @ U / factorial(j) for j in range(s + 1))
+    assert np.linalg.norm(Unew - ref) < 1e-14 * np.linalg.norm(ref)
+    nodes = {2: [0, 0.5], 3: [0, 0.5, 1.0], 4: [0, 0.5, 0.5, 1.0]}[s]
+    assert np.allclose(co[:, 0], nodes)
