@@ -33,9 +33,9 @@ HBM_PEAK_GBS = 8000.0
 # elementwise kernel of known size (factors 2.0 and 1.0); valid only for the kernel and host-plan
 # sources with this digest (otherwise the traffic is reported as null).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "b4bc29d8357e20db6ae4a2ba50d400ccf1855708240bb04f7291209201120db7",
+    "sources_sha256": "2c525b11a612192af5413f26986d31fc140895273efcd15c837b65dfc2670a92",
     "config": (2, "f32", 1),
-    "bytes_per_launch": (2.0 * 14774.5 + 1.0 * 22913.8) * 1024,
+    "bytes_per_launch": (2.0 * 14750.2 + 1.0 * 22913.7) * 1024,
 }
 STAGE_SOURCES = ("kernels.hip", "stage_common.h", "device.h", "plan.cpp", "api.cpp")
 
@@ -86,6 +86,7 @@ def run_variant(mesh, k, dtype, shots, steps, warmup):
     for sh in range(shots):
         eng.set_state(1e-3 * rng.standard_normal(eng.n_dof), shot=sh)
         eng.set_sources(sh, [[0.5, 0.25 + 0.01 * sh]], [[0.0, 1.0]], 10.0, 0.12, 1.0)
+    eng.autotune()  # launch shape and store cache policy (outside the timed region)
     h = 1.0 / 256
     dt = 0.5 * min(CFL_SQUARE[k], CFL_TRI[k]) * h / M.max_wave_speed(mesh)
     eng.erk_step(0.0, dt, warmup)
@@ -158,6 +159,7 @@ def run_basin(dtype, steps=100, warmup=5):
     eng.set_receivers(np.stack([np.linspace(1000.0, 19000.0, 64), np.full(64, -0.25 * h0)], axis=1),
                       np.ones(64, np.int32))
     dt = eng.dt_cfl(0.5)
+    eng.autotune()
     eng.erk_step(0.0, dt, warmup)
     eng.synchronize()
     st = torch.cuda.current_stream()
@@ -188,6 +190,7 @@ def run_batch(steps=200, warmup=4):
         for sh in range(4):
             e.set_sources(sh, [pos[sh]], [[0.0, 1.0]], 10.0, 0.12, 1.0)
         dts.append(e.dt_cfl(0.5))
+        e.autotune()
         engines.append(e)
     b = Batch(engines)
     b.erk_step([0.0] * len(engines), dts, warmup)
