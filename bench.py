@@ -297,6 +297,15 @@ def main():
         print("workload", json.dumps(v), file=sys.stderr, flush=True)
         workloads.append(v)
     cpu = cpu_baseline(mesh, args.k) if args.cpu_baseline else None
+    # speed-ups over float64 single-shot stepping of the same workload on the same GPU
+    speedups = {}
+    base = [v for v in variants if (v["k"], v["dtype"], v["shots"]) == (args.k, "f64", 1)]
+    if base:
+        ref = base[0]["value"]
+        speedups["%s_%dshot_vs_f64_1shot" % (head["dtype"], args.shots)] = head["value"] / ref
+        for v in variants:
+            if v["k"] == args.k and v is not base[0]:
+                speedups["%s_%dshot_vs_f64_1shot" % (v["dtype"], v["shots"])] = v["value"] / ref
     traffic = None
     if (stage_sources_digest() == MEASURED_TRAFFIC["sources_sha256"]
             and (args.k, args.dtype, args.shots) == MEASURED_TRAFFIC["config"]):
@@ -323,6 +332,7 @@ def main():
                      "traffic_unit": "HBM bytes per launch"},
         "cpu_baseline": cpu,
         "variants": variants,
+        "speedups": speedups,
         "adjoint": adjoint,
         "workloads": workloads,
     }

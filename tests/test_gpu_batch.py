@@ -160,3 +160,28 @@ def test_full_size_batch_sampled():
     b.close()
     for e in engines:
         e.close()
+
+
+@pytest.mark.parametrize("lanes", [60, 125, 255])
+def test_five_shots_every_launch_shape(lanes):
+    """Five shots (lanes per workgroup 60, 125 or 255: cells of a workgroup 12, 25 or 51, so the
+    last workgroup of every group is ragged) on a hanging-node hybrid mesh, k = 2, float64, with
+    different initial states per shot; every shot against the oracle."""
+    from oracle import Oracle
+    from paper_2505_15771_amd import Engine
+    say("case: 5 shots, %d lanes per workgroup" % lanes)
+    mesh = M.hanging_square(9, seed=13)
+    o = Oracle(mesh, 2)
+    e = Engine(mesh, 2, n_shots=5)
+    e.set_launch(lanes)
+    dt = e.dt_cfl(0.5)
+    refs = []
+    for sh in range(5):
+        U0 = np.random.default_rng(900 + sh).standard_normal(o.ndof)
+        e.set_state(U0, shot=sh)
+        refs.append(o.erk(U0, 0.0, dt, 9))
+    e.erk_step(0.0, dt, 9)
+    for sh in range(5):
+        err = rel(e.get_state(sh), refs[sh])
+        say("shot", sh, err)
+        assert err < 1e-12
