@@ -60,6 +60,9 @@ hho_status hho_inspect_grad_coefs(const hho_inspect *p, double *gm);
  * c is the stage node (stage time t_n + c dt). */
 hho_status hho_inspect_erk(int32_t stages, double *coefs);
 
+/* The time step of hho_dt_cfl for ERK(stages) (2, 3 or 4) on the inspected plan. */
+hho_status hho_inspect_dt_cfl(const hho_inspect *p, int32_t stages, double factor, double *dt);
+
 #ifdef __cplusplus
 }
 #endif

@@ -639,7 +639,7 @@ hho_status rebuild_sources(hho_ctx *ctx) {
 // CFL* from Table tab::ratio_geo (triangles, squares, hexagons; polygons with five or more faces
 // use the hexagon value), c_T the largest wave speed of the cell and h_T the side of the
 // generating square (sqrt(area) for quadrilaterals and polygons, sqrt(2 area) for triangles).
-double cfl_time_step(const Plan &P, const hho_mesh *mesh, int stages) {
+double cfl_time_step(const Plan &P, int stages) {
     static const double table[3][3][3] = {
         // s = 2: triangle, square, hexagon for k = 1, 2, 3
         {{0.191, 0.106, 0.072}, {0.205, 0.099, 0.063}, {0.264, 0.136, 0.082}},
@@ -653,8 +653,9 @@ double cfl_time_step(const Plan &P, const hho_mesh *mesh, int stages) {
         const int nF = P.cell_ptr[c + 1] - P.cell_ptr[c];
         const int shape = nF == 3 ? 0 : (nF == 4 ? 1 : 2);
         const double h = std::sqrt(P.area[c] * (nF == 3 ? 2.0 : 1.0));
-        const double speed = P.medium[c] == kFluid ? mesh->a[c]
-                                                   : std::sqrt((mesh->a[c] + 2.0 * mesh->b[c]) / mesh->rho[c]);
+        // c (fluid: kappa / rho = c^2) or c_P (solid: (lambda + 2 mu) / rho)
+        const int ic = P.ic_of_cell[c];
+        const double speed = std::sqrt(P.mat[(size_t)kStiff * P.n_ic + ic] * P.mat[(size_t)kInvRho * P.n_ic + ic]);
         dt = std::min(dt, table[stages - 2][shape][P.k - 1] * h / speed);
     }
     return dt;
@@ -902,7 +903,7 @@ hho_status hho_setup(const hho_mesh *mesh, const hho_params *prm, hho_ctx **out)
         ctx->max_blocks = std::max(ctx->max_blocks, d.n_blocks);
     }
     if ((s = dalloc(ctx, (void **)&ctx->e_part, (size_t)ctx->max_blocks * P.S * sizeof(double)))) return fail(s);
-    ctx->cfl_dt = cfl_time_step(P, mesh, prm->rk_stages);
+    ctx->cfl_dt = cfl_time_step(P, prm->rk_stages);
     {
         hipError_t e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
         if (e != hipSuccess) {
@@ -1452,6 +1453,13 @@ hho_status hho_inspect_arrays(const hho_inspect *p, double *tables, int32_t *gro
     if (c0) std::copy(P.c0.begin(), P.c0.end(), c0);
     if (mat) std::copy(P.mat.begin(), P.mat.end(), mat);
     if (ic_of_cell) std::copy(P.ic_of_cell.begin(), P.ic_of_cell.end(), ic_of_cell);
+    return HHO_OK;
+}
+
+hho_status hho_inspect_dt_cfl(const hho_inspect *p, int32_t stages, double factor, double *dt) {
+    std::vector<StageCoef> co;
+    if (!p || !dt || !(factor > 0.0) || !erk_coefficients(stages, co)) return HHO_ERR_ARG;
+    *dt = factor * cfl_time_step(p->plan, stages);
     return HHO_OK;
 }
 

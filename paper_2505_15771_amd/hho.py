@@ -71,6 +71,7 @@ EXPORTS = {
     "hho_inspect_arrays": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
     "hho_inspect_grad_coefs": (C.c_int, [C.c_void_p, C.c_void_p]),
     "hho_inspect_erk": (C.c_int, [C.c_int32, C.c_void_p]),
+    "hho_inspect_dt_cfl": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double)]),
 }
 
 _lib = None
@@ -328,6 +329,11 @@ class Inspect:
                                _ptr(self.mat), _ptr(self.ic_of_cell))
         self.gm = np.zeros((8, self.n_ic))
         lib.hho_inspect_grad_coefs(h, _ptr(self.gm))
+        self.dt_cfl = {}
+        for s in (2, 3, 4):
+            dt = C.c_double()
+            _check(lib, lib.hho_inspect_dt_cfl(h, s, 1.0, C.byref(dt)), None)
+            self.dt_cfl[s] = dt.value
         lib.hho_inspect_destroy(h)
         self._h = None
 

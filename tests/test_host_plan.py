@@ -161,3 +161,26 @@ def test_erk_increment_form_reproduces_tableau(s):
     assert np.linalg.norm(Unew - ref) < 1e-14 * np.linalg.norm(ref)
     nodes = {2: [0, 0.5], 3: [0, 0.5, 1.0], 4: [0, 0.5, 0.5, 1.0]}[s]
     assert np.allclose(co[:, 0], nodes)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("shape", ["quads", "triangles", "hybrid"])
+def test_cfl_step_spectral_margin(k, shape):
+    """The time step of hho_dt_cfl (eq. CFL with the paper's CFL* tables) against the spectrum
+    of the condensed operator L (the oracle's dense matrix on the two-material CFL geometry of
+    Sec. 5.1): at half the tabulated step, every eigenvalue lambda satisfies |R(dt lambda)| <= 1
+    for the ERK(4) amplification polynomial R(z) = sum_{j<=4} z^j / j!, i.e. the step that the
+    benchmarks and the GPU tests use is stable.  (At the full tabulated step the strict spectral
+    limit is exceeded: the largest stable step is about 0.83 x the tabulated one on squares and
+    0.52 x on half-square triangles with these stabilisation parameters.)"""
+    from math import factorial
+    from oracle import Oracle
+    from paper_2505_15771_amd import Inspect
+    mesh = M.with_materials(M.bilayer_vertical(5 if k == 2 else 6, p_split={"quads": 0.0, "triangles": 1.0,
+                                                                            "hybrid": 0.5}[shape], seed=3))
+    ins = Inspect(mesh, k)
+    lam = np.linalg.eigvals(Oracle(mesh, k).dense_operator())
+    assert np.max(lam.real) < 1e-10 * np.max(np.abs(lam))  # dissipative semi-discretisation
+    z = 0.5 * ins.dt_cfl[4] * lam
+    R = sum(z ** j / factorial(j) for j in range(5))
+    assert np.max(np.abs(R)) <= 1.0 + 1e-12
