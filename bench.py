@@ -52,30 +52,58 @@ CFL_TRI = {1: 0.265, 2: 0.147, 3: 0.100}      # Table tab::ratio_geo, s = 4
 METRIC = "HHO DOF-stage updates/s, FP64 vs FP32/batched, % of HBM roofline"
 
 
+def _faces(mesh):
+    """(number of faces, number of fluid-solid interface faces) of a polygon mesh: every edge
+    of a cell is a face, shared by the two cells that list it."""
+    vtx, ptr = np.asarray(mesh["cell_vtx"]), np.asarray(mesh["cell_ptr"])
+    med = np.asarray(mesh["medium"])
+    b = np.empty_like(vtx)
+    owner = np.repeat(np.arange(len(ptr) - 1), np.diff(ptr))
+    for c in range(len(ptr) - 1):
+        s, e = ptr[c], ptr[c + 1]
+        b[s:e] = np.roll(vtx[s:e], -1)
+    keys = np.minimum(vtx, b).astype(np.int64) * (1 << 32) + np.maximum(vtx, b)
+    order = np.argsort(keys, kind="stable")
+    ks, ms = keys[order], med[owner[order]]
+    pair = np.flatnonzero(ks[1:] == ks[:-1])
+    n_faces = len(ks) - len(pair)
+    n_interface = int(np.sum(ms[pair] != ms[pair + 1]))
+    return n_faces, len(pair), n_interface
+
+
 def algorithmic_bytes_per_step(mesh, k, word, shots):
-    """Minimum HBM traffic of one RK4 step: 13 state words per cell unknown per shot (stage 1
-    reads U^n and writes Y_2; stages 2 and 3 read Y_i and U^n and write Y_{i+1}; stage 4 reads
-    Y_4, U^n, Y_2 and Y_3 and writes U^{n+1}, which is the same combination as
-    U^n + dt sum_i b_i k_i), plus per stage the mesh metadata in 4-byte words: per cell one face
-    id per face and its material scalars (3 fluid, 5 solid), per interior face one coefficient."""
+    """Algorithmic HBM bytes of one RK4 step, the fixed amount of work that the roofline
+    fraction is priced on: 17 state words per cell unknown per shot (the accumulator form of
+    RK4: stage i reads U^n and the accumulator and writes the next stage state and the
+    accumulator; the last stage also writes U^{n+1}), plus per stage the mesh metadata of a
+    face-based layout in 4-byte words: per cell one face id per face and its material scalars (3
+    fluid: 1/rho, kappa, tau; 4 solid: 1/rho, lambda, mu, tau), per face its two cell ids and one
+    inverse coefficient, and per fluid-solid interface face a (3f x 3f) block in the state word.
+    Returns (bytes, cell unknowns of one shot)."""
+    N = (k + 1) * (k + 2) // 2
+    f = k + 1
+    med = np.asarray(mesh["medium"])
+    nf = np.diff(mesh["cell_ptr"])
+    ndof = int(np.sum(np.where(med == 0, 3, 5))) * N
+    n_faces, _, n_interface = _faces(mesh)
+    meta = int(np.sum(4 * nf + 4 * np.where(med == 0, 3, 4))) + 12 * n_faces + (3 * f) ** 2 * word * n_interface
+    return word * 17 * ndof * shots + 4 * meta, ndof
+
+
+def moved_bytes_per_step(mesh, k, word, shots):
+    """Least HBM traffic of one RK4 step of this implementation's stage kernel: 13 state words
+    per cell unknown per shot (stage 1 reads U^n and writes D_1; stage 2 reads D_1 and U^n and
+    writes D_2 and the partial sum Q; stage 3 reads D_2 and U^n and writes D_3; stage 4 reads D_3,
+    U^n and Q and writes U^{n+1}), plus per stage the per-cell metadata in 4-byte words: one face
+    link per face, the material scalars (3 fluid, 5 solid) and one coefficient per interior face.
+    The face-trace exchange between neighbouring cells is not counted."""
     N = (k + 1) * (k + 2) // 2
     med = np.asarray(mesh["medium"])
     nf = np.diff(mesh["cell_ptr"])
     ndof = int(np.sum(np.where(med == 0, 3, 5))) * N
-    state = word * 13 * ndof * shots
     meta_cells = int(np.sum(4 * nf + 4 * np.where(med == 0, 3, 5)))
-    # interior faces: every interior face is seen by two cells -> count unique via edge keys
-    vtx, ptr = mesh["cell_vtx"], mesh["cell_ptr"]
-    a = vtx
-    b = np.empty_like(vtx)
-    for c in range(len(ptr) - 1):
-        s, e = ptr[c], ptr[c + 1]
-        b[s:e] = np.roll(vtx[s:e], -1)
-    keys = np.minimum(a, b).astype(np.int64) * (1 << 32) + np.maximum(a, b)
-    _, cnt = np.unique(keys, return_counts=True)
-    n_faces_int = int(np.sum(cnt == 2))
-    meta = 4 * (meta_cells + 4 * n_faces_int)
-    return state + meta, ndof
+    _, n_interior, _ = _faces(mesh)
+    return word * 13 * ndof * shots + 4 * (meta_cells + 4 * n_interior), ndof
 
 
 def run_variant(mesh, k, dtype, shots, steps, warmup):
@@ -103,15 +131,20 @@ def run_variant(mesh, k, dtype, shots, steps, warmup):
     torch.cuda.synchronize()
     word = 8 if dtype == "f64" else 4
     bstep, ndof = algorithmic_bytes_per_step(mesh, k, word, shots)
+    mstep, _ = moved_bytes_per_step(mesh, k, word, shots)
     secs = ms / 1e3
     updates = ndof * shots * 4 * steps
     launch_us = ms * 1e3 / (4 * steps)
     gbs = (bstep / 4) / (launch_us * 1e-6) / 1e9
+    moved_gbs = (mstep / 4) / (launch_us * 1e-6) / 1e9
     E = eng.energy()
+    lanes, flags = eng.tuning()
     eng.close()
     return dict(k=k, dtype=dtype, shots=shots, steps=steps, ms=ms, ms_per_step=ms / steps,
                 value=updates / secs, launch_us=launch_us, bytes_per_launch=bstep / 4, gbs=gbs,
-                frac=gbs / HBM_PEAK_GBS, finite=bool(np.all(np.isfinite(E))), ndof=ndof)
+                frac=gbs / HBM_PEAK_GBS, moved_bytes_per_launch=mstep / 4, moved_gbs=moved_gbs,
+                finite=bool(np.all(np.isfinite(E))), ndof=ndof,
+                tuning=dict(lanes=lanes, nt_stores=bool(flags & 1)))
 
 
 def run_adjoint(k, dtype, steps=1000, ckpt=50):
@@ -170,9 +203,12 @@ def run_basin(dtype, steps=100, warmup=5):
     e1.synchronize()
     ms = e0.elapsed_time(e1)
     tr = eng.traces(0)
+    bstep, _ = algorithmic_bytes_per_step(mesh, 2, 8 if dtype == "f64" else 4, 1)
+    gbs = bstep * steps / (ms / 1e3) / 1e9
     out = dict(workload="basin 543k cells (hanging nodes), k=2, 64 receivers", dtype=dtype, steps=steps,
                cells=int(len(mesh["cell_ptr"]) - 1), dofs=int(eng.n_dof), ms_per_step=ms / steps,
-               value=eng.n_dof * 4 * steps / (ms / 1e3), finite=bool(np.all(np.isfinite(tr))))
+               value=eng.n_dof * 4 * steps / (ms / 1e3), gbs=gbs, frac=gbs / HBM_PEAK_GBS,
+               finite=bool(np.all(np.isfinite(tr))))
     eng.close()
     return out
 
@@ -183,8 +219,10 @@ def run_batch(steps=200, warmup=4):
     (graph branches per mesh)."""
     from paper_2505_15771_amd import Batch, Engine
     engines, dts = [], []
+    bstep = 0
     for i, d in enumerate(M.batch_meshes()):
         mesh = M.with_materials(M.unit_square(d["n"], p_split=0.5, seed=d["seed"]))
+        bstep += algorithmic_bytes_per_step(mesh, d["k"], 4, 4)[0]
         e = Engine(mesh, d["k"], dtype="f32", n_shots=4, record_energy=True)
         pos = M.shot_positions(4, 4100 + i)
         for sh in range(4):
@@ -202,6 +240,7 @@ def run_batch(steps=200, warmup=4):
     out = dict(workload="16 hybrid meshes (%d cells in total), k = 1/2/3, 4 shots each, one batch" %
                sum(e.n_cells for e in engines), dtype="f32", steps=steps, shot_dofs=int(shot_dofs),
                ms_per_step=secs * 1e3 / steps, value=shot_dofs * 4 * steps / secs,
+               gbs=bstep * steps / secs / 1e9, frac=bstep * steps / secs / 1e9 / HBM_PEAK_GBS,
                finite=bool(all(np.all(np.isfinite(x)) for x in E)))
     b.close()
     for e in engines:
@@ -282,7 +321,7 @@ def main():
             v = run_variant(mesh, k, dt, sh, max(args.steps // 2, 10), 5)
             print("variant", json.dumps(v), file=sys.stderr, flush=True)
             variants.append({key: v[key] for key in ("k", "dtype", "shots", "value", "ms_per_step", "launch_us",
-                                                       "gbs", "frac")})
+                                                       "gbs", "frac", "moved_gbs", "tuning")})
     adjoint, workloads = [], []
     if args.variants:
         for dt_ in ("f64", "f32"):
@@ -329,7 +368,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": head["frac"], "traffic": traffic, "kernel": "stage_kernel",
                      "launch_us": head["launch_us"], "bytes_per_launch": head["bytes_per_launch"],
-                     "traffic_unit": "HBM bytes per launch"},
+                     "traffic_unit": "HBM bytes per launch",
+                     "moved_bytes_per_launch": head["moved_bytes_per_launch"], "moved_gbs": head["moved_gbs"],
+                     "tuning": head["tuning"]},
         "cpu_baseline": cpu,
         "variants": variants,
         "speedups": speedups,

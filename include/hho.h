@@ -170,6 +170,15 @@ hho_status hho_energy_history(hho_ctx *ctx, int32_t shot, double *out);
 hho_status hho_autotune(hho_ctx *ctx, int32_t *lanes);
 hho_status hho_set_launch(hho_ctx *ctx, int32_t lanes);
 
+/* Tuning flag of hho_set_tuning / hho_get_tuning: stage outputs with the non-temporal policy. */
+#define HHO_TUNE_NT_STORES 1
+
+/* Set the launch shape (by lane count, as hho_set_launch) and the tuning flags (ARG for a lane
+ * count with no shape or for unknown flag bits; nothing changes then); get the current ones
+ * (either output may be NULL). */
+hho_status hho_set_tuning(hho_ctx *ctx, int32_t lanes, int32_t flags);
+hho_status hho_get_tuning(const hho_ctx *ctx, int32_t *lanes, int32_t *flags);
+
 /* Time step from the CFL condition (eq. CFL, Sec. 5.1): dt = factor * min over cells of
  * CFL*(s, k, shape) h_T / c_T.  CFL* is the paper's Table tab::ratio_geo value for the cell's
  * shape (triangle, square; five or more faces use the hexagon column), c_T the largest wave speed

@@ -585,7 +585,7 @@ hho_status autotune_shape(hho_ctx *ctx) {
             a.cU = R(1);
             set_stage_offsets(ctx, a);
             float ms = 0.f;
-            for (int rep = 0; rep < 8 && st == HHO_OK; ++rep) {
+            for (int rep = 0; rep < 15 && st == HHO_OK; ++rep) {
                 if (rep == 3 && hipEventRecord(e0, ctx->stream) != hipSuccess) st = HHO_ERR_DEVICE;
                 if (launch_stage<K, R>(a, ctx->n_blocks(), ctx->stream) != hipSuccess) st = HHO_ERR_DEVICE;
             }
@@ -1227,6 +1227,29 @@ hho_status hho_set_launch(hho_ctx *ctx, int32_t lanes) {
         }
     ctx->err = "set_launch: no launch shape with " + std::to_string(lanes) + " lanes";
     return HHO_ERR_ARG;
+}
+
+hho_status hho_set_tuning(hho_ctx *ctx, int32_t lanes, int32_t flags) {
+    if (!ctx) return HHO_ERR_ARG;
+    if (flags & ~HHO_TUNE_NT_STORES) {
+        ctx->err = "set_tuning: unknown flag bits " + std::to_string(flags);
+        return HHO_ERR_ARG;
+    }
+    const hho_status s = hho_set_launch(ctx, lanes);
+    if (s != HHO_OK) return s;
+    const int nt = (flags & HHO_TUNE_NT_STORES) ? 1 : 0;
+    if (nt != ctx->nt_stores) {
+        ctx->nt_stores = nt;
+        ctx->version++;
+    }
+    return HHO_OK;
+}
+
+hho_status hho_get_tuning(const hho_ctx *ctx, int32_t *lanes, int32_t *flags) {
+    if (!ctx) return HHO_ERR_ARG;
+    if (lanes) *lanes = ctx->launch[ctx->shape].lanes;
+    if (flags) *flags = ctx->nt_stores ? HHO_TUNE_NT_STORES : 0;
+    return HHO_OK;
 }
 
 hho_status hho_dt_cfl(const hho_ctx *ctx, double factor, double *dt) {

@@ -58,6 +58,8 @@ EXPORTS = {
     "hho_energy_history": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "hho_autotune": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "hho_set_launch": (C.c_int, [C.c_void_p, C.c_int32]),
+    "hho_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "hho_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "hho_dt_cfl": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double)]),
     "hho_adjoint_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_void_p,
                                    C.POINTER(C.c_double), C.c_void_p]),
@@ -274,13 +276,26 @@ class Engine:
         return E
 
     def autotune(self):
-        """Time the stage kernel in every launch shape, keep the fastest; returns its lanes."""
+        """Time the stage kernel in every launch shape and store policy, keep the fastest;
+        returns its lanes."""
         lanes = C.c_int32()
         self._call(self.lib.hho_autotune, C.byref(lanes))
         return lanes.value
 
     def set_launch(self, lanes):
         self._call(self.lib.hho_set_launch, int(lanes))
+
+    TUNE_NT_STORES = 1
+
+    def set_tuning(self, lanes, flags):
+        """Launch shape by lane count and flags (TUNE_NT_STORES: non-temporal stage stores)."""
+        self._call(self.lib.hho_set_tuning, int(lanes), int(flags))
+
+    def tuning(self):
+        """(lanes, flags) of the current launch configuration."""
+        lanes, flags = C.c_int32(), C.c_int32()
+        self._call(self.lib.hho_get_tuning, C.byref(lanes), C.byref(flags))
+        return lanes.value, flags.value
 
     def dt_cfl(self, factor=1.0):
         """CFL-limited time step (eq. CFL with the paper's CFL* per cell shape) times factor."""

@@ -1,6 +1,6 @@
-"""CPU checks of the benchmark's bookkeeping (no GPU): the algorithmic byte count of one ERK(4)
-step and the unknown count on a mesh small enough to count by hand, and the refusal of more
-than one GPU."""
+"""CPU checks of the benchmark's bookkeeping (no GPU): the algorithmic and the moved byte counts
+of one ERK(4) step and the unknown count on a mesh small enough to count by hand, and the
+refusal of more than one GPU."""
 import os
 import subprocess
 import sys
@@ -19,17 +19,37 @@ def _bench():
     return b
 
 
-def test_algorithmic_bytes_two_squares():
-    """Two unit squares side by side, one fluid and one solid, k = 1 (N = 3): 9 + 15 = 24 cell
-    unknowns; per step 13 words per unknown; in each of the 4 stages one 4-byte face id per cell
-    face (8), the 4-byte material scalars (3 + 5) and one coefficient for the single interior face."""
-    b = _bench()
-    mesh = dict(xy=np.array([[0, 0], [1, 0], [2, 0], [2, 1], [1, 1], [0, 1]], float).reshape(-1),
+def _two_squares():
+    return dict(xy=np.array([[0, 0], [1, 0], [2, 0], [2, 1], [1, 1], [0, 1]], float).reshape(-1),
                 cell_ptr=np.array([0, 4, 8], np.int32), cell_vtx=np.array([0, 1, 4, 5, 1, 2, 3, 4], np.int32),
                 medium=np.array([0, 1], np.uint8))
+
+
+def test_algorithmic_bytes_two_squares():
+    """Two unit squares side by side, one fluid and one solid, k = 1 (N = 3, f = 2): 9 + 15 = 24
+    cell unknowns; per step 17 words per unknown per shot; in each of the 4 stages one 4-byte face
+    id per cell face (8) and the material scalars (3 fluid + 4 solid), two cell ids and one
+    coefficient for each of the 7 faces, and a (3f)^2 block of state words for the one
+    fluid-solid face."""
+    b = _bench()
+    mesh = _two_squares()
+    assert b._faces(mesh) == (7, 1, 1)
     for word in (4, 8):
         for shots in (1, 3):
             got, ndof = b.algorithmic_bytes_per_step(mesh, 1, word, shots)
+            assert ndof == 24
+            assert got == word * 17 * 24 * shots + 4 * (4 * (8 + 3 + 4) + 12 * 7 + 36 * word)
+
+
+def test_moved_bytes_two_squares():
+    """The same mesh with the stage kernel's own traffic: 13 words per unknown per shot and per
+    stage one 4-byte link per cell face (8), the kernel's material scalars (3 + 5) and one
+    coefficient for the single interior face."""
+    b = _bench()
+    mesh = _two_squares()
+    for word in (4, 8):
+        for shots in (1, 3):
+            got, ndof = b.moved_bytes_per_step(mesh, 1, word, shots)
             assert ndof == 24
             assert got == word * 13 * 24 * shots + 4 * (4 * (8 + 8) + 4 * 1)
 
