@@ -88,7 +88,7 @@ __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<
         mx[b] = bld<R>(B.r, boff, B.yin + (N + b) * B.rowb);
         my[b] = bld<R>(B.r, boff, B.yin + (2 * N + b) * B.rowb);
     }
-    load_incoming<K, NF, R>(B, kFluid, nF, lk, boff, rn);
+    load_incoming<K, NF, R>(B, kFluid, a.S, shot, lk, rn);
     const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
     const R kap = bld<R>(B.r, coff, B.mat + kStiff * B.crowb);
     const R irho = bld<R>(B.r, coff, B.mat + kInvRho * B.crowb);
@@ -240,7 +240,7 @@ __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<
         bst(B.r, boff, B.yout + (N + b) * B.rowb, zx[b]);
         bst(B.r, boff, B.yout + (2 * N + b) * B.rowb, zy[b]);
     }
-    fluid_traces<K, NF, R>(a, B, tb, nF, lk, shot, zp, zx, zy, tau);
+    fluid_traces<K, NF, R>(a, B, tb, nF, lk, boff, zp, zx, zy, tau);
 }
 
 // ------------------------------------------------------------------------- solid cells
@@ -269,7 +269,7 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
         s2[b] = bld<R>(B.r, boff, B.yin + (3 * N + b) * B.rowb);
         s3[b] = bld<R>(B.r, boff, B.yin + (4 * N + b) * B.rowb);
     }
-    load_incoming<K, NF, R>(B, kSolid, nF, lk, boff, rn);
+    load_incoming<K, NF, R>(B, kSolid, a.S, shot, lk, rn);
     const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
     const R itau = bld<R>(B.r, coff, B.mat + kInvTau * B.crowb);
     const R irho = bld<R>(B.r, coff, B.mat + kInvRho * B.crowb);
@@ -476,7 +476,7 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
         bst(B.r, boff, B.yout + (3 * N + b) * B.rowb, z2[b]);
         bst(B.r, boff, B.yout + (4 * N + b) * B.rowb, z3[b]);
     }
-    solid_traces<K, NF, R>(a, B, tb, nF, lk, shot, zx, zy, z1, z2, z3, tau, itau);
+    solid_traces<K, NF, R>(a, B, tb, nF, lk, boff, zx, zy, z1, z2, z3, tau, itau);
 }
 
 template <int K, int NF, typename R>
@@ -563,9 +563,9 @@ __device__ __forceinline__ void start_body(const StageArgs<R> &a, const GroupDev
         for (int b = 0; b < N; ++b)
             if (q < nb) bst(B.r, boff, B.yout + (q * N + b) * B.rowb, z[q][b]);
     if (G.medium == kFluid)
-        fluid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.shot, z[0], z[1], z[2], tau);
+        fluid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.boff, z[0], z[1], z[2], tau);
     else
-        solid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.shot, z[0], z[1], z[2], z[3], z[4], tau, itau);
+        solid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.boff, z[0], z[1], z[2], z[3], z[4], tau, itau);
 }
 
 template <int K, typename R>

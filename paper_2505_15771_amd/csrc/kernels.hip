@@ -13,21 +13,20 @@
 // mass matrices are identities):
 //   1. face solves (eq. ex_solve, first line) for every non-boundary face F of T:
 //        r_T = tau_T G^T u_T - G^T (flux_T . n)       (own trace contribution)
-//        r_T'                                          (the neighbour's, read from T's own
-//                                                      incoming slots)
+//        r_T'                                          (the neighbour's, gathered from the
+//                                                      neighbour's own trace slots)
 //        same medium:  u_F = (r_T + r_T') / (tau_T + tau_T')
 //        interface:    tau_f p_F + n_G.v_F = r_f,  -n_G p_F + tau_s v_F = r_s   (3f x 3f)
 //   2. cell residual (eq. ex_solve, second line) R = F_T - K_T u_T - K_TF u_F,
 //   3. k = M^{-1} R (1/rho, kappa, or the stiffness C in the E basis),
 //   4. Runge-Kutta combine (eq. ERK); then T computes the trace contributions of its new
-//      stage state and stores each one directly into the incoming slot of the neighbour
-//      across that face, already in the neighbour's face basis (mode i flips sign as
-//      (-1)^i between the two orientations of a face; a solid cell writing across the
-//      interface also divides by its tau_s, which the fluid side needs).  So the next stage
-//      reads its incoming contributions at its own lane, coalesced and independent of the
-//      face links; the scattered accesses are stores.  Trace buffers are [slot][lane][mode]
-//      (slot = local face and component): the F modes of one contribution are contiguous, so
-//      a scattered store writes one 12- or 16-byte piece instead of F separate words.
+//      stage state on each of its faces and stores them in its own slots, already in the
+//      neighbour's face basis (mode i flips sign as (-1)^i between the two orientations of a
+//      face; a solid cell's contribution across the interface is also divided by its tau_s,
+//      which the fluid side needs).  Trace buffers are [slot][lane][mode] (slot = local face
+//      and component), so these stores are coalesced and each lane writes whole F-mode
+//      pieces; the next stage gathers, through the face links, the pieces of its neighbours
+//      (one wide load of F modes per face and component).
 #include <hip/hip_runtime.h>
 
 #include "stage_common.h"
@@ -184,7 +183,7 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
     R y[3 * N], uk[KEEP ? 3 * N : 1], dk[KEEP ? 3 * N : 1];
     load_state<3 * N, R, KEEP>(a, B, boff, y, uk, dk);
     const R *p = y, *mx = y + N, *my = y + 2 * N;
-    load_incoming<K, NF, R>(B, kFluid, nF, lk, boff, rn);
+    load_incoming<K, NF, R>(B, kFluid, a.S, shot, lk, rn);
     const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
     const R kap = bld<R>(B.r, coff, B.mat + kStiff * B.crowb);
     const R irho = bld<R>(B.r, coff, B.mat + kInvRho * B.crowb);
@@ -279,7 +278,7 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
     rk_update<3 * N, R, KEEP, POL>(a, B, boff, y, kv, nw, uk, dk);
     const R *np = nw, *nmx = nw + N, *nmy = nw + 2 * N;
     if (STORE) store_recompute<K, NF, 3 * N, R, NF, 1>(a, lk, boff, y, kv, fv);
-    fluid_traces<K, NF, R, POL>(a, B, tb, nF, lk, shot, np, nmx, nmy, tau);
+    fluid_traces<K, NF, R, POL>(a, B, tb, nF, lk, boff, np, nmx, nmy, tau);
     if (a.last) {
         if (energy) {
             double sp = 0, sm = 0;
@@ -329,7 +328,7 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
     R y[5 * N], uk[KEEP ? 5 * N : 1], dk[KEEP ? 5 * N : 1];
     load_state<5 * N, R, KEEP>(a, B, boff, y, uk, dk);
     const R *vx = y, *vy = y + N, *s1 = y + 2 * N, *s2 = y + 3 * N, *s3 = y + 4 * N;
-    load_incoming<K, NF, R>(B, kSolid, nF, lk, boff, rn);
+    load_incoming<K, NF, R>(B, kSolid, a.S, shot, lk, rn);
     const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
     const R itau = bld<R>(B.r, coff, B.mat + kInvTau * B.crowb);
     const R irho = bld<R>(B.r, coff, B.mat + kInvRho * B.crowb);
@@ -465,7 +464,7 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
     rk_update<5 * N, R, KEEP, POL>(a, B, boff, y, kv, nw, uk, dk);
     const R *nvx = nw, *nvy = nw + N, *ns1 = nw + 2 * N, *ns2 = nw + 3 * N, *ns3 = nw + 4 * N;
     if (STORE) store_recompute<K, NF, 5 * N, R, NF, 2>(a, lk, boff, y, kv, fv);
-    solid_traces<K, NF, R, POL>(a, B, tb, nF, lk, shot, nvx, nvy, ns1, ns2, ns3, tau, itau);
+    solid_traces<K, NF, R, POL>(a, B, tb, nF, lk, boff, nvx, nvy, ns1, ns2, ns3, tau, itau);
     if (a.last) {
         if (energy) {
             const double ca = a.emat[(long long)1 * nic + ic], cb = a.emat[(long long)2 * nic + ic];
@@ -547,9 +546,9 @@ __device__ __forceinline__ void traces_body(const StageArgs<R> &a, const GroupDe
 #pragma unroll
         for (int b = 0; b < N; ++b) v[q][b] = q < nb ? bld<R>(B.r, L.boff, B.yin + (q * N + b) * B.rowb) : R(0);
     if (G.medium == kFluid)
-        fluid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.shot, v[0], v[1], v[2], tau);
+        fluid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.boff, v[0], v[1], v[2], tau);
     else
-        solid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.shot, v[0], v[1], v[2], v[3], v[4], tau, itau);
+        solid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.boff, v[0], v[1], v[2], v[3], v[4], tau, itau);
 }
 
 template <int K, typename R>

@@ -1,6 +1,7 @@
 // Device helpers shared by the forward stage kernels (kernels.hip) and the adjoint stage
 // kernels (adjoint.hip): buffer addressing of the arena, lane decoding, face links, incoming
-// trace contributions and the outgoing trace scatter.  Included once per translation unit.
+// trace contributions (gathered from the neighbours) and the outgoing trace stores.  Included
+// once per translation unit.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -238,35 +239,35 @@ __device__ __forceinline__ void load_links(const Bufs<R> &B, int nF, int ic, int
     }
 }
 
-// Incoming neighbour contributions (trace buffers [slot = 2 j + c][lane][mode i], byte offset
-// ((2 j + c) LT + lane) F sizeof(R) + i sizeof(R)).  Rows of every face of the group are loaded without
-// waiting for the links (a boundary face's slot is never written and its value is unused);
-// only a fluid cell's second component, present across the interface, depends on the link.
+// Neighbour contributions across the faces of a lane.  Trace buffers are [slot = 2 j + c][lane]
+// [mode i] (byte offset ((2 j + c) LT + lane) F sizeof(R) + i sizeof(R)); every lane stores the
+// contributions of its own faces in its own slots (coalesced stores, see fluid_traces) and
+// gathers its neighbours' here: across face j the neighbour icn = link >> 4 wrote slot 2 jn + c of
+// its lane (icn, shot), jn = link & 7.  Boundary faces (link -1) read nothing.  Components: a
+// fluid neighbour writes c = 0 (its scalar contribution), a solid one c = 0 and 1 (the vector);
+// a fluid cell reads c = 1 only across the interface, a solid cell only away from it.
 template <int K, int NF, typename R>
-__device__ __forceinline__ void load_incoming(const Bufs<R> &B, int medium, int nF, const int *lk, unsigned boff,
+__device__ __forceinline__ void load_incoming(const Bufs<R> &B, int medium, int S, int shot, const int *lk,
                                               R (*rn)[2][Dim<K>::F]) {
     constexpr int F = Dim<K>::F;
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
 #pragma unroll
         for (int i = 0; i < F; ++i) rn[j][0][i] = rn[j][1][i] = R(0);
-        if (j >= nF) continue;
-        bldv<F, R>(B.r, F * boff, B.tin + (j * 2) * F * B.rowb, rn[j][0]);
-        if (medium == kSolid) bldv<F, R>(B.r, F * boff, B.tin + (j * 2 + 1) * F * B.rowb, rn[j][1]);
-    }
-    if (medium == kFluid) {
-#pragma unroll
-        for (int j = 0; j < NF; ++j) {
-            if (lk[j] < 0 || !((lk[j] >> 3) & 1)) continue;
-            bldv<F, R>(B.r, F * boff, B.tin + (j * 2 + 1) * F * B.rowb, rn[j][1]);
-        }
+        if (lk[j] < 0) continue;
+        const int jn = lk[j] & 7;
+        const bool itf = (lk[j] >> 3) & 1;
+        const unsigned nb = (unsigned)((lk[j] >> 4) * S + shot) * (unsigned)sizeof(R);
+        bldv<F, R>(B.r, F * nb, B.tin + (jn * 2) * F * B.rowb, rn[j][0]);
+        if (medium == kSolid ? !itf : itf) bldv<F, R>(B.r, F * nb, B.tin + (jn * 2 + 1) * F * B.rowb, rn[j][1]);
     }
 }
 
 // ------------------------------------------------------------------------- outgoing traces
 template <int K, int NF, typename R, int POL = 0>
 __device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
-                                             const int *lk, int shot, const R *p, const R *mx, const R *my, R tau) {
+                                             const int *lk, unsigned boff, const R *p, const R *mx, const R *my,
+                                             R tau) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
     const HHO_CONST R *Gt = tb + 3 * N * N;
     const HHO_CONST R *nr = Gt + nF * N * F;
@@ -287,19 +288,17 @@ __device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const Bufs<R
             for (int i = 0; i < F; ++i)
                 if (g_nonzero(b, i)) r[i] += Gt[(j * N + b) * F + i] * q;
         }
-        const int icn = lk[j] >> 4, jn = lk[j] & 7;
-        const unsigned nb = (unsigned)(icn * a.S + shot) * (unsigned)sizeof(R);
         R o[F];
 #pragma unroll
         for (int i = 0; i < F; ++i) o[i] = sgn<R>(i) * r[i];
-        bstv<F, R, POL>(B.r, F * nb, B.tout + (jn * 2) * F * B.rowb, o);
+        bstv<F, R, POL>(B.r, F * boff, B.tout + (j * 2) * F * B.rowb, o);
     }
 }
 
 template <int K, int NF, typename R, int POL = 0>
 __device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
-                                             const int *lk, int shot, const R *vx, const R *vy, const R *s1, const R *s2,
-                                             const R *s3, R tau, R itau) {
+                                             const int *lk, unsigned boff, const R *vx, const R *vy, const R *s1,
+                                             const R *s2, const R *s3, R tau, R itau) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
     const R r2 = R(kRsqrt2);
     const HHO_CONST R *Gt = tb + 3 * N * N;
@@ -329,8 +328,6 @@ __device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R
                 ry[i] += Gt[(j * N + b) * F + i] * qy;
             }
         }
-        const int icn = lk[j] >> 4, jn = lk[j] & 7;
-        const unsigned nb = (unsigned)(icn * a.S + shot) * (unsigned)sizeof(R);
         // across the interface the fluid side needs r_s / tau_s
         const R w = ((lk[j] >> 3) & 1) ? itau : R(1);
         R ox[F], oy[F];
@@ -339,8 +336,8 @@ __device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R
             ox[i] = sgn<R>(i) * w * rx[i];
             oy[i] = sgn<R>(i) * w * ry[i];
         }
-        bstv<F, R, POL>(B.r, F * nb, B.tout + (jn * 2) * F * B.rowb, ox);
-        bstv<F, R, POL>(B.r, F * nb, B.tout + (jn * 2 + 1) * F * B.rowb, oy);
+        bstv<F, R, POL>(B.r, F * boff, B.tout + (j * 2) * F * B.rowb, ox);
+        bstv<F, R, POL>(B.r, F * boff, B.tout + (j * 2 + 1) * F * B.rowb, oy);
     }
 }
 
