@@ -248,6 +248,29 @@ def run_batch(steps=200, warmup=4):
     return out
 
 
+def copy_bandwidth(mib=1024, reps=20):
+    """Achievable HBM bandwidth of a plain device copy (torch's elementwise copy kernel) of
+    `mib` MiB: bytes read plus bytes written per second, best of `reps` timed copies."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    st = torch.cuda.current_stream()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        dst.copy_(src)
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    return 2.0 * mib * (1 << 20) / (best * 1e-3) / 1e9
+
+
 def cpu_baseline(mesh, k, budget_s=15.0):
     """The FP64 oracle as it stands, on the host cores, for about budget_s seconds of stepping."""
     from oracle import Oracle
@@ -345,6 +368,8 @@ def main():
         for v in variants:
             if v["k"] == args.k and v is not base[0]:
                 speedups["%s_%dshot_vs_f64_1shot" % (v["dtype"], v["shots"])] = v["value"] / ref
+    copy_gbs = copy_bandwidth()
+    print("copy", json.dumps({"gbs": copy_gbs}), file=sys.stderr, flush=True)
     traffic = None
     if (stage_sources_digest() == MEASURED_TRAFFIC["sources_sha256"]
             and (args.k, args.dtype, args.shots) == MEASURED_TRAFFIC["config"]):
@@ -370,6 +395,7 @@ def main():
                      "launch_us": head["launch_us"], "bytes_per_launch": head["bytes_per_launch"],
                      "traffic_unit": "HBM bytes per launch",
                      "moved_bytes_per_launch": head["moved_bytes_per_launch"], "moved_gbs": head["moved_gbs"],
+                     "copy_gbs": copy_gbs, "frac_of_copy": head["gbs"] / copy_gbs,
                      "tuning": head["tuning"]},
         "cpu_baseline": cpu,
         "variants": variants,

@@ -560,48 +560,86 @@ hho_status autotune_shape(hho_ctx *ctx) {
         hho_status s = compute_traces<K, R>(ctx);
         if (s != HHO_OK) return s;
     }
+    std::vector<StageCoef> co;
+    if (!erk_coefficients(ctx->stages, co)) {
+        ctx->err = "unsupported ERK stage count";
+        return HHO_ERR_ARG;
+    }
     ctx->h_clock = Clock{0.0, 0.0, 0, 0};
     HCK(hipMemcpyAsync(ctx->clock, &ctx->h_clock, sizeof(Clock), hipMemcpyHostToDevice, ctx->stream));
     hipEvent_t e0, e1;
     HCK(hipEventCreate(&e0));
     HCK(hipEventCreate(&e1));
+    // Candidates: every launch shape with both store policies.  One pass = the stages before the
+    // last of one step (they write only stage buffers and the two trace buffers that are not the
+    // current one, so the state and its traces are unchanged).  Candidates take turns over several
+    // rounds (so that clock and cache drift hit all of them alike) and each is ranked by the median
+    // of its rounds.
     const int keep = ctx->shape, keep_nt = ctx->nt_stores;
-    int best = keep, best_nt = keep_nt;
-    float best_ms = 1e30f;
+    const int n_shape = (int)ctx->launch.size(), n_cand = 2 * n_shape, s = ctx->stages;
+    constexpr int kRounds = 5, kPasses = 3;
+    std::vector<std::vector<float>> times(n_cand);
+    const int Tc = ctx->tcur, Tbuf[2] = {(Tc + 1) % 3, (Tc + 2) % 3};
+    void *stg[3] = {ctx->Y[0], ctx->Y[1], ctx->acc};
+    auto pass = [&](StageArgs<R> &a) -> bool {
+        for (int i = 0; i < std::max(s - 1, 1); ++i) {
+            const StageCoef &q = co[i];
+            a.first = i == 0;
+            a.last = 0;
+            a.Yin = i == 0 ? (const R *)ctx->U : (const R *)stg[i - 1];
+            a.Yout = (R *)stg[i];
+            a.qa = (R)q.qa;
+            a.qb = (R)q.qb;
+            a.cd = (R)q.cd;
+            a.q_write = q.q_write;
+            a.q_read = 0;
+            a.Yq = q.q_write ? (R *)stg[0] : nullptr;
+            a.Tin = (const R *)ctx->T[i == 0 ? Tc : Tbuf[(i - 1) % 2]];
+            a.Tout = (R *)ctx->T[Tbuf[i % 2]];
+            a.c = q.c;
+            a.cU = (R)q.cU;
+            a.cY = (R)q.cY;
+            a.ck = (R)q.ck;
+            a.cb = (R)q.cb;
+            set_stage_offsets(ctx, a);
+            if (launch_stage<K, R>(a, ctx->n_blocks(), ctx->stream) != hipSuccess) return false;
+        }
+        return true;
+    };
     hho_status st = HHO_OK;
-    for (int nt = 0; nt < 2 && st == HHO_OK; ++nt) {
-        ctx->nt_stores = nt;
-        for (size_t sh = 0; sh < ctx->launch.size() && st == HHO_OK; ++sh) {
-            ctx->shape = (int)sh;
+    for (int round = 0; round < kRounds && st == HHO_OK; ++round) {
+        for (int c = 0; c < n_cand && st == HHO_OK; ++c) {
+            ctx->nt_stores = c / n_shape;
+            ctx->shape = c % n_shape;
             StageArgs<R> a = base_args<R>(ctx);
             a.U = (R *)ctx->U;
             a.acc = (R *)ctx->acc;
-            a.Yin = (const R *)ctx->U;
-            a.Yout = (R *)ctx->Y[0];
-            a.Tin = (const R *)ctx->T[ctx->tcur];
-            a.Tout = (R *)ctx->T[(ctx->tcur + 1) % 3];
-            a.first = 1;
-            a.last = 0;
-            a.cU = R(1);
-            set_stage_offsets(ctx, a);
             float ms = 0.f;
-            for (int rep = 0; rep < 15 && st == HHO_OK; ++rep) {
-                if (rep == 3 && hipEventRecord(e0, ctx->stream) != hipSuccess) st = HHO_ERR_DEVICE;
-                if (launch_stage<K, R>(a, ctx->n_blocks(), ctx->stream) != hipSuccess) st = HHO_ERR_DEVICE;
-            }
+            if (!pass(a) || hipEventRecord(e0, ctx->stream) != hipSuccess) st = HHO_ERR_DEVICE;
+            for (int p = 0; p < kPasses && st == HHO_OK; ++p)
+                if (!pass(a)) st = HHO_ERR_DEVICE;
             if (st == HHO_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess ||
                                  hipEventSynchronize(e1) != hipSuccess ||
                                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
                 st = HHO_ERR_DEVICE;
-            if (st == HHO_OK && ms < best_ms) {
-                best_ms = ms;
-                best = (int)sh;
-                best_nt = nt;
-            }
+            times[c].push_back(ms);
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    int best = keep, best_nt = keep_nt;
+    if (st == HHO_OK) {
+        float best_ms = 1e30f;
+        for (int c = 0; c < n_cand; ++c) {
+            std::vector<float> &t = times[c];
+            std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
+            if (t[t.size() / 2] < best_ms) {
+                best_ms = t[t.size() / 2];
+                best = c % n_shape;
+                best_nt = c / n_shape;
+            }
+        }
+    }
     ctx->shape = best;
     ctx->nt_stores = best_nt;
     if (best != keep || best_nt != keep_nt) ctx->version++;
