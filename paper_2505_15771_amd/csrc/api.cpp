@@ -26,10 +26,18 @@ struct AdjWork {
     int32_t *link = nullptr;
     void *c0 = nullptr, *mat = nullptr;
     // forward data of one checkpoint segment: per (step, stage) slot the primal rows of Y_i
-    // ([2N][LT]), k_i ([5N][LT]) and the primal face values of Y_i ([trace rows][LT])
+    // ([2N][LT]), k_i ([5N][LT]) and the primal face values of Y_i ([trace rows][LT]); two
+    // segments' worth (store_slots each), so that the recompute of one segment overlaps the
+    // adjoint stages of the next
     size_t slot_elems = 0, k_off = 0, f_off = 0;
-    void *store = nullptr;
+    void *store[2] = {nullptr, nullptr};
     size_t store_slots = 0;
+    // second stream (default priority) for the forward recompute, its events, and the clock that
+    // the adjoint kernels read (only dt), apart from the forward clock the recompute advances
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_start = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
+    Clock *aclock = nullptr;
+    Clock h_aclock{};
     void *ckpt = nullptr;  // checkpoints U^{g * every} and U^N, [n + 1][5N][LT]
     size_t ckpt_states = 0;
     double *gacc = nullptr, *gm = nullptr, *grad = nullptr, *dobs = nullptr;
@@ -295,12 +303,12 @@ StageArgs<R> base_args(hho_ctx *ctx) {
 }
 
 template <int K, typename R>
-hho_status compute_traces(hho_ctx *ctx) {
+hho_status compute_traces(hho_ctx *ctx, hipStream_t st = nullptr) {
     StageArgs<R> a = base_args<R>(ctx);
     a.Yin = (const R *)ctx->U;
     a.Tout = (R *)ctx->T[ctx->tcur];
     set_stage_offsets(ctx, a);
-    HCK((launch_traces<K, R>(a, ctx->n_blocks(), ctx->stream)));
+    HCK((launch_traces<K, R>(a, ctx->n_blocks(), st ? st : ctx->stream)));
     ctx->traces_valid = true;
     return HHO_OK;
 }
@@ -745,12 +753,24 @@ hho_status ensure_adjoint(hho_ctx *ctx, int every, int n_seg) {
             (s = upload(ctx, &w.ic_of_cell, ic)))
             return s;
     }
+    if (!w.aux) {
+        HCK(hipStreamCreateWithFlags(&w.aux, hipStreamNonBlocking));
+        HCK(hipEventCreateWithFlags(&w.ev_start, hipEventDisableTiming));
+        for (int b = 0; b < 2; ++b) {
+            HCK(hipEventCreateWithFlags(&w.ev_rec[b], hipEventDisableTiming));
+            HCK(hipEventCreateWithFlags(&w.ev_adj[b], hipEventDisableTiming));
+        }
+        if ((s = dalloc(ctx, (void **)&w.aclock, sizeof(Clock)))) return s;
+    }
     const size_t slots = (size_t)every * ctx->stages;
     if (slots > w.store_slots) {
-        dfree(ctx, w.store);
-        w.store = nullptr;
+        for (int b = 0; b < 2; ++b) {
+            dfree(ctx, w.store[b]);
+            w.store[b] = nullptr;
+        }
         w.store_slots = 0;
-        if ((s = dalloc(ctx, &w.store, slots * w.slot_elems * rs))) return s;
+        for (int b = 0; b < 2; ++b)
+            if ((s = dalloc(ctx, &w.store[b], slots * w.slot_elems * rs))) return s;
         w.store_slots = slots;
     }
     if ((size_t)n_seg + 1 > w.ckpt_states) {
@@ -795,19 +815,40 @@ hho_status adjoint_sweep(hho_ctx *ctx, const std::vector<StageCoef> &co, int eve
     a.Yout = (R *)w.Z[0];
     a.Tout = (R *)w.T[0];
     a.inject = n_steps;
+    // the adjoint kernels read dt from a clock of their own
+    w.h_aclock = Clock{t0, dt, 0, 0};
+    HCK(hipMemcpyAsync(w.aclock, &w.h_aclock, sizeof(Clock), hipMemcpyHostToDevice, ctx->stream));
+    a.clock = w.aclock;
     set_stage_offsets(ctx, a);
     HCK((launch_adjoint_start<K, R>(a, ctx->n_blocks(), ctx->stream)));
-    int cur = 0;
-    R *store = (R *)w.store;
-    for (int g = n_seg - 1; g >= 0; --g) {
-        const int n0 = g * every, len = std::min(every, n_steps - n0);
-        HCK(hipMemcpyAsync(ctx->U, (char *)w.ckpt + (size_t)g * sbytes, sbytes, hipMemcpyDeviceToDevice,
-                           ctx->stream));
-        hho_status st = compute_traces<K, R>(ctx);
+    // Segments from the last: the forward recompute of segment g - 1 (stream aux: the forward
+    // state, traces and clock of the context, store buffer (g - 1) % 2) runs while the adjoint
+    // stages of segment g (the caller's stream: the adjoint arena, store buffer g % 2) run.
+    // Events order the recompute of a segment before its adjoint stages, and the adjoint stages
+    // that read a store buffer before the recompute that overwrites it.
+    HCK(hipEventRecord(w.ev_start, ctx->stream));  // the start kernel has read U^N
+    HCK(hipStreamWaitEvent(w.aux, w.ev_start, 0));
+    bool adj_pending[2] = {false, false};
+    auto recompute = [&](int g) -> hho_status {
+        const int b = g % 2, n0 = g * every, len = std::min(every, n_steps - n0);
+        if (adj_pending[b]) HCK(hipStreamWaitEvent(w.aux, w.ev_adj[b], 0));
+        HCK(hipMemcpyAsync(ctx->U, (char *)w.ckpt + (size_t)g * sbytes, sbytes, hipMemcpyDeviceToDevice, w.aux));
+        hho_status st = compute_traces<K, R>(ctx, w.aux);
         if (st != HHO_OK) return st;
         clocks[g] = Clock{t0, dt, n0, 0};
-        HCK(hipMemcpyAsync(ctx->clock, &clocks[g], sizeof(Clock), hipMemcpyHostToDevice, ctx->stream));
-        if ((st = enqueue_steps<K, R>(ctx, ctx->stream, len, store))) return st;
+        HCK(hipMemcpyAsync(ctx->clock, &clocks[g], sizeof(Clock), hipMemcpyHostToDevice, w.aux));
+        if ((st = enqueue_steps<K, R>(ctx, w.aux, len, (R *)w.store[b]))) return st;
+        HCK(hipEventRecord(w.ev_rec[b], w.aux));
+        return HHO_OK;
+    };
+    hho_status st = recompute(n_seg - 1);
+    if (st != HHO_OK) return st;
+    int cur = 0;
+    for (int g = n_seg - 1; g >= 0; --g) {
+        const int b = g % 2, n0 = g * every, len = std::min(every, n_steps - n0);
+        HCK(hipStreamWaitEvent(ctx->stream, w.ev_rec[b], 0));
+        if (g > 0 && (st = recompute(g - 1)) != HHO_OK) return st;
+        const R *store = (const R *)w.store[b];
         for (int n = len - 1; n >= 0; --n) {
             for (int i = s - 1; i >= 0; --i) {
                 const R *slot = store + (size_t)(n * s + i) * w.slot_elems;
@@ -828,6 +869,8 @@ hho_status adjoint_sweep(hho_ctx *ctx, const std::vector<StageCoef> &co, int eve
                 cur ^= 1;
             }
         }
+        HCK(hipEventRecord(w.ev_adj[b], ctx->stream));
+        adj_pending[b] = true;
     }
     return HHO_OK;
 }
@@ -960,6 +1003,13 @@ void hho_destroy(hho_ctx *ctx) {
     else (void)hipDeviceSynchronize();
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    AdjWork &w = ctx->adj;
+    if (w.aux) {
+        (void)hipStreamSynchronize(w.aux);
+        (void)hipStreamDestroy(w.aux);
+    }
+    for (hipEvent_t e : {w.ev_start, w.ev_rec[0], w.ev_rec[1], w.ev_adj[0], w.ev_adj[1]})
+        if (e) (void)hipEventDestroy(e);
     for (void *p : ctx->allocs) (void)hipFree(p);
     delete ctx;
 }
