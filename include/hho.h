@@ -196,9 +196,10 @@ hho_status hho_dt_cfl(const hho_ctx *ctx, double factor, double *dt);
  * (input cell order, float64, summed over shots; slot 2 is 0 on fluid cells).
  * d_obs[shot][n_steps][n_rec][2] (float64, host) in the layout of hho_get_traces; may be NULL
  * when no receivers are set (then J = 0 and grad = 0).  The reverse sweep keeps checkpoints of
- * the state every ckpt_every steps (0: about sqrt(n_steps)) and recomputes one segment of
- * stage data at a time, so device memory grows as n_steps / ckpt_every states plus
- * ckpt_every * rk_stages stage records; the workspace is kept for later calls.
+ * the state every ckpt_every steps (0: about sqrt(n_steps)) and recomputes the stage data of one
+ * segment while the adjoint stages of the following segment run (on a second stream the
+ * context creates, default priority), so device memory grows as n_steps / ckpt_every states plus
+ * 2 * ckpt_every * rk_stages stage records; the workspace is kept for later calls.
  * On return (synchronised) the state is U^{n_steps}, and hho_get_traces / hho_energy_history
  * report the forward run, as after hho_erk_step.  Only rk_stages 2 and 4 (subdiagonal
  * Runge-Kutta matrices) are supported: ARG otherwise; UNSTABLE as hho_erk_step. */
