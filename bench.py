@@ -213,6 +213,49 @@ def run_basin(dtype, steps=100, warmup=5):
     return out
 
 
+PAPER_BILAYER = {1: (0.159, 161.0), 3: (0.054, 3322.0)}  # Table tab::cfl_cpu: ERK(4) dt~, CPU s
+
+
+def run_paper_bilayer(k, dtype="f64"):
+    """The paper's timed ERK(4) run (Sec. 5.2, Table tab::cfl_cpu): granite-water bilayer,
+    161 x 110 squares of 23.6 m, a pressure pulse in the water, T_f = 0.5 s at the paper's
+    normalised step dt~ = cP dt / h (0.159 for k = 1, 0.054 for k = 3).  Reports the time of
+    the whole run on the GPU (state resident, graph captured by a warm-up call) and the setup
+    time (plan, upload, autotuning), beside the paper's CPU seconds (hardware not stated)."""
+    import torch
+    from paper_2505_15771_amd import Engine
+    mesh = M.granite_water()
+    dtt, paper_s = PAPER_BILAYER[k]
+    dt = dtt * 23.6 / 6000.0
+    n = int(np.ceil(0.5 / dt - 1e-9))
+    t0 = time.perf_counter()
+    eng = Engine(mesh, k, dtype=dtype, record_energy=True)
+    U0 = M.pressure_pulse(mesh, k)
+    eng.set_state(U0)
+    eng.autotune()
+    eng.synchronize()
+    setup_s = time.perf_counter() - t0
+    eng.erk_step(0.0, dt, 64)  # warm-up: graph capture
+    eng.set_state(U0)
+    E_init = float(eng.energy()[0])
+    eng.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    eng.erk_step(0.0, dt, n)
+    e1.record(st)
+    e1.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3
+    E = eng.energy_history()
+    out = dict(workload="paper granite-water bilayer (Table tab::cfl_cpu), 17710 squares, k=%d, ERK(4), "
+                        "T_f = 0.5 s" % k, dtype=dtype, k=k, steps=n, dt=dt, cell_dofs=int(eng.n_dof),
+               run_s=secs, setup_s=setup_s, value=eng.n_dof * 4 * n / secs,
+               paper_cpu_s=paper_s, paper_hardware="not stated", speedup_vs_paper=paper_s / secs,
+               energy_ratio=float(E[-1] / E_init), finite=bool(np.all(np.isfinite(E))))
+    eng.close()
+    return out
+
+
 def run_batch(steps=200, warmup=4):
     """Sixteen hybrid meshes of 20k-300k cells (k = 1, 2, 3 in turn), four Ricker shots each at
     seeded positions, float32 stepping with the float64 energy check, all advanced by one batch
@@ -302,7 +345,7 @@ def main():
     ap.add_argument("--shots", type=int, default=1)
     ap.add_argument("--variants", type=int, default=1, help="also time the float64 / k=3 / batched variants")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--only", choices=("adjoint", "basin", "batch"), default=None,
+    ap.add_argument("--only", choices=("adjoint", "basin", "batch", "paper"), default=None,
                     help="run one extra workload alone and print its JSON line (for profiling)")
     ap.add_argument("--only-steps", type=int, default=200)
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -330,7 +373,8 @@ def main():
     if args.only:
         fn = {"adjoint": lambda: run_adjoint(2, args.dtype, steps=args.only_steps, ckpt=50),
               "basin": lambda: run_basin(args.dtype, steps=args.only_steps),
-              "batch": lambda: run_batch(steps=args.only_steps)}[args.only]
+              "batch": lambda: run_batch(steps=args.only_steps),
+              "paper": lambda: [run_paper_bilayer(1), run_paper_bilayer(3)]}[args.only]
         print(json.dumps(fn()), flush=True)
         return
     mesh = M.hybrid_square(256)
@@ -358,6 +402,10 @@ def main():
         v = run_batch()
         print("workload", json.dumps(v), file=sys.stderr, flush=True)
         workloads.append(v)
+        for k_ in (1, 3):
+            v = run_paper_bilayer(k_)
+            print("workload", json.dumps(v), file=sys.stderr, flush=True)
+            workloads.append(v)
     cpu = cpu_baseline(mesh, args.k) if args.cpu_baseline else None
     # speed-ups over float64 single-shot stepping of the same workload on the same GPU
     speedups = {}

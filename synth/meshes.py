@@ -286,3 +286,42 @@ def random_state(ndof_per_cell, seed, scale=1.0):
     """Seeded random cell coefficients (one value per cell degree of freedom)."""
     rng = np.random.default_rng(seed)
     return scale * rng.standard_normal(int(np.sum(ndof_per_cell)))
+
+
+def granite_water(nx=161, ny_s=68, ny_f=42):
+    """The granite-water bilayer of the paper's explicit/implicit timing study (Sec. 5.2,
+    Table tab::cfl_cpu): x in (-1.9, 1.9) km, granite (rho = 2690, cP = 6000 m/s,
+    cS = 3000 m/s) below the interface, water (rho = 1025, c = 1500 m/s) above, squares of
+    23.6 m.  The 2.6 km height is split into ny_s + ny_f = 110 rows of 23.64 m so that the
+    interface is a row line: it lies at y = 7.3 m instead of y = 0 (68 rows of granite below,
+    42 of water above)."""
+    ny = ny_s + ny_f
+    L, H = 3800.0, 2600.0
+    y0 = -1600.0
+    rng = np.random.default_rng(0)
+    m = _lattice_mesh(nx, ny, -L / 2, L / 2, y0, y0 + H, None, 0.0, rng)
+    y_int = y0 + ny_s * H / ny
+    bc = _barycentres(m)
+    m["medium"] = np.where(bc[:, 1] > y_int, FLUID, SOLID).astype(np.uint8)
+    return with_materials(m, rho_f=1025.0, c_f=1500.0, rho_s=2690.0, cp_s=6000.0, cs_s=3000.0)
+
+
+def pressure_pulse(mesh, k, center=(0.0, 200.0), sigma=50.0):
+    """Initial state with a Gaussian pressure bump exp(-|x - center|^2 / (2 sigma^2)) in the
+    fluid: the lowest (constant) coefficient of p per fluid cell, scaled by sqrt(area) (the
+    constant function of an orthonormal cell basis is 1/sqrt(area)); everything else zero.
+    External layout: per cell in input order, [p | m_x | m_y] (fluid) or [v_x | v_y | s]
+    (solid), N = (k+1)(k+2)/2 coefficients per field."""
+    N = (k + 1) * (k + 2) // 2
+    med = np.asarray(mesh["medium"])
+    per = np.where(med == FLUID, 3 * N, 5 * N)
+    off = np.concatenate([[0], np.cumsum(per)[:-1]])
+    xy, ptr, vtx = mesh["xy"], mesh["cell_ptr"], mesh["cell_vtx"]
+    U = np.zeros(int(per.sum()))
+    bc = _barycentres(mesh)
+    for c in np.flatnonzero(med == FLUID):
+        p = xy[vtx[ptr[c]:ptr[c + 1]]]
+        area = 0.5 * abs(np.dot(p[:, 0], np.roll(p[:, 1], -1)) - np.dot(p[:, 1], np.roll(p[:, 0], -1)))
+        r2 = (bc[c, 0] - center[0]) ** 2 + (bc[c, 1] - center[1]) ** 2
+        U[off[c]] = np.exp(-r2 / (2 * sigma ** 2)) * np.sqrt(area)
+    return U

@@ -58,3 +58,22 @@ def test_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=300)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_paper_bilayer_workload():
+    """The granite-water bilayer of the paper's timing table: 161 x 110 squares (6762 water, 10948
+    granite), 225,078 cell unknowns at k = 1, the interface on a row line, and the step counts
+    that reach T_f = 0.5 s at the paper's normalised steps (800 for k = 1, 2355 for k = 3)."""
+    from synth import meshes as M
+    b = _bench()
+    m = M.granite_water()
+    med = np.asarray(m["medium"])
+    assert len(med) == 17710 and int(np.sum(med == 0)) == 6762 and int(np.sum(med == 1)) == 10948
+    ys = m["xy"][m["cell_vtx"], 1].reshape(-1, 4)
+    y_int = -1600.0 + 68 * 2600.0 / 110
+    assert np.all(np.where(med == 0, ys.min(axis=1) >= y_int - 1e-9, ys.max(axis=1) <= y_int + 1e-9))
+    U = M.pressure_pulse(m, 1)
+    assert U.shape == (225078,) and np.all(U[np.cumsum(np.where(med == 0, 9, 15))[med == 1] - 15] == 0)
+    for k, n in ((1, 800), (3, 2355)):
+        dt = b.PAPER_BILAYER[k][0] * 23.6 / 6000.0
+        assert int(np.ceil(0.5 / dt - 1e-9)) == n
