@@ -179,6 +179,30 @@ hho_status hho_set_launch(hho_ctx *ctx, int32_t lanes);
 hho_status hho_set_tuning(hho_ctx *ctx, int32_t lanes, int32_t flags);
 hho_status hho_get_tuning(const hho_ctx *ctx, int32_t *lanes, int32_t *flags);
 
+/* Per-shot time steps: shot i advances with dt * scale[i] in every following hho_erk_step (and
+ * batch step) of the context: stage times t0 + (n + c_i) dt scale[i], receivers and energies per
+ * shot as before.  scale[S] (host, > 0 and finite, ARG otherwise); NULL resets every multiplier
+ * to 1.  hho_adjoint_step refuses a context with multipliers set. */
+hho_status hho_set_dt_scale(hho_ctx *ctx, const double *scale);
+
+/* CFL stability limit by the energy criterion of Algorithm algo_CFL (Sec. 5.1), with the shots of
+ * the context as simultaneous candidates.  Candidate step counts over [0, t_final]:
+ * N_0 = n_start, N_{j+1} = N_j - max(1, floor(delta N_j)), each run with dt = t_final / N_j from
+ * the states the shots hold on entry (set all shots to the same state for the paper's procedure),
+ * sources and loads as set on ctx.  A round advances S candidates in one launch sequence: N_max
+ * steps of the smallest dt, shot i with the multiplier N_max / N_i; candidate i is judged on the
+ * energies after its first N_i steps.  It is unstable when the energy exceeds (1 + eps) times
+ * the initial or the previous step's energy, or is not finite.  Rounds stop at the first
+ * unstable candidate (in order) or after max_rounds.  Outputs: n_stable = the last stable N (0
+ * if the first was unstable), n_unstable = the first unstable N (0 if none); tried[] and
+ * growth[] (capacity cap, may be NULL when cap = 0) the candidates judged, in order, with their
+ * largest relative energy increase (+inf when not finite); n_tried (may be NULL) their count.
+ * CFL* brackets follow as c dt / h.  On return the entry states are restored, the multipliers
+ * reset and the energy recording setting is as on entry. */
+hho_status hho_cfl_search(hho_ctx *ctx, double t_final, int32_t n_start, double delta, double eps,
+                          int32_t max_rounds, int32_t *n_stable, int32_t *n_unstable, int32_t *tried,
+                          double *growth, int32_t cap, int32_t *n_tried);
+
 /* Time step from the CFL condition (eq. CFL, Sec. 5.1): dt = factor * min over cells of
  * CFL*(s, k, shape) h_T / c_T.  CFL* is the paper's Table tab::ratio_geo value for the cell's
  * shape (triangle, square; five or more faces use the hexagon column), c_T the largest wave speed

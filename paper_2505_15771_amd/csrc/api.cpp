@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -103,6 +104,10 @@ struct hho_ctx {
     // Stage outputs stored with the non-temporal cache policy (chosen by hho_autotune: faster
     // for some large working sets, slower when the stage data stays in the last-level cache).
     int nt_stores = 0;
+    // per-shot multipliers of dt (hho_set_dt_scale), [S] on the device; used when dt_scaled
+    double *dt_scale = nullptr;
+    bool dt_scaled = false;
+    void *cfl_save = nullptr;  // entry states of hho_cfl_search
     AdjWork adj;
 };
 
@@ -299,6 +304,7 @@ StageArgs<R> base_args(hho_ctx *ctx) {
     a.o_c0 = arena_off(ctx->arena, ctx->c0);
     a.o_mat = arena_off(ctx->arena, ctx->mat);
     a.nt_stores = ctx->nt_stores;
+    a.dt_scale = ctx->dt_scaled ? ctx->dt_scale : nullptr;
     return a;
 }
 
@@ -875,6 +881,26 @@ hho_status adjoint_sweep(hho_ctx *ctx, const std::vector<StageCoef> &co, int eve
     return HHO_OK;
 }
 
+// Steps of hho_erk_step without the closing stability check: graph replays of kGraphSteps steps,
+// then the remainder launched directly.  E0 receives the initial energies when recorded.
+hho_status run_steps(hho_ctx *ctx, double t0, double dt, int n_steps, std::vector<double> &E0) {
+    hho_status s;
+    if ((s = begin_steps(ctx, t0, dt, n_steps, E0))) return s;
+    const int full = n_steps / kGraphSteps, rem = n_steps % kGraphSteps;
+    if (full > 0) {
+        if ((s = ensure_graph(ctx))) return s;
+        for (int g = 0; g < full; ++g) HCK(hipGraphLaunch(ctx->gexec, ctx->stream));
+    }
+    if (rem > 0) {
+        s = dispatch(ctx, [&](auto kc, auto *r) {
+            using R = std::remove_pointer_t<decltype(r)>;
+            return enqueue_steps<decltype(kc)::value, R>(ctx, ctx->stream, rem);
+        });
+        if (s != HHO_OK) return s;
+    }
+    return HHO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1189,21 +1215,113 @@ hho_status hho_erk_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps) {
     hho_status s = set_device(ctx);
     if (s != HHO_OK) return s;
     std::vector<double> E0;
-    if ((s = begin_steps(ctx, t0, dt, n_steps, E0))) return s;
-    const int full = n_steps / kGraphSteps, rem = n_steps % kGraphSteps;
-    if (full > 0) {
-        if ((s = ensure_graph(ctx))) return s;
-        for (int g = 0; g < full; ++g) HCK(hipGraphLaunch(ctx->gexec, ctx->stream));
-    }
-    if (rem > 0) {
-        s = dispatch(ctx, [&](auto kc, auto *r) {
-            using R = std::remove_pointer_t<decltype(r)>;
-            return enqueue_steps<decltype(kc)::value, R>(ctx, ctx->stream, rem);
-        });
-        if (s != HHO_OK) return s;
-    }
+    if ((s = run_steps(ctx, t0, dt, n_steps, E0))) return s;
     return end_steps(ctx, n_steps, E0);
 }
+
+hho_status hho_set_dt_scale(hho_ctx *ctx, const double *scale) {
+    if (!ctx) return HHO_ERR_ARG;
+    const int S = ctx->plan.S;
+    if (!scale) {
+        if (ctx->dt_scaled) ctx->version++;
+        ctx->dt_scaled = false;
+        return HHO_OK;
+    }
+    for (int i = 0; i < S; ++i)
+        if (!(scale[i] > 0.0) || !std::isfinite(scale[i])) {
+            ctx->err = "set_dt_scale: multipliers must be finite and > 0";
+            return HHO_ERR_ARG;
+        }
+    hho_status s = set_device(ctx);
+    if (s != HHO_OK) return s;
+    if (!ctx->dt_scale && (s = dalloc(ctx, (void **)&ctx->dt_scale, (size_t)S * sizeof(double)))) return s;
+    HCK(hipMemcpyAsync(ctx->dt_scale, scale, (size_t)S * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HCK(hipStreamSynchronize(ctx->stream));
+    if (!ctx->dt_scaled) ctx->version++;
+    ctx->dt_scaled = true;
+    return HHO_OK;
+}
+
+hho_status hho_cfl_search(hho_ctx *ctx, double t_final, int32_t n_start, double delta, double eps,
+                          int32_t max_rounds, int32_t *n_stable, int32_t *n_unstable, int32_t *tried,
+                          double *growth, int32_t cap, int32_t *n_tried) {
+    if (!ctx) return HHO_ERR_ARG;
+    if (!(t_final > 0.0) || !std::isfinite(t_final) || n_start < 1 || !(delta > 0.0) || !(delta < 1.0) ||
+        !(eps > 0.0) || max_rounds < 1 || !n_stable || !n_unstable || cap < 0 || (cap > 0 && (!tried || !growth))) {
+        ctx->err = "cfl_search: t_final > 0, n_start >= 1, 0 < delta < 1, eps > 0, max_rounds >= 1 required";
+        return HHO_ERR_ARG;
+    }
+    hho_status s = set_device(ctx);
+    if (s != HHO_OK) return s;
+    const int S = ctx->plan.S;
+    const size_t sbytes = (size_t)ctx->rows * ctx->LT * ctx->rsize;
+    if (!ctx->cfl_save && (s = dalloc(ctx, &ctx->cfl_save, sbytes))) return s;
+    HCK(hipMemcpyAsync(ctx->cfl_save, ctx->U, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+    const int keep_energy = ctx->record_energy;
+    if (!keep_energy) {
+        ctx->record_energy = 1;
+        ctx->version++;
+    }
+    *n_stable = 0;
+    *n_unstable = 0;
+    int count = 0;
+    long long next = n_start;
+    std::vector<double> scale(S), E;
+    for (int round = 0; round < max_rounds && *n_unstable == 0 && next >= 1 && s == HHO_OK; ++round) {
+        // this round's candidates: N_j, N_{j+1} = N_j - max(1, floor(delta N_j)), ...
+        std::vector<int> N;
+        for (int i = 0; i < S && next >= 1; ++i) {
+            N.push_back((int)next);
+            next -= std::max<long long>(1, (long long)std::floor(delta * (double)next));
+        }
+        const int nmax = N[0];
+        for (int i = 0; i < S; ++i) scale[i] = i < (int)N.size() ? (double)nmax / N[i] : 1.0;
+        if ((s = hho_set_dt_scale(ctx, scale.data()))) break;
+        HCK(hipMemcpyAsync(ctx->U, ctx->cfl_save, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+        ctx->traces_valid = false;
+        std::vector<double> E0;
+        if ((s = run_steps(ctx, 0.0, t_final / nmax, nmax, E0))) break;
+        E.resize((size_t)nmax * S);
+        HCK(hipMemcpyAsync(E.data(), ctx->e_hist, E.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HCK(hipStreamSynchronize(ctx->stream));
+        // Algorithm algo_CFL: relative energy increase over the initial and the previous energy
+        for (size_t i = 0; i < N.size(); ++i) {
+            double g = 0.0, prev = E0[i];
+            bool bad = !(E0[i] > 0.0) || !std::isfinite(E0[i]);
+            for (int n = 0; n < N[i] && !bad; ++n) {
+                const double e = E[(size_t)n * S + i];
+                if (!std::isfinite(e)) {
+                    bad = true;
+                    break;
+                }
+                g = std::max(g, std::max((e - E0[i]) / E0[i], (e - prev) / prev));
+                prev = e;
+            }
+            if (bad) g = std::numeric_limits<double>::infinity();
+            if (count < cap) {
+                tried[count] = N[i];
+                growth[count] = g;
+            }
+            ++count;
+            if (g > eps) {
+                *n_unstable = N[i];
+                break;
+            }
+            *n_stable = N[i];
+        }
+    }
+    if (n_tried) *n_tried = count;
+    const hho_status s2 = hho_set_dt_scale(ctx, nullptr);
+    if (!keep_energy) {
+        ctx->record_energy = 0;
+        ctx->version++;
+    }
+    HCK(hipMemcpyAsync(ctx->U, ctx->cfl_save, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+    HCK(hipStreamSynchronize(ctx->stream));
+    ctx->traces_valid = false;
+    return s != HHO_OK ? s : s2;
+}
+
 
 hho_status hho_adjoint_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps, int32_t ckpt_every,
                             const double *d_obs, double *J, double *grad) {
@@ -1211,6 +1329,10 @@ hho_status hho_adjoint_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps,
     if (n_steps < 1 || !(dt > 0.0) || !std::isfinite(t0) || ckpt_every < 0 || !J || !grad ||
         (ctx->nrec > 0 && !d_obs)) {
         ctx->err = "adjoint_step: n_steps >= 1, dt > 0, ckpt_every >= 0, J, grad (and d_obs with receivers) required";
+        return HHO_ERR_ARG;
+    }
+    if (ctx->dt_scaled) {
+        ctx->err = "adjoint_step: per-shot time-step multipliers are set (hho_set_dt_scale); reset them first";
         return HHO_ERR_ARG;
     }
     std::vector<StageCoef> co;

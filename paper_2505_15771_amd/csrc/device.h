@@ -66,6 +66,8 @@ struct StageArgs {
     R *Yq;
     int first, last;
     int nt_stores;        // stage outputs with the non-temporal cache policy (large working sets)
+    // per-shot multiplier of the clock's dt ([S], float64; null: every shot steps with dt)
+    const double *dt_scale;
     // point sources
     const int32_t *src_first;  // [n_ic], -1 = none
     const SrcDev *src;

@@ -85,8 +85,8 @@ __device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> 
 // so the compiler cannot move a load above an earlier store.
 template <int ND, typename R, bool KEEP, int POL>
 __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, const R *y,
-                                          const R *kv, R *out, const R *uk, const R *dk) {
-    const R dt = R(uni(a.clock)->dt);
+                                          const R *kv, R *out, const R *uk, const R *dk, int shot) {
+    const R dt = R(shot_dt(a, shot));
     R u[ND], din[ND];
     const bool need_d = a.last ? a.cd != R(0) : (a.cY != R(0) || a.q_write);
     if (KEEP) {
@@ -247,7 +247,7 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
     }
     // loads F_T(t)
     for (int m = 0; m < a.nterms; ++m) {
-        const R w = R(sin(a.omega[m] * stage_time(a) + a.phase[m]));
+        const R w = R(sin(a.omega[m] * stage_time(a, shot) + a.phase[m]));
         const int gr = m * 5 * N;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
@@ -260,7 +260,7 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
         for (int e = a.src_first[ic]; e >= 0;) {
             const SrcDev &s = a.src[e];
             if (s.shot == shot) {
-                const R w = R(s.amp * ricker(stage_time(a), s.f0, s.t0) * s.dirx);
+                const R w = R(s.amp * ricker(stage_time(a, shot), s.f0, s.t0) * s.dirx);
 #pragma unroll
                 for (int b = 0; b < N; ++b) rp[b] += w * R(s.phi[b]);
             }
@@ -275,7 +275,7 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
         kv[N + b] = irho * rmx[b];
         kv[2 * N + b] = irho * rmy[b];
     }
-    rk_update<3 * N, R, KEEP, POL>(a, B, boff, y, kv, nw, uk, dk);
+    rk_update<3 * N, R, KEEP, POL>(a, B, boff, y, kv, nw, uk, dk, shot);
     const R *np = nw, *nmx = nw + N, *nmy = nw + 2 * N;
     if (STORE) store_recompute<K, NF, 3 * N, R, NF, 1>(a, lk, boff, y, kv, fv);
     fluid_traces<K, NF, R, POL>(a, B, tb, nF, lk, boff, np, nmx, nmy, tau);
@@ -426,7 +426,7 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
         }
     }
     for (int m = 0; m < a.nterms; ++m) {
-        const R w = R(sin(a.omega[m] * stage_time(a) + a.phase[m]));
+        const R w = R(sin(a.omega[m] * stage_time(a, shot) + a.phase[m]));
         const int gr = m * 5 * N;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
@@ -441,7 +441,7 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
         for (int e = a.src_first[ic]; e >= 0;) {
             const SrcDev &s = a.src[e];
             if (s.shot == shot) {
-                const double w = s.amp * ricker(stage_time(a), s.f0, s.t0);
+                const double w = s.amp * ricker(stage_time(a, shot), s.f0, s.t0);
                 const R wx = R(w * s.dirx), wy = R(w * s.diry);
 #pragma unroll
                 for (int b = 0; b < N; ++b) {
@@ -461,7 +461,7 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
         kv[3 * N + b] = lam * rs1[b] + l2m * rs2[b];
         kv[4 * N + b] = tmu * rs3[b];
     }
-    rk_update<5 * N, R, KEEP, POL>(a, B, boff, y, kv, nw, uk, dk);
+    rk_update<5 * N, R, KEEP, POL>(a, B, boff, y, kv, nw, uk, dk, shot);
     const R *nvx = nw, *nvy = nw + N, *ns1 = nw + 2 * N, *ns2 = nw + 3 * N, *ns3 = nw + 4 * N;
     if (STORE) store_recompute<K, NF, 5 * N, R, NF, 2>(a, lk, boff, y, kv, fv);
     solid_traces<K, NF, R, POL>(a, B, tb, nF, lk, boff, nvx, nvy, ns1, ns2, ns3, tau, itau);

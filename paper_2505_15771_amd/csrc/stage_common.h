@@ -162,10 +162,18 @@ __device__ __forceinline__ Bufs<R> make_bufs(const StageArgs<R> &a) {
     return b;
 }
 
+// Time step of a shot: the clock's dt, times the shot's multiplier when one is set.
 template <typename R>
-__device__ __forceinline__ double stage_time(const StageArgs<R> &a) {
+__device__ __forceinline__ double shot_dt(const StageArgs<R> &a, int shot) {
+    const double dt = uni(a.clock)->dt;
+    return a.dt_scale ? dt * a.dt_scale[shot] : dt;
+}
+
+// Time of the current stage of a shot: t_n + c dt with t_n = t0 + step dt.
+template <typename R>
+__device__ __forceinline__ double stage_time(const StageArgs<R> &a, int shot) {
     const HHO_CONST Clock *c = uni(a.clock);
-    return c->t0 + ((double)c->step + a.c) * c->dt;
+    return c->t0 + ((double)c->step + a.c) * shot_dt(a, shot);
 }
 
 template <typename R>

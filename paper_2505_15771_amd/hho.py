@@ -61,6 +61,10 @@ EXPORTS = {
     "hho_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "hho_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "hho_dt_cfl": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double)]),
+    "hho_set_dt_scale": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "hho_cfl_search": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_int32,
+                                 C.POINTER(C.c_int32)]),
     "hho_adjoint_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_void_p,
                                    C.POINTER(C.c_double), C.c_void_p]),
     "hho_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
@@ -296,6 +300,27 @@ class Engine:
         lanes, flags = C.c_int32(), C.c_int32()
         self._call(self.lib.hho_get_tuning, C.byref(lanes), C.byref(flags))
         return lanes.value, flags.value
+
+    def set_dt_scale(self, scale=None):
+        """Per-shot multipliers of dt (None: all 1)."""
+        if scale is None:
+            self._call(self.lib.hho_set_dt_scale, None)
+        else:
+            sc = np.ascontiguousarray(scale, dtype=np.float64)
+            if sc.shape != (self.n_shots,):
+                raise ValueError("one multiplier per shot")
+            self._call(self.lib.hho_set_dt_scale, _ptr(sc))
+
+    def cfl_search(self, t_final, n_start, delta=0.01, eps=0.05, max_rounds=100, cap=4096):
+        """Algorithm algo_CFL with the shots as simultaneous candidates (hho_cfl_search): returns
+        (last stable N, first unstable N, [(N, largest relative energy increase), ...])."""
+        ns, nu, cnt = C.c_int32(), C.c_int32(), C.c_int32()
+        tried = np.zeros(cap, np.int32)
+        growth = np.zeros(cap)
+        self._call(self.lib.hho_cfl_search, float(t_final), int(n_start), float(delta), float(eps),
+                   int(max_rounds), C.byref(ns), C.byref(nu), _ptr(tried), _ptr(growth), int(cap), C.byref(cnt))
+        m = min(cnt.value, cap)
+        return ns.value, nu.value, list(zip(tried[:m].tolist(), growth[:m].tolist()))
 
     def dt_cfl(self, factor=1.0):
         """CFL-limited time step (eq. CFL with the paper's CFL* per cell shape) times factor."""

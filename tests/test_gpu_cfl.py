@@ -1,0 +1,83 @@
+"""GPU tests of per-shot time steps (hho_set_dt_scale) and of the batched search of Algorithm
+algo_CFL (hho_cfl_search) against the oracle's sequential search (oracle/cfl.py)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from synth import meshes as M
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_per_shot_time_steps(dtype, tol):
+    """Three shots with multipliers 1, 0.5, 0.3 of dt (a Ricker source in each, so the stage
+    times matter too) against the oracle stepping each with its own dt; resetting the
+    multipliers restores the common dt."""
+    from oracle import Oracle
+    from paper_2505_15771_amd import Engine
+    say("case: per-shot dt, %s" % dtype)
+    mesh = M.hanging_square(8, seed=21)
+    o = Oracle(mesh, 2)
+    o.set_point_sources([[0.4, 0.3]], [[0.0, 1.0]], 10.0, 0.05, 1.0)
+    e = Engine(mesh, 2, dtype=dtype, n_shots=3)
+    scales = [1.0, 0.5, 0.3]
+    dt = e.dt_cfl(0.5)
+    U0 = [np.random.default_rng(600 + i).standard_normal(o.ndof) for i in range(3)]
+    for sh in range(3):
+        e.set_state(U0[sh], shot=sh)
+        e.set_sources(sh, [[0.4, 0.3]], [[0.0, 1.0]], 10.0, 0.05, 1.0)
+    e.set_dt_scale(scales)
+    e.erk_step(0.01, dt, 9)
+    for sh in range(3):
+        ref = o.erk(U0[sh], 0.01, dt * scales[sh], 9)
+        err = rel(e.get_state(sh), ref)
+        say("shot", sh, "rel L2", err)
+        assert err < tol
+    e.set_dt_scale(None)
+    for sh in range(3):
+        e.set_state(U0[sh], shot=sh)
+    e.erk_step(0.0, dt, 3)
+    assert rel(e.get_state(2), o.erk(U0[2], 0.0, dt, 3)) < tol
+    with pytest.raises(Exception):
+        e.set_dt_scale([1.0, 0.0, 1.0])
+    e.close()
+
+
+@pytest.mark.parametrize("s,shots", [(4, 8), (2, 5)])
+def test_cfl_search_matches_oracle(s, shots):
+    """hho_cfl_search with several rounds of simultaneous candidates gives the oracle's
+    sequential bracket of Algorithm algo_CFL (same last stable and first unstable step count)
+    and the same energy increase for every candidate judged (float64)."""
+    from oracle import Oracle
+    from oracle.cfl import cfl_bracket
+    from paper_2505_15771_amd import Engine
+    say("case: cfl search s=%d shots=%d" % (s, shots))
+    mesh = M.with_materials(M.bilayer_vertical(4, p_split=0.5, seed=3))
+    o = Oracle(mesh, 1)
+    U0 = np.random.default_rng(44).standard_normal(o.ndof)
+    n_start = 90 if s == 4 else 110
+    ns, nu, tried = cfl_bracket(o, U0, 1.0, n_start, delta=0.02, s=s)
+    say("oracle bracket", ns, nu, "after", len(tried), "runs")
+    e = Engine(mesh, 1, rk_stages=s, n_shots=shots)
+    for sh in range(shots):
+        e.set_state(U0, shot=sh)
+    gns, gnu, gtried = e.cfl_search(1.0, n_start, delta=0.02, eps=0.05)
+    say("gpu bracket", gns, gnu, "after", len(gtried), "candidates")
+    assert (gns, gnu) == (ns, nu)
+    assert [t[0] for t in gtried] == [t[0] for t in tried]
+    for (n1, g1), (n2, g2) in zip(gtried, tried):
+        assert (math.isinf(g1) and math.isinf(g2)) or abs(g1 - g2) <= 1e-9 * max(1.0, abs(g2)), (n1, g1, g2)
+    assert rel(e.get_state(0), U0) < 1e-15   # entry states restored
+    e.close()

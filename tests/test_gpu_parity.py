@@ -82,6 +82,28 @@ def test_random_state_hanging_hybrid(k, s):
     assert err < TOL64
 
 
+@pytest.mark.parametrize("eta_f,eta_s,stab_speed", [(0.3, 3.0, 0), (2.0, 0.5, 1), (0.8, 1.5, 1)])
+@pytest.mark.parametrize("dtype,tol", [("f64", TOL64), ("f32", 1e-5)])
+def test_stabilisation_weights_and_speed(eta_f, eta_s, stab_speed, dtype, tol):
+    """The stabilisation weights eta^f, eta^s (the paper's sweep of Sec. 5.1) and the solid
+    stabilisation speed (c_P or c_S) change tau and every coefficient derived from it on the
+    host; ERK(3) steps on a hanging-node hybrid mesh match the oracle built with the same values."""
+    say("case: eta_f=%g eta_s=%g stab_speed=%d %s" % (eta_f, eta_s, stab_speed, dtype))
+    mesh = M.with_materials(M.unit_square(10, p_split=0.5, seed=17,
+                                          refine=np.random.default_rng(18).random((10, 10)) < 0.3),
+                            perturb=0.1, seed=19)
+    o = oracle(mesh, 2, eta_f=eta_f, eta_s=eta_s, stab_speed=stab_speed)
+    U0 = np.random.default_rng(77).standard_normal(o.ndof)
+    dt = 0.2 * 0.087 * 0.05 / math.sqrt(3.0)
+    ref = o.erk(U0, 0.0, dt, 6, s=3)
+    e = engine(mesh, 2, rk_stages=3, eta_f=eta_f, eta_s=eta_s, stab_speed=stab_speed, dtype=dtype)
+    e.set_state(U0)
+    e.erk_step(0.0, dt, 6)
+    err = rel(e.get_state(), ref)
+    say("rel L2 =", err)
+    assert err < tol
+
+
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_float32_stepping(k):
     """float32 matvecs and accumulation against the float64 oracle."""
