@@ -256,6 +256,49 @@ def run_paper_bilayer(k, dtype="f64"):
     return out
 
 
+def run_cfl(k, n=32, shots=32, delta=0.01, eps=0.05):
+    """Algorithm algo_CFL (Sec. 5.1) on the two-material CFL geometry with h = 1/n, ERK(4),
+    T_f = 1, from a seeded random state (every mode excited): hho_cfl_search with `shots`
+    simultaneous candidates, against the paper's procedure run one candidate at a time on the
+    same GPU (one-shot context, hho_erk_step per candidate, stopping at the first unstable)."""
+    import torch
+    from paper_2505_15771_amd import Engine, Unstable
+    mesh = M.with_materials(M.bilayer_vertical(n))
+    e = Engine(mesh, k, n_shots=shots)
+    U0 = M.random_state(np.full(1, e.n_dof), 9000 + k)
+    n_start = int(np.ceil(1.0 / (0.7 * e.dt_cfl(1.0))))
+    for sh in range(shots):
+        e.set_state(U0, shot=sh)
+    e.cfl_search(1.0, n_start, delta, eps, max_rounds=1)  # warm-up (graph capture, workspace)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ns, nu, tried = e.cfl_search(1.0, n_start, delta, eps)
+    t_batched = time.perf_counter() - t0
+    e.close()
+    one = Engine(mesh, k, record_energy=True)
+    one.set_state(U0)
+    one.erk_step(0.0, 1.0 / n_start, 40)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_ns, seq_nu = 0, 0
+    for N, _ in tried:
+        one.set_state(U0)
+        try:
+            one.erk_step(0.0, 1.0 / N, N)
+        except Unstable:
+            seq_nu = N
+            break
+        seq_ns = N
+    t_seq = time.perf_counter() - t0
+    one.close()
+    c, h = np.sqrt(3.0), 1.0 / n
+    return dict(workload="CFL* search (Algorithm algo_CFL), two-material CFL geometry h = 1/%d, k = %d, ERK(4), "
+                         "random initial state, %d candidates per launch" % (n, k, shots),
+                cfl_bracket=[c / nu / h if nu else None, c / ns / h if ns else None], n_stable=ns, n_unstable=nu,
+                candidates=len(tried), batched_s=t_batched, one_at_a_time_s=t_seq,
+                speedup=t_seq / t_batched, same_bracket=(seq_ns, seq_nu) == (ns, nu))
+
+
 def run_batch(steps=200, warmup=4):
     """Sixteen hybrid meshes of 20k-300k cells (k = 1, 2, 3 in turn), four Ricker shots each at
     seeded positions, float32 stepping with the float64 energy check, all advanced by one batch
@@ -345,7 +388,7 @@ def main():
     ap.add_argument("--shots", type=int, default=1)
     ap.add_argument("--variants", type=int, default=1, help="also time the float64 / k=3 / batched variants")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--only", choices=("adjoint", "basin", "batch", "paper"), default=None,
+    ap.add_argument("--only", choices=("adjoint", "basin", "batch", "paper", "cfl"), default=None,
                     help="run one extra workload alone and print its JSON line (for profiling)")
     ap.add_argument("--only-steps", type=int, default=200)
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -374,7 +417,8 @@ def main():
         fn = {"adjoint": lambda: run_adjoint(2, args.dtype, steps=args.only_steps, ckpt=50),
               "basin": lambda: run_basin(args.dtype, steps=args.only_steps),
               "batch": lambda: run_batch(steps=args.only_steps),
-              "paper": lambda: [run_paper_bilayer(1), run_paper_bilayer(3)]}[args.only]
+              "paper": lambda: [run_paper_bilayer(1), run_paper_bilayer(3)],
+              "cfl": lambda: [run_cfl(k_) for k_ in (1, 2, 3)]}[args.only]
         print(json.dumps(fn()), flush=True)
         return
     mesh = M.hybrid_square(256)
@@ -404,6 +448,10 @@ def main():
         workloads.append(v)
         for k_ in (1, 3):
             v = run_paper_bilayer(k_)
+            print("workload", json.dumps(v), file=sys.stderr, flush=True)
+            workloads.append(v)
+        for k_ in (1, 2, 3):
+            v = run_cfl(k_)
             print("workload", json.dumps(v), file=sys.stderr, flush=True)
             workloads.append(v)
     cpu = cpu_baseline(mesh, args.k) if args.cpu_baseline else None
