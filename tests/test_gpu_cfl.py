@@ -81,3 +81,38 @@ def test_cfl_search_matches_oracle(s, shots):
         assert (math.isinf(g1) and math.isinf(g2)) or abs(g1 - g2) <= 1e-9 * max(1.0, abs(g2)), (n1, g1, g2)
     assert rel(e.get_state(0), U0) < 1e-15   # entry states restored
     e.close()
+
+
+def test_cfl_search_edges_and_errors():
+    """A first candidate that is already unstable gives (0, n_start); a search whose rounds run
+    out reports no unstable candidate; bad arguments are refused without changing the state;
+    the adjoint refuses a context with per-shot multipliers."""
+    from paper_2505_15771_amd import Engine, HHOError
+    mesh = M.with_materials(M.bilayer_vertical(3))
+    e = Engine(mesh, 1, n_shots=4)
+    U0 = np.random.default_rng(5).standard_normal(e.n_dof)
+    for sh in range(4):
+        e.set_state(U0, shot=sh)
+    dt_big = 3.0 * e.dt_cfl(1.0)
+    n_unstable = max(1, int(1.0 / dt_big))
+    ns, nu, tried = e.cfl_search(1.0, n_unstable, delta=0.01)
+    say("too large a step:", ns, nu, tried[:2])
+    assert (ns, nu) == (0, n_unstable) and len(tried) == 1
+    n_safe = int(np.ceil(1.0 / (0.2 * e.dt_cfl(1.0))))
+    ns, nu, tried = e.cfl_search(1.0, n_safe, delta=0.001, max_rounds=1)
+    assert nu == 0 and ns == tried[-1][0] and len(tried) == 4
+    for bad in (dict(t_final=0.0, n_start=10), dict(t_final=1.0, n_start=0),
+                dict(t_final=1.0, n_start=10, delta=1.5), dict(t_final=1.0, n_start=10, eps=0.0)):
+        with pytest.raises(HHOError):
+            e.cfl_search(**bad)
+    assert rel(e.get_state(3), U0) < 1e-15
+    e.close()
+    a = Engine(mesh, 1)
+    a.set_state(U0)
+    a.set_dt_scale([0.5])
+    with pytest.raises(HHOError):
+        a.adjoint(0.0, a.dt_cfl(0.5), 4)
+    a.set_dt_scale(None)
+    J, g = a.adjoint(0.0, a.dt_cfl(0.5), 4)
+    assert np.isfinite(J) and np.all(np.isfinite(g))
+    a.close()
