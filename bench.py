@@ -95,13 +95,14 @@ def moved_bytes_per_step(mesh, k, word, shots):
     per cell unknown per shot (stage 1 reads U^n and writes D_1; stage 2 reads D_1 and U^n and
     writes D_2 and the partial sum Q; stage 3 reads D_2 and U^n and writes D_3; stage 4 reads D_3,
     U^n and Q and writes U^{n+1}), plus per stage the per-cell metadata in 4-byte words: one face
-    link per face, the material scalars (3 fluid, 5 solid) and one coefficient per interior face.
+    link per face, the material scalars the kernel loads (3 fluid: tau, kappa, 1/rho; 6 solid: tau,
+    1/tau, 1/rho, lambda + 2 mu, lambda, 2 mu) and one coefficient per interior face.
     The face-trace exchange between neighbouring cells is not counted."""
     N = (k + 1) * (k + 2) // 2
     med = np.asarray(mesh["medium"])
     nf = np.diff(mesh["cell_ptr"])
     ndof = int(np.sum(np.where(med == 0, 3, 5))) * N
-    meta_cells = int(np.sum(4 * nf + 4 * np.where(med == 0, 3, 5)))
+    meta_cells = int(np.sum(4 * nf + 4 * np.where(med == 0, 3, 6)))
     _, n_interior, _ = _faces(mesh)
     return word * 13 * ndof * shots + 4 * (meta_cells + 4 * n_interior), ndof
 

@@ -43,15 +43,15 @@ def test_algorithmic_bytes_two_squares():
 
 def test_moved_bytes_two_squares():
     """The same mesh with the stage kernel's own traffic: 13 words per unknown per shot and per
-    stage one 4-byte link per cell face (8), the kernel's material scalars (3 + 5) and one
-    coefficient for the single interior face."""
+    stage one 4-byte link per cell face (8), the material scalars the kernel loads (3 + 6) and
+    one coefficient for the single interior face."""
     b = _bench()
     mesh = _two_squares()
     for word in (4, 8):
         for shots in (1, 3):
             got, ndof = b.moved_bytes_per_step(mesh, 1, word, shots)
             assert ndof == 24
-            assert got == word * 13 * 24 * shots + 4 * (4 * (8 + 8) + 4 * 1)
+            assert got == word * 13 * 24 * shots + 4 * (4 * (8 + 9) + 4 * 1)
 
 
 def test_refuses_more_than_one_gpu():
