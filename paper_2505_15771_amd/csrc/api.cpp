@@ -1265,51 +1265,58 @@ hho_status hho_cfl_search(hho_ctx *ctx, double t_final, int32_t n_start, double 
     *n_stable = 0;
     *n_unstable = 0;
     int count = 0;
-    long long next = n_start;
-    std::vector<double> scale(S), E;
-    for (int round = 0; round < max_rounds && *n_unstable == 0 && next >= 1 && s == HHO_OK; ++round) {
-        // this round's candidates: N_j, N_{j+1} = N_j - max(1, floor(delta N_j)), ...
-        std::vector<int> N;
-        for (int i = 0; i < S && next >= 1; ++i) {
-            N.push_back((int)next);
-            next -= std::max<long long>(1, (long long)std::floor(delta * (double)next));
-        }
-        const int nmax = N[0];
-        for (int i = 0; i < S; ++i) scale[i] = i < (int)N.size() ? (double)nmax / N[i] : 1.0;
-        if ((s = hho_set_dt_scale(ctx, scale.data()))) break;
-        HCK(hipMemcpyAsync(ctx->U, ctx->cfl_save, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
-        ctx->traces_valid = false;
-        std::vector<double> E0;
-        if ((s = run_steps(ctx, 0.0, t_final / nmax, nmax, E0))) break;
-        E.resize((size_t)nmax * S);
-        HCK(hipMemcpyAsync(E.data(), ctx->e_hist, E.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-        HCK(hipStreamSynchronize(ctx->stream));
-        // Algorithm algo_CFL: relative energy increase over the initial and the previous energy
-        for (size_t i = 0; i < N.size(); ++i) {
-            double g = 0.0, prev = E0[i];
-            bool bad = !(E0[i] > 0.0) || !std::isfinite(E0[i]);
-            for (int n = 0; n < N[i] && !bad; ++n) {
-                const double e = E[(size_t)n * S + i];
-                if (!std::isfinite(e)) {
-                    bad = true;
+    // the rounds (a device failure returns from here; the restore below runs in every case)
+    auto rounds = [&]() -> hho_status {
+        long long next = n_start;
+        std::vector<double> scale(S), E;
+        hho_status st = HHO_OK;
+        for (int round = 0; round < max_rounds && *n_unstable == 0 && next >= 1; ++round) {
+            // this round's candidates: N_j, N_{j+1} = N_j - max(1, floor(delta N_j)), ...
+            std::vector<int> N;
+            for (int i = 0; i < S && next >= 1; ++i) {
+                N.push_back((int)next);
+                next -= std::max<long long>(1, (long long)std::floor(delta * (double)next));
+            }
+            const int nmax = N[0];
+            for (int i = 0; i < S; ++i) scale[i] = i < (int)N.size() ? (double)nmax / N[i] : 1.0;
+            if ((st = hho_set_dt_scale(ctx, scale.data()))) return st;
+            HCK(hipMemcpyAsync(ctx->U, ctx->cfl_save, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+            ctx->traces_valid = false;
+            std::vector<double> E0;
+            if ((st = run_steps(ctx, 0.0, t_final / nmax, nmax, E0))) return st;
+            E.resize((size_t)nmax * S);
+            HCK(hipMemcpyAsync(E.data(), ctx->e_hist, E.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+            HCK(hipStreamSynchronize(ctx->stream));
+            // Algorithm algo_CFL: relative energy increase over the initial and the previous energy
+            for (size_t i = 0; i < N.size(); ++i) {
+                double g = 0.0, prev = E0[i];
+                bool bad = !(E0[i] > 0.0) || !std::isfinite(E0[i]);
+                for (int n = 0; n < N[i] && !bad; ++n) {
+                    const double e = E[(size_t)n * S + i];
+                    if (!std::isfinite(e)) {
+                        bad = true;
+                        break;
+                    }
+                    g = std::max(g, std::max((e - E0[i]) / E0[i], (e - prev) / prev));
+                    prev = e;
+                }
+                if (bad) g = std::numeric_limits<double>::infinity();
+                if (count < cap) {
+                    tried[count] = N[i];
+                    growth[count] = g;
+                }
+                ++count;
+                if (g > eps) {
+                    *n_unstable = N[i];
                     break;
                 }
-                g = std::max(g, std::max((e - E0[i]) / E0[i], (e - prev) / prev));
-                prev = e;
+                *n_stable = N[i];
             }
-            if (bad) g = std::numeric_limits<double>::infinity();
-            if (count < cap) {
-                tried[count] = N[i];
-                growth[count] = g;
-            }
-            ++count;
-            if (g > eps) {
-                *n_unstable = N[i];
-                break;
-            }
-            *n_stable = N[i];
         }
-    }
+        return st;
+    };
+    s = rounds();
     if (n_tried) *n_tried = count;
     const hho_status s2 = hho_set_dt_scale(ctx, nullptr);
     if (!keep_energy) {
