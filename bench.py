@@ -214,6 +214,40 @@ def run_basin(dtype, steps=100, warmup=5):
     return out
 
 
+def run_precision(k=2, steps=2000):
+    """Float32 error of the paper-sized run: the 256 x 256 hybrid workload (Ricker source, eight
+    pressure receivers at y = 0.75), `steps` steps at half the CFL step, stepped in float32 and in
+    float64 on the GPU (the float64 path equals the float64 oracle to ~1e-13, see the parity
+    tests); relative L2 error of the float32 state and receiver traces every 500 steps."""
+    from paper_2505_15771_amd import Engine
+    mesh = M.hybrid_square(256)
+    src, dirs = [[0.5, 0.25]], [[0.0, 1.0]]
+    rx = M.receiver_line(8, 0.75)
+    engines = {}
+    for dt_ in ("f64", "f32"):
+        e = Engine(mesh, k, dtype=dt_)
+        e.set_sources(0, src, dirs, 10.0, 0.12, 1.0)
+        e.set_receivers(rx, np.zeros(8, np.int32))
+        e.set_state(1e-3 * np.random.default_rng(2003).standard_normal(e.n_dof))
+        engines[dt_] = e
+    dt = engines["f64"].dt_cfl(0.5)
+    out = []
+    t = 0.0
+    for block in range(steps // 500):
+        tr = {}
+        for dt_, e in engines.items():
+            e.erk_step(t, dt, 500)
+            tr[dt_] = e.traces()
+        t += 500 * dt
+        a, b_ = engines["f32"].get_state(), engines["f64"].get_state()
+        out.append(dict(steps=500 * (block + 1), state=float(np.linalg.norm(a - b_) / np.linalg.norm(b_)),
+                        traces=float(np.linalg.norm(tr["f32"] - tr["f64"]) / np.linalg.norm(tr["f64"]))))
+    for e in engines.values():
+        e.close()
+    return dict(workload="float32 vs float64 error, 256x256 hybrid mesh, k=%d, Ricker source, %d steps" % (k, steps),
+                errors=out)
+
+
 PAPER_BILAYER = {1: (0.159, 161.0), 3: (0.054, 3322.0)}  # Table tab::cfl_cpu: ERK(4) dt~, CPU s
 
 
@@ -389,7 +423,7 @@ def main():
     ap.add_argument("--shots", type=int, default=1)
     ap.add_argument("--variants", type=int, default=1, help="also time the float64 / k=3 / batched variants")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--only", choices=("adjoint", "basin", "batch", "paper", "cfl"), default=None,
+    ap.add_argument("--only", choices=("adjoint", "basin", "batch", "paper", "cfl", "precision"), default=None,
                     help="run one extra workload alone and print its JSON line (for profiling)")
     ap.add_argument("--only-steps", type=int, default=200)
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -420,7 +454,8 @@ def main():
               "basin": lambda: run_basin(args.dtype, steps=args.only_steps),
               "batch": lambda: run_batch(steps=args.only_steps),
               "paper": lambda: [run_paper_bilayer(1), run_paper_bilayer(3)],
-              "cfl": lambda: [run_cfl(k_) for k_ in (1, 2, 3)]}[args.only]
+              "cfl": lambda: [run_cfl(k_) for k_ in (1, 2, 3)],
+              "precision": lambda: run_precision(steps=args.only_steps)}[args.only]
         print(json.dumps(fn()), flush=True)
         return
     mesh = M.hybrid_square(256)
@@ -456,6 +491,9 @@ def main():
             v = run_cfl(k_)
             print("workload", json.dumps(v), file=sys.stderr, flush=True)
             workloads.append(v)
+        v = run_precision()
+        print("workload", json.dumps(v), file=sys.stderr, flush=True)
+        workloads.append(v)
     cpu = cpu_baseline(mesh, args.k) if args.cpu_baseline else None
     # speed-ups over float64 single-shot stepping of the same workload on the same GPU
     speedups = {}
