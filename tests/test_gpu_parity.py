@@ -279,3 +279,41 @@ def test_full_size_float32_error_growth():
         eu, et = rel(e.get_state(), U), rel(e.traces(), tr)
         say("steps", 50 * (block + 1), "state", eu, "traces", et)
         assert eu < TOL32 and et < TOL32
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", TOL64), ("f32", 1e-5)])
+def test_mirrored_mesh(dtype, tol):
+    """The mirror-symmetric hybrid mesh of the oracle's symmetry pin (random cuts on one side,
+    reflected on the other, so every face is seen in both orientations): ERK(4) steps from a
+    random state match the oracle, and from mirror-symmetric data the GPU state stays symmetric
+    (compared through the oracle's point evaluation at mirrored points)."""
+    from test_oracle_pins import _mirrored_hybrid
+    say("case: mirrored hybrid mesh %s" % dtype)
+    mesh = _mirrored_hybrid()
+    o = oracle(mesh, 2)
+    e = engine(mesh, 2, dtype=dtype)
+    U0 = np.random.default_rng(31).standard_normal(o.ndof)
+    e.set_state(U0)
+    e.erk_step(0.0, 0.002, 12)
+    err = rel(e.get_state(), o.erk(U0, 0.0, 0.002, 12))
+    say("rel L2 =", err)
+    assert err < tol
+    g = lambda x, y: np.exp(-20 * (x - 0.5) ** 2) * np.sin(np.pi * y)
+    odd = lambda x, y: (x - 0.5) * np.exp(-10 * (x - 0.5) ** 2) * np.cos(2 * y)
+    S0 = o.project([g, odd, lambda x, y: g(x, y) * y],
+                   [odd, g, lambda x, y: g(x, y) * (1 + y), lambda x, y: np.cos(3 * y) * g(x, y), odd])
+    e.set_state(S0)
+    e.erk_step(0.0, 0.002, 12)
+    V = e.get_state()
+    parity = {0: [1, -1, 1], 1: [-1, 1, 1, 1, -1]}
+    worst, scale = 0.0, 0.0
+    for x, y in np.random.default_rng(8).uniform(0.02, 0.98, (100, 2)):
+        if abs(x - 0.5) < 1e-3 or abs(y - 0.5) < 1e-3:
+            continue
+        c1, a = o.point_values(V, x, y)
+        _, b = o.point_values(V, 1.0 - x, y)
+        worst = max(worst, float(np.max(np.abs(a - np.array(parity[int(o.medium[c1])]) * b))))
+        scale = max(scale, float(np.max(np.abs(a))))
+    say("symmetry defect", worst / scale)
+    assert worst <= (1e-12 if dtype == "f64" else 1e-5) * scale
+    e.close()

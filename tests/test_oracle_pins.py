@@ -375,3 +375,58 @@ def test_manufactured_convergence(k):
         errs.append(math.sqrt(o.mass_dot(U - Ue, U - Ue) / o.mass_dot(Ue, Ue)))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert rates[-1] > k + 0.5, (errs, rates)
+
+
+def _mirrored_hybrid(n=4, seed=5):
+    """A hybrid mesh of [0, 1/2] x [0, 1] (random diagonal cuts, interface y = 1/2) and its mirror
+    image across x = 1/2 (vertex order reversed to stay counter-clockwise), joined on x = 1/2:
+    a mesh that is mirror-symmetric although its vertex ids, face orientations and cell order are
+    not."""
+    half = M.unit_square(n, p_split=0.5, seed=seed)
+    xy = np.array(half["xy"], float).reshape(-1, 2)
+    xy[:, 0] *= 0.5
+    nv = len(xy)
+    mir = xy.copy()
+    mir[:, 0] = 1.0 - mir[:, 0]
+    on_axis = np.isclose(xy[:, 0], 0.5)
+    new_id = np.arange(nv) + nv
+    new_id[on_axis] = np.flatnonzero(on_axis)            # shared vertices on the axis
+    keep = ~on_axis
+    remap = np.full(nv, -1)
+    remap[keep] = nv + np.arange(int(keep.sum()))
+    remap[on_axis] = np.flatnonzero(on_axis)
+    ptr, vtx = np.asarray(half["cell_ptr"]), np.asarray(half["cell_vtx"])
+    cells2 = [remap[vtx[ptr[c]:ptr[c + 1]]][::-1] for c in range(len(ptr) - 1)]
+    all_xy = np.concatenate([xy, mir[keep]])
+    cell_vtx = np.concatenate([vtx] + cells2).astype(np.int32)
+    cell_ptr = np.concatenate([ptr, ptr[-1] + np.cumsum([len(c) for c in cells2])]).astype(np.int32)
+    medium = np.concatenate([half["medium"], half["medium"]]).astype(np.uint8)
+    return M.with_materials(dict(xy=all_xy, cell_ptr=cell_ptr, cell_vtx=cell_vtx, medium=medium))
+
+
+def test_mirror_symmetry():
+    """A mirror-symmetric mesh (random on one side, reflected on the other) with mirror-symmetric
+    initial data keeps a mirror-symmetric solution through ERK(4) steps (p, m_y, v_y, s_xx, s_yy
+    even and m_x, v_x, s_xy odd in x - 1/2): every face orientation, sign and face-basis flip is
+    exercised in both senses.  Compared at seeded points and their mirror images."""
+    from oracle import Oracle
+    mesh = _mirrored_hybrid()
+    o = Oracle(mesh, 2)
+    g = lambda x, y: np.exp(-20 * (x - 0.5) ** 2) * np.sin(np.pi * y)
+    odd = lambda x, y: (x - 0.5) * np.exp(-10 * (x - 0.5) ** 2) * np.cos(2 * y)
+    U0 = o.project([g, odd, lambda x, y: g(x, y) * y],
+                   [odd, g, lambda x, y: g(x, y) * (1 + y), lambda x, y: np.cos(3 * y) * g(x, y), odd])
+    U = o.erk(U0, 0.0, 0.002, 12)
+    parity = {0: [1, -1, 1], 1: [-1, 1, 1, 1, -1]}
+    rng = np.random.default_rng(7)
+    worst, scale = 0.0, 0.0
+    for x, y in rng.uniform(0.02, 0.98, (200, 2)):
+        if abs(x - 0.5) < 1e-3 or abs(y - 0.5) < 1e-3:
+            continue
+        c1, a = o.point_values(U, x, y)
+        c2, b = o.point_values(U, 1.0 - x, y)
+        sgn = np.array(parity[int(o.medium[c1])])
+        worst = max(worst, float(np.max(np.abs(a - sgn * b))))
+        scale = max(scale, float(np.max(np.abs(a))))
+    assert scale > 1e-3
+    assert worst <= 1e-12 * scale
