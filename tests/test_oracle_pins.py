@@ -404,6 +404,35 @@ def test_pure_acoustic_standing_wave(k):
     assert rates[-1] > k + 0.8, (errs, rates)   # measured 2.03 (k = 1), 3.04 (k = 2)
 
 
+def test_energy_balance_converges_fourth_order():
+    """Energy balance of the stabilised semi-discretisation: dE/dt = -D(U) with D the
+    stabilisation energy (the dissipation of the least-squares terms), so
+    E(T) + int_0^T D dt - E(0) vanishes for the exact flow.  Along ERK(4) steps, with the
+    integral by Simpson's rule on the step values, the residual must fall as dt^4 (ratio 16 per
+    halving) while about 10 % of the energy is dissipated: a wrong dissipation term, a wrong
+    energy weight or a time-integration defect leaves an O(1) or slower residual."""
+    m = M.with_materials(M.unit_square(4, p_split=0.5, seed=3), perturb=0.1, seed=4)
+    o = Oracle(m, 1)
+    U0 = o.project([lambda x, y: np.sin(3 * x) * np.cos(2 * y), lambda x, y: x * y, lambda x, y: np.cos(x)],
+                   [lambda x, y: y * y, lambda x, y: np.sin(x + y), lambda x, y: x, lambda x, y: np.cos(3 * y),
+                    lambda x, y: x * y])
+    E0, T = o.energy(U0), 0.2
+    res = []
+    for nst in (20, 40, 80):
+        dt = T / nst
+        U = U0.copy()
+        D = [o.stab_energy(U)]
+        for n in range(nst):
+            U = o.erk(U, n * dt, dt, 1)
+            D.append(o.stab_energy(U))
+        D = np.array(D)
+        integral = dt / 3 * (D[0] + D[-1] + 4 * D[1:-1:2].sum() + 2 * D[2:-1:2].sum())
+        res.append((o.energy(U) + integral - E0) / E0)
+        assert o.energy(U) < 0.95 * E0           # the run dissipates
+    assert res[0] / res[1] > 12 and res[1] / res[2] > 12, res
+    assert abs(res[2]) < 1e-5
+
+
 def _mirrored_hybrid(n=4, seed=5):
     """A hybrid mesh of [0, 1/2] x [0, 1] (random diagonal cuts, interface y = 1/2) and its mirror
     image across x = 1/2 (vertex order reversed to stay counter-clockwise), joined on x = 1/2:
