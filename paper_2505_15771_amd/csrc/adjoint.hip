@@ -110,10 +110,19 @@ __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<
         wk_p += (double)p[b] * (double)kp;
         wk_m -= (double)mx[b] * (double)kmx + (double)my[b] * (double)kmy;
     }
+    // issued for every face of the group without waiting for the links (the rows of a boundary
+    // face hold no values of this stage and are zeroed once the links have arrived)
 #pragma unroll
     for (int j = 0; j < NF; ++j)
 #pragma unroll
-        for (int i = 0; i < F; ++i) yf[j][i] = lk[j] < 0 ? R(0) : a.ffwd[(long long)((j * 2) * F + i) * LT + lane];
+        for (int i = 0; i < F; ++i) yf[j][i] = j < nF ? a.ffwd[(long long)((j * 2) * F + i) * LT + lane] : R(0);
+    // material derivatives of the gradient terms, read with the other loads
+    const double gm0 = gmv(a, 0, ic), gm1 = gmv(a, 1, ic), gm2 = gmv(a, 2, ic), gm3 = gmv(a, 3, ic);
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+#pragma unroll
+        for (int i = 0; i < F; ++i)
+            if (lk[j] < 0) yf[j][i] = R(0);
     // adjoint residual R_c(z) (interface coupling reversed) and the stabilisation pairing
     R rp[N], rmx[N], rmy[N], tp[N];
 #pragma unroll
@@ -195,8 +204,8 @@ __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<
         load_lambda<3 * N, R>(a, B, boff, lam, lac);
         g0 = a.gacc[lane], g1 = a.gacc[LT + lane];
     }
-    g0 -= gmv(a, 0, ic) * wk_p + wk_m + gmv(a, 2, ic) * stab;
-    g1 -= gmv(a, 1, ic) * wk_p + gmv(a, 3, ic) * stab;
+    g0 -= gm0 * wk_p + wk_m + gm2 * stab;
+    g1 -= gm1 * wk_p + gm3 * stab;
     a.gacc[lane] = g0;
     a.gacc[LT + lane] = g1;
     R mu[3 * N];
@@ -300,13 +309,26 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
         P22 -= (double)s2[b] * k3;
         P33 -= (double)s3[b] * k4;
     }
+    // issued for every face of the group without waiting for the links (zeroed below for
+    // boundary faces, whose rows hold no values of this stage)
 #pragma unroll
     for (int j = 0; j < NF; ++j)
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int i = 0; i < F; ++i)
-                yf[j][c][i] = lk[j] < 0 ? R(0) : a.ffwd[(long long)((j * 2 + c) * F + i) * LT + lane];
+                yf[j][c][i] = j < nF ? a.ffwd[(long long)((j * 2 + c) * F + i) * LT + lane] : R(0);
+    // material derivatives of the gradient terms, read with the other loads
+    double gm[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) gm[q] = gmv(a, q, ic);
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int i = 0; i < F; ++i)
+                if (lk[j] < 0) yf[j][c][i] = R(0);
     R rvx[N], rvy[N], rs1[N], rs2[N], rs3[N], tvx[N], tvy[N], hs3[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
@@ -420,9 +442,9 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
         load_lambda<5 * N, R>(a, B, boff, lam, lac);
         g0 = a.gacc[lane], g1 = a.gacc[LT + lane], g2 = a.gacc[2 * LT + lane];
     }
-    g0 -= wk_v + gmv(a, 0, ic) * stab;
-    g1 -= gmv(a, 3, ic) * (P11 + P12 + P21 + P22) + gmv(a, 1, ic) * stab;
-    g2 -= gmv(a, 4, ic) * (P11 + P22) + gmv(a, 5, ic) * (P12 + P21) + gmv(a, 6, ic) * P33 + gmv(a, 2, ic) * stab;
+    g0 -= wk_v + gm[0] * stab;
+    g1 -= gm[3] * (P11 + P12 + P21 + P22) + gm[1] * stab;
+    g2 -= gm[4] * (P11 + P22) + gm[5] * (P12 + P21) + gm[6] * P33 + gm[2] * stab;
     a.gacc[lane] = g0;
     a.gacc[LT + lane] = g1;
     a.gacc[2 * LT + lane] = g2;
