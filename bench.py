@@ -409,8 +409,15 @@ def cpu_baseline(mesh, k, budget_s=15.0):
         if el > budget_s or n >= 1000:
             break
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return dict(value=o.ndof * 4 * n / el, unit="DOF-stage updates/s", cores=cores, kind="oracle",
-                sample="%d RK4 steps of the full 256x256 hybrid mesh, k=%d, float64, %.1f s" % (n, k, el))
+                sample="%d RK4 steps of the full 256x256 hybrid mesh, k=%d, float64, %.1f s" % (n, k, el),
+                cpu=model)
 
 
 def main():
