@@ -214,6 +214,34 @@ def run_basin(dtype, steps=100, warmup=5):
     return out
 
 
+def run_tableaux(k=2, dtype="f32", steps=200):
+    """The headline workload stepped with ERK(2), ERK(3) and ERK(4) of eq. ERK: time per step and
+    DOF-stage updates/s (a stage is one fused launch in every tableau; the combine moves 5, 9 and
+    13 state words per unknown per step)."""
+    import torch
+    from paper_2505_15771_amd import Engine
+    mesh = M.hybrid_square(256)
+    out = []
+    for s_ in (2, 3, 4):
+        e = Engine(mesh, k, rk_stages=s_, dtype=dtype)
+        e.set_state(1e-3 * np.random.default_rng(7).standard_normal(e.n_dof))
+        e.autotune()
+        dt = e.dt_cfl(0.5)
+        e.erk_step(0.0, dt, 20)
+        e.synchronize()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        e.erk_step(0.0, dt, steps)
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        out.append(dict(stages=s_, us_per_step=ms * 1e3 / steps, us_per_stage=ms * 1e3 / (steps * s_),
+                        value=e.n_dof * s_ * steps / (ms / 1e3)))
+        e.close()
+    return dict(workload="ERK(2/3/4) tableaux, 256x256 hybrid mesh, k=%d, %s, one shot" % (k, dtype), results=out)
+
+
 def run_precision(k=2, steps=2000):
     """Float32 error of the paper-sized run: the 256 x 256 hybrid workload (Ricker source, eight
     pressure receivers at y = 0.75), `steps` steps at half the CFL step, stepped in float32 and in
@@ -430,7 +458,8 @@ def main():
     ap.add_argument("--shots", type=int, default=1)
     ap.add_argument("--variants", type=int, default=1, help="also time the float64 / k=3 / batched variants")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--only", choices=("adjoint", "basin", "batch", "paper", "cfl", "precision"), default=None,
+    ap.add_argument("--only", choices=("adjoint", "basin", "batch", "paper", "cfl", "precision", "tableaux"),
+                    default=None,
                     help="run one extra workload alone and print its JSON line (for profiling)")
     ap.add_argument("--only-steps", type=int, default=200)
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -462,7 +491,8 @@ def main():
               "batch": lambda: run_batch(steps=args.only_steps),
               "paper": lambda: [run_paper_bilayer(1), run_paper_bilayer(3)],
               "cfl": lambda: [run_cfl(k_) for k_ in (1, 2, 3)],
-              "precision": lambda: run_precision(steps=args.only_steps)}[args.only]
+              "precision": lambda: run_precision(steps=args.only_steps),
+              "tableaux": lambda: run_tableaux(steps=args.only_steps)}[args.only]
         print(json.dumps(fn()), flush=True)
         return
     mesh = M.hybrid_square(256)
@@ -499,6 +529,9 @@ def main():
             print("workload", json.dumps(v), file=sys.stderr, flush=True)
             workloads.append(v)
         v = run_precision()
+        print("workload", json.dumps(v), file=sys.stderr, flush=True)
+        workloads.append(v)
+        v = run_tableaux()
         print("workload", json.dumps(v), file=sys.stderr, flush=True)
         workloads.append(v)
     cpu = cpu_baseline(mesh, args.k) if args.cpu_baseline else None
