@@ -3,4 +3,4 @@
 The compute path is libhho.so (hand-written HIP for gfx950 behind the C ABI of
 include/hho.h); this package only marshals arguments to it.
 """
-from .hho import Batch, Engine, HHOError, Inspect, Unstable, load_library  # noqa: F401
+from .hho import Batch, Engine, HHOError, Inspect, SdirkEngine, Unstable, load_library  # noqa: F401

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhho.so")
-SOURCES = ["plan.cpp", "api.cpp", "kernels.hip", "adjoint.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "kernels.hip", "adjoint.hip", "implicit_plan.cpp", "sdirk.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,929 @@
+// SDIRK engine: device kernels and the C ABI of include/hho_sdirk.h.
+//
+// One SDIRK stage (Sec. 4.1, eq. SDIRK_compact and the two solves following eq. cp_dirk), float64,
+// with every cell vector stored [row][cell] per cell group (medium, face-slot count):
+//   1. B_T = M U^n + dt sum_{j<=i} a_ij F_j - dt sum_{j<i} a_ij Y_j       (stage_rhs, src_add)
+//      with Y_j = K_T U_T^j + K_TF U_F^j the cell rows of K applied to stage j;
+//   2. g = A_T^{-1} B_T and the per-slot products V_T B_T (cell_apply: one lane per output row
+//      of the stacked per-cell matrix [A_T^{-1}; V_T], coalesced over the cells of a group);
+//   3. face right-hand side b = B_F - sum_T V_T B_T (face_rhs), with
+//      B_F^i = -sum_{j<i} (a_ij / a*) E_j and E_j = a* dt (K_FT U_T^j + K_F U_F^j) the face rows
+//      of stage j (E_j = B_F^j minus the final residual of its face solve);
+//   4. BiCGStab on S x = b, S = a* dt (K_F - a* dt K_FT A^{-1} K_TF), face-block Jacobi on the
+//      right; scalars stay on the device, the host checks the residual every few iterations;
+//   5. U_T = g - W_T x (recover) and Y_i = (B_T - M U_T) / (a* dt) (stage_Y: the stage equation
+//      A_T U_T + a* dt K_TF U_F = B_T rearranged, so K is never applied);
+//   last: U^{n+1} = U^n + dt M^{-1} sum_j b_j (F_j - Y_j) (final, src_add).
+// The algebra of steps 3 and 5 is that of the printed scheme: it only uses the stage equations
+// the solves satisfy (the face rows up to the residual that E_j carries).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hho_sdirk.h"
+#include "implicit_plan.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxGroups = 32;
+
+struct GroupTable {
+    int ng;
+    int medium[kMaxGroups], nT[kMaxGroups], nFT[kMaxGroups], n[kMaxGroups];
+    long long vec_off[kMaxGroups], cf_off[kMaxGroups], mat_off[kMaxGroups], w_off[kMaxGroups], m_off[kMaxGroups];
+    long long item_off[kMaxGroups + 1];  // items of the launch, per group (prefix)
+    int Np, N;
+};
+
+__device__ __forceinline__ int find_group(const GroupTable &G, long long e) {
+    int g = 0;
+    while (g + 1 < G.ng && e >= G.item_off[g + 1]) ++g;
+    return g;
+}
+
+// (M u)(e) for cell-vector element e = vec_off + r * n + i of group g
+__device__ __forceinline__ double apply_mass(const GroupTable &G, int g, int r, int i, const double *u,
+                                             const double *mat, bool inverse) {
+    const int n = G.n[g];
+    const long long vo = G.vec_off[g], mo = G.m_off[g];
+    const double x = u[vo + (long long)r * n + i];
+    if (G.medium[g] == 0) {
+        if (r < G.Np) return x * mat[mo + (inverse ? 2 : 0) * n + i];
+        return x * mat[mo + (inverse ? 3 : 1) * n + i];
+    }
+    if (r < 2 * G.Np) return x * mat[mo + (inverse ? 4 : 0) * n + i];
+    const int q = r - 2 * G.Np, al = q / G.N, a = q - al * G.N;
+    const double ca = mat[mo + (inverse ? 5 : 1) * n + i], cb = mat[mo + (inverse ? 6 : 2) * n + i];
+    const double cc = mat[mo + (inverse ? 7 : 3) * n + i];
+    const long long base = vo + (long long)(2 * G.Np + a) * n + i;
+    const double s0 = u[base], s1 = u[base + (long long)G.N * n], s2 = u[base + 2LL * G.N * n];
+    if (al == 0) return ca * s0 + cb * s1;
+    if (al == 1) return cb * s0 + ca * s1;
+    return cc * s2;
+}
+
+// B = M U0 - dt sum_{j<i} a_ij Y_j      (items: cell-vector elements)
+__global__ void __launch_bounds__(kThreads) k_stage_rhs(GroupTable G, long long ndof, const double *__restrict__ U0,
+                                                        const double *__restrict__ Y, int nprev, double w0, double w1,
+                                                        const double *__restrict__ mat, double *__restrict__ B) {
+    const long long e = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= ndof) return;
+    const int g = find_group(G, e);
+    const long long loc = e - G.vec_off[g];
+    const int r = (int)(loc / G.n[g]), i = (int)(loc - (long long)r * G.n[g]);
+    double v = apply_mass(G, g, r, i, U0, mat, false);
+    if (nprev > 0) v -= w0 * Y[e];
+    if (nprev > 1) v -= w1 * Y[ndof + e];
+    B[e] = v;
+}
+
+// out = mats x B per cell: rows [0, nT) -> g, rows [nT, nT + nFT) -> per-slot vector cf
+__global__ void __launch_bounds__(kThreads) k_cell_apply(GroupTable G, long long nitems, const double *__restrict__ mats,
+                                                         const double *__restrict__ B, double *__restrict__ gv,
+                                                         double *__restrict__ cf) {
+    const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (t >= nitems) return;
+    const int g = find_group(G, t);
+    const int n = G.n[g], nT = G.nT[g];
+    const long long loc = t - G.item_off[g];
+    const int r = (int)(loc / n), i = (int)(loc - (long long)r * n);
+    const double *m = mats + G.mat_off[g] + (long long)r * nT * n + i;
+    const double *b = B + G.vec_off[g] + i;
+    double acc = 0.0;
+    for (int c = 0; c < nT; ++c) acc += m[(long long)c * n] * b[(long long)c * n];
+    if (r < nT) gv[G.vec_off[g] + (long long)r * n + i] = acc;
+    else cf[G.cf_off[g] + (long long)(r - nT) * n + i] = acc;
+}
+
+// bF_i = -sum_{j<i} (a_ij / a*) E_j ; rhs = bF_i - (V B) fed by the (at most two) cells
+__global__ void __launch_bounds__(kThreads) k_face_rhs(int nfd, const int *__restrict__ feed, const double *__restrict__ cf,
+                                                       const double *__restrict__ E, int nprev, double q0, double q1,
+                                                       double *__restrict__ bF, double *__restrict__ rhs) {
+    const int d = blockIdx.x * kThreads + threadIdx.x;
+    if (d >= nfd) return;
+    double v = 0.0;
+    if (nprev > 0) v -= q0 * E[d];
+    if (nprev > 1) v -= q1 * E[(long long)nfd + d];
+    bF[d] = v;
+    const int f0 = feed[2 * d], f1 = feed[2 * d + 1];
+    double s = v;
+    if (f0 >= 0) s -= cf[f0];
+    if (f1 >= 0) s -= cf[f1];
+    rhs[d] = s;
+}
+
+// U = g - W x     (items: cell-vector elements)
+__global__ void __launch_bounds__(kThreads) k_recover(GroupTable G, long long ndof, const double *__restrict__ wmat,
+                                                      const int *__restrict__ slot_dof, const double *__restrict__ x,
+                                                      const double *__restrict__ gv, double *__restrict__ U) {
+    const long long e = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= ndof) return;
+    const int g = find_group(G, e);
+    const int n = G.n[g], nS = G.nFT[g];
+    const long long loc = e - G.vec_off[g];
+    const int r = (int)(loc / n), i = (int)(loc - (long long)r * n);
+    const double *w = wmat + G.w_off[g] + (long long)r * nS * n + i;
+    const int *sd = slot_dof + G.cf_off[g] + i;
+    double acc = gv[e];
+    for (int q = 0; q < nS; ++q) acc -= w[(long long)q * n] * x[sd[(long long)q * n]];
+    U[e] = acc;
+}
+
+// Y_i = (B - M U) / (a* dt)
+__global__ void __launch_bounds__(kThreads) k_stage_Y(GroupTable G, long long ndof, const double *__restrict__ B,
+                                                      const double *__restrict__ U, const double *__restrict__ mat,
+                                                      double inv_adt, double *__restrict__ Yi) {
+    const long long e = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= ndof) return;
+    const int g = find_group(G, e);
+    const long long loc = e - G.vec_off[g];
+    const int r = (int)(loc / G.n[g]), i = (int)(loc - (long long)r * G.n[g]);
+    Yi[e] = (B[e] - apply_mass(G, g, r, i, U, mat, false)) * inv_adt;
+}
+
+// U = U0 - dt M^{-1} sum_j b_j Y_j     (Z = sum_j b_j Y_j formed first into Zbuf)
+__global__ void __launch_bounds__(kThreads) k_combine_Y(long long ndof, const double *__restrict__ Y, int s, double b0,
+                                                        double b1, double b2, double *__restrict__ Z) {
+    const long long e = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= ndof) return;
+    double v = b0 * Y[e];
+    if (s > 1) v += b1 * Y[ndof + e];
+    if (s > 2) v += b2 * Y[2 * ndof + e];
+    Z[e] = v;
+}
+
+__global__ void __launch_bounds__(kThreads) k_final(GroupTable G, long long ndof, const double *__restrict__ U0,
+                                                    const double *__restrict__ Z, const double *__restrict__ mat, double dt,
+                                                    double *__restrict__ U) {
+    const long long e = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= ndof) return;
+    const int g = find_group(G, e);
+    const long long loc = e - G.vec_off[g];
+    const int r = (int)(loc / G.n[g]), i = (int)(loc - (long long)r * G.n[g]);
+    U[e] = U0[e] - dt * apply_mass(G, g, r, i, Z, mat, true);
+}
+
+struct SrcDev {
+    long long idx;      // cell-vector element
+    double coef;        // phi'_a(x_s) d
+    double f0, t0, amp;
+    double minv;        // inverse mass of that row (1/rho or kappa)
+};
+
+__device__ __forceinline__ double ricker(double t, double f0, double t0) {
+    const double a = 3.14159265358979323846 * f0 * (t - t0);
+    return (1.0 - 2.0 * a * a) * exp(-a * a);
+}
+
+// out[idx] += sum_j w_j amp R(t + c_j dt) coef (times minv when final)
+__global__ void k_src_add(int n, const SrcDev *__restrict__ src, double t, double dt, int nw, double w0, double w1,
+                          double w2, double c0, double c1, double c2, int final_update, double *__restrict__ out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const SrcDev s = src[q];
+    double acc = w0 * ricker(t + c0 * dt, s.f0, s.t0);
+    if (nw > 1) acc += w1 * ricker(t + c1 * dt, s.f0, s.t0);
+    if (nw > 2) acc += w2 * ricker(t + c2 * dt, s.f0, s.t0);
+    acc *= dt * s.amp * s.coef;
+    if (final_update) acc *= s.minv;
+    atomicAdd(out + s.idx, acc);
+}
+
+// ---------------------------------------------------------------- BiCGStab
+enum Scalar { S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_RR, S_BB, S_DONE, S_ITER, S_TOL2, S_TRR, kNumScalars = 16 };
+
+// y = A x (mode 0) or y = b - A x (mode 1); 8 lanes per row
+__global__ void __launch_bounds__(kThreads) k_spmv(int nrows, const int *__restrict__ ptr, const int *__restrict__ col,
+                                                   const double *__restrict__ val, const double *__restrict__ x,
+                                                   const double *__restrict__ b, double *__restrict__ y, int mode,
+                                                   const double *__restrict__ sc, int respect_done) {
+    if (respect_done && sc[S_DONE] != 0.0) return;
+    const int t = blockIdx.x * kThreads + threadIdx.x;
+    const int row = t >> 3, lane = t & 7;
+    double acc = 0.0;
+    if (row < nrows) {
+        const int e1 = ptr[row + 1];
+        for (int q = ptr[row] + lane; q < e1; q += 8) acc += val[q] * x[col[q]];
+    }
+    acc += __shfl_xor(acc, 4, 8);
+    acc += __shfl_xor(acc, 2, 8);
+    acc += __shfl_xor(acc, 1, 8);
+    if (row < nrows && lane == 0) y[row] = mode ? b[row] - acc : acc;
+}
+
+// partial sums of a.b and c.d per block (part[2 * block + {0, 1}])
+__global__ void __launch_bounds__(kThreads) k_dot2(int n, const double *__restrict__ a, const double *__restrict__ b,
+                                                   const double *__restrict__ c, const double *__restrict__ d,
+                                                   double *__restrict__ part, const double *__restrict__ sc,
+                                                   int respect_done) {
+    if (respect_done && sc[S_DONE] != 0.0) return;
+    __shared__ double s0[kThreads], s1[kThreads];
+    double x0 = 0.0, x1 = 0.0;
+    for (int q = blockIdx.x * kThreads + threadIdx.x; q < n; q += gridDim.x * kThreads) {
+        x0 += a[q] * b[q];
+        if (c) x1 += c[q] * d[q];
+    }
+    s0[threadIdx.x] = x0;
+    s1[threadIdx.x] = x1;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s0[threadIdx.x] += s0[threadIdx.x + w];
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s0[0];
+        part[2 * blockIdx.x + 1] = s1[0];
+    }
+}
+
+enum Finalize { F_INIT = 0, F_ALPHA = 1, F_OMEGA = 2, F_RR = 3, F_TRUE = 4 };
+
+// reduce the partial sums (fixed order) and update the solver scalars (one block)
+__global__ void __launch_bounds__(kThreads) k_finalize(int nblk, const double *__restrict__ part, double *__restrict__ sc,
+                                                       int kind, int max_iter) {
+    if (kind != F_INIT && kind != F_TRUE && sc[S_DONE] != 0.0) return;
+    __shared__ double s0[kThreads], s1[kThreads];
+    double x0 = 0.0, x1 = 0.0;
+    for (int q = threadIdx.x; q < nblk; q += kThreads) {
+        x0 += part[2 * q];
+        x1 += part[2 * q + 1];
+    }
+    s0[threadIdx.x] = x0;
+    s1[threadIdx.x] = x1;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s0[threadIdx.x] += s0[threadIdx.x + w];
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double a = s0[0], b = s1[0];
+    if (kind == F_INIT) {           // a = b.b, b = r.r (r_hat = r)
+        sc[S_BB] = a;
+        sc[S_RR] = b;
+        sc[S_RHO] = b;
+        sc[S_ALPHA] = 1.0;
+        sc[S_OMEGA] = 1.0;
+        sc[S_BETA] = 0.0;
+        sc[S_ITER] = 0.0;
+        sc[S_DONE] = (b <= sc[S_TOL2] * a) ? 1.0 : 0.0;
+    } else if (kind == F_ALPHA) {   // a = r_hat.v
+        if (a == 0.0 || !isfinite(a)) sc[S_DONE] = 2.0;
+        else sc[S_ALPHA] = sc[S_RHO] / a;
+    } else if (kind == F_OMEGA) {   // a = t.s, b = t.t
+        sc[S_OMEGA] = b > 0.0 ? a / b : 0.0;
+    } else if (kind == F_RR) {      // a = r.r, b = r_hat.r
+        sc[S_RR] = a;
+        sc[S_ITER] += 1.0;
+        if (!isfinite(a)) sc[S_DONE] = 2.0;
+        else if (a <= sc[S_TOL2] * sc[S_BB]) sc[S_DONE] = 1.0;
+        else if (b == 0.0 || sc[S_OMEGA] == 0.0) sc[S_DONE] = 2.0;
+        else {
+            sc[S_BETA] = (b / sc[S_RHO]) * (sc[S_ALPHA] / sc[S_OMEGA]);
+            sc[S_RHO] = b;
+            if (sc[S_ITER] >= (double)max_iter) sc[S_DONE] = 3.0;
+        }
+    } else {                        // F_TRUE: a = r.r of the true residual
+        sc[S_TRR] = a;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_update_p(int n, const double *__restrict__ r, const double *__restrict__ v,
+                                                       double *__restrict__ p, const double *__restrict__ sc) {
+    if (sc[S_DONE] != 0.0) return;
+    const int q = blockIdx.x * kThreads + threadIdx.x;
+    if (q >= n) return;
+    p[q] = r[q] + sc[S_BETA] * (p[q] - sc[S_OMEGA] * v[q]);
+}
+
+__global__ void __launch_bounds__(kThreads) k_update_s(int n, const double *__restrict__ r, const double *__restrict__ v,
+                                                       double *__restrict__ s, const double *__restrict__ sc) {
+    if (sc[S_DONE] != 0.0) return;
+    const int q = blockIdx.x * kThreads + threadIdx.x;
+    if (q >= n) return;
+    s[q] = r[q] - sc[S_ALPHA] * v[q];
+}
+
+__global__ void __launch_bounds__(kThreads) k_update_xr(int n, double *__restrict__ x, const double *__restrict__ ph,
+                                                        const double *__restrict__ sh, const double *__restrict__ s,
+                                                        const double *__restrict__ t, double *__restrict__ r,
+                                                        const double *__restrict__ sc) {
+    if (sc[S_DONE] != 0.0) return;
+    const int q = blockIdx.x * kThreads + threadIdx.x;
+    if (q >= n) return;
+    const double al = sc[S_ALPHA], om = sc[S_OMEGA];
+    x[q] += al * ph[q] + om * sh[q];
+    r[q] = s[q] - om * t[q];
+}
+
+// E_i = bF_i - (rhs - S x), the true residual given in res
+__global__ void __launch_bounds__(kThreads) k_face_rows(int n, const double *__restrict__ bF, const double *__restrict__ res,
+                                                        double *__restrict__ Ei) {
+    const int q = blockIdx.x * kThreads + threadIdx.x;
+    if (q >= n) return;
+    Ei[q] = bF[q] - res[q];
+}
+
+__global__ void __launch_bounds__(kThreads) k_copy(long long n, const double *__restrict__ a, double *__restrict__ b) {
+    const long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (q < n) b[q] = a[q];
+}
+
+// energy partial sums: 1/2 U . M U per block
+__global__ void __launch_bounds__(kThreads) k_energy(GroupTable G, long long ndof, const double *__restrict__ U,
+                                                     const double *__restrict__ mat, double *__restrict__ part) {
+    __shared__ double s0[kThreads];
+    double acc = 0.0;
+    for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < ndof; e += (long long)gridDim.x * kThreads) {
+        const int g = find_group(G, e);
+        const long long loc = e - G.vec_off[g];
+        const int r = (int)(loc / G.n[g]), i = (int)(loc - (long long)r * G.n[g]);
+        acc += 0.5 * U[e] * apply_mass(G, g, r, i, U, mat, false);
+    }
+    s0[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s0[threadIdx.x] += s0[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { part[2 * blockIdx.x] = s0[0]; part[2 * blockIdx.x + 1] = 0.0; }
+}
+
+unsigned grid_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+constexpr int kDotBlocks = 512;
+constexpr int kChunk = 8;  // BiCGStab iterations enqueued between residual checks
+
+}  // namespace
+
+struct hho_sdirk {
+    hho::imp::Plan plan;
+    std::string err;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    double tol = 1e-10;
+    int max_iter = 1000;
+    std::vector<void *> allocs;
+    GroupTable gvec{}, gmat{};
+    // device buffers
+    double *mats = nullptr, *wmat = nullptr, *mat = nullptr;
+    int *slot_dof = nullptr, *feed = nullptr;
+    int *S_ptr = nullptr, *S_col = nullptr, *P_ptr = nullptr, *P_col = nullptr;
+    double *S_val = nullptr, *P_val = nullptr;
+    double *U = nullptr, *U0 = nullptr, *B = nullptr, *gv = nullptr, *Y = nullptr, *Z = nullptr, *cf = nullptr;
+    double *E = nullptr, *bF = nullptr, *rhs = nullptr;
+    double *x = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
+    double *ph = nullptr, *sh = nullptr, *part = nullptr, *sc = nullptr;
+    double *h_sc = nullptr;  // pinned
+    SrcDev *src = nullptr;
+    int n_src = 0;
+    int64_t solves = 0, iterations = 0;
+    double max_res = 0.0;
+};
+
+namespace {
+
+std::string g_sdirk_error;
+
+#define SCK(call)                                                                        \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);                \
+            return e_ == hipErrorOutOfMemory ? HHO_ERR_OOM : HHO_ERR_DEVICE;             \
+        }                                                                                \
+    } while (0)
+
+template <typename T>
+hho_status dev_alloc(hho_sdirk *ctx, T **p, size_t count) {
+    void *q = nullptr;
+    size_t bytes = std::max<size_t>(count * sizeof(T), 8);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        ctx->err = "hipMalloc(" + std::to_string(bytes) + " bytes): " + hipGetErrorString(e);
+        return e == hipErrorOutOfMemory ? HHO_ERR_OOM : HHO_ERR_DEVICE;
+    }
+    ctx->allocs.push_back(q);
+    *p = (T *)q;
+    e = hipMemsetAsync(q, 0, bytes, ctx->stream);
+    if (e != hipSuccess) {
+        ctx->err = std::string("hipMemsetAsync: ") + hipGetErrorString(e);
+        return HHO_ERR_DEVICE;
+    }
+    return HHO_OK;
+}
+
+template <typename T>
+hho_status upload(hho_sdirk *ctx, T **p, const std::vector<T> &v) {
+    hho_status st = dev_alloc(ctx, p, v.size());
+    if (st != HHO_OK) return st;
+    if (!v.empty()) SCK(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+    SCK(hipStreamSynchronize(ctx->stream));
+    return HHO_OK;
+}
+
+hho::imp::Options options_of(const hho_sdirk_params *p) {
+    hho::imp::Options o;
+    o.k = p->k;
+    o.mixed = p->mixed;
+    o.alpha = p->alpha;
+    o.eta_f = p->eta_f;
+    o.eta_s = p->eta_s;
+    o.stab_speed = p->stab_speed;
+    o.ell = p->ell;
+    o.stages = p->stages;
+    o.dt = p->dt;
+    return o;
+}
+
+std::string build_plan(const hho_mesh *m, const hho_sdirk_params *p, hho::imp::Plan &P, int *code) {
+    if (!m || !p) {
+        *code = HHO_ERR_ARG;
+        return "null mesh or params";
+    }
+    return hho::imp::build(m->n_vertices, m->xy, m->n_cells, m->cell_ptr, m->cell_vtx, m->medium, m->rho, m->a, m->b,
+                           options_of(p), P, code);
+}
+
+void fill_groups(hho_sdirk *ctx) {
+    const auto &P = ctx->plan;
+    GroupTable G{};
+    G.ng = (int)P.groups.size();
+    G.Np = P.Np;
+    G.N = P.N;
+    for (int g = 0; g < G.ng; ++g) {
+        const auto &q = P.groups[g];
+        G.medium[g] = q.medium;
+        G.nT[g] = q.nT;
+        G.nFT[g] = q.nFT;
+        G.n[g] = q.n;
+        G.vec_off[g] = q.vec_off;
+        G.cf_off[g] = q.cf_off;
+        G.mat_off[g] = q.mat_off;
+        G.w_off[g] = q.w_off;
+        G.m_off[g] = q.m_off;
+    }
+    ctx->gvec = G;
+    ctx->gmat = G;
+    long long acc = 0;
+    for (int g = 0; g < G.ng; ++g) {
+        ctx->gvec.item_off[g] = P.groups[g].vec_off;
+        ctx->gmat.item_off[g] = acc;
+        acc += (long long)(P.groups[g].nT + P.groups[g].nFT) * P.groups[g].n;
+    }
+    ctx->gvec.item_off[G.ng] = P.n_dof;
+    ctx->gmat.item_off[G.ng] = acc;
+}
+
+long long mat_items(const hho_sdirk *ctx) { return ctx->gmat.item_off[ctx->gmat.ng]; }
+
+// dot products a.b (and c.d) into the scalar update `kind`
+hho_status dots(hho_sdirk *ctx, const double *a, const double *b, const double *c, const double *d, int kind,
+                int respect_done) {
+    const int n = ctx->plan.n_fdof;
+    const int nblk = std::min<int>(kDotBlocks, std::max<int>(1, (int)grid_for(n)));
+    hipLaunchKernelGGL(k_dot2, dim3(nblk), dim3(kThreads), 0, ctx->stream, n, a, b, c, d, ctx->part, ctx->sc,
+                       respect_done);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, ctx->stream, nblk, ctx->part, ctx->sc, kind,
+                       ctx->max_iter);
+    SCK(hipGetLastError());
+    return HHO_OK;
+}
+
+hho_status spmv(hho_sdirk *ctx, bool precond, const double *x, const double *b, double *y, int mode, int respect_done) {
+    const int n = ctx->plan.n_fdof;
+    hipLaunchKernelGGL(k_spmv, dim3(grid_for(8LL * n)), dim3(kThreads), 0, ctx->stream, n,
+                       precond ? ctx->P_ptr : ctx->S_ptr, precond ? ctx->P_col : ctx->S_col,
+                       precond ? ctx->P_val : ctx->S_val, x, b, y, mode, ctx->sc, respect_done);
+    SCK(hipGetLastError());
+    return HHO_OK;
+}
+
+hho_status read_scalars(hho_sdirk *ctx) {
+    SCK(hipMemcpyAsync(ctx->h_sc, ctx->sc, kNumScalars * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    SCK(hipStreamSynchronize(ctx->stream));
+    return HHO_OK;
+}
+
+#define SST(call)                          \
+    do {                                   \
+        hho_status s_ = (call);            \
+        if (s_ != HHO_OK) return s_;       \
+    } while (0)
+
+// BiCGStab on S x = rhs (x holds the initial guess); then E_i = bF - (rhs - S x)
+hho_status face_solve(hho_sdirk *ctx, double *Ei) {
+    const int n = ctx->plan.n_fdof;
+    if (n == 0) return HHO_OK;
+    const unsigned gr = grid_for(n);
+    int restarts = 0;
+    for (;;) {
+        SST(spmv(ctx, false, ctx->x, ctx->rhs, ctx->r, 1, 0));   // r = rhs - S x
+        hipLaunchKernelGGL(k_copy, dim3(gr), dim3(kThreads), 0, ctx->stream, (long long)n, ctx->r, ctx->rh);
+        SCK(hipMemsetAsync(ctx->p, 0, n * sizeof(double), ctx->stream));
+        SCK(hipMemsetAsync(ctx->v, 0, n * sizeof(double), ctx->stream));
+        SST(dots(ctx, ctx->rhs, ctx->rhs, ctx->r, ctx->r, F_INIT, 0));
+        SST(read_scalars(ctx));
+        if (ctx->h_sc[S_BB] == 0.0) {   // zero right-hand side: the solution is zero
+            SCK(hipMemsetAsync(ctx->x, 0, n * sizeof(double), ctx->stream));
+            break;
+        }
+        int it = 0;
+        while (ctx->h_sc[S_DONE] == 0.0) {
+            for (int c = 0; c < kChunk; ++c) {
+                hipLaunchKernelGGL(k_update_p, dim3(gr), dim3(kThreads), 0, ctx->stream, n, ctx->r, ctx->v, ctx->p, ctx->sc);
+                SST(spmv(ctx, true, ctx->p, nullptr, ctx->ph, 0, 1));
+                SST(spmv(ctx, false, ctx->ph, nullptr, ctx->v, 0, 1));
+                SST(dots(ctx, ctx->rh, ctx->v, nullptr, nullptr, F_ALPHA, 1));
+                hipLaunchKernelGGL(k_update_s, dim3(gr), dim3(kThreads), 0, ctx->stream, n, ctx->r, ctx->v, ctx->s, ctx->sc);
+                SST(spmv(ctx, true, ctx->s, nullptr, ctx->sh, 0, 1));
+                SST(spmv(ctx, false, ctx->sh, nullptr, ctx->t, 0, 1));
+                SST(dots(ctx, ctx->t, ctx->s, ctx->t, ctx->t, F_OMEGA, 1));
+                hipLaunchKernelGGL(k_update_xr, dim3(gr), dim3(kThreads), 0, ctx->stream, n, ctx->x, ctx->ph, ctx->sh,
+                                   ctx->s, ctx->t, ctx->r, ctx->sc);
+                SST(dots(ctx, ctx->r, ctx->r, ctx->rh, ctx->r, F_RR, 1));
+            }
+            SCK(hipGetLastError());
+            SST(read_scalars(ctx));
+            it += kChunk;
+        }
+        ctx->iterations += (int64_t)ctx->h_sc[S_ITER];
+        if (ctx->h_sc[S_DONE] == 1.0) break;
+        if (ctx->h_sc[S_DONE] == 3.0 || restarts >= 2) {
+            ctx->err = ctx->h_sc[S_DONE] == 3.0 ? "face solve: no convergence within max_iter iterations"
+                                                : "face solve: BiCGStab broke down";
+            return HHO_ERR_UNSTABLE;
+        }
+        ++restarts;  // breakdown: restart from the current iterate with a fresh shadow residual
+    }
+    // true residual and the face rows of this stage
+    SST(spmv(ctx, false, ctx->x, ctx->rhs, ctx->r, 1, 0));
+    SST(dots(ctx, ctx->r, ctx->r, nullptr, nullptr, F_TRUE, 0));
+    hipLaunchKernelGGL(k_face_rows, dim3(gr), dim3(kThreads), 0, ctx->stream, n, ctx->bF, ctx->r, Ei);
+    SCK(hipGetLastError());
+    SST(read_scalars(ctx));
+    ctx->solves += 1;
+    if (ctx->h_sc[S_BB] > 0.0)
+        ctx->max_res = std::max(ctx->max_res, std::sqrt(ctx->h_sc[S_TRR] / ctx->h_sc[S_BB]));
+    return HHO_OK;
+}
+
+hho_status add_sources(hho_sdirk *ctx, double *out, double t, double dt, int nw, const double *w, const double *c,
+                       int final_update) {
+    if (ctx->n_src == 0) return HHO_OK;
+    hipLaunchKernelGGL(k_src_add, dim3((ctx->n_src + 63) / 64), dim3(64), 0, ctx->stream, ctx->n_src, ctx->src, t, dt, nw,
+                       w[0], nw > 1 ? w[1] : 0.0, nw > 2 ? w[2] : 0.0, c[0], nw > 1 ? c[1] : 0.0, nw > 2 ? c[2] : 0.0,
+                       final_update, out);
+    SCK(hipGetLastError());
+    return HHO_OK;
+}
+
+hho_status one_step(hho_sdirk *ctx, double t) {
+    const auto &P = ctx->plan;
+    const long long nd = P.n_dof;
+    const int s = P.stages;
+    const double dt = P.dt, ast = P.ast, adt = ast * dt;
+    const unsigned gv = grid_for(nd);
+    hipLaunchKernelGGL(k_copy, dim3(gv), dim3(kThreads), 0, ctx->stream, nd, ctx->U, ctx->U0);
+    for (int i = 0; i < s; ++i) {
+        // B_T
+        hipLaunchKernelGGL(k_stage_rhs, dim3(gv), dim3(kThreads), 0, ctx->stream, ctx->gvec, nd, ctx->U0, ctx->Y, i,
+                           i > 0 ? dt * P.A[i][0] : 0.0, i > 1 ? dt * P.A[i][1] : 0.0, ctx->mat, ctx->B);
+        SCK(hipGetLastError());
+        double w[3] = {P.A[i][0], P.A[i][1], P.A[i][2]};
+        SST(add_sources(ctx, ctx->B, t, dt, i + 1, w, P.c, 0));
+        // g = A^{-1} B, cf = V B
+        hipLaunchKernelGGL(k_cell_apply, dim3(grid_for(mat_items(ctx))), dim3(kThreads), 0, ctx->stream, ctx->gmat,
+                           mat_items(ctx), ctx->mats, ctx->B, ctx->gv, ctx->cf);
+        // face right-hand side
+        if (P.n_fdof > 0)
+            hipLaunchKernelGGL(k_face_rhs, dim3(grid_for(P.n_fdof)), dim3(kThreads), 0, ctx->stream, P.n_fdof, ctx->feed,
+                               ctx->cf, ctx->E, i, i > 0 ? P.A[i][0] / ast : 0.0, i > 1 ? P.A[i][1] / ast : 0.0, ctx->bF,
+                               ctx->rhs);
+        SCK(hipGetLastError());
+        SST(face_solve(ctx, ctx->E + (size_t)i * P.n_fdof));
+        // cell recovery and the cell rows of K U^{n,i}
+        hipLaunchKernelGGL(k_recover, dim3(gv), dim3(kThreads), 0, ctx->stream, ctx->gvec, nd, ctx->wmat, ctx->slot_dof,
+                           ctx->x, ctx->gv, ctx->U);
+        hipLaunchKernelGGL(k_stage_Y, dim3(gv), dim3(kThreads), 0, ctx->stream, ctx->gvec, nd, ctx->B, ctx->U, ctx->mat,
+                           1.0 / adt, ctx->Y + (size_t)i * nd);
+        SCK(hipGetLastError());
+    }
+    // U^{n+1} = U^n + dt M^{-1} sum_j b_j (F_j - Y_j)
+    hipLaunchKernelGGL(k_combine_Y, dim3(gv), dim3(kThreads), 0, ctx->stream, nd, ctx->Y, s, P.b[0], P.b[1], P.b[2],
+                       ctx->Z);
+    hipLaunchKernelGGL(k_final, dim3(gv), dim3(kThreads), 0, ctx->stream, ctx->gvec, nd, ctx->U0, ctx->Z, ctx->mat, dt,
+                       ctx->U);
+    SCK(hipGetLastError());
+    SST(add_sources(ctx, ctx->U, t, dt, s, P.b, P.c, 1));
+    return HHO_OK;
+}
+
+// external layout <-> group layout
+void to_group(const hho::imp::Plan &P, const double *ext, std::vector<double> &grp) {
+    grp.assign(P.n_dof, 0.0);
+    for (int c = 0; c < P.n_cells; ++c) {
+        const auto &g = P.groups[P.cell_group[c]];
+        const int i = P.cell_index[c];
+        for (int r = 0; r < g.nT; ++r) grp[g.vec_off + (int64_t)r * g.n + i] = ext[P.ext_off[c] + r];
+    }
+}
+
+void from_group(const hho::imp::Plan &P, const std::vector<double> &grp, double *ext) {
+    for (int c = 0; c < P.n_cells; ++c) {
+        const auto &g = P.groups[P.cell_group[c]];
+        const int i = P.cell_index[c];
+        for (int r = 0; r < g.nT; ++r) ext[P.ext_off[c] + r] = grp[g.vec_off + (int64_t)r * g.n + i];
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hho_sdirk_last_error(const hho_sdirk *ctx) { return ctx ? ctx->err.c_str() : g_sdirk_error.c_str(); }
+
+hho_status hho_sdirk_setup(const hho_mesh *mesh, const hho_sdirk_params *prm, hho_sdirk **out) {
+    g_sdirk_error.clear();
+    if (!out) {
+        g_sdirk_error = "null output pointer";
+        return HHO_ERR_ARG;
+    }
+    *out = nullptr;
+    if (prm && (!(prm->tol > 0.0) || !(prm->tol < 1.0) || prm->max_iter < 1)) {
+        g_sdirk_error = "tol must lie in (0, 1) and max_iter be >= 1";
+        return HHO_ERR_ARG;
+    }
+    hho_sdirk *ctx = new hho_sdirk();
+    int code = 0;
+    std::string msg = build_plan(mesh, prm, ctx->plan, &code);
+    if (!msg.empty()) {
+        g_sdirk_error = msg;
+        delete ctx;
+        return (hho_status)code;
+    }
+    if ((int)ctx->plan.groups.size() > kMaxGroups) {
+        g_sdirk_error = "too many cell groups";
+        delete ctx;
+        return HHO_ERR_MESH;
+    }
+    ctx->device = prm->device;
+    ctx->stream = (hipStream_t)prm->stream;
+    ctx->tol = prm->tol;
+    ctx->max_iter = prm->max_iter;
+    auto fail = [&](hho_status st) {
+        g_sdirk_error = ctx->err;
+        hho_sdirk_destroy(ctx);
+        return st;
+    };
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        ctx->err = "hipSetDevice failed";
+        return fail(HHO_ERR_DEVICE);
+    }
+    fill_groups(ctx);
+    const auto &P = ctx->plan;
+    hho_status st = HHO_OK;
+#define UP(ptr, vec)                                  \
+    if ((st = upload(ctx, &ptr, vec)) != HHO_OK) return fail(st);
+#define AL(ptr, count)                                \
+    if ((st = dev_alloc(ctx, &ptr, count)) != HHO_OK) return fail(st);
+    UP(ctx->mats, P.mats);
+    UP(ctx->wmat, P.wmat);
+    UP(ctx->mat, P.mat);
+    UP(ctx->slot_dof, P.slot_dof);
+    UP(ctx->feed, P.feed);
+    UP(ctx->S_ptr, P.S_ptr);
+    UP(ctx->S_col, P.S_col);
+    UP(ctx->S_val, P.S_val);
+    UP(ctx->P_ptr, P.P_ptr);
+    UP(ctx->P_col, P.P_col);
+    UP(ctx->P_val, P.P_val);
+    const size_t nd = (size_t)P.n_dof, nf = (size_t)P.n_fdof;
+    AL(ctx->U, nd);
+    AL(ctx->U0, nd);
+    AL(ctx->B, nd);
+    AL(ctx->gv, nd);
+    AL(ctx->Z, nd);
+    AL(ctx->Y, nd * P.stages);
+    AL(ctx->cf, (size_t)P.n_slot);
+    AL(ctx->E, nf * P.stages);
+    AL(ctx->bF, nf);
+    AL(ctx->rhs, nf);
+    AL(ctx->x, nf);
+    AL(ctx->r, nf);
+    AL(ctx->rh, nf);
+    AL(ctx->p, nf);
+    AL(ctx->v, nf);
+    AL(ctx->s, nf);
+    AL(ctx->t, nf);
+    AL(ctx->ph, nf);
+    AL(ctx->sh, nf);
+    AL(ctx->part, 2 * (size_t)kDotBlocks);
+    AL(ctx->sc, kNumScalars);
+#undef UP
+#undef AL
+    if (hipHostMalloc((void **)&ctx->h_sc, kNumScalars * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        ctx->err = "hipHostMalloc failed";
+        return fail(HHO_ERR_OOM);
+    }
+    const double tol2 = ctx->tol * ctx->tol;
+    if (hipMemcpyAsync(ctx->sc + S_TOL2, &tol2, sizeof(double), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        ctx->err = "upload of the solver tolerance failed";
+        return fail(HHO_ERR_DEVICE);
+    }
+    *out = ctx;
+    return HHO_OK;
+}
+
+void hho_sdirk_destroy(hho_sdirk *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (void *p : ctx->allocs) (void)hipFree(p);
+    if (ctx->h_sc) (void)hipHostFree(ctx->h_sc);
+    delete ctx;
+}
+
+hho_status hho_sdirk_sizes(const hho_sdirk *ctx, int64_t *n_dof, int32_t *n_face_dof, int64_t *nnz) {
+    if (!ctx) return HHO_ERR_ARG;
+    if (n_dof) *n_dof = ctx->plan.n_dof;
+    if (n_face_dof) *n_face_dof = ctx->plan.n_fdof;
+    if (nnz) *nnz = (int64_t)ctx->plan.S_val.size();
+    return HHO_OK;
+}
+
+hho_status hho_sdirk_set_state(hho_sdirk *ctx, const double *U, int32_t on_device) {
+    if (!ctx) return HHO_ERR_ARG;
+    if (!U) {
+        ctx->err = "null state";
+        return HHO_ERR_ARG;
+    }
+    SCK(hipSetDevice(ctx->device));
+    const auto &P = ctx->plan;
+    std::vector<double> ext(P.n_dof), grp;
+    if (on_device) {
+        SCK(hipMemcpyAsync(ext.data(), U, P.n_dof * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        SCK(hipStreamSynchronize(ctx->stream));
+    } else {
+        std::memcpy(ext.data(), U, P.n_dof * sizeof(double));
+    }
+    to_group(P, ext.data(), grp);
+    SCK(hipMemcpyAsync(ctx->U, grp.data(), P.n_dof * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    SCK(hipMemsetAsync(ctx->x, 0, std::max<size_t>(P.n_fdof, 1) * sizeof(double), ctx->stream));
+    SCK(hipStreamSynchronize(ctx->stream));
+    return HHO_OK;
+}
+
+hho_status hho_sdirk_get_state(hho_sdirk *ctx, double *U, int32_t on_device) {
+    if (!ctx) return HHO_ERR_ARG;
+    if (!U) {
+        ctx->err = "null state";
+        return HHO_ERR_ARG;
+    }
+    SCK(hipSetDevice(ctx->device));
+    const auto &P = ctx->plan;
+    std::vector<double> grp(P.n_dof), ext(P.n_dof);
+    SCK(hipMemcpyAsync(grp.data(), ctx->U, P.n_dof * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    SCK(hipStreamSynchronize(ctx->stream));
+    from_group(P, grp, ext.data());
+    if (on_device) {
+        SCK(hipMemcpyAsync(U, ext.data(), P.n_dof * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        SCK(hipStreamSynchronize(ctx->stream));
+    } else {
+        std::memcpy(U, ext.data(), P.n_dof * sizeof(double));
+    }
+    return HHO_OK;
+}
+
+hho_status hho_sdirk_set_sources(hho_sdirk *ctx, int32_t n, const double *xy, const double *dir, const double *f0,
+                                 const double *t0, const double *amp) {
+    if (!ctx) return HHO_ERR_ARG;
+    if (n < 0 || (n > 0 && (!xy || !dir || !f0 || !t0 || !amp))) {
+        ctx->err = "invalid source arrays";
+        return HHO_ERR_ARG;
+    }
+    SCK(hipSetDevice(ctx->device));
+    const auto &P = ctx->plan;
+    std::vector<SrcDev> v;
+    std::vector<double> phi(P.Np);
+    for (int q = 0; q < n; ++q) {
+        const int c = hho::imp::locate(P, xy[2 * q], xy[2 * q + 1]);
+        if (c < 0) {
+            ctx->err = "source " + std::to_string(q) + " lies outside the mesh";
+            return HHO_ERR_ARG;
+        }
+        hho::imp::eval_basis(P, c, xy[2 * q], xy[2 * q + 1], phi.data());
+        const auto &g = P.groups[P.cell_group[c]];
+        const int i = P.cell_index[c];
+        const int ncomp = P.medium[c] == 0 ? 1 : 2;
+        const double minv = P.medium[c] == 0 ? P.kappa[c] : 1.0 / P.rho[c];
+        for (int cc = 0; cc < ncomp; ++cc)
+            for (int a = 0; a < P.Np; ++a) {
+                const double coef = phi[a] * dir[2 * q + cc];
+                if (coef == 0.0) continue;
+                v.push_back({g.vec_off + (int64_t)(cc * P.Np + a) * g.n + i, coef, f0[q], t0[q], amp[q], minv});
+            }
+    }
+    ctx->n_src = 0;
+    ctx->src = nullptr;  // earlier buffers stay in allocs until destroy
+    if (!v.empty()) {
+        hho_status st = dev_alloc(ctx, &ctx->src, v.size());
+        if (st != HHO_OK) return st;
+        SCK(hipMemcpyAsync(ctx->src, v.data(), v.size() * sizeof(SrcDev), hipMemcpyHostToDevice, ctx->stream));
+        SCK(hipStreamSynchronize(ctx->stream));
+    }
+    ctx->n_src = (int)v.size();
+    return HHO_OK;
+}
+
+hho_status hho_sdirk_step(hho_sdirk *ctx, double t0, int32_t n_steps) {
+    if (!ctx) return HHO_ERR_ARG;
+    if (n_steps < 0 || !std::isfinite(t0)) {
+        ctx->err = "n_steps must be >= 0 and t0 finite";
+        return HHO_ERR_ARG;
+    }
+    SCK(hipSetDevice(ctx->device));
+    for (int n = 0; n < n_steps; ++n) {
+        hho_status st = one_step(ctx, t0 + n * ctx->plan.dt);
+        if (st != HHO_OK) {
+            // leave the state of the failing step's start
+            hipLaunchKernelGGL(k_copy, dim3(grid_for(ctx->plan.n_dof)), dim3(kThreads), 0, ctx->stream,
+                               (long long)ctx->plan.n_dof, ctx->U0, ctx->U);
+            (void)hipStreamSynchronize(ctx->stream);
+            return st;
+        }
+    }
+    SCK(hipStreamSynchronize(ctx->stream));
+    return HHO_OK;
+}
+
+hho_status hho_sdirk_energy(hho_sdirk *ctx, double *E) {
+    if (!ctx || !E) return HHO_ERR_ARG;
+    SCK(hipSetDevice(ctx->device));
+    const long long nd = ctx->plan.n_dof;
+    const int nblk = std::min<int>(kDotBlocks, std::max<int>(1, (int)grid_for(nd)));
+    hipLaunchKernelGGL(k_energy, dim3(nblk), dim3(kThreads), 0, ctx->stream, ctx->gvec, nd, ctx->U, ctx->mat, ctx->part);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, ctx->stream, nblk, ctx->part, ctx->sc, (int)F_TRUE,
+                       ctx->max_iter);
+    SCK(hipGetLastError());
+    SCK(hipMemcpyAsync(ctx->h_sc, ctx->sc, kNumScalars * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    SCK(hipStreamSynchronize(ctx->stream));
+    *E = ctx->h_sc[S_TRR];
+    return HHO_OK;
+}
+
+hho_status hho_sdirk_stats(const hho_sdirk *ctx, int64_t *solves, int64_t *iterations, double *max_rel_residual) {
+    if (!ctx) return HHO_ERR_ARG;
+    if (solves) *solves = ctx->solves;
+    if (iterations) *iterations = ctx->iterations;
+    if (max_rel_residual) *max_rel_residual = ctx->max_res;
+    return HHO_OK;
+}
+
+hho_status hho_sdirk_inspect_sizes(const hho_mesh *mesh, const hho_sdirk_params *prm, int64_t *sizes) {
+    g_sdirk_error.clear();
+    if (!sizes) return HHO_ERR_ARG;
+    hho::imp::Plan P;
+    int code = 0;
+    std::string msg = build_plan(mesh, prm, P, &code);
+    if (!msg.empty()) {
+        g_sdirk_error = msg;
+        return (hho_status)code;
+    }
+    sizes[0] = P.n_dof;
+    sizes[1] = P.n_fdof;
+    sizes[2] = (int64_t)P.S_val.size();
+    sizes[3] = P.n_faces;
+    sizes[4] = (int64_t)P.groups.size();
+    return HHO_OK;
+}
+
+hho_status hho_sdirk_inspect_face_matrix(const hho_mesh *mesh, const hho_sdirk_params *prm, int32_t *ptr, int32_t *col,
+                                         double *val, int32_t *face) {
+    g_sdirk_error.clear();
+    hho::imp::Plan P;
+    int code = 0;
+    std::string msg = build_plan(mesh, prm, P, &code);
+    if (!msg.empty()) {
+        g_sdirk_error = msg;
+        return (hho_status)code;
+    }
+    if (ptr) std::copy(P.S_ptr.begin(), P.S_ptr.end(), ptr);
+    if (col) std::copy(P.S_col.begin(), P.S_col.end(), col);
+    if (val) std::copy(P.S_val.begin(), P.S_val.end(), val);
+    if (face) std::copy(P.fdof_face.begin(), P.fdof_face.end(), face);
+    return HHO_OK;
+}
+
+}  // extern "C"

@@ -1,4 +1,4 @@
-"""ctypes binding of libhho.so (C ABI in include/hho.h and include/hho_inspect.h).
+"""ctypes binding of libhho.so (C ABI in include/hho.h, include/hho_inspect.h, include/hho_sdirk.h).
 
 Argument marshalling only: every step of the explicit Runge-Kutta path runs in the
 HIP kernels of the library.  If the library is not built this module raises; there is
@@ -32,6 +32,13 @@ class _Mesh(C.Structure):
     _fields_ = [("n_vertices", C.c_int32), ("xy", C.c_void_p), ("n_cells", C.c_int32),
                 ("cell_ptr", C.c_void_p), ("cell_vtx", C.c_void_p), ("medium", C.c_void_p),
                 ("rho", C.c_void_p), ("a", C.c_void_p), ("b", C.c_void_p)]
+
+
+class _SdirkParams(C.Structure):
+    _fields_ = [("k", C.c_int32), ("mixed", C.c_int32), ("alpha", C.c_int32), ("eta_f", C.c_double),
+                ("eta_s", C.c_double), ("stab_speed", C.c_int32), ("ell", C.c_double), ("stages", C.c_int32),
+                ("dt", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32), ("device", C.c_int32),
+                ("stream", C.c_void_p)]
 
 
 class _Params(C.Structure):
@@ -78,6 +85,18 @@ EXPORTS = {
     "hho_inspect_grad_coefs": (C.c_int, [C.c_void_p, C.c_void_p]),
     "hho_inspect_erk": (C.c_int, [C.c_int32, C.c_void_p]),
     "hho_inspect_dt_cfl": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double)]),
+    "hho_sdirk_setup": (C.c_int, [C.POINTER(_Mesh), C.POINTER(_SdirkParams), C.POINTER(C.c_void_p)]),
+    "hho_sdirk_destroy": (None, [C.c_void_p]),
+    "hho_sdirk_last_error": (C.c_char_p, [C.c_void_p]),
+    "hho_sdirk_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+    "hho_sdirk_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "hho_sdirk_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "hho_sdirk_set_sources": (C.c_int, [C.c_void_p, C.c_int32] + [C.c_void_p] * 5),
+    "hho_sdirk_step": (C.c_int, [C.c_void_p, C.c_double, C.c_int32]),
+    "hho_sdirk_energy": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "hho_sdirk_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "hho_sdirk_inspect_sizes": (C.c_int, [C.POINTER(_Mesh), C.POINTER(_SdirkParams), C.c_void_p]),
+    "hho_sdirk_inspect_face_matrix": (C.c_int, [C.POINTER(_Mesh), C.POINTER(_SdirkParams)] + [C.c_void_p] * 4),
 }
 
 _lib = None
@@ -413,3 +432,119 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _sdirk_params(k, mixed, alpha, eta_f, eta_s, stab_speed, ell, stages, dt, tol, max_iter, device, stream):
+    p = _SdirkParams()
+    p.k, p.mixed, p.alpha = int(k), int(mixed), int(alpha)
+    p.eta_f, p.eta_s, p.stab_speed, p.ell = float(eta_f), float(eta_s), int(stab_speed), float(ell)
+    p.stages, p.dt, p.tol, p.max_iter = int(stages), float(dt), float(tol), int(max_iter)
+    p.device, p.stream = int(device), stream
+    return p
+
+
+def _sdirk_check(lib, code, h):
+    if code != 0:
+        msg = lib.hho_sdirk_last_error(h).decode()
+        raise (Unstable if code == 6 else HHOError)(code, msg)
+
+
+class SdirkEngine:
+    """SDIRK(stages, stages+1) stepping with static condensation of the cell unknowns and a
+    BiCGStab face solve (hho_sdirk_setup); see include/hho_sdirk.h.  State arrays are float64 in
+    that header's per-cell layout, numpy (host) or contiguous float64 torch cuda tensors."""
+
+    def __init__(self, mesh, k, dt, stages=3, mixed=True, alpha=1, eta_f=1.0, eta_s=1.0, stab_speed=0, ell=0.0,
+                 tol=1e-10, max_iter=2000, device=0, stream=None):
+        lib = load_library()
+        self.lib = lib
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    stream = torch.cuda.current_stream(device).cuda_stream
+            except Exception:
+                stream = None
+        keep = {}
+        m = _mesh_struct(mesh, keep)
+        p = _sdirk_params(k, mixed, alpha, eta_f, eta_s, stab_speed, ell, stages, dt, tol, max_iter, device, stream)
+        h = C.c_void_p()
+        _sdirk_check(lib, lib.hho_sdirk_setup(C.byref(m), C.byref(p), C.byref(h)), None)
+        self._h = h
+        self.k, self.dt, self.stages = k, dt, stages
+        nd, nf, nnz = C.c_int64(), C.c_int32(), C.c_int64()
+        self._call(lib.hho_sdirk_sizes, C.byref(nd), C.byref(nf), C.byref(nnz))
+        self.n_dof, self.n_face_dof, self.nnz = nd.value, nf.value, nnz.value
+
+    def _call(self, fn, *args):
+        _sdirk_check(self.lib, fn(self._h, *args), self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.hho_sdirk_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, U):
+        dp = Engine._dev_ptr(U)
+        if dp is not None:
+            self._call(self.lib.hho_sdirk_set_state, dp, 1)
+            return
+        U = np.ascontiguousarray(U, np.float64)
+        if U.size != self.n_dof:
+            raise ValueError("state has %d values, expected %d" % (U.size, self.n_dof))
+        self._call(self.lib.hho_sdirk_set_state, _ptr(U), 0)
+
+    def get_state(self, out=None):
+        if out is not None and Engine._dev_ptr(out) is not None:
+            self._call(self.lib.hho_sdirk_get_state, Engine._dev_ptr(out), 1)
+            return out
+        U = np.zeros(self.n_dof)
+        self._call(self.lib.hho_sdirk_get_state, _ptr(U), 0)
+        return U
+
+    def set_sources(self, xy, direction, f0, t0, amp):
+        xy = np.ascontiguousarray(np.asarray(xy, np.float64).reshape(-1))
+        n = len(xy) // 2
+        d = np.ascontiguousarray(np.broadcast_to(np.asarray(direction, np.float64), (n, 2)).reshape(-1))
+        arr = lambda v: np.ascontiguousarray(np.broadcast_to(np.asarray(v, np.float64), (n,)))
+        f0, t0, amp = arr(f0), arr(t0), arr(amp)
+        self._call(self.lib.hho_sdirk_set_sources, n, _ptr(xy), _ptr(d), _ptr(f0), _ptr(t0), _ptr(amp))
+
+    def step(self, t0, n_steps):
+        self._call(self.lib.hho_sdirk_step, float(t0), int(n_steps))
+
+    def energy(self):
+        e = C.c_double()
+        self._call(self.lib.hho_sdirk_energy, C.byref(e))
+        return e.value
+
+    def stats(self):
+        """(face solves, BiCGStab iterations, largest final relative residual) since setup."""
+        a, b, c = C.c_int64(), C.c_int64(), C.c_double()
+        self._call(self.lib.hho_sdirk_stats, C.byref(a), C.byref(b), C.byref(c))
+        return a.value, b.value, c.value
+
+
+def sdirk_face_matrix(mesh, k, dt, stages=3, mixed=True, alpha=1, eta_f=1.0, eta_s=1.0, stab_speed=0, ell=0.0):
+    """Host-only: the condensed face matrix of hho_sdirk_setup as (ptr, col, val, face) with
+    face[d] = (lower vertex, higher vertex, index in the face block) of face unknown d."""
+    lib = load_library()
+    keep = {}
+    m = _mesh_struct(mesh, keep)
+    p = _sdirk_params(k, mixed, alpha, eta_f, eta_s, stab_speed, ell, stages, dt, 1e-10, 1, 0, None)
+    sz = np.zeros(5, np.int64)
+    _sdirk_check(lib, lib.hho_sdirk_inspect_sizes(C.byref(m), C.byref(p), _ptr(sz)), None)
+    nfd, nnz = int(sz[1]), int(sz[2])
+    ptr = np.zeros(nfd + 1, np.int32)
+    col = np.zeros(max(nnz, 1), np.int32)
+    val = np.zeros(max(nnz, 1))
+    face = np.zeros((max(nfd, 1), 3), np.int32)
+    _sdirk_check(lib, lib.hho_sdirk_inspect_face_matrix(C.byref(m), C.byref(p), _ptr(ptr), _ptr(col), _ptr(val),
+                                                        _ptr(face)), None)
+    return ptr, col[:nnz], val[:nnz], face[:nfd]
