@@ -319,6 +319,73 @@ def run_paper_bilayer(k, dtype="f64"):
     return out
 
 
+SDIRK_BILAYER = {"dtt": 0.398, "paper_cpu_s": {"direct": {1: 207.0, 3: 1095.0}, "iterative": {1: 281.0, 3: 1352.0}}}
+
+
+def sdirk_bytes_per_step(fp, stages, iterations):
+    """Algorithmic bytes of one SDIRK(s, s+1) step of the engine (float64): per stage the
+    per-cell matrices once ([A^{-1}; V] and W), the cell vectors of the stage (U^n, the earlier
+    Y_j, B, g, U, Y_i: 8 + i words per unknown over the stage, i earlier stages), the face-slot
+    products and their indices, and the face vectors outside the iterations (about 12 words per
+    face unknown); per BiCGStab iteration two products with the face matrix and two with the
+    face-block preconditioner (8-byte value + 4-byte column per nonzero, row pointers, source and
+    result vectors) and 22 face-vector words of the updates and dot products; the final combine
+    (s + 4 words per cell unknown)."""
+    nd, nf = fp["n_dof"], fp["n_face_dof"]
+    stage = 0.0
+    for i in range(stages):
+        stage += 8.0 * fp["cell_matrix_values"] + 8.0 * (8 + i) * nd
+        stage += (2 * 8 + 4) * fp["n_slot"] + 8.0 * nf + 8.0 * (12 + i) * nf
+    spmv = lambda nnz: 12.0 * nnz + 4.0 * (nf + 1) + 16.0 * nf
+    it = 2 * spmv(fp["nnz"]) + 2 * spmv(fp["precond_nnz"]) + 8.0 * 22 * nf
+    return stage + iterations * it + 8.0 * (stages + 4) * nd
+
+
+def run_sdirk_bilayer(k, steps=None, tol=1e-8):
+    """The paper's implicit run of Table tab::cfl_cpu (Sec. 5.2): the granite-water bilayer,
+    SDIRK(3,4), mixed order k' = k + 1 with the O(1/h) Lehrenfeld-Schoberl stabilisation, normalised
+    step dt~ = cP dt / h = 0.398, from the pressure pulse to T_f = 0.5 s (or `steps` steps), face
+    solves by BiCGStab to the relative residual `tol`.  Reports the run time, the iterations per
+    face solve, DOF-stage updates/s (cell unknowns x stages x steps / s) and the algorithmic bytes
+    of the whole step per second against the HBM peak, beside the paper's CPU seconds for its
+    direct and iterative solvers (hardware not stated)."""
+    from paper_2505_15771_amd import SdirkEngine
+    mesh = M.granite_water()
+    dt = SDIRK_BILAYER["dtt"] * 23.6 / 6000.0
+    n_full = int(np.ceil(0.5 / dt - 1e-9))
+    n = n_full if steps is None else min(steps, n_full)
+    t0 = time.perf_counter()
+    eng = SdirkEngine(mesh, k, dt, stages=3, mixed=True, alpha=1, tol=tol, max_iter=5000)
+    setup_s = time.perf_counter() - t0
+    U0 = M.pressure_pulse(mesh, k, k_primal=k + 1)
+    eng.set_state(U0)
+    eng.step(0.0, 2)   # warm-up
+    eng.set_state(U0)
+    E0 = eng.energy()
+    s0, i0, _ = eng.stats()
+    t1 = time.perf_counter()
+    eng.step(0.0, n)
+    secs = time.perf_counter() - t1
+    s1, i1, res = eng.stats()
+    E1 = eng.energy()
+    fp = eng.footprint()
+    iters = (i1 - i0) / max(s1 - s0, 1)
+    byt = sdirk_bytes_per_step(fp, 3, iters * 3)
+    gbs = byt * n / secs / 1e9
+    out = dict(workload="paper granite-water bilayer (Table tab::cfl_cpu), 17710 squares, k=%d, SDIRK(3,4), "
+                        "mixed order, T_f = 0.5 s" % k, dtype="f64", k=k, steps=n, steps_to_t_final=n_full, dt=dt,
+               cell_dofs=fp["n_dof"], face_dofs=fp["n_face_dof"], face_matrix_nnz=fp["nnz"], tol=tol,
+               iterations_per_solve=iters, max_rel_residual=res, run_s=secs, ms_per_step=1e3 * secs / n,
+               setup_s=setup_s, value=fp["n_dof"] * 3 * n / secs, unit="DOF-stage updates/s",
+               bytes_per_step=byt, gbs=gbs, frac=gbs / HBM_PEAK_GBS,
+               run_s_to_t_final=secs * n_full / n,
+               paper_cpu_s=dict(direct=SDIRK_BILAYER["paper_cpu_s"]["direct"][k],
+                                iterative=SDIRK_BILAYER["paper_cpu_s"]["iterative"][k]),
+               paper_hardware="not stated", energy_ratio=E1 / E0)
+    eng.close()
+    return out
+
+
 def run_cfl(k, n=32, shots=32, delta=0.01, eps=0.05):
     """Algorithm algo_CFL (Sec. 5.1) on the two-material CFL geometry with h = 1/n, ERK(4),
     T_f = 1, from a seeded random state (every mode excited): hho_cfl_search with `shots`
@@ -458,7 +525,7 @@ def main():
     ap.add_argument("--shots", type=int, default=1)
     ap.add_argument("--variants", type=int, default=1, help="also time the float64 / k=3 / batched variants")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--only", choices=("adjoint", "basin", "batch", "paper", "cfl", "precision", "tableaux"),
+    ap.add_argument("--only", choices=("adjoint", "basin", "batch", "paper", "cfl", "precision", "tableaux", "sdirk"),
                     default=None,
                     help="run one extra workload alone and print its JSON line (for profiling)")
     ap.add_argument("--only-steps", type=int, default=200)
@@ -492,7 +559,9 @@ def main():
               "paper": lambda: [run_paper_bilayer(1), run_paper_bilayer(3)],
               "cfl": lambda: [run_cfl(k_) for k_ in (1, 2, 3)],
               "precision": lambda: run_precision(steps=args.only_steps),
-              "tableaux": lambda: run_tableaux(steps=args.only_steps)}[args.only]
+              "tableaux": lambda: run_tableaux(steps=args.only_steps),
+              "sdirk": lambda: [run_sdirk_bilayer(1, steps=args.only_steps), run_sdirk_bilayer(3, steps=args.only_steps)]
+              }[args.only]
         print(json.dumps(fn()), flush=True)
         return
     mesh = M.hybrid_square(256)
@@ -524,6 +593,11 @@ def main():
             v = run_paper_bilayer(k_)
             print("workload", json.dumps(v), file=sys.stderr, flush=True)
             workloads.append(v)
+            w = run_sdirk_bilayer(k_)
+            w["erk4_run_s"] = v["run_s"]
+            w["erk4_over_sdirk_time"] = v["run_s"] / w["run_s_to_t_final"]
+            print("workload", json.dumps(w), file=sys.stderr, flush=True)
+            workloads.append(w)
         for k_ in (1, 2, 3):
             v = run_cfl(k_)
             print("workload", json.dumps(v), file=sys.stderr, flush=True)

@@ -116,6 +116,25 @@ bool gj_inverse(int n, std::vector<double> A, std::vector<double> &X) {
     return true;
 }
 
+// Inverse after symmetric diagonal scaling D A D, D = diag(A_ii)^(-1/2) (every matrix inverted
+// here has a positive diagonal: a mass matrix plus a term whose symmetric part is positive
+// semi-definite), so that materials of very different magnitudes (1/kappa next to rho) do not
+// trip the pivot test; A^{-1} = D (D A D)^{-1} D.
+bool scaled_inverse(int n, const std::vector<double> &A, std::vector<double> &X) {
+    std::vector<double> d(n), B((size_t)n * n);
+    for (int i = 0; i < n; ++i) {
+        const double a = A[(size_t)i * n + i];
+        if (!(a > 0.0) || !std::isfinite(a)) return false;
+        d[i] = 1.0 / std::sqrt(a);
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) B[(size_t)i * n + j] = d[i] * A[(size_t)i * n + j] * d[j];
+    if (!gj_inverse(n, B, X)) return false;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) X[(size_t)i * n + j] *= d[i] * d[j];
+    return true;
+}
+
 // (E_alpha)_{cd} of the symmetric tensor basis
 double tensor_basis(int al, int c, int d) {
     if (al == 0) return (c == 0 && d == 0) ? 1.0 : 0.0;
@@ -600,7 +619,7 @@ std::string build(int nv, const double *xy, int nc, const int32_t *cell_ptr, con
         // condensation of the cell unknowns
         std::vector<double> Amat((size_t)nT * nT), Ainv;
         for (size_t q = 0; q < Amat.size(); ++q) Amat[q] = MT[q] + adt * KT[q];
-        if (!gj_inverse(nT, Amat, Ainv)) return "stage matrix of cell " + std::to_string(c) + " is singular";
+        if (!scaled_inverse(nT, Amat, Ainv)) return "stage matrix of cell " + std::to_string(c) + " is singular";
         std::vector<double> V((size_t)nS * nT, 0.0), W((size_t)nT * nS, 0.0), ST((size_t)nS * nS, 0.0);
         for (int q = 0; q < nS; ++q)
             for (int r = 0; r < nT; ++r) {
@@ -661,6 +680,14 @@ std::string build(int nv, const double *xy, int nc, const int32_t *cell_ptr, con
             P.S_col[q] = rows[d][q - P.S_ptr[d]].first;
             P.S_val[q] = rows[d][q - P.S_ptr[d]].second;
         }
+    P.dscale.assign(P.n_fdof, 1.0);
+    for (int d = 0; d < P.n_fdof; ++d) {
+        double dg = 0.0;
+        for (int q = P.S_ptr[d]; q < P.S_ptr[d + 1]; ++q)
+            if (P.S_col[q] == d) dg = P.S_val[q];
+        if (!(dg > 0.0) || !std::isfinite(dg)) { *code = 3; return "face matrix has a non-positive diagonal entry"; }
+        P.dscale[d] = 1.0 / std::sqrt(dg);
+    }
     P.P_ptr.assign(P.n_fdof + 1, 0);
     for (int f = 0; f < nfc; ++f) {
         const int w = fw[f] * nf, d0 = foff[f];
@@ -669,9 +696,10 @@ std::string build(int nv, const double *xy, int nc, const int32_t *cell_ptr, con
         for (int i = 0; i < w; ++i)
             for (int q = P.S_ptr[d0 + i]; q < P.S_ptr[d0 + i + 1]; ++q) {
                 const int col = P.S_col[q];
-                if (col >= d0 && col < d0 + w) B[(size_t)i * w + (col - d0)] = P.S_val[q];
+                if (col >= d0 && col < d0 + w)
+                    B[(size_t)i * w + (col - d0)] = P.dscale[d0 + i] * P.S_val[q] * P.dscale[col];
             }
-        if (!gj_inverse(w, B, Bi)) return "diagonal block of face " + std::to_string(f) + " is singular";
+        if (!scaled_inverse(w, B, Bi)) return "diagonal block of face " + std::to_string(f) + " is singular";
         for (int i = 0; i < w; ++i) {
             P.P_ptr[d0 + i + 1] = w;
             for (int j = 0; j < w; ++j) { P.P_col.push_back(d0 + j); P.P_val.push_back(Bi[(size_t)i * w + j]); }

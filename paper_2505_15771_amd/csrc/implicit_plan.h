@@ -53,7 +53,11 @@ struct Plan {
     // condensed face matrix S = a* dt (K_F - a* dt K_FT (M + a* dt K_T)^{-1} K_TF), CSR
     std::vector<int32_t> S_ptr, S_col;
     std::vector<double> S_val;
-    // block-Jacobi preconditioner: inverse of the diagonal block of every face, CSR
+    // symmetric scaling of the face system: it is solved as (D S D) y = D b, x = D y, with
+    // D = diag(S)^(-1/2), so that fluid and solid face rows (weights 1/(rho c) against rho c)
+    // weigh alike in the residual norm
+    std::vector<double> dscale;  // [n_fdof]
+    // block-Jacobi preconditioner: inverse of the diagonal block of every face of D S D, CSR
     std::vector<int32_t> P_ptr, P_col;
     std::vector<double> P_val;
     // for every face unknown the (at most two) per-slot entries that feed it, -1 if none

@@ -100,10 +100,11 @@ __global__ void __launch_bounds__(kThreads) k_cell_apply(GroupTable G, long long
     else cf[G.cf_off[g] + (long long)(r - nT) * n + i] = acc;
 }
 
-// bF_i = -sum_{j<i} (a_ij / a*) E_j ; rhs = bF_i - (V B) fed by the (at most two) cells
+// bF_i = -sum_{j<i} (a_ij / a*) E_j ; rhs = D (bF_i - (V B) fed by the (at most two) cells)
 __global__ void __launch_bounds__(kThreads) k_face_rhs(int nfd, const int *__restrict__ feed, const double *__restrict__ cf,
                                                        const double *__restrict__ E, int nprev, double q0, double q1,
-                                                       double *__restrict__ bF, double *__restrict__ rhs) {
+                                                       const double *__restrict__ dsc, double *__restrict__ bF,
+                                                       double *__restrict__ rhs) {
     const int d = blockIdx.x * kThreads + threadIdx.x;
     if (d >= nfd) return;
     double v = 0.0;
@@ -114,13 +115,14 @@ __global__ void __launch_bounds__(kThreads) k_face_rhs(int nfd, const int *__res
     double s = v;
     if (f0 >= 0) s -= cf[f0];
     if (f1 >= 0) s -= cf[f1];
-    rhs[d] = s;
+    rhs[d] = dsc[d] * s;   // right-hand side of the scaled system
 }
 
-// U = g - W x     (items: cell-vector elements)
+// U = g - W x, x = D y the face unknowns     (items: cell-vector elements)
 __global__ void __launch_bounds__(kThreads) k_recover(GroupTable G, long long ndof, const double *__restrict__ wmat,
-                                                      const int *__restrict__ slot_dof, const double *__restrict__ x,
-                                                      const double *__restrict__ gv, double *__restrict__ U) {
+                                                      const int *__restrict__ slot_dof, const double *__restrict__ y,
+                                                      const double *__restrict__ dsc, const double *__restrict__ gv,
+                                                      double *__restrict__ U) {
     const long long e = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (e >= ndof) return;
     const int g = find_group(G, e);
@@ -130,7 +132,10 @@ __global__ void __launch_bounds__(kThreads) k_recover(GroupTable G, long long nd
     const double *w = wmat + G.w_off[g] + (long long)r * nS * n + i;
     const int *sd = slot_dof + G.cf_off[g] + i;
     double acc = gv[e];
-    for (int q = 0; q < nS; ++q) acc -= w[(long long)q * n] * x[sd[(long long)q * n]];
+    for (int q = 0; q < nS; ++q) {
+        const int d = sd[(long long)q * n];
+        acc -= w[(long long)q * n] * (dsc[d] * y[d]);   // x = D y
+    }
     U[e] = acc;
 }
 
@@ -326,12 +331,12 @@ __global__ void __launch_bounds__(kThreads) k_update_xr(int n, double *__restric
     r[q] = s[q] - om * t[q];
 }
 
-// E_i = bF_i - (rhs - S x), the true residual given in res
+// E_i = bF_i - (b - S x), the true residual of the scaled system given in res
 __global__ void __launch_bounds__(kThreads) k_face_rows(int n, const double *__restrict__ bF, const double *__restrict__ res,
-                                                        double *__restrict__ Ei) {
+                                                        const double *__restrict__ dsc, double *__restrict__ Ei) {
     const int q = blockIdx.x * kThreads + threadIdx.x;
     if (q >= n) return;
-    Ei[q] = bF[q] - res[q];
+    Ei[q] = bF[q] - res[q] / dsc[q];   // res = D (b - S x)
 }
 
 __global__ void __launch_bounds__(kThreads) k_copy(long long n, const double *__restrict__ a, double *__restrict__ b) {
@@ -379,7 +384,7 @@ struct hho_sdirk {
     double *mats = nullptr, *wmat = nullptr, *mat = nullptr;
     int *slot_dof = nullptr, *feed = nullptr;
     int *S_ptr = nullptr, *S_col = nullptr, *P_ptr = nullptr, *P_col = nullptr;
-    double *S_val = nullptr, *P_val = nullptr;
+    double *S_val = nullptr, *P_val = nullptr, *dsc = nullptr;
     double *U = nullptr, *U0 = nullptr, *B = nullptr, *gv = nullptr, *Y = nullptr, *Z = nullptr, *cf = nullptr;
     double *E = nullptr, *bF = nullptr, *rhs = nullptr;
     double *x = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
@@ -521,12 +526,15 @@ hho_status read_scalars(hho_sdirk *ctx) {
         if (s_ != HHO_OK) return s_;       \
     } while (0)
 
-// BiCGStab on S x = rhs (x holds the initial guess); then E_i = bF - (rhs - S x)
+// BiCGStab on the scaled face system (D S D) y = D b (y holds the initial guess, the previous
+// stage's solution); then E_i = bF - (b - S x).  A solve whose recursively updated residual met the
+// tolerance but whose true residual is more than 10 tol restarts from its iterate (residual
+// replacement), at most three times; a breakdown restarts at most twice.
 hho_status face_solve(hho_sdirk *ctx, double *Ei) {
     const int n = ctx->plan.n_fdof;
     if (n == 0) return HHO_OK;
     const unsigned gr = grid_for(n);
-    int restarts = 0;
+    int restarts = 0, replacements = 0;
     for (;;) {
         SST(spmv(ctx, false, ctx->x, ctx->rhs, ctx->r, 1, 0));   // r = rhs - S x
         hipLaunchKernelGGL(k_copy, dim3(gr), dim3(kThreads), 0, ctx->stream, (long long)n, ctx->r, ctx->rh);
@@ -538,7 +546,6 @@ hho_status face_solve(hho_sdirk *ctx, double *Ei) {
             SCK(hipMemsetAsync(ctx->x, 0, n * sizeof(double), ctx->stream));
             break;
         }
-        int it = 0;
         while (ctx->h_sc[S_DONE] == 0.0) {
             for (int c = 0; c < kChunk; ++c) {
                 hipLaunchKernelGGL(k_update_p, dim3(gr), dim3(kThreads), 0, ctx->stream, n, ctx->r, ctx->v, ctx->p, ctx->sc);
@@ -555,10 +562,16 @@ hho_status face_solve(hho_sdirk *ctx, double *Ei) {
             }
             SCK(hipGetLastError());
             SST(read_scalars(ctx));
-            it += kChunk;
         }
         ctx->iterations += (int64_t)ctx->h_sc[S_ITER];
-        if (ctx->h_sc[S_DONE] == 1.0) break;
+        if (ctx->h_sc[S_DONE] == 1.0) {
+            SST(spmv(ctx, false, ctx->x, ctx->rhs, ctx->r, 1, 0));
+            SST(dots(ctx, ctx->r, ctx->r, nullptr, nullptr, F_TRUE, 0));
+            SST(read_scalars(ctx));
+            if (ctx->h_sc[S_TRR] <= 100.0 * ctx->h_sc[S_TOL2] * ctx->h_sc[S_BB] || replacements >= 3) break;
+            ++replacements;
+            continue;
+        }
         if (ctx->h_sc[S_DONE] == 3.0 || restarts >= 2) {
             ctx->err = ctx->h_sc[S_DONE] == 3.0 ? "face solve: no convergence within max_iter iterations"
                                                 : "face solve: BiCGStab broke down";
@@ -569,7 +582,7 @@ hho_status face_solve(hho_sdirk *ctx, double *Ei) {
     // true residual and the face rows of this stage
     SST(spmv(ctx, false, ctx->x, ctx->rhs, ctx->r, 1, 0));
     SST(dots(ctx, ctx->r, ctx->r, nullptr, nullptr, F_TRUE, 0));
-    hipLaunchKernelGGL(k_face_rows, dim3(gr), dim3(kThreads), 0, ctx->stream, n, ctx->bF, ctx->r, Ei);
+    hipLaunchKernelGGL(k_face_rows, dim3(gr), dim3(kThreads), 0, ctx->stream, n, ctx->bF, ctx->r, ctx->dsc, Ei);
     SCK(hipGetLastError());
     SST(read_scalars(ctx));
     ctx->solves += 1;
@@ -608,13 +621,13 @@ hho_status one_step(hho_sdirk *ctx, double t) {
         // face right-hand side
         if (P.n_fdof > 0)
             hipLaunchKernelGGL(k_face_rhs, dim3(grid_for(P.n_fdof)), dim3(kThreads), 0, ctx->stream, P.n_fdof, ctx->feed,
-                               ctx->cf, ctx->E, i, i > 0 ? P.A[i][0] / ast : 0.0, i > 1 ? P.A[i][1] / ast : 0.0, ctx->bF,
-                               ctx->rhs);
+                               ctx->cf, ctx->E, i, i > 0 ? P.A[i][0] / ast : 0.0, i > 1 ? P.A[i][1] / ast : 0.0, ctx->dsc,
+                               ctx->bF, ctx->rhs);
         SCK(hipGetLastError());
         SST(face_solve(ctx, ctx->E + (size_t)i * P.n_fdof));
         // cell recovery and the cell rows of K U^{n,i}
         hipLaunchKernelGGL(k_recover, dim3(gv), dim3(kThreads), 0, ctx->stream, ctx->gvec, nd, ctx->wmat, ctx->slot_dof,
-                           ctx->x, ctx->gv, ctx->U);
+                           ctx->x, ctx->dsc, ctx->gv, ctx->U);
         hipLaunchKernelGGL(k_stage_Y, dim3(gv), dim3(kThreads), 0, ctx->stream, ctx->gvec, nd, ctx->B, ctx->U, ctx->mat,
                            1.0 / adt, ctx->Y + (size_t)i * nd);
         SCK(hipGetLastError());
@@ -704,7 +717,13 @@ hho_status hho_sdirk_setup(const hho_mesh *mesh, const hho_sdirk_params *prm, hh
     UP(ctx->feed, P.feed);
     UP(ctx->S_ptr, P.S_ptr);
     UP(ctx->S_col, P.S_col);
-    UP(ctx->S_val, P.S_val);
+    {
+        std::vector<double> scaled(P.S_val.size());
+        for (int d = 0; d < P.n_fdof; ++d)
+            for (int q = P.S_ptr[d]; q < P.S_ptr[d + 1]; ++q) scaled[q] = P.dscale[d] * P.S_val[q] * P.dscale[P.S_col[q]];
+        UP(ctx->S_val, scaled);
+    }
+    UP(ctx->dsc, P.dscale);
     UP(ctx->P_ptr, P.P_ptr);
     UP(ctx->P_col, P.P_col);
     UP(ctx->P_val, P.P_val);
@@ -880,6 +899,18 @@ hho_status hho_sdirk_energy(hho_sdirk *ctx, double *E) {
     SCK(hipMemcpyAsync(ctx->h_sc, ctx->sc, kNumScalars * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     SCK(hipStreamSynchronize(ctx->stream));
     *E = ctx->h_sc[S_TRR];
+    return HHO_OK;
+}
+
+hho_status hho_sdirk_footprint(const hho_sdirk *ctx, int64_t *sizes) {
+    if (!ctx || !sizes) return HHO_ERR_ARG;
+    const auto &P = ctx->plan;
+    sizes[0] = P.n_dof;
+    sizes[1] = P.n_fdof;
+    sizes[2] = (int64_t)P.S_val.size();
+    sizes[3] = (int64_t)P.P_val.size();
+    sizes[4] = (int64_t)(P.mats.size() + P.wmat.size());
+    sizes[5] = P.n_slot;
     return HHO_OK;
 }
 

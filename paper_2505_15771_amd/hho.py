@@ -94,6 +94,7 @@ EXPORTS = {
     "hho_sdirk_set_sources": (C.c_int, [C.c_void_p, C.c_int32] + [C.c_void_p] * 5),
     "hho_sdirk_step": (C.c_int, [C.c_void_p, C.c_double, C.c_int32]),
     "hho_sdirk_energy": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "hho_sdirk_footprint": (C.c_int, [C.c_void_p, C.c_void_p]),
     "hho_sdirk_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "hho_sdirk_inspect_sizes": (C.c_int, [C.POINTER(_Mesh), C.POINTER(_SdirkParams), C.c_void_p]),
     "hho_sdirk_inspect_face_matrix": (C.c_int, [C.POINTER(_Mesh), C.POINTER(_SdirkParams)] + [C.c_void_p] * 4),
@@ -523,6 +524,13 @@ class SdirkEngine:
         e = C.c_double()
         self._call(self.lib.hho_sdirk_energy, C.byref(e))
         return e.value
+
+    def footprint(self):
+        """dict of the device plan sizes (hho_sdirk_footprint)."""
+        sz = np.zeros(6, np.int64)
+        self._call(self.lib.hho_sdirk_footprint, _ptr(sz))
+        keys = ("n_dof", "n_face_dof", "nnz", "precond_nnz", "cell_matrix_values", "n_slot")
+        return dict(zip(keys, (int(v) for v in sz)))
 
     def stats(self):
         """(face solves, BiCGStab iterations, largest final relative residual) since setup."""

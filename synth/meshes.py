@@ -306,15 +306,18 @@ def granite_water(nx=161, ny_s=68, ny_f=42):
     return with_materials(m, rho_f=1025.0, c_f=1500.0, rho_s=2690.0, cp_s=6000.0, cs_s=3000.0)
 
 
-def pressure_pulse(mesh, k, center=(0.0, 200.0), sigma=50.0):
+def pressure_pulse(mesh, k, center=(0.0, 200.0), sigma=50.0, k_primal=None):
     """Initial state with a Gaussian pressure bump exp(-|x - center|^2 / (2 sigma^2)) in the
     fluid: the lowest (constant) coefficient of p per fluid cell, scaled by sqrt(area) (the
     constant function of an orthonormal cell basis is 1/sqrt(area)); everything else zero.
     External layout: per cell in input order, [p | m_x | m_y] (fluid) or [v_x | v_y | s]
-    (solid), N = (k+1)(k+2)/2 coefficients per field."""
+    (solid), N = (k+1)(k+2)/2 coefficients per field, or N' = (k'+1)(k'+2)/2 for p and v when
+    k_primal = k' is given (cell degree k' of the primal fields, k of the dual ones)."""
     N = (k + 1) * (k + 2) // 2
+    kp = k if k_primal is None else k_primal
+    Np = (kp + 1) * (kp + 2) // 2
     med = np.asarray(mesh["medium"])
-    per = np.where(med == FLUID, 3 * N, 5 * N)
+    per = np.where(med == FLUID, Np + 2 * N, 2 * Np + 3 * N)
     off = np.concatenate([[0], np.cumsum(per)[:-1]])
     xy, ptr, vtx = mesh["xy"], mesh["cell_ptr"], mesh["cell_vtx"]
     U = np.zeros(int(per.sum()))

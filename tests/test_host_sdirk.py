@@ -50,6 +50,33 @@ def test_face_matrix_matches_oracle_schur_complement(k, mixed, stages, alpha, st
     assert np.abs(S - S_ref).max() <= 1e-13 * np.abs(S_ref).max()
 
 
+@pytest.mark.parametrize("k", [1, 3])
+def test_face_matrix_with_physical_materials(k):
+    """Granite (rho 2690, cP 6000 m/s) under water (rho 1025, c 1500 m/s) on a coarse bilayer: mass
+    entries from 1/kappa ~ 4e-10 to rho ~ 3e3 in one stage matrix.  The plan's per-cell inverses
+    are scaled so that this spread is harmless; the face matrix still equals the oracle's."""
+    m = M.granite_water(nx=6, ny_s=3, ny_f=2)
+    dt = 0.398 * 3800.0 / 6 / 6000.0
+    io = ImplicitOracle(m, k)
+    A, _, _ = sdirk_tableau(3)
+    adt = A[0, 0] * dt
+    K = io.K.toarray()
+    nd = io.ndof
+    KT, KTF, KFT, KF = K[:nd, :nd], K[:nd, nd:], K[nd:, :nd], K[nd:, nd:]
+    S_ref = adt * (KF - adt * KFT @ np.linalg.solve(io.M.toarray() + adt * KT, KTF))
+    ptr, col, val, face = hho.sdirk_face_matrix(m, k, dt)
+    key = {}
+    for f in range(len(io.ftag)):
+        for i in range(int(io.foff[f + 1] - io.foff[f])):
+            key[(int(io.fv[f, 0]), int(io.fv[f, 1]), i)] = int(io.foff[f]) - nd + i
+    perm = np.array([key[tuple(int(v) for v in face[d])] for d in range(len(face))])
+    S = _dense(ptr, col, val)
+    S_ref = S_ref[np.ix_(perm, perm)]
+    # row-wise relative comparison: fluid and solid rows differ by orders of magnitude
+    scale = np.abs(S_ref).max(axis=1, keepdims=True)
+    assert (np.abs(S - S_ref) <= 1e-12 * scale).all()
+
+
 def test_given_domain_length_scales_the_weights():
     """alpha = 1 with l_Omega given explicitly equal to the diameter gives the same matrix as the
     computed diameter (sqrt 2 for the unit square); another l_Omega changes it."""
