@@ -200,14 +200,16 @@ __global__ void k_src_add(int n, const SrcDev *__restrict__ src, double t, doubl
 }
 
 // ---------------------------------------------------------------- BiCGStab
-enum Scalar { S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_RR, S_BB, S_DONE, S_ITER, S_TOL2, S_TRR, kNumScalars = 16 };
+// Solver scalars live on the device; every dot product is summed per block inside the kernel that
+// produces its operands, and a one-block kernel reduces the block sums (fixed order) and updates
+// the scalars, so an iteration is p-update, S p_hat, (alpha), s-update, S s_hat, (omega),
+// x/r-update, (rho, beta, stop test): eight launches.
+enum Scalar { S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_BB, S_DONE, S_ITER, S_TOL2, S_TRR, S_RR, kNumScalars = 16 };
 
 // y = A x (mode 0) or y = b - A x (mode 1); 8 lanes per row
 __global__ void __launch_bounds__(kThreads) k_spmv(int nrows, const int *__restrict__ ptr, const int *__restrict__ col,
                                                    const double *__restrict__ val, const double *__restrict__ x,
-                                                   const double *__restrict__ b, double *__restrict__ y, int mode,
-                                                   const double *__restrict__ sc, int respect_done) {
-    if (respect_done && sc[S_DONE] != 0.0) return;
+                                                   const double *__restrict__ b, double *__restrict__ y, int mode) {
     const int t = blockIdx.x * kThreads + threadIdx.x;
     const int row = t >> 3, lane = t & 7;
     double acc = 0.0;
@@ -221,18 +223,9 @@ __global__ void __launch_bounds__(kThreads) k_spmv(int nrows, const int *__restr
     if (row < nrows && lane == 0) y[row] = mode ? b[row] - acc : acc;
 }
 
-// partial sums of a.b and c.d per block (part[2 * block + {0, 1}])
-__global__ void __launch_bounds__(kThreads) k_dot2(int n, const double *__restrict__ a, const double *__restrict__ b,
-                                                   const double *__restrict__ c, const double *__restrict__ d,
-                                                   double *__restrict__ part, const double *__restrict__ sc,
-                                                   int respect_done) {
-    if (respect_done && sc[S_DONE] != 0.0) return;
+// block sums of two per-thread values into part[2 * blockIdx + {0, 1}]
+__device__ __forceinline__ void block_partials(double x0, double x1, double *__restrict__ part) {
     __shared__ double s0[kThreads], s1[kThreads];
-    double x0 = 0.0, x1 = 0.0;
-    for (int q = blockIdx.x * kThreads + threadIdx.x; q < n; q += gridDim.x * kThreads) {
-        x0 += a[q] * b[q];
-        if (c) x1 += c[q] * d[q];
-    }
     s0[threadIdx.x] = x0;
     s1[threadIdx.x] = x1;
     __syncthreads();
@@ -249,9 +242,21 @@ __global__ void __launch_bounds__(kThreads) k_dot2(int n, const double *__restri
     }
 }
 
+// partial sums of a.b and c.d per block (grid-stride)
+__global__ void __launch_bounds__(kThreads) k_dot2(int n, const double *__restrict__ a, const double *__restrict__ b,
+                                                   const double *__restrict__ c, const double *__restrict__ d,
+                                                   double *__restrict__ part) {
+    double x0 = 0.0, x1 = 0.0;
+    for (int q = blockIdx.x * kThreads + threadIdx.x; q < n; q += gridDim.x * kThreads) {
+        x0 += a[q] * b[q];
+        if (c) x1 += c[q] * d[q];
+    }
+    block_partials(x0, x1, part);
+}
+
 enum Finalize { F_INIT = 0, F_ALPHA = 1, F_OMEGA = 2, F_RR = 3, F_TRUE = 4 };
 
-// reduce the partial sums (fixed order) and update the solver scalars (one block)
+// one block: reduce nblk partial pairs (a, b) in a fixed order and update the scalars
 __global__ void __launch_bounds__(kThreads) k_finalize(int nblk, const double *__restrict__ part, double *__restrict__ sc,
                                                        int kind, int max_iter) {
     if (kind != F_INIT && kind != F_TRUE && sc[S_DONE] != 0.0) return;
@@ -303,32 +308,91 @@ __global__ void __launch_bounds__(kThreads) k_finalize(int nblk, const double *_
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_update_p(int n, const double *__restrict__ r, const double *__restrict__ v,
-                                                       double *__restrict__ p, const double *__restrict__ sc) {
+// p = r + beta (p_old - omega v) and p_hat = P p (P the face-block inverse: the row's block of p
+// is recomputed from r, p_old and v, so p_old stays unwritten)
+__global__ void __launch_bounds__(kThreads) k_bicg_p(int n, const int *__restrict__ Pptr, const int *__restrict__ Pcol,
+                                                     const double *__restrict__ Pval, const double *__restrict__ r,
+                                                     const double *__restrict__ v, const double *__restrict__ p_old,
+                                                     double *__restrict__ p_new, double *__restrict__ ph,
+                                                     const double *__restrict__ sc) {
     if (sc[S_DONE] != 0.0) return;
-    const int q = blockIdx.x * kThreads + threadIdx.x;
-    if (q >= n) return;
-    p[q] = r[q] + sc[S_BETA] * (p[q] - sc[S_OMEGA] * v[q]);
+    const int d = blockIdx.x * kThreads + threadIdx.x;
+    if (d >= n) return;
+    const double beta = sc[S_BETA], om = sc[S_OMEGA];
+    double acc = 0.0;
+    for (int q = Pptr[d]; q < Pptr[d + 1]; ++q) {
+        const int j = Pcol[q];
+        acc += Pval[q] * (r[j] + beta * (p_old[j] - om * v[j]));
+    }
+    p_new[d] = r[d] + beta * (p_old[d] - om * v[d]);
+    ph[d] = acc;
 }
 
-__global__ void __launch_bounds__(kThreads) k_update_s(int n, const double *__restrict__ r, const double *__restrict__ v,
-                                                       double *__restrict__ s, const double *__restrict__ sc) {
+// y = S x (8 lanes per row, grid-stride over rows) with the block sums of (w.y) and (y.y); the grid
+// is capped so that the one-block reduction that follows has few block sums to add
+__global__ void __launch_bounds__(kThreads) k_bicg_spmv(int n, const int *__restrict__ ptr, const int *__restrict__ col,
+                                                        const double *__restrict__ val, const double *__restrict__ x,
+                                                        double *__restrict__ y, const double *__restrict__ w,
+                                                        double *__restrict__ part, const double *__restrict__ sc) {
     if (sc[S_DONE] != 0.0) return;
-    const int q = blockIdx.x * kThreads + threadIdx.x;
-    if (q >= n) return;
-    s[q] = r[q] - sc[S_ALPHA] * v[q];
+    const int lane = threadIdx.x & 7;
+    const int rows_per_pass = gridDim.x * (kThreads >> 3);
+    double d0 = 0.0, d1 = 0.0;
+    for (int base = 0; base < n; base += rows_per_pass) {
+        const int row = base + blockIdx.x * (kThreads >> 3) + (threadIdx.x >> 3);
+        double acc = 0.0;
+        if (row < n) {
+            const int e1 = ptr[row + 1];
+            for (int q = ptr[row] + lane; q < e1; q += 8) acc += val[q] * x[col[q]];
+        }
+        acc += __shfl_xor(acc, 4, 8);
+        acc += __shfl_xor(acc, 2, 8);
+        acc += __shfl_xor(acc, 1, 8);
+        if (row < n && lane == 0) {
+            y[row] = acc;
+            d0 += w[row] * acc;
+            d1 += acc * acc;
+        }
+    }
+    block_partials(d0, d1, part);
 }
 
-__global__ void __launch_bounds__(kThreads) k_update_xr(int n, double *__restrict__ x, const double *__restrict__ ph,
-                                                        const double *__restrict__ sh, const double *__restrict__ s,
-                                                        const double *__restrict__ t, double *__restrict__ r,
-                                                        const double *__restrict__ sc) {
+// s = r - alpha v and s_hat = P s
+__global__ void __launch_bounds__(kThreads) k_bicg_s(int n, const int *__restrict__ Pptr, const int *__restrict__ Pcol,
+                                                     const double *__restrict__ Pval, const double *__restrict__ r,
+                                                     const double *__restrict__ v, double *__restrict__ s,
+                                                     double *__restrict__ sh, const double *__restrict__ sc) {
     if (sc[S_DONE] != 0.0) return;
-    const int q = blockIdx.x * kThreads + threadIdx.x;
-    if (q >= n) return;
-    const double al = sc[S_ALPHA], om = sc[S_OMEGA];
-    x[q] += al * ph[q] + om * sh[q];
-    r[q] = s[q] - om * t[q];
+    const int d = blockIdx.x * kThreads + threadIdx.x;
+    if (d >= n) return;
+    const double al = sc[S_ALPHA];
+    double acc = 0.0;
+    for (int q = Pptr[d]; q < Pptr[d + 1]; ++q) {
+        const int j = Pcol[q];
+        acc += Pval[q] * (r[j] - al * v[j]);
+    }
+    s[d] = r[d] - al * v[d];
+    sh[d] = acc;
+}
+
+// x += alpha p_hat + omega s_hat; r = s - omega t; block sums of (r.r) and (r_hat.r)
+__global__ void __launch_bounds__(kThreads) k_bicg_x(int n, double *__restrict__ x, double *__restrict__ r,
+                                                     const double *__restrict__ rh, const double *__restrict__ ph,
+                                                     const double *__restrict__ sh, const double *__restrict__ s,
+                                                     const double *__restrict__ t, double *__restrict__ part,
+                                                     const double *__restrict__ sc) {
+    if (sc[S_DONE] != 0.0) return;
+    const int d = blockIdx.x * kThreads + threadIdx.x;
+    double d0 = 0.0, d1 = 0.0;
+    if (d < n) {
+        const double al = sc[S_ALPHA], om = sc[S_OMEGA];
+        x[d] += al * ph[d] + om * sh[d];
+        const double rn = s[d] - om * t[d];
+        r[d] = rn;
+        d0 = rn * rn;
+        d1 = rh[d] * rn;
+    }
+    block_partials(d0, d1, part);
 }
 
 // E_i = bF_i - (b - S x), the true residual of the scaled system given in res
@@ -367,7 +431,8 @@ __global__ void __launch_bounds__(kThreads) k_energy(GroupTable G, long long ndo
 unsigned grid_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 constexpr int kDotBlocks = 512;
-constexpr int kChunk = 8;  // BiCGStab iterations enqueued between residual checks
+constexpr int kSpmvBlocks = 1024;  // grid cap of the solver's matrix products
+constexpr int kChunk = 8;  // BiCGStab iterations between residual checks (even: parities repeat)
 
 }  // namespace
 
@@ -387,8 +452,12 @@ struct hho_sdirk {
     double *S_val = nullptr, *P_val = nullptr, *dsc = nullptr;
     double *U = nullptr, *U0 = nullptr, *B = nullptr, *gv = nullptr, *Y = nullptr, *Z = nullptr, *cf = nullptr;
     double *E = nullptr, *bF = nullptr, *rhs = nullptr;
-    double *x = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
-    double *ph = nullptr, *sh = nullptr, *part = nullptr, *sc = nullptr;
+    double *x = nullptr, *r = nullptr, *rh = nullptr, *pb[2] = {nullptr, nullptr}, *v = nullptr, *s = nullptr;
+    double *t = nullptr, *ph = nullptr, *sh = nullptr, *part = nullptr, *sc = nullptr;
+    double *partS = nullptr;  // block sums of the solver kernels
+    // kChunk iterations captured once as a graph (fixed arguments), replayed per chunk
+    hipStream_t cap = nullptr;
+    hipGraphExec_t chunk = nullptr;
     double *h_sc = nullptr;  // pinned
     SrcDev *src = nullptr;
     int n_src = 0;
@@ -492,24 +561,23 @@ void fill_groups(hho_sdirk *ctx) {
 
 long long mat_items(const hho_sdirk *ctx) { return ctx->gmat.item_off[ctx->gmat.ng]; }
 
-// dot products a.b (and c.d) into the scalar update `kind`
-hho_status dots(hho_sdirk *ctx, const double *a, const double *b, const double *c, const double *d, int kind,
-                int respect_done) {
+// dot products a.b (and c.d) reduced into the solver scalars (F_INIT starts a solve, F_TRUE stores
+// the true residual)
+hho_status dots(hho_sdirk *ctx, const double *a, const double *b, const double *c, const double *d, int kind) {
     const int n = ctx->plan.n_fdof;
     const int nblk = std::min<int>(kDotBlocks, std::max<int>(1, (int)grid_for(n)));
-    hipLaunchKernelGGL(k_dot2, dim3(nblk), dim3(kThreads), 0, ctx->stream, n, a, b, c, d, ctx->part, ctx->sc,
-                       respect_done);
+    hipLaunchKernelGGL(k_dot2, dim3(nblk), dim3(kThreads), 0, ctx->stream, n, a, b, c, d, ctx->part);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, ctx->stream, nblk, ctx->part, ctx->sc, kind,
                        ctx->max_iter);
     SCK(hipGetLastError());
     return HHO_OK;
 }
 
-hho_status spmv(hho_sdirk *ctx, bool precond, const double *x, const double *b, double *y, int mode, int respect_done) {
+// r = b - S x
+hho_status residual(hho_sdirk *ctx, const double *x, const double *b, double *r) {
     const int n = ctx->plan.n_fdof;
-    hipLaunchKernelGGL(k_spmv, dim3(grid_for(8LL * n)), dim3(kThreads), 0, ctx->stream, n,
-                       precond ? ctx->P_ptr : ctx->S_ptr, precond ? ctx->P_col : ctx->S_col,
-                       precond ? ctx->P_val : ctx->S_val, x, b, y, mode, ctx->sc, respect_done);
+    hipLaunchKernelGGL(k_spmv, dim3(grid_for(8LL * n)), dim3(kThreads), 0, ctx->stream, n, ctx->S_ptr, ctx->S_col,
+                       ctx->S_val, x, b, r, 1);
     SCK(hipGetLastError());
     return HHO_OK;
 }
@@ -518,6 +586,46 @@ hho_status read_scalars(hho_sdirk *ctx) {
     SCK(hipMemcpyAsync(ctx->h_sc, ctx->sc, kNumScalars * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     SCK(hipStreamSynchronize(ctx->stream));
     return HHO_OK;
+}
+
+// kChunk BiCGStab iterations, eight launches each, on stream st (p alternates between two
+// buffers by iteration parity; kChunk is even, so every chunk starts from the same buffer)
+void enqueue_chunk(hho_sdirk *ctx, hipStream_t st) {
+    const int n = ctx->plan.n_fdof;
+    const dim3 gr(grid_for(n)), gs(std::min<unsigned>(grid_for(8LL * n), kSpmvBlocks)), b(kThreads);
+    const int ns = (int)gs.x;
+    for (int it = 0; it < kChunk; ++it) {
+        const int par = it & 1;
+        hipLaunchKernelGGL(k_bicg_p, gr, b, 0, st, n, ctx->P_ptr, ctx->P_col, ctx->P_val, ctx->r, ctx->v, ctx->pb[par],
+                           ctx->pb[par ^ 1], ctx->ph, ctx->sc);
+        hipLaunchKernelGGL(k_bicg_spmv, gs, b, 0, st, n, ctx->S_ptr, ctx->S_col, ctx->S_val, ctx->ph, ctx->v, ctx->rh,
+                           ctx->partS, ctx->sc);
+        hipLaunchKernelGGL(k_finalize, dim3(1), b, 0, st, ns, ctx->partS, ctx->sc, (int)F_ALPHA, ctx->max_iter);
+        hipLaunchKernelGGL(k_bicg_s, gr, b, 0, st, n, ctx->P_ptr, ctx->P_col, ctx->P_val, ctx->r, ctx->v, ctx->s, ctx->sh,
+                           ctx->sc);
+        hipLaunchKernelGGL(k_bicg_spmv, gs, b, 0, st, n, ctx->S_ptr, ctx->S_col, ctx->S_val, ctx->sh, ctx->t, ctx->s,
+                           ctx->partS, ctx->sc);
+        hipLaunchKernelGGL(k_finalize, dim3(1), b, 0, st, ns, ctx->partS, ctx->sc, (int)F_OMEGA, ctx->max_iter);
+        hipLaunchKernelGGL(k_bicg_x, gr, b, 0, st, n, ctx->x, ctx->r, ctx->rh, ctx->ph, ctx->sh, ctx->s, ctx->t,
+                           ctx->partS, ctx->sc);
+        hipLaunchKernelGGL(k_finalize, dim3(1), b, 0, st, (int)gr.x, ctx->partS, ctx->sc, (int)F_RR, ctx->max_iter);
+    }
+}
+
+// capture one chunk into a graph (once per context); on failure chunks are launched directly
+void capture_chunk(hho_sdirk *ctx) {
+    if (ctx->chunk || !ctx->cap) return;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return;
+    enqueue_chunk(ctx, ctx->cap);
+    if (hipStreamEndCapture(ctx->cap, &graph) != hipSuccess || !graph) {
+        (void)hipGetLastError();
+        return;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) == hipSuccess) ctx->chunk = ex;
+    (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
 }
 
 #define SST(call)                          \
@@ -535,38 +643,28 @@ hho_status face_solve(hho_sdirk *ctx, double *Ei) {
     if (n == 0) return HHO_OK;
     const unsigned gr = grid_for(n);
     int restarts = 0, replacements = 0;
+    capture_chunk(ctx);
     for (;;) {
-        SST(spmv(ctx, false, ctx->x, ctx->rhs, ctx->r, 1, 0));   // r = rhs - S x
+        SST(residual(ctx, ctx->x, ctx->rhs, ctx->r));
         hipLaunchKernelGGL(k_copy, dim3(gr), dim3(kThreads), 0, ctx->stream, (long long)n, ctx->r, ctx->rh);
-        SCK(hipMemsetAsync(ctx->p, 0, n * sizeof(double), ctx->stream));
+        SCK(hipMemsetAsync(ctx->pb[0], 0, n * sizeof(double), ctx->stream));
         SCK(hipMemsetAsync(ctx->v, 0, n * sizeof(double), ctx->stream));
-        SST(dots(ctx, ctx->rhs, ctx->rhs, ctx->r, ctx->r, F_INIT, 0));
+        SST(dots(ctx, ctx->rhs, ctx->rhs, ctx->r, ctx->r, F_INIT));
         SST(read_scalars(ctx));
         if (ctx->h_sc[S_BB] == 0.0) {   // zero right-hand side: the solution is zero
             SCK(hipMemsetAsync(ctx->x, 0, n * sizeof(double), ctx->stream));
             break;
         }
         while (ctx->h_sc[S_DONE] == 0.0) {
-            for (int c = 0; c < kChunk; ++c) {
-                hipLaunchKernelGGL(k_update_p, dim3(gr), dim3(kThreads), 0, ctx->stream, n, ctx->r, ctx->v, ctx->p, ctx->sc);
-                SST(spmv(ctx, true, ctx->p, nullptr, ctx->ph, 0, 1));
-                SST(spmv(ctx, false, ctx->ph, nullptr, ctx->v, 0, 1));
-                SST(dots(ctx, ctx->rh, ctx->v, nullptr, nullptr, F_ALPHA, 1));
-                hipLaunchKernelGGL(k_update_s, dim3(gr), dim3(kThreads), 0, ctx->stream, n, ctx->r, ctx->v, ctx->s, ctx->sc);
-                SST(spmv(ctx, true, ctx->s, nullptr, ctx->sh, 0, 1));
-                SST(spmv(ctx, false, ctx->sh, nullptr, ctx->t, 0, 1));
-                SST(dots(ctx, ctx->t, ctx->s, ctx->t, ctx->t, F_OMEGA, 1));
-                hipLaunchKernelGGL(k_update_xr, dim3(gr), dim3(kThreads), 0, ctx->stream, n, ctx->x, ctx->ph, ctx->sh,
-                                   ctx->s, ctx->t, ctx->r, ctx->sc);
-                SST(dots(ctx, ctx->r, ctx->r, ctx->rh, ctx->r, F_RR, 1));
-            }
+            if (ctx->chunk) SCK(hipGraphLaunch(ctx->chunk, ctx->stream));
+            else enqueue_chunk(ctx, ctx->stream);
             SCK(hipGetLastError());
             SST(read_scalars(ctx));
         }
         ctx->iterations += (int64_t)ctx->h_sc[S_ITER];
         if (ctx->h_sc[S_DONE] == 1.0) {
-            SST(spmv(ctx, false, ctx->x, ctx->rhs, ctx->r, 1, 0));
-            SST(dots(ctx, ctx->r, ctx->r, nullptr, nullptr, F_TRUE, 0));
+            SST(residual(ctx, ctx->x, ctx->rhs, ctx->r));
+            SST(dots(ctx, ctx->r, ctx->r, nullptr, nullptr, F_TRUE));
             SST(read_scalars(ctx));
             if (ctx->h_sc[S_TRR] <= 100.0 * ctx->h_sc[S_TOL2] * ctx->h_sc[S_BB] || replacements >= 3) break;
             ++replacements;
@@ -580,8 +678,8 @@ hho_status face_solve(hho_sdirk *ctx, double *Ei) {
         ++restarts;  // breakdown: restart from the current iterate with a fresh shadow residual
     }
     // true residual and the face rows of this stage
-    SST(spmv(ctx, false, ctx->x, ctx->rhs, ctx->r, 1, 0));
-    SST(dots(ctx, ctx->r, ctx->r, nullptr, nullptr, F_TRUE, 0));
+    SST(residual(ctx, ctx->x, ctx->rhs, ctx->r));
+    SST(dots(ctx, ctx->r, ctx->r, nullptr, nullptr, F_TRUE));
     hipLaunchKernelGGL(k_face_rows, dim3(gr), dim3(kThreads), 0, ctx->stream, n, ctx->bF, ctx->r, ctx->dsc, Ei);
     SCK(hipGetLastError());
     SST(read_scalars(ctx));
@@ -741,13 +839,15 @@ hho_status hho_sdirk_setup(const hho_mesh *mesh, const hho_sdirk_params *prm, hh
     AL(ctx->x, nf);
     AL(ctx->r, nf);
     AL(ctx->rh, nf);
-    AL(ctx->p, nf);
+    AL(ctx->pb[0], nf);
+    AL(ctx->pb[1], nf);
     AL(ctx->v, nf);
     AL(ctx->s, nf);
     AL(ctx->t, nf);
     AL(ctx->ph, nf);
     AL(ctx->sh, nf);
     AL(ctx->part, 2 * (size_t)kDotBlocks);
+    AL(ctx->partS, 2 * (size_t)grid_for(8LL * std::max<int>(P.n_fdof, 1)));
     AL(ctx->sc, kNumScalars);
 #undef UP
 #undef AL
@@ -755,6 +855,7 @@ hho_status hho_sdirk_setup(const hho_mesh *mesh, const hho_sdirk_params *prm, hh
         ctx->err = "hipHostMalloc failed";
         return fail(HHO_ERR_OOM);
     }
+    if (hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) ctx->cap = nullptr;
     const double tol2 = ctx->tol * ctx->tol;
     if (hipMemcpyAsync(ctx->sc + S_TOL2, &tol2, sizeof(double), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
@@ -769,6 +870,8 @@ void hho_sdirk_destroy(hho_sdirk *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->chunk) (void)hipGraphExecDestroy(ctx->chunk);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     for (void *p : ctx->allocs) (void)hipFree(p);
     if (ctx->h_sc) (void)hipHostFree(ctx->h_sc);
     delete ctx;
