@@ -277,9 +277,12 @@ def run_precision(k=2, steps=2000):
 
 
 PAPER_BILAYER = {1: (0.159, 161.0), 3: (0.054, 3322.0)}  # Table tab::cfl_cpu: ERK(4) dt~, CPU s
+# the sensors of the timing case (Sec. 5.2): S^f records p, S^s and S^i record v (S^i at y = 0 lies
+# in the granite, 7.3 m below this mesh's interface)
+BILAYER_SENSORS = ([[-500.0, 200.0], [-1000.0, -500.0], [-400.0, 0.0]], [0, 1, 1])
 
 
-def run_paper_bilayer(k, dtype="f64"):
+def run_paper_bilayer(k, dtype="f64", sensors=False):
     """The paper's timed ERK(4) run (Sec. 5.2, Table tab::cfl_cpu): granite-water bilayer,
     161 x 110 squares of 23.6 m, a pressure pulse in the water, T_f = 0.5 s at the paper's
     normalised step dt~ = cP dt / h (0.159 for k = 1, 0.054 for k = 3).  Reports the time of
@@ -293,6 +296,8 @@ def run_paper_bilayer(k, dtype="f64"):
     n = int(np.ceil(0.5 / dt - 1e-9))
     t0 = time.perf_counter()
     eng = Engine(mesh, k, dtype=dtype, record_energy=True)
+    if sensors:
+        eng.set_receivers(*BILAYER_SENSORS)
     U0 = M.pressure_pulse(mesh, k)
     eng.set_state(U0)
     eng.autotune()
@@ -315,6 +320,8 @@ def run_paper_bilayer(k, dtype="f64"):
                run_s=secs, setup_s=setup_s, value=eng.n_dof * 4 * n / secs,
                paper_cpu_s=paper_s, paper_hardware="not stated", speedup_vs_paper=paper_s / secs,
                energy_ratio=float(E[-1] / E_init), finite=bool(np.all(np.isfinite(E))))
+    if sensors:
+        out["_traces"] = (dt * np.arange(1, n + 1), eng.traces())
     eng.close()
     return out
 
@@ -341,7 +348,18 @@ def sdirk_bytes_per_step(fp, stages, iterations):
     return stage + iterations * it + 8.0 * (stages + 4) * nd
 
 
-def run_sdirk_bilayer(k, steps=None, tol=1e-8):
+def sensor_differences(t_a, tr_a, t_b, tr_b):
+    """Relative l2-in-time differences of run a's sensor traces from run b's, b interpolated
+    linearly at a's times (the measure of eq. error_ricker, between two runs): one value per
+    sensor, components together."""
+    out = []
+    for r in range(tr_a.shape[1]):
+        b = np.stack([np.interp(t_a, t_b, tr_b[:, r, c]) for c in range(2)], axis=1)
+        out.append(float(np.linalg.norm(tr_a[:, r, :] - b) / max(np.linalg.norm(b), 1e-300)))
+    return out
+
+
+def run_sdirk_bilayer(k, steps=None, tol=1e-8, erk_traces=None):
     """The paper's implicit run of Table tab::cfl_cpu (Sec. 5.2): the granite-water bilayer,
     SDIRK(3,4), mixed order k' = k + 1 with the O(1/h) Lehrenfeld-Schoberl stabilisation, normalised
     step dt~ = cP dt / h = 0.398, from the pressure pulse to T_f = 0.5 s (or `steps` steps), face
@@ -358,6 +376,7 @@ def run_sdirk_bilayer(k, steps=None, tol=1e-8):
     eng = SdirkEngine(mesh, k, dt, stages=3, mixed=True, alpha=1, tol=tol, max_iter=5000)
     setup_s = time.perf_counter() - t0
     U0 = M.pressure_pulse(mesh, k, k_primal=k + 1)
+    eng.set_receivers(*BILAYER_SENSORS)
     eng.set_state(U0)
     eng.step(0.0, 2)   # warm-up
     eng.set_state(U0)
@@ -382,6 +401,9 @@ def run_sdirk_bilayer(k, steps=None, tol=1e-8):
                paper_cpu_s=dict(direct=SDIRK_BILAYER["paper_cpu_s"]["direct"][k],
                                 iterative=SDIRK_BILAYER["paper_cpu_s"]["iterative"][k]),
                paper_hardware="not stated", energy_ratio=E1 / E0)
+    if erk_traces is not None and n == n_full:
+        d = sensor_differences(dt * np.arange(1, n + 1), eng.traces(), *erk_traces)
+        out["sensor_diff_vs_erk4"] = dict(zip(("S_f_p", "S_s_v", "S_i_v"), d))
     eng.close()
     return out
 
@@ -560,7 +582,9 @@ def main():
               "cfl": lambda: [run_cfl(k_) for k_ in (1, 2, 3)],
               "precision": lambda: run_precision(steps=args.only_steps),
               "tableaux": lambda: run_tableaux(steps=args.only_steps),
-              "sdirk": lambda: [run_sdirk_bilayer(1, steps=args.only_steps), run_sdirk_bilayer(3, steps=args.only_steps)]
+              "sdirk": lambda: [run_sdirk_bilayer(k_, steps=args.only_steps,
+                                                  erk_traces=run_paper_bilayer(k_, sensors=True)["_traces"])
+                                for k_ in (1, 3)]
               }[args.only]
         print(json.dumps(fn()), flush=True)
         return
@@ -590,10 +614,11 @@ def main():
         print("workload", json.dumps(v), file=sys.stderr, flush=True)
         workloads.append(v)
         for k_ in (1, 3):
-            v = run_paper_bilayer(k_)
+            v = run_paper_bilayer(k_, sensors=True)
+            erk_tr = v.pop("_traces")
             print("workload", json.dumps(v), file=sys.stderr, flush=True)
             workloads.append(v)
-            w = run_sdirk_bilayer(k_)
+            w = run_sdirk_bilayer(k_, erk_traces=erk_tr)
             w["erk4_run_s"] = v["run_s"]
             w["erk4_over_sdirk_time"] = v["run_s"] / w["run_s_to_t_final"]
             print("workload", json.dumps(w), file=sys.stderr, flush=True)

@@ -95,6 +95,15 @@ hho_status hho_sdirk_set_sources(hho_sdirk *ctx, int32_t n, const double *xy, co
  * twice); the state is then that of the failing stage's step start. */
 hho_status hho_sdirk_step(hho_sdirk *ctx, double t0, int32_t n_steps);
 
+/* Receivers (replace earlier ones; n = 0 removes them): field 0 records p (the point must lie in
+ * a fluid cell), field 1 records (v_x, v_y) (solid cell); point values of the degree-k' cell
+ * polynomials (sensors of Sec. 5.2) recorded after every step of hho_sdirk_step.  The containing
+ * cell is the lowest-id cell whose closed polygon holds the point.  Errors: ARG. */
+hho_status hho_sdirk_receivers(hho_sdirk *ctx, int32_t n, const double *xy, const int32_t *field);
+
+/* Traces of the last hho_sdirk_step call: out[n_steps][n_rec][2] (second slot 0 for p), float64. */
+hho_status hho_sdirk_get_traces(hho_sdirk *ctx, double *out);
+
 /* Energy of the current state (Sec. 5.1, cell unknowns only), float64. */
 hho_status hho_sdirk_energy(hho_sdirk *ctx, double *E);
 

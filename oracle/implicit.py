@@ -365,6 +365,22 @@ class ImplicitOracle:
                 o += n
         return U
 
+    def point_values(self, U, x, y):
+        """(cell, values) of the cell polynomials of U at (x, y) in the lowest-id cell holding it:
+        fluid (p, m_x, m_y), solid (v_x, v_y, s_1, s_2, s_3)."""
+        c = self.geo.locate(x, y)
+        if c < 0:
+            raise ValueError("point outside the mesh")
+        ph, _, _ = self._cell_basis(c, np.array([x]), np.array([y]))
+        ph = ph[:, 0]
+        o = int(self.off[c])
+        sizes = [self.Np, self.N, self.N] if self.medium[c] == FLUID else [self.Np, self.Np] + [self.N] * 3
+        vals = []
+        for n in sizes:
+            vals.append(float(ph[:n] @ U[o:o + n]))
+            o += n
+        return c, np.array(vals)
+
     def energy(self, U):
         """Half the mass-weighted squared norm of the cell unknowns (Sec. 5.1)."""
         return 0.5 * float(U @ (self.M @ U))

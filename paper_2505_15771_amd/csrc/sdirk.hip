@@ -408,6 +408,19 @@ __global__ void __launch_bounds__(kThreads) k_copy(long long n, const double *__
     if (q < n) b[q] = a[q];
 }
 
+// receiver r, component c: out[2 r + c] = sum_a coef[(2 r + c) Np + a] U[idx[(2 r + c) Np + a]]
+__global__ void k_record(int n2, int Np, const long long *__restrict__ idx, const double *__restrict__ coef,
+                         const double *__restrict__ U, double *__restrict__ out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n2) return;
+    double acc = 0.0;
+    for (int a = 0; a < Np; ++a) {
+        const long long e = idx[(long long)q * Np + a];
+        if (e >= 0) acc += coef[(long long)q * Np + a] * U[e];
+    }
+    out[q] = acc;
+}
+
 // energy partial sums: 1/2 U . M U per block
 __global__ void __launch_bounds__(kThreads) k_energy(GroupTable G, long long ndof, const double *__restrict__ U,
                                                      const double *__restrict__ mat, double *__restrict__ part) {
@@ -461,6 +474,12 @@ struct hho_sdirk {
     double *h_sc = nullptr;  // pinned
     SrcDev *src = nullptr;
     int n_src = 0;
+    // receivers: per (receiver, component) Np (element, coefficient) pairs; traces of the last call
+    long long *rec_idx = nullptr;
+    double *rec_coef = nullptr, *traces = nullptr;
+    int n_rec = 0;
+    size_t trace_cap = 0;
+    int last_steps = 0;
     int64_t solves = 0, iterations = 0;
     double max_res = 0.0;
 };
@@ -495,6 +514,15 @@ hho_status dev_alloc(hho_sdirk *ctx, T **p, size_t count) {
         return HHO_ERR_DEVICE;
     }
     return HHO_OK;
+}
+
+// free a buffer made by dev_alloc (null-safe)
+void release(hho_sdirk *ctx, void *p) {
+    if (!p) return;
+    auto it = std::find(ctx->allocs.begin(), ctx->allocs.end(), p);
+    if (it != ctx->allocs.end()) ctx->allocs.erase(it);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(p);
 }
 
 template <typename T>
@@ -958,7 +986,8 @@ hho_status hho_sdirk_set_sources(hho_sdirk *ctx, int32_t n, const double *xy, co
             }
     }
     ctx->n_src = 0;
-    ctx->src = nullptr;  // earlier buffers stay in allocs until destroy
+    release(ctx, ctx->src);
+    ctx->src = nullptr;
     if (!v.empty()) {
         hho_status st = dev_alloc(ctx, &ctx->src, v.size());
         if (st != HHO_OK) return st;
@@ -976,6 +1005,18 @@ hho_status hho_sdirk_step(hho_sdirk *ctx, double t0, int32_t n_steps) {
         return HHO_ERR_ARG;
     }
     SCK(hipSetDevice(ctx->device));
+    if (ctx->n_rec > 0) {
+        const size_t need = (size_t)std::max(n_steps, 1) * ctx->n_rec * 2;
+        if (need > ctx->trace_cap) {
+            release(ctx, ctx->traces);
+            ctx->traces = nullptr;
+            ctx->trace_cap = 0;
+            hho_status st = dev_alloc(ctx, &ctx->traces, need);
+            if (st != HHO_OK) return st;
+            ctx->trace_cap = need;
+        }
+    }
+    ctx->last_steps = 0;
     for (int n = 0; n < n_steps; ++n) {
         hho_status st = one_step(ctx, t0 + n * ctx->plan.dt);
         if (st != HHO_OK) {
@@ -985,7 +1026,73 @@ hho_status hho_sdirk_step(hho_sdirk *ctx, double t0, int32_t n_steps) {
             (void)hipStreamSynchronize(ctx->stream);
             return st;
         }
+        if (ctx->n_rec > 0) {
+            hipLaunchKernelGGL(k_record, dim3((2 * ctx->n_rec + 63) / 64), dim3(64), 0, ctx->stream, 2 * ctx->n_rec,
+                               ctx->plan.Np, ctx->rec_idx, ctx->rec_coef, ctx->U,
+                               ctx->traces + (size_t)n * ctx->n_rec * 2);
+            SCK(hipGetLastError());
+        }
+        ctx->last_steps = n + 1;
     }
+    SCK(hipStreamSynchronize(ctx->stream));
+    return HHO_OK;
+}
+
+hho_status hho_sdirk_receivers(hho_sdirk *ctx, int32_t n, const double *xy, const int32_t *field) {
+    if (!ctx) return HHO_ERR_ARG;
+    if (n < 0 || (n > 0 && (!xy || !field))) {
+        ctx->err = "invalid receiver arrays";
+        return HHO_ERR_ARG;
+    }
+    SCK(hipSetDevice(ctx->device));
+    const auto &P = ctx->plan;
+    const int Np = P.Np;
+    std::vector<long long> idx((size_t)std::max(n, 1) * 2 * Np, -1);
+    std::vector<double> coef((size_t)std::max(n, 1) * 2 * Np, 0.0), phi(Np);
+    for (int q = 0; q < n; ++q) {
+        const int c = hho::imp::locate(P, xy[2 * q], xy[2 * q + 1]);
+        if (c < 0) {
+            ctx->err = "receiver " + std::to_string(q) + " lies outside the mesh";
+            return HHO_ERR_ARG;
+        }
+        if (field[q] != (int)P.medium[c] || (field[q] != 0 && field[q] != 1)) {
+            ctx->err = "receiver " + std::to_string(q) + ": field 0 (p) needs a fluid cell, field 1 (v) a solid one";
+            return HHO_ERR_ARG;
+        }
+        hho::imp::eval_basis(P, c, xy[2 * q], xy[2 * q + 1], phi.data());
+        const auto &g = P.groups[P.cell_group[c]];
+        const int i = P.cell_index[c];
+        for (int comp = 0; comp < (field[q] == 0 ? 1 : 2); ++comp)
+            for (int a = 0; a < Np; ++a) {
+                idx[((size_t)2 * q + comp) * Np + a] = g.vec_off + (int64_t)(comp * Np + a) * g.n + i;
+                coef[((size_t)2 * q + comp) * Np + a] = phi[a];
+            }
+    }
+    release(ctx, ctx->rec_idx);
+    release(ctx, ctx->rec_coef);
+    ctx->rec_idx = nullptr;
+    ctx->rec_coef = nullptr;
+    ctx->n_rec = 0;
+    ctx->last_steps = 0;
+    if (n > 0) {
+        hho_status st = dev_alloc(ctx, &ctx->rec_idx, idx.size());
+        if (st != HHO_OK) return st;
+        st = dev_alloc(ctx, &ctx->rec_coef, coef.size());
+        if (st != HHO_OK) return st;
+        SCK(hipMemcpyAsync(ctx->rec_idx, idx.data(), idx.size() * sizeof(long long), hipMemcpyHostToDevice, ctx->stream));
+        SCK(hipMemcpyAsync(ctx->rec_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        SCK(hipStreamSynchronize(ctx->stream));
+    }
+    ctx->n_rec = n;
+    return HHO_OK;
+}
+
+hho_status hho_sdirk_get_traces(hho_sdirk *ctx, double *out) {
+    if (!ctx || !out) return HHO_ERR_ARG;
+    if (ctx->n_rec == 0 || ctx->last_steps == 0) return HHO_OK;
+    SCK(hipSetDevice(ctx->device));
+    SCK(hipMemcpyAsync(out, ctx->traces, (size_t)ctx->last_steps * ctx->n_rec * 2 * sizeof(double),
+                       hipMemcpyDeviceToHost, ctx->stream));
     SCK(hipStreamSynchronize(ctx->stream));
     return HHO_OK;
 }

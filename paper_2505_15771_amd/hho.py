@@ -94,6 +94,8 @@ EXPORTS = {
     "hho_sdirk_set_sources": (C.c_int, [C.c_void_p, C.c_int32] + [C.c_void_p] * 5),
     "hho_sdirk_step": (C.c_int, [C.c_void_p, C.c_double, C.c_int32]),
     "hho_sdirk_energy": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "hho_sdirk_receivers": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "hho_sdirk_get_traces": (C.c_int, [C.c_void_p, C.c_void_p]),
     "hho_sdirk_footprint": (C.c_int, [C.c_void_p, C.c_void_p]),
     "hho_sdirk_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "hho_sdirk_inspect_sizes": (C.c_int, [C.POINTER(_Mesh), C.POINTER(_SdirkParams), C.c_void_p]),
@@ -517,8 +519,22 @@ class SdirkEngine:
         f0, t0, amp = arr(f0), arr(t0), arr(amp)
         self._call(self.lib.hho_sdirk_set_sources, n, _ptr(xy), _ptr(d), _ptr(f0), _ptr(t0), _ptr(amp))
 
+    def set_receivers(self, xy, field):
+        xy = np.ascontiguousarray(np.asarray(xy, np.float64).reshape(-1))
+        field = np.ascontiguousarray(np.asarray(field, np.int32).reshape(-1))
+        self._call(self.lib.hho_sdirk_receivers, len(field), _ptr(xy), _ptr(field))
+        self.n_rec = len(field)
+
     def step(self, t0, n_steps):
         self._call(self.lib.hho_sdirk_step, float(t0), int(n_steps))
+        self.last_steps = int(n_steps)
+
+    def traces(self):
+        """[n_steps, n_rec, 2] point values after every step of the last step() call."""
+        out = np.zeros((self.last_steps, getattr(self, "n_rec", 0), 2))
+        if out.size:
+            self._call(self.lib.hho_sdirk_get_traces, _ptr(out))
+        return out
 
     def energy(self):
         e = C.c_double()

@@ -89,3 +89,17 @@ def test_sdirk_bytes_per_step_counts():
     spmv = lambda nnz: 12.0 * nnz + 4.0 * 41 + 16.0 * 40
     per_it = 2 * spmv(400) + 2 * spmv(160) + 8.0 * 22 * 40
     assert bench.sdirk_bytes_per_step(fp, s, it) == stage + it * per_it + 8.0 * (s + 4) * 100
+
+
+def test_sensor_differences():
+    """Relative l2 differences between two runs' traces, the second interpolated at the first's
+    times: zero for the same smooth signal sampled on two grids (up to interpolation error), and
+    the relative size of a known perturbation."""
+    import bench
+    ta, tb = np.linspace(0.01, 1.0, 100), np.linspace(0.001, 1.0, 1000)
+    sig = lambda t: np.stack([np.sin(3 * t), np.cos(2 * t)], axis=1)[:, None, :]
+    a, b = sig(ta), sig(tb)
+    d = bench.sensor_differences(ta, a, tb, b)
+    assert len(d) == 1 and d[0] < 1e-4
+    d2 = bench.sensor_differences(ta, 1.01 * a, tb, b)
+    assert abs(d2[0] - 0.01) < 1e-4

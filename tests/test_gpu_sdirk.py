@@ -202,3 +202,39 @@ def test_full_size_bilayer_properties(k):
     err = rel(runs[1e-8], runs[1e-13])
     say("  tol 1e-8 vs 1e-13: rel L2", err)
     assert err < 1e-6
+
+
+def test_receiver_traces_parity():
+    """Receivers of p in the fluid and of v in the solid, recorded after every step, against the
+    oracle's point values of its state after each step; receivers in the wrong medium are refused."""
+    from oracle.implicit import ImplicitOracle
+    from paper_2505_15771_amd import SdirkEngine
+    from paper_2505_15771_amd.hho import HHOError
+    say("case: sdirk receivers")
+    m = _coupled(6, 80)
+    k, dt = 2, 0.02
+    io = ImplicitOracle(m, k)
+    io.set_point_sources([[0.45, 0.3]], [[0.0, 1.0]], 10.0, 0.05, 1.0)
+    e = SdirkEngine(m, k, dt, stages=3, tol=1e-14)
+    e.set_sources([[0.45, 0.3]], [[0.0, 1.0]], 10.0, 0.05, 1.0)
+    rx = [[0.3, 0.8], [0.7, 0.2], [0.52, 0.49]]
+    fld = [0, 1, 1]
+    e.set_receivers(rx, fld)
+    U0 = 0.1 * np.random.default_rng(81).standard_normal(io.ndof)
+    e.set_state(U0)
+    e.step(0.0, 6)
+    tr = e.traces()
+    assert tr.shape == (6, 3, 2)
+    U = U0.copy()
+    ref = np.zeros_like(tr)
+    for n in range(6):
+        U = io.sdirk(U, n * dt, dt, 1, s=3)
+        for r, (xy, f) in enumerate(zip(rx, fld)):
+            _, vals = io.point_values(U, *xy)
+            ref[n, r, :1 + f] = vals[:1 + f]
+    err = rel(tr, ref)
+    say("  traces rel L2", err)
+    assert err < TOL
+    with pytest.raises(HHOError):
+        e.set_receivers([[0.3, 0.2]], [0])    # p receiver in the solid
+    e.close()
