@@ -200,11 +200,15 @@ __global__ void k_src_add(int n, const SrcDev *__restrict__ src, double t, doubl
 }
 
 // ---------------------------------------------------------------- BiCGStab
-// Solver scalars live on the device; every dot product is summed per block inside the kernel that
-// produces its operands, and a one-block kernel reduces the block sums (fixed order) and updates
-// the scalars, so an iteration is p-update, S p_hat, (alpha), s-update, S s_hat, (omega),
-// x/r-update, (rho, beta, stop test): eight launches.
-enum Scalar { S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_BB, S_DONE, S_ITER, S_TOL2, S_TRR, S_RR, kNumScalars = 16 };
+// Solver scalars live on the device.  Every dot product is summed per workgroup inside the kernel
+// that produces its operands; the kernel that needs the result has each of its workgroups add
+// those block sums itself (the same sums in the same order, so every workgroup gets the same
+// value), and its workgroup 0 records the new scalars.  An iteration is five launches:
+// p-update, S p_hat, s-update, S s_hat, x/r-update.  Iteration scalars are kept per parity of the
+// iteration: iteration j reads block j & 1 and writes block (j & 1) ^ 1, so no workgroup reads a
+// slot that workgroup 0 of the same launch writes.
+enum Scalar { S_DONE = 0, S_BB, S_TOL2, S_TRR, S_ITER_OUT, S_RR_OUT, S_PAR = 8, kNumScalars = 32 };
+enum ParScalar { P_RHO = 0, P_ALPHA, P_OMEGA, P_ITER, kParStride = 8 };
 
 // y = A x (mode 0) or y = b - A x (mode 1); 8 lanes per row
 __global__ void __launch_bounds__(kThreads) k_spmv(int nrows, const int *__restrict__ ptr, const int *__restrict__ col,
@@ -223,7 +227,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv(int nrows, const int *__restr
     if (row < nrows && lane == 0) y[row] = mode ? b[row] - acc : acc;
 }
 
-// block sums of two per-thread values into part[2 * blockIdx + {0, 1}]
+// workgroup sums of two per-thread values into part[2 * blockIdx + {0, 1}]
 __device__ __forceinline__ void block_partials(double x0, double x1, double *__restrict__ part) {
     __shared__ double s0[kThreads], s1[kThreads];
     s0[threadIdx.x] = x0;
@@ -242,24 +246,8 @@ __device__ __forceinline__ void block_partials(double x0, double x1, double *__r
     }
 }
 
-// partial sums of a.b and c.d per block (grid-stride)
-__global__ void __launch_bounds__(kThreads) k_dot2(int n, const double *__restrict__ a, const double *__restrict__ b,
-                                                   const double *__restrict__ c, const double *__restrict__ d,
-                                                   double *__restrict__ part) {
-    double x0 = 0.0, x1 = 0.0;
-    for (int q = blockIdx.x * kThreads + threadIdx.x; q < n; q += gridDim.x * kThreads) {
-        x0 += a[q] * b[q];
-        if (c) x1 += c[q] * d[q];
-    }
-    block_partials(x0, x1, part);
-}
-
-enum Finalize { F_INIT = 0, F_ALPHA = 1, F_OMEGA = 2, F_RR = 3, F_TRUE = 4 };
-
-// one block: reduce nblk partial pairs (a, b) in a fixed order and update the scalars
-__global__ void __launch_bounds__(kThreads) k_finalize(int nblk, const double *__restrict__ part, double *__restrict__ sc,
-                                                       int kind, int max_iter) {
-    if (kind != F_INIT && kind != F_TRUE && sc[S_DONE] != 0.0) return;
+// the sums of nblk workgroup-sum pairs, in a fixed order (identical in every workgroup)
+__device__ __forceinline__ void reduce_partials(int nblk, const double *__restrict__ part, double &a, double &b) {
     __shared__ double s0[kThreads], s1[kThreads];
     double x0 = 0.0, x1 = 0.0;
     for (int q = threadIdx.x; q < nblk; q += kThreads) {
@@ -276,60 +264,99 @@ __global__ void __launch_bounds__(kThreads) k_finalize(int nblk, const double *_
         }
         __syncthreads();
     }
-    if (threadIdx.x != 0) return;
-    const double a = s0[0], b = s1[0];
-    if (kind == F_INIT) {           // a = b.b, b = r.r (r_hat = r)
-        sc[S_BB] = a;
-        sc[S_RR] = b;
-        sc[S_RHO] = b;
-        sc[S_ALPHA] = 1.0;
-        sc[S_OMEGA] = 1.0;
-        sc[S_BETA] = 0.0;
-        sc[S_ITER] = 0.0;
-        sc[S_DONE] = (b <= sc[S_TOL2] * a) ? 1.0 : 0.0;
-    } else if (kind == F_ALPHA) {   // a = r_hat.v
-        if (a == 0.0 || !isfinite(a)) sc[S_DONE] = 2.0;
-        else sc[S_ALPHA] = sc[S_RHO] / a;
-    } else if (kind == F_OMEGA) {   // a = t.s, b = t.t
-        sc[S_OMEGA] = b > 0.0 ? a / b : 0.0;
-    } else if (kind == F_RR) {      // a = r.r, b = r_hat.r
-        sc[S_RR] = a;
-        sc[S_ITER] += 1.0;
-        if (!isfinite(a)) sc[S_DONE] = 2.0;
-        else if (a <= sc[S_TOL2] * sc[S_BB]) sc[S_DONE] = 1.0;
-        else if (b == 0.0 || sc[S_OMEGA] == 0.0) sc[S_DONE] = 2.0;
-        else {
-            sc[S_BETA] = (b / sc[S_RHO]) * (sc[S_ALPHA] / sc[S_OMEGA]);
-            sc[S_RHO] = b;
-            if (sc[S_ITER] >= (double)max_iter) sc[S_DONE] = 3.0;
+    a = s0[0];
+    b = s1[0];
+    __syncthreads();
+}
+
+// partial sums of a.b and c.d per workgroup (grid-stride)
+__global__ void __launch_bounds__(kThreads) k_dot2(int n, const double *__restrict__ a, const double *__restrict__ b,
+                                                   const double *__restrict__ c, const double *__restrict__ d,
+                                                   double *__restrict__ part) {
+    double x0 = 0.0, x1 = 0.0;
+    for (int q = blockIdx.x * kThreads + threadIdx.x; q < n; q += gridDim.x * kThreads) {
+        x0 += a[q] * b[q];
+        if (c) x1 += c[q] * d[q];
+    }
+    block_partials(x0, x1, part);
+}
+
+enum Finalize { F_INIT = 0, F_TRUE = 1 };
+
+// one workgroup: reduce nblk partial pairs; F_INIT starts a solve (a = b.b, b = r.r with
+// r_hat = r: the parity-0 scalars, and partA = (r.r, r_hat.r) in its first of nA pairs for the
+// first iteration), F_TRUE stores a as the squared norm of a true residual
+__global__ void __launch_bounds__(kThreads) k_finalize(int nblk, const double *__restrict__ part, double *__restrict__ sc,
+                                                       int kind, double *__restrict__ partA, int nA) {
+    double a, b;
+    reduce_partials(nblk, part, a, b);
+    if (kind == F_INIT) {
+        for (int q = threadIdx.x; q < nA; q += kThreads) {
+            partA[2 * q] = q == 0 ? b : 0.0;
+            partA[2 * q + 1] = q == 0 ? b : 0.0;
         }
-    } else {                        // F_TRUE: a = r.r of the true residual
+        if (threadIdx.x == 0) {
+            double *p0 = sc + S_PAR;
+            sc[S_BB] = a;
+            sc[S_RR_OUT] = b;
+            sc[S_ITER_OUT] = 0.0;
+            p0[P_RHO] = b;
+            p0[P_ALPHA] = 1.0;
+            p0[P_OMEGA] = 1.0;
+            p0[P_ITER] = 0.0;
+            sc[S_DONE] = (b <= sc[S_TOL2] * a) ? 1.0 : 0.0;
+        }
+    } else if (threadIdx.x == 0) {
         sc[S_TRR] = a;
     }
 }
 
-// p = r + beta (p_old - omega v) and p_hat = P p (P the face-block inverse: the row's block of p
-// is recomputed from r, p_old and v, so p_old stays unwritten)
-__global__ void __launch_bounds__(kThreads) k_bicg_p(int n, const int *__restrict__ Pptr, const int *__restrict__ Pcol,
-                                                     const double *__restrict__ Pval, const double *__restrict__ r,
+// Face-block preconditioner: row d's block occupies the columns [pstart[d], pstart[d] + w) with
+// w = pptr[d + 1] - pptr[d]; values pval[pptr[d] + j] (float32: the preconditioner only steers
+// the iteration, the residual tests use the float64 matrix).
+
+// iteration start: from the previous iteration's (r.r, r_hat.r) decide to stop (converged,
+// breakdown, iteration limit); else beta = (rho / rho_old)(alpha / omega),
+// p = r + beta (p_old - omega v) and p_hat = P p (the row's block of p recomputed from r, p_old, v)
+__global__ void __launch_bounds__(kThreads) k_bicg_p(int n, const int *__restrict__ pptr, const int *__restrict__ pstart,
+                                                     const float *__restrict__ pval, const double *__restrict__ r,
                                                      const double *__restrict__ v, const double *__restrict__ p_old,
-                                                     double *__restrict__ p_new, double *__restrict__ ph,
-                                                     const double *__restrict__ sc) {
+                                                     double *__restrict__ p_new, double *__restrict__ ph, int nA,
+                                                     const double *__restrict__ partA, double *__restrict__ sc, int par,
+                                                     int max_iter) {
     if (sc[S_DONE] != 0.0) return;
+    double rr, rho;
+    reduce_partials(nA, partA, rr, rho);
+    const double *so = sc + S_PAR + par * kParStride;
+    double *sn = sc + S_PAR + (par ^ 1) * kParStride;
+    const double it = so[P_ITER];
+    int stop = 0;
+    if (!isfinite(rr) || !isfinite(rho)) stop = 2;
+    else if (rr <= sc[S_TOL2] * sc[S_BB]) stop = 1;
+    else if (rho == 0.0 || so[P_OMEGA] == 0.0) stop = 2;
+    else if (it >= (double)max_iter) stop = 3;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[S_RR_OUT] = rr;
+        if (stop) {
+            sc[S_DONE] = (double)stop;
+        } else {
+            sn[P_RHO] = rho;
+            sn[P_ITER] = it + 1.0;
+            sc[S_ITER_OUT] = it + 1.0;
+        }
+    }
+    if (stop) return;
     const int d = blockIdx.x * kThreads + threadIdx.x;
     if (d >= n) return;
-    const double beta = sc[S_BETA], om = sc[S_OMEGA];
+    const double beta = (rho / so[P_RHO]) * (so[P_ALPHA] / so[P_OMEGA]), om = so[P_OMEGA];
+    const int q0 = pptr[d], w = pptr[d + 1] - q0, j0 = pstart[d];
     double acc = 0.0;
-    for (int q = Pptr[d]; q < Pptr[d + 1]; ++q) {
-        const int j = Pcol[q];
-        acc += Pval[q] * (r[j] + beta * (p_old[j] - om * v[j]));
-    }
+    for (int j = 0; j < w; ++j) acc += (double)pval[q0 + j] * (r[j0 + j] + beta * (p_old[j0 + j] - om * v[j0 + j]));
     p_new[d] = r[d] + beta * (p_old[d] - om * v[d]);
     ph[d] = acc;
 }
 
-// y = S x (8 lanes per row, grid-stride over rows) with the block sums of (w.y) and (y.y); the grid
-// is capped so that the one-block reduction that follows has few block sums to add
+// y = S x (8 lanes per row, grid-stride over rows) with the workgroup sums of (w.y) and (y.y)
 __global__ void __launch_bounds__(kThreads) k_bicg_spmv(int n, const int *__restrict__ ptr, const int *__restrict__ col,
                                                         const double *__restrict__ val, const double *__restrict__ x,
                                                         double *__restrict__ y, const double *__restrict__ w,
@@ -357,42 +384,54 @@ __global__ void __launch_bounds__(kThreads) k_bicg_spmv(int n, const int *__rest
     block_partials(d0, d1, part);
 }
 
-// s = r - alpha v and s_hat = P s
-__global__ void __launch_bounds__(kThreads) k_bicg_s(int n, const int *__restrict__ Pptr, const int *__restrict__ Pcol,
-                                                     const double *__restrict__ Pval, const double *__restrict__ r,
+// alpha = rho / (r_hat.v); s = r - alpha v and s_hat = P s
+__global__ void __launch_bounds__(kThreads) k_bicg_s(int n, const int *__restrict__ pptr, const int *__restrict__ pstart,
+                                                     const float *__restrict__ pval, const double *__restrict__ r,
                                                      const double *__restrict__ v, double *__restrict__ s,
-                                                     double *__restrict__ sh, const double *__restrict__ sc) {
+                                                     double *__restrict__ sh, int nB, const double *__restrict__ partB,
+                                                     double *__restrict__ sc, int par) {
     if (sc[S_DONE] != 0.0) return;
+    double rv, unused;
+    reduce_partials(nB, partB, rv, unused);
+    double *sn = sc + S_PAR + (par ^ 1) * kParStride;
+    if (rv == 0.0 || !isfinite(rv)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) sc[S_DONE] = 2.0;
+        return;
+    }
+    const double al = sn[P_RHO] / rv;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sn[P_ALPHA] = al;
     const int d = blockIdx.x * kThreads + threadIdx.x;
     if (d >= n) return;
-    const double al = sc[S_ALPHA];
+    const int q0 = pptr[d], w = pptr[d + 1] - q0, j0 = pstart[d];
     double acc = 0.0;
-    for (int q = Pptr[d]; q < Pptr[d + 1]; ++q) {
-        const int j = Pcol[q];
-        acc += Pval[q] * (r[j] - al * v[j]);
-    }
+    for (int j = 0; j < w; ++j) acc += (double)pval[q0 + j] * (r[j0 + j] - al * v[j0 + j]);
     s[d] = r[d] - al * v[d];
     sh[d] = acc;
 }
 
-// x += alpha p_hat + omega s_hat; r = s - omega t; block sums of (r.r) and (r_hat.r)
+// omega = (t.s) / (t.t); x += alpha p_hat + omega s_hat; r = s - omega t; sums of (r.r), (r_hat.r)
 __global__ void __launch_bounds__(kThreads) k_bicg_x(int n, double *__restrict__ x, double *__restrict__ r,
                                                      const double *__restrict__ rh, const double *__restrict__ ph,
                                                      const double *__restrict__ sh, const double *__restrict__ s,
-                                                     const double *__restrict__ t, double *__restrict__ part,
-                                                     const double *__restrict__ sc) {
+                                                     const double *__restrict__ t, int nC,
+                                                     const double *__restrict__ partC, double *__restrict__ partA,
+                                                     double *__restrict__ sc, int par) {
     if (sc[S_DONE] != 0.0) return;
+    double ts, tt;
+    reduce_partials(nC, partC, ts, tt);
+    double *sn = sc + S_PAR + (par ^ 1) * kParStride;
+    const double om = tt > 0.0 ? ts / tt : 0.0, al = sn[P_ALPHA];
+    if (blockIdx.x == 0 && threadIdx.x == 0) sn[P_OMEGA] = om;
     const int d = blockIdx.x * kThreads + threadIdx.x;
     double d0 = 0.0, d1 = 0.0;
     if (d < n) {
-        const double al = sc[S_ALPHA], om = sc[S_OMEGA];
         x[d] += al * ph[d] + om * sh[d];
         const double rn = s[d] - om * t[d];
         r[d] = rn;
         d0 = rn * rn;
         d1 = rh[d] * rn;
     }
-    block_partials(d0, d1, part);
+    block_partials(d0, d1, partA);
 }
 
 // E_i = bF_i - (b - S x), the true residual of the scaled system given in res
@@ -461,13 +500,14 @@ struct hho_sdirk {
     // device buffers
     double *mats = nullptr, *wmat = nullptr, *mat = nullptr;
     int *slot_dof = nullptr, *feed = nullptr;
-    int *S_ptr = nullptr, *S_col = nullptr, *P_ptr = nullptr, *P_col = nullptr;
-    double *S_val = nullptr, *P_val = nullptr, *dsc = nullptr;
+    int *S_ptr = nullptr, *S_col = nullptr, *P_ptr = nullptr, *P_start = nullptr;
+    float *P_val = nullptr;
+    double *S_val = nullptr, *dsc = nullptr;
     double *U = nullptr, *U0 = nullptr, *B = nullptr, *gv = nullptr, *Y = nullptr, *Z = nullptr, *cf = nullptr;
     double *E = nullptr, *bF = nullptr, *rhs = nullptr;
     double *x = nullptr, *r = nullptr, *rh = nullptr, *pb[2] = {nullptr, nullptr}, *v = nullptr, *s = nullptr;
     double *t = nullptr, *ph = nullptr, *sh = nullptr, *part = nullptr, *sc = nullptr;
-    double *partS = nullptr;  // block sums of the solver kernels
+    double *partA = nullptr, *partB = nullptr, *partC = nullptr;  // workgroup sums of the solver kernels
     // kChunk iterations captured once as a graph (fixed arguments), replayed per chunk
     hipStream_t cap = nullptr;
     hipGraphExec_t chunk = nullptr;
@@ -595,8 +635,8 @@ hho_status dots(hho_sdirk *ctx, const double *a, const double *b, const double *
     const int n = ctx->plan.n_fdof;
     const int nblk = std::min<int>(kDotBlocks, std::max<int>(1, (int)grid_for(n)));
     hipLaunchKernelGGL(k_dot2, dim3(nblk), dim3(kThreads), 0, ctx->stream, n, a, b, c, d, ctx->part);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, ctx->stream, nblk, ctx->part, ctx->sc, kind,
-                       ctx->max_iter);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, ctx->stream, nblk, ctx->part, ctx->sc, kind, ctx->partA,
+                       (int)grid_for(n));
     SCK(hipGetLastError());
     return HHO_OK;
 }
@@ -616,27 +656,25 @@ hho_status read_scalars(hho_sdirk *ctx) {
     return HHO_OK;
 }
 
-// kChunk BiCGStab iterations, eight launches each, on stream st (p alternates between two
-// buffers by iteration parity; kChunk is even, so every chunk starts from the same buffer)
+// kChunk BiCGStab iterations, five launches each, on stream st (p alternates between two buffers
+// and the iteration scalars between two blocks by iteration parity; kChunk is even, so every
+// chunk starts from parity 0)
 void enqueue_chunk(hho_sdirk *ctx, hipStream_t st) {
     const int n = ctx->plan.n_fdof;
     const dim3 gr(grid_for(n)), gs(std::min<unsigned>(grid_for(8LL * n), kSpmvBlocks)), b(kThreads);
-    const int ns = (int)gs.x;
+    const int nA = (int)gr.x, nS = (int)gs.x;
     for (int it = 0; it < kChunk; ++it) {
         const int par = it & 1;
-        hipLaunchKernelGGL(k_bicg_p, gr, b, 0, st, n, ctx->P_ptr, ctx->P_col, ctx->P_val, ctx->r, ctx->v, ctx->pb[par],
-                           ctx->pb[par ^ 1], ctx->ph, ctx->sc);
+        hipLaunchKernelGGL(k_bicg_p, gr, b, 0, st, n, ctx->P_ptr, ctx->P_start, ctx->P_val, ctx->r, ctx->v,
+                           ctx->pb[par], ctx->pb[par ^ 1], ctx->ph, nA, ctx->partA, ctx->sc, par, ctx->max_iter);
         hipLaunchKernelGGL(k_bicg_spmv, gs, b, 0, st, n, ctx->S_ptr, ctx->S_col, ctx->S_val, ctx->ph, ctx->v, ctx->rh,
-                           ctx->partS, ctx->sc);
-        hipLaunchKernelGGL(k_finalize, dim3(1), b, 0, st, ns, ctx->partS, ctx->sc, (int)F_ALPHA, ctx->max_iter);
-        hipLaunchKernelGGL(k_bicg_s, gr, b, 0, st, n, ctx->P_ptr, ctx->P_col, ctx->P_val, ctx->r, ctx->v, ctx->s, ctx->sh,
-                           ctx->sc);
+                           ctx->partB, ctx->sc);
+        hipLaunchKernelGGL(k_bicg_s, gr, b, 0, st, n, ctx->P_ptr, ctx->P_start, ctx->P_val, ctx->r, ctx->v, ctx->s,
+                           ctx->sh, nS, ctx->partB, ctx->sc, par);
         hipLaunchKernelGGL(k_bicg_spmv, gs, b, 0, st, n, ctx->S_ptr, ctx->S_col, ctx->S_val, ctx->sh, ctx->t, ctx->s,
-                           ctx->partS, ctx->sc);
-        hipLaunchKernelGGL(k_finalize, dim3(1), b, 0, st, ns, ctx->partS, ctx->sc, (int)F_OMEGA, ctx->max_iter);
-        hipLaunchKernelGGL(k_bicg_x, gr, b, 0, st, n, ctx->x, ctx->r, ctx->rh, ctx->ph, ctx->sh, ctx->s, ctx->t,
-                           ctx->partS, ctx->sc);
-        hipLaunchKernelGGL(k_finalize, dim3(1), b, 0, st, (int)gr.x, ctx->partS, ctx->sc, (int)F_RR, ctx->max_iter);
+                           ctx->partC, ctx->sc);
+        hipLaunchKernelGGL(k_bicg_x, gr, b, 0, st, n, ctx->x, ctx->r, ctx->rh, ctx->ph, ctx->sh, ctx->s, ctx->t, nS,
+                           ctx->partC, ctx->partA, ctx->sc, par);
     }
 }
 
@@ -689,7 +727,7 @@ hho_status face_solve(hho_sdirk *ctx, double *Ei) {
             SCK(hipGetLastError());
             SST(read_scalars(ctx));
         }
-        ctx->iterations += (int64_t)ctx->h_sc[S_ITER];
+        ctx->iterations += (int64_t)ctx->h_sc[S_ITER_OUT];
         if (ctx->h_sc[S_DONE] == 1.0) {
             SST(residual(ctx, ctx->x, ctx->rhs, ctx->r));
             SST(dots(ctx, ctx->r, ctx->r, nullptr, nullptr, F_TRUE));
@@ -851,8 +889,14 @@ hho_status hho_sdirk_setup(const hho_mesh *mesh, const hho_sdirk_params *prm, hh
     }
     UP(ctx->dsc, P.dscale);
     UP(ctx->P_ptr, P.P_ptr);
-    UP(ctx->P_col, P.P_col);
-    UP(ctx->P_val, P.P_val);
+    {
+        std::vector<int> start(P.n_fdof);
+        std::vector<float> pv(P.P_val.size());
+        for (int d = 0; d < P.n_fdof; ++d) start[d] = P.P_col[P.P_ptr[d]];
+        for (size_t q = 0; q < pv.size(); ++q) pv[q] = (float)P.P_val[q];
+        UP(ctx->P_start, start);
+        UP(ctx->P_val, pv);
+    }
     const size_t nd = (size_t)P.n_dof, nf = (size_t)P.n_fdof;
     AL(ctx->U, nd);
     AL(ctx->U0, nd);
@@ -875,7 +919,9 @@ hho_status hho_sdirk_setup(const hho_mesh *mesh, const hho_sdirk_params *prm, hh
     AL(ctx->ph, nf);
     AL(ctx->sh, nf);
     AL(ctx->part, 2 * (size_t)kDotBlocks);
-    AL(ctx->partS, 2 * (size_t)grid_for(8LL * std::max<int>(P.n_fdof, 1)));
+    AL(ctx->partA, 2 * (size_t)grid_for(std::max<int>(P.n_fdof, 1)));
+    AL(ctx->partB, 2 * (size_t)kSpmvBlocks);
+    AL(ctx->partC, 2 * (size_t)kSpmvBlocks);
     AL(ctx->sc, kNumScalars);
 #undef UP
 #undef AL
@@ -1104,7 +1150,7 @@ hho_status hho_sdirk_energy(hho_sdirk *ctx, double *E) {
     const int nblk = std::min<int>(kDotBlocks, std::max<int>(1, (int)grid_for(nd)));
     hipLaunchKernelGGL(k_energy, dim3(nblk), dim3(kThreads), 0, ctx->stream, ctx->gvec, nd, ctx->U, ctx->mat, ctx->part);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, ctx->stream, nblk, ctx->part, ctx->sc, (int)F_TRUE,
-                       ctx->max_iter);
+                       ctx->partA, 0);
     SCK(hipGetLastError());
     SCK(hipMemcpyAsync(ctx->h_sc, ctx->sc, kNumScalars * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     SCK(hipStreamSynchronize(ctx->stream));
