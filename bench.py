@@ -337,14 +337,17 @@ def sdirk_bytes_per_step(fp, stages, iterations):
     face unknown); per BiCGStab iteration two products with the face matrix and two with the
     face-block preconditioner (8-byte value + 4-byte column per nonzero, row pointers, source and
     result vectors) and 22 face-vector words of the updates and dot products; the final combine
-    (s + 4 words per cell unknown)."""
+    (s + 4 words per cell unknown).  The face matrix moves 8 bytes per nonzero, its shared column
+    lists 4 bytes per stored index and 8 bytes of row offsets per row; the preconditioner 4 bytes
+    per nonzero and 8 per row."""
     nd, nf = fp["n_dof"], fp["n_face_dof"]
     stage = 0.0
     for i in range(stages):
         stage += 8.0 * fp["cell_matrix_values"] + 8.0 * (8 + i) * nd
         stage += (2 * 8 + 4) * fp["n_slot"] + 8.0 * nf + 8.0 * (12 + i) * nf
-    spmv = lambda nnz: 12.0 * nnz + 4.0 * (nf + 1) + 16.0 * nf
-    it = 2 * spmv(fp["nnz"]) + 2 * spmv(fp["precond_nnz"]) + 8.0 * 22 * nf
+    smat = 8.0 * fp["nnz"] + 4.0 * fp["shared_cols"] + 8.0 * nf + 16.0 * nf
+    pmat = 4.0 * fp["precond_nnz"] + 8.0 * nf + 16.0 * nf
+    it = 2 * smat + 2 * pmat + 8.0 * 22 * nf
     return stage + iterations * it + 8.0 * (stages + 4) * nd
 
 

@@ -107,10 +107,11 @@ hho_status hho_sdirk_get_traces(hho_sdirk *ctx, double *out);
 /* Energy of the current state (Sec. 5.1, cell unknowns only), float64. */
 hho_status hho_sdirk_energy(hho_sdirk *ctx, double *E);
 
-/* Footprint of the plan on the device: sizes[0..5] = cell unknowns, face unknowns, nonzeros of the
- * face matrix, nonzeros of the face-block preconditioner, float64 values of the per-cell matrices
- * ([A_T^{-1}; V_T] and W_T over all cells), face-slot unknowns (sum over cells of the face
- * unknowns each cell couples to). */
+/* Footprint of the plan on the device: sizes[0..6] = cell unknowns, face unknowns, nonzeros of the
+ * face matrix (float64 values), nonzeros of the face-block preconditioner (float32 values),
+ * float64 values of the per-cell matrices ([A_T^{-1}; V_T] and W_T over all cells), face-slot
+ * unknowns (sum over cells of the face unknowns each cell couples to), column indices stored for
+ * the face matrix (rows with the same column list share one). */
 hho_status hho_sdirk_footprint(const hho_sdirk *ctx, int64_t *sizes);
 
 /* Counters since setup: face solves, BiCGStab iterations, largest final relative residual. */

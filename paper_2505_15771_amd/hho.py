@@ -543,9 +543,9 @@ class SdirkEngine:
 
     def footprint(self):
         """dict of the device plan sizes (hho_sdirk_footprint)."""
-        sz = np.zeros(6, np.int64)
+        sz = np.zeros(7, np.int64)
         self._call(self.lib.hho_sdirk_footprint, _ptr(sz))
-        keys = ("n_dof", "n_face_dof", "nnz", "precond_nnz", "cell_matrix_values", "n_slot")
+        keys = ("n_dof", "n_face_dof", "nnz", "precond_nnz", "cell_matrix_values", "n_slot", "shared_cols")
         return dict(zip(keys, (int(v) for v in sz)))
 
     def stats(self):

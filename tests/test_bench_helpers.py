@@ -81,13 +81,16 @@ def test_paper_bilayer_workload():
 
 def test_sdirk_bytes_per_step_counts():
     """The SDIRK step's byte model on made-up sizes: matrices once per stage, 8 + i cell-vector
-    words for stage i, per iteration two products with S and two with the preconditioner."""
+    words for stage i, per iteration two products with S (8-byte values, shared column lists) and
+    two with the float32 preconditioner."""
     import bench
-    fp = dict(n_dof=100, n_face_dof=40, nnz=400, precond_nnz=160, cell_matrix_values=1000, n_slot=80)
+    fp = dict(n_dof=100, n_face_dof=40, nnz=400, precond_nnz=160, cell_matrix_values=1000, n_slot=80,
+              shared_cols=120)
     s, it = 3, 10
     stage = sum(8.0 * 1000 + 8.0 * (8 + i) * 100 + 20 * 80 + 8.0 * 40 + 8.0 * (12 + i) * 40 for i in range(s))
-    spmv = lambda nnz: 12.0 * nnz + 4.0 * 41 + 16.0 * 40
-    per_it = 2 * spmv(400) + 2 * spmv(160) + 8.0 * 22 * 40
+    smat = 8.0 * 400 + 4.0 * 120 + 24.0 * 40
+    pmat = 4.0 * 160 + 24.0 * 40
+    per_it = 2 * smat + 2 * pmat + 8.0 * 22 * 40
     assert bench.sdirk_bytes_per_step(fp, s, it) == stage + it * per_it + 8.0 * (s + 4) * 100
 
 
