@@ -7,6 +7,8 @@
 #include <limits>
 #include <cmath>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -903,123 +905,143 @@ hho_status run_steps(hho_ctx *ctx, double t0, double dt, int n_steps, std::vecto
 
 }  // namespace
 
+// Runs one C ABI call; a C++ exception (a failed host allocation, above all) becomes a status
+// code and a message instead of crossing the ABI.
+template <typename F>
+hho_status guarded(std::string *err, F &&body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        if (err) *err = "host memory allocation failed";
+        return HHO_ERR_OOM;
+    } catch (const std::exception &e) {
+        if (err) *err = std::string("internal error: ") + e.what();
+        return HHO_ERR_DEVICE;
+    } catch (...) {
+        if (err) *err = "internal error";
+        return HHO_ERR_DEVICE;
+    }
+}
+
 extern "C" {
 
 const char *hho_last_error(const hho_ctx *ctx) { return ctx ? ctx->err.c_str() : g_setup_error.c_str(); }
 
 hho_status hho_setup(const hho_mesh *mesh, const hho_params *prm, hho_ctx **out) {
-    g_setup_error.clear();
-    if (!out) return HHO_ERR_ARG;
-    *out = nullptr;
-    if (!mesh || !prm) {
-        g_setup_error = "null mesh or params";
-        return HHO_ERR_ARG;
-    }
-    if (prm->dtype != 0 && prm->dtype != 1) {
-        g_setup_error = "dtype must be 0 (float64) or 1 (float32)";
-        return HHO_ERR_ARG;
-    }
-    std::vector<StageCoef> co;
-    if (!erk_coefficients(prm->rk_stages, co)) {
-        g_setup_error = "rk_stages must be 2, 3 or 4";
-        return HHO_ERR_ARG;
-    }
-    hho_ctx *ctx = new hho_ctx();
-    ctx->dtype = prm->dtype;
-    ctx->stages = prm->rk_stages;
-    ctx->record_energy = prm->record_energy ? 1 : 0;
-    ctx->device = prm->device;
-    ctx->stream = (hipStream_t)prm->stream;
-    ctx->rsize = prm->dtype == 0 ? 8 : 4;
-    int code = 0;
-    std::string msg = build_plan(mesh->n_vertices, mesh->xy, mesh->n_cells, mesh->cell_ptr, mesh->cell_vtx,
-                                 mesh->medium, mesh->rho, mesh->a, mesh->b, prm->k, prm->eta_f, prm->eta_s,
-                                 prm->stab_speed, prm->n_shots, ctx->plan, &code);
-    if (code != 0) {
-        g_setup_error = msg;
-        delete ctx;
-        return (hho_status)code;
-    }
-    auto fail = [&](hho_status s) {
-        g_setup_error = ctx->err;
-        hho_destroy(ctx);
-        return s;
-    };
-    hho_status s = set_device(ctx);
-    if (s != HHO_OK) return fail(s);
-    Plan &P = ctx->plan;
-    ctx->LT = (long long)P.n_ic * P.S;
-    ctx->rows = 5 * P.N;
-    ctx->trows = trace_rows(P);
-    const size_t sbytes = (size_t)ctx->rows * ctx->LT * ctx->rsize;
-    const size_t tbytes = (size_t)ctx->trows * ctx->LT * ctx->rsize;
-    const size_t lbytes = (size_t)P.max_nf * P.n_ic * 4;
-    const size_t cbytes = (size_t)P.max_nf * P.n_ic * ctx->rsize;
-    const size_t mbytes = (size_t)kNumMat * P.n_ic * ctx->rsize;
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t total = 4 * al(sbytes) + 3 * al(tbytes) + al(lbytes) + al(cbytes) + al(mbytes);
-    // the kernels address the arena through one buffer resource with 32-bit byte offsets
-    if (total >= (1ull << 32)) {
-        ctx->err = "cells x shots too large for one context (arena of " + std::to_string(total) +
-                   " bytes exceeds 4 GiB)";
-        return fail(HHO_ERR_ARG);
-    }
-    if ((s = dalloc(ctx, &ctx->arena, total))) return fail(s);
-    ctx->arena_bytes = total;
-    {
-        char *p = (char *)ctx->arena;
-        auto take = [&](size_t b) {
-            void *q = p;
-            p += al(b);
-            return q;
+    return guarded(&g_setup_error, [&]() -> hho_status {
+        g_setup_error.clear();
+        if (!out) return HHO_ERR_ARG;
+        *out = nullptr;
+        if (!mesh || !prm) {
+            g_setup_error = "null mesh or params";
+            return HHO_ERR_ARG;
+        }
+        if (prm->dtype != 0 && prm->dtype != 1) {
+            g_setup_error = "dtype must be 0 (float64) or 1 (float32)";
+            return HHO_ERR_ARG;
+        }
+        std::vector<StageCoef> co;
+        if (!erk_coefficients(prm->rk_stages, co)) {
+            g_setup_error = "rk_stages must be 2, 3 or 4";
+            return HHO_ERR_ARG;
+        }
+        hho_ctx *ctx = new hho_ctx();
+        ctx->dtype = prm->dtype;
+        ctx->stages = prm->rk_stages;
+        ctx->record_energy = prm->record_energy ? 1 : 0;
+        ctx->device = prm->device;
+        ctx->stream = (hipStream_t)prm->stream;
+        ctx->rsize = prm->dtype == 0 ? 8 : 4;
+        int code = 0;
+        std::string msg = build_plan(mesh->n_vertices, mesh->xy, mesh->n_cells, mesh->cell_ptr, mesh->cell_vtx,
+                                     mesh->medium, mesh->rho, mesh->a, mesh->b, prm->k, prm->eta_f, prm->eta_s,
+                                     prm->stab_speed, prm->n_shots, ctx->plan, &code);
+        if (code != 0) {
+            g_setup_error = msg;
+            delete ctx;
+            return (hho_status)code;
+        }
+        auto fail = [&](hho_status s) {
+            g_setup_error = ctx->err;
+            hho_destroy(ctx);
+            return s;
         };
-        ctx->U = take(sbytes);
-        ctx->Y[0] = take(sbytes);
-        ctx->Y[1] = take(sbytes);
-        ctx->acc = take(sbytes);
-        for (int i = 0; i < 3; ++i) ctx->T[i] = take(tbytes);
-        ctx->link = (int32_t *)take(lbytes);
-        ctx->c0 = take(cbytes);
-        ctx->mat = take(mbytes);
-    }
-    std::vector<int64_t> map(P.n_ext);
-    for (int c = 0; c < P.n_cells; ++c) {
-        const int nr = (P.medium[c] == kFluid ? 3 : 5) * P.N;
-        for (int r = 0; r < nr; ++r)
-            map[P.ext_off[c] + r] = (int64_t)r * ctx->LT + (int64_t)P.ic_of_cell[c] * P.S;
-    }
-    if ((s = copy_in(ctx, ctx->link, P.link)) || (s = copy_in_real(ctx, ctx->c0, P.c0)) ||
-        (s = copy_in_real(ctx, ctx->mat, P.mat)) || (s = upload_real(ctx, &ctx->tab, P.tables)) ||
-        (s = upload(ctx, &ctx->emat, P.emat)) || (s = upload(ctx, &ctx->map, map)) ||
-        (s = dalloc(ctx, (void **)&ctx->staging, std::max<size_t>(1, P.n_ext) * 4 * sizeof(double))) ||
-        (s = dalloc(ctx, (void **)&ctx->e_now, (size_t)P.S * sizeof(double))) ||
-        (s = dalloc(ctx, (void **)&ctx->clock, 2 * sizeof(Clock))))
-        return fail(s);
-    for (const Plan::Launch &L : P.launches) {
-        std::vector<GroupDev> gd;
-        for (size_t g = 0; g < P.groups.size(); ++g) {
-            const Group &G = P.groups[g];
-            gd.push_back({G.medium, G.nF, G.tab_off, G.ic_begin, G.ncells, L.blk_begin[g]});
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return fail(s);
+        Plan &P = ctx->plan;
+        ctx->LT = (long long)P.n_ic * P.S;
+        ctx->rows = 5 * P.N;
+        ctx->trows = trace_rows(P);
+        const size_t sbytes = (size_t)ctx->rows * ctx->LT * ctx->rsize;
+        const size_t tbytes = (size_t)ctx->trows * ctx->LT * ctx->rsize;
+        const size_t lbytes = (size_t)P.max_nf * P.n_ic * 4;
+        const size_t cbytes = (size_t)P.max_nf * P.n_ic * ctx->rsize;
+        const size_t mbytes = (size_t)kNumMat * P.n_ic * ctx->rsize;
+        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        const size_t total = 4 * al(sbytes) + 3 * al(tbytes) + al(lbytes) + al(cbytes) + al(mbytes);
+        // the kernels address the arena through one buffer resource with 32-bit byte offsets
+        if (total >= (1ull << 32)) {
+            ctx->err = "cells x shots too large for one context (arena of " + std::to_string(total) +
+                       " bytes exceeds 4 GiB)";
+            return fail(HHO_ERR_ARG);
         }
-        hho_ctx::LaunchDev d;
-        d.n_blocks = (int)L.blk_group.size();
-        d.cpb = L.cpb;
-        d.lanes = L.lanes;
-        if ((s = upload(ctx, &d.groups, gd)) || (s = upload(ctx, &d.blk_group, L.blk_group))) return fail(s);
-        ctx->launch.push_back(d);
-        ctx->max_blocks = std::max(ctx->max_blocks, d.n_blocks);
-    }
-    if ((s = dalloc(ctx, (void **)&ctx->e_part, (size_t)ctx->max_blocks * P.S * sizeof(double)))) return fail(s);
-    ctx->cfl_dt = cfl_time_step(P, prm->rk_stages);
-    {
-        hipError_t e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
-        if (e != hipSuccess) {
-            ctx->err = std::string("hipStreamCreate: ") + hipGetErrorString(e);
-            return fail(HHO_ERR_DEVICE);
+        if ((s = dalloc(ctx, &ctx->arena, total))) return fail(s);
+        ctx->arena_bytes = total;
+        {
+            char *p = (char *)ctx->arena;
+            auto take = [&](size_t b) {
+                void *q = p;
+                p += al(b);
+                return q;
+            };
+            ctx->U = take(sbytes);
+            ctx->Y[0] = take(sbytes);
+            ctx->Y[1] = take(sbytes);
+            ctx->acc = take(sbytes);
+            for (int i = 0; i < 3; ++i) ctx->T[i] = take(tbytes);
+            ctx->link = (int32_t *)take(lbytes);
+            ctx->c0 = take(cbytes);
+            ctx->mat = take(mbytes);
         }
-    }
-    *out = ctx;
-    return HHO_OK;
+        std::vector<int64_t> map(P.n_ext);
+        for (int c = 0; c < P.n_cells; ++c) {
+            const int nr = (P.medium[c] == kFluid ? 3 : 5) * P.N;
+            for (int r = 0; r < nr; ++r)
+                map[P.ext_off[c] + r] = (int64_t)r * ctx->LT + (int64_t)P.ic_of_cell[c] * P.S;
+        }
+        if ((s = copy_in(ctx, ctx->link, P.link)) || (s = copy_in_real(ctx, ctx->c0, P.c0)) ||
+            (s = copy_in_real(ctx, ctx->mat, P.mat)) || (s = upload_real(ctx, &ctx->tab, P.tables)) ||
+            (s = upload(ctx, &ctx->emat, P.emat)) || (s = upload(ctx, &ctx->map, map)) ||
+            (s = dalloc(ctx, (void **)&ctx->staging, std::max<size_t>(1, P.n_ext) * 4 * sizeof(double))) ||
+            (s = dalloc(ctx, (void **)&ctx->e_now, (size_t)P.S * sizeof(double))) ||
+            (s = dalloc(ctx, (void **)&ctx->clock, 2 * sizeof(Clock))))
+            return fail(s);
+        for (const Plan::Launch &L : P.launches) {
+            std::vector<GroupDev> gd;
+            for (size_t g = 0; g < P.groups.size(); ++g) {
+                const Group &G = P.groups[g];
+                gd.push_back({G.medium, G.nF, G.tab_off, G.ic_begin, G.ncells, L.blk_begin[g]});
+            }
+            hho_ctx::LaunchDev d;
+            d.n_blocks = (int)L.blk_group.size();
+            d.cpb = L.cpb;
+            d.lanes = L.lanes;
+            if ((s = upload(ctx, &d.groups, gd)) || (s = upload(ctx, &d.blk_group, L.blk_group))) return fail(s);
+            ctx->launch.push_back(d);
+            ctx->max_blocks = std::max(ctx->max_blocks, d.n_blocks);
+        }
+        if ((s = dalloc(ctx, (void **)&ctx->e_part, (size_t)ctx->max_blocks * P.S * sizeof(double)))) return fail(s);
+        ctx->cfl_dt = cfl_time_step(P, prm->rk_stages);
+        {
+            hipError_t e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                ctx->err = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+                return fail(HHO_ERR_DEVICE);
+            }
+        }
+        *out = ctx;
+        return HHO_OK;
+    });
 }
 
 void hho_destroy(hho_ctx *ctx) {
@@ -1041,465 +1063,497 @@ void hho_destroy(hho_ctx *ctx) {
 }
 
 hho_status hho_sizes(const hho_ctx *ctx, int64_t *n_dof, int32_t *n_cells, int32_t *n_faces) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (n_dof) *n_dof = ctx->plan.n_ext;
-    if (n_cells) *n_cells = ctx->plan.n_cells;
-    if (n_faces) *n_faces = ctx->plan.n_faces;
-    return HHO_OK;
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (n_dof) *n_dof = ctx->plan.n_ext;
+        if (n_cells) *n_cells = ctx->plan.n_cells;
+        if (n_faces) *n_faces = ctx->plan.n_faces;
+        return HHO_OK;
+    });
 }
 
 hho_status hho_set_state(hho_ctx *ctx, int32_t shot, const double *U, int32_t on_device) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (!U || shot < 0 || shot >= ctx->plan.S) {
-        ctx->err = "set_state: null pointer or shot out of range";
-        return HHO_ERR_ARG;
-    }
-    hho_status s = set_device(ctx);
-    if (s != HHO_OK) return s;
-    const long long n = ctx->plan.n_ext;
-    const double *src = U;
-    if (!on_device) {
-        HCK(hipMemcpyAsync(ctx->staging, U, n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-        src = ctx->staging;
-    }
-    if (ctx->dtype == 0) HCK(launch_scatter<double>(src, ctx->map, n, shot, (double *)ctx->U, ctx->stream));
-    else HCK(launch_scatter<float>(src, ctx->map, n, shot, (float *)ctx->U, ctx->stream));
-    HCK(hipStreamSynchronize(ctx->stream));
-    ctx->traces_valid = false;
-    return HHO_OK;
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (!U || shot < 0 || shot >= ctx->plan.S) {
+            ctx->err = "set_state: null pointer or shot out of range";
+            return HHO_ERR_ARG;
+        }
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return s;
+        const long long n = ctx->plan.n_ext;
+        const double *src = U;
+        if (!on_device) {
+            HCK(hipMemcpyAsync(ctx->staging, U, n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+            src = ctx->staging;
+        }
+        if (ctx->dtype == 0) HCK(launch_scatter<double>(src, ctx->map, n, shot, (double *)ctx->U, ctx->stream));
+        else HCK(launch_scatter<float>(src, ctx->map, n, shot, (float *)ctx->U, ctx->stream));
+        HCK(hipStreamSynchronize(ctx->stream));
+        ctx->traces_valid = false;
+        return HHO_OK;
+    });
 }
 
 hho_status hho_get_state(hho_ctx *ctx, int32_t shot, double *U, int32_t on_device) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (!U || shot < 0 || shot >= ctx->plan.S) {
-        ctx->err = "get_state: null pointer or shot out of range";
-        return HHO_ERR_ARG;
-    }
-    hho_status s = set_device(ctx);
-    if (s != HHO_OK) return s;
-    const long long n = ctx->plan.n_ext;
-    double *dst = on_device ? U : ctx->staging;
-    if (ctx->dtype == 0) HCK(launch_gather<double>((const double *)ctx->U, ctx->map, n, shot, dst, ctx->stream));
-    else HCK(launch_gather<float>((const float *)ctx->U, ctx->map, n, shot, dst, ctx->stream));
-    if (!on_device) HCK(hipMemcpyAsync(U, ctx->staging, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HCK(hipStreamSynchronize(ctx->stream));
-    return HHO_OK;
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (!U || shot < 0 || shot >= ctx->plan.S) {
+            ctx->err = "get_state: null pointer or shot out of range";
+            return HHO_ERR_ARG;
+        }
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return s;
+        const long long n = ctx->plan.n_ext;
+        double *dst = on_device ? U : ctx->staging;
+        if (ctx->dtype == 0) HCK(launch_gather<double>((const double *)ctx->U, ctx->map, n, shot, dst, ctx->stream));
+        else HCK(launch_gather<float>((const float *)ctx->U, ctx->map, n, shot, dst, ctx->stream));
+        if (!on_device) HCK(hipMemcpyAsync(U, ctx->staging, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HCK(hipStreamSynchronize(ctx->stream));
+        return HHO_OK;
+    });
 }
 
 hho_status hho_set_sources(hho_ctx *ctx, int32_t shot, int32_t n, const double *xy, const double *dir,
                            const double *f0, const double *t0, const double *amp) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (shot < 0 || shot >= ctx->plan.S || n < 0 || (n > 0 && (!xy || !dir || !f0 || !t0 || !amp))) {
-        ctx->err = "set_sources: bad arguments";
-        return HHO_ERR_ARG;
-    }
-    hho_status s = set_device(ctx);
-    if (s != HHO_OK) return s;
-    std::vector<SrcDev> keep;
-    for (const SrcDev &e : ctx->h_src)
-        if (e.shot != shot) keep.push_back(e);
-    for (int i = 0; i < n; ++i) {
-        const int c = locate_cell(ctx->plan, xy[2 * i], xy[2 * i + 1]);
-        if (c < 0) {
-            ctx->err = "set_sources: source " + std::to_string(i) + " lies outside the mesh";
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (shot < 0 || shot >= ctx->plan.S || n < 0 || (n > 0 && (!xy || !dir || !f0 || !t0 || !amp))) {
+            ctx->err = "set_sources: bad arguments";
             return HHO_ERR_ARG;
         }
-        SrcDev e;
-        std::memset(&e, 0, sizeof(e));
-        e.ic = ctx->plan.ic_of_cell[c];
-        e.shot = shot;
-        e.dirx = dir[2 * i];
-        e.diry = dir[2 * i + 1];
-        e.f0 = f0[i];
-        e.t0 = t0[i];
-        e.amp = amp[i];
-        eval_basis(ctx->plan, c, xy[2 * i], xy[2 * i + 1], e.phi);
-        keep.push_back(e);
-    }
-    ctx->h_src = keep;
-    ctx->version++;
-    return rebuild_sources(ctx);
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return s;
+        std::vector<SrcDev> keep;
+        for (const SrcDev &e : ctx->h_src)
+            if (e.shot != shot) keep.push_back(e);
+        for (int i = 0; i < n; ++i) {
+            const int c = locate_cell(ctx->plan, xy[2 * i], xy[2 * i + 1]);
+            if (c < 0) {
+                ctx->err = "set_sources: source " + std::to_string(i) + " lies outside the mesh";
+                return HHO_ERR_ARG;
+            }
+            SrcDev e;
+            std::memset(&e, 0, sizeof(e));
+            e.ic = ctx->plan.ic_of_cell[c];
+            e.shot = shot;
+            e.dirx = dir[2 * i];
+            e.diry = dir[2 * i + 1];
+            e.f0 = f0[i];
+            e.t0 = t0[i];
+            e.amp = amp[i];
+            eval_basis(ctx->plan, c, xy[2 * i], xy[2 * i + 1], e.phi);
+            keep.push_back(e);
+        }
+        ctx->h_src = keep;
+        ctx->version++;
+        return rebuild_sources(ctx);
+    });
 }
 
 hho_status hho_set_loads(hho_ctx *ctx, int32_t n_terms, const double *g, const double *omega,
                          const double *phase) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (n_terms < 0 || n_terms > 4 || (n_terms > 0 && (!g || !omega || !phase))) {
-        ctx->err = "set_loads: 0..4 terms with non-null arrays";
-        return HHO_ERR_ARG;
-    }
-    hho_status s = set_device(ctx);
-    if (s != HHO_OK) return s;
-    const Plan &P = ctx->plan;
-    ctx->nterms = 0;
-    ctx->version++;
-    if (n_terms == 0) return HHO_OK;
-    const int rows = 5 * P.N;
-    std::vector<double> h((size_t)n_terms * rows * P.n_ic, 0.0);
-    for (int m = 0; m < n_terms; ++m)
-        for (int c = 0; c < P.n_cells; ++c) {
-            const int nr = (P.medium[c] == kFluid ? 3 : 5) * P.N, ic = P.ic_of_cell[c];
-            for (int r = 0; r < nr; ++r)
-                h[((size_t)m * rows + r) * P.n_ic + ic] = g[(size_t)m * P.n_ext + P.ext_off[c] + r];
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (n_terms < 0 || n_terms > 4 || (n_terms > 0 && (!g || !omega || !phase))) {
+            ctx->err = "set_loads: 0..4 terms with non-null arrays";
+            return HHO_ERR_ARG;
         }
-    if (ctx->gload) {
-        (void)hipFree(ctx->gload);
-        ctx->allocs.erase(std::find(ctx->allocs.begin(), ctx->allocs.end(), ctx->gload));
-        ctx->gload = nullptr;
-    }
-    if ((s = upload_real(ctx, &ctx->gload, h))) return s;
-    for (int m = 0; m < n_terms; ++m) {
-        ctx->omega[m] = omega[m];
-        ctx->phase[m] = phase[m];
-    }
-    ctx->nterms = n_terms;
-    return HHO_OK;
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return s;
+        const Plan &P = ctx->plan;
+        ctx->nterms = 0;
+        ctx->version++;
+        if (n_terms == 0) return HHO_OK;
+        const int rows = 5 * P.N;
+        std::vector<double> h((size_t)n_terms * rows * P.n_ic, 0.0);
+        for (int m = 0; m < n_terms; ++m)
+            for (int c = 0; c < P.n_cells; ++c) {
+                const int nr = (P.medium[c] == kFluid ? 3 : 5) * P.N, ic = P.ic_of_cell[c];
+                for (int r = 0; r < nr; ++r)
+                    h[((size_t)m * rows + r) * P.n_ic + ic] = g[(size_t)m * P.n_ext + P.ext_off[c] + r];
+            }
+        if (ctx->gload) {
+            (void)hipFree(ctx->gload);
+            ctx->allocs.erase(std::find(ctx->allocs.begin(), ctx->allocs.end(), ctx->gload));
+            ctx->gload = nullptr;
+        }
+        if ((s = upload_real(ctx, &ctx->gload, h))) return s;
+        for (int m = 0; m < n_terms; ++m) {
+            ctx->omega[m] = omega[m];
+            ctx->phase[m] = phase[m];
+        }
+        ctx->nterms = n_terms;
+        return HHO_OK;
+    });
 }
 
 hho_status hho_receivers(hho_ctx *ctx, int32_t n, const double *xy, const int32_t *field) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (n < 0 || (n > 0 && (!xy || !field))) {
-        ctx->err = "receivers: bad arguments";
-        return HHO_ERR_ARG;
-    }
-    hho_status s = set_device(ctx);
-    if (s != HHO_OK) return s;
-    const Plan &P = ctx->plan;
-    std::vector<RecDev> v;
-    for (int i = 0; i < n; ++i) {
-        const int c = locate_cell(P, xy[2 * i], xy[2 * i + 1]);
-        if (c < 0) {
-            ctx->err = "receivers: receiver " + std::to_string(i) + " lies outside the mesh";
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (n < 0 || (n > 0 && (!xy || !field))) {
+            ctx->err = "receivers: bad arguments";
             return HHO_ERR_ARG;
         }
-        if (field[i] != (int)P.medium[c]) {
-            ctx->err = "receivers: receiver " + std::to_string(i) + " records " +
-                       (field[i] == 0 ? "p but lies in the solid" : "v but lies in the fluid");
-            return HHO_ERR_ARG;
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return s;
+        const Plan &P = ctx->plan;
+        std::vector<RecDev> v;
+        for (int i = 0; i < n; ++i) {
+            const int c = locate_cell(P, xy[2 * i], xy[2 * i + 1]);
+            if (c < 0) {
+                ctx->err = "receivers: receiver " + std::to_string(i) + " lies outside the mesh";
+                return HHO_ERR_ARG;
+            }
+            if (field[i] != (int)P.medium[c]) {
+                ctx->err = "receivers: receiver " + std::to_string(i) + " records " +
+                           (field[i] == 0 ? "p but lies in the solid" : "v but lies in the fluid");
+                return HHO_ERR_ARG;
+            }
+            RecDev r;
+            std::memset(&r, 0, sizeof(r));
+            r.ic = P.ic_of_cell[c];
+            r.field = field[i];
+            r.r = i;
+            eval_basis(P, c, xy[2 * i], xy[2 * i + 1], r.phi);
+            v.push_back(r);
         }
-        RecDev r;
-        std::memset(&r, 0, sizeof(r));
-        r.ic = P.ic_of_cell[c];
-        r.field = field[i];
-        r.r = i;
-        eval_basis(P, c, xy[2 * i], xy[2 * i + 1], r.phi);
-        v.push_back(r);
-    }
-    std::stable_sort(v.begin(), v.end(), [](const RecDev &x, const RecDev &y) { return x.ic < y.ic; });
-    std::vector<int32_t> first(P.n_ic, -1);
-    for (size_t e = 0; e < v.size(); ++e) {
-        v[e].next = (e + 1 < v.size() && v[e + 1].ic == v[e].ic) ? (int)e + 1 : -1;
-        if (e == 0 || v[e - 1].ic != v[e].ic) first[v[e].ic] = (int)e;
-    }
-    if (!ctx->rec_first && (s = dalloc(ctx, (void **)&ctx->rec_first, first.size() * sizeof(int32_t)))) return s;
-    if ((size_t)n > 0) {
-        RecDev *d = nullptr;
-        if ((s = dalloc(ctx, (void **)&d, v.size() * sizeof(RecDev)))) return s;
-        HCK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(RecDev), hipMemcpyHostToDevice, ctx->stream));
-        ctx->rec = d;
-    }
-    HCK(hipMemcpyAsync(ctx->rec_first, first.data(), first.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                       ctx->stream));
-    HCK(hipStreamSynchronize(ctx->stream));
-    ctx->nrec = n;
-    ctx->version++;
-    return HHO_OK;
+        std::stable_sort(v.begin(), v.end(), [](const RecDev &x, const RecDev &y) { return x.ic < y.ic; });
+        std::vector<int32_t> first(P.n_ic, -1);
+        for (size_t e = 0; e < v.size(); ++e) {
+            v[e].next = (e + 1 < v.size() && v[e + 1].ic == v[e].ic) ? (int)e + 1 : -1;
+            if (e == 0 || v[e - 1].ic != v[e].ic) first[v[e].ic] = (int)e;
+        }
+        if (!ctx->rec_first && (s = dalloc(ctx, (void **)&ctx->rec_first, first.size() * sizeof(int32_t)))) return s;
+        if ((size_t)n > 0) {
+            RecDev *d = nullptr;
+            if ((s = dalloc(ctx, (void **)&d, v.size() * sizeof(RecDev)))) return s;
+            HCK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(RecDev), hipMemcpyHostToDevice, ctx->stream));
+            ctx->rec = d;
+        }
+        HCK(hipMemcpyAsync(ctx->rec_first, first.data(), first.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           ctx->stream));
+        HCK(hipStreamSynchronize(ctx->stream));
+        ctx->nrec = n;
+        ctx->version++;
+        return HHO_OK;
+    });
 }
 
 hho_status hho_erk_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (n_steps < 0 || !(dt > 0.0) || !std::isfinite(t0)) {
-        ctx->err = "erk_step: n_steps >= 0 and dt > 0 required";
-        return HHO_ERR_ARG;
-    }
-    hho_status s = set_device(ctx);
-    if (s != HHO_OK) return s;
-    std::vector<double> E0;
-    if ((s = run_steps(ctx, t0, dt, n_steps, E0))) return s;
-    return end_steps(ctx, n_steps, E0);
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (n_steps < 0 || !(dt > 0.0) || !std::isfinite(t0)) {
+            ctx->err = "erk_step: n_steps >= 0 and dt > 0 required";
+            return HHO_ERR_ARG;
+        }
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return s;
+        std::vector<double> E0;
+        if ((s = run_steps(ctx, t0, dt, n_steps, E0))) return s;
+        return end_steps(ctx, n_steps, E0);
+    });
 }
 
 hho_status hho_set_dt_scale(hho_ctx *ctx, const double *scale) {
-    if (!ctx) return HHO_ERR_ARG;
-    const int S = ctx->plan.S;
-    if (!scale) {
-        if (ctx->dt_scaled) ctx->version++;
-        ctx->dt_scaled = false;
-        return HHO_OK;
-    }
-    for (int i = 0; i < S; ++i)
-        if (!(scale[i] > 0.0) || !std::isfinite(scale[i])) {
-            ctx->err = "set_dt_scale: multipliers must be finite and > 0";
-            return HHO_ERR_ARG;
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        const int S = ctx->plan.S;
+        if (!scale) {
+            if (ctx->dt_scaled) ctx->version++;
+            ctx->dt_scaled = false;
+            return HHO_OK;
         }
-    hho_status s = set_device(ctx);
-    if (s != HHO_OK) return s;
-    if (!ctx->dt_scale && (s = dalloc(ctx, (void **)&ctx->dt_scale, (size_t)S * sizeof(double)))) return s;
-    HCK(hipMemcpyAsync(ctx->dt_scale, scale, (size_t)S * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    HCK(hipStreamSynchronize(ctx->stream));
-    if (!ctx->dt_scaled) ctx->version++;
-    ctx->dt_scaled = true;
-    return HHO_OK;
+        for (int i = 0; i < S; ++i)
+            if (!(scale[i] > 0.0) || !std::isfinite(scale[i])) {
+                ctx->err = "set_dt_scale: multipliers must be finite and > 0";
+                return HHO_ERR_ARG;
+            }
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return s;
+        if (!ctx->dt_scale && (s = dalloc(ctx, (void **)&ctx->dt_scale, (size_t)S * sizeof(double)))) return s;
+        HCK(hipMemcpyAsync(ctx->dt_scale, scale, (size_t)S * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        HCK(hipStreamSynchronize(ctx->stream));
+        if (!ctx->dt_scaled) ctx->version++;
+        ctx->dt_scaled = true;
+        return HHO_OK;
+    });
 }
 
 hho_status hho_cfl_search(hho_ctx *ctx, double t_final, int32_t n_start, double delta, double eps,
                           int32_t max_rounds, int32_t *n_stable, int32_t *n_unstable, int32_t *tried,
                           double *growth, int32_t cap, int32_t *n_tried) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (!(t_final > 0.0) || !std::isfinite(t_final) || n_start < 1 || !(delta > 0.0) || !(delta < 1.0) ||
-        !(eps > 0.0) || max_rounds < 1 || !n_stable || !n_unstable || cap < 0 || (cap > 0 && (!tried || !growth))) {
-        ctx->err = "cfl_search: t_final > 0, n_start >= 1, 0 < delta < 1, eps > 0, max_rounds >= 1 required";
-        return HHO_ERR_ARG;
-    }
-    hho_status s = set_device(ctx);
-    if (s != HHO_OK) return s;
-    const int S = ctx->plan.S;
-    const size_t sbytes = (size_t)ctx->rows * ctx->LT * ctx->rsize;
-    if (!ctx->cfl_save && (s = dalloc(ctx, &ctx->cfl_save, sbytes))) return s;
-    HCK(hipMemcpyAsync(ctx->cfl_save, ctx->U, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
-    const int keep_energy = ctx->record_energy;
-    if (!keep_energy) {
-        ctx->record_energy = 1;
-        ctx->version++;
-    }
-    *n_stable = 0;
-    *n_unstable = 0;
-    int count = 0;
-    // the rounds (a device failure returns from here; the restore below runs in every case)
-    auto rounds = [&]() -> hho_status {
-        long long next = n_start;
-        std::vector<double> scale(S), E;
-        hho_status st = HHO_OK;
-        for (int round = 0; round < max_rounds && *n_unstable == 0 && next >= 1; ++round) {
-            // this round's candidates: N_j, N_{j+1} = N_j - max(1, floor(delta N_j)), ...
-            std::vector<int> N;
-            for (int i = 0; i < S && next >= 1; ++i) {
-                N.push_back((int)next);
-                next -= std::max<long long>(1, (long long)std::floor(delta * (double)next));
-            }
-            const int nmax = N[0];
-            for (int i = 0; i < S; ++i) scale[i] = i < (int)N.size() ? (double)nmax / N[i] : 1.0;
-            if ((st = hho_set_dt_scale(ctx, scale.data()))) return st;
-            HCK(hipMemcpyAsync(ctx->U, ctx->cfl_save, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
-            ctx->traces_valid = false;
-            std::vector<double> E0;
-            if ((st = run_steps(ctx, 0.0, t_final / nmax, nmax, E0))) return st;
-            E.resize((size_t)nmax * S);
-            HCK(hipMemcpyAsync(E.data(), ctx->e_hist, E.size() * sizeof(double), hipMemcpyDeviceToHost,
-                               ctx->stream));
-            HCK(hipStreamSynchronize(ctx->stream));
-            // Algorithm algo_CFL: relative energy increase over the initial and the previous energy
-            for (size_t i = 0; i < N.size(); ++i) {
-                double g = 0.0, prev = E0[i];
-                bool bad = !(E0[i] > 0.0) || !std::isfinite(E0[i]);
-                for (int n = 0; n < N[i] && !bad; ++n) {
-                    const double e = E[(size_t)n * S + i];
-                    if (!std::isfinite(e)) {
-                        bad = true;
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (!(t_final > 0.0) || !std::isfinite(t_final) || n_start < 1 || !(delta > 0.0) || !(delta < 1.0) ||
+            !(eps > 0.0) || max_rounds < 1 || !n_stable || !n_unstable || cap < 0 || (cap > 0 && (!tried || !growth))) {
+            ctx->err = "cfl_search: t_final > 0, n_start >= 1, 0 < delta < 1, eps > 0, max_rounds >= 1 required";
+            return HHO_ERR_ARG;
+        }
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return s;
+        const int S = ctx->plan.S;
+        const size_t sbytes = (size_t)ctx->rows * ctx->LT * ctx->rsize;
+        if (!ctx->cfl_save && (s = dalloc(ctx, &ctx->cfl_save, sbytes))) return s;
+        HCK(hipMemcpyAsync(ctx->cfl_save, ctx->U, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+        const int keep_energy = ctx->record_energy;
+        if (!keep_energy) {
+            ctx->record_energy = 1;
+            ctx->version++;
+        }
+        *n_stable = 0;
+        *n_unstable = 0;
+        int count = 0;
+        // the rounds (a device failure returns from here; the restore below runs in every case)
+        auto rounds = [&]() -> hho_status {
+            long long next = n_start;
+            std::vector<double> scale(S), E;
+            hho_status st = HHO_OK;
+            for (int round = 0; round < max_rounds && *n_unstable == 0 && next >= 1; ++round) {
+                // this round's candidates: N_j, N_{j+1} = N_j - max(1, floor(delta N_j)), ...
+                std::vector<int> N;
+                for (int i = 0; i < S && next >= 1; ++i) {
+                    N.push_back((int)next);
+                    next -= std::max<long long>(1, (long long)std::floor(delta * (double)next));
+                }
+                const int nmax = N[0];
+                for (int i = 0; i < S; ++i) scale[i] = i < (int)N.size() ? (double)nmax / N[i] : 1.0;
+                if ((st = hho_set_dt_scale(ctx, scale.data()))) return st;
+                HCK(hipMemcpyAsync(ctx->U, ctx->cfl_save, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+                ctx->traces_valid = false;
+                std::vector<double> E0;
+                if ((st = run_steps(ctx, 0.0, t_final / nmax, nmax, E0))) return st;
+                E.resize((size_t)nmax * S);
+                HCK(hipMemcpyAsync(E.data(), ctx->e_hist, E.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+                HCK(hipStreamSynchronize(ctx->stream));
+                // Algorithm algo_CFL: relative energy increase over the initial and the previous energy
+                for (size_t i = 0; i < N.size(); ++i) {
+                    double g = 0.0, prev = E0[i];
+                    bool bad = !(E0[i] > 0.0) || !std::isfinite(E0[i]);
+                    for (int n = 0; n < N[i] && !bad; ++n) {
+                        const double e = E[(size_t)n * S + i];
+                        if (!std::isfinite(e)) {
+                            bad = true;
+                            break;
+                        }
+                        g = std::max(g, std::max((e - E0[i]) / E0[i], (e - prev) / prev));
+                        prev = e;
+                    }
+                    if (bad) g = std::numeric_limits<double>::infinity();
+                    if (count < cap) {
+                        tried[count] = N[i];
+                        growth[count] = g;
+                    }
+                    ++count;
+                    if (g > eps) {
+                        *n_unstable = N[i];
                         break;
                     }
-                    g = std::max(g, std::max((e - E0[i]) / E0[i], (e - prev) / prev));
-                    prev = e;
+                    *n_stable = N[i];
                 }
-                if (bad) g = std::numeric_limits<double>::infinity();
-                if (count < cap) {
-                    tried[count] = N[i];
-                    growth[count] = g;
-                }
-                ++count;
-                if (g > eps) {
-                    *n_unstable = N[i];
-                    break;
-                }
-                *n_stable = N[i];
             }
+            return st;
+        };
+        s = rounds();
+        if (n_tried) *n_tried = count;
+        const hho_status s2 = hho_set_dt_scale(ctx, nullptr);
+        if (!keep_energy) {
+            ctx->record_energy = 0;
+            ctx->version++;
         }
-        return st;
-    };
-    s = rounds();
-    if (n_tried) *n_tried = count;
-    const hho_status s2 = hho_set_dt_scale(ctx, nullptr);
-    if (!keep_energy) {
-        ctx->record_energy = 0;
-        ctx->version++;
-    }
-    HCK(hipMemcpyAsync(ctx->U, ctx->cfl_save, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
-    HCK(hipStreamSynchronize(ctx->stream));
-    ctx->traces_valid = false;
-    return s != HHO_OK ? s : s2;
+        HCK(hipMemcpyAsync(ctx->U, ctx->cfl_save, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+        HCK(hipStreamSynchronize(ctx->stream));
+        ctx->traces_valid = false;
+        return s != HHO_OK ? s : s2;
+    });
 }
 
 
 hho_status hho_adjoint_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps, int32_t ckpt_every,
                             const double *d_obs, double *J, double *grad) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (n_steps < 1 || !(dt > 0.0) || !std::isfinite(t0) || ckpt_every < 0 || !J || !grad ||
-        (ctx->nrec > 0 && !d_obs)) {
-        ctx->err = "adjoint_step: n_steps >= 1, dt > 0, ckpt_every >= 0, J, grad (and d_obs with receivers) required";
-        return HHO_ERR_ARG;
-    }
-    if (ctx->dt_scaled) {
-        ctx->err = "adjoint_step: per-shot time-step multipliers are set (hho_set_dt_scale); reset them first";
-        return HHO_ERR_ARG;
-    }
-    std::vector<StageCoef> co;
-    if (!erk_coefficients(ctx->stages, co)) return HHO_ERR_ARG;
-    for (const StageCoef &q : co)
-        if (q.cY != 0.0) {
-            ctx->err = "adjoint_step: the reverse sweep needs a subdiagonal Runge-Kutta matrix (rk_stages 2 or 4)";
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (n_steps < 1 || !(dt > 0.0) || !std::isfinite(t0) || ckpt_every < 0 || !J || !grad ||
+            (ctx->nrec > 0 && !d_obs)) {
+            ctx->err = "adjoint_step: n_steps >= 1, dt > 0, ckpt_every >= 0, J, grad (and d_obs with receivers) required";
             return HHO_ERR_ARG;
         }
-    hho_status s = set_device(ctx);
-    if (s != HHO_OK) return s;
-    const int every = ckpt_every > 0 ? std::min<int>(ckpt_every, n_steps)
-                                     : std::max(1, (int)std::ceil(std::sqrt((double)n_steps)));
-    const int n_seg = (n_steps + every - 1) / every;
-    if ((s = ensure_adjoint(ctx, every, n_seg))) return s;
-    AdjWork &w = ctx->adj;
-    const Plan &P = ctx->plan;
-    const int S = P.S;
-    const size_t sbytes = (size_t)ctx->rows * ctx->LT * ctx->rsize;
-    // forward pass with checkpoints U^{g * every}, then U^N
-    std::vector<double> E0;
-    if ((s = begin_steps(ctx, t0, dt, n_steps, E0))) return s;
-    for (int g = 0; g < n_seg; ++g) {
-        HCK(hipMemcpyAsync((char *)w.ckpt + (size_t)g * sbytes, ctx->U, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
-        const int len = std::min(every, n_steps - g * every);
+        if (ctx->dt_scaled) {
+            ctx->err = "adjoint_step: per-shot time-step multipliers are set (hho_set_dt_scale); reset them first";
+            return HHO_ERR_ARG;
+        }
+        std::vector<StageCoef> co;
+        if (!erk_coefficients(ctx->stages, co)) return HHO_ERR_ARG;
+        for (const StageCoef &q : co)
+            if (q.cY != 0.0) {
+                ctx->err = "adjoint_step: the reverse sweep needs a subdiagonal Runge-Kutta matrix (rk_stages 2 or 4)";
+                return HHO_ERR_ARG;
+            }
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return s;
+        const int every = ckpt_every > 0 ? std::min<int>(ckpt_every, n_steps)
+                                         : std::max(1, (int)std::ceil(std::sqrt((double)n_steps)));
+        const int n_seg = (n_steps + every - 1) / every;
+        if ((s = ensure_adjoint(ctx, every, n_seg))) return s;
+        AdjWork &w = ctx->adj;
+        const Plan &P = ctx->plan;
+        const int S = P.S;
+        const size_t sbytes = (size_t)ctx->rows * ctx->LT * ctx->rsize;
+        // forward pass with checkpoints U^{g * every}, then U^N
+        std::vector<double> E0;
+        if ((s = begin_steps(ctx, t0, dt, n_steps, E0))) return s;
+        for (int g = 0; g < n_seg; ++g) {
+            HCK(hipMemcpyAsync((char *)w.ckpt + (size_t)g * sbytes, ctx->U, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+            const int len = std::min(every, n_steps - g * every);
+            s = dispatch(ctx, [&](auto kc, auto *r) {
+                using R = std::remove_pointer_t<decltype(r)>;
+                return enqueue_steps<decltype(kc)::value, R>(ctx, ctx->stream, len, (R *)nullptr, (g * every) & 1);
+            });
+            if (s != HHO_OK) return s;
+        }
+        if ((s = end_steps(ctx, n_steps, E0))) return s;
+        void *uN = (char *)w.ckpt + (size_t)n_seg * sbytes;
+        HCK(hipMemcpyAsync(uN, ctx->U, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+        // misfit J = 1/2 dt sum_shots sum_n sum_r |R_r U^n - d_r^n|^2 from the recorded traces
+        double Jv = 0.0;
+        const size_t per_shot = (size_t)n_steps * ctx->nrec * 2;
+        if (ctx->nrec > 0) {
+            const size_t stride = ctx->rec_cap / (size_t)S;
+            std::vector<double> tr(stride * S);
+            HCK(hipMemcpyAsync(tr.data(), ctx->rec_out, tr.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+            HCK(hipStreamSynchronize(ctx->stream));
+            for (int sh = 0; sh < S; ++sh)
+                for (size_t e = 0; e < per_shot; ++e) {
+                    const double d = tr[sh * stride + e] - d_obs[sh * per_shot + e];
+                    Jv += d * d;
+                }
+            Jv *= 0.5 * dt;
+            const size_t need = per_shot * S;
+            if (need > w.dobs_cap) {
+                dfree(ctx, w.dobs);
+                w.dobs = nullptr;
+                w.dobs_cap = 0;
+                if ((s = dalloc(ctx, (void **)&w.dobs, need * sizeof(double)))) return s;
+                w.dobs_cap = need;
+            }
+            HCK(hipMemcpyAsync(w.dobs, d_obs, need * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        }
+        // reverse sweep
+        HCK(hipMemsetAsync(w.lam, 0, sbytes, ctx->stream));
+        HCK(hipMemsetAsync(w.gacc, 0, 3 * (size_t)ctx->LT * sizeof(double), ctx->stream));
+        std::vector<Clock> clocks(n_seg);
         s = dispatch(ctx, [&](auto kc, auto *r) {
             using R = std::remove_pointer_t<decltype(r)>;
-            return enqueue_steps<decltype(kc)::value, R>(ctx, ctx->stream, len, (R *)nullptr, (g * every) & 1);
+            return adjoint_sweep<decltype(kc)::value, R>(ctx, co, every, n_seg, n_steps, t0, dt, clocks);
         });
         if (s != HHO_OK) return s;
-    }
-    if ((s = end_steps(ctx, n_steps, E0))) return s;
-    void *uN = (char *)w.ckpt + (size_t)n_seg * sbytes;
-    HCK(hipMemcpyAsync(uN, ctx->U, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
-    // misfit J = 1/2 dt sum_shots sum_n sum_r |R_r U^n - d_r^n|^2 from the recorded traces
-    double Jv = 0.0;
-    const size_t per_shot = (size_t)n_steps * ctx->nrec * 2;
-    if (ctx->nrec > 0) {
-        const size_t stride = ctx->rec_cap / (size_t)S;
-        std::vector<double> tr(stride * S);
-        HCK(hipMemcpyAsync(tr.data(), ctx->rec_out, tr.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HCK(launch_grad_reduce(w.gacc, ctx->LT, S, w.ic_of_cell, P.n_cells, w.grad, ctx->stream));
+        HCK(hipMemcpyAsync(grad, w.grad, 3 * (size_t)P.n_cells * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        // leave the context at U^N, as after hho_erk_step
+        HCK(hipMemcpyAsync(ctx->U, uN, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+        ctx->h_clock = Clock{t0, dt, n_steps, 0};
+        HCK(hipMemcpyAsync(ctx->clock, &ctx->h_clock, sizeof(Clock), hipMemcpyHostToDevice, ctx->stream));
         HCK(hipStreamSynchronize(ctx->stream));
-        for (int sh = 0; sh < S; ++sh)
-            for (size_t e = 0; e < per_shot; ++e) {
-                const double d = tr[sh * stride + e] - d_obs[sh * per_shot + e];
-                Jv += d * d;
-            }
-        Jv *= 0.5 * dt;
-        const size_t need = per_shot * S;
-        if (need > w.dobs_cap) {
-            dfree(ctx, w.dobs);
-            w.dobs = nullptr;
-            w.dobs_cap = 0;
-            if ((s = dalloc(ctx, (void **)&w.dobs, need * sizeof(double)))) return s;
-            w.dobs_cap = need;
-        }
-        HCK(hipMemcpyAsync(w.dobs, d_obs, need * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    }
-    // reverse sweep
-    HCK(hipMemsetAsync(w.lam, 0, sbytes, ctx->stream));
-    HCK(hipMemsetAsync(w.gacc, 0, 3 * (size_t)ctx->LT * sizeof(double), ctx->stream));
-    std::vector<Clock> clocks(n_seg);
-    s = dispatch(ctx, [&](auto kc, auto *r) {
-        using R = std::remove_pointer_t<decltype(r)>;
-        return adjoint_sweep<decltype(kc)::value, R>(ctx, co, every, n_seg, n_steps, t0, dt, clocks);
+        ctx->traces_valid = false;
+        *J = Jv;
+        return HHO_OK;
     });
-    if (s != HHO_OK) return s;
-    HCK(launch_grad_reduce(w.gacc, ctx->LT, S, w.ic_of_cell, P.n_cells, w.grad, ctx->stream));
-    HCK(hipMemcpyAsync(grad, w.grad, 3 * (size_t)P.n_cells * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    // leave the context at U^N, as after hho_erk_step
-    HCK(hipMemcpyAsync(ctx->U, uN, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
-    ctx->h_clock = Clock{t0, dt, n_steps, 0};
-    HCK(hipMemcpyAsync(ctx->clock, &ctx->h_clock, sizeof(Clock), hipMemcpyHostToDevice, ctx->stream));
-    HCK(hipStreamSynchronize(ctx->stream));
-    ctx->traces_valid = false;
-    *J = Jv;
-    return HHO_OK;
 }
 
 hho_status hho_autotune(hho_ctx *ctx, int32_t *lanes) {
-    if (!ctx) return HHO_ERR_ARG;
-    hho_status s = set_device(ctx);
-    if (s != HHO_OK) return s;
-    s = dispatch(ctx, [&](auto kc, auto *r) {
-        using R = std::remove_pointer_t<decltype(r)>;
-        return autotune_shape<decltype(kc)::value, R>(ctx);
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return s;
+        s = dispatch(ctx, [&](auto kc, auto *r) {
+            using R = std::remove_pointer_t<decltype(r)>;
+            return autotune_shape<decltype(kc)::value, R>(ctx);
+        });
+        if (s != HHO_OK) return s;
+        if (lanes) *lanes = ctx->launch[ctx->shape].lanes;
+        return HHO_OK;
     });
-    if (s != HHO_OK) return s;
-    if (lanes) *lanes = ctx->launch[ctx->shape].lanes;
-    return HHO_OK;
 }
 
 hho_status hho_set_launch(hho_ctx *ctx, int32_t lanes) {
-    if (!ctx) return HHO_ERR_ARG;
-    for (size_t i = 0; i < ctx->launch.size(); ++i)
-        if (ctx->launch[i].lanes == lanes || ctx->launch[i].lanes == lanes / ctx->plan.S * ctx->plan.S) {
-            if ((int)i != ctx->shape) {
-                ctx->shape = (int)i;
-                ctx->version++;
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        for (size_t i = 0; i < ctx->launch.size(); ++i)
+            if (ctx->launch[i].lanes == lanes || ctx->launch[i].lanes == lanes / ctx->plan.S * ctx->plan.S) {
+                if ((int)i != ctx->shape) {
+                    ctx->shape = (int)i;
+                    ctx->version++;
+                }
+                return HHO_OK;
             }
-            return HHO_OK;
-        }
-    ctx->err = "set_launch: no launch shape with " + std::to_string(lanes) + " lanes";
-    return HHO_ERR_ARG;
+        ctx->err = "set_launch: no launch shape with " + std::to_string(lanes) + " lanes";
+        return HHO_ERR_ARG;
+    });
 }
 
 hho_status hho_set_tuning(hho_ctx *ctx, int32_t lanes, int32_t flags) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (flags & ~HHO_TUNE_NT_STORES) {
-        ctx->err = "set_tuning: unknown flag bits " + std::to_string(flags);
-        return HHO_ERR_ARG;
-    }
-    const hho_status s = hho_set_launch(ctx, lanes);
-    if (s != HHO_OK) return s;
-    const int nt = (flags & HHO_TUNE_NT_STORES) ? 1 : 0;
-    if (nt != ctx->nt_stores) {
-        ctx->nt_stores = nt;
-        ctx->version++;
-    }
-    return HHO_OK;
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (flags & ~HHO_TUNE_NT_STORES) {
+            ctx->err = "set_tuning: unknown flag bits " + std::to_string(flags);
+            return HHO_ERR_ARG;
+        }
+        const hho_status s = hho_set_launch(ctx, lanes);
+        if (s != HHO_OK) return s;
+        const int nt = (flags & HHO_TUNE_NT_STORES) ? 1 : 0;
+        if (nt != ctx->nt_stores) {
+            ctx->nt_stores = nt;
+            ctx->version++;
+        }
+        return HHO_OK;
+    });
 }
 
 hho_status hho_get_tuning(const hho_ctx *ctx, int32_t *lanes, int32_t *flags) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (lanes) *lanes = ctx->launch[ctx->shape].lanes;
-    if (flags) *flags = ctx->nt_stores ? HHO_TUNE_NT_STORES : 0;
-    return HHO_OK;
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (lanes) *lanes = ctx->launch[ctx->shape].lanes;
+        if (flags) *flags = ctx->nt_stores ? HHO_TUNE_NT_STORES : 0;
+        return HHO_OK;
+    });
 }
 
 hho_status hho_dt_cfl(const hho_ctx *ctx, double factor, double *dt) {
-    if (!ctx || !dt || !(factor > 0.0)) return HHO_ERR_ARG;
-    *dt = factor * ctx->cfl_dt;
-    return HHO_OK;
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx || !dt || !(factor > 0.0)) return HHO_ERR_ARG;
+        *dt = factor * ctx->cfl_dt;
+        return HHO_OK;
+    });
 }
 
 hho_status hho_batch_create(hho_ctx *const *ctxs, int32_t n, hho_batch **out) {
-    if (!ctxs || n <= 0 || !out) return HHO_ERR_ARG;
-    *out = nullptr;
-    for (int i = 0; i < n; ++i)
-        if (!ctxs[i] || ctxs[i]->device != ctxs[0]->device) {
-            g_setup_error = "batch: contexts must be non-null and on one device";
-            return HHO_ERR_ARG;
+    return guarded(&g_setup_error, [&]() -> hho_status {
+        if (!ctxs || n <= 0 || !out) return HHO_ERR_ARG;
+        *out = nullptr;
+        for (int i = 0; i < n; ++i)
+            if (!ctxs[i] || ctxs[i]->device != ctxs[0]->device) {
+                g_setup_error = "batch: contexts must be non-null and on one device";
+                return HHO_ERR_ARG;
+            }
+        hho_batch *b = new hho_batch();
+        b->ctxs.assign(ctxs, ctxs + n);
+        (void)hipSetDevice(ctxs[0]->device);
+        for (int i = 0; i <= n; ++i) {
+            hipStream_t st;
+            hipEvent_t ev;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                g_setup_error = "batch: stream or event creation failed";
+                hho_batch_destroy(b);
+                return HHO_ERR_DEVICE;
+            }
+            b->streams.push_back(st);
+            b->events.push_back(ev);
         }
-    hho_batch *b = new hho_batch();
-    b->ctxs.assign(ctxs, ctxs + n);
-    (void)hipSetDevice(ctxs[0]->device);
-    for (int i = 0; i <= n; ++i) {
-        hipStream_t st;
-        hipEvent_t ev;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-            g_setup_error = "batch: stream or event creation failed";
-            hho_batch_destroy(b);
-            return HHO_ERR_DEVICE;
-        }
-        b->streams.push_back(st);
-        b->events.push_back(ev);
-    }
-    *out = b;
-    return HHO_OK;
+        *out = b;
+        return HHO_OK;
+    });
 }
 
 void hho_batch_destroy(hho_batch *b) {
@@ -1515,127 +1569,137 @@ void hho_batch_destroy(hho_batch *b) {
 const char *hho_batch_last_error(const hho_batch *b) { return b ? b->err.c_str() : g_setup_error.c_str(); }
 
 hho_status hho_batch_erk_step(hho_batch *b, const double *t0, const double *dt, int32_t n_steps) {
-    if (!b || !t0 || !dt || n_steps < 0) return HHO_ERR_ARG;
-    const int n = (int)b->ctxs.size();
-    hho_ctx *c0 = b->ctxs[0];
-    hipStream_t launch_st = c0->stream;
-    if (hipSetDevice(c0->device) != hipSuccess) return HHO_ERR_DEVICE;
-    std::vector<std::vector<double>> E0(n);
-    for (int i = 0; i < n; ++i) {
-        hho_ctx *ctx = b->ctxs[i];
-        if (!(dt[i] > 0.0)) {
-            b->err = "batch_erk_step: dt must be positive";
-            return HHO_ERR_ARG;
+    return guarded(b ? &const_cast<hho_batch *>(b)->err : &g_setup_error, [&]() -> hho_status {
+        if (!b || !t0 || !dt || n_steps < 0) return HHO_ERR_ARG;
+        const int n = (int)b->ctxs.size();
+        hho_ctx *c0 = b->ctxs[0];
+        hipStream_t launch_st = c0->stream;
+        if (hipSetDevice(c0->device) != hipSuccess) return HHO_ERR_DEVICE;
+        std::vector<std::vector<double>> E0(n);
+        for (int i = 0; i < n; ++i) {
+            hho_ctx *ctx = b->ctxs[i];
+            if (!(dt[i] > 0.0)) {
+                b->err = "batch_erk_step: dt must be positive";
+                return HHO_ERR_ARG;
+            }
+            hho_status s = begin_steps(ctx, t0[i], dt[i], n_steps, E0[i]);
+            if (s != HHO_OK) {
+                b->err = ctx->err;
+                return s;
+            }
+            // the batch launches on the first context's stream
+            if (ctx->stream != launch_st) {
+                if (hipStreamSynchronize(ctx->stream) != hipSuccess) return HHO_ERR_DEVICE;
+            }
         }
-        hho_status s = begin_steps(ctx, t0[i], dt[i], n_steps, E0[i]);
-        if (s != HHO_OK) {
-            b->err = ctx->err;
-            return s;
+        if (hipStreamSynchronize(launch_st) != hipSuccess) return HHO_ERR_DEVICE;
+        const int full = n_steps / kGraphSteps, rem = n_steps % kGraphSteps;
+        bool fresh = b->gexec && (int)b->versions.size() == n;
+        for (int i = 0; fresh && i < n; ++i) fresh = b->versions[i] == b->ctxs[i]->version;
+        if (full > 0 && !fresh) {
+            if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+            b->gexec = nullptr;
+            hho_status s = capture_batch(b, kGraphSteps, &b->gexec);
+            if (s != HHO_OK) return s;
+            b->versions.clear();
+            for (hho_ctx *ctx : b->ctxs) b->versions.push_back(ctx->version);
         }
-        // the batch launches on the first context's stream
-        if (ctx->stream != launch_st) {
-            if (hipStreamSynchronize(ctx->stream) != hipSuccess) return HHO_ERR_DEVICE;
+        for (int g = 0; g < full; ++g)
+            if (hipGraphLaunch(b->gexec, launch_st) != hipSuccess) {
+                b->err = "batch: hipGraphLaunch failed";
+                return HHO_ERR_DEVICE;
+            }
+        for (int i = 0; i < n && rem > 0; ++i) {
+            hho_ctx *ctx = b->ctxs[i];
+            hho_status s = dispatch(ctx, [&](auto kc, auto *r) {
+                using R = std::remove_pointer_t<decltype(r)>;
+                return enqueue_steps<decltype(kc)::value, R>(ctx, launch_st, rem);
+            });
+            if (s != HHO_OK) {
+                b->err = ctx->err;
+                return s;
+            }
         }
-    }
-    if (hipStreamSynchronize(launch_st) != hipSuccess) return HHO_ERR_DEVICE;
-    const int full = n_steps / kGraphSteps, rem = n_steps % kGraphSteps;
-    bool fresh = b->gexec && (int)b->versions.size() == n;
-    for (int i = 0; fresh && i < n; ++i) fresh = b->versions[i] == b->ctxs[i]->version;
-    if (full > 0 && !fresh) {
-        if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-        b->gexec = nullptr;
-        hho_status s = capture_batch(b, kGraphSteps, &b->gexec);
-        if (s != HHO_OK) return s;
-        b->versions.clear();
-        for (hho_ctx *ctx : b->ctxs) b->versions.push_back(ctx->version);
-    }
-    for (int g = 0; g < full; ++g)
-        if (hipGraphLaunch(b->gexec, launch_st) != hipSuccess) {
-            b->err = "batch: hipGraphLaunch failed";
-            return HHO_ERR_DEVICE;
+        if (hipStreamSynchronize(launch_st) != hipSuccess) return HHO_ERR_DEVICE;
+        hho_status worst = HHO_OK;
+        for (int i = 0; i < n; ++i) {
+            hho_status s = end_steps(b->ctxs[i], n_steps, E0[i]);
+            if (s != HHO_OK && worst == HHO_OK) {
+                worst = s;
+                b->err = "context " + std::to_string(i) + ": " + b->ctxs[i]->err;
+            }
         }
-    for (int i = 0; i < n && rem > 0; ++i) {
-        hho_ctx *ctx = b->ctxs[i];
-        hho_status s = dispatch(ctx, [&](auto kc, auto *r) {
-            using R = std::remove_pointer_t<decltype(r)>;
-            return enqueue_steps<decltype(kc)::value, R>(ctx, launch_st, rem);
-        });
-        if (s != HHO_OK) {
-            b->err = ctx->err;
-            return s;
-        }
-    }
-    if (hipStreamSynchronize(launch_st) != hipSuccess) return HHO_ERR_DEVICE;
-    hho_status worst = HHO_OK;
-    for (int i = 0; i < n; ++i) {
-        hho_status s = end_steps(b->ctxs[i], n_steps, E0[i]);
-        if (s != HHO_OK && worst == HHO_OK) {
-            worst = s;
-            b->err = "context " + std::to_string(i) + ": " + b->ctxs[i]->err;
-        }
-    }
-    return worst;
+        return worst;
+    });
 }
 
 hho_status hho_synchronize(hho_ctx *ctx) {
-    if (!ctx) return HHO_ERR_ARG;
-    hho_status s = set_device(ctx);
-    if (s != HHO_OK) return s;
-    HCK(hipStreamSynchronize(ctx->stream));
-    return HHO_OK;
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return s;
+        HCK(hipStreamSynchronize(ctx->stream));
+        return HHO_OK;
+    });
 }
 
 hho_status hho_get_traces(hho_ctx *ctx, int32_t shot, double *out) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (!out || shot < 0 || shot >= ctx->plan.S) {
-        ctx->err = "get_traces: bad arguments";
-        return HHO_ERR_ARG;
-    }
-    if (ctx->nrec == 0 || ctx->last_steps == 0) return HHO_OK;
-    hho_status s = set_device(ctx);
-    if (s != HHO_OK) return s;
-    // shots are strided by the recording capacity, which may exceed the last call's steps
-    const size_t n = (size_t)ctx->last_steps * ctx->nrec * 2;
-    const size_t stride = ctx->rec_cap / (size_t)ctx->plan.S;
-    HCK(hipMemcpyAsync(out, ctx->rec_out + (size_t)shot * stride, n * sizeof(double), hipMemcpyDeviceToHost,
-                       ctx->stream));
-    HCK(hipStreamSynchronize(ctx->stream));
-    return HHO_OK;
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (!out || shot < 0 || shot >= ctx->plan.S) {
+            ctx->err = "get_traces: bad arguments";
+            return HHO_ERR_ARG;
+        }
+        if (ctx->nrec == 0 || ctx->last_steps == 0) return HHO_OK;
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return s;
+        // shots are strided by the recording capacity, which may exceed the last call's steps
+        const size_t n = (size_t)ctx->last_steps * ctx->nrec * 2;
+        const size_t stride = ctx->rec_cap / (size_t)ctx->plan.S;
+        HCK(hipMemcpyAsync(out, ctx->rec_out + (size_t)shot * stride, n * sizeof(double), hipMemcpyDeviceToHost,
+                           ctx->stream));
+        HCK(hipStreamSynchronize(ctx->stream));
+        return HHO_OK;
+    });
 }
 
 hho_status hho_energy(hho_ctx *ctx, double *E) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (!E) {
-        ctx->err = "energy: null output";
-        return HHO_ERR_ARG;
-    }
-    hho_status s = set_device(ctx);
-    if (s != HHO_OK) return s;
-    s = dispatch(ctx, [&](auto kc, auto *r) {
-        using R = std::remove_pointer_t<decltype(r)>;
-        return energy_now<decltype(kc)::value, R>(ctx, ctx->e_now);
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (!E) {
+            ctx->err = "energy: null output";
+            return HHO_ERR_ARG;
+        }
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return s;
+        s = dispatch(ctx, [&](auto kc, auto *r) {
+            using R = std::remove_pointer_t<decltype(r)>;
+            return energy_now<decltype(kc)::value, R>(ctx, ctx->e_now);
+        });
+        if (s != HHO_OK) return s;
+        HCK(hipMemcpyAsync(E, ctx->e_now, ctx->plan.S * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HCK(hipStreamSynchronize(ctx->stream));
+        return HHO_OK;
     });
-    if (s != HHO_OK) return s;
-    HCK(hipMemcpyAsync(E, ctx->e_now, ctx->plan.S * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HCK(hipStreamSynchronize(ctx->stream));
-    return HHO_OK;
 }
 
 hho_status hho_energy_history(hho_ctx *ctx, int32_t shot, double *out) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (!out || shot < 0 || shot >= ctx->plan.S || !ctx->record_energy) {
-        ctx->err = "energy_history: bad arguments or record_energy = 0";
-        return HHO_ERR_ARG;
-    }
-    hho_status s = set_device(ctx);
-    if (s != HHO_OK) return s;
-    const int S = ctx->plan.S;
-    std::vector<double> E((size_t)ctx->last_steps * S);
-    if (!E.empty())
-        HCK(hipMemcpyAsync(E.data(), ctx->e_hist, E.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HCK(hipStreamSynchronize(ctx->stream));
-    for (int n = 0; n < ctx->last_steps; ++n) out[n] = E[(size_t)n * S + shot];
-    return HHO_OK;
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (!out || shot < 0 || shot >= ctx->plan.S || !ctx->record_energy) {
+            ctx->err = "energy_history: bad arguments or record_energy = 0";
+            return HHO_ERR_ARG;
+        }
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return s;
+        const int S = ctx->plan.S;
+        std::vector<double> E((size_t)ctx->last_steps * S);
+        if (!E.empty())
+            HCK(hipMemcpyAsync(E.data(), ctx->e_hist, E.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HCK(hipStreamSynchronize(ctx->stream));
+        for (int n = 0; n < ctx->last_steps; ++n) out[n] = E[(size_t)n * S + shot];
+        return HHO_OK;
+    });
 }
 
 }  // extern "C"
@@ -1650,74 +1714,86 @@ struct hho_inspect {
 extern "C" {
 
 hho_status hho_inspect_create(const hho_mesh *mesh, const hho_params *prm, hho_inspect **out) {
-    g_setup_error.clear();
-    if (!out || !mesh || !prm) return HHO_ERR_ARG;
-    *out = nullptr;
-    hho_inspect *p = new hho_inspect();
-    int code = 0;
-    std::string msg = build_plan(mesh->n_vertices, mesh->xy, mesh->n_cells, mesh->cell_ptr, mesh->cell_vtx,
-                                 mesh->medium, mesh->rho, mesh->a, mesh->b, prm->k, prm->eta_f, prm->eta_s,
-                                 prm->stab_speed, prm->n_shots, p->plan, &code);
-    if (code != 0) {
-        g_setup_error = msg;
-        delete p;
-        return (hho_status)code;
-    }
-    *out = p;
-    return HHO_OK;
+    return guarded(&g_setup_error, [&]() -> hho_status {
+        g_setup_error.clear();
+        if (!out || !mesh || !prm) return HHO_ERR_ARG;
+        *out = nullptr;
+        hho_inspect *p = new hho_inspect();
+        int code = 0;
+        std::string msg = build_plan(mesh->n_vertices, mesh->xy, mesh->n_cells, mesh->cell_ptr, mesh->cell_vtx,
+                                     mesh->medium, mesh->rho, mesh->a, mesh->b, prm->k, prm->eta_f, prm->eta_s,
+                                     prm->stab_speed, prm->n_shots, p->plan, &code);
+        if (code != 0) {
+            g_setup_error = msg;
+            delete p;
+            return (hho_status)code;
+        }
+        *out = p;
+        return HHO_OK;
+    });
 }
 
 void hho_inspect_destroy(hho_inspect *p) { delete p; }
 
 hho_status hho_inspect_sizes(const hho_inspect *p, int64_t *sz) {
-    if (!p || !sz) return HHO_ERR_ARG;
-    const Plan &P = p->plan;
-    const int64_t v[10] = {P.N, P.F, P.n_ic, P.max_nf, (int64_t)P.groups.size(), (int64_t)P.tables.size(),
-                           P.n_cells, P.n_faces, P.cpb, (int64_t)P.blk_group.size()};
-    std::memcpy(sz, v, sizeof(v));
-    return HHO_OK;
+    return guarded(&g_setup_error, [&]() -> hho_status {
+        if (!p || !sz) return HHO_ERR_ARG;
+        const Plan &P = p->plan;
+        const int64_t v[10] = {P.N, P.F, P.n_ic, P.max_nf, (int64_t)P.groups.size(), (int64_t)P.tables.size(),
+                               P.n_cells, P.n_faces, P.cpb, (int64_t)P.blk_group.size()};
+        std::memcpy(sz, v, sizeof(v));
+        return HHO_OK;
+    });
 }
 
 hho_status hho_inspect_arrays(const hho_inspect *p, double *tables, int32_t *groups, int32_t *link, double *c0,
                               double *mat, int32_t *ic_of_cell) {
-    if (!p) return HHO_ERR_ARG;
-    const Plan &P = p->plan;
-    if (tables) std::copy(P.tables.begin(), P.tables.end(), tables);
-    if (groups)
-        for (size_t g = 0; g < P.groups.size(); ++g) {
-            const Group &G = P.groups[g];
-            const int32_t v[6] = {G.medium, G.nF, G.tab_off, G.ic_begin, G.ncells, G.blk_begin};
-            std::memcpy(groups + 6 * g, v, sizeof(v));
-        }
-    if (link) std::copy(P.link.begin(), P.link.end(), link);
-    if (c0) std::copy(P.c0.begin(), P.c0.end(), c0);
-    if (mat) std::copy(P.mat.begin(), P.mat.end(), mat);
-    if (ic_of_cell) std::copy(P.ic_of_cell.begin(), P.ic_of_cell.end(), ic_of_cell);
-    return HHO_OK;
+    return guarded(&g_setup_error, [&]() -> hho_status {
+        if (!p) return HHO_ERR_ARG;
+        const Plan &P = p->plan;
+        if (tables) std::copy(P.tables.begin(), P.tables.end(), tables);
+        if (groups)
+            for (size_t g = 0; g < P.groups.size(); ++g) {
+                const Group &G = P.groups[g];
+                const int32_t v[6] = {G.medium, G.nF, G.tab_off, G.ic_begin, G.ncells, G.blk_begin};
+                std::memcpy(groups + 6 * g, v, sizeof(v));
+            }
+        if (link) std::copy(P.link.begin(), P.link.end(), link);
+        if (c0) std::copy(P.c0.begin(), P.c0.end(), c0);
+        if (mat) std::copy(P.mat.begin(), P.mat.end(), mat);
+        if (ic_of_cell) std::copy(P.ic_of_cell.begin(), P.ic_of_cell.end(), ic_of_cell);
+        return HHO_OK;
+    });
 }
 
 hho_status hho_inspect_dt_cfl(const hho_inspect *p, int32_t stages, double factor, double *dt) {
-    std::vector<StageCoef> co;
-    if (!p || !dt || !(factor > 0.0) || !erk_coefficients(stages, co)) return HHO_ERR_ARG;
-    *dt = factor * cfl_time_step(p->plan, stages);
-    return HHO_OK;
+    return guarded(&g_setup_error, [&]() -> hho_status {
+        std::vector<StageCoef> co;
+        if (!p || !dt || !(factor > 0.0) || !erk_coefficients(stages, co)) return HHO_ERR_ARG;
+        *dt = factor * cfl_time_step(p->plan, stages);
+        return HHO_OK;
+    });
 }
 
 hho_status hho_inspect_erk(int32_t stages, double *coefs) {
-    std::vector<StageCoef> co;
-    if (!coefs || !erk_coefficients(stages, co)) return HHO_ERR_ARG;
-    for (int i = 0; i < stages; ++i) {
-        const StageCoef &q = co[i];
-        const double v[9] = {q.c, q.cY, q.ck, q.cb, q.qa, q.qb, q.cd, (double)q.q_write, (double)q.q_read};
-        std::memcpy(coefs + 9 * i, v, sizeof(v));
-    }
-    return HHO_OK;
+    return guarded(&g_setup_error, [&]() -> hho_status {
+        std::vector<StageCoef> co;
+        if (!coefs || !erk_coefficients(stages, co)) return HHO_ERR_ARG;
+        for (int i = 0; i < stages; ++i) {
+            const StageCoef &q = co[i];
+            const double v[9] = {q.c, q.cY, q.ck, q.cb, q.qa, q.qb, q.cd, (double)q.q_write, (double)q.q_read};
+            std::memcpy(coefs + 9 * i, v, sizeof(v));
+        }
+        return HHO_OK;
+    });
 }
 
 hho_status hho_inspect_grad_coefs(const hho_inspect *p, double *gm) {
-    if (!p || !gm) return HHO_ERR_ARG;
-    std::copy(p->plan.gm.begin(), p->plan.gm.end(), gm);
-    return HHO_OK;
+    return guarded(&g_setup_error, [&]() -> hho_status {
+        if (!p || !gm) return HHO_ERR_ARG;
+        std::copy(p->plan.gm.begin(), p->plan.gm.end(), gm);
+        return HHO_OK;
+    });
 }
 
 }  // extern "C"

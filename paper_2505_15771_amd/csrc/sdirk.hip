@@ -21,6 +21,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -836,137 +838,157 @@ void from_group(const hho::imp::Plan &P, const std::vector<double> &grp, double 
 
 }  // namespace
 
+// Runs one C ABI call; a C++ exception (a failed host allocation, above all) becomes a status
+// code and a message instead of crossing the ABI.
+template <typename F>
+hho_status guarded(std::string *err, F &&body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        if (err) *err = "host memory allocation failed";
+        return HHO_ERR_OOM;
+    } catch (const std::exception &e) {
+        if (err) *err = std::string("internal error: ") + e.what();
+        return HHO_ERR_DEVICE;
+    } catch (...) {
+        if (err) *err = "internal error";
+        return HHO_ERR_DEVICE;
+    }
+}
+
 extern "C" {
 
 const char *hho_sdirk_last_error(const hho_sdirk *ctx) { return ctx ? ctx->err.c_str() : g_sdirk_error.c_str(); }
 
 hho_status hho_sdirk_setup(const hho_mesh *mesh, const hho_sdirk_params *prm, hho_sdirk **out) {
-    g_sdirk_error.clear();
-    if (!out) {
-        g_sdirk_error = "null output pointer";
-        return HHO_ERR_ARG;
-    }
-    *out = nullptr;
-    if (prm && (!(prm->tol > 0.0) || !(prm->tol < 1.0) || prm->max_iter < 1)) {
-        g_sdirk_error = "tol must lie in (0, 1) and max_iter be >= 1";
-        return HHO_ERR_ARG;
-    }
-    hho_sdirk *ctx = new hho_sdirk();
-    int code = 0;
-    std::string msg = build_plan(mesh, prm, ctx->plan, &code);
-    if (!msg.empty()) {
-        g_sdirk_error = msg;
-        delete ctx;
-        return (hho_status)code;
-    }
-    if ((int)ctx->plan.groups.size() > kMaxGroups) {
-        g_sdirk_error = "too many cell groups";
-        delete ctx;
-        return HHO_ERR_MESH;
-    }
-    ctx->device = prm->device;
-    ctx->stream = (hipStream_t)prm->stream;
-    ctx->tol = prm->tol;
-    ctx->max_iter = prm->max_iter;
-    auto fail = [&](hho_status st) {
-        g_sdirk_error = ctx->err;
-        hho_sdirk_destroy(ctx);
-        return st;
-    };
-    if (hipSetDevice(ctx->device) != hipSuccess) {
-        ctx->err = "hipSetDevice failed";
-        return fail(HHO_ERR_DEVICE);
-    }
-    fill_groups(ctx);
-    const auto &P = ctx->plan;
-    hho_status st = HHO_OK;
-#define UP(ptr, vec)                                  \
-    if ((st = upload(ctx, &ptr, vec)) != HHO_OK) return fail(st);
-#define AL(ptr, count)                                \
-    if ((st = dev_alloc(ctx, &ptr, count)) != HHO_OK) return fail(st);
-    UP(ctx->mats, P.mats);
-    UP(ctx->wmat, P.wmat);
-    UP(ctx->mat, P.mat);
-    UP(ctx->slot_dof, P.slot_dof);
-    UP(ctx->feed, P.feed);
-    UP(ctx->S_ptr, P.S_ptr);
-    {
-        // shared column lists: a row reuses the previous row's list when it is the same
-        std::vector<int> coff(std::max(P.n_fdof, 1), 0), cols;
-        int last = -1;
-        for (int d = 0; d < P.n_fdof; ++d) {
-            const int a = P.S_ptr[d], len = P.S_ptr[d + 1] - a;
-            bool same = last >= 0 && P.S_ptr[last + 1] - P.S_ptr[last] == len &&
-                        std::equal(P.S_col.begin() + a, P.S_col.begin() + a + len, P.S_col.begin() + P.S_ptr[last]);
-            if (same) {
-                coff[d] = coff[last];
-            } else {
-                coff[d] = (int)cols.size();
-                cols.insert(cols.end(), P.S_col.begin() + a, P.S_col.begin() + a + len);
-            }
-            last = d;
+    return guarded(&g_sdirk_error, [&]() -> hho_status {
+        g_sdirk_error.clear();
+        if (!out) {
+            g_sdirk_error = "null output pointer";
+            return HHO_ERR_ARG;
         }
-        ctx->n_shared_cols = (int64_t)cols.size();
-        UP(ctx->S_coff, coff);
-        UP(ctx->S_cols, cols);
-    }
-    {
-        std::vector<double> scaled(P.S_val.size());
-        for (int d = 0; d < P.n_fdof; ++d)
-            for (int q = P.S_ptr[d]; q < P.S_ptr[d + 1]; ++q) scaled[q] = P.dscale[d] * P.S_val[q] * P.dscale[P.S_col[q]];
-        UP(ctx->S_val, scaled);
-    }
-    UP(ctx->dsc, P.dscale);
-    UP(ctx->P_ptr, P.P_ptr);
-    {
-        std::vector<int> start(P.n_fdof);
-        std::vector<float> pv(P.P_val.size());
-        for (int d = 0; d < P.n_fdof; ++d) start[d] = P.P_col[P.P_ptr[d]];
-        for (size_t q = 0; q < pv.size(); ++q) pv[q] = (float)P.P_val[q];
-        UP(ctx->P_start, start);
-        UP(ctx->P_val, pv);
-    }
-    const size_t nd = (size_t)P.n_dof, nf = (size_t)P.n_fdof;
-    AL(ctx->U, nd);
-    AL(ctx->U0, nd);
-    AL(ctx->B, nd);
-    AL(ctx->gv, nd);
-    AL(ctx->Z, nd);
-    AL(ctx->Y, nd * P.stages);
-    AL(ctx->cf, (size_t)P.n_slot);
-    AL(ctx->E, nf * P.stages);
-    AL(ctx->bF, nf);
-    AL(ctx->rhs, nf);
-    AL(ctx->x, nf);
-    AL(ctx->r, nf);
-    AL(ctx->rh, nf);
-    AL(ctx->pb[0], nf);
-    AL(ctx->pb[1], nf);
-    AL(ctx->v, nf);
-    AL(ctx->s, nf);
-    AL(ctx->t, nf);
-    AL(ctx->ph, nf);
-    AL(ctx->sh, nf);
-    AL(ctx->part, 2 * (size_t)kDotBlocks);
-    AL(ctx->partA, 2 * (size_t)grid_for(std::max<int>(P.n_fdof, 1)));
-    AL(ctx->partB, 2 * (size_t)kSpmvBlocks);
-    AL(ctx->partC, 2 * (size_t)kSpmvBlocks);
-    AL(ctx->sc, kNumScalars);
-#undef UP
-#undef AL
-    if (hipHostMalloc((void **)&ctx->h_sc, kNumScalars * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-        ctx->err = "hipHostMalloc failed";
-        return fail(HHO_ERR_OOM);
-    }
-    if (hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) ctx->cap = nullptr;
-    const double tol2 = ctx->tol * ctx->tol;
-    if (hipMemcpyAsync(ctx->sc + S_TOL2, &tol2, sizeof(double), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess) {
-        ctx->err = "upload of the solver tolerance failed";
-        return fail(HHO_ERR_DEVICE);
-    }
-    *out = ctx;
-    return HHO_OK;
+        *out = nullptr;
+        if (prm && (!(prm->tol > 0.0) || !(prm->tol < 1.0) || prm->max_iter < 1)) {
+            g_sdirk_error = "tol must lie in (0, 1) and max_iter be >= 1";
+            return HHO_ERR_ARG;
+        }
+        hho_sdirk *ctx = new hho_sdirk();
+        int code = 0;
+        std::string msg = build_plan(mesh, prm, ctx->plan, &code);
+        if (!msg.empty()) {
+            g_sdirk_error = msg;
+            delete ctx;
+            return (hho_status)code;
+        }
+        if ((int)ctx->plan.groups.size() > kMaxGroups) {
+            g_sdirk_error = "too many cell groups";
+            delete ctx;
+            return HHO_ERR_MESH;
+        }
+        ctx->device = prm->device;
+        ctx->stream = (hipStream_t)prm->stream;
+        ctx->tol = prm->tol;
+        ctx->max_iter = prm->max_iter;
+        auto fail = [&](hho_status st) {
+            g_sdirk_error = ctx->err;
+            hho_sdirk_destroy(ctx);
+            return st;
+        };
+        if (hipSetDevice(ctx->device) != hipSuccess) {
+            ctx->err = "hipSetDevice failed";
+            return fail(HHO_ERR_DEVICE);
+        }
+        fill_groups(ctx);
+        const auto &P = ctx->plan;
+        hho_status st = HHO_OK;
+    #define UP(ptr, vec)                                  \
+        if ((st = upload(ctx, &ptr, vec)) != HHO_OK) return fail(st);
+    #define AL(ptr, count)                                \
+        if ((st = dev_alloc(ctx, &ptr, count)) != HHO_OK) return fail(st);
+        UP(ctx->mats, P.mats);
+        UP(ctx->wmat, P.wmat);
+        UP(ctx->mat, P.mat);
+        UP(ctx->slot_dof, P.slot_dof);
+        UP(ctx->feed, P.feed);
+        UP(ctx->S_ptr, P.S_ptr);
+        {
+            // shared column lists: a row reuses the previous row's list when it is the same
+            std::vector<int> coff(std::max(P.n_fdof, 1), 0), cols;
+            int last = -1;
+            for (int d = 0; d < P.n_fdof; ++d) {
+                const int a = P.S_ptr[d], len = P.S_ptr[d + 1] - a;
+                bool same = last >= 0 && P.S_ptr[last + 1] - P.S_ptr[last] == len &&
+                            std::equal(P.S_col.begin() + a, P.S_col.begin() + a + len, P.S_col.begin() + P.S_ptr[last]);
+                if (same) {
+                    coff[d] = coff[last];
+                } else {
+                    coff[d] = (int)cols.size();
+                    cols.insert(cols.end(), P.S_col.begin() + a, P.S_col.begin() + a + len);
+                }
+                last = d;
+            }
+            ctx->n_shared_cols = (int64_t)cols.size();
+            UP(ctx->S_coff, coff);
+            UP(ctx->S_cols, cols);
+        }
+        {
+            std::vector<double> scaled(P.S_val.size());
+            for (int d = 0; d < P.n_fdof; ++d)
+                for (int q = P.S_ptr[d]; q < P.S_ptr[d + 1]; ++q) scaled[q] = P.dscale[d] * P.S_val[q] * P.dscale[P.S_col[q]];
+            UP(ctx->S_val, scaled);
+        }
+        UP(ctx->dsc, P.dscale);
+        UP(ctx->P_ptr, P.P_ptr);
+        {
+            std::vector<int> start(P.n_fdof);
+            std::vector<float> pv(P.P_val.size());
+            for (int d = 0; d < P.n_fdof; ++d) start[d] = P.P_col[P.P_ptr[d]];
+            for (size_t q = 0; q < pv.size(); ++q) pv[q] = (float)P.P_val[q];
+            UP(ctx->P_start, start);
+            UP(ctx->P_val, pv);
+        }
+        const size_t nd = (size_t)P.n_dof, nf = (size_t)P.n_fdof;
+        AL(ctx->U, nd);
+        AL(ctx->U0, nd);
+        AL(ctx->B, nd);
+        AL(ctx->gv, nd);
+        AL(ctx->Z, nd);
+        AL(ctx->Y, nd * P.stages);
+        AL(ctx->cf, (size_t)P.n_slot);
+        AL(ctx->E, nf * P.stages);
+        AL(ctx->bF, nf);
+        AL(ctx->rhs, nf);
+        AL(ctx->x, nf);
+        AL(ctx->r, nf);
+        AL(ctx->rh, nf);
+        AL(ctx->pb[0], nf);
+        AL(ctx->pb[1], nf);
+        AL(ctx->v, nf);
+        AL(ctx->s, nf);
+        AL(ctx->t, nf);
+        AL(ctx->ph, nf);
+        AL(ctx->sh, nf);
+        AL(ctx->part, 2 * (size_t)kDotBlocks);
+        AL(ctx->partA, 2 * (size_t)grid_for(std::max<int>(P.n_fdof, 1)));
+        AL(ctx->partB, 2 * (size_t)kSpmvBlocks);
+        AL(ctx->partC, 2 * (size_t)kSpmvBlocks);
+        AL(ctx->sc, kNumScalars);
+    #undef UP
+    #undef AL
+        if (hipHostMalloc((void **)&ctx->h_sc, kNumScalars * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            ctx->err = "hipHostMalloc failed";
+            return fail(HHO_ERR_OOM);
+        }
+        if (hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) ctx->cap = nullptr;
+        const double tol2 = ctx->tol * ctx->tol;
+        if (hipMemcpyAsync(ctx->sc + S_TOL2, &tol2, sizeof(double), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(ctx->stream) != hipSuccess) {
+            ctx->err = "upload of the solver tolerance failed";
+            return fail(HHO_ERR_DEVICE);
+        }
+        *out = ctx;
+        return HHO_OK;
+    });
 }
 
 void hho_sdirk_destroy(hho_sdirk *ctx) {
@@ -981,266 +1003,290 @@ void hho_sdirk_destroy(hho_sdirk *ctx) {
 }
 
 hho_status hho_sdirk_sizes(const hho_sdirk *ctx, int64_t *n_dof, int32_t *n_face_dof, int64_t *nnz) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (n_dof) *n_dof = ctx->plan.n_dof;
-    if (n_face_dof) *n_face_dof = ctx->plan.n_fdof;
-    if (nnz) *nnz = (int64_t)ctx->plan.S_val.size();
-    return HHO_OK;
+    return guarded(ctx ? &const_cast<hho_sdirk *>(ctx)->err : &g_sdirk_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (n_dof) *n_dof = ctx->plan.n_dof;
+        if (n_face_dof) *n_face_dof = ctx->plan.n_fdof;
+        if (nnz) *nnz = (int64_t)ctx->plan.S_val.size();
+        return HHO_OK;
+    });
 }
 
 hho_status hho_sdirk_set_state(hho_sdirk *ctx, const double *U, int32_t on_device) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (!U) {
-        ctx->err = "null state";
-        return HHO_ERR_ARG;
-    }
-    SCK(hipSetDevice(ctx->device));
-    const auto &P = ctx->plan;
-    std::vector<double> ext(P.n_dof), grp;
-    if (on_device) {
-        SCK(hipMemcpyAsync(ext.data(), U, P.n_dof * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    return guarded(ctx ? &const_cast<hho_sdirk *>(ctx)->err : &g_sdirk_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (!U) {
+            ctx->err = "null state";
+            return HHO_ERR_ARG;
+        }
+        SCK(hipSetDevice(ctx->device));
+        const auto &P = ctx->plan;
+        std::vector<double> ext(P.n_dof), grp;
+        if (on_device) {
+            SCK(hipMemcpyAsync(ext.data(), U, P.n_dof * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+            SCK(hipStreamSynchronize(ctx->stream));
+        } else {
+            std::memcpy(ext.data(), U, P.n_dof * sizeof(double));
+        }
+        to_group(P, ext.data(), grp);
+        SCK(hipMemcpyAsync(ctx->U, grp.data(), P.n_dof * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        SCK(hipMemsetAsync(ctx->x, 0, std::max<size_t>(P.n_fdof, 1) * sizeof(double), ctx->stream));
         SCK(hipStreamSynchronize(ctx->stream));
-    } else {
-        std::memcpy(ext.data(), U, P.n_dof * sizeof(double));
-    }
-    to_group(P, ext.data(), grp);
-    SCK(hipMemcpyAsync(ctx->U, grp.data(), P.n_dof * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    SCK(hipMemsetAsync(ctx->x, 0, std::max<size_t>(P.n_fdof, 1) * sizeof(double), ctx->stream));
-    SCK(hipStreamSynchronize(ctx->stream));
-    return HHO_OK;
+        return HHO_OK;
+    });
 }
 
 hho_status hho_sdirk_get_state(hho_sdirk *ctx, double *U, int32_t on_device) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (!U) {
-        ctx->err = "null state";
-        return HHO_ERR_ARG;
-    }
-    SCK(hipSetDevice(ctx->device));
-    const auto &P = ctx->plan;
-    std::vector<double> grp(P.n_dof), ext(P.n_dof);
-    SCK(hipMemcpyAsync(grp.data(), ctx->U, P.n_dof * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    SCK(hipStreamSynchronize(ctx->stream));
-    from_group(P, grp, ext.data());
-    if (on_device) {
-        SCK(hipMemcpyAsync(U, ext.data(), P.n_dof * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    return guarded(ctx ? &const_cast<hho_sdirk *>(ctx)->err : &g_sdirk_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (!U) {
+            ctx->err = "null state";
+            return HHO_ERR_ARG;
+        }
+        SCK(hipSetDevice(ctx->device));
+        const auto &P = ctx->plan;
+        std::vector<double> grp(P.n_dof), ext(P.n_dof);
+        SCK(hipMemcpyAsync(grp.data(), ctx->U, P.n_dof * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
         SCK(hipStreamSynchronize(ctx->stream));
-    } else {
-        std::memcpy(U, ext.data(), P.n_dof * sizeof(double));
-    }
-    return HHO_OK;
+        from_group(P, grp, ext.data());
+        if (on_device) {
+            SCK(hipMemcpyAsync(U, ext.data(), P.n_dof * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+            SCK(hipStreamSynchronize(ctx->stream));
+        } else {
+            std::memcpy(U, ext.data(), P.n_dof * sizeof(double));
+        }
+        return HHO_OK;
+    });
 }
 
 hho_status hho_sdirk_set_sources(hho_sdirk *ctx, int32_t n, const double *xy, const double *dir, const double *f0,
                                  const double *t0, const double *amp) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (n < 0 || (n > 0 && (!xy || !dir || !f0 || !t0 || !amp))) {
-        ctx->err = "invalid source arrays";
-        return HHO_ERR_ARG;
-    }
-    SCK(hipSetDevice(ctx->device));
-    const auto &P = ctx->plan;
-    std::vector<SrcDev> v;
-    std::vector<double> phi(P.Np);
-    for (int q = 0; q < n; ++q) {
-        const int c = hho::imp::locate(P, xy[2 * q], xy[2 * q + 1]);
-        if (c < 0) {
-            ctx->err = "source " + std::to_string(q) + " lies outside the mesh";
+    return guarded(ctx ? &const_cast<hho_sdirk *>(ctx)->err : &g_sdirk_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (n < 0 || (n > 0 && (!xy || !dir || !f0 || !t0 || !amp))) {
+            ctx->err = "invalid source arrays";
             return HHO_ERR_ARG;
         }
-        hho::imp::eval_basis(P, c, xy[2 * q], xy[2 * q + 1], phi.data());
-        const auto &g = P.groups[P.cell_group[c]];
-        const int i = P.cell_index[c];
-        const int ncomp = P.medium[c] == 0 ? 1 : 2;
-        const double minv = P.medium[c] == 0 ? P.kappa[c] : 1.0 / P.rho[c];
-        for (int cc = 0; cc < ncomp; ++cc)
-            for (int a = 0; a < P.Np; ++a) {
-                const double coef = phi[a] * dir[2 * q + cc];
-                if (coef == 0.0) continue;
-                v.push_back({g.vec_off + (int64_t)(cc * P.Np + a) * g.n + i, coef, f0[q], t0[q], amp[q], minv});
+        SCK(hipSetDevice(ctx->device));
+        const auto &P = ctx->plan;
+        std::vector<SrcDev> v;
+        std::vector<double> phi(P.Np);
+        for (int q = 0; q < n; ++q) {
+            const int c = hho::imp::locate(P, xy[2 * q], xy[2 * q + 1]);
+            if (c < 0) {
+                ctx->err = "source " + std::to_string(q) + " lies outside the mesh";
+                return HHO_ERR_ARG;
             }
-    }
-    ctx->n_src = 0;
-    release(ctx, ctx->src);
-    ctx->src = nullptr;
-    if (!v.empty()) {
-        hho_status st = dev_alloc(ctx, &ctx->src, v.size());
-        if (st != HHO_OK) return st;
-        SCK(hipMemcpyAsync(ctx->src, v.data(), v.size() * sizeof(SrcDev), hipMemcpyHostToDevice, ctx->stream));
-        SCK(hipStreamSynchronize(ctx->stream));
-    }
-    ctx->n_src = (int)v.size();
-    return HHO_OK;
+            hho::imp::eval_basis(P, c, xy[2 * q], xy[2 * q + 1], phi.data());
+            const auto &g = P.groups[P.cell_group[c]];
+            const int i = P.cell_index[c];
+            const int ncomp = P.medium[c] == 0 ? 1 : 2;
+            const double minv = P.medium[c] == 0 ? P.kappa[c] : 1.0 / P.rho[c];
+            for (int cc = 0; cc < ncomp; ++cc)
+                for (int a = 0; a < P.Np; ++a) {
+                    const double coef = phi[a] * dir[2 * q + cc];
+                    if (coef == 0.0) continue;
+                    v.push_back({g.vec_off + (int64_t)(cc * P.Np + a) * g.n + i, coef, f0[q], t0[q], amp[q], minv});
+                }
+        }
+        ctx->n_src = 0;
+        release(ctx, ctx->src);
+        ctx->src = nullptr;
+        if (!v.empty()) {
+            hho_status st = dev_alloc(ctx, &ctx->src, v.size());
+            if (st != HHO_OK) return st;
+            SCK(hipMemcpyAsync(ctx->src, v.data(), v.size() * sizeof(SrcDev), hipMemcpyHostToDevice, ctx->stream));
+            SCK(hipStreamSynchronize(ctx->stream));
+        }
+        ctx->n_src = (int)v.size();
+        return HHO_OK;
+    });
 }
 
 hho_status hho_sdirk_step(hho_sdirk *ctx, double t0, int32_t n_steps) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (n_steps < 0 || !std::isfinite(t0)) {
-        ctx->err = "n_steps must be >= 0 and t0 finite";
-        return HHO_ERR_ARG;
-    }
-    SCK(hipSetDevice(ctx->device));
-    if (ctx->n_rec > 0) {
-        const size_t need = (size_t)std::max(n_steps, 1) * ctx->n_rec * 2;
-        if (need > ctx->trace_cap) {
-            release(ctx, ctx->traces);
-            ctx->traces = nullptr;
-            ctx->trace_cap = 0;
-            hho_status st = dev_alloc(ctx, &ctx->traces, need);
-            if (st != HHO_OK) return st;
-            ctx->trace_cap = need;
+    return guarded(ctx ? &const_cast<hho_sdirk *>(ctx)->err : &g_sdirk_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (n_steps < 0 || !std::isfinite(t0)) {
+            ctx->err = "n_steps must be >= 0 and t0 finite";
+            return HHO_ERR_ARG;
         }
-    }
-    ctx->last_steps = 0;
-    for (int n = 0; n < n_steps; ++n) {
-        hho_status st = one_step(ctx, t0 + n * ctx->plan.dt);
-        if (st != HHO_OK) {
-            // leave the state of the failing step's start
-            hipLaunchKernelGGL(k_copy, dim3(grid_for(ctx->plan.n_dof)), dim3(kThreads), 0, ctx->stream,
-                               (long long)ctx->plan.n_dof, ctx->U0, ctx->U);
-            (void)hipStreamSynchronize(ctx->stream);
-            return st;
-        }
+        SCK(hipSetDevice(ctx->device));
         if (ctx->n_rec > 0) {
-            hipLaunchKernelGGL(k_record, dim3((2 * ctx->n_rec + 63) / 64), dim3(64), 0, ctx->stream, 2 * ctx->n_rec,
-                               ctx->plan.Np, ctx->rec_idx, ctx->rec_coef, ctx->U,
-                               ctx->traces + (size_t)n * ctx->n_rec * 2);
-            SCK(hipGetLastError());
+            const size_t need = (size_t)std::max(n_steps, 1) * ctx->n_rec * 2;
+            if (need > ctx->trace_cap) {
+                release(ctx, ctx->traces);
+                ctx->traces = nullptr;
+                ctx->trace_cap = 0;
+                hho_status st = dev_alloc(ctx, &ctx->traces, need);
+                if (st != HHO_OK) return st;
+                ctx->trace_cap = need;
+            }
         }
-        ctx->last_steps = n + 1;
-    }
-    SCK(hipStreamSynchronize(ctx->stream));
-    return HHO_OK;
+        ctx->last_steps = 0;
+        for (int n = 0; n < n_steps; ++n) {
+            hho_status st = one_step(ctx, t0 + n * ctx->plan.dt);
+            if (st != HHO_OK) {
+                // leave the state of the failing step's start
+                hipLaunchKernelGGL(k_copy, dim3(grid_for(ctx->plan.n_dof)), dim3(kThreads), 0, ctx->stream,
+                                   (long long)ctx->plan.n_dof, ctx->U0, ctx->U);
+                (void)hipStreamSynchronize(ctx->stream);
+                return st;
+            }
+            if (ctx->n_rec > 0) {
+                hipLaunchKernelGGL(k_record, dim3((2 * ctx->n_rec + 63) / 64), dim3(64), 0, ctx->stream, 2 * ctx->n_rec,
+                                   ctx->plan.Np, ctx->rec_idx, ctx->rec_coef, ctx->U,
+                                   ctx->traces + (size_t)n * ctx->n_rec * 2);
+                SCK(hipGetLastError());
+            }
+            ctx->last_steps = n + 1;
+        }
+        SCK(hipStreamSynchronize(ctx->stream));
+        return HHO_OK;
+    });
 }
 
 hho_status hho_sdirk_receivers(hho_sdirk *ctx, int32_t n, const double *xy, const int32_t *field) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (n < 0 || (n > 0 && (!xy || !field))) {
-        ctx->err = "invalid receiver arrays";
-        return HHO_ERR_ARG;
-    }
-    SCK(hipSetDevice(ctx->device));
-    const auto &P = ctx->plan;
-    const int Np = P.Np;
-    std::vector<long long> idx((size_t)std::max(n, 1) * 2 * Np, -1);
-    std::vector<double> coef((size_t)std::max(n, 1) * 2 * Np, 0.0), phi(Np);
-    for (int q = 0; q < n; ++q) {
-        const int c = hho::imp::locate(P, xy[2 * q], xy[2 * q + 1]);
-        if (c < 0) {
-            ctx->err = "receiver " + std::to_string(q) + " lies outside the mesh";
+    return guarded(ctx ? &const_cast<hho_sdirk *>(ctx)->err : &g_sdirk_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (n < 0 || (n > 0 && (!xy || !field))) {
+            ctx->err = "invalid receiver arrays";
             return HHO_ERR_ARG;
         }
-        if (field[q] != (int)P.medium[c] || (field[q] != 0 && field[q] != 1)) {
-            ctx->err = "receiver " + std::to_string(q) + ": field 0 (p) needs a fluid cell, field 1 (v) a solid one";
-            return HHO_ERR_ARG;
-        }
-        hho::imp::eval_basis(P, c, xy[2 * q], xy[2 * q + 1], phi.data());
-        const auto &g = P.groups[P.cell_group[c]];
-        const int i = P.cell_index[c];
-        for (int comp = 0; comp < (field[q] == 0 ? 1 : 2); ++comp)
-            for (int a = 0; a < Np; ++a) {
-                idx[((size_t)2 * q + comp) * Np + a] = g.vec_off + (int64_t)(comp * Np + a) * g.n + i;
-                coef[((size_t)2 * q + comp) * Np + a] = phi[a];
+        SCK(hipSetDevice(ctx->device));
+        const auto &P = ctx->plan;
+        const int Np = P.Np;
+        std::vector<long long> idx((size_t)std::max(n, 1) * 2 * Np, -1);
+        std::vector<double> coef((size_t)std::max(n, 1) * 2 * Np, 0.0), phi(Np);
+        for (int q = 0; q < n; ++q) {
+            const int c = hho::imp::locate(P, xy[2 * q], xy[2 * q + 1]);
+            if (c < 0) {
+                ctx->err = "receiver " + std::to_string(q) + " lies outside the mesh";
+                return HHO_ERR_ARG;
             }
-    }
-    release(ctx, ctx->rec_idx);
-    release(ctx, ctx->rec_coef);
-    ctx->rec_idx = nullptr;
-    ctx->rec_coef = nullptr;
-    ctx->n_rec = 0;
-    ctx->last_steps = 0;
-    if (n > 0) {
-        hho_status st = dev_alloc(ctx, &ctx->rec_idx, idx.size());
-        if (st != HHO_OK) return st;
-        st = dev_alloc(ctx, &ctx->rec_coef, coef.size());
-        if (st != HHO_OK) return st;
-        SCK(hipMemcpyAsync(ctx->rec_idx, idx.data(), idx.size() * sizeof(long long), hipMemcpyHostToDevice, ctx->stream));
-        SCK(hipMemcpyAsync(ctx->rec_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-        SCK(hipStreamSynchronize(ctx->stream));
-    }
-    ctx->n_rec = n;
-    return HHO_OK;
+            if (field[q] != (int)P.medium[c] || (field[q] != 0 && field[q] != 1)) {
+                ctx->err = "receiver " + std::to_string(q) + ": field 0 (p) needs a fluid cell, field 1 (v) a solid one";
+                return HHO_ERR_ARG;
+            }
+            hho::imp::eval_basis(P, c, xy[2 * q], xy[2 * q + 1], phi.data());
+            const auto &g = P.groups[P.cell_group[c]];
+            const int i = P.cell_index[c];
+            for (int comp = 0; comp < (field[q] == 0 ? 1 : 2); ++comp)
+                for (int a = 0; a < Np; ++a) {
+                    idx[((size_t)2 * q + comp) * Np + a] = g.vec_off + (int64_t)(comp * Np + a) * g.n + i;
+                    coef[((size_t)2 * q + comp) * Np + a] = phi[a];
+                }
+        }
+        release(ctx, ctx->rec_idx);
+        release(ctx, ctx->rec_coef);
+        ctx->rec_idx = nullptr;
+        ctx->rec_coef = nullptr;
+        ctx->n_rec = 0;
+        ctx->last_steps = 0;
+        if (n > 0) {
+            hho_status st = dev_alloc(ctx, &ctx->rec_idx, idx.size());
+            if (st != HHO_OK) return st;
+            st = dev_alloc(ctx, &ctx->rec_coef, coef.size());
+            if (st != HHO_OK) return st;
+            SCK(hipMemcpyAsync(ctx->rec_idx, idx.data(), idx.size() * sizeof(long long), hipMemcpyHostToDevice, ctx->stream));
+            SCK(hipMemcpyAsync(ctx->rec_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+            SCK(hipStreamSynchronize(ctx->stream));
+        }
+        ctx->n_rec = n;
+        return HHO_OK;
+    });
 }
 
 hho_status hho_sdirk_get_traces(hho_sdirk *ctx, double *out) {
-    if (!ctx || !out) return HHO_ERR_ARG;
-    if (ctx->n_rec == 0 || ctx->last_steps == 0) return HHO_OK;
-    SCK(hipSetDevice(ctx->device));
-    SCK(hipMemcpyAsync(out, ctx->traces, (size_t)ctx->last_steps * ctx->n_rec * 2 * sizeof(double),
-                       hipMemcpyDeviceToHost, ctx->stream));
-    SCK(hipStreamSynchronize(ctx->stream));
-    return HHO_OK;
+    return guarded(ctx ? &const_cast<hho_sdirk *>(ctx)->err : &g_sdirk_error, [&]() -> hho_status {
+        if (!ctx || !out) return HHO_ERR_ARG;
+        if (ctx->n_rec == 0 || ctx->last_steps == 0) return HHO_OK;
+        SCK(hipSetDevice(ctx->device));
+        SCK(hipMemcpyAsync(out, ctx->traces, (size_t)ctx->last_steps * ctx->n_rec * 2 * sizeof(double),
+                           hipMemcpyDeviceToHost, ctx->stream));
+        SCK(hipStreamSynchronize(ctx->stream));
+        return HHO_OK;
+    });
 }
 
 hho_status hho_sdirk_energy(hho_sdirk *ctx, double *E) {
-    if (!ctx || !E) return HHO_ERR_ARG;
-    SCK(hipSetDevice(ctx->device));
-    const long long nd = ctx->plan.n_dof;
-    const int nblk = std::min<int>(kDotBlocks, std::max<int>(1, (int)grid_for(nd)));
-    hipLaunchKernelGGL(k_energy, dim3(nblk), dim3(kThreads), 0, ctx->stream, ctx->gvec, nd, ctx->U, ctx->mat, ctx->part);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, ctx->stream, nblk, ctx->part, ctx->sc, (int)F_TRUE,
-                       ctx->partA, 0);
-    SCK(hipGetLastError());
-    SCK(hipMemcpyAsync(ctx->h_sc, ctx->sc, kNumScalars * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    SCK(hipStreamSynchronize(ctx->stream));
-    *E = ctx->h_sc[S_TRR];
-    return HHO_OK;
+    return guarded(ctx ? &const_cast<hho_sdirk *>(ctx)->err : &g_sdirk_error, [&]() -> hho_status {
+        if (!ctx || !E) return HHO_ERR_ARG;
+        SCK(hipSetDevice(ctx->device));
+        const long long nd = ctx->plan.n_dof;
+        const int nblk = std::min<int>(kDotBlocks, std::max<int>(1, (int)grid_for(nd)));
+        hipLaunchKernelGGL(k_energy, dim3(nblk), dim3(kThreads), 0, ctx->stream, ctx->gvec, nd, ctx->U, ctx->mat, ctx->part);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, ctx->stream, nblk, ctx->part, ctx->sc, (int)F_TRUE,
+                           ctx->partA, 0);
+        SCK(hipGetLastError());
+        SCK(hipMemcpyAsync(ctx->h_sc, ctx->sc, kNumScalars * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        SCK(hipStreamSynchronize(ctx->stream));
+        *E = ctx->h_sc[S_TRR];
+        return HHO_OK;
+    });
 }
 
 hho_status hho_sdirk_footprint(const hho_sdirk *ctx, int64_t *sizes) {
-    if (!ctx || !sizes) return HHO_ERR_ARG;
-    const auto &P = ctx->plan;
-    sizes[0] = P.n_dof;
-    sizes[1] = P.n_fdof;
-    sizes[2] = (int64_t)P.S_val.size();
-    sizes[3] = (int64_t)P.P_val.size();
-    sizes[4] = (int64_t)(P.mats.size() + P.wmat.size());
-    sizes[5] = P.n_slot;
-    sizes[6] = ctx->n_shared_cols;
-    return HHO_OK;
+    return guarded(ctx ? &const_cast<hho_sdirk *>(ctx)->err : &g_sdirk_error, [&]() -> hho_status {
+        if (!ctx || !sizes) return HHO_ERR_ARG;
+        const auto &P = ctx->plan;
+        sizes[0] = P.n_dof;
+        sizes[1] = P.n_fdof;
+        sizes[2] = (int64_t)P.S_val.size();
+        sizes[3] = (int64_t)P.P_val.size();
+        sizes[4] = (int64_t)(P.mats.size() + P.wmat.size());
+        sizes[5] = P.n_slot;
+        sizes[6] = ctx->n_shared_cols;
+        return HHO_OK;
+    });
 }
 
 hho_status hho_sdirk_stats(const hho_sdirk *ctx, int64_t *solves, int64_t *iterations, double *max_rel_residual) {
-    if (!ctx) return HHO_ERR_ARG;
-    if (solves) *solves = ctx->solves;
-    if (iterations) *iterations = ctx->iterations;
-    if (max_rel_residual) *max_rel_residual = ctx->max_res;
-    return HHO_OK;
+    return guarded(ctx ? &const_cast<hho_sdirk *>(ctx)->err : &g_sdirk_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (solves) *solves = ctx->solves;
+        if (iterations) *iterations = ctx->iterations;
+        if (max_rel_residual) *max_rel_residual = ctx->max_res;
+        return HHO_OK;
+    });
 }
 
 hho_status hho_sdirk_inspect_sizes(const hho_mesh *mesh, const hho_sdirk_params *prm, int64_t *sizes) {
-    g_sdirk_error.clear();
-    if (!sizes) return HHO_ERR_ARG;
-    hho::imp::Plan P;
-    int code = 0;
-    std::string msg = build_plan(mesh, prm, P, &code);
-    if (!msg.empty()) {
-        g_sdirk_error = msg;
-        return (hho_status)code;
-    }
-    sizes[0] = P.n_dof;
-    sizes[1] = P.n_fdof;
-    sizes[2] = (int64_t)P.S_val.size();
-    sizes[3] = P.n_faces;
-    sizes[4] = (int64_t)P.groups.size();
-    return HHO_OK;
+    return guarded(&g_sdirk_error, [&]() -> hho_status {
+        g_sdirk_error.clear();
+        if (!sizes) return HHO_ERR_ARG;
+        hho::imp::Plan P;
+        int code = 0;
+        std::string msg = build_plan(mesh, prm, P, &code);
+        if (!msg.empty()) {
+            g_sdirk_error = msg;
+            return (hho_status)code;
+        }
+        sizes[0] = P.n_dof;
+        sizes[1] = P.n_fdof;
+        sizes[2] = (int64_t)P.S_val.size();
+        sizes[3] = P.n_faces;
+        sizes[4] = (int64_t)P.groups.size();
+        return HHO_OK;
+    });
 }
 
 hho_status hho_sdirk_inspect_face_matrix(const hho_mesh *mesh, const hho_sdirk_params *prm, int32_t *ptr, int32_t *col,
                                          double *val, int32_t *face) {
-    g_sdirk_error.clear();
-    hho::imp::Plan P;
-    int code = 0;
-    std::string msg = build_plan(mesh, prm, P, &code);
-    if (!msg.empty()) {
-        g_sdirk_error = msg;
-        return (hho_status)code;
-    }
-    if (ptr) std::copy(P.S_ptr.begin(), P.S_ptr.end(), ptr);
-    if (col) std::copy(P.S_col.begin(), P.S_col.end(), col);
-    if (val) std::copy(P.S_val.begin(), P.S_val.end(), val);
-    if (face) std::copy(P.fdof_face.begin(), P.fdof_face.end(), face);
-    return HHO_OK;
+    return guarded(&g_sdirk_error, [&]() -> hho_status {
+        g_sdirk_error.clear();
+        hho::imp::Plan P;
+        int code = 0;
+        std::string msg = build_plan(mesh, prm, P, &code);
+        if (!msg.empty()) {
+            g_sdirk_error = msg;
+            return (hho_status)code;
+        }
+        if (ptr) std::copy(P.S_ptr.begin(), P.S_ptr.end(), ptr);
+        if (col) std::copy(P.S_col.begin(), P.S_col.end(), col);
+        if (val) std::copy(P.S_val.begin(), P.S_val.end(), val);
+        if (face) std::copy(P.fdof_face.begin(), P.fdof_face.end(), face);
+        return HHO_OK;
+    });
 }
 
 }  // extern "C"
