@@ -454,6 +454,41 @@ def run_cfl(k, n=32, shots=32, delta=0.01, eps=0.05):
                 speedup=t_seq / t_batched, same_bracket=(seq_ns, seq_nu) == (ns, nu))
 
 
+ETA_GRID = {"fluid": (0.2, 0.4, 0.6, 0.7, 0.8, 0.9, 1.0, 1.2, 1.5, 2.0),
+            "solid": (0.5, 0.8, 1.0, 1.25, 1.4, 1.5, 1.6, 1.75, 2.0, 2.5, 3.0)}
+
+
+def run_eta_sweep(n=16, shots=32, delta=0.02, eps=0.05, ks=(1, 2, 3)):
+    """CFL* as a function of the stabilisation weight (Sec. 5.1, Figure CFL_decoupled): pure
+    acoustic (rho = c = 1) and pure elastic (rho = 1, cP = sqrt 3, cS = 1) unit squares of n x n
+    quads, ERK(4), Algorithm algo_CFL by hho_cfl_search (T_f = 1, `shots` candidates per launch,
+    step-count decrement delta, energy criterion eps) from a seeded random state, for every eta on
+    the grid; CFL* = c dt / h at the last stable step count.  The paper finds the maximisers
+    eta^f = 0.8 and eta^s = 1.5."""
+    from paper_2505_15771_amd import Engine
+    out = dict(workload="CFL* vs stabilisation weight (Figure CFL_decoupled), unit square %dx%d quads, ERK(4)" % (n, n),
+               results=[])
+    t0 = time.perf_counter()
+    for medium, code, c in (("fluid", M.FLUID, 1.0), ("solid", M.SOLID, np.sqrt(3.0))):
+        mesh = M.with_materials(M.single_medium(n, code))
+        for k in ks:
+            curve = []
+            for eta in ETA_GRID[medium]:
+                kw = dict(eta_f=eta) if medium == "fluid" else dict(eta_s=eta)
+                e = Engine(mesh, k, n_shots=shots, **kw)
+                U0 = M.random_state(np.full(1, e.n_dof), 9100 + k)
+                for sh in range(shots):
+                    e.set_state(U0, shot=sh)
+                n_start = int(np.ceil(1.0 / (0.25 * e.dt_cfl(1.0))))
+                ns, nu, tried = e.cfl_search(1.0, n_start, delta, eps)
+                e.close()
+                curve.append(dict(eta=eta, cfl=c * n / ns if ns else None, n_stable=ns, n_unstable=nu))
+            best = max((r for r in curve if r["cfl"]), key=lambda r: r["cfl"])
+            out["results"].append(dict(medium=medium, k=k, curve=curve, eta_best=best["eta"], cfl_best=best["cfl"]))
+    out["run_s"] = time.perf_counter() - t0
+    return out
+
+
 def run_batch(steps=200, warmup=4):
     """Sixteen hybrid meshes of 20k-300k cells (k = 1, 2, 3 in turn), four Ricker shots each at
     seeded positions, float32 stepping with the float64 energy check, all advanced by one batch
@@ -550,7 +585,8 @@ def main():
     ap.add_argument("--shots", type=int, default=1)
     ap.add_argument("--variants", type=int, default=1, help="also time the float64 / k=3 / batched variants")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--only", choices=("adjoint", "basin", "batch", "paper", "cfl", "precision", "tableaux", "sdirk"),
+    ap.add_argument("--only", choices=("adjoint", "basin", "batch", "paper", "cfl", "precision", "tableaux", "sdirk",
+                                       "eta"),
                     default=None,
                     help="run one extra workload alone and print its JSON line (for profiling)")
     ap.add_argument("--only-steps", type=int, default=200)
@@ -585,6 +621,7 @@ def main():
               "cfl": lambda: [run_cfl(k_) for k_ in (1, 2, 3)],
               "precision": lambda: run_precision(steps=args.only_steps),
               "tableaux": lambda: run_tableaux(steps=args.only_steps),
+              "eta": lambda: run_eta_sweep(),
               "sdirk": lambda: [run_sdirk_bilayer(k_, steps=args.only_steps,
                                                   erk_traces=run_paper_bilayer(k_, sensors=True)["_traces"])
                                 for k_ in (1, 3)]
@@ -634,6 +671,9 @@ def main():
         print("workload", json.dumps(v), file=sys.stderr, flush=True)
         workloads.append(v)
         v = run_tableaux()
+        print("workload", json.dumps(v), file=sys.stderr, flush=True)
+        workloads.append(v)
+        v = run_eta_sweep()
         print("workload", json.dumps(v), file=sys.stderr, flush=True)
         workloads.append(v)
     cpu = cpu_baseline(mesh, args.k) if args.cpu_baseline else None
