@@ -140,6 +140,88 @@ def bilayer_vertical(n, p_split=0.0, seed=0):
     return m
 
 
+def _clip(poly, axis, value, keep_below):
+    """Sutherland-Hodgman clip of an integer polygon by x_axis <= value (keep_below) or >= value.
+    Crossing points are computed exactly (the honeycomb only meets its clip lines at lattice
+    points or along edges)."""
+    out = []
+    n = len(poly)
+    inside = (lambda q: q[axis] <= value) if keep_below else (lambda q: q[axis] >= value)
+    for t in range(n):
+        a, b = poly[t], poly[(t + 1) % n]
+        ia, ib = inside(a), inside(b)
+        if ia:
+            out.append(a)
+        if ia != ib:
+            da, db = a[axis] - value, b[axis] - value
+            num = [a[c] * (db) - b[c] * (da) for c in range(2)]
+            den = db - da
+            q = [num[0] // den if num[0] % den == 0 else None, num[1] // den if num[1] % den == 0 else None]
+            if q[0] is None or q[1] is None:
+                raise ValueError("clip crossing off the lattice")
+            q = tuple(q)
+            if not out or out[-1] != q:
+                out.append(q)
+    # drop repeated vertices
+    res = []
+    for q in out:
+        if not res or res[-1] != q:
+            res.append(q)
+    if len(res) > 1 and res[0] == res[-1]:
+        res.pop()
+    return res
+
+
+def honeycomb_bilayer(X=30):
+    """Regular hexagons (pointy-top) on the CFL geometry: solid for x < 0, fluid for x > 0,
+    x in (-1, 1), y in (0, H) with H the lattice height closest to 1.  Hexagons are built on an
+    integer lattice (centres (2i + j mod 2, 3j), vertices at (c_x, c_y -+ 2), (c_x +- 1, c_y -+ 1)),
+    clipped by the domain and split along x = 0, which all pass through lattice points, then
+    scaled by (1/X, 1/(sqrt(3) X)) so that every hexagon is regular.  Cells cut by the boundary or
+    the interface are quadrilaterals or pentagons.  X must be even."""
+    if X % 2:
+        raise ValueError("X must be even")
+    J = max(1, int(round(X / np.sqrt(3.0))))
+    Y = 3 * J
+    cells = []
+    for j in range(-1, J + 2):
+        for cx in range(-X - 2, X + 3):
+            if (cx - j) % 2:
+                continue
+            cy = 3 * j
+            hexv = [(cx, cy - 2), (cx + 1, cy - 1), (cx + 1, cy + 1), (cx, cy + 2), (cx - 1, cy + 1), (cx - 1, cy - 1)]
+            P = hexv
+            for axis, value, below in ((0, X, True), (0, -X, False), (1, Y, True), (1, 0, False)):
+                if len(P) < 3:
+                    break
+                P = _clip(P, axis, value, below)
+            if len(P) < 3:
+                continue
+            for half in (_clip(P, 0, 0, True), _clip(P, 0, 0, False)):
+                if len(half) < 3:
+                    continue
+                area2 = sum(half[t][0] * half[(t + 1) % len(half)][1] - half[(t + 1) % len(half)][0] * half[t][1]
+                            for t in range(len(half)))
+                if area2 > 0:
+                    cells.append(half)
+    ids = {}
+    for c in cells:
+        for q in c:
+            ids.setdefault(q, len(ids))
+    sx = 1.0 / X
+    sy = sx / np.sqrt(3.0)
+    xy = np.empty((len(ids), 2))
+    for q, v in ids.items():
+        xy[v] = (q[0] * sx, q[1] * sy)
+    cell_ptr = np.zeros(len(cells) + 1, dtype=np.int32)
+    cell_ptr[1:] = np.cumsum([len(c) for c in cells])
+    cell_vtx = np.fromiter((ids[q] for c in cells for q in c), dtype=np.int32, count=int(cell_ptr[-1]))
+    m = dict(xy=xy, cell_ptr=cell_ptr, cell_vtx=cell_vtx, h=float(np.sqrt(2.0 * np.sqrt(3.0)) / X))
+    bc = _barycentres(m)
+    m["medium"] = np.where(bc[:, 0] > 0.0, FLUID, SOLID).astype(np.uint8)
+    return m
+
+
 def with_materials(mesh, rho_f=1.0, c_f=1.0, rho_s=1.0, cp_s=np.sqrt(3.0), cs_s=1.0,
                    perturb=0.0, seed=None):
     """Attach per-cell (rho, a, b).  Each physical parameter (rho, c for fluid

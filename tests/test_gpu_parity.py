@@ -320,3 +320,22 @@ def test_mirrored_mesh(dtype, tol):
     say("symmetry defect", worst / scale)
     assert worst <= (1e-12 if dtype == "f64" else 1e-5) * scale
     e.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("dtype,tol", [("f64", TOL64), ("f32", 1e-5)])
+def test_honeycomb_mesh(k, dtype, tol):
+    """Regular hexagons (six faces per cell) with pentagons and quadrilaterals where the domain
+    boundary and the fluid-solid interface x = 0 cut them: ERK(4) from a random state against the
+    oracle."""
+    say("case: honeycomb k=%d %s" % (k, dtype))
+    mesh = M.with_materials(M.honeycomb_bilayer(8), perturb=0.1, seed=41)
+    o = oracle(mesh, k)
+    e = engine(mesh, k, dtype=dtype)
+    U0 = np.random.default_rng(40 + k).standard_normal(o.ndof)
+    dt = 0.3 * e.dt_cfl(1.0)
+    e.set_state(U0)
+    e.erk_step(0.0, dt, 10)
+    err = rel(e.get_state(), o.erk(U0, 0.0, dt, 10))
+    say("rel L2 =", err)
+    assert err < tol

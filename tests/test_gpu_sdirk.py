@@ -238,3 +238,21 @@ def test_receiver_traces_parity():
     with pytest.raises(HHOError):
         e.set_receivers([[0.3, 0.2]], [0])    # p receiver in the solid
     e.close()
+
+
+def test_honeycomb_parity():
+    """SDIRK(3,4), mixed order, on the hexagon bilayer (six-face cells, cut cells on the boundary
+    and along the interface)."""
+    from oracle.implicit import ImplicitOracle
+    from paper_2505_15771_amd import SdirkEngine
+    say("case: sdirk honeycomb")
+    m = M.with_materials(M.honeycomb_bilayer(6), perturb=0.1, seed=91)
+    io = ImplicitOracle(m, 2)
+    e = SdirkEngine(m, 2, 0.03, stages=3, tol=1e-14)
+    U0 = np.random.default_rng(92).standard_normal(io.ndof)
+    e.set_state(U0)
+    e.step(0.0, 3)
+    err = rel(e.get_state(), io.sdirk(U0, 0.0, 0.03, 3, s=3))
+    say("  rel L2", err)
+    assert err < TOL
+    e.close()

@@ -484,3 +484,28 @@ def test_mirror_symmetry():
         scale = max(scale, float(np.max(np.abs(a))))
     assert scale > 1e-3
     assert worst <= 1e-12 * scale
+
+
+def test_honeycomb_mesh_geometry():
+    """The hexagon bilayer generator: a conforming mesh (every edge in at most two cells, traversed
+    in opposite directions: the oracle's face matching accepts it), its cells tile the rectangle
+    (-1, 1) x (0, H) exactly, interior hexagons are regular (six equal edges), the interface x = 0
+    is made of faces, and the fluid lies on the right."""
+    m = M.honeycomb_bilayer(12)
+    mm = M.with_materials(m)
+    o = Oracle(mm, 1)
+    fv, fc, tag = o.face_info()
+    xy, ptr, vtx = m["xy"], m["cell_ptr"], m["cell_vtx"]
+    H = xy[:, 1].max()
+    area = 0.0
+    for c in range(len(ptr) - 1):
+        P = xy[vtx[ptr[c]:ptr[c + 1]]]
+        area += 0.5 * (np.dot(P[:, 0], np.roll(P[:, 1], -1)) - np.dot(P[:, 1], np.roll(P[:, 0], -1)))
+        if len(P) == 6:
+            L = np.hypot(*(np.roll(P, -1, axis=0) - P).T)
+            assert np.ptp(L) < 1e-12 * L.max()
+    assert abs(area - 2.0 * H) < 1e-12 and abs(H - 1.0) < 0.05
+    gam = np.flatnonzero(tag == 2)
+    assert len(gam) > 0 and np.abs(xy[fv[gam]][:, :, 0]).max() < 1e-15
+    bc = np.array([xy[vtx[ptr[c]:ptr[c + 1]]].mean(axis=0) for c in range(len(ptr) - 1)])
+    assert np.all((bc[:, 0] > 0) == (m["medium"] == M.FLUID))
