@@ -454,6 +454,49 @@ def run_cfl(k, n=32, shots=32, delta=0.01, eps=0.05):
                 speedup=t_seq / t_batched, same_bracket=(seq_ns, seq_nu) == (ns, nu))
 
 
+PAPER_RATIO_GEO = {  # Table tab::ratio_geo: CFL* (triangles, squares, hexagons) per (k, s)
+    (1, 2): (0.191, 0.205, 0.264), (1, 3): (0.238, 0.253, 0.329), (1, 4): (0.265, 0.282, 0.363),
+    (2, 2): (0.106, 0.099, 0.136), (2, 3): (0.133, 0.123, 0.170), (2, 4): (0.147, 0.138, 0.188),
+    (3, 2): (0.072, 0.063, 0.082), (3, 3): (0.090, 0.079, 0.102), (3, 4): (0.100, 0.087, 0.115)}
+
+
+def run_cfl_geometry(n=16, shots=32, delta=0.01, eps=0.05, stab_speed=0):
+    """CFL* on triangles, squares and hexagons (Table tab::ratio_geo) by hho_cfl_search on the
+    two-material CFL geometry: 2n x n squares of side h = 1/n, the same squares cut into triangles
+    (h = side of the generating square), and regular hexagons of about the same area (h = square
+    root of the hexagon area), ERK(2/3/4), k = 1..3, T_f = 1, from a seeded random state;
+    CFL* = sqrt(3) dt / h at the last stable step count, with the ratios to the triangles beside
+    the paper's.  stab_speed selects c^s in the solid weight (0: c_P, 1: c_S)."""
+    from paper_2505_15771_amd import Engine
+    X = 2 * int(round(0.5 * n * np.sqrt(2.0 * np.sqrt(3.0))))
+    hexm = M.honeycomb_bilayer(X)
+    meshes = (("triangles", M.with_materials(M.bilayer_vertical(n, p_split=1.0, seed=5)), 1.0 / n),
+              ("squares", M.with_materials(M.bilayer_vertical(n)), 1.0 / n),
+              ("hexagons", M.with_materials(hexm), hexm["h"]))
+    out = dict(workload="CFL* per cell shape (Table tab::ratio_geo), two-material CFL geometry, h ~ 1/%d, "
+                        "tau^s with %s" % (n, "c_P" if stab_speed == 0 else "c_S"), results=[])
+    t0 = time.perf_counter()
+    for k in (1, 2, 3):
+        for s in (2, 3, 4):
+            row = {}
+            for name, mesh, h in meshes:
+                e = Engine(mesh, k, rk_stages=s, n_shots=shots, stab_speed=stab_speed)
+                U0 = M.random_state(np.full(1, e.n_dof), 9200 + k)
+                for sh in range(shots):
+                    e.set_state(U0, shot=sh)
+                ns, nu, _ = e.cfl_search(1.0, int(np.ceil(1.0 / (0.5 * e.dt_cfl(1.0)))), delta, eps)
+                e.close()
+                row[name] = np.sqrt(3.0) / ns / h if ns else None
+            paper = PAPER_RATIO_GEO[(k, s)]
+            out["results"].append(dict(
+                k=k, stages=s, cfl=row,
+                ratio=[row[m] / row["triangles"] if row[m] and row["triangles"] else None
+                       for m in ("triangles", "squares", "hexagons")],
+                paper_cfl=paper, paper_ratio=[v / paper[0] for v in paper]))
+    out["run_s"] = time.perf_counter() - t0
+    return out
+
+
 ETA_GRID = {"fluid": (0.2, 0.4, 0.6, 0.7, 0.8, 0.9, 1.0, 1.2, 1.5, 2.0),
             "solid": (0.5, 0.8, 1.0, 1.25, 1.4, 1.5, 1.6, 1.75, 2.0, 2.5, 3.0)}
 
@@ -586,7 +629,7 @@ def main():
     ap.add_argument("--variants", type=int, default=1, help="also time the float64 / k=3 / batched variants")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--only", choices=("adjoint", "basin", "batch", "paper", "cfl", "precision", "tableaux", "sdirk",
-                                       "eta"),
+                                       "eta", "geometry"),
                     default=None,
                     help="run one extra workload alone and print its JSON line (for profiling)")
     ap.add_argument("--only-steps", type=int, default=200)
@@ -622,6 +665,7 @@ def main():
               "precision": lambda: run_precision(steps=args.only_steps),
               "tableaux": lambda: run_tableaux(steps=args.only_steps),
               "eta": lambda: run_eta_sweep(),
+              "geometry": lambda: [run_cfl_geometry(), run_cfl_geometry(stab_speed=1)],
               "sdirk": lambda: [run_sdirk_bilayer(k_, steps=args.only_steps,
                                                   erk_traces=run_paper_bilayer(k_, sensors=True)["_traces"])
                                 for k_ in (1, 3)]
@@ -676,6 +720,10 @@ def main():
         v = run_eta_sweep()
         print("workload", json.dumps(v), file=sys.stderr, flush=True)
         workloads.append(v)
+        for ss in (0, 1):
+            v = run_cfl_geometry(stab_speed=ss)
+            print("workload", json.dumps(v), file=sys.stderr, flush=True)
+            workloads.append(v)
     cpu = cpu_baseline(mesh, args.k) if args.cpu_baseline else None
     # speed-ups over float64 single-shot stepping of the same workload on the same GPU
     speedups = {}
