@@ -453,6 +453,13 @@ __global__ void __launch_bounds__(kThreads) k_face_rows(int n, const double *__r
     Ei[q] = bF[q] - res[q] / dsc[q];   // res = D (b - S x)
 }
 
+// out = ca a + cb b
+__global__ void __launch_bounds__(kThreads) k_axpby(int n, double ca, const double *__restrict__ a, double cb,
+                                                    const double *__restrict__ b, double *__restrict__ out) {
+    const int q = blockIdx.x * kThreads + threadIdx.x;
+    if (q < n) out[q] = ca * a[q] + cb * b[q];
+}
+
 __global__ void __launch_bounds__(kThreads) k_copy(long long n, const double *__restrict__ a, double *__restrict__ b) {
     const long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (q < n) b[q] = a[q];
@@ -533,6 +540,10 @@ struct hho_sdirk {
     int last_steps = 0;
     int64_t solves = 0, iterations = 0;
     int64_t n_shared_cols = 0;  // column indices stored for the face matrix
+    // face solutions of every stage at the last two steps (initial guesses by extrapolation)
+    double *xhist = nullptr;     // [stage][2][n_fdof], slot = step parity
+    int64_t step_count = 0;      // steps since the state was set
+    int hist_valid = 0;          // steps of history available (0, 1, 2)
     double max_res = 0.0;
 };
 
@@ -800,7 +811,19 @@ hho_status one_step(hho_sdirk *ctx, double t) {
                                ctx->cf, ctx->E, i, i > 0 ? P.A[i][0] / ast : 0.0, i > 1 ? P.A[i][1] / ast : 0.0, ctx->dsc,
                                ctx->bF, ctx->rhs);
         SCK(hipGetLastError());
+        // initial guess: the face solution of this stage at the previous steps, extrapolated
+        // linearly from two steps when there are two, else the last one, else the previous stage's
+        const int nf = P.n_fdof;
+        double *h_last = ctx->xhist + ((size_t)i * 2 + ((ctx->step_count - 1) & 1)) * nf;
+        double *h_prev = ctx->xhist + ((size_t)i * 2 + (ctx->step_count & 1)) * nf;
+        if (nf > 0 && ctx->hist_valid >= 2)
+            hipLaunchKernelGGL(k_axpby, dim3(grid_for(nf)), dim3(kThreads), 0, ctx->stream, nf, 2.0, h_last, -1.0, h_prev,
+                               ctx->x);
+        else if (nf > 0 && ctx->hist_valid == 1)
+            hipLaunchKernelGGL(k_copy, dim3(grid_for(nf)), dim3(kThreads), 0, ctx->stream, (long long)nf, h_last, ctx->x);
         SST(face_solve(ctx, ctx->E + (size_t)i * P.n_fdof));
+        if (nf > 0)
+            hipLaunchKernelGGL(k_copy, dim3(grid_for(nf)), dim3(kThreads), 0, ctx->stream, (long long)nf, ctx->x, h_prev);
         // cell recovery and the cell rows of K U^{n,i}
         hipLaunchKernelGGL(k_recover, dim3(gv), dim3(kThreads), 0, ctx->stream, ctx->gvec, nd, ctx->wmat, ctx->slot_dof,
                            ctx->x, ctx->dsc, ctx->gv, ctx->U);
@@ -815,6 +838,8 @@ hho_status one_step(hho_sdirk *ctx, double t) {
                        ctx->U);
     SCK(hipGetLastError());
     SST(add_sources(ctx, ctx->U, t, dt, s, P.b, P.c, 1));
+    ctx->step_count += 1;
+    ctx->hist_valid = std::min(ctx->hist_valid + 1, 2);
     return HHO_OK;
 }
 
@@ -957,6 +982,7 @@ hho_status hho_sdirk_setup(const hho_mesh *mesh, const hho_sdirk_params *prm, hh
         AL(ctx->cf, (size_t)P.n_slot);
         AL(ctx->E, nf * P.stages);
         AL(ctx->bF, nf);
+    AL(ctx->xhist, nf * 2 * P.stages);
         AL(ctx->rhs, nf);
         AL(ctx->x, nf);
         AL(ctx->r, nf);
@@ -1031,6 +1057,8 @@ hho_status hho_sdirk_set_state(hho_sdirk *ctx, const double *U, int32_t on_devic
         to_group(P, ext.data(), grp);
         SCK(hipMemcpyAsync(ctx->U, grp.data(), P.n_dof * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
         SCK(hipMemsetAsync(ctx->x, 0, std::max<size_t>(P.n_fdof, 1) * sizeof(double), ctx->stream));
+        ctx->hist_valid = 0;
+        ctx->step_count = 0;
         SCK(hipStreamSynchronize(ctx->stream));
         return HHO_OK;
     });
