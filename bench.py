@@ -148,26 +148,32 @@ def run_variant(mesh, k, dtype, shots, steps, warmup):
                 tuning=dict(lanes=lanes, nt_stores=bool(flags & 1)))
 
 
-def run_adjoint(k, dtype, steps=1000, ckpt=50):
-    """The adjoint workload: 128 x 128 hybrid mesh (seed 5001), k = 2, one Ricker source, 32
-    receivers; misfit gradient by hho_adjoint_step over `steps` steps with checkpoints every
-    `ckpt`, against the same number of forward steps."""
+def run_adjoint(k, dtype, steps=1000, ckpt=50, shots=1):
+    """The adjoint workload: 128 x 128 hybrid mesh (seed 5001), k = 2, one Ricker source per shot
+    (the first at (0.5, 0.25), the others at seeded positions in the solid), 32 receivers;
+    misfit gradient (summed over the shots) by hho_adjoint_step over `steps` steps with
+    checkpoints every `ckpt`, against the same number of forward steps."""
     import torch
     from paper_2505_15771_amd import Engine
     mesh = M.adjoint_square(128)
     rec_xy, rec_f = M.adjoint_receivers()
-    eng = Engine(mesh, k, dtype=dtype)
-    eng.set_sources(0, [[0.5, 0.25]], [[0.0, 1.0]], 10.0, 0.12, 1.0)
+    eng = Engine(mesh, k, dtype=dtype, n_shots=shots)
+    pos = np.concatenate([[[0.5, 0.25]], M.shot_positions(max(shots - 1, 0), 5100)])[:shots]
+    for sh in range(shots):
+        eng.set_sources(sh, [pos[sh]], [[0.0, 1.0]], 10.0, 0.12, 1.0)
     eng.set_receivers(rec_xy, rec_f)
     dt = eng.dt_cfl(0.5)
-    d_obs = np.zeros((1, steps, len(rec_f), 2))
+    d_obs = np.zeros((shots, steps, len(rec_f), 2))
+    zero = np.zeros(eng.n_dof)
     eng.adjoint(0.0, dt, 20, d_obs[:, :20], ckpt)  # warm-up (workspace allocation)
-    eng.set_state(np.zeros(eng.n_dof))
+    for sh in range(shots):
+        eng.set_state(zero, shot=sh)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     J, _ = eng.adjoint(0.0, dt, steps, d_obs, ckpt)
     t_adj = time.perf_counter() - t0
-    eng.set_state(np.zeros(eng.n_dof))
+    for sh in range(shots):
+        eng.set_state(zero, shot=sh)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     eng.erk_step(0.0, dt, steps)
@@ -175,9 +181,10 @@ def run_adjoint(k, dtype, steps=1000, ckpt=50):
     t_fwd = time.perf_counter() - t0
     cells = int(len(mesh["cell_ptr"]) - 1)
     eng.close()
-    return dict(workload="adjoint 128x128 hybrid, k=%d, %d steps, checkpoints every %d" % (k, steps, ckpt),
-                dtype=dtype, cells=cells, adjoint_ms=t_adj * 1e3, forward_ms=t_fwd * 1e3,
-                ratio=t_adj / t_fwd, finite=bool(np.isfinite(J)))
+    return dict(workload="adjoint 128x128 hybrid, k=%d, %d steps, checkpoints every %d, %d shot%s"
+                         % (k, steps, ckpt, shots, "s" if shots > 1 else ""),
+                dtype=dtype, cells=cells, shots=shots, adjoint_ms=t_adj * 1e3, forward_ms=t_fwd * 1e3,
+                adjoint_ms_per_shot=t_adj * 1e3 / shots, ratio=t_adj / t_fwd, finite=bool(np.isfinite(J)))
 
 
 def run_basin(dtype, steps=100, warmup=5):
@@ -657,7 +664,7 @@ def main():
               file=sys.stderr)
         del src, dst
     if args.only:
-        fn = {"adjoint": lambda: run_adjoint(2, args.dtype, steps=args.only_steps, ckpt=50),
+        fn = {"adjoint": lambda: run_adjoint(2, args.dtype, steps=args.only_steps, ckpt=50, shots=args.shots),
               "basin": lambda: run_basin(args.dtype, steps=args.only_steps),
               "batch": lambda: run_batch(steps=args.only_steps),
               "paper": lambda: [run_paper_bilayer(1), run_paper_bilayer(3)],
@@ -686,8 +693,8 @@ def main():
                                                        "gbs", "frac", "moved_gbs", "tuning")})
     adjoint, workloads = [], []
     if args.variants:
-        for dt_ in ("f64", "f32"):
-            v = run_adjoint(2, dt_)
+        for dt_, sh_ in (("f64", 1), ("f32", 1), ("f32", 8)):
+            v = run_adjoint(2, dt_, shots=sh_)
             print("adjoint", json.dumps(v), file=sys.stderr, flush=True)
             adjoint.append(v)
         for dt_ in ("f32", "f64"):
