@@ -222,6 +222,26 @@ def honeycomb_bilayer(X=30):
     return m
 
 
+def perturbed_square(n, amount=0.15, p_split=0.5, seed=0, interface_y=0.5):
+    """unit_square(n, p_split) with every vertex moved by a seeded uniform offset of up to
+    amount * h per coordinate, except along the constraints: corners stay, other boundary
+    vertices and vertices on the interface y = interface_y move only along their line.  Every
+    cell then has its own shape (no two cells are translates of each other), like a mesh from an
+    unstructured generator."""
+    m = unit_square(n, p_split=p_split, seed=seed, interface_y=interface_y)
+    h = 1.0 / n
+    rng = np.random.default_rng(seed + 7)
+    xy = m["xy"].copy()
+    d = rng.uniform(-amount * h, amount * h, xy.shape)
+    on_x = (np.abs(xy[:, 0]) < 1e-12) | (np.abs(xy[:, 0] - 1.0) < 1e-12)
+    on_y = (np.abs(xy[:, 1]) < 1e-12) | (np.abs(xy[:, 1] - 1.0) < 1e-12) | (np.abs(xy[:, 1] - interface_y) < 1e-12)
+    d[on_x, 0] = 0.0
+    d[on_y, 1] = 0.0
+    out = dict(m)
+    out["xy"] = xy + d
+    return out
+
+
 def with_materials(mesh, rho_f=1.0, c_f=1.0, rho_s=1.0, cp_s=np.sqrt(3.0), cs_s=1.0,
                    perturb=0.0, seed=None):
     """Attach per-cell (rho, a, b).  Each physical parameter (rho, c for fluid

@@ -339,3 +339,20 @@ def test_honeycomb_mesh(k, dtype, tol):
     err = rel(e.get_state(), o.erk(U0, 0.0, dt, 10))
     say("rel L2 =", err)
     assert err < tol
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_perturbed_vertices_mesh(k):
+    """Every vertex moved at random (no two cells share a shape, so every cell is its own class
+    and group): ERK(4) from a random state against the oracle, float64."""
+    say("case: perturbed-vertex mesh k=%d" % k)
+    mesh = M.with_materials(M.perturbed_square(6, seed=11), perturb=0.1, seed=12)
+    o = oracle(mesh, k)
+    e = engine(mesh, k)
+    U0 = np.random.default_rng(50 + k).standard_normal(o.ndof)
+    dt = 0.3 * e.dt_cfl(1.0)
+    e.set_state(U0)
+    e.erk_step(0.0, dt, 8)
+    err = rel(e.get_state(), o.erk(U0, 0.0, dt, 8))
+    say("rel L2 =", err)
+    assert err < TOL64
