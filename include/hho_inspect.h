@@ -13,7 +13,8 @@
  *            phi: orthonormal cell basis (see hho.h); psi_i = sqrt((2i+1)/|F|) P_i(xi),
  *            xi in [-1, 1] running along the counter-clockwise direction of the cell.
  *            These are the blocks of eq. rec_a / rec_e / stab (Sec. 3.3) in that basis.
- *   groups   [n_groups][6]: medium, n_faces, table offset, first ic, cells, first block
+ *   groups   [n_groups][6]: medium, n_faces, table offset (0 for a pooled group, see
+ *            hho_inspect_cell_tables), first ic, cells, first block
  *   link     [max_nf][n_ic]: (ic' << 4) | (interface << 3) | j' of the neighbour across
  *            local face j, -1 on the boundary
  *   c0       [max_nf][n_ic]: 1 / (tau_T + tau_T') on same-medium faces,
@@ -43,6 +44,14 @@ hho_status hho_inspect_sizes(const hho_inspect *p, int64_t *sizes);
  * pointer may be NULL to skip that array. */
 hho_status hho_inspect_arrays(const hho_inspect *p, double *tables, int32_t *groups, int32_t *link, double *c0,
                               double *mat, int32_t *ic_of_cell);
+
+/* Class table of every internal cell: ic_tab[n_ic] = offset of its class's table in `tables`
+ * (0 for padding), and pooled[n_groups] = 1 for the groups that hold the cells of small shape
+ * classes (fewer than 32 cells of that shape, on meshes with more than 64 shape classes): their
+ * lanes read the table at their own offset,
+ * laid out with the group's face count (faces beyond a cell's own count hold zeros).  Either
+ * output may be NULL. */
+hho_status hho_inspect_cell_tables(const hho_inspect *p, int32_t *ic_tab, int32_t *pooled);
 
 /* Material derivatives used by the adjoint gradient (hho_adjoint_step), gm[8][n_ic], float64:
  *   fluid (parameters rho, c; kappa = rho c^2, tau = eta / (rho c)):

@@ -65,6 +65,7 @@ struct hho_ctx {
     int32_t *link = nullptr;
     void *c0 = nullptr, *mat = nullptr, *tab = nullptr;
     double *emat = nullptr;
+    int32_t *ic_tab = nullptr;  // [n_ic] class table offset per internal cell
     // launch shapes (Plan::launches) and the one in use
     struct LaunchDev {
         GroupDev *groups = nullptr;
@@ -292,6 +293,8 @@ StageArgs<R> base_args(hho_ctx *ctx) {
     a.c0 = (const R *)ctx->c0;
     a.mat = (const R *)ctx->mat;
     a.tab = (const R *)ctx->tab;
+    a.ic_tab = ctx->ic_tab;
+    a.has_pooled = ctx->plan.has_pooled ? 1 : 0;
     a.groups = ctx->launch[ctx->shape].groups;
     a.blk_group = ctx->launch[ctx->shape].blk_group;
     a.n_ic = ctx->plan.n_ic;
@@ -1012,6 +1015,7 @@ hho_status hho_setup(const hho_mesh *mesh, const hho_params *prm, hho_ctx **out)
         if ((s = copy_in(ctx, ctx->link, P.link)) || (s = copy_in_real(ctx, ctx->c0, P.c0)) ||
             (s = copy_in_real(ctx, ctx->mat, P.mat)) || (s = upload_real(ctx, &ctx->tab, P.tables)) ||
             (s = upload(ctx, &ctx->emat, P.emat)) || (s = upload(ctx, &ctx->map, map)) ||
+            (s = upload(ctx, &ctx->ic_tab, P.ic_tab)) ||
             (s = dalloc(ctx, (void **)&ctx->staging, std::max<size_t>(1, P.n_ext) * 4 * sizeof(double))) ||
             (s = dalloc(ctx, (void **)&ctx->e_now, (size_t)P.S * sizeof(double))) ||
             (s = dalloc(ctx, (void **)&ctx->clock, 2 * sizeof(Clock))))
@@ -1020,7 +1024,7 @@ hho_status hho_setup(const hho_mesh *mesh, const hho_params *prm, hho_ctx **out)
             std::vector<GroupDev> gd;
             for (size_t g = 0; g < P.groups.size(); ++g) {
                 const Group &G = P.groups[g];
-                gd.push_back({G.medium, G.nF, G.tab_off, G.ic_begin, G.ncells, L.blk_begin[g]});
+                gd.push_back({G.medium, G.nF, G.tab_off, G.ic_begin, G.ncells, L.blk_begin[g], G.pooled ? 1 : 0});
             }
             hho_ctx::LaunchDev d;
             d.n_blocks = (int)L.blk_group.size();
@@ -1383,6 +1387,11 @@ hho_status hho_adjoint_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps,
             ctx->err = "adjoint_step: per-shot time-step multipliers are set (hho_set_dt_scale); reset them first";
             return HHO_ERR_ARG;
         }
+        if (ctx->plan.has_pooled) {
+            ctx->err = "adjoint_step: the mesh has more than 64 shape classes and pools the small ones, which the "
+                       "adjoint kernels do not handle";
+            return HHO_ERR_ARG;
+        }
         std::vector<StageCoef> co;
         if (!erk_coefficients(ctx->stages, co)) return HHO_ERR_ARG;
         for (const StageCoef &q : co)
@@ -1742,6 +1751,17 @@ hho_status hho_inspect_sizes(const hho_inspect *p, int64_t *sz) {
         const int64_t v[10] = {P.N, P.F, P.n_ic, P.max_nf, (int64_t)P.groups.size(), (int64_t)P.tables.size(),
                                P.n_cells, P.n_faces, P.cpb, (int64_t)P.blk_group.size()};
         std::memcpy(sz, v, sizeof(v));
+        return HHO_OK;
+    });
+}
+
+hho_status hho_inspect_cell_tables(const hho_inspect *p, int32_t *ic_tab, int32_t *pooled) {
+    return guarded(&g_setup_error, [&]() -> hho_status {
+        if (!p) return HHO_ERR_ARG;
+        const Plan &P = p->plan;
+        if (ic_tab) std::copy(P.ic_tab.begin(), P.ic_tab.end(), ic_tab);
+        if (pooled)
+            for (size_t g = 0; g < P.groups.size(); ++g) pooled[g] = P.groups[g].pooled ? 1 : 0;
         return HHO_OK;
     });
 }

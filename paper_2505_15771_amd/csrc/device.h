@@ -9,7 +9,7 @@
 namespace hho {
 
 struct GroupDev {
-    int medium, nF, tab_off, ic_begin, ncells, blk_begin;
+    int medium, nF, tab_off, ic_begin, ncells, blk_begin, pooled;
 };
 
 constexpr int kMaxN = 10;  // (k+1)(k+2)/2 for k = 3
@@ -49,6 +49,8 @@ struct StageArgs {
     const R *c0;          // [max_nf][n_ic]
     const R *mat;         // [kNumMat][n_ic]
     const R *tab;         // class tables
+    const int32_t *ic_tab;  // [n_ic] table offset of every cell (read by the pooled-group kernels)
+    int has_pooled;         // some groups are pooled: the stage and trace launches come in pairs
     const GroupDev *groups;
     const int32_t *blk_group;
     int n_ic, S, cpb;

@@ -499,9 +499,17 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
     }
 }
 
-template <int K, int NF, typename R, bool STORE, int POL>
+// Class tables: one per group, read through scalar loads; in a pooled group (cells of small
+// shape classes together) each lane finds its class's table at its own offset and reads it
+// through vector loads.
+template <bool POOLED, typename R>
+__device__ __forceinline__ const HHO_CONST R *class_table(const StageArgs<R> &a, const GroupDev &G, int ic) {
+    return POOLED ? uni(a.tab) + a.ic_tab[ic] : uni(a.tab) + G.tab_off;
+}
+
+template <int K, int NF, typename R, bool STORE, int POL, bool POOLED>
 __device__ __forceinline__ void stage_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L, double *e) {
-    const HHO_CONST R *tb = uni(a.tab) + G.tab_off;
+    const HHO_CONST R *tb = class_table<POOLED>(a, G, L.ic);
     const Bufs<R> B = make_bufs(a);
     if (G.medium == kFluid)
         fluid_stage<K, NF, R, STORE, POL>(a, B, tb, G.nF, L, e);
@@ -509,31 +517,35 @@ __device__ __forceinline__ void stage_body(const StageArgs<R> &a, const GroupDev
         solid_stage<K, NF, R, STORE, POL>(a, B, tb, G.nF, L, e);
 }
 
-template <int K, typename R, bool STORE, int POL>
+// With pooled groups a stage is two launches over the same grid: the one for the ordinary groups
+// (POOLED = false, which also advances the clock) and the one for the pooled groups; each
+// workgroup of a launch whose group is of the other kind returns at once.
+template <int K, typename R, bool STORE, int POL, bool POOLED = false>
 __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<R> a) {
-    if (a.last && a.clock_next && blockIdx.x == 0 && threadIdx.x == 0) {
+    if (!POOLED && a.last && a.clock_next && blockIdx.x == 0 && threadIdx.x == 0) {
         Clock c = *a.clock;
         c.step += 1;
         *a.clock_next = c;
     }
     GroupDev G;
     const LaneInfo L = decode_lane(a, G);
+    if ((G.pooled != 0) != POOLED) return;
     const bool want_e = a.last && a.e_part;
     double e = 0.0;
     double *ep = want_e ? &e : nullptr;
     if (L.active) {
         // faces beyond a cell's count carry link -1 and are skipped like boundary faces
-        if (G.nF <= 4) stage_body<K, 4, R, STORE, POL>(a, G, L, ep);
-        else stage_body<K, kMaxFaces, R, STORE, POL>(a, G, L, ep);
+        if (G.nF <= 4) stage_body<K, 4, R, STORE, POL, POOLED>(a, G, L, ep);
+        else stage_body<K, kMaxFaces, R, STORE, POL, POOLED>(a, G, L, ep);
     }
     if (want_e) block_energy(e, a.S, a.cpb, a.e_part);
 }
 
 // Outgoing trace contributions of the state in a.Yin (used once after the state is set).
-template <int K, int NF, typename R>
+template <int K, int NF, typename R, bool POOLED>
 __device__ __forceinline__ void traces_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L) {
     constexpr int N = Dim<K>::N;
-    const HHO_CONST R *tb = uni(a.tab) + G.tab_off;
+    const HHO_CONST R *tb = class_table<POOLED>(a, G, L.ic);
     const Bufs<R> B = make_bufs(a);
     int lk[NF];
     load_links<NF, R>(B, G.nF, L.ic, lk, (R *)nullptr);
@@ -551,13 +563,13 @@ __device__ __forceinline__ void traces_body(const StageArgs<R> &a, const GroupDe
         solid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.boff, v[0], v[1], v[2], v[3], v[4], tau, itau);
 }
 
-template <int K, typename R>
+template <int K, typename R, bool POOLED = false>
 __global__ __launch_bounds__(kBlock) void trace_kernel(StageArgs<R> a) {
     GroupDev G;
     const LaneInfo L = decode_lane(a, G);
-    if (!L.active) return;
-    if (G.nF <= 4) traces_body<K, 4, R>(a, G, L);
-    else traces_body<K, kMaxFaces, R>(a, G, L);
+    if (!L.active || (G.pooled != 0) != POOLED) return;
+    if (G.nF <= 4) traces_body<K, 4, R, POOLED>(a, G, L);
+    else traces_body<K, kMaxFaces, R, POOLED>(a, G, L);
 }
 
 // Energy of the state in a.Yin (Sec. 5.1), float64 partials per block and shot.
@@ -640,6 +652,8 @@ hipError_t launch_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
         hipLaunchKernelGGL((stage_kernel<K, R, false, kNonTemporal>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     else
         hipLaunchKernelGGL((stage_kernel<K, R, false, 0>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    if (a.has_pooled)
+        hipLaunchKernelGGL((stage_kernel<K, R, false, 0, true>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     return hipGetLastError();
 }
 
@@ -652,6 +666,7 @@ hipError_t launch_stage_store(const StageArgs<R> &a, int n_blocks, hipStream_t s
 template <int K, typename R>
 hipError_t launch_traces(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
     hipLaunchKernelGGL((trace_kernel<K, R>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    if (a.has_pooled) hipLaunchKernelGGL((trace_kernel<K, R, true>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     return hipGetLastError();
 }
 

@@ -281,6 +281,16 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
         }
     }
 
+    // on a mesh with many shape classes (e.g. vertices moved at random: every cell its own shape),
+    // the small classes (fewer than kPoolCells cells) are pooled: their tables use the face count
+    // of their pooled group.  A few small classes (hanging nodes, cut cells) keep their groups.
+    for (int c = 0; c < nc; ++c) P.classes[P.cell_class[c]].ncells += 1;
+    const bool pool = (int)P.classes.size() > kPoolMinClasses;
+    for (auto &ci : P.classes) {
+        ci.pooled = pool && ci.ncells < kPoolCells;
+        ci.nF_layout = !ci.pooled ? ci.nF : (ci.nF <= 4 ? std::min(4, P.max_nf) : P.max_nf);
+    }
+
     // per-class tables in the orthonormal bases
     *code = 3;  // HHO_ERR_SINGULAR
     P.basisC.assign(P.classes.size() * N * N, 0.0);
@@ -339,7 +349,8 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
         congr(Dmx, Dx);
         congr(Dmy, Dy);
         // faces: E_j = (phi_b, phi_a)_F, G_j = (phi_a, psi_i)_F in the local (counter-clockwise) face basis
-        std::vector<double> Bx = Dx, By = Dy, Ssum(N * N, 0.0), G(n * N * F, 0.0), nrm(2 * n);
+        const int nl = ci.nF_layout;  // table layout: faces beyond n hold zeros
+        std::vector<double> Bx = Dx, By = Dy, Ssum(N * N, 0.0), G(nl * N * F, 0.0), nrm(2 * nl, 0.0);
         for (int j = 0; j < n; ++j) {
             const double X0 = X[j], Y0 = Y[j], X1 = X[(j + 1) % n], Y1 = Y[(j + 1) % n];
             const double dX = X1 - X0, dY = Y1 - Y0, Ls = std::hypot(dX, dY), Lf = Ls * h;
@@ -423,7 +434,8 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
     std::map<std::pair<int, int>, int> gid;
     std::vector<std::vector<int>> members;
     for (int c = 0; c < nc; ++c) {
-        auto key = std::make_pair((int)medium[c], P.cell_class[c]);
+        const ClassInfo &cc = P.classes[P.cell_class[c]];
+        auto key = cc.pooled ? std::make_pair((int)medium[c], -1 - cc.nF_layout) : std::make_pair((int)medium[c], P.cell_class[c]);
         auto it = gid.find(key);
         int g;
         if (it == gid.end()) {
@@ -431,9 +443,10 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
             gid.emplace(key, g);
             Group G;
             G.medium = medium[c];
-            G.cls = P.cell_class[c];
-            G.nF = P.classes[G.cls].nF;
-            G.tab_off = P.classes[G.cls].offset;
+            G.pooled = cc.pooled;
+            G.cls = cc.pooled ? -1 : P.cell_class[c];
+            G.nF = cc.nF_layout;
+            G.tab_off = cc.pooled ? 0 : cc.offset;
             P.groups.push_back(G);
             members.emplace_back();
         } else {
@@ -508,6 +521,9 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
     }
     P.cell_of_ic.assign(P.n_ic, -1);
     for (int c = 0; c < nc; ++c) P.cell_of_ic[P.ic_of_cell[c]] = c;
+    P.ic_tab.assign(P.n_ic, 0);
+    for (int c = 0; c < nc; ++c) P.ic_tab[P.ic_of_cell[c]] = P.classes[P.cell_class[c]].offset;
+    for (const auto &G : P.groups) P.has_pooled |= G.pooled;
 
     // face links, face-solve coefficients and materials (structure of arrays over internal cells)
     const int nic = P.n_ic;

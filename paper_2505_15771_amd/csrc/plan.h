@@ -12,6 +12,8 @@ namespace hho {
 constexpr int kMaxFaces = 8;     // faces per cell (hanging nodes raise the count)
 constexpr int kBlock = 256;      // largest workgroup (lanes)
 constexpr int kLanesTarget = 64; // preferred lanes per workgroup: one wavefront
+constexpr int kPoolCells = 32;       // shape classes with fewer cells share pooled groups ...
+constexpr int kPoolMinClasses = 64;  // ... when the mesh has more classes than this
 
 enum Medium : int { kFluid = 0, kSolid = 1 };
 
@@ -23,11 +25,17 @@ struct ClassInfo {
     int nF = 0;
     int offset = 0;  // into Plan::tables
     int rep_cell = 0;
+    int ncells = 0;
+    bool pooled = false;  // fewer than kPoolCells cells: its cells go to a pooled group
+    int nF_layout = 0;    // faces in the table layout (pooled classes: the pooled group's count)
 };
 
+// A pooled group holds the cells of small shape classes of one medium and face-count bucket
+// (at most 4 faces, or more): its lanes read their class tables at per-cell offsets (ic_tab).
 struct Group {
     int medium = 0;
-    int cls = 0;
+    int cls = 0;          // -1 for a pooled group
+    bool pooled = false;
     int nF = 0;
     int tab_off = 0;
     int ic_begin = 0;  // first internal cell of the group
@@ -93,6 +101,8 @@ struct Plan {
     std::vector<double> area;      // [n_cells]
     std::vector<double> basisC;    // [n_classes][N][N] orthonormal basis coefficients (lower)
     std::vector<int> cell_class;   // [n_cells]
+    std::vector<int32_t> ic_tab;   // [n_ic] class table offset of every internal cell (0: padding)
+    bool has_pooled = false;
 };
 
 // Returns "" on success, otherwise an error message; *code receives the status code.

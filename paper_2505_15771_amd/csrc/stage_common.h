@@ -219,6 +219,7 @@ __device__ __forceinline__ LaneInfo decode_lane(const StageArgs<R> &a, GroupDev 
     G.ic_begin = gd->ic_begin;
     G.ncells = gd->ncells;
     G.blk_begin = gd->blk_begin;
+    G.pooled = gd->pooled;
     LaneInfo L;
     const int tid = threadIdx.x;
     const int cl = tid / a.S;

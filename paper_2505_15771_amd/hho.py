@@ -83,6 +83,7 @@ EXPORTS = {
     "hho_inspect_sizes": (C.c_int, [C.c_void_p, C.c_void_p]),
     "hho_inspect_arrays": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
     "hho_inspect_grad_coefs": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "hho_inspect_cell_tables": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "hho_inspect_erk": (C.c_int, [C.c_int32, C.c_void_p]),
     "hho_inspect_dt_cfl": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double)]),
     "hho_sdirk_setup": (C.c_int, [C.POINTER(_Mesh), C.POINTER(_SdirkParams), C.POINTER(C.c_void_p)]),
@@ -391,6 +392,9 @@ class Inspect:
                                _ptr(self.mat), _ptr(self.ic_of_cell))
         self.gm = np.zeros((8, self.n_ic))
         lib.hho_inspect_grad_coefs(h, _ptr(self.gm))
+        self.ic_tab = np.zeros(self.n_ic, np.int32)
+        self.pooled = np.zeros(self.n_groups, np.int32)
+        lib.hho_inspect_cell_tables(h, _ptr(self.ic_tab), _ptr(self.pooled))
         self.dt_cfl = {}
         for s in (2, 3, 4):
             dt = C.c_double()

@@ -15,9 +15,10 @@ import numpy as np
 R2 = 1.0 / np.sqrt(2.0)
 
 
-def _cell_tables(ins, g):
+def _cell_tables(ins, g, ic):
+    """Class tables of internal cell ic in group g (a pooled group's cells each have their own)."""
     N, F = ins.N, ins.F
-    med, nF, off = int(ins.groups[g, 0]), int(ins.groups[g, 1]), int(ins.groups[g, 2])
+    med, nF, off = int(ins.groups[g, 0]), int(ins.groups[g, 1]), int(ins.ic_tab[ic])
     t = ins.tables
     Bx = t[off:off + N * N].reshape(N, N)
     By = t[off + N * N:off + 2 * N * N].reshape(N, N)
@@ -60,7 +61,7 @@ def _face_values(ins, lay, state, adjoint):
     tau, itau = ins.mat[2], ins.mat[5]
     tr = {}
     for ic, u in state.items():
-        med, nF, Bx, By, Sm, G, nrm = _cell_tables(ins, lay.group_of_ic[ic])
+        med, nF, Bx, By, Sm, G, nrm = _cell_tables(ins, lay.group_of_ic[ic], ic)
         for j in range(nF):
             nx, ny = nrm[j]
             if med == 0:
@@ -74,7 +75,7 @@ def _face_values(ins, lay, state, adjoint):
     sc = -1.0 if adjoint else 1.0
     fv = {}
     for ic in state:
-        med, nF, Bx, By, Sm, G, nrm = _cell_tables(ins, lay.group_of_ic[ic])
+        med, nF, Bx, By, Sm, G, nrm = _cell_tables(ins, lay.group_of_ic[ic], ic)
         for j in range(nF):
             lk = int(ins.link[j, ic])
             if lk < 0:
@@ -112,7 +113,7 @@ def rhs(ins, mesh, U, adjoint=False):
     tau = ins.mat[2]
     out = np.zeros_like(U)
     for ic, u in state.items():
-        med, nF, Bx, By, Sm, G, nrm = _cell_tables(ins, lay.group_of_ic[ic])
+        med, nF, Bx, By, Sm, G, nrm = _cell_tables(ins, lay.group_of_ic[ic], ic)
         t = tau[ic]
         if med == 0:
             p, mx, my = u
@@ -166,7 +167,7 @@ def grad_terms(ins, mesh, Y, k, mu):
     gm = ins.gm
     grad = np.zeros((len(lay.med_in), 3))
     for ic, z in zs.items():
-        med, nF, Bx, By, Sm, G, nrm = _cell_tables(ins, lay.group_of_ic[ic])
+        med, nF, Bx, By, Sm, G, nrm = _cell_tables(ins, lay.group_of_ic[ic], ic)
         y, kk = ys[ic], ks[ic]
         nc = 1 if med == 0 else 2
         w = z.copy()

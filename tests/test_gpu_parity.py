@@ -343,16 +343,27 @@ def test_honeycomb_mesh(k, dtype, tol):
 
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_perturbed_vertices_mesh(k):
-    """Every vertex moved at random (no two cells share a shape, so every cell is its own class
-    and group): ERK(4) from a random state against the oracle, float64."""
+    """Every vertex moved at random (no two cells share a shape: more than 64 classes, all of them
+    pooled, every lane reading its own class table): ERK(4) from a random state against the
+    oracle, float64 and float32 stepping; the adjoint refuses such a mesh."""
+    from paper_2505_15771_amd.hho import HHOError
     say("case: perturbed-vertex mesh k=%d" % k)
-    mesh = M.with_materials(M.perturbed_square(6, seed=11), perturb=0.1, seed=12)
+    mesh = M.with_materials(M.perturbed_square(8, seed=11), perturb=0.1, seed=12)
     o = oracle(mesh, k)
     e = engine(mesh, k)
     U0 = np.random.default_rng(50 + k).standard_normal(o.ndof)
     dt = 0.3 * e.dt_cfl(1.0)
     e.set_state(U0)
     e.erk_step(0.0, dt, 8)
-    err = rel(e.get_state(), o.erk(U0, 0.0, dt, 8))
+    ref = o.erk(U0, 0.0, dt, 8)
+    err = rel(e.get_state(), ref)
     say("rel L2 =", err)
     assert err < TOL64
+    e32 = engine(mesh, k, dtype="f32")
+    e32.set_state(U0)
+    e32.erk_step(0.0, dt, 8)
+    err32 = rel(e32.get_state(), ref)
+    say("rel L2 (float32) =", err32)
+    assert err32 < 1e-5
+    with pytest.raises(HHOError):
+        e.adjoint(0.0, dt, 2, None)

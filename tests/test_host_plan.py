@@ -46,6 +46,8 @@ CASES = {
     "quads_interface": lambda: M.with_materials(M.unit_square(6), perturb=0.1, seed=1),
     "hybrid_interface": lambda: M.with_materials(M.unit_square(6, p_split=0.5, seed=3), perturb=0.1, seed=2),
     "hanging_interface": lambda: M.hanging_square(6, seed=5),
+    "perturbed_vertices": lambda: M.with_materials(M.perturbed_square(8, seed=6), perturb=0.1, seed=7),
+    "hexagons": lambda: M.with_materials(M.honeycomb_bilayer(6), perturb=0.1, seed=8),
 }
 
 
@@ -63,6 +65,23 @@ def test_plan_reproduces_oracle_operator(k, case):
     got = kernel_model.rhs(ins, mesh, U)
     ref = o.rhs(U)
     assert np.linalg.norm(got - ref) < 1e-12 * np.linalg.norm(ref)
+
+
+def test_small_classes_are_pooled():
+    """On a mesh with more than 64 shape classes, cells whose shape occurs fewer than 32 times go
+    to pooled groups (one per medium and face-count bucket) whose lanes find their own class
+    tables; shapes that repeat keep groups of their own, and meshes with few classes (hanging
+    nodes, cut cells) are not pooled.  With every vertex moved every group is pooled and the
+    internal cells are padded per pooled group only."""
+    from paper_2505_15771_amd import Inspect
+    ins = Inspect(M.with_materials(M.perturbed_square(8, seed=2)), 2)
+    assert ins.pooled.all() and ins.n_groups <= 4
+    assert ins.n_ic <= ins.n_cells + ins.n_groups * 256
+    tab_cells = {int(ins.ic_tab[ic]) for ic in ins.ic_of_cell}
+    assert len(tab_cells) == ins.n_cells          # one table per cell
+    big = Inspect(M.with_materials(M.unit_square(16)), 2)
+    assert not big.pooled.any()
+    assert not Inspect(M.hanging_square(8, seed=3), 2).pooled.any()
 
 
 def test_shape_classes_are_shared():
