@@ -529,7 +529,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<R> a) {
     }
     GroupDev G;
     const LaneInfo L = decode_lane(a, G);
-    if ((G.pooled != 0) != POOLED) return;
+    if ((POOLED || a.has_pooled) && (G.pooled != 0) != POOLED) return;
     const bool want_e = a.last && a.e_part;
     double e = 0.0;
     double *ep = want_e ? &e : nullptr;
@@ -567,7 +567,7 @@ template <int K, typename R, bool POOLED = false>
 __global__ __launch_bounds__(kBlock) void trace_kernel(StageArgs<R> a) {
     GroupDev G;
     const LaneInfo L = decode_lane(a, G);
-    if (!L.active || (G.pooled != 0) != POOLED) return;
+    if (!L.active || ((POOLED || a.has_pooled) && (G.pooled != 0) != POOLED)) return;
     if (G.nF <= 4) traces_body<K, 4, R, POOLED>(a, G, L);
     else traces_body<K, kMaxFaces, R, POOLED>(a, G, L);
 }
