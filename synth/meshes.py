@@ -222,12 +222,13 @@ def honeycomb_bilayer(X=30):
     return m
 
 
-def perturbed_square(n, amount=0.15, p_split=0.5, seed=0, interface_y=0.5):
+def perturbed_square(n, amount=0.15, p_split=0.5, seed=0, interface_y=0.5, x_max=None):
     """unit_square(n, p_split) with every vertex moved by a seeded uniform offset of up to
     amount * h per coordinate, except along the constraints: corners stay, other boundary
     vertices and vertices on the interface y = interface_y move only along their line.  Every
     cell then has its own shape (no two cells are translates of each other), like a mesh from an
-    unstructured generator."""
+    unstructured generator.  With x_max set only the vertices left of x = x_max move, so the
+    cells right of that line keep the lattice shapes."""
     m = unit_square(n, p_split=p_split, seed=seed, interface_y=interface_y)
     h = 1.0 / n
     rng = np.random.default_rng(seed + 7)
@@ -237,6 +238,8 @@ def perturbed_square(n, amount=0.15, p_split=0.5, seed=0, interface_y=0.5):
     on_y = (np.abs(xy[:, 1]) < 1e-12) | (np.abs(xy[:, 1] - 1.0) < 1e-12) | (np.abs(xy[:, 1] - interface_y) < 1e-12)
     d[on_x, 0] = 0.0
     d[on_y, 1] = 0.0
+    if x_max is not None:
+        d[xy[:, 0] >= x_max - 1e-12] = 0.0
     out = dict(m)
     out["xy"] = xy + d
     return out

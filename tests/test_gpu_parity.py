@@ -342,6 +342,58 @@ def test_honeycomb_mesh(k, dtype, tol):
 
 
 @pytest.mark.parametrize("k", [1, 2, 3])
+def test_partly_perturbed_mesh(k):
+    """Vertices moved left of x = 1/2 only: the cells there each have their own shape and go to
+    pooled groups (several workgroups each, ragged tails), the lattice cells on the right keep
+    groups with shared class tables, so every stage runs both launches over real work.  Two
+    shots with Ricker point sources in both halves, receivers in both halves and the energy
+    recorded at every step, float64 against the oracle; float32 stepping of the state."""
+    say("case: partly perturbed mesh k=%d" % k)
+    mesh = M.with_materials(M.perturbed_square(32, seed=5, x_max=0.5), perturb=0.1, seed=6)
+    from paper_2505_15771_amd import Inspect
+    ins = Inspect(mesh, k)
+    assert ins.pooled.any() and not ins.pooled.all()
+    rx = np.array([[0.21, 0.77], [0.81, 0.62], [0.33, 0.18], [0.74, 0.41]])
+    fld = np.array([0, 0, 1, 1], np.int32)
+    srcs = [np.array([[0.23, 0.31], [0.7, 0.8]]), np.array([[0.41, 0.66]])]
+    dirs = [np.array([[0.6, -0.8], [1.0, 0.0]]), np.array([[1.0, 0.0]])]
+    nsteps = 20
+    e = engine(mesh, k, n_shots=2, record_energy=True)
+    dt = 0.3 * e.dt_cfl(1.0)
+    e.set_receivers(rx, fld)
+    e32 = engine(mesh, k, n_shots=2, dtype="f32")
+    refs = []
+    for sh in range(2):
+        o = oracle(mesh, k)
+        U0 = 0.1 * np.random.default_rng(70 + sh).standard_normal(o.ndof)
+        o.set_point_sources(srcs[sh], dirs[sh], 10.0, 0.05, 1.0 + sh)
+        for eng in (e, e32):
+            eng.set_sources(sh, srcs[sh], dirs[sh], 10.0, 0.05, 1.0 + sh)
+            eng.set_state(U0, shot=sh)
+        U = U0.copy()
+        tr = np.zeros((nsteps, 4, 2))
+        En = np.zeros(nsteps)
+        for n in range(nsteps):
+            U = o.erk(U, n * dt, dt, 1)
+            En[n] = o.energy(U)
+            for r in range(4):
+                c, vals = o.point_values(U, *rx[r])
+                tr[n, r, :(1 if fld[r] == 0 else 2)] = vals[:1] if fld[r] == 0 else vals[:2]
+        refs.append((U, tr, En))
+    e.erk_step(0.0, dt, nsteps)
+    e32.erk_step(0.0, dt, nsteps)
+    for sh in range(2):
+        U, tr, En = refs[sh]
+        err_u = rel(e.get_state(sh), U)
+        err_t = rel(e.traces(sh), tr)
+        err_e = rel(e.energy_history(sh), En)
+        err32 = rel(e32.get_state(sh), U)
+        say("shot", sh, "state", err_u, "traces", err_t, "energy", err_e, "float32 state", err32)
+        assert err_u < TOL64 and err_t < TOL64 and err_e < TOL64
+        assert err32 < 1e-5
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_perturbed_vertices_mesh(k):
     """Every vertex moved at random (no two cells share a shape: more than 64 classes, all of them
     pooled, every lane reading its own class table): ERK(4) from a random state against the

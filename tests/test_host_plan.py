@@ -48,6 +48,7 @@ CASES = {
     "hanging_interface": lambda: M.hanging_square(6, seed=5),
     "perturbed_vertices": lambda: M.with_materials(M.perturbed_square(8, seed=6), perturb=0.1, seed=7),
     "hexagons": lambda: M.with_materials(M.honeycomb_bilayer(6), perturb=0.1, seed=8),
+    "partly_perturbed": lambda: M.with_materials(M.perturbed_square(16, seed=9, x_max=0.5), perturb=0.1, seed=10),
 }
 
 
@@ -79,6 +80,11 @@ def test_small_classes_are_pooled():
     assert ins.n_ic <= ins.n_cells + ins.n_groups * 256
     tab_cells = {int(ins.ic_tab[ic]) for ic in ins.ic_of_cell}
     assert len(tab_cells) == ins.n_cells          # one table per cell
+    part = Inspect(M.with_materials(M.perturbed_square(16, seed=2, x_max=0.5)), 2)
+    assert part.pooled.any() and not part.pooled.all()
+    shared = part.groups[part.pooled == 0]
+    for tab in set(shared[:, 2]):                  # lattice shapes right of x = 1/2, both media
+        assert shared[shared[:, 2] == tab, 4].sum() >= 32
     big = Inspect(M.with_materials(M.unit_square(16)), 2)
     assert not big.pooled.any()
     assert not Inspect(M.hanging_square(8, seed=3), 2).pooled.any()
