@@ -226,9 +226,7 @@ hho_status hho_dt_cfl(const hho_ctx *ctx, double factor, double *dt);
  * 2 * ckpt_every * rk_stages stage records; the workspace is kept for later calls.
  * On return (synchronised) the state is U^{n_steps}, and hho_get_traces / hho_energy_history
  * report the forward run, as after hho_erk_step.  Only rk_stages 2 and 4 (subdiagonal
- * Runge-Kutta matrices) are supported: ARG otherwise.  ARG also for a mesh whose small shape
- * classes are pooled (more than 64 shape classes; see hho_inspect_cell_tables).  UNSTABLE as
- * hho_erk_step. */
+ * Runge-Kutta matrices) are supported: ARG otherwise; UNSTABLE as hho_erk_step. */
 hho_status hho_adjoint_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps, int32_t ckpt_every,
                             const double *d_obs, double *J, double *grad);
 

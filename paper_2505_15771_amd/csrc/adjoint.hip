@@ -501,9 +501,9 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
     solid_traces<K, NF, R>(a, B, tb, nF, lk, boff, zx, zy, z1, z2, z3, tau, itau);
 }
 
-template <int K, int NF, typename R>
+template <int K, int NF, typename R, bool POOLED>
 __device__ __forceinline__ void adjoint_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L) {
-    const HHO_CONST R *tb = uni(a.tab) + G.tab_off;
+    const HHO_CONST R *tb = class_table<POOLED>(a, G, L.ic);
     const Bufs<R> B = make_bufs(a);
     if (G.medium == kFluid)
         fluid_adjoint<K, NF, R>(a, B, tb, G.nF, L);
@@ -511,21 +511,24 @@ __device__ __forceinline__ void adjoint_body(const StageArgs<R> &a, const GroupD
         solid_adjoint<K, NF, R>(a, B, tb, G.nF, L);
 }
 
-template <int K, typename R>
+// On a mesh with pooled groups every adjoint launch is two launches over the same grid, as the
+// forward stage: POOLED = false for the groups with shared tables, true for the pooled ones; a
+// workgroup whose group is of the other kind returns at once.
+template <int K, typename R, bool POOLED>
 __global__ __launch_bounds__(kBlock) void adjoint_kernel(StageArgs<R> a) {
     GroupDev G;
     const LaneInfo L = decode_lane(a, G);
-    if (!L.active) return;
-    if (G.nF <= 4) adjoint_body<K, 4, R>(a, G, L);
-    else adjoint_body<K, kMaxFaces, R>(a, G, L);
+    if (!L.active || ((POOLED || a.has_pooled) && (G.pooled != 0) != POOLED)) return;
+    if (G.nF <= 4) adjoint_body<K, 4, R, POOLED>(a, G, L);
+    else adjoint_body<K, kMaxFaces, R, POOLED>(a, G, L);
 }
 
 // Start of the reverse sweep: lambda += dt R^T (R U - d^n) (primal rows of U read from a.yfwd,
 // n = a.inject; receivers of the lane's cell), then z = D M^{-1}(zs_b lambda) and its outgoing traces.
-template <int K, int NF, typename R>
+template <int K, int NF, typename R, bool POOLED>
 __device__ __forceinline__ void start_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L) {
     constexpr int N = Dim<K>::N;
-    const HHO_CONST R *tb = uni(a.tab) + G.tab_off;
+    const HHO_CONST R *tb = class_table<POOLED>(a, G, L.ic);
     const Bufs<R> B = make_bufs(a);
     const int ic = L.ic, nb = G.medium == kFluid ? 3 : 5, ncomp = G.medium == kFluid ? 1 : 2;
     const unsigned boff = L.boff, coff = L.coff;
@@ -590,13 +593,13 @@ __device__ __forceinline__ void start_body(const StageArgs<R> &a, const GroupDev
         solid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.boff, z[0], z[1], z[2], z[3], z[4], tau, itau);
 }
 
-template <int K, typename R>
+template <int K, typename R, bool POOLED>
 __global__ __launch_bounds__(kBlock) void adjoint_start_kernel(StageArgs<R> a) {
     GroupDev G;
     const LaneInfo L = decode_lane(a, G);
-    if (!L.active) return;
-    if (G.nF <= 4) start_body<K, 4, R>(a, G, L);
-    else start_body<K, kMaxFaces, R>(a, G, L);
+    if (!L.active || ((POOLED || a.has_pooled) && (G.pooled != 0) != POOLED)) return;
+    if (G.nF <= 4) start_body<K, 4, R, POOLED>(a, G, L);
+    else start_body<K, kMaxFaces, R, POOLED>(a, G, L);
 }
 
 // grad[c][q] = sum over shots of the lane accumulators of cell c (input cell order).
@@ -624,13 +627,16 @@ hipError_t launch_grad_reduce(const double *gacc, long long LT, int S, const int
 
 template <int K, typename R>
 hipError_t launch_adjoint_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
-    hipLaunchKernelGGL((adjoint_kernel<K, R>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    hipLaunchKernelGGL((adjoint_kernel<K, R, false>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    if (a.has_pooled) hipLaunchKernelGGL((adjoint_kernel<K, R, true>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     return hipGetLastError();
 }
 
 template <int K, typename R>
 hipError_t launch_adjoint_start(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
-    hipLaunchKernelGGL((adjoint_start_kernel<K, R>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    hipLaunchKernelGGL((adjoint_start_kernel<K, R, false>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    if (a.has_pooled)
+        hipLaunchKernelGGL((adjoint_start_kernel<K, R, true>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     return hipGetLastError();
 }
 

@@ -1387,11 +1387,6 @@ hho_status hho_adjoint_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps,
             ctx->err = "adjoint_step: per-shot time-step multipliers are set (hho_set_dt_scale); reset them first";
             return HHO_ERR_ARG;
         }
-        if (ctx->plan.has_pooled) {
-            ctx->err = "adjoint_step: the mesh has more than 64 shape classes and pools the small ones, which the "
-                       "adjoint kernels do not handle";
-            return HHO_ERR_ARG;
-        }
         std::vector<StageCoef> co;
         if (!erk_coefficients(ctx->stages, co)) return HHO_ERR_ARG;
         for (const StageCoef &q : co)

@@ -499,14 +499,6 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
     }
 }
 
-// Class tables: one per group, read through scalar loads; in a pooled group (cells of small
-// shape classes together) each lane finds its class's table at its own offset and reads it
-// through vector loads.
-template <bool POOLED, typename R>
-__device__ __forceinline__ const HHO_CONST R *class_table(const StageArgs<R> &a, const GroupDev &G, int ic) {
-    return POOLED ? uni(a.tab) + a.ic_tab[ic] : uni(a.tab) + G.tab_off;
-}
-
 template <int K, int NF, typename R, bool STORE, int POL, bool POOLED>
 __device__ __forceinline__ void stage_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L, double *e) {
     const HHO_CONST R *tb = class_table<POOLED>(a, G, L.ic);
@@ -660,6 +652,8 @@ hipError_t launch_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
 template <int K, typename R>
 hipError_t launch_stage_store(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
     hipLaunchKernelGGL((stage_kernel<K, R, true, 0>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    if (a.has_pooled)
+        hipLaunchKernelGGL((stage_kernel<K, R, true, 0, true>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     return hipGetLastError();
 }
 

@@ -272,6 +272,14 @@ __device__ __forceinline__ void load_incoming(const Bufs<R> &B, int medium, int 
     }
 }
 
+// Class tables: one per group, read through scalar loads; in a pooled group (cells of small
+// shape classes together) each lane finds its class's table at its own offset and reads it
+// through vector loads.
+template <bool POOLED, typename R>
+__device__ __forceinline__ const HHO_CONST R *class_table(const StageArgs<R> &a, const GroupDev &G, int ic) {
+    return POOLED ? uni(a.tab) + a.ic_tab[ic] : uni(a.tab) + G.tab_off;
+}
+
 // ------------------------------------------------------------------------- outgoing traces
 template <int K, int NF, typename R, int POL = 0>
 __device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,

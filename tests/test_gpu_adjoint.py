@@ -168,6 +168,44 @@ def test_adjoint_float32():
     assert rel(g, g0) < 5e-5
 
 
+POOLED_MESHES = {
+    "all_pooled": lambda: M.with_materials(M.perturbed_square(8, seed=11), perturb=0.1, seed=12),
+    "half_pooled": lambda: M.with_materials(M.perturbed_square(16, seed=5, x_max=0.5), perturb=0.1, seed=6),
+}
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("case", list(POOLED_MESHES))
+def test_adjoint_pooled_mesh(case, k):
+    """Cells of their own shapes (vertices moved at random everywhere, or left of x = 1/2 only)
+    sit in pooled groups whose lanes read their own class tables, so every adjoint stage is two
+    launches: J, gradient and final state against the oracle in float64, 20 steps in checkpoint
+    segments of 6; float32 at k = 2."""
+    say("case: adjoint on %s mesh k=%d" % (case, k))
+    from paper_2505_15771_amd import Engine, Inspect
+    nsteps = 20
+    mesh = POOLED_MESHES[case]()
+    assert Inspect(mesh, k).pooled.any()
+    dt = time_step(mesh, k)
+    U0 = initial_state(mesh, k)
+    d = observed(mesh, k, nsteps, dt, SRC, 1.0, U0)
+    J0, g0, UN = oracle_gradient(mesh, k, nsteps, dt, SRC, 1.0, d, U0)
+    for dtype in (["f64", "f32"] if k == 2 else ["f64"]):
+        e = Engine(mesh, k, dtype=dtype)
+        e.set_sources(0, SRC, [[0.0, 1.0]], F0, T0, 1.0)
+        e.set_receivers(REC_XY, REC_F)
+        e.set_state(U0)
+        J, g = e.adjoint(0.0, dt, nsteps, d, ckpt_every=6)
+        say(dtype, "J rel", abs(J - J0) / J0, "grad rel L2", rel(g, g0), "state", rel(e.get_state(), UN))
+        if dtype == "f64":
+            assert abs(J - J0) < 1e-11 * J0
+            assert rel(g, g0) < 1e-11
+            assert rel(e.get_state(), UN) < 1e-12
+        else:
+            assert abs(J - J0) < 2e-5 * J0
+            assert rel(g, g0) < 5e-5
+
+
 def test_adjoint_argument_errors_and_no_receivers():
     from paper_2505_15771_amd import Engine, HHOError
     mesh = small_mesh()
