@@ -92,15 +92,19 @@ def test_dt_cfl_matches_table():
 
 
 def test_batch_of_meshes_and_shots():
-    """Three meshes of different sizes and degrees (k = 1, 2, 3), float32 and float64, several shots
-    each, advanced by one batch (graph branches per mesh) for 70 steps; every shot vs the oracle."""
+    """Four meshes of different sizes and degrees (k = 1, 2, 3), float32 and float64, several shots
+    each (the last with vertices moved on one half, so its stages are two launches), advanced by one
+    batch (graph branches per mesh) for 70 steps; every shot vs the oracle."""
     from oracle import Oracle
     from paper_2505_15771_amd import Batch, Engine
-    say("case: batch of 3 meshes")
-    specs = [(6, 1, "f64", 2), (9, 2, "f32", 3), (5, 3, "f64", 1)]
+    say("case: batch of 4 meshes")
+    specs = [(6, 1, "f64", 2), (9, 2, "f32", 3), (5, 3, "f64", 1), (16, 2, "f64", 2)]
     engines, refs, dts = [], [], []
     for i, (n, k, dtype, S) in enumerate(specs):
-        mesh = M.with_materials(M.unit_square(n, p_split=0.5, seed=30 + i), perturb=0.1, seed=40 + i)
+        if i < 3:
+            mesh = M.with_materials(M.unit_square(n, p_split=0.5, seed=30 + i), perturb=0.1, seed=40 + i)
+        else:  # vertices moved left of x = 1/2: pooled groups beside shared-table groups
+            mesh = M.with_materials(M.perturbed_square(n, seed=33, x_max=0.5), perturb=0.1, seed=43)
         e = Engine(mesh, k, dtype=dtype, n_shots=S)
         dt = e.dt_cfl(0.5)
         dts.append(dt)
@@ -116,7 +120,7 @@ def test_batch_of_meshes_and_shots():
         engines.append(e)
         refs.append(shots)
     b = Batch(engines)
-    b.erk_step([0.1] * 3, dts, 70)
+    b.erk_step([0.1] * len(specs), dts, 70)
     for i, e in enumerate(engines):
         tol = 1e-12 if specs[i][2] == "f64" else 1e-5
         for sh, ref in enumerate(refs[i]):

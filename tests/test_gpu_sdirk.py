@@ -256,3 +256,22 @@ def test_honeycomb_parity():
     say("  rel L2", err)
     assert err < TOL
     e.close()
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_perturbed_vertices_parity(k):
+    """SDIRK(3,4), mixed order, on a mesh whose vertices are all moved at random (every cell its
+    own shape; the implicit plan keeps per-cell matrices, so no shape classes are involved)."""
+    from oracle.implicit import ImplicitOracle
+    from paper_2505_15771_amd import SdirkEngine
+    say("case: sdirk perturbed vertices k=%d" % k)
+    m = M.with_materials(M.perturbed_square(8, seed=13), perturb=0.1, seed=14)
+    io = ImplicitOracle(m, k)
+    e = SdirkEngine(m, k, 0.02, stages=3, tol=1e-14)
+    U0 = np.random.default_rng(93).standard_normal(io.ndof)
+    e.set_state(U0)
+    e.step(0.0, 3)
+    err = rel(e.get_state(), io.sdirk(U0, 0.0, 0.02, 3, s=3))
+    say("  rel L2", err)
+    assert err < TOL
+    e.close()
