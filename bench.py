@@ -33,9 +33,9 @@ HBM_PEAK_GBS = 8000.0
 # elementwise kernel of known size (factors 2.0 and 1.0); valid only for the kernel and host-plan
 # sources with this digest (otherwise the traffic is reported as null).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "3d50172e218d15ce881fe9a3762ebf3e758432542fb8d4049491601678a1ed73",
+    "sources_sha256": "d14f57548794ac4ad90266fcec2b412dbec4be42197da7073c9974f7e6289554",
     "config": (2, "f32", 1),
-    "bytes_per_launch": (2.0 * 19121.5 + 1.0 * 18065.1) * 1024,
+    "bytes_per_launch": (2.0 * 19591.9 + 1.0 * 18054.8) * 1024,
 }
 STAGE_SOURCES = ("kernels.hip", "stage_common.h", "device.h", "plan.cpp", "api.cpp")
 
@@ -247,6 +247,42 @@ def run_tableaux(k=2, dtype="f32", steps=200):
                         value=e.n_dof * s_ * steps / (ms / 1e3)))
         e.close()
     return dict(workload="ERK(2/3/4) tableaux, 256x256 hybrid mesh, k=%d, %s, one shot" % (k, dtype), results=out)
+
+
+def run_perturbed(k=2, dtype="f32", steps=200, n=256):
+    """Meshes whose cells do not share shapes: the n x n hybrid mesh as generated, with every
+    vertex moved at random (every cell its own shape class, all pooled), and with the vertices
+    left of x = 1/2 moved (pooled groups beside shared-table groups); ERK(4) time per step and
+    DOF-stage updates/s of each, one shot."""
+    import torch
+    from paper_2505_15771_amd import Engine, Inspect
+    meshes = (("lattice shapes", M.with_materials(M.unit_square(n, p_split=0.5, seed=3))),
+              ("all vertices moved", M.with_materials(M.perturbed_square(n, seed=3))),
+              ("vertices left of x = 1/2 moved", M.with_materials(M.perturbed_square(n, seed=3, x_max=0.5))))
+    out = []
+    for name, mesh in meshes:
+        ins = Inspect(mesh, k)
+        pooled_cells = int(ins.groups[ins.pooled == 1, 4].sum())
+        t0 = time.perf_counter()
+        e = Engine(mesh, k, dtype=dtype)
+        setup = time.perf_counter() - t0
+        e.set_state(1e-3 * np.random.default_rng(7).standard_normal(e.n_dof))
+        e.autotune()
+        dt = 0.3 * e.dt_cfl(1.0)
+        e.erk_step(0.0, dt, 20)
+        e.synchronize()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        e.erk_step(0.0, dt, steps)
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        out.append(dict(mesh=name, cells=e.n_cells, groups=int(ins.n_groups), pooled_cells=pooled_cells,
+                        setup_s=setup, us_per_step=ms * 1e3 / steps, value=e.n_dof * 4 * steps / (ms / 1e3)))
+        e.close()
+    return dict(workload="%dx%d hybrid mesh with moved vertices, k=%d, %s, ERK(4), one shot" % (n, n, k, dtype),
+                unit="DOF-stage updates/s", results=out)
 
 
 def run_precision(k=2, steps=2000):
@@ -636,7 +672,7 @@ def main():
     ap.add_argument("--variants", type=int, default=1, help="also time the float64 / k=3 / batched variants")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--only", choices=("adjoint", "basin", "batch", "paper", "cfl", "precision", "tableaux", "sdirk",
-                                       "eta", "geometry"),
+                                       "eta", "geometry", "perturbed"),
                     default=None,
                     help="run one extra workload alone and print its JSON line (for profiling)")
     ap.add_argument("--only-steps", type=int, default=200)
@@ -672,6 +708,7 @@ def main():
               "precision": lambda: run_precision(steps=args.only_steps),
               "tableaux": lambda: run_tableaux(steps=args.only_steps),
               "eta": lambda: run_eta_sweep(),
+              "perturbed": lambda: run_perturbed(dtype=args.dtype, steps=args.only_steps),
               "geometry": lambda: [run_cfl_geometry(), run_cfl_geometry(stab_speed=1)],
               "sdirk": lambda: [run_sdirk_bilayer(k_, steps=args.only_steps,
                                                   erk_traces=run_paper_bilayer(k_, sensors=True)["_traces"])

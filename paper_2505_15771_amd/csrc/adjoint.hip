@@ -627,14 +627,15 @@ hipError_t launch_grad_reduce(const double *gacc, long long LT, int S, const int
 
 template <int K, typename R>
 hipError_t launch_adjoint_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
-    hipLaunchKernelGGL((adjoint_kernel<K, R, false>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    if (!a.all_pooled) hipLaunchKernelGGL((adjoint_kernel<K, R, false>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     if (a.has_pooled) hipLaunchKernelGGL((adjoint_kernel<K, R, true>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     return hipGetLastError();
 }
 
 template <int K, typename R>
 hipError_t launch_adjoint_start(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
-    hipLaunchKernelGGL((adjoint_start_kernel<K, R, false>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    if (!a.all_pooled)
+        hipLaunchKernelGGL((adjoint_start_kernel<K, R, false>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     if (a.has_pooled)
         hipLaunchKernelGGL((adjoint_start_kernel<K, R, true>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     return hipGetLastError();

@@ -295,6 +295,8 @@ StageArgs<R> base_args(hho_ctx *ctx) {
     a.tab = (const R *)ctx->tab;
     a.ic_tab = ctx->ic_tab;
     a.has_pooled = ctx->plan.has_pooled ? 1 : 0;
+    a.all_pooled = a.has_pooled;
+    for (const auto &G : ctx->plan.groups) a.all_pooled &= G.pooled ? 1 : 0;
     a.groups = ctx->launch[ctx->shape].groups;
     a.blk_group = ctx->launch[ctx->shape].blk_group;
     a.n_ic = ctx->plan.n_ic;

@@ -51,6 +51,7 @@ struct StageArgs {
     const R *tab;         // class tables
     const int32_t *ic_tab;  // [n_ic] table offset of every cell (read by the pooled-group kernels)
     int has_pooled;         // some groups are pooled: the stage and trace launches come in pairs
+    int all_pooled;         // every group is pooled: only the pooled launch runs (and advances the clock)
     const GroupDev *groups;
     const int32_t *blk_group;
     int n_ic, S, cpb;

@@ -511,10 +511,11 @@ __device__ __forceinline__ void stage_body(const StageArgs<R> &a, const GroupDev
 
 // With pooled groups a stage is two launches over the same grid: the one for the ordinary groups
 // (POOLED = false, which also advances the clock) and the one for the pooled groups; each
-// workgroup of a launch whose group is of the other kind returns at once.
+// workgroup of a launch whose group is of the other kind returns at once.  When every group is
+// pooled only the pooled launch runs, and it advances the clock.
 template <int K, typename R, bool STORE, int POL, bool POOLED = false>
 __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<R> a) {
-    if (!POOLED && a.last && a.clock_next && blockIdx.x == 0 && threadIdx.x == 0) {
+    if ((!POOLED || a.all_pooled) && a.last && a.clock_next && blockIdx.x == 0 && threadIdx.x == 0) {
         Clock c = *a.clock;
         c.step += 1;
         *a.clock_next = c;
@@ -640,10 +641,12 @@ __global__ void gather_kernel(const R *state, const int64_t *map, long long n, i
 
 template <int K, typename R>
 hipError_t launch_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
-    if (a.nt_stores)
-        hipLaunchKernelGGL((stage_kernel<K, R, false, kNonTemporal>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
-    else
-        hipLaunchKernelGGL((stage_kernel<K, R, false, 0>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    if (!a.all_pooled) {
+        if (a.nt_stores)
+            hipLaunchKernelGGL((stage_kernel<K, R, false, kNonTemporal>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+        else
+            hipLaunchKernelGGL((stage_kernel<K, R, false, 0>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    }
     if (a.has_pooled)
         hipLaunchKernelGGL((stage_kernel<K, R, false, 0, true>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     return hipGetLastError();
@@ -651,7 +654,8 @@ hipError_t launch_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
 
 template <int K, typename R>
 hipError_t launch_stage_store(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
-    hipLaunchKernelGGL((stage_kernel<K, R, true, 0>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    if (!a.all_pooled)
+        hipLaunchKernelGGL((stage_kernel<K, R, true, 0>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     if (a.has_pooled)
         hipLaunchKernelGGL((stage_kernel<K, R, true, 0, true>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     return hipGetLastError();
@@ -659,7 +663,7 @@ hipError_t launch_stage_store(const StageArgs<R> &a, int n_blocks, hipStream_t s
 
 template <int K, typename R>
 hipError_t launch_traces(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
-    hipLaunchKernelGGL((trace_kernel<K, R>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    if (!a.all_pooled) hipLaunchKernelGGL((trace_kernel<K, R>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     if (a.has_pooled) hipLaunchKernelGGL((trace_kernel<K, R, true>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     return hipGetLastError();
 }
