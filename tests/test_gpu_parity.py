@@ -416,3 +416,20 @@ def test_perturbed_vertices_mesh(k):
     err32 = rel(e32.get_state(), ref)
     say("rel L2 (float32) =", err32)
     assert err32 < 1e-5
+    # only the pooled launch runs on such a mesh, so it also advances the clock: a Ricker source
+    # and receivers after every step depend on it
+    nsteps, src, dirs = 12, [[0.4, 0.3]], [[0.6, -0.8]]
+    rx, fld = np.array([[0.3, 0.7], [0.6, 0.2]]), np.array([0, 1], np.int32)
+    o.set_point_sources(src, dirs, 10.0, 0.05, 1.0)
+    e.set_sources(0, src, dirs, 10.0, 0.05, 1.0)
+    e.set_receivers(rx, fld)
+    e.set_state(U0)
+    e.erk_step(0.0, dt, nsteps)
+    U, tr = U0.copy(), np.zeros((nsteps, 2, 2))
+    for n in range(nsteps):
+        U = o.erk(U, n * dt, dt, 1)
+        tr[n, 0, :1] = o.point_values(U, *rx[0])[1][:1]
+        tr[n, 1, :2] = o.point_values(U, *rx[1])[1][:2]
+    err_u, err_t = rel(e.get_state(), U), rel(e.traces(0), tr)
+    say("with source: state", err_u, "traces", err_t)
+    assert err_u < TOL64 and err_t < TOL64
