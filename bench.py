@@ -1,14 +1,18 @@
 """Benchmark of the HHO elasto-acoustic explicit Runge-Kutta path on one MI355X.
 
-Workload: the unit square with the two-material split (elastic below y = 1/2:
-rho = 1, cP = sqrt(3), cS = 1; acoustic above: rho = 1, c = 1), a 256 x 256 hybrid
-mesh (each square kept or cut along a random diagonal with probability 1/2, seed
-2001), per-cell materials perturbed by U[-10 %, +10 %] (seed 2002), HHO k = 2,
-classical RK4 at dt = 0.5 CFL* h / c_max.  A step is one RK4 step (four fused stage
-launches) over the whole mesh; inputs are resident in HBM before timing starts.
+Headline workload: sixteen seeded hybrid meshes of the two-material unit square (elastic below
+y = 1/2: rho = 1, cP = sqrt(3), cS = 1; acoustic above: rho = 1, c = 1), target cell counts
+log-spaced from 2e4 to 3e5 (1.72 M cells in total), HHO degree k = 1, 2, 3 in turn, four Ricker
+shots per mesh at seeded positions, float32 stepping with the float64 energy of every shot
+recorded after every step, all meshes advanced together by one batch of captured graphs.  A step
+is one classical RK4 step (four fused stage launches per mesh) of every mesh and shot; inputs are
+resident in HBM before timing starts.
 
-The headline value is float32 stepping of one shot; float64, k = 3 and batched
-(several shots per launch) variants are reported next to it.  Prints one JSON line.
+Reported next to it: the same workload stepped one shot at a time in float64 (the speed-up of the
+batched float32 path over it), the error of the batched float32 path against the float64 oracle,
+the oracle's own throughput on the host cores, and the 256 x 256 hybrid mesh stepped in float32 /
+float64, one or eight shots, k = 2 and 3.  The last stdout line is one compact JSON object; the
+other workloads print one JSON line each to stderr.
 """
 from __future__ import annotations
 
@@ -633,49 +637,231 @@ def copy_bandwidth(mib=1024, reps=20):
     return 2.0 * mib * (1 << 20) / (best * 1e-3) / 1e9
 
 
-def cpu_baseline(mesh, k, budget_s=15.0):
-    """The FP64 oracle as it stands, on the host cores, for about budget_s seconds of stepping."""
-    from oracle import Oracle
-    o = Oracle(mesh, k)
-    U = 1e-3 * np.random.default_rng(7).standard_normal(o.ndof)
-    h = 1.0 / 256
-    dt = 0.5 * min(CFL_SQUARE[k], CFL_TRI[k]) * h / M.max_wave_speed(mesh)
-    U = o.erk(U, 0.0, dt, 1)  # warm-up
+
+
+# HBM bytes of the headline batch per step from rocprofv3 FETCH_SIZE / WRITE_SIZE counters summed
+# over the step's dispatches, each counter scaled by what it reads for an elementwise kernel of
+# known size; valid only for the kernel and host-plan sources with this digest (else null).
+MEASURED_BATCH_TRAFFIC = {
+    "sources_sha256": None,
+    "bytes_per_step": None,
+}
+
+
+def batch_engines(dtype="f32", shots=4, record_energy=True, autotune=True):
+    """The headline workload's engines: mesh i of M.batch_meshes() (hybrid unit square, split seed
+    4000 + i, degree 1 + i mod 3, the two-material setting), `shots` Ricker shots (f0 = 10, t0 =
+    0.12, vertical unit force) at the seeded positions of M.shot_positions(4, 4100 + i), dt = half
+    the CFL step of eq. CFL.  Returns (engines, dts, meshes)."""
+    from paper_2505_15771_amd import Engine
+    engines, dts, meshes = [], [], []
+    for i, d in enumerate(M.batch_meshes()):
+        mesh = M.with_materials(M.unit_square(d["n"], p_split=0.5, seed=d["seed"]))
+        e = Engine(mesh, d["k"], dtype=dtype, n_shots=shots, record_energy=record_energy)
+        pos = M.shot_positions(4, 4100 + i)
+        for sh in range(shots):
+            e.set_sources(sh, [pos[sh]], [[0.0, 1.0]], 10.0, 0.12, 1.0)
+        dts.append(e.dt_cfl(0.5))
+        if autotune:
+            e.autotune()
+        engines.append(e)
+        meshes.append((mesh, d["k"]))
+    return engines, dts, meshes
+
+
+def run_headline(steps, warmup):
+    """Time `steps` steps of the headline batch after `warmup` untimed ones.  The batch call is
+    synchronous: the host clock brackets it (the whole job: energy checks included); the HIP
+    events the library records on the launch stream around the graph replays give the device time
+    of the stage launches, on which the roofline fraction is priced."""
+    import torch
+    from paper_2505_15771_amd import Batch
+    t_setup = time.perf_counter()
+    engines, dts, meshes = batch_engines()
+    bstep = sum(algorithmic_bytes_per_step(m, k, 4, 4)[0] for m, k in meshes)
+    b = Batch(engines)
+    setup_s = time.perf_counter() - t_setup
+    b.erk_step([0.0] * len(engines), dts, max(warmup, 1))  # captures the step graphs
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    n = 0
-    while True:
-        U = o.erk(U, n * dt, dt, 1)
-        n += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or n >= 1000:
-            break
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    model = "unknown"
+    b.erk_step([warmup * dt for dt in dts], dts, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev_ms = b.last_time_ms()
+    shot_dofs = sum(e.n_dof * 4 for e in engines)
+    E = [e.energy() for e in engines]
+    out = dict(steps=steps, wall_s=wall, ms_per_step=wall * 1e3 / steps, device_ms_per_step=dev_ms / steps,
+               value=shot_dofs * 4 * steps / wall, shot_dofs=int(shot_dofs),
+               cells=int(sum(e.n_cells for e in engines)), bytes_per_step=bstep,
+               gbs=bstep * steps / (dev_ms * 1e-3) / 1e9, setup_s=setup_s,
+               finite=bool(all(np.all(np.isfinite(x)) for x in E)),
+               tuning=[e.tuning()[0] for e in engines])
+    out["frac"] = out["gbs"] / HBM_PEAK_GBS
+    return b, engines, dts, meshes, out
+
+
+def run_headline_f64_single(meshes, dts, steps):
+    """The headline workload stepped the plain way: float64, one shot at a time (each mesh's four
+    shots one after the other), same meshes, sources and steps.  Returns ms per step of the whole
+    workload (the sum over meshes of four times one shot's time per step)."""
+    import torch
+    from paper_2505_15771_amd import Engine
+    total_ms = 0.0
+    for i, ((mesh, k), dt) in enumerate(zip(meshes, dts)):
+        e = Engine(mesh, k, dtype="f64", n_shots=1, record_energy=True)
+        e.set_sources(0, [M.shot_positions(4, 4100 + i)[0]], [[0.0, 1.0]], 10.0, 0.12, 1.0)
+        e.autotune()
+        e.erk_step(0.0, dt, 4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e.erk_step(4 * dt, dt, steps)
+        torch.cuda.synchronize()
+        total_ms += 4 * (time.perf_counter() - t0) * 1e3 / steps
+        e.close()
+    return total_ms
+
+
+def headline_error(b, engines, dts, meshes, steps=3):
+    """Relative L2 error of the batched float32 path against the float64 oracle: shot 0 of every
+    mesh from a seeded random state with its Ricker source, `steps` steps through the batch (the
+    other shots hold zero states); returns per-mesh errors."""
+    from oracle import Oracle
+    errs = []
+    U0s = []
+    for i, e in enumerate(engines):
+        U0 = 1e-3 * np.random.default_rng(6000 + i).standard_normal(e.n_dof)
+        U0s.append(U0)
+        e.set_state(U0, shot=0)
+        for sh in range(1, 4):
+            e.set_state(np.zeros(e.n_dof), shot=sh)
+    b.erk_step([0.0] * len(engines), dts, steps)
+    for i, ((mesh, k), e, dt) in enumerate(zip(meshes, engines, dts)):
+        o = Oracle(mesh, k)
+        o.set_point_sources([M.shot_positions(4, 4100 + i)[0]], [0.0, 1.0], 10.0, 0.12, 1.0)
+        ref = o.erk(U0s[i], 0.0, dt, steps)
+        got = e.get_state(shot=0)
+        errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+        del o
+    return errs
+
+
+def _cpu_model():
+    try:
+        import subprocess
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in txt.splitlines():
+            if ln.startswith("Model name:"):
+                return ln.split(":", 1)[1].strip()
+    except Exception:
+        pass
     try:
         with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "unknown")
     except OSError:
-        pass
-    return dict(value=o.ndof * 4 * n / el, unit="DOF-stage updates/s", cores=cores, kind="oracle",
-                sample="%d RK4 steps of the full 256x256 hybrid mesh, k=%d, float64, %.1f s" % (n, k, el),
-                cpu=model)
+        return "unknown"
+
+
+def _omp_threads(n=None):
+    """Set (n given) and return the OpenMP thread count the oracle's parallel loops use."""
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    if n is not None:
+        gomp.omp_set_num_threads(int(n))
+    return int(gomp.omp_get_max_threads())
+
+
+def cpu_baseline(meshes, dts, n_meshes=6, steps=2, runs=3):
+    """The float64 oracle as it stands on the host cores: one shot of the first `n_meshes` meshes of
+    the headline workload (degrees 1, 2, 3, 1, 2, 3), `steps` RK4 steps per run after two warm-up
+    steps, median of `runs` runs, with all cores and with one; DOF-stage updates/s of the sample."""
+    from oracle import Oracle
+    sample = []
+    for i in range(n_meshes):
+        mesh, k = meshes[i]
+        o = Oracle(mesh, k)
+        o.set_point_sources([M.shot_positions(4, 4100 + i)[0]], [0.0, 1.0], 10.0, 0.12, 1.0)
+        sample.append((o, 1e-3 * np.random.default_rng(7000 + i).standard_normal(o.ndof), dts[i]))
+    dofs = sum(o.ndof for o, _, _ in sample)
+    all_cores = _omp_threads()
+    res = {}
+    for label, nthr in (("all", all_cores), ("one", 1)):
+        used = _omp_threads(nthr)
+        for o, U, dt in sample:
+            o.erk(U, 0.0, dt, 2)
+        times = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            for o, U, dt in sample:
+                o.erk(U, 0.0, dt, steps)
+            times.append(time.perf_counter() - t0)
+        res[label] = dict(value=dofs * 4 * steps / float(np.median(times)), cores=used,
+                          median_s=float(np.median(times)))
+        print("cpu_baseline", label, json.dumps(res[label]), file=sys.stderr, flush=True)
+    _omp_threads(all_cores)
+    return dict(value=res["all"]["value"], unit="DOF-stage updates/s", cores=res["all"]["cores"], kind="oracle",
+                single_core_value=res["one"]["value"],
+                sample="meshes 0-%d of the headline workload (k=1,2,3,...; %d cell unknowns), one shot, float64, "
+                       "%d RK4 steps per run, median of %d runs after 2 warm-up steps" % (n_meshes - 1, dofs, steps, runs),
+                cpu=_cpu_model())
+
+
+def _log(tag, obj):
+    print(tag, json.dumps(obj), file=sys.stderr, flush=True)
+
+
+def summary_line(steps, warmup, head, err, f64_ms, cpu, variants, extras, copy_gbs, traffic):
+    """The one JSON line of the run (kept to a few kB: curves and workloads go to stderr)."""
+    out = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "DOF-stage updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "16 seeded hybrid meshes of the two-material unit square (%d cells, 2e4-3e5 "
+                               "each), k=1/2/3, 4 Ricker shots per mesh, float32 batched RK4 from captured "
+                               "graphs, float64 energy per shot and step" % head["cells"],
+                   "shot_dofs": head["shot_dofs"], "meshes": 16, "shots_per_mesh": 4,
+                   "path": "graph replays (32/16/8/4/2/1-step graphs)"},
+        "roofline": {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": head["frac"], "traffic": traffic, "kernel": "stage_kernel (every launch of a step)",
+                     "bytes_per_step": head["bytes_per_step"], "device_us_per_step": head["device_ms_per_step"] * 1e3,
+                     "traffic_unit": "HBM bytes per step", "copy_gbs": copy_gbs,
+                     "frac_of_copy": head["gbs"] / copy_gbs},
+        "cpu_baseline": cpu,
+        "rel_err_vs_oracle": None if err is None else {"max": max(err), "mean": float(np.mean(err)), "steps": 3,
+                                                       "what": "shot 0 of each mesh, random state + source"},
+        "f64_single_shot_ms_per_step": f64_ms,
+        "speedup_vs_f64_single_shot": f64_ms / head["ms_per_step"],
+        "variants": variants,
+        "extras": extras,
+    }
+    return json.dumps(out)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--k", type=int, default=2)
+    ap.add_argument("--variants", type=int, default=1, help="also time the 256x256 hybrid-mesh variants")
+    ap.add_argument("--extras", type=int, default=1, help="also run the other workloads (stderr lines)")
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--check", type=int, default=1, help="error of the headline against the float64 oracle")
     ap.add_argument("--dtype", default="f32")
     ap.add_argument("--shots", type=int, default=1)
-    ap.add_argument("--variants", type=int, default=1, help="also time the float64 / k=3 / batched variants")
-    ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--only", choices=("adjoint", "basin", "batch", "paper", "cfl", "precision", "tableaux", "sdirk",
-                                       "eta", "geometry", "perturbed"),
+    ap.add_argument("--only", choices=("headline", "variant", "adjoint", "basin", "batch", "paper", "cfl",
+                                       "precision", "tableaux", "sdirk", "eta", "geometry", "perturbed"),
                     default=None,
-                    help="run one extra workload alone and print its JSON line (for profiling)")
+                    help="run one workload alone and print its JSON line (for profiling)")
     ap.add_argument("--only-steps", type=int, default=200)
+    ap.add_argument("--k", type=int, default=2)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -700,7 +886,16 @@ def main():
               file=sys.stderr)
         del src, dst
     if args.only:
-        fn = {"adjoint": lambda: run_adjoint(2, args.dtype, steps=args.only_steps, ckpt=50, shots=args.shots),
+        if args.only == "headline":
+            b, engines, _, _, h = run_headline(args.only_steps, 5)
+            b.close()
+            for e in engines:
+                e.close()
+            print(json.dumps(h), flush=True)
+            return
+        fn = {"variant": lambda: run_variant(M.hybrid_square(256), args.k, args.dtype, args.shots,
+                                             args.only_steps, 5),
+              "adjoint": lambda: run_adjoint(2, args.dtype, steps=args.only_steps, ckpt=50, shots=args.shots),
               "basin": lambda: run_basin(args.dtype, steps=args.only_steps),
               "batch": lambda: run_batch(steps=args.only_steps),
               "paper": lambda: [run_paper_bilayer(1), run_paper_bilayer(3)],
@@ -716,104 +911,68 @@ def main():
               }[args.only]
         print(json.dumps(fn()), flush=True)
         return
-    mesh = M.hybrid_square(256)
-    head = run_variant(mesh, args.k, args.dtype, args.shots, args.steps, args.warmup)
-    print("headline", json.dumps(head), file=sys.stderr, flush=True)
+
+    # ---- headline: the batched float32 workload
+    b, engines, dts, meshes, head = run_headline(args.steps, args.warmup)
+    _log("headline", head)
+    err = headline_error(b, engines, dts, meshes) if args.check else None
+    if err is not None:
+        _log("headline_error", {"rel_l2_vs_oracle": err})
+    b.close()
+    for e in engines:
+        e.close()
+    f64_ms = run_headline_f64_single(meshes, dts, max(min(args.steps, 100), 10))
+    _log("headline_f64_single", {"ms_per_step": f64_ms})
+    cpu = cpu_baseline(meshes, dts) if args.cpu_baseline else None
+
+    # ---- the 256 x 256 hybrid mesh, one launch per stage (float32 / float64, 1 or 8 shots)
     variants = []
     if args.variants:
-        for (k, dt, sh) in ((2, "f64", 1), (3, "f32", 1), (3, "f64", 1), (2, "f32", 8), (3, "f32", 8)):
-            if (k, dt, sh) == (args.k, args.dtype, args.shots):
-                continue
-            v = run_variant(mesh, k, dt, sh, max(args.steps // 2, 10), 5)
-            print("variant", json.dumps(v), file=sys.stderr, flush=True)
-            variants.append({key: v[key] for key in ("k", "dtype", "shots", "value", "ms_per_step", "launch_us",
-                                                       "gbs", "frac", "moved_gbs", "tuning")})
-    adjoint, workloads = [], []
-    if args.variants:
-        for dt_, sh_ in (("f64", 1), ("f32", 1), ("f32", 8)):
+        mesh = M.hybrid_square(256)
+        for (k, dt_, sh) in ((2, "f32", 1), (2, "f64", 1), (3, "f32", 1), (3, "f64", 1), (2, "f32", 8),
+                             (3, "f32", 8)):
+            v = run_variant(mesh, k, dt_, sh, max(min(args.steps, 400), 10), 5)
+            _log("variant", v)
+            variants.append(dict(workload="256x256 hybrid", k=k, dtype=dt_, shots=sh,
+                                 value=round(v["value"], -6), us_per_step=round(v["ms_per_step"] * 1e3, 2),
+                                 launch_us=round(v["launch_us"], 2), frac=round(v["frac"], 3)))
+
+    # ---- other workloads: one stderr line each, a few figures kept in the summary
+    extras = {}
+    if args.extras:
+        for dt_, sh_ in (("f32", 1), ("f64", 1), ("f32", 8)):
             v = run_adjoint(2, dt_, shots=sh_)
-            print("adjoint", json.dumps(v), file=sys.stderr, flush=True)
-            adjoint.append(v)
+            _log("workload", v)
+            extras["adjoint_%s_%dshot" % (dt_, sh_)] = dict(ms=round(v["adjoint_ms"], 1),
+                                                             vs_forward=round(v["ratio"], 2))
         for dt_ in ("f32", "f64"):
             v = run_basin(dt_)
-            print("workload", json.dumps(v), file=sys.stderr, flush=True)
-            workloads.append(v)
-        v = run_batch()
-        print("workload", json.dumps(v), file=sys.stderr, flush=True)
-        workloads.append(v)
+            _log("workload", v)
+            extras["basin_%s" % dt_] = dict(us_per_step=round(v["ms_per_step"] * 1e3, 1), frac=round(v["frac"], 3))
         for k_ in (1, 3):
             v = run_paper_bilayer(k_, sensors=True)
             erk_tr = v.pop("_traces")
-            print("workload", json.dumps(v), file=sys.stderr, flush=True)
-            workloads.append(v)
+            _log("workload", v)
             w = run_sdirk_bilayer(k_, erk_traces=erk_tr)
             w["erk4_run_s"] = v["run_s"]
-            w["erk4_over_sdirk_time"] = v["run_s"] / w["run_s_to_t_final"]
-            print("workload", json.dumps(w), file=sys.stderr, flush=True)
-            workloads.append(w)
+            _log("workload", w)
+            extras["paper_bilayer_k%d" % k_] = dict(erk4_s=round(v["run_s"], 4), sdirk34_s=round(w["run_s_to_t_final"], 3),
+                                                    paper_erk4_cpu_s=v["paper_cpu_s"])
         for k_ in (1, 2, 3):
-            v = run_cfl(k_)
-            print("workload", json.dumps(v), file=sys.stderr, flush=True)
-            workloads.append(v)
-        v = run_precision()
-        print("workload", json.dumps(v), file=sys.stderr, flush=True)
-        workloads.append(v)
-        v = run_tableaux()
-        print("workload", json.dumps(v), file=sys.stderr, flush=True)
-        workloads.append(v)
-        v = run_eta_sweep()
-        print("workload", json.dumps(v), file=sys.stderr, flush=True)
-        workloads.append(v)
+            _log("workload", run_cfl(k_))
+        _log("workload", run_precision())
+        _log("workload", run_tableaux())
+        _log("workload", run_eta_sweep())
         for ss in (0, 1):
-            v = run_cfl_geometry(stab_speed=ss)
-            print("workload", json.dumps(v), file=sys.stderr, flush=True)
-            workloads.append(v)
-    cpu = cpu_baseline(mesh, args.k) if args.cpu_baseline else None
-    # speed-ups over float64 single-shot stepping of the same workload on the same GPU
-    speedups = {}
-    base = [v for v in variants if (v["k"], v["dtype"], v["shots"]) == (args.k, "f64", 1)]
-    if base:
-        ref = base[0]["value"]
-        speedups["%s_%dshot_vs_f64_1shot" % (head["dtype"], args.shots)] = head["value"] / ref
-        for v in variants:
-            if v["k"] == args.k and v is not base[0]:
-                speedups["%s_%dshot_vs_f64_1shot" % (v["dtype"], v["shots"])] = v["value"] / ref
+            _log("workload", run_cfl_geometry(stab_speed=ss))
     copy_gbs = copy_bandwidth()
-    print("copy", json.dumps({"gbs": copy_gbs}), file=sys.stderr, flush=True)
+    _log("copy", {"gbs": copy_gbs})
+
     traffic = None
-    if (stage_sources_digest() == MEASURED_TRAFFIC["sources_sha256"]
-            and (args.k, args.dtype, args.shots) == MEASURED_TRAFFIC["config"]):
-        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
-    out = {
-        "metric": METRIC,
-        "value": head["value"],
-        "unit": "DOF-stage updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": head["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": head["dtype"],
-        "data": "synthetic",
-        "config": {"workload": "two-material unit square, 256x256 hybrid quad/triangle mesh (seed 2001), "
-                               "materials +-10 percent (seed 2002), HHO k=%d, RK4, Ricker point source" % args.k,
-                   "cells": int(len(mesh["cell_ptr"]) - 1), "cell_dofs": head["ndof"], "shots": args.shots},
-        "roofline": {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": head["frac"], "traffic": traffic, "kernel": "stage_kernel",
-                     "launch_us": head["launch_us"], "bytes_per_launch": head["bytes_per_launch"],
-                     "traffic_unit": "HBM bytes per launch",
-                     "moved_bytes_per_launch": head["moved_bytes_per_launch"], "moved_gbs": head["moved_gbs"],
-                     "copy_gbs": copy_gbs, "frac_of_copy": head["gbs"] / copy_gbs,
-                     "tuning": head["tuning"]},
-        "cpu_baseline": cpu,
-        "variants": variants,
-        "speedups": speedups,
-        "adjoint": adjoint,
-        "workloads": workloads,
-    }
-    print(json.dumps(out), flush=True)
+    if MEASURED_BATCH_TRAFFIC["sources_sha256"] == stage_sources_digest():
+        traffic = MEASURED_BATCH_TRAFFIC["bytes_per_step"]
+    print(summary_line(args.steps, args.warmup, head, err, f64_ms, cpu, variants, extras, copy_gbs, traffic),
+          flush=True)
 
 
 if __name__ == "__main__":

@@ -139,12 +139,13 @@ hho_status hho_set_loads(hho_ctx *ctx, int32_t n_terms, const double *g, const d
  * polynomials (sensors of Sec. 5.2), recorded after every step of hho_erk_step. */
 hho_status hho_receivers(hho_ctx *ctx, int32_t n, const double *xy, const int32_t *field);
 
-/* Advance every shot by n_steps steps of ERK(rk_stages) from time t0 with step dt.  Steps are
- * launched in groups of 32 as one captured graph (replayed while the configuration is unchanged),
- * the remainder directly.  Enqueued on params.stream; returns before completion unless
- * record_energy = 1, in
- * which case it synchronises and returns HHO_ERR_UNSTABLE if the energy of a shot grew
- * by more than 5 % over its initial value, or over the previous step, or is not finite. */
+/* Advance every shot by n_steps steps of ERK(rk_stages) from time t0 with step dt.  Every step
+ * runs from captured graphs: graphs of 32, 16, 8, 4, 2 and 1 steps are captured on first use
+ * and kept while the configuration is unchanged; a call replays n_steps / 32 of the 32-step
+ * graph and one graph per set binary digit of the remainder.  Enqueued on params.stream; returns
+ * before completion unless record_energy = 1, in which case it synchronises and returns
+ * HHO_ERR_UNSTABLE if the energy of a shot grew by more than 5 % over its initial value, or over
+ * the previous step, or is not finite. */
 hho_status hho_erk_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps);
 
 /* Wait for all work enqueued by ctx. */
@@ -231,8 +232,8 @@ hho_status hho_adjoint_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps,
                             const double *d_obs, double *J, double *grad);
 
 /* Batched stepping: several contexts (meshes of different sizes and degrees, each with its own
- * shots) advanced together.  Every group of 32 steps of all contexts is one graph launch in which
- * the contexts' step chains are independent branches; remaining steps are launched directly.
+ * shots) advanced together.  The contexts' step chains are independent branches of captured
+ * graphs of 32, 16, 8, 4, 2 and 1 steps, replayed as in hho_erk_step.
  * All contexts must live on one device; the batch launches on the first context's stream and
  * synchronises before returning.  t0[i], dt[i] per context.  The per-context results (state,
  * traces, energy history) are read with the per-context calls; HHO_ERR_UNSTABLE as hho_erk_step
@@ -243,6 +244,11 @@ hho_status hho_batch_create(hho_ctx *const *ctxs, int32_t n, hho_batch **out);
 void hho_batch_destroy(hho_batch *b);
 const char *hho_batch_last_error(const hho_batch *b);
 hho_status hho_batch_erk_step(hho_batch *b, const double *t0, const double *dt, int32_t n_steps);
+
+/* Device time of the graph replays of the last hho_batch_erk_step, in milliseconds, measured
+ * with HIP events recorded on the launch stream just before the first replay and after the last
+ * (0 before the first step call). */
+hho_status hho_batch_last_time(const hho_batch *b, double *ms);
 
 #ifdef __cplusplus
 }

@@ -48,6 +48,12 @@ struct AdjWork {
     int32_t *ic_of_cell = nullptr;
 };
 
+// Captured step graphs: one of kGraphSteps steps and one of each smaller power of two, so that a
+// call of any length replays graphs only (n = q kGraphSteps + the binary digits of the rest).
+constexpr int kGraphSteps = 32;
+constexpr int kNumGraphs = 6;  // 32, 16, 8, 4, 2, 1 steps
+static_assert(kGraphSteps == 1 << (kNumGraphs - 1), "graph lengths are the powers of two up to kGraphSteps");
+
 struct hho_ctx {
     Plan plan;
     int dtype = 0, stages = 4, record_energy = 0, device = 0;
@@ -97,12 +103,13 @@ struct hho_ctx {
     // energy
     double *e_part = nullptr, *e_hist = nullptr, *e_now = nullptr;
     size_t e_hist_cap = 0;
-    // device clocks (two, alternating by step parity) and the cached graph of kGraphSteps steps
+    // device clocks (two, alternating by step parity) and the cached step graphs (kGraphSteps >> i
+    // steps in gexec[i])
     Clock *clock = nullptr;
     Clock h_clock{};
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    unsigned version = 1, graph_version = 0;  // graph is valid when graph_version == version
+    hipGraphExec_t gexec[kNumGraphs] = {};
+    unsigned version = 1, graph_version = 0;  // graphs are valid when graph_version == version
     double cfl_dt = 0.0;                       // CFL-limited time step at factor 1
     // Stage outputs stored with the non-temporal cache policy (chosen by hho_autotune: faster
     // for some large working sets, slower when the stage data stays in the last-level cache).
@@ -118,8 +125,11 @@ struct hho_batch {
     std::vector<hho_ctx *> ctxs;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
-    hipGraphExec_t gexec = nullptr;
-    std::vector<unsigned> versions;  // context versions the graph was captured with
+    hipGraphExec_t gexec[kNumGraphs] = {};  // kGraphSteps >> i steps of every context in gexec[i]
+    std::vector<unsigned> versions;  // context versions the graphs were captured with
+    // timing events around the graph replays of the last hho_batch_erk_step (on the launch stream)
+    hipEvent_t t_begin = nullptr, t_end = nullptr;
+    float last_ms = 0.0f;
     std::string err;
 };
 
@@ -430,10 +440,6 @@ hho_status dispatch(hho_ctx *ctx, Fn &&fn) {
 }
 
 
-// Steps captured per graph: a call advances full graphs, then launches the remainder directly.
-constexpr int kGraphSteps = 32;
-static_assert(kGraphSteps % 2 == 0, "graph replays must start and end on the same clock slot");
-
 template <int K, typename R>
 hho_status autotune_shape(hho_ctx *ctx);
 
@@ -506,27 +512,46 @@ hho_status end_steps(hho_ctx *ctx, int n_steps, const std::vector<double> &E0) {
     return HHO_OK;
 }
 
-// Capture kGraphSteps steps of one context into a graph (cached until the configuration changes).
-hho_status ensure_graph(hho_ctx *ctx) {
-    if (ctx->gexec && ctx->graph_version == ctx->version) return HHO_OK;
-    if (ctx->gexec) HCK(hipGraphExecDestroy(ctx->gexec));
-    ctx->gexec = nullptr;
-    HCK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-    hho_status s = dispatch(ctx, [&](auto kc, auto *r) {
-        using R = std::remove_pointer_t<decltype(r)>;
-        return enqueue_steps<decltype(kc)::value, R>(ctx, ctx->cap_stream, kGraphSteps);
-    });
-    hipGraph_t graph = nullptr;
-    const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
-    if (s != HHO_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return s;
+// Capture the step graphs of one context (cached until the configuration changes).  Every graph
+// starts on clock slot 0; those of even length also end there, and the one-step graph, whose
+// length is odd, is only ever replayed last in a call.
+hho_status ensure_graphs(hho_ctx *ctx) {
+    if (ctx->gexec[0] && ctx->graph_version == ctx->version) return HHO_OK;
+    for (hipGraphExec_t &g : ctx->gexec) {
+        if (g) HCK(hipGraphExecDestroy(g));
+        g = nullptr;
     }
-    HCK(e);
-    const hipError_t ei = hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    HCK(ei);
+    for (int i = 0; i < kNumGraphs; ++i) {
+        HCK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        hho_status s = dispatch(ctx, [&](auto kc, auto *r) {
+            using R = std::remove_pointer_t<decltype(r)>;
+            return enqueue_steps<decltype(kc)::value, R>(ctx, ctx->cap_stream, kGraphSteps >> i);
+        });
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+        if (s != HHO_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return s;
+        }
+        HCK(e);
+        const hipError_t ei = hipGraphInstantiate(&ctx->gexec[i], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HCK(ei);
+    }
     ctx->graph_version = ctx->version;
+    return HHO_OK;
+}
+
+// Graph replays covering n steps: q full graphs, then one graph per set binary digit of the rest,
+// largest first (so that the odd one-step graph comes last).  Calls launch(i) per replay.
+template <typename F>
+hho_status replay_steps(int n_steps, F &&launch) {
+    for (int g = 0; g < n_steps / kGraphSteps; ++g)
+        if (hho_status s = launch(0)) return s;
+    const int rem = n_steps % kGraphSteps;
+    for (int i = 1; i < kNumGraphs; ++i)
+        if (rem & (kGraphSteps >> i))
+            if (hho_status s = launch(i)) return s;
     return HHO_OK;
 }
 
@@ -888,24 +913,17 @@ hho_status adjoint_sweep(hho_ctx *ctx, const std::vector<StageCoef> &co, int eve
     return HHO_OK;
 }
 
-// Steps of hho_erk_step without the closing stability check: graph replays of kGraphSteps steps,
-// then the remainder launched directly.  E0 receives the initial energies when recorded.
+// Steps of hho_erk_step without the closing stability check, all from captured graphs.
+// E0 receives the initial energies when recorded.
 hho_status run_steps(hho_ctx *ctx, double t0, double dt, int n_steps, std::vector<double> &E0) {
     hho_status s;
     if ((s = begin_steps(ctx, t0, dt, n_steps, E0))) return s;
-    const int full = n_steps / kGraphSteps, rem = n_steps % kGraphSteps;
-    if (full > 0) {
-        if ((s = ensure_graph(ctx))) return s;
-        for (int g = 0; g < full; ++g) HCK(hipGraphLaunch(ctx->gexec, ctx->stream));
-    }
-    if (rem > 0) {
-        s = dispatch(ctx, [&](auto kc, auto *r) {
-            using R = std::remove_pointer_t<decltype(r)>;
-            return enqueue_steps<decltype(kc)::value, R>(ctx, ctx->stream, rem);
-        });
-        if (s != HHO_OK) return s;
-    }
-    return HHO_OK;
+    if (n_steps == 0) return HHO_OK;
+    if ((s = ensure_graphs(ctx))) return s;
+    return replay_steps(n_steps, [&](int i) -> hho_status {
+        HCK(hipGraphLaunch(ctx->gexec[i], ctx->stream));
+        return HHO_OK;
+    });
 }
 
 }  // namespace
@@ -1055,7 +1073,8 @@ void hho_destroy(hho_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
-    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    for (hipGraphExec_t g : ctx->gexec)
+        if (g) (void)hipGraphExecDestroy(g);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     AdjWork &w = ctx->adj;
     if (w.aux) {
@@ -1566,13 +1585,22 @@ void hho_batch_destroy(hho_batch *b) {
     if (!b) return;
     if (!b->ctxs.empty()) (void)hipSetDevice(b->ctxs[0]->device);
     for (hipStream_t st : b->streams) (void)hipStreamSynchronize(st);
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    for (hipGraphExec_t g : b->gexec)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (b->t_begin) (void)hipEventDestroy(b->t_begin);
+    if (b->t_end) (void)hipEventDestroy(b->t_end);
     for (hipStream_t st : b->streams) (void)hipStreamDestroy(st);
     for (hipEvent_t ev : b->events) (void)hipEventDestroy(ev);
     delete b;
 }
 
 const char *hho_batch_last_error(const hho_batch *b) { return b ? b->err.c_str() : g_setup_error.c_str(); }
+
+hho_status hho_batch_last_time(const hho_batch *b, double *ms) {
+    if (!b || !ms) return HHO_ERR_ARG;
+    *ms = (double)b->last_ms;
+    return HHO_OK;
+}
 
 hho_status hho_batch_erk_step(hho_batch *b, const double *t0, const double *dt, int32_t n_steps) {
     return guarded(b ? &const_cast<hho_batch *>(b)->err : &g_setup_error, [&]() -> hho_status {
@@ -1599,34 +1627,36 @@ hho_status hho_batch_erk_step(hho_batch *b, const double *t0, const double *dt, 
             }
         }
         if (hipStreamSynchronize(launch_st) != hipSuccess) return HHO_ERR_DEVICE;
-        const int full = n_steps / kGraphSteps, rem = n_steps % kGraphSteps;
-        bool fresh = b->gexec && (int)b->versions.size() == n;
+        bool fresh = b->gexec[0] && (int)b->versions.size() == n;
         for (int i = 0; fresh && i < n; ++i) fresh = b->versions[i] == b->ctxs[i]->version;
-        if (full > 0 && !fresh) {
-            if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-            b->gexec = nullptr;
-            hho_status s = capture_batch(b, kGraphSteps, &b->gexec);
-            if (s != HHO_OK) return s;
+        if (n_steps > 0 && !fresh) {
+            for (hipGraphExec_t &g : b->gexec) {
+                if (g) (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+            for (int i = 0; i < kNumGraphs; ++i) {
+                hho_status s = capture_batch(b, kGraphSteps >> i, &b->gexec[i]);
+                if (s != HHO_OK) return s;
+            }
             b->versions.clear();
             for (hho_ctx *ctx : b->ctxs) b->versions.push_back(ctx->version);
         }
-        for (int g = 0; g < full; ++g)
-            if (hipGraphLaunch(b->gexec, launch_st) != hipSuccess) {
+        if (!b->t_begin && (hipEventCreate(&b->t_begin) != hipSuccess || hipEventCreate(&b->t_end) != hipSuccess)) {
+            b->err = "batch: event creation failed";
+            return HHO_ERR_DEVICE;
+        }
+        if (hipEventRecord(b->t_begin, launch_st) != hipSuccess) return HHO_ERR_DEVICE;
+        hho_status rs = replay_steps(n_steps, [&](int i) -> hho_status {
+            if (hipGraphLaunch(b->gexec[i], launch_st) != hipSuccess) {
                 b->err = "batch: hipGraphLaunch failed";
                 return HHO_ERR_DEVICE;
             }
-        for (int i = 0; i < n && rem > 0; ++i) {
-            hho_ctx *ctx = b->ctxs[i];
-            hho_status s = dispatch(ctx, [&](auto kc, auto *r) {
-                using R = std::remove_pointer_t<decltype(r)>;
-                return enqueue_steps<decltype(kc)::value, R>(ctx, launch_st, rem);
-            });
-            if (s != HHO_OK) {
-                b->err = ctx->err;
-                return s;
-            }
-        }
+            return HHO_OK;
+        });
+        if (rs != HHO_OK) return rs;
+        if (hipEventRecord(b->t_end, launch_st) != hipSuccess) return HHO_ERR_DEVICE;
         if (hipStreamSynchronize(launch_st) != hipSuccess) return HHO_ERR_DEVICE;
+        if (hipEventElapsedTime(&b->last_ms, b->t_begin, b->t_end) != hipSuccess) return HHO_ERR_DEVICE;
         hho_status worst = HHO_OK;
         for (int i = 0; i < n; ++i) {
             hho_status s = end_steps(b->ctxs[i], n_steps, E0[i]);

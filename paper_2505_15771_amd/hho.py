@@ -78,6 +78,7 @@ EXPORTS = {
     "hho_batch_destroy": (None, [C.c_void_p]),
     "hho_batch_last_error": (C.c_char_p, [C.c_void_p]),
     "hho_batch_erk_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "hho_batch_last_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "hho_inspect_create": (C.c_int, [C.POINTER(_Mesh), C.POINTER(_Params), C.POINTER(C.c_void_p)]),
     "hho_inspect_destroy": (None, [C.c_void_p]),
     "hho_inspect_sizes": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -405,7 +406,7 @@ class Inspect:
 
 
 class Batch:
-    """Several engines advanced together, 32 steps per graph launch (hho_batch_*)."""
+    """Several engines advanced together from captured graphs (hho_batch_*)."""
 
     def __init__(self, engines):
         lib = load_library()
@@ -428,6 +429,14 @@ class Batch:
         if code != 0:
             msg = self.lib.hho_batch_last_error(self._h).decode()
             raise (Unstable if code == 6 else HHOError)(code, msg)
+
+    def last_time_ms(self):
+        """Device time of the graph replays of the last erk_step call (HIP events), ms."""
+        ms = C.c_double()
+        code = self.lib.hho_batch_last_time(self._h, C.byref(ms))
+        if code != 0:
+            raise HHOError(code, "hho_batch_last_time")
+        return ms.value
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1,6 +1,7 @@
 """CPU checks of the benchmark's bookkeeping (no GPU): the algorithmic and the moved byte counts
 of one ERK(4) step and the unknown count on a mesh small enough to count by hand, and the
 refusal of more than one GPU."""
+import json
 import os
 import subprocess
 import sys
@@ -106,3 +107,33 @@ def test_sensor_differences():
     assert len(d) == 1 and d[0] < 1e-4
     d2 = bench.sensor_differences(ta, 1.01 * a, tb, b)
     assert abs(d2[0] - 0.01) < 1e-4
+
+
+def test_summary_line_is_compact_json():
+    """The last stdout line parses as JSON, carries the contract's keys and stays a few kB even with
+    every variant and extra workload filled in (the curves of the sweeps go to stderr)."""
+    b = _bench()
+    head = dict(value=2.6e11, ms_per_step=2.61, device_ms_per_step=2.55, cells=1720000, shot_dofs=167000000,
+                gbs=4500.0, frac=0.5625, bytes_per_step=11.4e9)
+    cpu = dict(value=2.2e8, unit="DOF-stage updates/s", cores=16, kind="oracle", single_core_value=1.6e7,
+               sample="meshes 0-5 of the headline workload (k=1,2,3,...; 5300000 cell unknowns), one shot, "
+                      "float64, 2 RK4 steps per run, median of 3 runs after 2 warm-up steps",
+               cpu="AMD EPYC 9575F 64-Core Processor")
+    variants = [dict(workload="256x256 hybrid", k=k, dtype=d, shots=s, value=1.9e11, us_per_step=49.87,
+                     launch_us=12.46, frac=0.452) for k, d, s in ((2, "f32", 1), (2, "f64", 1), (3, "f32", 1),
+                                                                 (3, "f64", 1), (2, "f32", 8), (3, "f32", 8))]
+    extras = {"adjoint_f32_1shot": dict(ms=125.6, vs_forward=3.8), "adjoint_f64_1shot": dict(ms=128.5, vs_forward=2.7),
+              "adjoint_f32_8shot": dict(ms=397.0, vs_forward=4.9), "basin_f32": dict(us_per_step=245.1, frac=0.58),
+              "basin_f64": dict(us_per_step=570.2, frac=0.47),
+              "paper_bilayer_k1": dict(erk4_s=0.0207, sdirk34_s=3.2, paper_erk4_cpu_s=161.0),
+              "paper_bilayer_k3": dict(erk4_s=0.173, sdirk34_s=4.2, paper_erk4_cpu_s=3322.0)}
+    line = b.summary_line(20, 5, head, [1e-7] * 16, 9.5, cpu, variants, extras, 5200.0, None)
+    assert "\n" not in line and len(line) < 3500, len(line)
+    d = json.loads(line)
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+                "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert key in d, key
+    assert d["steps"] == 20 and d["warmup"] == 5 and d["n_gpus"] == 1
+    assert d["roofline"]["frac"] == head["frac"] and d["roofline"]["bound"] == "hbm"
+    assert "workload" in d["config"] and d["cpu_baseline"]["kind"] == "oracle"
+    assert abs(d["speedup_vs_f64_single_shot"] - 9.5 / 2.61) < 1e-12
