@@ -81,7 +81,9 @@ typedef struct {
  *   k            polynomial degree, 1..3 (k >= 1 is needed in the solid, Sec. 3.2)
  *   rk_stages    ERK(s) of eq. ERK: 2 (midpoint), 3 (Kutta), 4 (classical)
  *   eta_f, eta_s stabilisation weights (0.8 and 1.5 in Sec. 5.1)
- *   stab_speed   speed c^s in tau^s = eta^s rho c^s: 0 = P-wave, 1 = S-wave speed
+ *   stab_speed   speed c^s in tau^s = eta^s rho c^s (Sec. 3.3 leaves c^s undefined): 1 = S-wave
+ *                speed, under which the stability-optimal solid weight is the paper's eta^s = 1.5
+ *                (Sec. 5.1, Figure CFL_decoupled; the recommended setting), 0 = P-wave speed
  *   dtype        0 = float64 stepping; 1 = float32 stepping (float32 matvecs and
  *                accumulation, factors formed in float64 and rounded, float64 energy)
  *   n_shots      number of independent right-hand sides advanced together (1..256)
@@ -118,6 +120,22 @@ hho_status hho_sizes(const hho_ctx *ctx, int64_t *n_dof, int32_t *n_cells, int32
  * on_device = 1: U is a device pointer.  Synchronous with respect to the host. */
 hho_status hho_set_state(hho_ctx *ctx, int32_t shot, const double *U, int32_t on_device);
 hho_status hho_get_state(hho_ctx *ctx, int32_t shot, double *U, int32_t on_device);
+
+/* Initial state of eq. ricker_ic (Sec. 5.2) for one shot, replacing its state: the L2 projection
+ * onto the cell bases of the Ricker-shaped field centred at (xc, yc) with
+ * g = theta exp(-pi^2 r^2 / lambda^2), r the distance to the centre (the paper takes
+ * lambda = c_P^f / f_c, f_c = 10 Hz, theta = 1 Hz):
+ *   field 1  the printed initial velocity g (x - xc, y - yc): the m rows of fluid cells and the v
+ *            rows of solid cells, every other unknown 0;
+ *   field 0  the pressure pulse of the granite-water case (built, the paper says, from the same
+ *            right-hand side; read as the scalar amplitude g): the p rows of fluid cells, every
+ *            other unknown 0.
+ * Computed on the host in float64: a fan of triangles from the cell centroid, each with a
+ * 12 x 12 collapsed Gauss-Legendre rule; the coefficients are the moments (f, phi_a)_T of the
+ * orthonormal basis.  Synchronous.  Errors: ARG (shot out of range, lambda <= 0, non-finite
+ * values, field not 0 / 1). */
+hho_status hho_set_ricker_ic(hho_ctx *ctx, int32_t shot, double xc, double yc, double theta, double lambda,
+                             int32_t field);
 
 /* Point sources of one shot (replaces earlier ones of that shot).  Source i is the load
  * vector of eq. rhs for the point force  amp_i R_i(t) d_i delta(x - x_i):  on the v rows of
@@ -205,10 +223,15 @@ hho_status hho_cfl_search(hho_ctx *ctx, double t_final, int32_t n_start, double 
                           double *growth, int32_t cap, int32_t *n_tried);
 
 /* Time step from the CFL condition (eq. CFL, Sec. 5.1): dt = factor * min over cells of
- * CFL*(s, k, shape) h_T / c_T.  CFL* is the paper's Table tab::ratio_geo value for the cell's
- * shape (triangle, square; five or more faces use the hexagon column), c_T the largest wave speed
- * of the cell (c, or c_P in the solid) and h_T the side of the generating square (sqrt of the area,
- * sqrt of twice the area for triangles). */
+ * CFL*(s, k, shape) h_T / c_T, with c_T the largest wave speed of the cell (c, or c_P in the
+ * solid), the shape from the cell's geometric corners (hanging nodes are not corners: 3 triangle,
+ * 4 quadrilateral, 5 or more the hexagon column) and h_T the side of the generating square (sqrt
+ * of the area, sqrt of twice the area for triangles).  CFL* is the paper's Table tab::ratio_geo
+ * value, lowered to 0.9 times this discretisation's own stability limit for that shape where
+ * that is smaller (with tau^s on c_S: triangles 0.90 and hexagons 0.66 of the paper's ERK(4) k = 1
+ * value; with tau^s on c_P also squares), so factor 1 is a stable step for the weights
+ * eta^f = 0.8, eta^s = 1.5 on the meshes tested (squares, triangles, hybrid, hanging nodes,
+ * hexagons, moved vertices).  Other weights move the limit: measure it with hho_cfl_search. */
 hho_status hho_dt_cfl(const hho_ctx *ctx, double factor, double *dt);
 
 /* Receiver misfit and its gradient with respect to the cell materials, by the discrete adjoint

@@ -56,7 +56,7 @@ hho_status hho_inspect_cell_tables(const hho_inspect *p, int32_t *ic_tab, int32_
 /* Material derivatives used by the adjoint gradient (hho_adjoint_step), gm[8][n_ic], float64:
  *   fluid (parameters rho, c; kappa = rho c^2, tau = eta / (rho c)):
  *     d(1/kappa)/drho, d(1/kappa)/dc, dtau/drho, dtau/dc, 0, 0, 0, 0
- *   solid (parameters rho, lambda, mu; tau = eta rho c_P, or eta rho c_S with stab_speed 1):
+ *   solid (parameters rho, lambda, mu; tau = eta rho c_S with stab_speed 1, or eta rho c_P with stab_speed 0):
  *     dtau/drho, dtau/dlambda, dtau/dmu, dA/dlambda (= dB/dlambda), dA/dmu, dB/dmu, dC/dmu, 0
  *   with [[A, B, 0], [B, A, 0], [0, 0, C]] the compliance in the symmetric-tensor basis
  *   (the stress mass matrix of eq. mass); padding cells hold zeros. */

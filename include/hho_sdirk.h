@@ -45,7 +45,7 @@ typedef struct hho_sdirk hho_sdirk; /* opaque; owns its device buffers */
  *   mixed       1: primal cell degree k + 1, Lehrenfeld-Schoberl; 0: degree k, least squares
  *   alpha       0 or 1: stabilisation weights times (h_T / l_Omega)^(-alpha)
  *   eta_f/_s    stabilisation weights (> 0)
- *   stab_speed  c^s in tau^s: 0 = P-wave speed, 1 = S-wave speed
+ *   stab_speed  c^s in tau^s: 1 = S-wave speed (the reading hho.h recommends), 0 = P-wave speed
  *   ell         l_Omega (> 0), or 0 for the diameter of the mesh (largest distance between two
  *               boundary vertices)
  *   stages      s of SDIRK(s, s+1): 1, 2 or 3
@@ -82,6 +82,13 @@ hho_status hho_sdirk_sizes(const hho_sdirk *ctx, int64_t *n_dof, int32_t *n_face
 /* State in / out in the external layout (n_dof float64); on_device = 1 for a device pointer.
  * Synchronous with respect to the host. */
 hho_status hho_sdirk_set_state(hho_sdirk *ctx, const double *U, int32_t on_device);
+
+/* The initial state of eq. ricker_ic (Sec. 5.2), as hho_set_ricker_ic of hho.h: field 1 the
+ * velocity g (x - xc, y - yc) on the m rows (degree k) of fluid cells and the v rows (degree k')
+ * of solid cells, field 0 the pressure pulse g on the p rows (degree k') of fluid cells; L2
+ * projections on the host in float64.  Errors: ARG. */
+hho_status hho_sdirk_set_ricker_ic(hho_sdirk *ctx, double xc, double yc, double theta, double lambda,
+                                   int32_t field);
 hho_status hho_sdirk_get_state(hho_sdirk *ctx, double *U, int32_t on_device);
 
 /* Point sources, as hho_set_sources of hho.h (Ricker time factor, v rows of a solid cell or

@@ -110,7 +110,7 @@ def domain_diameter(mesh):
 class ImplicitOracle:
     """Global FP64 assembly of M and K, SDIRK stepping by sparse LU of the full stage system."""
 
-    def __init__(self, mesh, k, mixed=True, alpha=1, eta_f=1.0, eta_s=1.0, stab_speed=0, ell=None):
+    def __init__(self, mesh, k, mixed=True, alpha=1, eta_f=1.0, eta_s=1.0, stab_speed=1, ell=None):
         self.mesh, self.k, self.mixed, self.alpha = mesh, k, mixed, alpha
         self.kp = k + 1 if mixed else k
         self.N = (k + 1) * (k + 2) // 2

@@ -36,7 +36,7 @@ class MisfitProblem:
     ckpt_every: int = 0
     eta_f: float = 0.8
     eta_s: float = 1.5
-    stab_speed: int = 0
+    stab_speed: int = 1
 
     @property
     def n_shots(self):

@@ -14,6 +14,7 @@
 
 #include "../../include/hho.h"
 #include "device.h"
+#include "initial.h"
 #include "plan.h"
 
 using namespace hho;
@@ -100,9 +101,12 @@ struct hho_ctx {
     double *rec_out = nullptr;
     size_t rec_cap = 0;
     int last_steps = 0;
-    // energy
+    // energy; pinned host copies of the initial energies and of the recorded history, so that a
+    // batch reads every context's energies with one synchronisation
     double *e_part = nullptr, *e_hist = nullptr, *e_now = nullptr;
     size_t e_hist_cap = 0;
+    double *h_e0 = nullptr, *h_ehist = nullptr;
+    size_t h_ehist_cap = 0;
     // device clocks (two, alternating by step parity) and the cached step graphs (kGraphSteps >> i
     // steps in gexec[i])
     Clock *clock = nullptr;
@@ -347,6 +351,33 @@ hho_status energy_now(hho_ctx *ctx, double *out_dev) {
     return HHO_OK;
 }
 
+// Host-side check of one stage launch's arguments against the buffers they address (run for every
+// launch enqueued or captured, before it is): every per-lane array inside the arena, the energy
+// partials within the context's allocation, the recording capacities the kernels test against
+// within the allocated histories, and the workgroup within the largest block.  A failure is an
+// internal error reported as HHO_ERR_DEVICE; nothing is launched.
+template <typename R>
+hho_status check_stage_args(hho_ctx *ctx, const StageArgs<R> &a, int n_blocks, int ecap) {
+    const size_t sbytes = (size_t)ctx->rows * ctx->LT * sizeof(R), tbytes = (size_t)ctx->trows * ctx->LT * sizeof(R);
+    std::string bad;
+    auto within = [&](const void *p, unsigned off, size_t bytes, const char *what) {
+        if (p && (size_t)off + bytes > ctx->arena_bytes) bad = what;
+    };
+    within(a.Yin, a.o_yin, sbytes, "stage input");
+    within(a.Yout, a.o_yout, sbytes, "stage output");
+    within(a.U, a.o_u, sbytes, "state");
+    within(a.Yq, a.o_yq, sbytes, "partial sum");
+    within(a.Tin, a.o_tin, tbytes, "incoming traces");
+    within(a.Tout, a.o_tout, tbytes, "outgoing traces");
+    if (n_blocks > ctx->max_blocks || (size_t)a.cpb * a.S > (size_t)kBlock) bad = "launch shape";
+    if (a.e_part && a.e_part != ctx->e_part) bad = "energy partials";
+    if ((size_t)std::max(ecap, 0) * a.S > ctx->e_hist_cap) bad = "energy history capacity";
+    if (a.rec_first && (size_t)a.rec_steps * a.S * a.nrec * 2 > ctx->rec_cap) bad = "receiver capacity";
+    if (bad.empty()) return HHO_OK;
+    ctx->err = "internal: stage launch argument out of its buffer (" + bad + ")";
+    return HHO_ERR_DEVICE;
+}
+
 // Enqueue n_steps steps on stream st.  Every launch argument is the same for every step (the
 // stage time and step index come from the device clock, advanced by the last stage of each step),
 // so the sequence can be captured once into a graph and replayed.
@@ -408,6 +439,7 @@ hho_status enqueue_steps(hho_ctx *ctx, hipStream_t st, int n_steps, R *store = n
             a.clock = ctx->clock + ((parity + n) & 1);
             a.clock_next = ctx->clock + ((parity + n + 1) & 1);
             set_stage_offsets(ctx, a);
+            if (hho_status cs = check_stage_args(ctx, a, ctx->n_blocks(), ecap)) return cs;
             if (store) {
                 const AdjWork &w = ctx->adj;
                 R *slot = store + (size_t)(n * s + i) * w.slot_elems;
@@ -444,7 +476,9 @@ template <int K, typename R>
 hho_status autotune_shape(hho_ctx *ctx);
 
 // Common start of a stepping call: output capacities, device clock, initial energy, traces.
-hho_status begin_steps(hho_ctx *ctx, double t0, double dt, int n_steps, std::vector<double> &E0) {
+// With defer, the initial energies are only enqueued (into ctx->h_e0): the caller synchronises
+// the context's stream and reads them with read_initial_energy.
+hho_status begin_steps(hho_ctx *ctx, double t0, double dt, int n_steps, std::vector<double> &E0, bool defer = false) {
     const int S = ctx->plan.S;
     hho_status s;
     if (ctx->nrec > 0) {
@@ -462,6 +496,14 @@ hho_status begin_steps(hho_ctx *ctx, double t0, double dt, int n_steps, std::vec
             ctx->e_hist_cap = need;
             ctx->version++;
         }
+        if (!ctx->h_e0) HCK(hipHostMalloc((void **)&ctx->h_e0, (size_t)S * sizeof(double), hipHostMallocDefault));
+        if (need > ctx->h_ehist_cap) {
+            if (ctx->h_ehist) HCK(hipHostFree(ctx->h_ehist));
+            ctx->h_ehist = nullptr;
+            ctx->h_ehist_cap = 0;
+            HCK(hipHostMalloc((void **)&ctx->h_ehist, need * sizeof(double), hipHostMallocDefault));
+            ctx->h_ehist_cap = need;
+        }
     }
     ctx->h_clock.t0 = t0;
     ctx->h_clock.dt = dt;
@@ -475,8 +517,11 @@ hho_status begin_steps(hho_ctx *ctx, double t0, double dt, int n_steps, std::vec
             return energy_now<decltype(kc)::value, R>(ctx, ctx->e_now);
         });
         if (s != HHO_OK) return s;
-        HCK(hipMemcpyAsync(E0.data(), ctx->e_now, S * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-        HCK(hipStreamSynchronize(ctx->stream));
+        HCK(hipMemcpyAsync(ctx->h_e0, ctx->e_now, S * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        if (!defer) {
+            HCK(hipStreamSynchronize(ctx->stream));
+            std::copy(ctx->h_e0, ctx->h_e0 + S, E0.begin());
+        }
     }
     if (!ctx->traces_valid) {
         s = dispatch(ctx, [&](auto kc, auto *r) {
@@ -488,14 +533,26 @@ hho_status begin_steps(hho_ctx *ctx, double t0, double dt, int n_steps, std::vec
     return HHO_OK;
 }
 
-// Energy criterion of Algorithm algo_CFL (Sec. 5.1) on the recorded history: growth above
-// 5 % over the initial or the previous energy of an undriven run, or a non-finite energy.
-hho_status end_steps(hho_ctx *ctx, int n_steps, const std::vector<double> &E0) {
+// Initial energies enqueued by begin_steps(defer = true), once the context's stream is synchronised.
+void read_initial_energy(const hho_ctx *ctx, std::vector<double> &E0) {
+    if (ctx->record_energy) std::copy(ctx->h_e0, ctx->h_e0 + ctx->plan.S, E0.begin());
+}
+
+// Enqueue the copy of the recorded energy history (n_steps steps) into ctx->h_ehist on `st`.
+hho_status enqueue_history_copy(hho_ctx *ctx, int n_steps, hipStream_t st) {
+    if (!ctx->record_energy || n_steps == 0) return HHO_OK;
+    HCK(hipMemcpyAsync(ctx->h_ehist, ctx->e_hist, (size_t)n_steps * ctx->plan.S * sizeof(double),
+                       hipMemcpyDeviceToHost, st));
+    return HHO_OK;
+}
+
+// Energy criterion of Algorithm algo_CFL (Sec. 5.1) on the history copied into ctx->h_ehist:
+// growth above 5 % over the initial or the previous energy of an undriven run, or a non-finite
+// energy.
+hho_status check_history(hho_ctx *ctx, int n_steps, const std::vector<double> &E0) {
     if (!ctx->record_energy || n_steps == 0) return HHO_OK;
     const int S = ctx->plan.S;
-    std::vector<double> E((size_t)n_steps * S);
-    HCK(hipMemcpyAsync(E.data(), ctx->e_hist, E.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HCK(hipStreamSynchronize(ctx->stream));
+    const double *E = ctx->h_ehist;
     const bool driven = !ctx->h_src.empty() || ctx->nterms > 0;
     for (int sh = 0; sh < S; ++sh) {
         double prev = E0[sh];
@@ -510,6 +567,15 @@ hho_status end_steps(hho_ctx *ctx, int n_steps, const std::vector<double> &E0) {
         }
     }
     return HHO_OK;
+}
+
+// Closing stability check of one context's stepping call (synchronises its stream).
+hho_status end_steps(hho_ctx *ctx, int n_steps, const std::vector<double> &E0) {
+    if (!ctx->record_energy || n_steps == 0) return HHO_OK;
+    hho_status s = enqueue_history_copy(ctx, n_steps, ctx->stream);
+    if (s != HHO_OK) return s;
+    HCK(hipStreamSynchronize(ctx->stream));
+    return check_history(ctx, n_steps, E0);
 }
 
 // Capture the step graphs of one context (cached until the configuration changes).  Every graph
@@ -719,12 +785,34 @@ hho_status rebuild_sources(hho_ctx *ctx) {
 }
 
 
+// Geometric corners of a cell: the vertices where its boundary turns.  A hanging node lies on a
+// straight edge and is not a corner, so a square with hanging nodes counts 4 and a triangle with
+// one counts 3.
+int geometric_corners(const Plan &P, int c) {
+    const int b = P.cell_ptr[c], n = P.cell_ptr[c + 1] - b;
+    int corners = 0;
+    for (int i = 0; i < n; ++i) {
+        const int v0 = P.cell_vtx[b + (i + n - 1) % n], v1 = P.cell_vtx[b + i], v2 = P.cell_vtx[b + (i + 1) % n];
+        const double ax = P.xy[2 * v1] - P.xy[2 * v0], ay = P.xy[2 * v1 + 1] - P.xy[2 * v0 + 1];
+        const double bx = P.xy[2 * v2] - P.xy[2 * v1], by = P.xy[2 * v2 + 1] - P.xy[2 * v1 + 1];
+        const double cross = ax * by - ay * bx;
+        if (std::fabs(cross) > 1e-9 * std::sqrt((ax * ax + ay * ay) * (bx * bx + by * by))) ++corners;
+    }
+    return corners;
+}
+
 // CFL-limited time step (eq. CFL, Sec. 5.1): min over cells of CFL*(s, k, shape) h_T / c_T, with
-// CFL* from Table tab::ratio_geo (triangles, squares, hexagons; polygons with five or more faces
-// use the hexagon value), c_T the largest wave speed of the cell and h_T the side of the
-// generating square (sqrt(area) for quadrilaterals and polygons, sqrt(2 area) for triangles).
+// c_T the largest wave speed of the cell (c, or c_P in the solid), the shape from the cell's
+// geometric corners (3: triangle, 4: quadrilateral, 5 or more: polygon, hexagon column) and h_T
+// the side of the generating square (sqrt of the area; sqrt of twice the area for triangles).
+// CFL* is the paper's Table tab::ratio_geo value, lowered to 0.9 times this discretisation's own
+// stability limit where that is smaller, so that factor 1 is stable on every shape.  Those limits
+// were measured with hho_cfl_search (Algorithm algo_CFL from a random state, which excites every
+// mode, T_f = 1, delta = 1 %) on the two-material CFL geometry at h = 1/16 (squares, the squares
+// cut along a diagonal, and hexagons), with the weights eta^f = 0.8, eta^s = 1.5 and both readings
+// of the solid stabilisation speed; with other weights the limit moves (hho_cfl_search measures it).
 double cfl_time_step(const Plan &P, int stages) {
-    static const double table[3][3][3] = {
+    static const double paper[3][3][3] = {
         // s = 2: triangle, square, hexagon for k = 1, 2, 3
         {{0.191, 0.106, 0.072}, {0.205, 0.099, 0.063}, {0.264, 0.136, 0.082}},
         // s = 3
@@ -732,15 +820,26 @@ double cfl_time_step(const Plan &P, int stages) {
         // s = 4
         {{0.265, 0.147, 0.100}, {0.282, 0.138, 0.087}, {0.363, 0.188, 0.115}},
     };
+    // measured limits [stab_speed][s - 2][shape][k - 1]
+    static const double measured[2][3][3][3] = {
+        {{{0.0979, 0.0540, 0.0360}, {0.1680, 0.0871, 0.0585}, {0.0946, 0.0509, 0.0331}},
+         {{0.1232, 0.0678, 0.0454}, {0.2099, 0.1087, 0.0733}, {0.1188, 0.0636, 0.0415}},
+         {{0.1358, 0.0751, 0.0504}, {0.2329, 0.1210, 0.0817}, {0.1317, 0.0705, 0.0460}}},
+        {{{0.1732, 0.0979, 0.0628}, {0.2857, 0.1459, 0.0909}, {0.1723, 0.0946, 0.0618}},
+         {{0.2165, 0.1226, 0.0792}, {0.3553, 0.1823, 0.1140}, {0.2148, 0.1188, 0.0776}},
+         {{0.2410, 0.1352, 0.0880}, {0.3959, 0.2023, 0.1265}, {0.2386, 0.1311, 0.0854}}},
+    };
     double dt = 1e300;
     for (int c = 0; c < P.n_cells; ++c) {
-        const int nF = P.cell_ptr[c + 1] - P.cell_ptr[c];
-        const int shape = nF == 3 ? 0 : (nF == 4 ? 1 : 2);
-        const double h = std::sqrt(P.area[c] * (nF == 3 ? 2.0 : 1.0));
+        const int corners = geometric_corners(P, c);
+        const int shape = corners <= 3 ? 0 : (corners == 4 ? 1 : 2);
+        const double h = std::sqrt(P.area[c] * (shape == 0 ? 2.0 : 1.0));
+        const double cfl = std::min(paper[stages - 2][shape][P.k - 1],
+                                    0.9 * measured[P.stab_speed ? 1 : 0][stages - 2][shape][P.k - 1]);
         // c (fluid: kappa / rho = c^2) or c_P (solid: (lambda + 2 mu) / rho)
         const int ic = P.ic_of_cell[c];
         const double speed = std::sqrt(P.mat[(size_t)kStiff * P.n_ic + ic] * P.mat[(size_t)kInvRho * P.n_ic + ic]);
-        dt = std::min(dt, table[stages - 2][shape][P.k - 1] * h / speed);
+        dt = std::min(dt, cfl * h / speed);
     }
     return dt;
 }
@@ -1076,6 +1175,8 @@ void hho_destroy(hho_ctx *ctx) {
     for (hipGraphExec_t g : ctx->gexec)
         if (g) (void)hipGraphExecDestroy(g);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->h_e0) (void)hipHostFree(ctx->h_e0);
+    if (ctx->h_ehist) (void)hipHostFree(ctx->h_ehist);
     AdjWork &w = ctx->adj;
     if (w.aux) {
         (void)hipStreamSynchronize(w.aux);
@@ -1117,6 +1218,47 @@ hho_status hho_set_state(hho_ctx *ctx, int32_t shot, const double *U, int32_t on
         HCK(hipStreamSynchronize(ctx->stream));
         ctx->traces_valid = false;
         return HHO_OK;
+    });
+}
+
+hho_status hho_set_ricker_ic(hho_ctx *ctx, int32_t shot, double xc, double yc, double theta, double lambda,
+                             int32_t field) {
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (shot < 0 || shot >= ctx->plan.S || !(lambda > 0.0) || !std::isfinite(lambda) || !std::isfinite(xc) ||
+            !std::isfinite(yc) || !std::isfinite(theta) || (field != 0 && field != 1)) {
+            ctx->err = "set_ricker_ic: shot out of range, lambda <= 0, a non-finite value or field not 0 / 1";
+            return HHO_ERR_ARG;
+        }
+        const Plan &P = ctx->plan;
+        const RickerIC ic{xc, yc, theta, lambda, field};
+        // graded exponents of the scaled monomials (degree-major, decreasing power of x)
+        int px[kMaxN], py[kMaxN];
+        for (int d = 0, m = 0; d <= P.k; ++d)
+            for (int a = d; a >= 0; --a, ++m) {
+                px[m] = a;
+                py[m] = d - a;
+            }
+        std::vector<double> U((size_t)P.n_ext, 0.0);
+        for (int c = 0; c < P.n_cells; ++c) {
+            const double h = P.hT[c], cx = P.centroid[2 * c], cy = P.centroid[2 * c + 1];
+            const double *C = P.basisC.data() + (size_t)P.cell_class[c] * P.N * P.N;
+            auto eval = [&](double x, double y, double *phi) {
+                const double X = (x - cx) / h, Y = (y - cy) / h;
+                double mu[kMaxN];
+                for (int m = 0; m < P.N; ++m) mu[m] = std::pow(X, px[m]) * std::pow(Y, py[m]);
+                for (int a = 0; a < P.N; ++a) {
+                    double v = 0.0;
+                    for (int m = 0; m <= a; ++m) v += C[a * P.N + m] * mu[m];
+                    phi[a] = v;
+                }
+            };
+            const int b = P.cell_ptr[c];
+            project_ricker_cell(ic, P.xy.data(), P.cell_vtx.data() + b, P.cell_ptr[c + 1] - b, cx, cy,
+                                P.medium[c] == kFluid, P.N, P.N, P.N, eval, U.data() + P.ext_off[c]);
+        }
+        const hho_status s = hho_set_state(ctx, shot, U.data(), 0);
+        return s;
     });
 }
 
@@ -1616,17 +1758,18 @@ hho_status hho_batch_erk_step(hho_batch *b, const double *t0, const double *dt, 
                 b->err = "batch_erk_step: dt must be positive";
                 return HHO_ERR_ARG;
             }
-            hho_status s = begin_steps(ctx, t0[i], dt[i], n_steps, E0[i]);
+            hho_status s = begin_steps(ctx, t0[i], dt[i], n_steps, E0[i], true);
             if (s != HHO_OK) {
                 b->err = ctx->err;
                 return s;
             }
-            // the batch launches on the first context's stream
-            if (ctx->stream != launch_st) {
-                if (hipStreamSynchronize(ctx->stream) != hipSuccess) return HHO_ERR_DEVICE;
-            }
         }
+        // the batch launches on the first context's stream: every context's set-up work is done
+        for (int i = 0; i < n; ++i)
+            if (b->ctxs[i]->stream != launch_st && hipStreamSynchronize(b->ctxs[i]->stream) != hipSuccess)
+                return HHO_ERR_DEVICE;
         if (hipStreamSynchronize(launch_st) != hipSuccess) return HHO_ERR_DEVICE;
+        for (int i = 0; i < n; ++i) read_initial_energy(b->ctxs[i], E0[i]);
         bool fresh = b->gexec[0] && (int)b->versions.size() == n;
         for (int i = 0; fresh && i < n; ++i) fresh = b->versions[i] == b->ctxs[i]->version;
         if (n_steps > 0 && !fresh) {
@@ -1655,11 +1798,18 @@ hho_status hho_batch_erk_step(hho_batch *b, const double *t0, const double *dt, 
         });
         if (rs != HHO_OK) return rs;
         if (hipEventRecord(b->t_end, launch_st) != hipSuccess) return HHO_ERR_DEVICE;
+        for (int i = 0; i < n; ++i) {
+            hho_status s = enqueue_history_copy(b->ctxs[i], n_steps, launch_st);
+            if (s != HHO_OK) {
+                b->err = b->ctxs[i]->err;
+                return s;
+            }
+        }
         if (hipStreamSynchronize(launch_st) != hipSuccess) return HHO_ERR_DEVICE;
         if (hipEventElapsedTime(&b->last_ms, b->t_begin, b->t_end) != hipSuccess) return HHO_ERR_DEVICE;
         hho_status worst = HHO_OK;
         for (int i = 0; i < n; ++i) {
-            hho_status s = end_steps(b->ctxs[i], n_steps, E0[i]);
+            hho_status s = check_history(b->ctxs[i], n_steps, E0[i]);
             if (s != HHO_OK && worst == HHO_OK) {
                 worst = s;
                 b->err = "context " + std::to_string(i) + ": " + b->ctxs[i]->err;

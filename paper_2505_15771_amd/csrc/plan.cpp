@@ -151,6 +151,9 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
     P.N = (k + 1) * (k + 2) / 2;
     P.F = k + 1;
     P.S = n_shots;
+    P.stab_speed = stab_speed;
+    P.eta_f = eta_f;
+    P.eta_s = eta_s;
     P.n_cells = nc;
     P.n_vertices = nv;
     const int N = P.N, F = P.F;

@@ -62,6 +62,8 @@ constexpr int kNumGradCoef = 8;
 
 struct Plan {
     int k = 1, N = 3, F = 2, S = 1;
+    int stab_speed = 1;             // c^s in tau^s: 0 P-wave, 1 S-wave speed
+    double eta_f = 0.8, eta_s = 1.5;
     int n_cells = 0, n_faces = 0, n_vertices = 0;
     int max_nf = 0;
     int cpb = 256;           // cells per block of the default launch shape

@@ -28,6 +28,7 @@
 
 #include "../../include/hho_sdirk.h"
 #include "implicit_plan.h"
+#include "initial.h"
 
 namespace {
 
@@ -1061,6 +1062,47 @@ hho_status hho_sdirk_set_state(hho_sdirk *ctx, const double *U, int32_t on_devic
         ctx->step_count = 0;
         SCK(hipStreamSynchronize(ctx->stream));
         return HHO_OK;
+    });
+}
+
+hho_status hho_sdirk_set_ricker_ic(hho_sdirk *ctx, double xc, double yc, double theta, double lambda,
+                                   int32_t field) {
+    return guarded(ctx ? &const_cast<hho_sdirk *>(ctx)->err : &g_sdirk_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (!(lambda > 0.0) || !std::isfinite(lambda) || !std::isfinite(xc) || !std::isfinite(yc) ||
+            !std::isfinite(theta) || (field != 0 && field != 1)) {
+            ctx->err = "set_ricker_ic: lambda <= 0, a non-finite value or field not 0 / 1";
+            return HHO_ERR_ARG;
+        }
+        const auto &P = ctx->plan;
+        const hho::RickerIC ic{xc, yc, theta, lambda, field};
+        int px[16], py[16];
+        for (int d = 0, m = 0; d <= P.kp; ++d)
+            for (int a = d; a >= 0; --a, ++m) {
+                px[m] = a;
+                py[m] = d - a;
+            }
+        std::vector<double> U((size_t)P.n_dof, 0.0);
+        for (int c = 0; c < P.n_cells; ++c) {
+            const double h = P.hT[c], cx = P.centroid[2 * c], cy = P.centroid[2 * c + 1];
+            const double *C = P.basisC.data() + (size_t)c * P.Np * P.Np;
+            auto eval = [&](double x, double y, double *phi) {
+                const double X = (x - cx) / h, Y = (y - cy) / h;
+                double mu[16];
+                for (int m = 0; m < P.Np; ++m) mu[m] = std::pow(X, px[m]) * std::pow(Y, py[m]);
+                for (int a = 0; a < P.Np; ++a) {
+                    double v = 0.0;
+                    for (int m = 0; m <= a; ++m) v += C[a * P.Np + m] * mu[m];
+                    phi[a] = v;
+                }
+            };
+            // primal fields (p, v) of degree k', dual ones (m, s) of degree k: the first N functions
+            const bool fluid = P.medium[c] == 0;
+            const int b = P.cell_ptr[c];
+            hho::project_ricker_cell(ic, P.xy.data(), P.cell_vtx.data() + b, P.cell_ptr[c + 1] - b, cx, cy, fluid, P.Np,
+                                fluid ? P.N : P.Np, P.Np, eval, U.data() + P.ext_off[c]);
+        }
+        return hho_sdirk_set_state(ctx, U.data(), 0);
     });
 }
 

@@ -56,6 +56,8 @@ EXPORTS = {
     "hho_set_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
     "hho_get_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
     "hho_set_sources": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32] + [C.c_void_p] * 5),
+    "hho_set_ricker_ic": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double,
+                                    C.c_int32]),
     "hho_set_loads": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "hho_receivers": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "hho_erk_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int32]),
@@ -94,6 +96,7 @@ EXPORTS = {
     "hho_sdirk_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
     "hho_sdirk_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
     "hho_sdirk_set_sources": (C.c_int, [C.c_void_p, C.c_int32] + [C.c_void_p] * 5),
+    "hho_sdirk_set_ricker_ic": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32]),
     "hho_sdirk_step": (C.c_int, [C.c_void_p, C.c_double, C.c_int32]),
     "hho_sdirk_energy": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "hho_sdirk_receivers": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
@@ -171,7 +174,7 @@ class Engine:
     State arrays are float64 in the per-cell layout of hho.h, either numpy arrays
     (host) or contiguous float64 torch cuda tensors (device)."""
 
-    def __init__(self, mesh, k, rk_stages=4, eta_f=0.8, eta_s=1.5, stab_speed=0, dtype="f64", n_shots=1,
+    def __init__(self, mesh, k, rk_stages=4, eta_f=0.8, eta_s=1.5, stab_speed=1, dtype="f64", n_shots=1,
                  record_energy=False, device=0, stream=None):
         lib = load_library()
         self.lib = lib
@@ -252,6 +255,12 @@ class Engine:
         arr = lambda v: np.ascontiguousarray(np.broadcast_to(np.asarray(v, np.float64), (n,)))
         f0, t0, amp = arr(f0), arr(t0), arr(amp)
         self._call(self.lib.hho_set_sources, int(shot), n, _ptr(xy), _ptr(d), _ptr(f0), _ptr(t0), _ptr(amp))
+
+    def set_ricker_ic(self, center, lam, theta=1.0, field=1, shot=0):
+        """hho_set_ricker_ic: the shot's state becomes the projected field of eq. ricker_ic
+        (field 1: velocity, field 0: pressure pulse) centred at `center` with wavelength lam."""
+        self._call(self.lib.hho_set_ricker_ic, int(shot), float(center[0]), float(center[1]), float(theta),
+                   float(lam), int(field))
 
     def set_loads(self, g, omega, phase):
         g = np.ascontiguousarray(np.asarray(g, np.float64).reshape(-1))
@@ -370,7 +379,7 @@ def erk_coefficients(stages):
 class Inspect:
     """Host-only view of the execution plan (include/hho_inspect.h)."""
 
-    def __init__(self, mesh, k, eta_f=0.8, eta_s=1.5, stab_speed=0, n_shots=1):
+    def __init__(self, mesh, k, eta_f=0.8, eta_s=1.5, stab_speed=1, n_shots=1):
         lib = load_library()
         self.lib = lib
         keep = {}
@@ -470,7 +479,7 @@ class SdirkEngine:
     BiCGStab face solve (hho_sdirk_setup); see include/hho_sdirk.h.  State arrays are float64 in
     that header's per-cell layout, numpy (host) or contiguous float64 torch cuda tensors."""
 
-    def __init__(self, mesh, k, dt, stages=3, mixed=True, alpha=1, eta_f=1.0, eta_s=1.0, stab_speed=0, ell=0.0,
+    def __init__(self, mesh, k, dt, stages=3, mixed=True, alpha=1, eta_f=1.0, eta_s=1.0, stab_speed=1, ell=0.0,
                  tol=1e-10, max_iter=2000, device=0, stream=None):
         lib = load_library()
         self.lib = lib
@@ -515,6 +524,11 @@ class SdirkEngine:
         if U.size != self.n_dof:
             raise ValueError("state has %d values, expected %d" % (U.size, self.n_dof))
         self._call(self.lib.hho_sdirk_set_state, _ptr(U), 0)
+
+    def set_ricker_ic(self, center, lam, theta=1.0, field=1):
+        """hho_sdirk_set_ricker_ic: the projected field of eq. ricker_ic as the state."""
+        self._call(self.lib.hho_sdirk_set_ricker_ic, float(center[0]), float(center[1]), float(theta), float(lam),
+                   int(field))
 
     def get_state(self, out=None):
         if out is not None and Engine._dev_ptr(out) is not None:
@@ -568,7 +582,7 @@ class SdirkEngine:
         return a.value, b.value, c.value
 
 
-def sdirk_face_matrix(mesh, k, dt, stages=3, mixed=True, alpha=1, eta_f=1.0, eta_s=1.0, stab_speed=0, ell=0.0):
+def sdirk_face_matrix(mesh, k, dt, stages=3, mixed=True, alpha=1, eta_f=1.0, eta_s=1.0, stab_speed=1, ell=0.0):
     """Host-only: the condensed face matrix of hho_sdirk_setup as (ptr, col, val, face) with
     face[d] = (lower vertex, higher vertex, index in the face block) of face unknown d."""
     lib = load_library()

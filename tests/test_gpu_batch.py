@@ -82,13 +82,23 @@ def test_autotune_keeps_results():
 
 
 def test_dt_cfl_matches_table():
-    """hho_dt_cfl: the CFL condition eq. CFL with Table tab::ratio_geo on a hybrid mesh of squares
-    and half-square triangles (side h), c_max = sqrt(3): dt = min(0.265, 0.282) * h / sqrt(3) at k = 1."""
+    """hho_dt_cfl on a hybrid mesh of squares and half-square triangles (side h = 1/16, c_max =
+    sqrt(3)): per shape the smaller of the paper's Table tab::ratio_geo value and 0.9 times this
+    discretisation's measured limit (ERK(4), k = 1, tau^s on c_S: squares min(0.282, 0.9 x 0.3959),
+    triangles min(0.265, 0.9 x 0.2410)), the triangles deciding; with tau^s on c_P the squares'
+    0.9 x 0.2329 and the triangles' 0.9 x 0.1358.  Squares with hanging nodes (five vertices, four
+    corners) take the square value: on a mesh of squares only, refining some of them (children of
+    side h / 2 and their hanging-node neighbours) gives the children's step."""
     from paper_2505_15771_amd import Engine
     mesh = M.with_materials(M.unit_square(16, p_split=0.5, seed=25))
-    for k, s, cfl in ((1, 4, 0.265), (2, 4, 0.138), (3, 3, 0.079)):
-        e = Engine(mesh, k, rk_stages=s)
-        assert abs(e.dt_cfl(0.5) - 0.5 * cfl / 16 / math.sqrt(3.0)) < 1e-15
+    for k, s, ss, cfl in ((1, 4, 1, 0.9 * 0.2410), (2, 4, 1, 0.9 * 0.1352), (3, 3, 1, 0.9 * 0.0792),
+                          (1, 4, 0, 0.9 * 0.1358)):
+        e = Engine(mesh, k, rk_stages=s, stab_speed=ss)
+        assert abs(e.dt_cfl(0.5) - 0.5 * cfl / 16 / math.sqrt(3.0)) < 1e-15, (k, s, ss)
+    refine = np.zeros((8, 8), bool)
+    refine[2:4, 3:6] = True
+    quads = M.with_materials(M.unit_square(8, refine=refine))
+    assert abs(Engine(quads, 1).dt_cfl(1.0) - 0.282 / 16 / math.sqrt(3.0)) < 1e-15
 
 
 def test_batch_of_meshes_and_shots():

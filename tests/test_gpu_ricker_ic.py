@@ -1,0 +1,106 @@
+"""GPU-side initial state of eq. ricker_ic (Sec. 5.2): hho_set_ricker_ic and
+hho_sdirk_set_ricker_ic (L2 projections computed by the library) against the oracles' own L2
+projections of the same field (their quadrature, their bases), on hybrid meshes with hanging
+nodes, k = 1..3, both fields (the printed velocity and the pressure pulse), and on the paper's
+granite-water timing mesh with the paper's pulse (x_c = 0, y_c = 200 m, lambda = c_P^f / f_c =
+150 m).  Both sides' quadratures are converged far below the tolerance (1e-12 relative L2) for
+these pulses: the oracle's changes by less than 2e-15 between 12 and 16 points per direction."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from synth import meshes as M
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def ricker_fields(xc, yc, lam, theta, field):
+    """The field of eq. ricker_ic as callables for the oracles' projections: (fluid p, m_x, m_y),
+    (solid v_x, v_y, s_1, s_2, s_3)."""
+    g = lambda x, y: theta * np.exp(-math.pi ** 2 * ((x - xc) ** 2 + (y - yc) ** 2) / lam ** 2)
+    z = lambda x, y: 0 * x
+    if field == 0:
+        return [g, z, z], [z] * 5
+    vx = lambda x, y: g(x, y) * (x - xc)
+    vy = lambda x, y: g(x, y) * (y - yc)
+    return [z, vx, vy], [vx, vy, z, z, z]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("field", [0, 1])
+def test_ricker_ic_matches_oracle_projection(k, field):
+    from oracle import Oracle
+    from paper_2505_15771_amd import Engine
+    say("case: ricker ic k=%d field=%d" % (k, field))
+    mesh = M.hanging_square(8, seed=3)
+    xc, yc, lam, theta = 0.45, 0.56, 0.3, 1.3   # centre in the fluid, the pulse reaching the solid
+    ref = Oracle(mesh, k).project(*ricker_fields(xc, yc, lam, theta, field), nq=16)
+    for dtype, tol in (("f64", 1e-12), ("f32", 1e-6)):
+        e = Engine(mesh, k, dtype=dtype, n_shots=2)
+        e.set_ricker_ic((xc, yc), lam, theta=theta, field=field, shot=1)
+        err = rel(e.get_state(1), ref)
+        say(dtype, "rel L2", err, "shot 0 untouched", np.linalg.norm(e.get_state(0)))
+        assert err < tol and not np.any(e.get_state(0))
+        e.close()
+
+
+def test_ricker_ic_granite_water_pulse():
+    """The timing case of Sec. 5.2: pressure pulse at (0, 200 m), lambda = 1500 / 10 m, on the
+    161 x 110 granite-water mesh, k = 3; then four ERK(4) steps from it against the oracle."""
+    from oracle import Oracle
+    from paper_2505_15771_amd import Engine
+    say("case: granite-water pulse k=3")
+    mesh = M.granite_water()
+    o = Oracle(mesh, 3)
+    ref = o.project(*ricker_fields(0.0, 200.0, 150.0, 1.0, 0), nq=14)
+    e = Engine(mesh, 3)
+    e.set_ricker_ic((0.0, 200.0), 150.0, theta=1.0, field=0)
+    err = rel(e.get_state(), ref)
+    say("projection rel L2", err)
+    assert err < 1e-12
+    dt = 0.054 * 23.6 / 6000.0
+    e.erk_step(0.0, dt, 4)
+    err = rel(e.get_state(), o.erk(ref, 0.0, dt, 4))
+    say("after 4 steps rel L2", err)
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 3])
+@pytest.mark.parametrize("field", [0, 1])
+def test_sdirk_ricker_ic_matches_oracle_projection(k, field):
+    """Mixed order (primal fields of degree k + 1, dual of degree k) against the implicit oracle's
+    projection."""
+    from oracle.implicit import ImplicitOracle
+    from paper_2505_15771_amd import SdirkEngine
+    say("case: sdirk ricker ic k=%d field=%d" % (k, field))
+    mesh = M.hanging_square(6, seed=4)
+    xc, yc, lam = 0.5, 0.7, 0.5
+    ref = ImplicitOracle(mesh, k).project(*ricker_fields(xc, yc, lam, 1.0, field))
+    e = SdirkEngine(mesh, k, 0.01)
+    e.set_ricker_ic((xc, yc), lam, field=field)
+    err = rel(e.get_state(), ref)
+    say("rel L2", err)
+    assert err < 1e-12
+    e.close()
+
+
+def test_ricker_ic_argument_errors():
+    from paper_2505_15771_amd import Engine, HHOError
+    e = Engine(M.hanging_square(4, seed=2), 1)
+    for bad in (dict(lam=0.0), dict(lam=-1.0), dict(lam=0.2, field=2), dict(lam=0.2, shot=1),
+                dict(lam=float("nan"))):
+        with pytest.raises(HHOError) as ex:
+            e.set_ricker_ic((0.5, 0.5), **bad)
+        assert ex.value.code == 1
+    e.close()

@@ -188,24 +188,35 @@ def test_erk_increment_form_reproduces_tableau(s):
     assert np.allclose(co[:, 0], nodes)
 
 
-@pytest.mark.parametrize("k", [1, 2])
-@pytest.mark.parametrize("shape", ["quads", "triangles", "hybrid"])
-def test_cfl_step_spectral_margin(k, shape):
-    """The time step of hho_dt_cfl (eq. CFL with the paper's CFL* tables) against the spectrum
-    of the condensed operator L (the oracle's dense matrix on the two-material CFL geometry of
-    Sec. 5.1): at half the tabulated step, every eigenvalue lambda satisfies |R(dt lambda)| <= 1
-    for the ERK(4) amplification polynomial R(z) = sum_{j<=4} z^j / j!, i.e. the step that the
-    benchmarks and the GPU tests use is stable.  (At the full tabulated step the strict spectral
-    limit is exceeded: the largest stable step is about 0.83 x the tabulated one on squares and
-    0.52 x on half-square triangles with these stabilisation parameters.)"""
+def _cfl_test_mesh(shape, k):
+    n = {1: 5, 2: 4, 3: 3}[k]
+    if shape in ("quads", "triangles", "hybrid"):
+        return M.with_materials(M.bilayer_vertical(n, p_split={"quads": 0.0, "triangles": 1.0, "hybrid": 0.5}[shape],
+                                                   seed=3))
+    if shape == "hanging":
+        return M.hanging_square(n + 1, seed=5, frac=0.35)
+    if shape == "hexagons":
+        return M.with_materials(M.honeycomb_bilayer(2 * n))
+    return M.with_materials(M.perturbed_square(n + 1, seed=4))
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("shape", ["quads", "triangles", "hybrid", "hanging", "hexagons", "perturbed"])
+def test_cfl_step_is_stable(k, shape):
+    """hho_dt_cfl at factor 1 (eq. CFL with the CFL* of Table tab::ratio_geo, lowered where this
+    discretisation's own limit is smaller) against the spectrum of the condensed operator L (the
+    oracle's dense matrix): every eigenvalue lambda satisfies |R_s(dt lambda)| <= 1 for the
+    amplification polynomial R_s(z) = sum_{j<=s} z^j / j! of ERK(s), s = 2, 3, 4, on squares,
+    triangles, hybrid meshes, squares and triangles with hanging nodes, hexagons, and quads and
+    triangles with moved vertices."""
     from math import factorial
     from oracle import Oracle
     from paper_2505_15771_amd import Inspect
-    mesh = M.with_materials(M.bilayer_vertical(5 if k == 2 else 6, p_split={"quads": 0.0, "triangles": 1.0,
-                                                                            "hybrid": 0.5}[shape], seed=3))
+    mesh = _cfl_test_mesh(shape, k)
     ins = Inspect(mesh, k)
     lam = np.linalg.eigvals(Oracle(mesh, k).dense_operator())
     assert np.max(lam.real) < 1e-10 * np.max(np.abs(lam))  # dissipative semi-discretisation
-    z = 0.5 * ins.dt_cfl[4] * lam
-    R = sum(z ** j / factorial(j) for j in range(5))
-    assert np.max(np.abs(R)) <= 1.0 + 1e-12
+    for s_ in (2, 3, 4):
+        z = ins.dt_cfl[s_] * lam
+        R = sum(z ** j / factorial(j) for j in range(s_ + 1))
+        assert np.max(np.abs(R)) <= 1.0 + 1e-12, (s_, float(np.max(np.abs(R))))

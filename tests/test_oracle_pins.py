@@ -321,10 +321,21 @@ def test_tableaux_orders():
 
 
 # ----------------------------------------------------------------------------- sources / receivers
+def _load_functional(o, mesh, xs, W, t):
+    """F(t) . W for the point-source load F of the oracle at time t: with U = 0 the oracle's
+    right-hand side is M^{-1} F, and M = rho M0 on the velocity rows of a solid cell."""
+    dU = o.rhs(np.zeros(o.ndof), t)
+    c = o.locate(*xs)
+    off = o.offsets[c]
+    M0 = o.cell_ops(c)["M0"]
+    F = np.concatenate([mesh["rho"][c] * M0 @ dU[off + i * o.N: off + (i + 1) * o.N] for i in range(2)])
+    return F @ W[off: off + 2 * o.N]
+
+
 def test_point_source_load_and_point_values():
-    """eq. rhs read as a load vector: a point force d R(t) delta_{x_s} tested with a
-    polynomial w gives R(t) d.w(x_s); R is the Ricker wavelet (1 - 2a^2) exp(-a^2),
-    a = pi f0 (t - t0).  Point values of a projected polynomial are exact."""
+    """eq. rhs read as a load vector: a point force d R(t) delta_{x_s} tested with a polynomial
+    w gives amp R(t) d.w(x_s), one time factor for every test polynomial (two random fields give
+    the same quotient at every time).  Point values of a projected polynomial are exact."""
     mesh = M.with_materials(M.unit_square(4, p_split=0.5, seed=3))
     o = Oracle(mesh, 2)
     rng = np.random.default_rng(8)
@@ -332,23 +343,53 @@ def test_point_source_load_and_point_values():
     d = np.array([0.3, -1.0])
     f0, t0, amp = 10.0, 0.12, 2.5
     o.set_point_sources(xs, d, f0, t0, amp)
-    t = 0.093
-    a = math.pi * f0 * (t - t0)
-    R = amp * (1 - 2 * a * a) * math.exp(-a * a)
-    wx, wy = Poly(2, rng), Poly(2, rng)
-    Wc = o.project([zero] * 3, [wx, wy, zero, zero, zero])
-    dU = o.rhs(np.zeros(o.ndof), t)
-    # dU = M^{-1} F with M = rho M0 on the v rows -> F = rho M0 dU; F . Wc = R d . w(x_s)
-    c = o.locate(*xs)
-    rho = mesh["rho"][c]
-    off = o.offsets[c]
-    M0 = o.cell_ops(c)["M0"]
-    F = np.concatenate([rho * M0 @ dU[off + i * o.N: off + (i + 1) * o.N] for i in range(2)])
-    got = F @ Wc[off: off + 2 * o.N]
-    assert abs(got - R * (d[0] * wx(*xs) + d[1] * wy(*xs))) < 1e-12 * abs(R)
+    fields = [(Poly(2, rng), Poly(2, rng)) for _ in range(2)]
+    Ws = [o.project([zero] * 3, [wx, wy, zero, zero, zero]) for wx, wy in fields]
+    for t in (0.05, 0.093, 0.12, 0.2):
+        q = [_load_functional(o, mesh, xs, W, t) / (d[0] * wx(*xs) + d[1] * wy(*xs))
+             for W, (wx, wy) in zip(Ws, fields)]
+        assert abs(q[0] - q[1]) < 1e-12 * max(abs(q[0]), 1e-3)
     # point values
-    cc, vals = o.point_values(Wc, 0.61, 0.13)
+    cc, vals = o.point_values(Ws[0], 0.61, 0.13)
+    wx, wy = fields[0]
     assert abs(vals[0] - wx(0.61, 0.13)) < 1e-12 and abs(vals[1] - wy(0.61, 0.13)) < 1e-12
+
+
+def test_ricker_time_factor_properties():
+    """The time factor R of the oracle's point source (read A10 as the Ricker wavelet of peak
+    frequency f0 centred at t0), measured through the load vector, has the properties that fix
+    that wavelet: R(t0) = 1 is its maximum, it is even about t0, it vanishes at
+    t0 +- 1 / (sqrt(2) pi f0), its time integral is zero, and it equals -(2 pi^2 f0^2)^-1 times
+    the second derivative of the Gaussian exp(-pi^2 f0^2 (t - t0)^2) (central differences)."""
+    mesh = M.with_materials(M.unit_square(4))
+    o = Oracle(mesh, 1)
+    xs = np.array([0.4, 0.2])
+    f0, t0, amp = 7.0, 0.3, 3.0
+    o.set_point_sources(xs, [0.0, 1.0], f0, t0, amp)
+    W = o.project([zero] * 3, [zero, lambda x, y: 1.0 + 0 * x, zero, zero, zero])  # w = (0, 1)
+
+    def R(t):
+        return _load_functional(o, mesh, xs, W, t) / amp
+
+    assert abs(R(t0) - 1.0) < 1e-13
+    for s_ in (0.003, 0.01, 0.05, 0.2):
+        assert R(t0 + s_) < 1.0 and abs(R(t0 + s_) - R(t0 - s_)) < 1e-13
+    tz = 1.0 / (math.sqrt(2.0) * math.pi * f0)
+    assert abs(R(t0 + tz)) < 1e-13 and abs(R(t0 - tz)) < 1e-13
+    assert R(t0 + 0.5 * tz) > 0 and R(t0 + 1.5 * tz) < 0
+    # zero mean: composite trapezoid over t0 +- 6 / f0 (the tails beyond are below 1e-150)
+    ts = np.linspace(t0 - 6.0 / f0, t0 + 6.0 / f0, 6001)
+    vals = np.array([R(t) for t in ts])
+    integral = float(np.sum(0.5 * (vals[1:] + vals[:-1]) * np.diff(ts)))
+    assert abs(integral) < 1e-9 * float(np.sum(np.abs(vals)) * (ts[1] - ts[0]))
+
+    def G(t):
+        return math.exp(-(math.pi * f0 * (t - t0)) ** 2)
+
+    h = 1e-5
+    for t in (t0 - 0.07, t0 - 0.02, t0, t0 + 0.013, t0 + 0.05):
+        g2 = (G(t + h) - 2 * G(t) + G(t - h)) / (h * h)
+        assert abs(R(t) + g2 / (2 * math.pi ** 2 * f0 ** 2)) < 2e-6
 
 
 # ----------------------------------------------------------------------------- P6 convergence
