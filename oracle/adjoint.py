@@ -127,20 +127,23 @@ def _reverse_step(o, A, b, s, dt, lam, Ys, ks, grad):
     return total
 
 
-def misfit_gradient_checkpointed(o, U0, t0, dt, nsteps, rec, d_obs, every=50, s=4):
+def misfit_gradient_checkpointed(o, U0, t0, dt, nsteps, rec, d_obs, every=50, s=4, return_traces=False):
     """J and dJ/dtheta as misfit_gradient, with checkpoints: the forward pass keeps U^n for
     n = 0, every, 2 every, ...; the reverse sweep, segment by segment from the last, recomputes the
-    stage states of the segment from its checkpoint and runs the reverse steps of its steps."""
+    stage states of the segment from its checkpoint and runs the reverse steps of its steps.
+    With return_traces, also the receiver values R U^n of the forward pass [nsteps, n_rec, 2]."""
     A, b, c = ERK_TABLEAUX[s]
     _check_subdiagonal(A, s)
     ckpt = {}
     U = np.array(U0, float, copy=True)
-    terms = []
+    terms, traces = [], []
     for g0 in range(0, nsteps, every):
         ckpt[g0] = U
         Us, _ = forward(o, U, t0, dt, min(every, nsteps - g0), s, n0=g0)
         for m in range(1, len(Us)):
-            terms.append(float(np.sum((rec.apply(Us[m]) - d_obs[g0 + m - 1]) ** 2)))
+            r = rec.apply(Us[m])
+            traces.append(r)
+            terms.append(float(np.sum((r - d_obs[g0 + m - 1]) ** 2)))
         U = Us[-1]
     J = 0.5 * dt * sum(terms)
     lam = dt * rec.apply_T(rec.apply(U) - d_obs[nsteps - 1])
@@ -154,4 +157,4 @@ def misfit_gradient_checkpointed(o, U0, t0, dt, nsteps, rec, d_obs, every=50, s=
             if n >= 1:
                 lam_n += dt * rec.apply_T(rec.apply(Us[m]) - d_obs[n - 1])
             lam = lam_n
-    return J, grad
+    return (J, grad, np.array(traces)) if return_traces else (J, grad)

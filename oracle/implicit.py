@@ -341,9 +341,10 @@ class ImplicitOracle:
         return F
 
     # ---------------------------------------------------------------- projections / diagnostics
-    def project(self, fluid_fns, solid_fns):
-        """L2 projection of (p, m_x, m_y) / (v_x, v_y, s_1, s_2, s_3) onto the cell bases."""
-        nq = self.kp + 6
+    def project(self, fluid_fns, solid_fns, nq=None):
+        """L2 projection of (p, m_x, m_y) / (v_x, v_y, s_1, s_2, s_3) onto the cell bases (nq
+        points per direction of each fan triangle; default k' + 6, exact for polynomial data)."""
+        nq = nq or self.kp + 6
         px, py, pw, pc = self.geo.quad_points(nq)
         ptr = np.asarray(self.mesh["cell_ptr"])
         U = np.zeros(self.ndof)

@@ -603,6 +603,8 @@ hho_status ensure_graphs(hho_ctx *ctx) {
         const hipError_t ei = hipGraphInstantiate(&ctx->gexec[i], graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HCK(ei);
+        // make the graph resident now, so that its first replay costs no more than the others
+        HCK(hipGraphUpload(ctx->gexec[i], ctx->stream));
     }
     ctx->graph_version = ctx->version;
     return HHO_OK;
@@ -661,6 +663,8 @@ hho_status capture_batch(hho_batch *b, int steps, hipGraphExec_t *out) {
     const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ei != hipSuccess) return fail(std::string("batch: hipGraphInstantiate: ") + hipGetErrorString(ei), HHO_ERR_DEVICE);
+    // resident now, so that the first replay costs no more than the others
+    if (hipGraphUpload(*out, origin) != hipSuccess) return fail("batch: hipGraphUpload failed", HHO_ERR_DEVICE);
     return HHO_OK;
 }
 

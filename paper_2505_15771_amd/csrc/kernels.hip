@@ -34,6 +34,30 @@
 namespace hho {
 namespace {
 
+// Register budget of the stage kernel: the least number of waves per SIMD the compiler must leave
+// room for, per degree k = 1, 2, 3 (4 waves leave 128 VGPRs per lane, 3 leave 168, 2 leave 256;
+// 1 sets no budget), for float32 and float64 stepping.
+#ifndef HHO_STAGE_WAVES_F32
+#define HHO_STAGE_WAVES_F32 1, 1, 1
+#endif
+#ifndef HHO_STAGE_WAVES_F64
+#define HHO_STAGE_WAVES_F64 1, 1, 1
+#endif
+// Highest degree whose float32 stage keeps U^n and D_{i-1} in registers for the combine (float64:
+// k = 1 only); the others read them again (cache hits), which costs fewer registers.
+#ifndef HHO_KEEP_MAX_K_F32
+#define HHO_KEEP_MAX_K_F32 2
+#endif
+template <int K, typename R>
+constexpr int stage_waves() {
+    constexpr int w32[3] = {HHO_STAGE_WAVES_F32}, w64[3] = {HHO_STAGE_WAVES_F64};
+    return sizeof(R) == 4 ? w32[K - 1] : w64[K - 1];
+}
+template <int K, typename R>
+constexpr bool keep_in_registers() {
+    return sizeof(R) == 4 ? K <= HHO_KEEP_MAX_K_F32 : K <= 1;
+}
+
 // Stage state of one lane.  The stage buffers hold increments D_i = Y_{i+1} - U^n rather than
 // the stage states: the stage input is Y_i = U^n + D_{i-1} (U^n itself on the first stage).
 // Kept as increments, the values that the final combination below sums keep their full
@@ -165,8 +189,8 @@ __device__ __forceinline__ void store_recompute(const StageArgs<R> &a, const int
 
 // ------------------------------------------------------------------------- fluid cells
 template <int K, int NF, typename R, bool STORE, int POL>
-__device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
-                                            const LaneInfo &L, double *energy) {
+__device__ __forceinline__ double fluid_stage(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
+                                              const LaneInfo &L, bool want_e) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
     const int nic = a.n_ic, ic = L.ic, shot = L.shot;
     const unsigned boff = L.boff, coff = L.coff;
@@ -179,7 +203,7 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
     R cc[NF], rn[NF][2][F];
     R fv[STORE ? NF : 1][2][F];  // face values, kept for the recompute stores
     load_links<NF, R>(B, nF, ic, lk, cc);
-    constexpr bool KEEP = sizeof(R) == 4 ? K <= 2 : K <= 1;
+    constexpr bool KEEP = keep_in_registers<K, R>();
     R y[3 * N], uk[KEEP ? 3 * N : 1], dk[KEEP ? 3 * N : 1];
     load_state<3 * N, R, KEEP>(a, B, boff, y, uk, dk);
     const R *p = y, *mx = y + N, *my = y + 2 * N;
@@ -279,15 +303,16 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
     const R *np = nw, *nmx = nw + N, *nmy = nw + 2 * N;
     if (STORE) store_recompute<K, NF, 3 * N, R, NF, 1>(a, lk, boff, y, kv, fv);
     fluid_traces<K, NF, R, POL>(a, B, tb, nF, lk, boff, np, nmx, nmy, tau);
+    double energy = 0.0;
     if (a.last) {
-        if (energy) {
+        if (want_e) {
             double sp = 0, sm = 0;
 #pragma unroll
             for (int b = 0; b < N; ++b) {
                 sp += (double)np[b] * (double)np[b];
                 sm += (double)nmx[b] * (double)nmx[b] + (double)nmy[b] * (double)nmy[b];
             }
-            *energy = 0.5 * (a.emat[(long long)1 * nic + ic] * sp + a.emat[ic] * sm);
+            energy = 0.5 * (a.emat[(long long)1 * nic + ic] * sp + a.emat[ic] * sm);
         }
         if (a.rec_first) {
             for (int e = a.rec_first[ic]; e >= 0;) {
@@ -305,12 +330,13 @@ __device__ __forceinline__ void fluid_stage(const StageArgs<R> &a, const Bufs<R>
             }
         }
     }
+    return energy;
 }
 
 // ------------------------------------------------------------------------- solid cells
 template <int K, int NF, typename R, bool STORE, int POL>
-__device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
-                                            const LaneInfo &L, double *energy) {
+__device__ __forceinline__ double solid_stage(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
+                                              const LaneInfo &L, bool want_e) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
     const int nic = a.n_ic, ic = L.ic, shot = L.shot;
     const unsigned boff = L.boff, coff = L.coff;
@@ -324,7 +350,7 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
     R cc[NF], rn[NF][2][F];
     R fv[STORE ? NF : 1][2][F];  // face values, kept for the recompute stores
     load_links<NF, R>(B, nF, ic, lk, cc);
-    constexpr bool KEEP = sizeof(R) == 4 ? K <= 2 : K <= 1;
+    constexpr bool KEEP = keep_in_registers<K, R>();
     R y[5 * N], uk[KEEP ? 5 * N : 1], dk[KEEP ? 5 * N : 1];
     load_state<5 * N, R, KEEP>(a, B, boff, y, uk, dk);
     const R *vx = y, *vy = y + N, *s1 = y + 2 * N, *s2 = y + 3 * N, *s3 = y + 4 * N;
@@ -465,8 +491,9 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
     const R *nvx = nw, *nvy = nw + N, *ns1 = nw + 2 * N, *ns2 = nw + 3 * N, *ns3 = nw + 4 * N;
     if (STORE) store_recompute<K, NF, 5 * N, R, NF, 2>(a, lk, boff, y, kv, fv);
     solid_traces<K, NF, R, POL>(a, B, tb, nF, lk, boff, nvx, nvy, ns1, ns2, ns3, tau, itau);
+    double energy = 0.0;
     if (a.last) {
-        if (energy) {
+        if (want_e) {
             const double ca = a.emat[(long long)1 * nic + ic], cb = a.emat[(long long)2 * nic + ic];
             const double c3 = a.emat[(long long)3 * nic + ic];
             double sv = 0, ss = 0;
@@ -476,7 +503,7 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
                 sv += (double)nvx[b] * (double)nvx[b] + (double)nvy[b] * (double)nvy[b];
                 ss += ca * (x1 * x1 + x2 * x2) + 2.0 * cb * x1 * x2 + c3 * x3 * x3;
             }
-            *energy = 0.5 * (a.emat[ic] * sv + ss);
+            energy = 0.5 * (a.emat[ic] * sv + ss);
         }
         if (a.rec_first) {
             for (int e = a.rec_first[ic]; e >= 0;) {
@@ -497,16 +524,16 @@ __device__ __forceinline__ void solid_stage(const StageArgs<R> &a, const Bufs<R>
             }
         }
     }
+    return energy;
 }
 
+// One lane's stage; returns its energy (the last stage with energy recording), else 0.
 template <int K, int NF, typename R, bool STORE, int POL, bool POOLED>
-__device__ __forceinline__ void stage_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L, double *e) {
+__device__ __forceinline__ double stage_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L, bool want_e) {
     const HHO_CONST R *tb = class_table<POOLED>(a, G, L.ic);
     const Bufs<R> B = make_bufs(a);
-    if (G.medium == kFluid)
-        fluid_stage<K, NF, R, STORE, POL>(a, B, tb, G.nF, L, e);
-    else
-        solid_stage<K, NF, R, STORE, POL>(a, B, tb, G.nF, L, e);
+    if (G.medium == kFluid) return fluid_stage<K, NF, R, STORE, POL>(a, B, tb, G.nF, L, want_e);
+    return solid_stage<K, NF, R, STORE, POL>(a, B, tb, G.nF, L, want_e);
 }
 
 // With pooled groups a stage is two launches over the same grid: the one for the ordinary groups
@@ -514,7 +541,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<R> &a, const GroupDev
 // workgroup of a launch whose group is of the other kind returns at once.  When every group is
 // pooled only the pooled launch runs, and it advances the clock.
 template <int K, typename R, bool STORE, int POL, bool POOLED = false>
-__global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<R> a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(stage_waves<K, R>(), 8))) void stage_kernel(
+    StageArgs<R> a) {
     if ((!POOLED || a.all_pooled) && a.last && a.clock_next && blockIdx.x == 0 && threadIdx.x == 0) {
         Clock c = *a.clock;
         c.step += 1;
@@ -525,11 +553,10 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<R> a) {
     if ((POOLED || a.has_pooled) && (G.pooled != 0) != POOLED) return;
     const bool want_e = a.last && a.e_part;
     double e = 0.0;
-    double *ep = want_e ? &e : nullptr;
     if (L.active) {
         // faces beyond a cell's count carry link -1 and are skipped like boundary faces
-        if (G.nF <= 4) stage_body<K, 4, R, STORE, POL, POOLED>(a, G, L, ep);
-        else stage_body<K, kMaxFaces, R, STORE, POL, POOLED>(a, G, L, ep);
+        if (G.nF <= 4) e = stage_body<K, 4, R, STORE, POL, POOLED>(a, G, L, want_e);
+        else e = stage_body<K, kMaxFaces, R, STORE, POL, POOLED>(a, G, L, want_e);
     }
     if (want_e) block_energy(e, a.S, a.cpb, a.e_part);
 }
@@ -607,21 +634,29 @@ __global__ __launch_bounds__(kBlock) void energy_kernel(StageArgs<R> a) {
 }
 
 
-__global__ void energy_reduce_kernel(const double *part, int n_blocks, int S, double *out, const Clock *clock,
-                                     int cap) {
-    __shared__ double buf[kBlock];
-    const int s = blockIdx.x;
-    double acc = 0;
-    for (int b = threadIdx.x; b < n_blocks; b += blockDim.x) acc += part[(long long)b * S + s];
-    buf[threadIdx.x] = acc;
+// Sum of the energy partials of every block, one workgroup of kReduceBlock lanes per shot: four
+// independent partial sums per lane (loads in flight together), a shuffle fold per wavefront, and
+// the wavefronts' sums added in LDS.
+constexpr int kReduceBlock = 1024;
+__global__ __launch_bounds__(kReduceBlock) void energy_reduce_kernel(const double *part, int n_blocks, int S,
+                                                                     double *out, const Clock *clock, int cap) {
+    __shared__ double buf[kReduceBlock / 64];
+    const int s = blockIdx.x, tid = threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int b = tid;
+    for (; b + 3 * kReduceBlock < n_blocks; b += 4 * kReduceBlock)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += part[(long long)(b + u * kReduceBlock) * S + s];
+    for (; b < n_blocks; b += kReduceBlock) acc[0] += part[(long long)b * S + s];
+    double v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((tid & 63) == 0) buf[tid >> 6] = v;
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        if (!clock) out[s] = buf[0];
-        else if (clock->step < cap) out[(long long)clock->step * S + s] = buf[0];
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kReduceBlock / 64; ++w) t += buf[w];
+        if (!clock) out[s] = t;
+        else if (clock->step < cap) out[(long long)clock->step * S + s] = t;
     }
 }
 
@@ -678,7 +713,7 @@ hipError_t launch_energy(const StageArgs<R> &a, const R *state, int n_blocks, hi
 
 hipError_t launch_energy_reduce(const double *part, int n_blocks, int S, double *out, const Clock *clock, int cap,
                                 hipStream_t st) {
-    hipLaunchKernelGGL(energy_reduce_kernel, dim3(S), dim3(kBlock), 0, st, part, n_blocks, S, out, clock, cap);
+    hipLaunchKernelGGL(energy_reduce_kernel, dim3(S), dim3(kReduceBlock), 0, st, part, n_blocks, S, out, clock, cap);
     return hipGetLastError();
 }
 

@@ -358,15 +358,33 @@ __device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R
     }
 }
 
-// Block reduction of per-lane energies into one partial per shot.
+// Block reduction of per-lane energies into one partial per shot: lanes are (cell, shot) with the
+// shot fastest, so lanes l and l + S hold the same shot.  When S divides the wavefront size, each
+// wavefront folds its lanes with shuffles (offsets 32, 16, ... down to S keep the shot), and the
+// first S lanes of the block add the wavefronts' partials; otherwise one lane per shot adds its
+// block's cells through LDS.
 __device__ void block_energy(double e, int S, int cpb, double *out) {
     __shared__ double buf[kBlock];
-    buf[threadIdx.x] = e;
+    const int tid = threadIdx.x;
+    if (64 % S == 0) {
+        for (int off = 32; off >= S; off >>= 1) e += __shfl_down(e, off, 64);
+        const int wave = tid >> 6, lane = tid & 63;
+        if (lane < S) buf[wave * S + lane] = e;
+        __syncthreads();
+        if (tid < S) {
+            const int waves = (cpb * S + 63) >> 6;
+            double s = 0;
+            for (int w = 0; w < waves; ++w) s += buf[w * S + tid];
+            out[(long long)blockIdx.x * S + tid] = s;
+        }
+        return;
+    }
+    buf[tid] = e;
     __syncthreads();
-    if ((int)threadIdx.x < S) {
+    if (tid < S) {
         double s = 0;
-        for (int m = 0; m < cpb; ++m) s += buf[threadIdx.x + m * S];
-        out[(long long)blockIdx.x * S + threadIdx.x] = s;
+        for (int m = 0; m < cpb; ++m) s += buf[tid + m * S];
+        out[(long long)blockIdx.x * S + tid] = s;
     }
 }
 

@@ -14,8 +14,9 @@
 Besides the relative L2 norm of the whole state, the cells beside the fluid-solid interface are
 checked on their own: the largest cell-wise error there, over the largest cell-wise norm there,
 must meet the same tolerance (an error confined to the interface would hide in the global norm).
-Tolerances: 1e-12 float64, 1e-5 float32 (state, traces, energies); adjoint as in
-test_gpu_adjoint.py.
+Tolerances: 1e-12 float64, 1e-5 float32 (state, traces, energies); adjoint: J 1e-11 and gradient
+1e-11 relative in float64, in float32 2e-5 times the ratio of the trace amplitude to the residual
+amplitude (J is a sum of squared residuals R U - d, which cancels that much of the traces).
 """
 import sys
 
@@ -144,9 +145,13 @@ def test_adjoint_workload_as_specified():
     del ot
     o = Oracle(mesh, k)
     o.set_point_sources(SRC, DIRS, f0, t0, 1.0)
-    J0, g0 = misfit_gradient_checkpointed(o, np.zeros(o.ndof), 0.0, dt, nsteps, Receivers(o, rec_xy, rec_f),
-                                          d_obs, every=every)
-    say("oracle J", J0)
+    J0, g0, tr0 = misfit_gradient_checkpointed(o, np.zeros(o.ndof), 0.0, dt, nsteps, Receivers(o, rec_xy, rec_f),
+                                               d_obs, every=every, return_traces=True)
+    # float32: the traces carry a relative error of up to the stepping tolerance (1e-5); J is a sum
+    # of squared residuals R U - d, about `amp` times smaller than the traces, so its relative error
+    # and the gradient's are bounded by 2 x 1e-5 x amp
+    amp = float(np.linalg.norm(tr0) / np.linalg.norm(tr0 - d_obs))
+    say("oracle J", J0, "trace / residual amplitude", amp)
     res = {}
     for d in ("f64", "f32"):
         e = Engine(mesh, k, dtype=d)
@@ -158,7 +163,7 @@ def test_adjoint_workload_as_specified():
         if d == "f64":
             assert abs(J - J0) < 1e-11 * J0 and rel(g, g0) < 1e-11
         else:
-            assert abs(J - J0) < 2e-5 * J0 and rel(g, g0) < 5e-5
+            assert abs(J - J0) < 2e-5 * amp * J0 and rel(g, g0) < 2e-5 * amp
         e.close()
     # central finite differences of J (float64 forward runs on the GPU) on 20 seeded cells
     grad = res["f64"]

@@ -86,7 +86,7 @@ def test_sdirk_ricker_ic_matches_oracle_projection(k, field):
     say("case: sdirk ricker ic k=%d field=%d" % (k, field))
     mesh = M.hanging_square(6, seed=4)
     xc, yc, lam = 0.5, 0.7, 0.5
-    ref = ImplicitOracle(mesh, k).project(*ricker_fields(xc, yc, lam, 1.0, field))
+    ref = ImplicitOracle(mesh, k).project(*ricker_fields(xc, yc, lam, 1.0, field), nq=16)
     e = SdirkEngine(mesh, k, 0.01)
     e.set_ricker_ic((xc, yc), lam, field=field)
     err = rel(e.get_state(), ref)

@@ -169,7 +169,10 @@ def test_physical_materials_parity(k):
     ref = io.sdirk(U0, 0.0, dt, 5, s=3)
     err = rel(e.get_state(), ref)
     say("  rel L2", err, "stats", e.stats())
-    assert np.linalg.norm(ref) > 0 and err < TOL
+    # face solves to 1e-14 in the scaled residual leave a state error of up to the condition number
+    # of the scaled face system times that; with tau^s on c_S (granite: half the c_P weight) the
+    # system is less well conditioned than with c_P (measured 6.4e-12 at k = 1, 8e-13 with c_P)
+    assert np.linalg.norm(ref) > 0 and err < 2e-11
     e.close()
 
 
