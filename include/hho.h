@@ -176,6 +176,16 @@ hho_status hho_get_traces(hho_ctx *ctx, int32_t shot, double *out);
 /* Energy of the current state of every shot, float64: E[n_shots]. */
 hho_status hho_energy(hho_ctx *ctx, double *E);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the energies of hho_energy written to E[n_shots], a
+ * device pointer (float64), enqueued on params.stream without synchronising.  The per-block
+ * partial sums go to a static 2 MiB scratch array of the library on the context's device
+ * (262144 doubles; resolved at hho_setup), so the call allocates nothing; ARG when the context
+ * needs more than that (blocks of the launch shape x shots).  Every call on one device shares
+ * that array: calls that overlap on one GPU (other host threads, other streams) race; calls in
+ * one stream order are safe.  Results equal hho_energy's. */
+hho_status hho_energy_noalloc(hho_ctx *ctx, double *E);
+
 /* Energies recorded after each step of the last hho_erk_step call (record_energy = 1):
  * out[n_steps] for one shot. */
 hho_status hho_energy_history(hho_ctx *ctx, int32_t shot, double *out);

@@ -15,6 +15,7 @@
 #include "../../include/hho.h"
 #include "device.h"
 #include "initial.h"
+#include "internal.h"
 #include "plan.h"
 
 using namespace hho;
@@ -1031,6 +1032,33 @@ hho_status run_steps(hho_ctx *ctx, double t0, double dt, int n_steps, std::vecto
 
 }  // namespace
 
+namespace hho {
+
+int ctx_device(const hho_ctx *ctx) { return ctx->device; }
+
+void ctx_set_error(hho_ctx *ctx, const std::string &msg) { ctx->err = msg; }
+
+hho_status energy_into(hho_ctx *ctx, double *part, size_t cap, double *out) {
+    const size_t need = (size_t)ctx->n_blocks() * (size_t)ctx->plan.S;
+    if (need > cap) {
+        ctx->err = "energy: " + std::to_string(need) + " partial sums (blocks x shots) exceed the scratch capacity of " +
+                   std::to_string(cap);
+        return HHO_ERR_ARG;
+    }
+    return dispatch(ctx, [&](auto kc, auto *r) -> hho_status {
+        using R = std::remove_pointer_t<decltype(r)>;
+        StageArgs<R> a = base_args<R>(ctx);
+        a.e_part = part;
+        a.Yin = (const R *)ctx->U;
+        set_stage_offsets(ctx, a);
+        HCK((launch_energy<decltype(kc)::value, R>(a, (const R *)ctx->U, ctx->n_blocks(), ctx->stream)));
+        HCK(launch_energy_reduce(part, ctx->n_blocks(), ctx->plan.S, out, nullptr, 0, ctx->stream));
+        return HHO_OK;
+    });
+}
+
+}  // namespace hho
+
 // Runs one C ABI call; a C++ exception (a failed host allocation, above all) becomes a status
 // code and a message instead of crossing the ABI.
 template <typename F>
@@ -1163,6 +1191,13 @@ hho_status hho_setup(const hho_mesh *mesh, const hho_params *prm, hho_ctx **out)
             hipError_t e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
             if (e != hipSuccess) {
                 ctx->err = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+                return fail(HHO_ERR_DEVICE);
+            }
+        }
+        {
+            const std::string m = noalloc_init(ctx->device);
+            if (!m.empty()) {
+                ctx->err = m;
                 return fail(HHO_ERR_DEVICE);
             }
         }

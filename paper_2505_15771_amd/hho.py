@@ -64,6 +64,7 @@ EXPORTS = {
     "hho_synchronize": (C.c_int, [C.c_void_p]),
     "hho_get_traces": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "hho_energy": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "hho_energy_noalloc": (C.c_int, [C.c_void_p, C.c_void_p]),
     "hho_energy_history": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "hho_autotune": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "hho_set_launch": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -311,6 +312,14 @@ class Engine:
         E = np.zeros(self.n_shots)
         self._call(self.lib.hho_energy, _ptr(E))
         return E
+
+    def energy_noalloc(self, out):
+        """hho_energy_noalloc: energies into `out`, a contiguous float64 cuda tensor of n_shots
+        values, on the context's stream (no device allocation, no synchronisation)."""
+        if not (out.is_cuda and out.is_contiguous() and str(out.dtype) == "torch.float64"
+                and out.numel() == self.n_shots):
+            raise ValueError("energy_noalloc: out must be a contiguous float64 cuda tensor of n_shots values")
+        self._call(self.lib.hho_energy_noalloc, C.c_void_p(out.data_ptr()))
 
     def autotune(self):
         """Time the stage kernel in every launch shape and store policy, keep the fastest;
