@@ -107,6 +107,45 @@ typedef struct {
  * upload of SoA buffers.  State starts at zero.  Errors: ARG, MESH, SINGULAR, OOM, DEVICE. */
 hho_status hho_setup(const hho_mesh *mesh, const hho_params *params, hho_ctx **out);
 
+/* Three-dimensional mesh of tetrahedra and hexahedra aligned with the fluid / solid partition
+ * (the method of Sec. 2-3 with d = 3; Table tab::DOFS counts its unknowns):
+ *   xyz[3*n_vertices]         vertex coordinates (x, y, z)
+ *   cell_ptr[n_cells+1]       CSR offsets into cell_vtx: 4 ids (tetrahedron) or 8 ids (hexahedron
+ *                             with planar faces: vertices 0-3 around the bottom face, 4-7 above
+ *                             vertices 0-3 in the same order); cells must be convex
+ *   medium, rho, a, b         as in hho_mesh (solid: lambda, mu of 3D isotropic elasticity)
+ * Every face (same vertex set) must be shared by at most two cells.  Local faces: tetrahedron
+ * face j is opposite vertex j; hexahedron faces (0 1 2 3), (4 5 6 7), (0 1 5 4), (1 2 6 5),
+ * (2 3 7 6), (3 0 4 7). */
+typedef struct {
+    int32_t n_vertices;
+    const double *xyz;
+    int32_t n_cells;
+    const int32_t *cell_ptr;
+    const int32_t *cell_vtx;
+    const uint8_t *medium;
+    const double *rho;
+    const double *a;
+    const double *b;
+} hho_mesh3d;
+
+/* hho_setup for a three-dimensional mesh.  The returned context works with hho_sizes,
+ * hho_set_state / hho_get_state, hho_erk_step, hho_energy, hho_energy_history, hho_energy_noalloc,
+ * hho_set_dt_scale, hho_cfl_search, the tuning calls and hho_batch_*; point sources, loads,
+ * receivers, the Ricker initial field, the adjoint and hho_dt_cfl are two-dimensional only (ARG).
+ * State layout (external, per cell contiguous, float64), N = (k+1)(k+2)(k+3)/6:
+ *   fluid cell  [p | m_x | m_y | m_z]
+ *   solid cell  [v_x | v_y | v_z | s_1 | s_2 | s_3 | s_4 | s_5 | s_6]
+ * in the orthonormalised graded monomials ((x-x_T)/h_T)^a ((y-y_T)/h_T)^b ((z-z_T)/h_T)^c (degree
+ * major; within a degree decreasing a, then decreasing b; x_T the barycentre, h_T the largest
+ * vertex distance); stress coefficients on E_1..E_3 = e_i e_i^T and E_4, E_5, E_6 =
+ * (e_i e_j^T + e_j e_i^T)/sqrt(2) for ij = xy, xz, yz.  Face unknowns (eliminated at every stage)
+ * live in a basis of P^k(F) fixed by the face: monomials in a frame whose origin is the face
+ * centroid and whose first axis runs from the face's lowest-id vertex to its second-lowest-id
+ * vertex, orthonormalised in L2(F).  Errors: ARG, MESH (vertex count, repeated vertex, non-planar
+ * face, non-convex or degenerate cell, face shared by three cells), SINGULAR, OOM, DEVICE. */
+hho_status hho_setup3d(const hho_mesh3d *mesh, const hho_params *params, hho_ctx **out);
+
 /* Release every device buffer and the context (NULL is ignored). */
 void hho_destroy(hho_ctx *ctx);
 

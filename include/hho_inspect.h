@@ -35,6 +35,11 @@ extern "C" {
 typedef struct hho_inspect hho_inspect;
 
 hho_status hho_inspect_create(const hho_mesh *mesh, const hho_params *params, hho_inspect **out);
+/* Plan of a three-dimensional mesh (see hho_setup3d).  Table layout per shape class: B_x, B_y,
+ * B_z, S (N x N each), then G_j (N x F, F = (k+1)(k+2)/2) for every local face, then the outward
+ * unit normals n_j (3 values per face); mat holds 1/rho, kappa or lambda + 2 mu, eta tau, lambda,
+ * 2 mu, 1/(eta tau). */
+hho_status hho_inspect3d_create(const hho_mesh3d *mesh, const hho_params *params, hho_inspect **out);
 void hho_inspect_destroy(hho_inspect *p);
 
 /* sizes[0..9] = N, F, n_ic, max_nf, n_groups, n_table_values, n_cells, n_faces, cpb, n_blocks */

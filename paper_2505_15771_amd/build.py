@@ -16,7 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhho.so")
-SOURCES = ["plan.cpp", "api.cpp", "kernels.hip", "adjoint.hip", "implicit_plan.cpp", "sdirk.hip", "noalloc.hip"]
+SOURCES = ["plan.cpp", "plan3d.cpp", "api.cpp", "kernels.hip", "kernels3d_k1.hip", "kernels3d_k2.hip",
+           "adjoint.hip", "implicit_plan.cpp",
+           "sdirk.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

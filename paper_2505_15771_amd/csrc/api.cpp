@@ -304,6 +304,7 @@ template <typename R>
 StageArgs<R> base_args(hho_ctx *ctx) {
     StageArgs<R> a;
     std::memset(&a, 0, sizeof(a));
+    a.dim = ctx->plan.dim;
     a.link = ctx->link;
     a.c0 = (const R *)ctx->c0;
     a.mat = (const R *)ctx->mat;
@@ -457,6 +458,13 @@ hho_status enqueue_steps(hho_ctx *ctx, hipStream_t st, int n_steps, R *store = n
                                      ecap, st));
     }
     return HHO_OK;
+}
+
+// Entry points built for polygonal meshes only (point location, loads, the adjoint, the tabulated
+// CFL step): ARG on a three-dimensional context.
+hho_status two_dim_only(hho_ctx *ctx, const char *what) {
+    ctx->err = std::string(what) + ": not available on a three-dimensional context";
+    return HHO_ERR_ARG;
 }
 
 template <typename Fn>
@@ -1077,6 +1085,126 @@ hho_status guarded(std::string *err, F &&body) noexcept {
     }
 }
 
+namespace {
+
+// Device side of hho_setup / hho_setup3d once the context's plan is built: buffers, uploads,
+// launch shapes, capture stream.  On failure the context is destroyed and the message kept as
+// the setup error.
+hho_status setup_device(hho_ctx *ctx, const hho_params *prm, hho_ctx **out) {
+    auto fail = [&](hho_status s) {
+        g_setup_error = ctx->err;
+        hho_destroy(ctx);
+        return s;
+    };
+    hho_status s = set_device(ctx);
+    if (s != HHO_OK) return fail(s);
+    Plan &P = ctx->plan;
+    ctx->LT = (long long)P.n_ic * P.S;
+    ctx->rows = P.rows_s * P.N;
+    ctx->trows = trace_rows(P);
+    const size_t sbytes = (size_t)ctx->rows * ctx->LT * ctx->rsize;
+    const size_t tbytes = (size_t)ctx->trows * ctx->LT * ctx->rsize;
+    const size_t lbytes = (size_t)P.max_nf * P.n_ic * 4;
+    const size_t cbytes = (size_t)P.max_nf * P.n_ic * ctx->rsize;
+    const size_t mbytes = (size_t)kNumMat * P.n_ic * ctx->rsize;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t total = 4 * al(sbytes) + 3 * al(tbytes) + al(lbytes) + al(cbytes) + al(mbytes);
+    // the kernels address the arena through one buffer resource with 32-bit byte offsets
+    if (total >= (1ull << 32)) {
+        ctx->err = "cells x shots too large for one context (arena of " + std::to_string(total) +
+                   " bytes exceeds 4 GiB)";
+        return fail(HHO_ERR_ARG);
+    }
+    if ((s = dalloc(ctx, &ctx->arena, total))) return fail(s);
+    ctx->arena_bytes = total;
+    {
+        char *p = (char *)ctx->arena;
+        auto take = [&](size_t b) {
+            void *q = p;
+            p += al(b);
+            return q;
+        };
+        ctx->U = take(sbytes);
+        ctx->Y[0] = take(sbytes);
+        ctx->Y[1] = take(sbytes);
+        ctx->acc = take(sbytes);
+        for (int i = 0; i < 3; ++i) ctx->T[i] = take(tbytes);
+        ctx->link = (int32_t *)take(lbytes);
+        ctx->c0 = take(cbytes);
+        ctx->mat = take(mbytes);
+    }
+    std::vector<int64_t> map(P.n_ext);
+    for (int c = 0; c < P.n_cells; ++c) {
+        const int nr = (P.medium[c] == kFluid ? P.rows_f : P.rows_s) * P.N;
+        for (int r = 0; r < nr; ++r)
+            map[P.ext_off[c] + r] = (int64_t)r * ctx->LT + (int64_t)P.ic_of_cell[c] * P.S;
+    }
+    if ((s = copy_in(ctx, ctx->link, P.link)) || (s = copy_in_real(ctx, ctx->c0, P.c0)) ||
+        (s = copy_in_real(ctx, ctx->mat, P.mat)) || (s = upload_real(ctx, &ctx->tab, P.tables)) ||
+        (s = upload(ctx, &ctx->emat, P.emat)) || (s = upload(ctx, &ctx->map, map)) ||
+        (s = upload(ctx, &ctx->ic_tab, P.ic_tab)) ||
+        (s = dalloc(ctx, (void **)&ctx->staging, std::max<size_t>(1, P.n_ext) * 4 * sizeof(double))) ||
+        (s = dalloc(ctx, (void **)&ctx->e_now, (size_t)P.S * sizeof(double))) ||
+        (s = dalloc(ctx, (void **)&ctx->clock, 2 * sizeof(Clock))))
+        return fail(s);
+    for (const Plan::Launch &L : P.launches) {
+        std::vector<GroupDev> gd;
+        for (size_t g = 0; g < P.groups.size(); ++g) {
+            const Group &G = P.groups[g];
+            gd.push_back({G.medium, G.nF, G.tab_off, G.ic_begin, G.ncells, L.blk_begin[g], G.pooled ? 1 : 0});
+        }
+        hho_ctx::LaunchDev d;
+        d.n_blocks = (int)L.blk_group.size();
+        d.cpb = L.cpb;
+        d.lanes = L.lanes;
+        if ((s = upload(ctx, &d.groups, gd)) || (s = upload(ctx, &d.blk_group, L.blk_group))) return fail(s);
+        ctx->launch.push_back(d);
+        ctx->max_blocks = std::max(ctx->max_blocks, d.n_blocks);
+    }
+    if ((s = dalloc(ctx, (void **)&ctx->e_part, (size_t)ctx->max_blocks * P.S * sizeof(double)))) return fail(s);
+    ctx->cfl_dt = P.dim == 2 ? cfl_time_step(P, prm->rk_stages) : 0.0;
+    {
+        hipError_t e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            ctx->err = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+            return fail(HHO_ERR_DEVICE);
+        }
+    }
+    {
+        const std::string m = noalloc_init(ctx->device);
+        if (!m.empty()) {
+            ctx->err = m;
+            return fail(HHO_ERR_DEVICE);
+        }
+    }
+    *out = ctx;
+    return HHO_OK;
+}
+
+// Checks of the parameters shared by both dimensions; creates the context (plan not built).
+hho_status new_context(const hho_params *prm, hho_ctx **ctx_out) {
+    if (prm->dtype != 0 && prm->dtype != 1) {
+        g_setup_error = "dtype must be 0 (float64) or 1 (float32)";
+        return HHO_ERR_ARG;
+    }
+    std::vector<StageCoef> co;
+    if (!erk_coefficients(prm->rk_stages, co)) {
+        g_setup_error = "rk_stages must be 2, 3 or 4";
+        return HHO_ERR_ARG;
+    }
+    hho_ctx *ctx = new hho_ctx();
+    ctx->dtype = prm->dtype;
+    ctx->stages = prm->rk_stages;
+    ctx->record_energy = prm->record_energy ? 1 : 0;
+    ctx->device = prm->device;
+    ctx->stream = (hipStream_t)prm->stream;
+    ctx->rsize = prm->dtype == 0 ? 8 : 4;
+    *ctx_out = ctx;
+    return HHO_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *hho_last_error(const hho_ctx *ctx) { return ctx ? ctx->err.c_str() : g_setup_error.c_str(); }
@@ -1090,22 +1218,8 @@ hho_status hho_setup(const hho_mesh *mesh, const hho_params *prm, hho_ctx **out)
             g_setup_error = "null mesh or params";
             return HHO_ERR_ARG;
         }
-        if (prm->dtype != 0 && prm->dtype != 1) {
-            g_setup_error = "dtype must be 0 (float64) or 1 (float32)";
-            return HHO_ERR_ARG;
-        }
-        std::vector<StageCoef> co;
-        if (!erk_coefficients(prm->rk_stages, co)) {
-            g_setup_error = "rk_stages must be 2, 3 or 4";
-            return HHO_ERR_ARG;
-        }
-        hho_ctx *ctx = new hho_ctx();
-        ctx->dtype = prm->dtype;
-        ctx->stages = prm->rk_stages;
-        ctx->record_energy = prm->record_energy ? 1 : 0;
-        ctx->device = prm->device;
-        ctx->stream = (hipStream_t)prm->stream;
-        ctx->rsize = prm->dtype == 0 ? 8 : 4;
+        hho_ctx *ctx = nullptr;
+        if (hho_status s = new_context(prm, &ctx)) return s;
         int code = 0;
         std::string msg = build_plan(mesh->n_vertices, mesh->xy, mesh->n_cells, mesh->cell_ptr, mesh->cell_vtx,
                                      mesh->medium, mesh->rho, mesh->a, mesh->b, prm->k, prm->eta_f, prm->eta_s,
@@ -1115,94 +1229,31 @@ hho_status hho_setup(const hho_mesh *mesh, const hho_params *prm, hho_ctx **out)
             delete ctx;
             return (hho_status)code;
         }
-        auto fail = [&](hho_status s) {
-            g_setup_error = ctx->err;
-            hho_destroy(ctx);
-            return s;
-        };
-        hho_status s = set_device(ctx);
-        if (s != HHO_OK) return fail(s);
-        Plan &P = ctx->plan;
-        ctx->LT = (long long)P.n_ic * P.S;
-        ctx->rows = 5 * P.N;
-        ctx->trows = trace_rows(P);
-        const size_t sbytes = (size_t)ctx->rows * ctx->LT * ctx->rsize;
-        const size_t tbytes = (size_t)ctx->trows * ctx->LT * ctx->rsize;
-        const size_t lbytes = (size_t)P.max_nf * P.n_ic * 4;
-        const size_t cbytes = (size_t)P.max_nf * P.n_ic * ctx->rsize;
-        const size_t mbytes = (size_t)kNumMat * P.n_ic * ctx->rsize;
-        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-        const size_t total = 4 * al(sbytes) + 3 * al(tbytes) + al(lbytes) + al(cbytes) + al(mbytes);
-        // the kernels address the arena through one buffer resource with 32-bit byte offsets
-        if (total >= (1ull << 32)) {
-            ctx->err = "cells x shots too large for one context (arena of " + std::to_string(total) +
-                       " bytes exceeds 4 GiB)";
-            return fail(HHO_ERR_ARG);
+        return setup_device(ctx, prm, out);
+    });
+}
+
+hho_status hho_setup3d(const hho_mesh3d *mesh, const hho_params *prm, hho_ctx **out) {
+    return guarded(&g_setup_error, [&]() -> hho_status {
+        g_setup_error.clear();
+        if (!out) return HHO_ERR_ARG;
+        *out = nullptr;
+        if (!mesh || !prm) {
+            g_setup_error = "null mesh or params";
+            return HHO_ERR_ARG;
         }
-        if ((s = dalloc(ctx, &ctx->arena, total))) return fail(s);
-        ctx->arena_bytes = total;
-        {
-            char *p = (char *)ctx->arena;
-            auto take = [&](size_t b) {
-                void *q = p;
-                p += al(b);
-                return q;
-            };
-            ctx->U = take(sbytes);
-            ctx->Y[0] = take(sbytes);
-            ctx->Y[1] = take(sbytes);
-            ctx->acc = take(sbytes);
-            for (int i = 0; i < 3; ++i) ctx->T[i] = take(tbytes);
-            ctx->link = (int32_t *)take(lbytes);
-            ctx->c0 = take(cbytes);
-            ctx->mat = take(mbytes);
+        hho_ctx *ctx = nullptr;
+        if (hho_status s = new_context(prm, &ctx)) return s;
+        int code = 0;
+        std::string msg = build_plan3d(mesh->n_vertices, mesh->xyz, mesh->n_cells, mesh->cell_ptr, mesh->cell_vtx,
+                                       mesh->medium, mesh->rho, mesh->a, mesh->b, prm->k, prm->eta_f, prm->eta_s,
+                                       prm->stab_speed, prm->n_shots, ctx->plan, &code);
+        if (code != 0) {
+            g_setup_error = msg;
+            delete ctx;
+            return (hho_status)code;
         }
-        std::vector<int64_t> map(P.n_ext);
-        for (int c = 0; c < P.n_cells; ++c) {
-            const int nr = (P.medium[c] == kFluid ? 3 : 5) * P.N;
-            for (int r = 0; r < nr; ++r)
-                map[P.ext_off[c] + r] = (int64_t)r * ctx->LT + (int64_t)P.ic_of_cell[c] * P.S;
-        }
-        if ((s = copy_in(ctx, ctx->link, P.link)) || (s = copy_in_real(ctx, ctx->c0, P.c0)) ||
-            (s = copy_in_real(ctx, ctx->mat, P.mat)) || (s = upload_real(ctx, &ctx->tab, P.tables)) ||
-            (s = upload(ctx, &ctx->emat, P.emat)) || (s = upload(ctx, &ctx->map, map)) ||
-            (s = upload(ctx, &ctx->ic_tab, P.ic_tab)) ||
-            (s = dalloc(ctx, (void **)&ctx->staging, std::max<size_t>(1, P.n_ext) * 4 * sizeof(double))) ||
-            (s = dalloc(ctx, (void **)&ctx->e_now, (size_t)P.S * sizeof(double))) ||
-            (s = dalloc(ctx, (void **)&ctx->clock, 2 * sizeof(Clock))))
-            return fail(s);
-        for (const Plan::Launch &L : P.launches) {
-            std::vector<GroupDev> gd;
-            for (size_t g = 0; g < P.groups.size(); ++g) {
-                const Group &G = P.groups[g];
-                gd.push_back({G.medium, G.nF, G.tab_off, G.ic_begin, G.ncells, L.blk_begin[g], G.pooled ? 1 : 0});
-            }
-            hho_ctx::LaunchDev d;
-            d.n_blocks = (int)L.blk_group.size();
-            d.cpb = L.cpb;
-            d.lanes = L.lanes;
-            if ((s = upload(ctx, &d.groups, gd)) || (s = upload(ctx, &d.blk_group, L.blk_group))) return fail(s);
-            ctx->launch.push_back(d);
-            ctx->max_blocks = std::max(ctx->max_blocks, d.n_blocks);
-        }
-        if ((s = dalloc(ctx, (void **)&ctx->e_part, (size_t)ctx->max_blocks * P.S * sizeof(double)))) return fail(s);
-        ctx->cfl_dt = cfl_time_step(P, prm->rk_stages);
-        {
-            hipError_t e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
-            if (e != hipSuccess) {
-                ctx->err = std::string("hipStreamCreate: ") + hipGetErrorString(e);
-                return fail(HHO_ERR_DEVICE);
-            }
-        }
-        {
-            const std::string m = noalloc_init(ctx->device);
-            if (!m.empty()) {
-                ctx->err = m;
-                return fail(HHO_ERR_DEVICE);
-            }
-        }
-        *out = ctx;
-        return HHO_OK;
+        return setup_device(ctx, prm, out);
     });
 }
 
@@ -1264,6 +1315,7 @@ hho_status hho_set_ricker_ic(hho_ctx *ctx, int32_t shot, double xc, double yc, d
                              int32_t field) {
     return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
         if (!ctx) return HHO_ERR_ARG;
+        if (ctx->plan.dim != 2) return two_dim_only(ctx, "set_ricker_ic");
         if (shot < 0 || shot >= ctx->plan.S || !(lambda > 0.0) || !std::isfinite(lambda) || !std::isfinite(xc) ||
             !std::isfinite(yc) || !std::isfinite(theta) || (field != 0 && field != 1)) {
             ctx->err = "set_ricker_ic: shot out of range, lambda <= 0, a non-finite value or field not 0 / 1";
@@ -1324,6 +1376,7 @@ hho_status hho_set_sources(hho_ctx *ctx, int32_t shot, int32_t n, const double *
                            const double *f0, const double *t0, const double *amp) {
     return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
         if (!ctx) return HHO_ERR_ARG;
+        if (ctx->plan.dim != 2) return two_dim_only(ctx, "set_sources");
         if (shot < 0 || shot >= ctx->plan.S || n < 0 || (n > 0 && (!xy || !dir || !f0 || !t0 || !amp))) {
             ctx->err = "set_sources: bad arguments";
             return HHO_ERR_ARG;
@@ -1361,6 +1414,7 @@ hho_status hho_set_loads(hho_ctx *ctx, int32_t n_terms, const double *g, const d
                          const double *phase) {
     return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
         if (!ctx) return HHO_ERR_ARG;
+        if (ctx->plan.dim != 2) return two_dim_only(ctx, "set_loads");
         if (n_terms < 0 || n_terms > 4 || (n_terms > 0 && (!g || !omega || !phase))) {
             ctx->err = "set_loads: 0..4 terms with non-null arrays";
             return HHO_ERR_ARG;
@@ -1397,6 +1451,7 @@ hho_status hho_set_loads(hho_ctx *ctx, int32_t n_terms, const double *g, const d
 hho_status hho_receivers(hho_ctx *ctx, int32_t n, const double *xy, const int32_t *field) {
     return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
         if (!ctx) return HHO_ERR_ARG;
+        if (ctx->plan.dim != 2) return two_dim_only(ctx, "receivers");
         if (n < 0 || (n > 0 && (!xy || !field))) {
             ctx->err = "receivers: bad arguments";
             return HHO_ERR_ARG;
@@ -1580,6 +1635,7 @@ hho_status hho_adjoint_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps,
                             const double *d_obs, double *J, double *grad) {
     return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
         if (!ctx) return HHO_ERR_ARG;
+        if (ctx->plan.dim != 2) return two_dim_only(ctx, "adjoint_step");
         if (n_steps < 1 || !(dt > 0.0) || !std::isfinite(t0) || ckpt_every < 0 || !J || !grad ||
             (ctx->nrec > 0 && !d_obs)) {
             ctx->err = "adjoint_step: n_steps >= 1, dt > 0, ckpt_every >= 0, J, grad (and d_obs with receivers) required";
@@ -1728,6 +1784,7 @@ hho_status hho_get_tuning(const hho_ctx *ctx, int32_t *lanes, int32_t *flags) {
 hho_status hho_dt_cfl(const hho_ctx *ctx, double factor, double *dt) {
     return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
         if (!ctx || !dt || !(factor > 0.0)) return HHO_ERR_ARG;
+        if (ctx->plan.dim != 2) return two_dim_only(const_cast<hho_ctx *>(ctx), "dt_cfl");
         *dt = factor * ctx->cfl_dt;
         return HHO_OK;
     });
@@ -1958,6 +2015,26 @@ hho_status hho_inspect_create(const hho_mesh *mesh, const hho_params *prm, hho_i
     });
 }
 
+hho_status hho_inspect3d_create(const hho_mesh3d *mesh, const hho_params *prm, hho_inspect **out) {
+    return guarded(&g_setup_error, [&]() -> hho_status {
+        g_setup_error.clear();
+        if (!out || !mesh || !prm) return HHO_ERR_ARG;
+        *out = nullptr;
+        hho_inspect *p = new hho_inspect();
+        int code = 0;
+        std::string msg = build_plan3d(mesh->n_vertices, mesh->xyz, mesh->n_cells, mesh->cell_ptr, mesh->cell_vtx,
+                                       mesh->medium, mesh->rho, mesh->a, mesh->b, prm->k, prm->eta_f, prm->eta_s,
+                                       prm->stab_speed, prm->n_shots, p->plan, &code);
+        if (code != 0) {
+            g_setup_error = msg;
+            delete p;
+            return (hho_status)code;
+        }
+        *out = p;
+        return HHO_OK;
+    });
+}
+
 void hho_inspect_destroy(hho_inspect *p) { delete p; }
 
 hho_status hho_inspect_sizes(const hho_inspect *p, int64_t *sz) {
@@ -2006,6 +2083,7 @@ hho_status hho_inspect_dt_cfl(const hho_inspect *p, int32_t stages, double facto
     return guarded(&g_setup_error, [&]() -> hho_status {
         std::vector<StageCoef> co;
         if (!p || !dt || !(factor > 0.0) || !erk_coefficients(stages, co)) return HHO_ERR_ARG;
+        if (p->plan.dim != 2) return HHO_ERR_ARG;
         *dt = factor * cfl_time_step(p->plan, stages);
         return HHO_OK;
     });

@@ -39,6 +39,7 @@ struct Clock {
 
 template <typename R>
 struct StageArgs {
+    int dim;        // 2: polygons (kernels.hip), 3: tetrahedra and hexahedra (kernels3d.hip)
     const R *Yin;   // stage input: U^n (first stage) or the increment D_{i-1}  [rows][LT]
     R *Yout;        // stage output: the increment D_i   [rows][LT]  (unused on the last stage)
     R *U;           // U^n (read), U^{n+1} (written on the last stage)
@@ -104,7 +105,8 @@ struct StageArgs {
     int nobs;
 };
 
-// Launchers (kernels.hip).  K = polynomial degree, R = double or float.
+// Launchers (kernels.hip).  K = polynomial degree, R = double or float.  The stage, trace and
+// energy launchers forward arguments with dim = 3 to the three-dimensional kernels.
 template <int K, typename R>
 hipError_t launch_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st);
 
@@ -118,6 +120,16 @@ hipError_t launch_energy(const StageArgs<R> &a, const R *state, int n_blocks, hi
 // to out[clock->step * S + s] (an energy history), skipped past `cap` steps.
 hipError_t launch_energy_reduce(const double *part, int n_blocks, int S, double *out, const Clock *clock, int cap,
                                 hipStream_t st);
+
+// Three-dimensional stage, trace and energy launches (kernels3d_k*.hip; energy of a.Yin), for
+// k <= kMaxK3: at k = 3 a solid tetrahedron carries 180 unknowns, beyond one lane's registers.
+constexpr int kMaxK3 = 2;
+template <int K, typename R>
+hipError_t launch_stage3(const StageArgs<R> &a, int n_blocks, hipStream_t st);
+template <int K, typename R>
+hipError_t launch_traces3(const StageArgs<R> &a, int n_blocks, hipStream_t st);
+template <int K, typename R>
+hipError_t launch_energy3(const StageArgs<R> &a, int n_blocks, hipStream_t st);
 
 // Forward stage with the recompute stores (ystore / kstore / fstore non-null).
 template <int K, typename R>

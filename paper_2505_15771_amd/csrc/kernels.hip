@@ -676,6 +676,10 @@ __global__ void gather_kernel(const R *state, const int64_t *map, long long n, i
 
 template <int K, typename R>
 hipError_t launch_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
+    if (a.dim == 3) {
+        if constexpr (K <= kMaxK3) return launch_stage3<K, R>(a, n_blocks, st);
+        else return hipErrorNotSupported;
+    }
     if (!a.all_pooled) {
         if (a.nt_stores)
             hipLaunchKernelGGL((stage_kernel<K, R, false, kNonTemporal>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
@@ -689,6 +693,7 @@ hipError_t launch_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
 
 template <int K, typename R>
 hipError_t launch_stage_store(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
+    if (a.dim == 3) return hipErrorNotSupported;  // the adjoint is two-dimensional
     if (!a.all_pooled)
         hipLaunchKernelGGL((stage_kernel<K, R, true, 0>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     if (a.has_pooled)
@@ -698,6 +703,10 @@ hipError_t launch_stage_store(const StageArgs<R> &a, int n_blocks, hipStream_t s
 
 template <int K, typename R>
 hipError_t launch_traces(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
+    if (a.dim == 3) {
+        if constexpr (K <= kMaxK3) return launch_traces3<K, R>(a, n_blocks, st);
+        else return hipErrorNotSupported;
+    }
     if (!a.all_pooled) hipLaunchKernelGGL((trace_kernel<K, R>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     if (a.has_pooled) hipLaunchKernelGGL((trace_kernel<K, R, true>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
     return hipGetLastError();
@@ -707,6 +716,10 @@ template <int K, typename R>
 hipError_t launch_energy(const StageArgs<R> &a, const R *state, int n_blocks, hipStream_t st) {
     StageArgs<R> b = a;
     b.Yin = state;
+    if (a.dim == 3) {
+        if constexpr (K <= kMaxK3) return launch_energy3<K, R>(b, n_blocks, st);
+        else return hipErrorNotSupported;
+    }
     hipLaunchKernelGGL((energy_kernel<K, R>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, b);
     return hipGetLastError();
 }

@@ -102,7 +102,7 @@ struct CellGeom {
 
 }  // namespace
 
-int trace_rows(const Plan &plan) { return plan.max_nf * 2 * plan.F; }
+int trace_rows(const Plan &plan) { return plan.max_nf * plan.tcomp * plan.F; }
 
 void eval_basis(const Plan &plan, int c, double x, double y, double *phi) {
     const int N = plan.N;

@@ -61,6 +61,9 @@ constexpr int kNumEnergyMat = 4;
 constexpr int kNumGradCoef = 8;
 
 struct Plan {
+    // dim = 2: polygons, F = k + 1 face modes, cell rows 3N (fluid) / 5N (solid), 2 trace components
+    // dim = 3: tetrahedra and hexahedra, F = (k+1)(k+2)/2, cell rows 4N / 9N, 3 trace components
+    int dim = 2, tcomp = 2, rows_f = 3, rows_s = 5;
     int k = 1, N = 3, F = 2, S = 1;
     int stab_speed = 1;             // c^s in tau^s: 0 P-wave, 1 S-wave speed
     double eta_f = 0.8, eta_s = 1.5;
@@ -96,11 +99,12 @@ struct Plan {
     // with tau the stabilisation weight and [[A, B, 0], [B, A, 0], [0, 0, C]] the compliance.
     std::vector<double> gm;
     // geometry needed for point location / evaluation
-    std::vector<double> xy;
+    std::vector<double> xy;   // dim 2: vertex coordinates [2 * n_vertices]
+    std::vector<double> xyz;  // dim 3: [3 * n_vertices]
     std::vector<int32_t> cell_ptr, cell_vtx;
-    std::vector<double> centroid;  // [2*n_cells]
+    std::vector<double> centroid;  // [dim * n_cells]
     std::vector<double> hT;        // [n_cells]
-    std::vector<double> area;      // [n_cells]
+    std::vector<double> area;      // [n_cells] (dim 3: volume)
     std::vector<double> basisC;    // [n_classes][N][N] orthonormal basis coefficients (lower)
     std::vector<int> cell_class;   // [n_cells]
     std::vector<int32_t> ic_tab;   // [n_ic] class table offset of every internal cell (0: padding)
@@ -118,6 +122,16 @@ void eval_basis(const Plan &plan, int c, double x, double y, double *phi);
 // Lowest-id cell whose closed polygon contains (x, y), -1 if none.
 int locate_cell(const Plan &plan, double x, double y);
 
-int trace_rows(const Plan &plan);  // rows of a trace buffer: max_nf * 2 * F
+int trace_rows(const Plan &plan);  // rows of a trace buffer: max_nf * tcomp * F
+
+// Three-dimensional plan: cells are tetrahedra (4 vertex ids) or hexahedra with planar faces
+// (8 vertex ids, 0-3 around the bottom face, 4-7 above them); same status convention.
+std::string build_plan3d(int nv, const double *xyz, int nc, const int32_t *cell_ptr, const int32_t *cell_vtx,
+                         const uint8_t *medium, const double *rho, const double *a, const double *b, int k,
+                         double eta_f, double eta_s, int stab_speed, int n_shots, Plan &plan, int *code);
+// Orthonormal cell basis of input cell c at (x, y, z) -> phi[N] (three-dimensional plan).
+void eval_basis3(const Plan &plan, int c, double x, double y, double z, double *phi);
+// Lowest-id cell containing (x, y, z), -1 if none (three-dimensional plan).
+int locate_cell3(const Plan &plan, double x, double y, double z);
 
 }  // namespace hho

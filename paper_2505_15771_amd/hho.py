@@ -34,6 +34,12 @@ class _Mesh(C.Structure):
                 ("rho", C.c_void_p), ("a", C.c_void_p), ("b", C.c_void_p)]
 
 
+class _Mesh3d(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("xyz", C.c_void_p), ("n_cells", C.c_int32),
+                ("cell_ptr", C.c_void_p), ("cell_vtx", C.c_void_p), ("medium", C.c_void_p),
+                ("rho", C.c_void_p), ("a", C.c_void_p), ("b", C.c_void_p)]
+
+
 class _SdirkParams(C.Structure):
     _fields_ = [("k", C.c_int32), ("mixed", C.c_int32), ("alpha", C.c_int32), ("eta_f", C.c_double),
                 ("eta_s", C.c_double), ("stab_speed", C.c_int32), ("ell", C.c_double), ("stages", C.c_int32),
@@ -50,6 +56,7 @@ class _Params(C.Structure):
 EXPORTS = {
     # name: (restype, argtypes)
     "hho_setup": (C.c_int, [C.POINTER(_Mesh), C.POINTER(_Params), C.POINTER(C.c_void_p)]),
+    "hho_setup3d": (C.c_int, [C.POINTER(_Mesh3d), C.POINTER(_Params), C.POINTER(C.c_void_p)]),
     "hho_destroy": (None, [C.c_void_p]),
     "hho_last_error": (C.c_char_p, [C.c_void_p]),
     "hho_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
@@ -83,6 +90,7 @@ EXPORTS = {
     "hho_batch_erk_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "hho_batch_last_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "hho_inspect_create": (C.c_int, [C.POINTER(_Mesh), C.POINTER(_Params), C.POINTER(C.c_void_p)]),
+    "hho_inspect3d_create": (C.c_int, [C.POINTER(_Mesh3d), C.POINTER(_Params), C.POINTER(C.c_void_p)]),
     "hho_inspect_destroy": (None, [C.c_void_p]),
     "hho_inspect_sizes": (C.c_int, [C.c_void_p, C.c_void_p]),
     "hho_inspect_arrays": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
@@ -153,6 +161,32 @@ def _mesh_struct(mesh, keep):
     return m
 
 
+def _mesh3d_struct(mesh, keep):
+    """Three-dimensional mesh: xyz [n_vertices, 3] and either cell_ptr / cell_vtx (CSR) or `cells`
+    (a list of 4- or 8-tuples of vertex ids)."""
+    xyz = np.ascontiguousarray(mesh["xyz"], np.float64).reshape(-1)
+    if "cell_ptr" in mesh:
+        ptr, vtx = mesh["cell_ptr"], mesh["cell_vtx"]
+    else:
+        cells = mesh["cells"]
+        ptr = np.concatenate([[0], np.cumsum([len(c) for c in cells])])
+        vtx = np.concatenate([np.asarray(c) for c in cells])
+    arrs = dict(xyz=xyz,
+                cell_ptr=np.ascontiguousarray(ptr, np.int32),
+                cell_vtx=np.ascontiguousarray(vtx, np.int32),
+                medium=np.ascontiguousarray(mesh["medium"], np.uint8),
+                rho=np.ascontiguousarray(mesh["rho"], np.float64),
+                a=np.ascontiguousarray(mesh["a"], np.float64),
+                b=np.ascontiguousarray(mesh["b"], np.float64))
+    keep.update(arrs)
+    m = _Mesh3d()
+    m.n_vertices = len(xyz) // 3
+    m.n_cells = len(arrs["cell_ptr"]) - 1
+    for name in ("xyz", "cell_ptr", "cell_vtx", "medium", "rho", "a", "b"):
+        setattr(m, name, arrs[name].ctypes.data)
+    return m
+
+
 def _params(k, rk_stages, eta_f, eta_s, stab_speed, dtype, n_shots, record_energy, device, stream):
     p = _Params()
     p.k, p.rk_stages, p.eta_f, p.eta_s = int(k), int(rk_stages), float(eta_f), float(eta_s)
@@ -170,7 +204,8 @@ def _check(lib, code, h):
 
 
 class Engine:
-    """One discretisation on one GPU (hho_setup); see include/hho.h for the semantics.
+    """One discretisation on one GPU (hho_setup, or hho_setup3d for a mesh with "xyz"); see
+    include/hho.h for the semantics.
 
     State arrays are float64 in the per-cell layout of hho.h, either numpy arrays
     (host) or contiguous float64 torch cuda tensors (device)."""
@@ -188,10 +223,12 @@ class Engine:
                 stream = None
         self.stream = stream
         keep = {}
-        m = _mesh_struct(mesh, keep)
+        self.dim = 3 if "xyz" in mesh else 2
+        m = _mesh3d_struct(mesh, keep) if self.dim == 3 else _mesh_struct(mesh, keep)
         p = _params(k, rk_stages, eta_f, eta_s, stab_speed, dtype, n_shots, record_energy, device, stream)
         h = C.c_void_p()
-        _check(lib, lib.hho_setup(C.byref(m), C.byref(p), C.byref(h)), None)
+        setup = lib.hho_setup3d if self.dim == 3 else lib.hho_setup
+        _check(lib, setup(C.byref(m), C.byref(p), C.byref(h)), None)
         self._h = h
         self.k, self.n_shots, self.record_energy = k, n_shots, record_energy
         self.medium = keep["medium"].copy()
@@ -392,10 +429,12 @@ class Inspect:
         lib = load_library()
         self.lib = lib
         keep = {}
-        m = _mesh_struct(mesh, keep)
+        self.dim = 3 if "xyz" in mesh else 2
+        m = _mesh3d_struct(mesh, keep) if self.dim == 3 else _mesh_struct(mesh, keep)
         p = _params(k, 4, eta_f, eta_s, stab_speed, "f64", n_shots, False, 0, None)
         h = C.c_void_p()
-        _check(lib, lib.hho_inspect_create(C.byref(m), C.byref(p), C.byref(h)), None)
+        create = lib.hho_inspect3d_create if self.dim == 3 else lib.hho_inspect_create
+        _check(lib, create(C.byref(m), C.byref(p), C.byref(h)), None)
         self._h = h
         sz = np.zeros(10, np.int64)
         lib.hho_inspect_sizes(h, _ptr(sz))
@@ -415,7 +454,7 @@ class Inspect:
         self.pooled = np.zeros(self.n_groups, np.int32)
         lib.hho_inspect_cell_tables(h, _ptr(self.ic_tab), _ptr(self.pooled))
         self.dt_cfl = {}
-        for s in (2, 3, 4):
+        for s in ((2, 3, 4) if self.dim == 2 else ()):
             dt = C.c_double()
             _check(lib, lib.hho_inspect_dt_cfl(h, s, 1.0, C.byref(dt)), None)
             self.dt_cfl[s] = dt.value

@@ -433,3 +433,82 @@ def pressure_pulse(mesh, k, center=(0.0, 200.0), sigma=50.0, k_primal=None):
         r2 = (bc[c, 0] - center[0]) ** 2 + (bc[c, 1] - center[1]) ** 2
         U[off[c]] = np.exp(-r2 / (2 * sigma ** 2)) * np.sqrt(area)
     return U
+
+
+# ----------------------------------------------------------------------------- three dimensions
+# Three-dimensional meshes are dicts with xyz float64 [n_vertices, 3], cell_ptr / cell_vtx (4 ids
+# per tetrahedron, 8 per hexahedron: 0-3 around the bottom face counter-clockwise seen from above,
+# 4-7 above them), medium, and after with_materials3d rho, a, b.
+
+# the six tetrahedra of a cube around its diagonal from corner 0 to corner 6
+_KUHN = ((0, 1, 2, 6), (0, 2, 3, 6), (0, 3, 7, 6), (0, 7, 4, 6), (0, 4, 5, 6), (0, 5, 1, 6))
+
+
+def unit_cube(n, tets=True, jitter=0.0, seed=0, interface_z=0.5, shear=None):
+    """n^3 cubes on [0, 1]^3, solid below z = interface_z and fluid above (cell centres).  tets:
+    every cube cut into six tetrahedra (else kept as a hexahedron).  jitter: interior vertices off
+    the interface plane moved by U[-jitter, jitter] h per coordinate (seeded; tetrahedra only).
+    shear: a 3 x 3 matrix applied to every vertex (hexahedra stay parallelepipeds)."""
+    g = np.linspace(0.0, 1.0, n + 1)
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    xyz = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+    def vid(i, j, l):
+        return (i * (n + 1) + j) * (n + 1) + l
+
+    cells = []
+    for i in range(n):
+        for j in range(n):
+            for l in range(n):
+                h = (vid(i, j, l), vid(i + 1, j, l), vid(i + 1, j + 1, l), vid(i, j + 1, l),
+                     vid(i, j, l + 1), vid(i + 1, j, l + 1), vid(i + 1, j + 1, l + 1), vid(i, j + 1, l + 1))
+                if tets:
+                    cells += [tuple(h[t] for t in tt) for tt in _KUHN]
+                else:
+                    cells.append(h)
+    cells = np.array(cells, np.int64)
+    cent = xyz[cells].mean(axis=1)
+    medium = np.where(cent[:, 2] < interface_z, SOLID, FLUID).astype(np.uint8)
+    if jitter > 0.0:
+        if not tets:
+            raise ValueError("jitter keeps faces planar only for tetrahedra")
+        rng = np.random.default_rng(seed)
+        d = rng.uniform(-jitter, jitter, xyz.shape) / n
+        fixed = np.zeros(len(xyz), bool)
+        for ax in range(3):
+            fixed |= (np.abs(xyz[:, ax]) < 1e-12) | (np.abs(xyz[:, ax] - 1.0) < 1e-12)
+        fixed |= np.abs(xyz[:, 2] - interface_z) < 1e-12
+        xyz = xyz + np.where(fixed[:, None], 0.0, d)
+    if shear is not None:
+        xyz = xyz @ np.asarray(shear, float).T
+    if tets:  # positive orientation
+        P = xyz[cells]
+        det = np.einsum("ij,ij->i", P[:, 1] - P[:, 0], np.cross(P[:, 2] - P[:, 0], P[:, 3] - P[:, 0]))
+        flip = det < 0
+        cells[flip, 1], cells[flip, 2] = cells[flip, 2].copy(), cells[flip, 1].copy()
+    nv = cells.shape[1]
+    return dict(xyz=xyz, cell_ptr=np.arange(0, nv * len(cells) + 1, nv, dtype=np.int32),
+                cell_vtx=cells.reshape(-1).astype(np.int32), medium=medium)
+
+
+def with_materials3d(mesh, rho_f=1.0, c_f=1.0, rho_s=1.0, lam=1.0, mu=1.0, perturb=0.0, seed=0):
+    """Piecewise-constant materials: fluid (rho_f, c_f), solid (rho_s, lambda, mu); with perturb, every
+    per-cell parameter times (1 + U[-perturb, perturb]) (seeded)."""
+    med = np.asarray(mesh["medium"])
+    nc = len(med)
+    rng = np.random.default_rng(seed)
+    f = (lambda: 1.0 + rng.uniform(-perturb, perturb, nc)) if perturb > 0 else (lambda: np.ones(nc))
+    rho = np.where(med == FLUID, rho_f, rho_s) * f()
+    a = np.where(med == FLUID, c_f, lam) * f()
+    b = np.where(med == FLUID, 0.0, mu) * f()
+    out = dict(mesh)
+    out.update(rho=rho, a=a, b=b)
+    return out
+
+
+def max_wave_speed3d(mesh):
+    """Largest wave speed of a three-dimensional mesh with materials (c_P in the solid)."""
+    med = np.asarray(mesh["medium"])
+    rho, a, b = (np.asarray(mesh[k_]) for k_ in ("rho", "a", "b"))
+    c = np.where(med == FLUID, a, np.sqrt(np.maximum(a + 2.0 * b, 0.0) / rho))
+    return float(c.max())

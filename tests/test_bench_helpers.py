@@ -137,3 +137,18 @@ def test_summary_line_is_compact_json():
     assert d["roofline"]["frac"] == head["frac"] and d["roofline"]["bound"] == "hbm"
     assert "workload" in d["config"] and d["cpu_baseline"]["kind"] == "oracle"
     assert abs(d["speedup_vs_f64_single_shot"] - 9.5 / 2.61) < 1e-12
+
+
+def test_faces3d_counts_match_the_host_plan():
+    """bench.py's three-dimensional face count (algorithmic bytes) against the library's face links."""
+    import numpy as np
+    import bench
+    from paper_2505_15771_amd.hho import Inspect
+    from synth import meshes as M
+    for mesh in (M.with_materials3d(M.unit_cube(4)), M.with_materials3d(M.unit_cube(3, tets=False))):
+        ins = Inspect(mesh, 1)
+        L = ins.link
+        n_faces, n_interior, n_interface = bench._faces3d(mesh)
+        assert n_faces == ins.n_faces
+        assert n_interior == int(np.sum(L >= 0)) // 2
+        assert n_interface == int(np.sum((L >= 0) & (((L >> 3) & 1) == 1))) // 2

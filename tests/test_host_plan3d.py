@@ -1,0 +1,78 @@
+"""CPU checks of the three-dimensional host plan (hho_inspect3d_create, no GPU).
+
+The stage derivative k = M^{-1}(-K_eff U) that the three-dimensional kernels compute is
+reassembled in NumPy from the exported plan (tests/kernel_model3d.py: class tables in the
+orthonormal bases, face frames fixed by the faces, links, face-solve coefficients, materials) and
+compared with the three-dimensional FP64 oracle's on tetrahedra, sheared hexahedra (parallelepipeds)
+and tetrahedra with moved vertices (every cell its own shape class, pooled tables), k = 1 and 2,
+with the fluid-solid interface and perturbed materials.
+"""
+import numpy as np
+import pytest
+
+import kernel_model3d as KM
+from synth import meshes as M
+
+SHEAR = [[1.0, 0.2, 0.1], [0.0, 1.0, 0.3], [0.0, 0.0, 1.0]]
+
+
+def oracle_mesh(mesh):
+    cells = [tuple(int(v) for v in mesh["cell_vtx"][mesh["cell_ptr"][c]:mesh["cell_ptr"][c + 1]])
+             for c in range(len(mesh["medium"]))]
+    return dict(xyz=mesh["xyz"], cells=cells, medium=mesh["medium"], rho=mesh["rho"], a=mesh["a"], b=mesh["b"])
+
+
+CASES = {
+    "tets": lambda: M.with_materials3d(M.unit_cube(3), rho_f=2.0, c_f=1.5, rho_s=3.0, lam=2.0, mu=0.7),
+    "hexes-sheared": lambda: M.with_materials3d(M.unit_cube(3, tets=False, shear=SHEAR), perturb=0.1, seed=5),
+    "tets-moved": lambda: M.with_materials3d(M.unit_cube(4, jitter=0.25, seed=3), perturb=0.1, seed=4),
+}
+
+
+@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_plan3d_stage_derivative_matches_oracle(case, k):
+    from oracle.oracle3d import Oracle3D
+    from paper_2505_15771_amd.hho import Inspect
+    mesh = CASES[case]()
+    o = Oracle3D(oracle_mesh(mesh), k)
+    ins = Inspect(mesh, k)
+    U = np.random.default_rng(11).standard_normal(o.ndof)
+    ref = o.rhs(U)
+    got = KM.stage_derivative(ins, mesh, U)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err < 1e-12, err
+    if case == "tets-moved":
+        # every cell its own shape: more classes than the pooling threshold, all tables pooled
+        assert ins.pooled.all() and ins.n_groups == 2
+
+
+def test_plan3d_shape_classes_of_structured_meshes():
+    from paper_2505_15771_amd.hho import Inspect
+    # six tetrahedron shapes per cube, two media; one hexahedron shape, two media
+    assert Inspect(M.with_materials3d(M.unit_cube(4)), 1).n_groups == 12
+    hx = Inspect(M.with_materials3d(M.unit_cube(4, tets=False)), 2)
+    assert hx.n_groups == 2 and hx.N == 10 and hx.F == 6 and hx.max_nf == 6
+
+
+def test_plan3d_rejects_bad_input():
+    from paper_2505_15771_amd.hho import HHOError, Inspect
+    mesh = M.with_materials3d(M.unit_cube(2, tets=False))
+    with pytest.raises(HHOError) as e:
+        Inspect(mesh, 3)  # degree 3 is two-dimensional only
+    assert e.value.code == 1
+    bent = dict(mesh)
+    bent["xyz"] = mesh["xyz"].copy()
+    bent["xyz"][0, 2] -= 0.1  # corner moved out of the plane of its three faces
+    with pytest.raises(HHOError) as e:
+        Inspect(bent, 1)
+    assert e.value.code == 2
+    three = dict(mesh)
+    ptr, vtx = mesh["cell_ptr"], mesh["cell_vtx"]
+    three["cell_vtx"] = np.concatenate([vtx, vtx[ptr[0]:ptr[1]]])
+    three["cell_ptr"] = np.concatenate([ptr, [ptr[-1] + 8]]).astype(np.int32)
+    for key in ("medium", "rho", "a", "b"):
+        three[key] = np.concatenate([mesh[key], mesh[key][:1]])
+    with pytest.raises(HHOError) as e:
+        Inspect(three, 1)  # a cell listed twice: its faces are shared by three cells
+    assert e.value.code == 2
