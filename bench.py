@@ -245,7 +245,7 @@ def run_adjoint(k, dtype, steps=1000, ckpt=50, shots=1):
     dt = eng.dt_cfl(0.5)
     d_obs = np.zeros((shots, steps, len(rec_f), 2))
     zero = np.zeros(eng.n_dof)
-    eng.adjoint(0.0, dt, 20, d_obs[:, :20], ckpt)  # warm-up (workspace allocation)
+    eng.adjoint(0.0, dt, steps, d_obs, ckpt)  # warm-up: workspace allocation and the segment graphs
     for sh in range(shots):
         eng.set_state(zero, shot=sh)
     torch.cuda.synchronize()

@@ -130,9 +130,10 @@ typedef struct {
 } hho_mesh3d;
 
 /* hho_setup for a three-dimensional mesh.  The returned context works with hho_sizes,
- * hho_set_state / hho_get_state, hho_erk_step, hho_energy, hho_energy_history, hho_energy_noalloc,
- * hho_set_dt_scale, hho_cfl_search, the tuning calls and hho_batch_*; point sources, loads,
- * receivers, the Ricker initial field, the adjoint and hho_dt_cfl are two-dimensional only (ARG).
+ * hho_set_state / hho_get_state, hho_set_sources, hho_receivers / hho_get_traces, hho_erk_step,
+ * hho_energy, hho_energy_history, hho_energy_noalloc, hho_set_dt_scale, hho_cfl_search, the tuning
+ * calls and hho_batch_*; separable loads, the Ricker initial field, the adjoint and hho_dt_cfl are
+ * two-dimensional only (ARG).
  * State layout (external, per cell contiguous, float64), N = (k+1)(k+2)(k+3)/6:
  *   fluid cell  [p | m_x | m_y | m_z]
  *   solid cell  [v_x | v_y | v_z | s_1 | s_2 | s_3 | s_4 | s_5 | s_6]
@@ -181,7 +182,9 @@ hho_status hho_set_ricker_ic(hho_ctx *ctx, int32_t shot, double xc, double yc, d
  * the solid cell containing x_i (direction d_i = (dir[2i], dir[2i+1])), or on the p rows
  * of a fluid cell with weight dir[2i].  R_i is the Ricker wavelet
  * (1 - 2 a^2) exp(-a^2), a = pi f0_i (t - t0_i).  The containing cell is the lowest-id
- * cell whose closed polygon holds x_i.  Errors: ARG (point outside the mesh). */
+ * cell whose closed polygon holds x_i.  On a three-dimensional context xy and dir hold three
+ * values per source (x, y, z; d_x, d_y, d_z; a fluid source has weight d_x) and the cell is the
+ * lowest-id cell that contains x_i.  Errors: ARG (point outside the mesh). */
 hho_status hho_set_sources(hho_ctx *ctx, int32_t shot, int32_t n, const double *xy, const double *dir,
                            const double *f0, const double *t0, const double *amp);
 
@@ -193,7 +196,8 @@ hho_status hho_set_loads(hho_ctx *ctx, int32_t n_terms, const double *g, const d
 
 /* Register receivers (replaces earlier ones): field 0 records p (point must lie in the
  * fluid), field 1 records (v_x, v_y) (solid).  Values are point evaluations of the cell
- * polynomials (sensors of Sec. 5.2), recorded after every step of hho_erk_step. */
+ * polynomials (sensors of Sec. 5.2), recorded after every step of hho_erk_step.  On a
+ * three-dimensional context xy holds (x, y, z) per receiver and field 1 records (v_x, v_y, v_z). */
 hho_status hho_receivers(hho_ctx *ctx, int32_t n, const double *xy, const int32_t *field);
 
 /* Advance every shot by n_steps steps of ERK(rk_stages) from time t0 with step dt.  Every step
@@ -209,7 +213,8 @@ hho_status hho_erk_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps);
 hho_status hho_synchronize(hho_ctx *ctx);
 
 /* Receiver traces of the last hho_erk_step call for one shot: out[n_steps][n_rec][2]
- * (second slot 0 for p receivers), float64. */
+ * (second slot 0 for p receivers), float64; out[n_steps][n_rec][3] on a three-dimensional
+ * context (p, 0, 0 or v_x, v_y, v_z). */
 hho_status hho_get_traces(hho_ctx *ctx, int32_t shot, double *out);
 
 /* Energy of the current state of every shot, float64: E[n_shots]. */

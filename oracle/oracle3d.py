@@ -399,6 +399,41 @@ class Oracle3D:
         self._AFF_lu = spla.splu(sp.csc_matrix(self.AFF)) if self.nfdof else None
         self._M_lu = spla.splu(sp.csc_matrix(self.M))
 
+    # ------------------------------------------------------------------ points: sources, receivers
+    def locate(self, x):
+        """Lowest-id cell whose closed cell holds the point x: barycentric coordinates of x in the
+        cell's tetrahedra (the tetrahedron itself, or the six of a hexahedron) all >= -1e-12."""
+        x = np.asarray(x, float)
+        for c in range(self.nc):
+            for P in self._cell_tets(c):
+                D = np.stack([P[1] - P[0], P[2] - P[0], P[3] - P[0]], axis=1)
+                lam = np.linalg.solve(D, x - P[0])
+                if lam.min() >= -1e-12 and lam.sum() <= 1.0 + 1e-12:
+                    return c
+        raise ValueError("point outside the mesh")
+
+    def point_load(self, x, direction):
+        """Load vector of eq. rhs for the point force d delta(. - x): phi_a(x) d on the v rows of
+        the solid cell holding x, phi_a(x) d_x on the p rows of a fluid cell."""
+        c = self.locate(x)
+        phi, _ = self.cell_basis(c, np.asarray(x, float)[None, :])
+        F = np.zeros(self.ndof)
+        N = self.N
+        if self.medium[c] == FLUID:
+            F[self.off[c]: self.off[c] + N] = direction[0] * phi[0]
+        else:
+            for comp in range(3):
+                F[self.off[c] + comp * N: self.off[c] + (comp + 1) * N] = direction[comp] * phi[0]
+        return F
+
+    def point_values(self, U, x):
+        """(p,) in a fluid cell or (v_x, v_y, v_z) in a solid cell: the cell polynomials at x."""
+        c = self.locate(x)
+        phi, _ = self.cell_basis(c, np.asarray(x, float)[None, :])
+        N = self.N
+        comps = 1 if self.medium[c] == FLUID else 3
+        return np.array([phi[0] @ U[self.off[c] + i * N: self.off[c] + (i + 1) * N] for i in range(comps)])
+
     # ------------------------------------------------------------------ dynamics
     def face_values(self, U):
         """U_F = -A_FF^{-1} A_FT U_T (eq. ex_solve, first line)."""
@@ -416,16 +451,21 @@ class Oracle3D:
             r = r + F
         return self._M_lu.solve(r)
 
-    def erk(self, U, dt, nsteps, s=4):
+    def erk(self, U, dt, nsteps, s=4, load=None, t0=0.0, record=None):
+        """n steps of ERK(s) (eq. ERK) from time t0; load(t) gives the load vector F(t) of eq. rhs
+        at the stage times t_n + c_i dt; record(n, U) is called after every step."""
         from .oracle import ERK_TABLEAUX
-        A, b, _ = ERK_TABLEAUX[s]
+        A, b, c = ERK_TABLEAUX[s]
         U = np.array(U, float, copy=True)
-        for _ in range(nsteps):
+        for n in range(nsteps):
+            tn = t0 + n * dt
             ks = []
             for i in range(s):
                 Y = U + dt * sum(A[i, j] * ks[j] for j in range(i)) if i else U
-                ks.append(self.rhs(Y))
+                ks.append(self.rhs(Y, None if load is None else load(tn + c[i] * dt)))
             U = U + dt * sum(b[i] * ks[i] for i in range(s))
+            if record is not None:
+                record(n, U)
         return U
 
     def energy(self, U):
@@ -464,6 +504,13 @@ class Oracle3D:
         psi = self.face_basis(F, X)
         MF = (psi * W[:, None]).T @ psi
         return np.linalg.solve(MF, (psi * W[:, None]).T @ fn(X[:, 0], X[:, 1], X[:, 2]))
+
+
+def ricker(t, f0, t0):
+    """Ricker wavelet (1 - 2 a^2) exp(-a^2), a = pi f0 (t - t0): the time factor of the point
+    sources (the same convention as the two-dimensional oracle)."""
+    a = math.pi * f0 * (t - t0)
+    return (1.0 - 2.0 * a * a) * math.exp(-a * a)
 
 
 def cube_mesh(n, tets=True, medium_of=None, materials=None, L=1.0):

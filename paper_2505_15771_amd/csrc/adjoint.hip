@@ -30,6 +30,14 @@ namespace {
 //   solid: 0 dtau/drho, 1 dtau/dlambda, 2 dtau/dmu, 3 dA/dlambda (= dB/dlambda),
 //          4 dA/dmu, 5 dB/dmu, 6 dC/dmu   (compliance [[A, B, 0], [B, A, 0], [0, 0, C]])
 
+// Forward step whose misfit derivative enters lambda in this launch: a.inject is relative (0 =
+// none) to the step offset held by the adjoint clock, which the host sets before each checkpoint
+// segment, so that the captured adjoint stages of a segment replay unchanged for every segment.
+template <typename R>
+__device__ __forceinline__ int inject_step(const StageArgs<R> &a) {
+    return a.inject >= 1 ? a.inject + uni(a.clock)->step : 0;
+}
+
 template <typename R>
 __device__ __forceinline__ double gmv(const StageArgs<R> &a, int slot, int ic) {
     return a.gm[(long long)slot * a.n_ic + ic];
@@ -219,13 +227,14 @@ __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<
     } else {
 #pragma unroll
         for (int r = 0; r < 3 * N; ++r) lam[r] += lac[r] + yb[r];
-        if (a.inject >= 1 && a.rec_first) {
+        const int inj = inject_step(a);
+        if (inj >= 1 && a.rec_first) {
             for (int e = a.rec_first[ic]; e >= 0;) {
                 const RecDev &rc = a.rec[e];
                 double v = 0;
 #pragma unroll
                 for (int b = 0; b < N; ++b) v += rc.phi[b] * (double)yp[b];
-                const double d = a.dobs[(((long long)shot * a.nobs + a.inject - 1) * a.nrec + rc.r) * 2];
+                const double d = a.dobs[(((long long)shot * a.nobs + inj - 1) * a.nrec + rc.r) * 2];
                 const double w = uni(a.clock)->dt * (v - d);
 #pragma unroll
                 for (int b = 0; b < N; ++b) lam[b] += R(w * rc.phi[b]);
@@ -458,7 +467,8 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
     } else {
 #pragma unroll
         for (int r = 0; r < 5 * N; ++r) lam[r] += lac[r] + yb[r];
-        if (a.inject >= 1 && a.rec_first) {
+        const int inj = inject_step(a);
+        if (inj >= 1 && a.rec_first) {
             for (int e = a.rec_first[ic]; e >= 0;) {
                 const RecDev &rc = a.rec[e];
                 double v0 = 0, v1 = 0;
@@ -467,7 +477,7 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
                     v0 += rc.phi[b] * (double)yx[b];
                     v1 += rc.phi[b] * (double)yy[b];
                 }
-                const double *d = a.dobs + (((long long)shot * a.nobs + a.inject - 1) * a.nrec + rc.r) * 2;
+                const double *d = a.dobs + (((long long)shot * a.nobs + inj - 1) * a.nrec + rc.r) * 2;
                 const double dt = uni(a.clock)->dt;
                 const double w0 = dt * (v0 - d[0]), w1 = dt * (v1 - d[1]);
 #pragma unroll
@@ -524,7 +534,8 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(StageArgs<R> a) {
 }
 
 // Start of the reverse sweep: lambda += dt R^T (R U - d^n) (primal rows of U read from a.yfwd,
-// n = a.inject; receivers of the lane's cell), then z = D M^{-1}(zs_b lambda) and its outgoing traces.
+// n = inject_step(a); receivers of the lane's cell), then z = D M^{-1}(zs_b lambda) and its outgoing
+// traces.
 template <int K, int NF, typename R, bool POOLED>
 __device__ __forceinline__ void start_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L) {
     constexpr int N = Dim<K>::N;
@@ -547,10 +558,11 @@ __device__ __forceinline__ void start_body(const StageArgs<R> &a, const GroupDev
     const R stiff = bld<R>(B.r, coff, B.mat + kStiff * B.crowb);
     const R lamL = bld<R>(B.r, coff, B.mat + kLam * B.crowb);
     const R tmu = bld<R>(B.r, coff, B.mat + kTwoMu * B.crowb);
-    if (a.inject >= 1 && a.rec_first) {
+    const int inj = inject_step(a);
+    if (inj >= 1 && a.rec_first) {
         for (int e = a.rec_first[ic]; e >= 0;) {
             const RecDev &rc = a.rec[e];
-            const double *d = a.dobs + (((long long)L.shot * a.nobs + a.inject - 1) * a.nrec + rc.r) * 2;
+            const double *d = a.dobs + (((long long)L.shot * a.nobs + inj - 1) * a.nrec + rc.r) * 2;
             const double dt = uni(a.clock)->dt;
             for (int c = 0; c < ncomp; ++c) {
                 double v = 0;

@@ -44,6 +44,14 @@ struct AdjWork {
     Clock *aclock = nullptr;
     Clock h_aclock{};
     void *ckpt = nullptr;  // checkpoints U^{g * every} and U^N, [n + 1][5N][LT]
+    // Captured graphs of one full checkpoint segment for store buffer b: the forward recompute with
+    // stage stores (replayed on aux) and the adjoint stages (replayed on the context's stream).  Valid
+    // while the key (segment length, steps, context version, buffers) is unchanged.
+    hipGraphExec_t rec_graph[2] = {nullptr, nullptr}, adj_graph[2] = {nullptr, nullptr};
+    int g_every = 0, g_steps = 0;
+    double g_dt = 0.0;  // the adjoint stage coefficients dt b_i, dt a_{i+1,i} are launch arguments
+    unsigned g_version = 0;
+    const void *g_key[4] = {nullptr, nullptr, nullptr, nullptr};
     size_t ckpt_states = 0;
     double *gacc = nullptr, *gm = nullptr, *grad = nullptr, *dobs = nullptr;
     size_t dobs_cap = 0;
@@ -97,6 +105,7 @@ struct hho_ctx {
     void *gload = nullptr;
     // receivers
     int nrec = 0;
+    int rec_w = 2;  // values per receiver and step (3 in three dimensions: p, or v_x, v_y, v_z)
     int32_t *rec_first = nullptr;
     RecDev *rec = nullptr;
     double *rec_out = nullptr;
@@ -374,7 +383,7 @@ hho_status check_stage_args(hho_ctx *ctx, const StageArgs<R> &a, int n_blocks, i
     if (n_blocks > ctx->max_blocks || (size_t)a.cpb * a.S > (size_t)kBlock) bad = "launch shape";
     if (a.e_part && a.e_part != ctx->e_part) bad = "energy partials";
     if ((size_t)std::max(ecap, 0) * a.S > ctx->e_hist_cap) bad = "energy history capacity";
-    if (a.rec_first && (size_t)a.rec_steps * a.S * a.nrec * 2 > ctx->rec_cap) bad = "receiver capacity";
+    if (a.rec_first && (size_t)a.rec_steps * a.S * a.nrec * ctx->rec_w > ctx->rec_cap) bad = "receiver capacity";
     if (bad.empty()) return HHO_OK;
     ctx->err = "internal: stage launch argument out of its buffer (" + bad + ")";
     return HHO_ERR_DEVICE;
@@ -408,7 +417,8 @@ hho_status enqueue_steps(hho_ctx *ctx, hipStream_t st, int n_steps, R *store = n
         a.phase[m] = ctx->phase[m];
     }
     a.nrec = ctx->nrec;
-    a.rec_steps = ctx->nrec > 0 ? (int)(ctx->rec_cap / ((size_t)S * ctx->nrec * 2)) : 0;
+    a.rec_w = ctx->rec_w;
+    a.rec_steps = ctx->nrec > 0 ? (int)(ctx->rec_cap / ((size_t)S * ctx->nrec * ctx->rec_w)) : 0;
     a.rec_out = ctx->rec_out;
     a.rec = ctx->rec;
     const int ecap = ctx->record_energy ? (int)(ctx->e_hist_cap / S) : 0;
@@ -491,7 +501,7 @@ hho_status begin_steps(hho_ctx *ctx, double t0, double dt, int n_steps, std::vec
     const int S = ctx->plan.S;
     hho_status s;
     if (ctx->nrec > 0) {
-        const size_t need = (size_t)S * std::max(n_steps, 1) * ctx->nrec * 2;
+        const size_t need = (size_t)S * std::max(n_steps, 1) * ctx->nrec * ctx->rec_w;
         if (need > ctx->rec_cap) {
             if ((s = dalloc(ctx, (void **)&ctx->rec_out, need * sizeof(double)))) return s;
             ctx->rec_cap = need;
@@ -965,12 +975,80 @@ hho_status adjoint_sweep(hho_ctx *ctx, const std::vector<StageCoef> &co, int eve
     a.Yout = (R *)w.Z[0];
     a.Tout = (R *)w.T[0];
     a.inject = n_steps;
-    // the adjoint kernels read dt from a clock of their own
+    // the adjoint kernels read dt, and the offset of the injected step, from a clock of their own
     w.h_aclock = Clock{t0, dt, 0, 0};
     HCK(hipMemcpyAsync(w.aclock, &w.h_aclock, sizeof(Clock), hipMemcpyHostToDevice, ctx->stream));
     a.clock = w.aclock;
     set_stage_offsets(ctx, a);
     HCK((launch_adjoint_start<K, R>(a, ctx->n_blocks(), ctx->stream)));
+    // The adjoint stages of one segment, from the last step back (stage inputs alternate between
+    // Z[0] and Z[1]; s * len stages per segment is even, so every segment starts on Z[0]).  The step
+    // whose misfit enters lambda is the segment's first step plus the relative index in a.inject.
+    auto adjoint_stages = [&](const R *store, int len, hipStream_t st) -> hho_status {
+        int cur = 0;
+        for (int n = len - 1; n >= 0; --n) {
+            for (int i = s - 1; i >= 0; --i) {
+                const R *slot = store + (size_t)(n * s + i) * w.slot_elems;
+                a.yfwd = slot;
+                a.kfwd = slot + w.k_off;
+                a.ffwd = slot + w.f_off;
+                a.Yin = (const R *)w.Z[cur];
+                a.Yout = (R *)w.Z[1 - cur];
+                a.Tin = (const R *)w.T[cur];
+                a.Tout = (R *)w.T[1 - cur];
+                a.first = i == s - 1;
+                a.last = i == 0;
+                a.mu_b = i > 0 ? (R)(dt * co[i - 1].cb) : R(0);
+                a.mu_a = i > 0 ? (R)(dt * co[i - 1].ck) : R(0);
+                a.inject = i == 0 ? n + 1 : 0;
+                set_stage_offsets(ctx, a);
+                HCK((launch_adjoint_stage<K, R>(a, ctx->n_blocks(), st)));
+                cur ^= 1;
+            }
+        }
+        return HHO_OK;
+    };
+    // Graphs of a full segment (every steps) for both store buffers, captured once per key.
+    const void *key[4] = {w.store[0], w.store[1], w.dobs, w.arena};
+    bool fresh = w.rec_graph[0] && w.g_every == every && w.g_steps == n_steps && w.g_dt == dt &&
+                 w.g_version == ctx->version;
+    for (int q = 0; q < 4 && fresh; ++q) fresh = key[q] == w.g_key[q];
+    if (!fresh) {
+        for (int b = 0; b < 2; ++b) {
+            if (w.rec_graph[b]) HCK(hipGraphExecDestroy(w.rec_graph[b]));
+            if (w.adj_graph[b]) HCK(hipGraphExecDestroy(w.adj_graph[b]));
+            w.rec_graph[b] = w.adj_graph[b] = nullptr;
+        }
+        auto capture = [&](hipGraphExec_t *out, auto &&body) -> hho_status {
+            HCK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+            hho_status st = body();
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+            if (st != HHO_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            HCK(e);
+            const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HCK(ei);
+            HCK(hipGraphUpload(*out, ctx->stream));
+            return HHO_OK;
+        };
+        for (int b = 0; b < 2; ++b) {
+            hho_status st = capture(&w.rec_graph[b], [&]() {
+                return enqueue_steps<K, R>(ctx, ctx->cap_stream, every, (R *)w.store[b]);
+            });
+            if (st == HHO_OK)
+                st = capture(&w.adj_graph[b], [&]() { return adjoint_stages((const R *)w.store[b], every, ctx->cap_stream); });
+            if (st != HHO_OK) return st;
+        }
+        w.g_every = every;
+        w.g_steps = n_steps;
+        w.g_dt = dt;
+        w.g_version = ctx->version;
+        for (int q = 0; q < 4; ++q) w.g_key[q] = key[q];
+    }
     // Segments from the last: the forward recompute of segment g - 1 (stream aux: the forward
     // state, traces and clock of the context, store buffer (g - 1) % 2) runs while the adjoint
     // stages of segment g (the caller's stream: the adjoint arena, store buffer g % 2) run.
@@ -987,41 +1065,29 @@ hho_status adjoint_sweep(hho_ctx *ctx, const std::vector<StageCoef> &co, int eve
         if (st != HHO_OK) return st;
         clocks[g] = Clock{t0, dt, n0, 0};
         HCK(hipMemcpyAsync(ctx->clock, &clocks[g], sizeof(Clock), hipMemcpyHostToDevice, w.aux));
-        if ((st = enqueue_steps<K, R>(ctx, w.aux, len, (R *)w.store[b]))) return st;
+        if (len == every) HCK(hipGraphLaunch(w.rec_graph[b], w.aux));
+        else if ((st = enqueue_steps<K, R>(ctx, w.aux, len, (R *)w.store[b]))) return st;
         HCK(hipEventRecord(w.ev_rec[b], w.aux));
         return HHO_OK;
     };
     hho_status st = recompute(n_seg - 1);
     if (st != HHO_OK) return st;
-    int cur = 0;
+    std::vector<int> offset(n_seg);
     for (int g = n_seg - 1; g >= 0; --g) {
         const int b = g % 2, n0 = g * every, len = std::min(every, n_steps - n0);
         HCK(hipStreamWaitEvent(ctx->stream, w.ev_rec[b], 0));
         if (g > 0 && (st = recompute(g - 1)) != HHO_OK) return st;
-        const R *store = (const R *)w.store[b];
-        for (int n = len - 1; n >= 0; --n) {
-            for (int i = s - 1; i >= 0; --i) {
-                const R *slot = store + (size_t)(n * s + i) * w.slot_elems;
-                a.yfwd = slot;
-                a.kfwd = slot + w.k_off;
-                a.ffwd = slot + w.f_off;
-                a.Yin = (const R *)w.Z[cur];
-                a.Yout = (R *)w.Z[1 - cur];
-                a.Tin = (const R *)w.T[cur];
-                a.Tout = (R *)w.T[1 - cur];
-                a.first = i == s - 1;
-                a.last = i == 0;
-                a.mu_b = i > 0 ? (R)(dt * co[i - 1].cb) : R(0);
-                a.mu_a = i > 0 ? (R)(dt * co[i - 1].ck) : R(0);
-                a.inject = i == 0 ? n0 + n : 0;
-                set_stage_offsets(ctx, a);
-                HCK((launch_adjoint_stage<K, R>(a, ctx->n_blocks(), ctx->stream)));
-                cur ^= 1;
-            }
-        }
+        // the adjoint clock's step: the offset of the segment's injected steps (n0 + n = n + 1 + offset)
+        offset[g] = n0 - 1;
+        HCK(hipMemcpyAsync(&w.aclock->step, &offset[g], sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+        if (len == every) HCK(hipGraphLaunch(w.adj_graph[b], ctx->stream));
+        else if ((st = adjoint_stages((const R *)w.store[b], len, ctx->stream))) return st;
         HCK(hipEventRecord(w.ev_adj[b], ctx->stream));
         adj_pending[b] = true;
     }
+    // the host-side values the copies above read stay alive until the stream has consumed them
+    HCK(hipStreamSynchronize(ctx->stream));
+    HCK(hipStreamSynchronize(w.aux));
     return HHO_OK;
 }
 
@@ -1099,6 +1165,7 @@ hho_status setup_device(hho_ctx *ctx, const hho_params *prm, hho_ctx **out) {
     hho_status s = set_device(ctx);
     if (s != HHO_OK) return fail(s);
     Plan &P = ctx->plan;
+    ctx->rec_w = P.dim == 3 ? 3 : 2;
     ctx->LT = (long long)P.n_ic * P.S;
     ctx->rows = P.rows_s * P.N;
     ctx->trows = trace_rows(P);
@@ -1268,6 +1335,10 @@ void hho_destroy(hho_ctx *ctx) {
     if (ctx->h_e0) (void)hipHostFree(ctx->h_e0);
     if (ctx->h_ehist) (void)hipHostFree(ctx->h_ehist);
     AdjWork &w = ctx->adj;
+    for (int b = 0; b < 2; ++b) {
+        if (w.rec_graph[b]) (void)hipGraphExecDestroy(w.rec_graph[b]);
+        if (w.adj_graph[b]) (void)hipGraphExecDestroy(w.adj_graph[b]);
+    }
     if (w.aux) {
         (void)hipStreamSynchronize(w.aux);
         (void)hipStreamDestroy(w.aux);
@@ -1376,7 +1447,6 @@ hho_status hho_set_sources(hho_ctx *ctx, int32_t shot, int32_t n, const double *
                            const double *f0, const double *t0, const double *amp) {
     return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
         if (!ctx) return HHO_ERR_ARG;
-        if (ctx->plan.dim != 2) return two_dim_only(ctx, "set_sources");
         if (shot < 0 || shot >= ctx->plan.S || n < 0 || (n > 0 && (!xy || !dir || !f0 || !t0 || !amp))) {
             ctx->err = "set_sources: bad arguments";
             return HHO_ERR_ARG;
@@ -1386,8 +1456,10 @@ hho_status hho_set_sources(hho_ctx *ctx, int32_t shot, int32_t n, const double *
         std::vector<SrcDev> keep;
         for (const SrcDev &e : ctx->h_src)
             if (e.shot != shot) keep.push_back(e);
+        const int d = ctx->plan.dim;
         for (int i = 0; i < n; ++i) {
-            const int c = locate_cell(ctx->plan, xy[2 * i], xy[2 * i + 1]);
+            const double *x = xy + (size_t)d * i;
+            const int c = d == 2 ? locate_cell(ctx->plan, x[0], x[1]) : locate_cell3(ctx->plan, x[0], x[1], x[2]);
             if (c < 0) {
                 ctx->err = "set_sources: source " + std::to_string(i) + " lies outside the mesh";
                 return HHO_ERR_ARG;
@@ -1396,12 +1468,14 @@ hho_status hho_set_sources(hho_ctx *ctx, int32_t shot, int32_t n, const double *
             std::memset(&e, 0, sizeof(e));
             e.ic = ctx->plan.ic_of_cell[c];
             e.shot = shot;
-            e.dirx = dir[2 * i];
-            e.diry = dir[2 * i + 1];
+            e.dirx = dir[(size_t)d * i];
+            e.diry = dir[(size_t)d * i + 1];
+            e.dirz = d == 3 ? dir[(size_t)d * i + 2] : 0.0;
             e.f0 = f0[i];
             e.t0 = t0[i];
             e.amp = amp[i];
-            eval_basis(ctx->plan, c, xy[2 * i], xy[2 * i + 1], e.phi);
+            if (d == 2) eval_basis(ctx->plan, c, x[0], x[1], e.phi);
+            else eval_basis3(ctx->plan, c, x[0], x[1], x[2], e.phi);
             keep.push_back(e);
         }
         ctx->h_src = keep;
@@ -1451,7 +1525,6 @@ hho_status hho_set_loads(hho_ctx *ctx, int32_t n_terms, const double *g, const d
 hho_status hho_receivers(hho_ctx *ctx, int32_t n, const double *xy, const int32_t *field) {
     return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
         if (!ctx) return HHO_ERR_ARG;
-        if (ctx->plan.dim != 2) return two_dim_only(ctx, "receivers");
         if (n < 0 || (n > 0 && (!xy || !field))) {
             ctx->err = "receivers: bad arguments";
             return HHO_ERR_ARG;
@@ -1460,8 +1533,10 @@ hho_status hho_receivers(hho_ctx *ctx, int32_t n, const double *xy, const int32_
         if (s != HHO_OK) return s;
         const Plan &P = ctx->plan;
         std::vector<RecDev> v;
+        const int d = P.dim;
         for (int i = 0; i < n; ++i) {
-            const int c = locate_cell(P, xy[2 * i], xy[2 * i + 1]);
+            const double *x = xy + (size_t)d * i;
+            const int c = d == 2 ? locate_cell(P, x[0], x[1]) : locate_cell3(P, x[0], x[1], x[2]);
             if (c < 0) {
                 ctx->err = "receivers: receiver " + std::to_string(i) + " lies outside the mesh";
                 return HHO_ERR_ARG;
@@ -1476,7 +1551,8 @@ hho_status hho_receivers(hho_ctx *ctx, int32_t n, const double *xy, const int32_
             r.ic = P.ic_of_cell[c];
             r.field = field[i];
             r.r = i;
-            eval_basis(P, c, xy[2 * i], xy[2 * i + 1], r.phi);
+            if (d == 2) eval_basis(P, c, x[0], x[1], r.phi);
+            else eval_basis3(P, c, x[0], x[1], x[2], r.phi);
             v.push_back(r);
         }
         std::stable_sort(v.begin(), v.end(), [](const RecDev &x, const RecDev &y) { return x.ic < y.ic; });
@@ -1665,14 +1741,20 @@ hho_status hho_adjoint_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps,
         // forward pass with checkpoints U^{g * every}, then U^N
         std::vector<double> E0;
         if ((s = begin_steps(ctx, t0, dt, n_steps, E0))) return s;
+        if ((s = ensure_graphs(ctx))) return s;
+        // segments replayed from the step graphs, which start on clock slot 0: after a segment of odd
+        // length the current clock sits in slot 1 and is copied back to slot 0
+        int slot = 0;
         for (int g = 0; g < n_seg; ++g) {
             HCK(hipMemcpyAsync((char *)w.ckpt + (size_t)g * sbytes, ctx->U, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
             const int len = std::min(every, n_steps - g * every);
-            s = dispatch(ctx, [&](auto kc, auto *r) {
-                using R = std::remove_pointer_t<decltype(r)>;
-                return enqueue_steps<decltype(kc)::value, R>(ctx, ctx->stream, len, (R *)nullptr, (g * every) & 1);
+            if (slot == 1) HCK(hipMemcpyAsync(ctx->clock, ctx->clock + 1, sizeof(Clock), hipMemcpyDeviceToDevice, ctx->stream));
+            s = replay_steps(len, [&](int i) -> hho_status {
+                HCK(hipGraphLaunch(ctx->gexec[i], ctx->stream));
+                return HHO_OK;
             });
             if (s != HHO_OK) return s;
+            slot = len & 1;
         }
         if ((s = end_steps(ctx, n_steps, E0))) return s;
         void *uN = (char *)w.ckpt + (size_t)n_seg * sbytes;
@@ -1936,7 +2018,7 @@ hho_status hho_get_traces(hho_ctx *ctx, int32_t shot, double *out) {
         hho_status s = set_device(ctx);
         if (s != HHO_OK) return s;
         // shots are strided by the recording capacity, which may exceed the last call's steps
-        const size_t n = (size_t)ctx->last_steps * ctx->nrec * 2;
+        const size_t n = (size_t)ctx->last_steps * ctx->nrec * ctx->rec_w;
         const size_t stride = ctx->rec_cap / (size_t)ctx->plan.S;
         HCK(hipMemcpyAsync(out, ctx->rec_out + (size_t)shot * stride, n * sizeof(double), hipMemcpyDeviceToHost,
                            ctx->stream));

@@ -18,6 +18,7 @@ constexpr int kMaxN = 10;  // (k+1)(k+2)/2 for k = 3
 struct SrcDev {
     int ic, shot, next, pad;
     double dirx, diry, f0, t0, amp;
+    double dirz;  // three-dimensional contexts
     double phi[kMaxN];
 };
 
@@ -84,8 +85,9 @@ struct StageArgs {
     const double *emat;        // [4][n_ic]
     const int32_t *rec_first;  // [n_ic], -1 = none (null = off)
     const RecDev *rec;
-    double *rec_out;           // [S][rec_steps][nrec][2]; steps beyond rec_steps are not recorded
+    double *rec_out;           // [S][rec_steps][nrec][rec_w]; steps beyond rec_steps are not recorded
     int nrec, rec_steps;
+    int rec_w;                 // values per receiver and step: 2 (two dimensions; p or v_x, v_y), 3
     // Every per-lane and per-cell array above except gload lives in one device arena that the
     // kernels address through a single buffer resource: byte offsets of each array in it.
     const void *arena;
@@ -100,7 +102,8 @@ struct StageArgs {
     double *gacc;              // gradient accumulator [3][LT], float64
     const double *gm;          // per-cell parameter derivative coefficients [8][n_ic], float64
     R mu_b, mu_a, zs_b;        // dt b_{i-1}, dt a_{i,i-1}, dt b_s
-    int inject;                // step n whose misfit derivative enters lambda^n (-1 = none)
+    int inject;                // the step n whose misfit derivative enters lambda^n is inject + clock->step
+                               // (the adjoint clock's step holds a per-segment offset); 0 = none
     const double *dobs;        // observed data [S][nobs][nrec][2]
     int nobs;
 };
@@ -140,7 +143,7 @@ hipError_t launch_stage_store(const StageArgs<R> &a, int n_blocks, hipStream_t s
 template <int K, typename R>
 hipError_t launch_adjoint_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st);
 
-// lambda += dt R^T (R U - d^n) at the receivers (U = a.yfwd, lambda = a.U, step a.inject), then
+// lambda += dt R^T (R U - d^n) at the receivers (U = a.yfwd, lambda = a.U, n = a.inject + clock step), then
 // z = D M^{-1} (a.zs_b lambda) and its outgoing traces (z = a.Yout, traces = a.Tout).
 template <int K, typename R>
 hipError_t launch_adjoint_start(const StageArgs<R> &a, int n_blocks, hipStream_t st);

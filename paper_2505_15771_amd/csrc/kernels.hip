@@ -53,6 +53,14 @@ constexpr int stage_waves() {
     constexpr int w32[3] = {HHO_STAGE_WAVES_F32}, w64[3] = {HHO_STAGE_WAVES_F64};
     return sizeof(R) == 4 ? w32[K - 1] : w64[K - 1];
 }
+// State loads (U^n, D_{i-1}, Q) of the launches with streaming stores: streaming as well when set.
+#ifndef HHO_NT_STATE_LOADS
+#define HHO_NT_STATE_LOADS 0
+#endif
+template <int POL>
+constexpr int state_load_policy() {
+    return (HHO_NT_STATE_LOADS && POL == kNonTemporal) ? kNonTemporal : 0;
+}
 template <int K, typename R>
 constexpr bool keep_in_registers() {
     return sizeof(R) == 4 ? K <= HHO_KEEP_MAX_K_F32 : K <= 1;
@@ -64,12 +72,13 @@ constexpr bool keep_in_registers() {
 // relative precision in float32 (a stored Y_i would round away the low bits of dt k_i).
 // With KEEP, U^n and D_{i-1} stay in registers (uk, dk) for the combine; otherwise the combine
 // reads them again (cache hits), which keeps the register count of the larger degrees down.
-template <int ND, typename R, bool KEEP>
+template <int ND, typename R, bool KEEP, int POL>
 __device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, R *y, R *uk,
                                            R *dk) {
+    constexpr int LP = state_load_policy<POL>();
     if (a.first) {
 #pragma unroll
-        for (int r = 0; r < ND; ++r) y[r] = bld<R>(B.r, boff, B.yin + r * B.rowb);
+        for (int r = 0; r < ND; ++r) y[r] = bldp<R, LP>(B.r, boff, B.yin + r * B.rowb);
         if (KEEP) {
 #pragma unroll
             for (int r = 0; r < ND; ++r) {
@@ -81,8 +90,8 @@ __device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> 
         R d[ND], u[ND];
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
-            d[r] = bld<R>(B.r, boff, B.yin + r * B.rowb);
-            u[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
+            d[r] = bldp<R, LP>(B.r, boff, B.yin + r * B.rowb);
+            u[r] = bldp<R, LP>(B.r, boff, B.u + r * B.rowb);
         }
 #pragma unroll
         for (int r = 0; r < ND; ++r) y[r] = u[r] + d[r];
@@ -110,6 +119,7 @@ __device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> 
 template <int ND, typename R, bool KEEP, int POL>
 __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, const R *y,
                                           const R *kv, R *out, const R *uk, const R *dk, int shot) {
+    constexpr int LP = state_load_policy<POL>();
     const R dt = R(shot_dt(a, shot));
     R u[ND], din[ND];
     const bool need_d = a.last ? a.cd != R(0) : (a.cY != R(0) || a.q_write);
@@ -128,13 +138,13 @@ __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &
     } else if (need_d) {
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
-            u[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
-            din[r] = bld<R>(B.r, boff, B.yin + r * B.rowb);
+            u[r] = bldp<R, LP>(B.r, boff, B.u + r * B.rowb);
+            din[r] = bldp<R, LP>(B.r, boff, B.yin + r * B.rowb);
         }
     } else {
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
-            u[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
+            u[r] = bldp<R, LP>(B.r, boff, B.u + r * B.rowb);
             din[r] = R(0);
         }
     }
@@ -151,7 +161,7 @@ __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &
         R q[ND];
         if (a.q_read) {
 #pragma unroll
-            for (int r = 0; r < ND; ++r) q[r] = bld<R>(B.r, boff, B.yq + r * B.rowb);
+            for (int r = 0; r < ND; ++r) q[r] = bldp<R, LP>(B.r, boff, B.yq + r * B.rowb);
         } else {
 #pragma unroll
             for (int r = 0; r < ND; ++r) q[r] = R(0);
@@ -205,7 +215,7 @@ __device__ __forceinline__ double fluid_stage(const StageArgs<R> &a, const Bufs<
     load_links<NF, R>(B, nF, ic, lk, cc);
     constexpr bool KEEP = keep_in_registers<K, R>();
     R y[3 * N], uk[KEEP ? 3 * N : 1], dk[KEEP ? 3 * N : 1];
-    load_state<3 * N, R, KEEP>(a, B, boff, y, uk, dk);
+    load_state<3 * N, R, KEEP, POL>(a, B, boff, y, uk, dk);
     const R *p = y, *mx = y + N, *my = y + 2 * N;
     load_incoming<K, NF, R>(B, kFluid, a.S, shot, lk, rn);
     const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
@@ -352,7 +362,7 @@ __device__ __forceinline__ double solid_stage(const StageArgs<R> &a, const Bufs<
     load_links<NF, R>(B, nF, ic, lk, cc);
     constexpr bool KEEP = keep_in_registers<K, R>();
     R y[5 * N], uk[KEEP ? 5 * N : 1], dk[KEEP ? 5 * N : 1];
-    load_state<5 * N, R, KEEP>(a, B, boff, y, uk, dk);
+    load_state<5 * N, R, KEEP, POL>(a, B, boff, y, uk, dk);
     const R *vx = y, *vy = y + N, *s1 = y + 2 * N, *s2 = y + 3 * N, *s3 = y + 4 * N;
     load_incoming<K, NF, R>(B, kSolid, a.S, shot, lk, rn);
     const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);

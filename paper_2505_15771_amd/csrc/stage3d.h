@@ -264,6 +264,18 @@ __device__ __forceinline__ double fluid_stage3(const StageArgs<R> &a, const Bufs
             rp[b] += tau * w;
         }
     }
+    // point sources (pressure): R(t) amp d_x phi(x_s)
+    if (a.src_first) {
+        for (int e = a.src_first[ic]; e >= 0;) {
+            const SrcDev &sr = a.src[e];
+            if (sr.shot == shot) {
+                const R w = R(sr.amp * ricker(stage_time(a, shot), sr.f0, sr.t0) * sr.dirx);
+#pragma unroll
+                for (int b = 0; b < N; ++b) rp[b] += w * R(sr.phi[b]);
+            }
+            e = sr.next;
+        }
+    }
     R kv[4 * N], nw[4 * N];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
@@ -284,6 +296,22 @@ __device__ __forceinline__ double fluid_stage3(const StageArgs<R> &a, const Bufs
             for (int d = 1; d <= 3; ++d) sm += (double)nw[d * N + b] * (double)nw[d * N + b];
         }
         energy = 0.5 * (a.emat[(long long)nic + ic] * sp + a.emat[ic] * sm);
+    }
+    if (a.last && a.rec_first) {
+        const int step = uni(a.clock)->step;
+        for (int e = a.rec_first[ic]; e >= 0;) {
+            const RecDev &rc = a.rec[e];
+            double v = 0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) v += rc.phi[b] * (double)nw[b];
+            if (step < a.rec_steps) {
+                double *o = a.rec_out + (((long long)shot * a.rec_steps + step) * a.nrec + rc.r) * a.rec_w;
+                o[0] = v;
+                o[1] = 0.0;
+                o[2] = 0.0;
+            }
+            e = rc.next;
+        }
     }
     return energy;
 }
@@ -424,6 +452,23 @@ __device__ __forceinline__ double solid_stage3(const StageArgs<R> &a, const Bufs
             rv[2][b] += tau * wz;
         }
     }
+    // point forces: R(t) amp d phi(x_s) on the velocity rows
+    if (a.src_first) {
+        for (int e = a.src_first[ic]; e >= 0;) {
+            const SrcDev &sr = a.src[e];
+            if (sr.shot == shot) {
+                const double w = sr.amp * ricker(stage_time(a, shot), sr.f0, sr.t0);
+                const R wx = R(w * sr.dirx), wy = R(w * sr.diry), wz = R(w * sr.dirz);
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    rv[0][b] += wx * R(sr.phi[b]);
+                    rv[1][b] += wy * R(sr.phi[b]);
+                    rv[2][b] += wz * R(sr.phi[b]);
+                }
+            }
+            e = sr.next;
+        }
+    }
     R kv[9 * N], nw[9 * N];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
@@ -456,6 +501,26 @@ __device__ __forceinline__ double solid_stage3(const StageArgs<R> &a, const Bufs
                   c3 * (x4 * x4 + x5 * x5 + x6 * x6);
         }
         energy = 0.5 * (a.emat[ic] * sv + ss);
+    }
+    if (a.last && a.rec_first) {
+        const int step = uni(a.clock)->step;
+        for (int e = a.rec_first[ic]; e >= 0;) {
+            const RecDev &rc = a.rec[e];
+            double v0 = 0, v1 = 0, v2 = 0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                v0 += rc.phi[b] * (double)nw[b];
+                v1 += rc.phi[b] * (double)nw[N + b];
+                v2 += rc.phi[b] * (double)nw[2 * N + b];
+            }
+            if (step < a.rec_steps) {
+                double *o = a.rec_out + (((long long)shot * a.rec_steps + step) * a.nrec + rc.r) * a.rec_w;
+                o[0] = v0;
+                o[1] = v1;
+                o[2] = v2;
+            }
+            e = rc.next;
+        }
     }
     return energy;
 }

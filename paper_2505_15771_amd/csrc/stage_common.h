@@ -52,6 +52,14 @@ template <>
 __device__ __forceinline__ double bld<double>(Rsrc r, unsigned voff, unsigned soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
+// Load with a cache policy LPOL (0 = default, 2 = streaming).
+template <typename R, int LPOL>
+__device__ __forceinline__ R bldp(Rsrc r, unsigned voff, unsigned soff) {
+    if constexpr (sizeof(R) == 4)
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, LPOL));
+    else
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, LPOL));
+}
 // Stores take a cache policy POL: 0 = default, kNonTemporal = streaming (used when the working
 // set of a context is larger than the last-level cache, so that stage outputs go through to
 // memory while the launch runs instead of in one write-back at its end).

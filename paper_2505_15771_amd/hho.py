@@ -287,9 +287,10 @@ class Engine:
         return U
 
     def set_sources(self, shot, xy, direction, f0, t0, amp):
+        """Ricker point forces of one shot: positions and directions with `dim` components each."""
         xy = np.ascontiguousarray(np.asarray(xy, np.float64).reshape(-1))
-        n = len(xy) // 2
-        d = np.ascontiguousarray(np.broadcast_to(np.asarray(direction, np.float64), (n, 2)).reshape(-1))
+        n = len(xy) // self.dim
+        d = np.ascontiguousarray(np.broadcast_to(np.asarray(direction, np.float64), (n, self.dim)).reshape(-1))
         arr = lambda v: np.ascontiguousarray(np.broadcast_to(np.asarray(v, np.float64), (n,)))
         f0, t0, amp = arr(f0), arr(t0), arr(amp)
         self._call(self.lib.hho_set_sources, int(shot), n, _ptr(xy), _ptr(d), _ptr(f0), _ptr(t0), _ptr(amp))
@@ -340,7 +341,8 @@ class Engine:
         self._call(self.lib.hho_synchronize)
 
     def traces(self, shot=0):
-        out = np.zeros((self.last_steps, self.n_rec, 2))
+        """[steps, receivers, 2] (two dimensions: p, 0 or v_x, v_y) or [steps, receivers, 3]."""
+        out = np.zeros((self.last_steps, self.n_rec, self.dim))
         if self.n_rec and self.last_steps:
             self._call(self.lib.hho_get_traces, int(shot), _ptr(out))
         return out

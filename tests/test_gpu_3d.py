@@ -182,14 +182,55 @@ def test_3d_full_size_properties():
 
 
 def test_3d_rejects_two_dimensional_calls():
+    """Separable loads, the adjoint, the tabulated CFL step and the Ricker initial field are
+    two-dimensional only: ARG on a three-dimensional context."""
     from paper_2505_15771_amd import Engine
     from paper_2505_15771_amd.hho import HHOError
     mesh, _ = MESHES["tets"]()
     e = Engine(mesh, 1)
-    for call in (lambda: e.set_sources(0, [[0.5, 0.5]], [[0.0, 1.0]], 10.0, 0.1, 1.0),
-                 lambda: e.set_receivers([[0.5, 0.5]], [0]),
+    for call in (lambda: e.set_loads(np.zeros((1, e.n_dof)), [1.0], [0.0]),
+                 lambda: e.adjoint(0.0, 1e-3, 2),
                  lambda: e.dt_cfl(0.5),
                  lambda: e.set_ricker_ic((0.5, 0.5), 0.1)):
         with pytest.raises(HHOError) as ex:
             call()
         assert ex.value.code == 1
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_3d_ricker_sources_and_receivers(dtype):
+    """Two shots on 4^3 cubes of tetrahedra, k = 2: shot 0 a Ricker point force in the solid,
+    shot 1 a Ricker pressure source in the fluid; two receivers per medium recording p or
+    (v_x, v_y, v_z) after every step; 60 steps from rest against the oracle driven by the same
+    point loads."""
+    from oracle.oracle3d import ricker
+    from paper_2505_15771_amd import Engine
+    mesh, n = MESHES["tets"]()
+    k = 2
+    say("case: 3d tets k=2 %s, Ricker sources in both media, 4 receivers, 60 steps" % dtype)
+    o = oracle3d(mesh, k, key="tets")
+    dt = dt_for(mesh, n, k)
+    f0, t0, amp = 10.0, 0.12, 1.0
+    src = [(np.array([0.41, 0.36, 0.29]), np.array([0.3, -0.2, 1.0])),
+           (np.array([0.62, 0.53, 0.77]), np.array([1.0, 0.0, 0.0]))]
+    rec = np.array([[0.31, 0.71, 0.74], [0.79, 0.22, 0.61], [0.28, 0.33, 0.21], [0.68, 0.57, 0.41]])
+    fld = [0, 0, 1, 1]
+    e = Engine(mesh, k, dtype=dtype, n_shots=2)
+    for sh, (x, d) in enumerate(src):
+        e.set_sources(sh, [x], [d], f0, t0, amp)
+    e.set_receivers(rec, fld)
+    e.erk_step(0.0, dt, 60)
+    tol = TOL64 if dtype == "f64" else TOL32
+    for sh, (x, d) in enumerate(src):
+        F = o.point_load(x, d)
+        traces = np.zeros((60, 4, 3))
+
+        def record(step, U):
+            for r in range(4):
+                v = o.point_values(U, rec[r])
+                traces[step, r, :len(v)] = v
+        ref = o.erk(np.zeros(o.ndof), dt, 60, load=lambda t: amp * ricker(t, f0, t0) * F, record=record)
+        err = rel(e.get_state(shot=sh), ref)
+        terr = rel(e.traces(shot=sh), traces)
+        say(dtype, "shot", sh, "state rel L2 =", err, "traces rel L2 =", terr)
+        assert err < tol and terr < tol

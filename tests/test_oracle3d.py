@@ -254,3 +254,80 @@ def test_acoustic_standing_wave_converges(k):
         errs.append(math.sqrt(float(d @ (o.M @ d))))
     rate = math.log(errs[0] / errs[1], 2)
     assert rate > k + 0.5, (errs, rate)
+
+
+# ------------------------------------------------------------------ point sources and receivers
+def _poly_fields(k, rng):
+    """Random polynomial fields of degree k: 4 fluid (p, m) and 9 solid (v, s) callables."""
+    def one():
+        cf = rng.standard_normal((k + 1, k + 1, k + 1))
+        def f(x, y, z):
+            out = np.zeros_like(x)
+            for a in range(k + 1):
+                for b in range(k + 1 - a):
+                    for c in range(k + 1 - a - b):
+                        out = out + cf[a, b, c] * x ** a * y ** b * z ** c
+            return out
+        return f
+    return [one() for _ in range(4)], [one() for _ in range(9)]
+
+
+@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("tets", [True, False])
+def test_point_load_and_point_values_reproduce_polynomials(tets, k):
+    """Point evaluation is exact on polynomial fields: for U the projection of fields of degree k,
+    F . U = d . u(x) for the point-force load F, and the receiver values are u(x), in either medium."""
+    o = Oracle3D(cube_mesh(2, tets=tets), k)
+    rng = np.random.default_rng(41)
+    ff, sf = _poly_fields(k, rng)
+    U = o.project(ff, sf)
+    for x, expect_medium in (([0.31, 0.42, 0.23], SOLID), ([0.62, 0.27, 0.81], FLUID)):
+        x = np.array(x)
+        assert o.medium[o.locate(x)] == expect_medium
+        d = rng.standard_normal(3)
+        F = o.point_load(x, d)
+        fields = ff if expect_medium == FLUID else sf
+        u = np.array([f(*x[:, None])[0] for f in fields[:(1 if expect_medium == FLUID else 3)]])
+        ref = d[0] * u[0] if expect_medium == FLUID else float(d @ u)
+        assert abs(F @ U - ref) < 1e-11 * max(1.0, abs(ref))
+        assert np.allclose(o.point_values(U, x), u, rtol=1e-11, atol=1e-11)
+
+
+def test_forced_erk_is_fourth_order():
+    """ERK(4) with a time-dependent load (a point force times sin(omega t)) against the exact solution
+    of U' = L U + M^{-1} F(t), from the matrix exponential of the system augmented with the
+    oscillator (a, b)' = (omega b, -omega a): the error falls by about 2^4 when dt halves."""
+    from scipy.linalg import expm
+    o = Oracle3D(cube_mesh(1, tets=True), 1)
+    L = o.dense_operator()
+    f = o.point_load(np.array([0.3, 0.6, 0.2]), np.array([0.2, -0.4, 1.0]))
+    g = o._M_lu.solve(f)
+    om = 9.0
+    n = o.ndof
+    Aug = np.zeros((n + 2, n + 2))
+    Aug[:n, :n] = L
+    Aug[:n, n] = g            # the load enters as sin(omega t) = a
+    Aug[n, n + 1] = om        # a' = omega b
+    Aug[n + 1, n] = -om       # b' = -omega a
+    U0 = np.random.default_rng(42).standard_normal(n)
+    T = 0.2
+    exact = (expm(T * Aug) @ np.concatenate([U0, [0.0, 1.0]]))[:n]
+    errs = []
+    for steps in (20, 40):
+        dt = T / steps
+        U = o.erk(U0, dt, steps, load=lambda t: math.sin(om * t) * f)
+        errs.append(np.linalg.norm(U - exact) / np.linalg.norm(exact))
+    assert errs[0] / errs[1] > 12.0, errs
+
+
+def test_ricker_time_factor_3d():
+    """The Ricker factor of the 3D oracle: maximum 1 at t0, zeros at t0 +- 1/(sqrt 2 pi f0), zero
+    time integral (trapezoidal rule on a fine grid)."""
+    from oracle.oracle3d import ricker
+    f0, t0 = 10.0, 0.12
+    assert ricker(t0, f0, t0) == 1.0
+    tz = 1.0 / (math.sqrt(2.0) * math.pi * f0)
+    assert abs(ricker(t0 + tz, f0, t0)) < 1e-15 and abs(ricker(t0 - tz, f0, t0)) < 1e-15
+    t = np.linspace(t0 - 1.0, t0 + 1.0, 200001)
+    r = np.array([ricker(x, f0, t0) for x in t])
+    assert abs(np.trapezoid(r, t)) < 1e-9 and r.max() <= 1.0
