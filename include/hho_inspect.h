@@ -53,9 +53,11 @@ hho_status hho_inspect_arrays(const hho_inspect *p, double *tables, int32_t *gro
 /* Class table of every internal cell: ic_tab[n_ic] = offset of its class's table in `tables`
  * (0 for padding), and pooled[n_groups] = 1 for the groups that hold the cells of small shape
  * classes (fewer than 32 cells of that shape, on meshes with more than 64 shape classes): their
- * lanes read the table at their own offset,
- * laid out with the group's face count (faces beyond a cell's own count hold zeros).  Either
- * output may be NULL. */
+ * lanes read the table at their own offset, laid out with the group's face count (faces beyond a
+ * cell's own count hold zeros) and packed without structural zeros: the entries of B_x, then of
+ * B_y, with deg(b) < deg(r) (row-major; deg the total degree of the graded basis function), the
+ * upper triangle r <= b of S (row-major), per face the entries G_j[a][i] with i <= deg(a)
+ * (row-major), then the normals.  Either output may be NULL. */
 hho_status hho_inspect_cell_tables(const hho_inspect *p, int32_t *ic_tab, int32_t *pooled);
 
 /* Material derivatives used by the adjoint gradient (hho_adjoint_step), gm[8][n_ic], float64:

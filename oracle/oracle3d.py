@@ -2,12 +2,12 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  The paper states its method for d = 2 and
 3 (Sec. 2-3; Table tab::DOFS counts the 3D unknowns) and names 3D as the next step (Sec. 6).
-This module writes the same method out for tetrahedra and parallelepiped hexahedra, as plainly as
-possible: every local form of eq. HHO1 / HHO2 with the reconstructions eq. rec_a / rec_e and the
-least-squares stabilisation eq. stab is integrated by quadrature and assembled into one global
-sparse matrix on the cell and face unknowns; the face unknowns are eliminated as in eq. ex_solve
-(their block is block-diagonal, one block per face), and the explicit Runge-Kutta tableaux of
-eq. ERK advance the cell unknowns.
+This module writes the same method out for tetrahedra, triangular prisms with parallelogram sides
+and parallelepiped hexahedra, as plainly as possible: every local form of eq. HHO1 / HHO2 with the
+reconstructions eq. rec_a / rec_e and the least-squares stabilisation eq. stab is integrated by
+quadrature and assembled into one global sparse matrix on the cell and face unknowns; the face
+unknowns are eliminated as in eq. ex_solve (their block is block-diagonal, one block per face),
+and the explicit Runge-Kutta tableaux of eq. ERK advance the cell unknowns.
 
 Readings (the same as the 2D oracle's):
   * the weak-form signs of eq. HHO1 / HHO2;
@@ -43,6 +43,11 @@ TET_FACES = ((1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2))
 # hexahedron: vertices 0-3 counter-clockwise at the bottom, 4-7 above them
 HEX_FACES = ((0, 1, 2, 3), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7))
 HEX_TETS = ((0, 1, 2, 6), (0, 2, 3, 6), (0, 3, 7, 6), (0, 7, 4, 6), (0, 4, 5, 6), (0, 5, 1, 6))
+# triangular prism: vertices 0-2 around the bottom triangle, 3-5 above them (parallelogram sides)
+PRISM_FACES = ((0, 1, 2), (3, 4, 5), (0, 1, 4, 3), (1, 2, 5, 4), (2, 0, 3, 5))
+PRISM_TETS = ((0, 1, 2, 3), (1, 2, 3, 4), (2, 3, 4, 5))
+LOCAL_FACES = {4: TET_FACES, 6: PRISM_FACES, 8: HEX_FACES}
+CELL_TETS = {6: PRISM_TETS, 8: HEX_TETS}
 
 
 def gauss01(n):
@@ -105,7 +110,8 @@ def _orthonormal(V, W):
 
 class Oracle3D:
     """mesh: dict with xyz [n_vertices, 3], cells (list of vertex-id tuples: 4 = tetrahedron,
-    8 = parallelepiped hexahedron), medium [n_cells], rho, a (fluid c, solid lambda), b (solid mu)."""
+    6 = triangular prism, 8 = parallelepiped hexahedron), medium [n_cells], rho, a (fluid c, solid
+    lambda), b (solid mu)."""
 
     def __init__(self, mesh, k, eta_f=0.8, eta_s=1.5):
         self.k = k
@@ -132,7 +138,7 @@ class Oracle3D:
         keys = {}
         self.cell_faces = []
         for c, vs in enumerate(self.cells):
-            loc = TET_FACES if len(vs) == 4 else HEX_FACES
+            loc = LOCAL_FACES[len(vs)]
             fl = []
             for lf in loc:
                 fv = tuple(vs[i] for i in lf)
@@ -153,7 +159,7 @@ class Oracle3D:
     def _cell_tets(self, c):
         vs = self.cells[c]
         P = self.xyz[list(vs)]
-        return [P] if len(vs) == 4 else [P[list(t)] for t in HEX_TETS]
+        return [P] if len(vs) == 4 else [P[list(t)] for t in CELL_TETS[len(vs)]]
 
     def cell_quad(self, c, n=None):
         n = n or self.nq_cell

@@ -74,18 +74,13 @@ template <int K, typename R>
 constexpr bool kEarlyLambda = sizeof(R) == 4 && K <= 2;
 
 // ------------------------------------------------------------------------- fluid cells
-template <int K, int NF, typename R>
-__device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
+template <int K, int NF, typename R, bool PK>
+__device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<R> &B, const Tab<K, R, PK> &T, int nF,
                                               const LaneInfo &L) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
     const int nic = a.n_ic, ic = L.ic, shot = L.shot;
     const unsigned boff = L.boff, coff = L.coff;
     const long long lane = boff / sizeof(R), LT = a.LT;
-    const HHO_CONST R *Bx = tb;
-    const HHO_CONST R *By = tb + N * N;
-    const HHO_CONST R *Sm = tb + 2 * N * N;
-    const HHO_CONST R *Gt = tb + 3 * N * N;
-    const HHO_CONST R *nr = Gt + nF * N * F;
     int lk[NF];
     R cc[NF], rn[NF][2][F];
     load_links<NF, R>(B, nF, ic, lk, cc);
@@ -143,12 +138,12 @@ __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             if (b_nonzero(r, b)) {
-                sx += Bx[r * N + b] * p[b];
-                sy += By[r * N + b] * p[b];
+                sx += T.bx(r, b) * p[b];
+                sy += T.by(r, b) * p[b];
             }
-            if (b_nonzero(b, r)) sd += Bx[b * N + r] * mx[b] + By[b * N + r] * my[b];
-            sd += Sm[r * N + b] * tp[b];
-            ys += (double)Sm[r * N + b] * (double)p[b];
+            if (b_nonzero(b, r)) sd += T.bx(b, r) * mx[b] + T.by(b, r) * my[b];
+            sd += T.s(r, b) * tp[b];
+            ys += (double)T.s(r, b) * (double)p[b];
         }
         rmx[r] = sx;
         rmy[r] = sy;
@@ -158,7 +153,7 @@ __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         if (lk[j] < 0) continue;  // boundary face: face values 0
-        const R nx = nr[2 * j], ny = nr[2 * j + 1];
+        const R nx = T.n(j, 0), ny = T.n(j, 1);
         R r[F];
 #pragma unroll
         for (int i = 0; i < F; ++i) r[i] = R(0);
@@ -167,7 +162,7 @@ __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<
             const R q = tp[b] - nx * mx[b] - ny * my[b];
 #pragma unroll
             for (int i = 0; i < F; ++i)
-                if (g_nonzero(b, i)) r[i] += Gt[(j * N + b) * F + i] * q;
+                if (g_nonzero(b, i)) r[i] += T.g(j, b, i) * q;
         }
         R pF[F];
         if (!((lk[j] >> 3) & 1)) {
@@ -186,9 +181,9 @@ __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 if (!g_nonzero(b, i)) continue;
-                w += Gt[(j * N + b) * F + i] * pF[i];
-                gy += (double)Gt[(j * N + b) * F + i] * (double)pF[i];
-                gw += (double)Gt[(j * N + b) * F + i] * (double)yf[j][i];
+                w += T.g(j, b, i) * pF[i];
+                gy += (double)T.g(j, b, i) * (double)pF[i];
+                gw += (double)T.g(j, b, i) * (double)yf[j][i];
             }
             rmx[b] += nx * w;
             rmy[b] += ny * w;
@@ -258,23 +253,18 @@ __device__ __forceinline__ void fluid_adjoint(const StageArgs<R> &a, const Bufs<
         bst(B.r, boff, B.yout + (N + b) * B.rowb, zx[b]);
         bst(B.r, boff, B.yout + (2 * N + b) * B.rowb, zy[b]);
     }
-    fluid_traces<K, NF, R>(a, B, tb, nF, lk, boff, zp, zx, zy, tau);
+    fluid_traces<K, NF, R, 0, PK>(a, B, T, lk, boff, zp, zx, zy, tau);
 }
 
 // ------------------------------------------------------------------------- solid cells
-template <int K, int NF, typename R>
-__device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
+template <int K, int NF, typename R, bool PK>
+__device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<R> &B, const Tab<K, R, PK> &T, int nF,
                                               const LaneInfo &L) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
     const int nic = a.n_ic, ic = L.ic, shot = L.shot;
     const unsigned boff = L.boff, coff = L.coff;
     const long long lane = boff / sizeof(R), LT = a.LT;
     const R r2 = R(kRsqrt2);
-    const HHO_CONST R *Bx = tb;
-    const HHO_CONST R *By = tb + N * N;
-    const HHO_CONST R *Sm = tb + 2 * N * N;
-    const HHO_CONST R *Gt = tb + 3 * N * N;
-    const HHO_CONST R *nr = Gt + nF * N * F;
     int lk[NF];
     R cc[NF], rn[NF][2][F];
     load_links<NF, R>(B, nF, ic, lk, cc);
@@ -352,15 +342,15 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
         double yx_s = 0, yy_s = 0;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            const R srb = Sm[r * N + b];
+            const R srb = T.s(r, b);
             if (b_nonzero(r, b)) {
-                const R bxrb = Bx[r * N + b], byrb = By[r * N + b];
+                const R bxrb = T.bx(r, b), byrb = T.by(r, b);
                 a1 += bxrb * vx[b];
                 a2 += byrb * vy[b];
                 a3 += byrb * vx[b] + bxrb * vy[b];
             }
             if (b_nonzero(b, r)) {
-                const R bxbr = Bx[b * N + r], bybr = By[b * N + r];
+                const R bxbr = T.bx(b, r), bybr = T.by(b, r);
                 bx += bxbr * s1[b] + bybr * hs3[b];
                 by += bybr * s2[b] + bxbr * hs3[b];
             }
@@ -379,7 +369,7 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         if (lk[j] < 0) continue;
-        const R nx = nr[2 * j], ny = nr[2 * j + 1];
+        const R nx = T.n(j, 0), ny = T.n(j, 1);
         R rx[F], ry[F];
 #pragma unroll
         for (int i = 0; i < F; ++i) rx[i] = ry[i] = R(0);
@@ -390,8 +380,8 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 if (!g_nonzero(b, i)) continue;
-                rx[i] += Gt[(j * N + b) * F + i] * qx;
-                ry[i] += Gt[(j * N + b) * F + i] * qy;
+                rx[i] += T.g(j, b, i) * qx;
+                ry[i] += T.g(j, b, i) * qy;
             }
         }
         R vFx[F], vFy[F];
@@ -418,7 +408,7 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 if (!g_nonzero(b, i)) continue;
-                const R g = Gt[(j * N + b) * F + i];
+                const R g = T.g(j, b, i);
                 wx += g * vFx[i];
                 wy += g * vFy[i];
                 gyx += (double)g * (double)vFx[i];
@@ -508,17 +498,17 @@ __device__ __forceinline__ void solid_adjoint(const StageArgs<R> &a, const Bufs<
         bst(B.r, boff, B.yout + (3 * N + b) * B.rowb, z2[b]);
         bst(B.r, boff, B.yout + (4 * N + b) * B.rowb, z3[b]);
     }
-    solid_traces<K, NF, R>(a, B, tb, nF, lk, boff, zx, zy, z1, z2, z3, tau, itau);
+    solid_traces<K, NF, R, 0, PK>(a, B, T, lk, boff, zx, zy, z1, z2, z3, tau, itau);
 }
 
 template <int K, int NF, typename R, bool POOLED>
 __device__ __forceinline__ void adjoint_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L) {
-    const HHO_CONST R *tb = class_table<POOLED>(a, G, L.ic);
+    const Tab<K, R, POOLED> T{class_table<POOLED>(a, G, L.ic), G.nF};
     const Bufs<R> B = make_bufs(a);
     if (G.medium == kFluid)
-        fluid_adjoint<K, NF, R>(a, B, tb, G.nF, L);
+        fluid_adjoint<K, NF, R, POOLED>(a, B, T, G.nF, L);
     else
-        solid_adjoint<K, NF, R>(a, B, tb, G.nF, L);
+        solid_adjoint<K, NF, R, POOLED>(a, B, T, G.nF, L);
 }
 
 // On a mesh with pooled groups every adjoint launch is two launches over the same grid, as the
@@ -539,7 +529,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(StageArgs<R> a) {
 template <int K, int NF, typename R, bool POOLED>
 __device__ __forceinline__ void start_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L) {
     constexpr int N = Dim<K>::N;
-    const HHO_CONST R *tb = class_table<POOLED>(a, G, L.ic);
+    const Tab<K, R, POOLED> T{class_table<POOLED>(a, G, L.ic), G.nF};
     const Bufs<R> B = make_bufs(a);
     const int ic = L.ic, nb = G.medium == kFluid ? 3 : 5, ncomp = G.medium == kFluid ? 1 : 2;
     const unsigned boff = L.boff, coff = L.coff;
@@ -600,9 +590,9 @@ __device__ __forceinline__ void start_body(const StageArgs<R> &a, const GroupDev
         for (int b = 0; b < N; ++b)
             if (q < nb) bst(B.r, boff, B.yout + (q * N + b) * B.rowb, z[q][b]);
     if (G.medium == kFluid)
-        fluid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.boff, z[0], z[1], z[2], tau);
+        fluid_traces<K, NF, R, 0, POOLED>(a, B, T, lk, L.boff, z[0], z[1], z[2], tau);
     else
-        solid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.boff, z[0], z[1], z[2], z[3], z[4], tau, itau);
+        solid_traces<K, NF, R, 0, POOLED>(a, B, T, lk, L.boff, z[0], z[1], z[2], z[3], z[4], tau, itau);
 }
 
 template <int K, typename R, bool POOLED>

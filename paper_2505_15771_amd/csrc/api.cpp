@@ -113,7 +113,9 @@ struct hho_ctx {
     int last_steps = 0;
     // energy; pinned host copies of the initial energies and of the recorded history, so that a
     // batch reads every context's energies with one synchronisation
+    // energy partials: kGraphSteps slots of [max_blocks][S] (one per step, summed once per graph)
     double *e_part = nullptr, *e_hist = nullptr, *e_now = nullptr;
+    size_t e_part_cap = 0;
     size_t e_hist_cap = 0;
     double *h_e0 = nullptr, *h_ehist = nullptr;
     size_t h_ehist_cap = 0;
@@ -381,7 +383,9 @@ hho_status check_stage_args(hho_ctx *ctx, const StageArgs<R> &a, int n_blocks, i
     within(a.Tin, a.o_tin, tbytes, "incoming traces");
     within(a.Tout, a.o_tout, tbytes, "outgoing traces");
     if (n_blocks > ctx->max_blocks || (size_t)a.cpb * a.S > (size_t)kBlock) bad = "launch shape";
-    if (a.e_part && a.e_part != ctx->e_part) bad = "energy partials";
+    if (a.e_part && (a.e_part != ctx->e_part ||
+                     (size_t)(std::max(a.e_slots, 1) - 1) * a.e_stride + (size_t)n_blocks * a.S > ctx->e_part_cap))
+        bad = "energy partials";
     if ((size_t)std::max(ecap, 0) * a.S > ctx->e_hist_cap) bad = "energy history capacity";
     if (a.rec_first && (size_t)a.rec_steps * a.S * a.nrec * ctx->rec_w > ctx->rec_cap) bad = "receiver capacity";
     if (bad.empty()) return HHO_OK;
@@ -446,7 +450,10 @@ hho_status enqueue_steps(hho_ctx *ctx, hipStream_t st, int n_steps, R *store = n
             a.cY = (R)q.cY;
             a.ck = (R)q.ck;
             a.cb = (R)q.cb;
+            // energy partials of step n in slot n % kGraphSteps, summed after every kGraphSteps-th step
             a.e_part = (a.last && ctx->record_energy && !store) ? ctx->e_part : nullptr;
+            a.e_slots = kGraphSteps;
+            a.e_stride = (long long)ctx->n_blocks() * S;
             a.rec_first = (a.last && ctx->nrec > 0 && !store) ? ctx->rec_first : nullptr;
             a.clock = ctx->clock + ((parity + n) & 1);
             a.clock_next = ctx->clock + ((parity + n + 1) & 1);
@@ -463,9 +470,12 @@ hho_status enqueue_steps(hho_ctx *ctx, hipStream_t st, int n_steps, R *store = n
                 HCK((launch_stage<K, R>(a, ctx->n_blocks(), st)));
             }
         }
-        if (ctx->record_energy && !store)
-            HCK(launch_energy_reduce(ctx->e_part, ctx->n_blocks(), S, ctx->e_hist, ctx->clock + ((parity + n) & 1),
-                                     ecap, st));
+        if (ctx->record_energy && !store && ((n + 1) % kGraphSteps == 0 || n == n_steps - 1)) {
+            const int count = n - n / kGraphSteps * kGraphSteps + 1;  // steps since the last sum
+            HCK(launch_energy_reduce_steps(ctx->e_part, ctx->n_blocks(), S, (long long)ctx->n_blocks() * S,
+                                           kGraphSteps, ctx->e_hist, ctx->clock + ((parity + n) & 1), count, ecap,
+                                           st));
+        }
     }
     return HHO_OK;
 }
@@ -1228,7 +1238,8 @@ hho_status setup_device(hho_ctx *ctx, const hho_params *prm, hho_ctx **out) {
         ctx->launch.push_back(d);
         ctx->max_blocks = std::max(ctx->max_blocks, d.n_blocks);
     }
-    if ((s = dalloc(ctx, (void **)&ctx->e_part, (size_t)ctx->max_blocks * P.S * sizeof(double)))) return fail(s);
+    ctx->e_part_cap = (size_t)kGraphSteps * ctx->max_blocks * P.S;
+    if ((s = dalloc(ctx, (void **)&ctx->e_part, ctx->e_part_cap * sizeof(double)))) return fail(s);
     ctx->cfl_dt = P.dim == 2 ? cfl_time_step(P, prm->rk_stages) : 0.0;
     {
         hipError_t e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);

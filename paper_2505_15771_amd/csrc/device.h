@@ -82,6 +82,10 @@ struct StageArgs {
     double omega[4], phase[4];
     // last-stage diagnostics
     double *e_part;            // energy partials [n_blocks][S] (null = off)
+    // with e_slots > 1 the partials of step n go to e_part + (n % e_slots) * e_stride, so that one
+    // reduction after several steps sums all of them (e_stride = n_blocks * S)
+    long long e_stride;
+    int e_slots;
     const double *emat;        // [4][n_ic]
     const int32_t *rec_first;  // [n_ic], -1 = none (null = off)
     const RecDev *rec;
@@ -123,6 +127,12 @@ hipError_t launch_energy(const StageArgs<R> &a, const R *state, int n_blocks, hi
 // to out[clock->step * S + s] (an energy history), skipped past `cap` steps.
 hipError_t launch_energy_reduce(const double *part, int n_blocks, int S, double *out, const Clock *clock, int cap,
                                 hipStream_t st);
+
+// The energy history of the `count` steps that end with the clock's step: step m = clock->step - j
+// (j < count) sums part[(m % slots) * stride + b * S + s] over the blocks b into out[m * S + s],
+// skipped past `cap` steps.
+hipError_t launch_energy_reduce_steps(const double *part, int n_blocks, int S, long long stride, int slots,
+                                      double *out, const Clock *clock, int count, int cap, hipStream_t st);
 
 // Three-dimensional stage, trace and energy launches (kernels3d_k*.hip; energy of a.Yin), for
 // k <= kMaxK3: at k = 3 a solid tetrahedron carries 180 unknowns, beyond one lane's registers.

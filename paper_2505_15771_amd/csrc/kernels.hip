@@ -53,14 +53,6 @@ constexpr int stage_waves() {
     constexpr int w32[3] = {HHO_STAGE_WAVES_F32}, w64[3] = {HHO_STAGE_WAVES_F64};
     return sizeof(R) == 4 ? w32[K - 1] : w64[K - 1];
 }
-// State loads (U^n, D_{i-1}, Q) of the launches with streaming stores: streaming as well when set.
-#ifndef HHO_NT_STATE_LOADS
-#define HHO_NT_STATE_LOADS 0
-#endif
-template <int POL>
-constexpr int state_load_policy() {
-    return (HHO_NT_STATE_LOADS && POL == kNonTemporal) ? kNonTemporal : 0;
-}
 template <int K, typename R>
 constexpr bool keep_in_registers() {
     return sizeof(R) == 4 ? K <= HHO_KEEP_MAX_K_F32 : K <= 1;
@@ -72,13 +64,12 @@ constexpr bool keep_in_registers() {
 // relative precision in float32 (a stored Y_i would round away the low bits of dt k_i).
 // With KEEP, U^n and D_{i-1} stay in registers (uk, dk) for the combine; otherwise the combine
 // reads them again (cache hits), which keeps the register count of the larger degrees down.
-template <int ND, typename R, bool KEEP, int POL>
+template <int ND, typename R, bool KEEP>
 __device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, R *y, R *uk,
                                            R *dk) {
-    constexpr int LP = state_load_policy<POL>();
     if (a.first) {
 #pragma unroll
-        for (int r = 0; r < ND; ++r) y[r] = bldp<R, LP>(B.r, boff, B.yin + r * B.rowb);
+        for (int r = 0; r < ND; ++r) y[r] = bld<R>(B.r, boff, B.yin + r * B.rowb);
         if (KEEP) {
 #pragma unroll
             for (int r = 0; r < ND; ++r) {
@@ -90,8 +81,8 @@ __device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> 
         R d[ND], u[ND];
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
-            d[r] = bldp<R, LP>(B.r, boff, B.yin + r * B.rowb);
-            u[r] = bldp<R, LP>(B.r, boff, B.u + r * B.rowb);
+            d[r] = bld<R>(B.r, boff, B.yin + r * B.rowb);
+            u[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
         }
 #pragma unroll
         for (int r = 0; r < ND; ++r) y[r] = u[r] + d[r];
@@ -119,7 +110,6 @@ __device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> 
 template <int ND, typename R, bool KEEP, int POL>
 __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, const R *y,
                                           const R *kv, R *out, const R *uk, const R *dk, int shot) {
-    constexpr int LP = state_load_policy<POL>();
     const R dt = R(shot_dt(a, shot));
     R u[ND], din[ND];
     const bool need_d = a.last ? a.cd != R(0) : (a.cY != R(0) || a.q_write);
@@ -138,13 +128,13 @@ __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &
     } else if (need_d) {
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
-            u[r] = bldp<R, LP>(B.r, boff, B.u + r * B.rowb);
-            din[r] = bldp<R, LP>(B.r, boff, B.yin + r * B.rowb);
+            u[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
+            din[r] = bld<R>(B.r, boff, B.yin + r * B.rowb);
         }
     } else {
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
-            u[r] = bldp<R, LP>(B.r, boff, B.u + r * B.rowb);
+            u[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
             din[r] = R(0);
         }
     }
@@ -161,7 +151,7 @@ __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &
         R q[ND];
         if (a.q_read) {
 #pragma unroll
-            for (int r = 0; r < ND; ++r) q[r] = bldp<R, LP>(B.r, boff, B.yq + r * B.rowb);
+            for (int r = 0; r < ND; ++r) q[r] = bld<R>(B.r, boff, B.yq + r * B.rowb);
         } else {
 #pragma unroll
             for (int r = 0; r < ND; ++r) q[r] = R(0);
@@ -198,24 +188,19 @@ __device__ __forceinline__ void store_recompute(const StageArgs<R> &a, const int
 }
 
 // ------------------------------------------------------------------------- fluid cells
-template <int K, int NF, typename R, bool STORE, int POL>
-__device__ __forceinline__ double fluid_stage(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
-                                              const LaneInfo &L, bool want_e) {
+template <int K, int NF, typename R, bool STORE, int POL, bool PK>
+__device__ __forceinline__ double fluid_stage(const StageArgs<R> &a, const Bufs<R> &B, const Tab<K, R, PK> &T,
+                                              int nF, const LaneInfo &L, bool want_e) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
     const int nic = a.n_ic, ic = L.ic, shot = L.shot;
     const unsigned boff = L.boff, coff = L.coff;
-    const HHO_CONST R *Bx = tb;
-    const HHO_CONST R *By = tb + N * N;
-    const HHO_CONST R *Sm = tb + 2 * N * N;
-    const HHO_CONST R *Gt = tb + 3 * N * N;
-    const HHO_CONST R *nr = Gt + nF * N * F;
     int lk[NF];
     R cc[NF], rn[NF][2][F];
     R fv[STORE ? NF : 1][2][F];  // face values, kept for the recompute stores
     load_links<NF, R>(B, nF, ic, lk, cc);
     constexpr bool KEEP = keep_in_registers<K, R>();
     R y[3 * N], uk[KEEP ? 3 * N : 1], dk[KEEP ? 3 * N : 1];
-    load_state<3 * N, R, KEEP, POL>(a, B, boff, y, uk, dk);
+    load_state<3 * N, R, KEEP>(a, B, boff, y, uk, dk);
     const R *p = y, *mx = y + N, *my = y + 2 * N;
     load_incoming<K, NF, R>(B, kFluid, a.S, shot, lk, rn);
     const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
@@ -230,11 +215,11 @@ __device__ __forceinline__ double fluid_stage(const StageArgs<R> &a, const Bufs<
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             if (b_nonzero(r, b)) {
-                sx += Bx[r * N + b] * p[b];
-                sy += By[r * N + b] * p[b];
+                sx += T.bx(r, b) * p[b];
+                sy += T.by(r, b) * p[b];
             }
-            if (b_nonzero(b, r)) sd += Bx[b * N + r] * mx[b] + By[b * N + r] * my[b];
-            sd += Sm[r * N + b] * tp[b];
+            if (b_nonzero(b, r)) sd += T.bx(b, r) * mx[b] + T.by(b, r) * my[b];
+            sd += T.s(r, b) * tp[b];
         }
         rmx[r] = sx;
         rmy[r] = sy;
@@ -243,7 +228,7 @@ __device__ __forceinline__ double fluid_stage(const StageArgs<R> &a, const Bufs<
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         if (lk[j] < 0) continue;  // boundary face: p_F = 0 (homogeneous Dirichlet)
-        const R nx = nr[2 * j], ny = nr[2 * j + 1];
+        const R nx = T.n(j, 0), ny = T.n(j, 1);
         R r[F];
 #pragma unroll
         for (int i = 0; i < F; ++i) r[i] = R(0);
@@ -252,7 +237,7 @@ __device__ __forceinline__ double fluid_stage(const StageArgs<R> &a, const Bufs<
             const R q = tp[b] - nx * mx[b] - ny * my[b];
 #pragma unroll
             for (int i = 0; i < F; ++i)
-                if (g_nonzero(b, i)) r[i] += Gt[(j * N + b) * F + i] * q;
+                if (g_nonzero(b, i)) r[i] += T.g(j, b, i) * q;
         }
         R pF[F];
         if (!((lk[j] >> 3) & 1)) {
@@ -273,7 +258,7 @@ __device__ __forceinline__ double fluid_stage(const StageArgs<R> &a, const Bufs<
             R w = 0;
 #pragma unroll
             for (int i = 0; i < F; ++i)
-                if (g_nonzero(b, i)) w += Gt[(j * N + b) * F + i] * pF[i];
+                if (g_nonzero(b, i)) w += T.g(j, b, i) * pF[i];
             rmx[b] += nx * w;
             rmy[b] += ny * w;
             rp[b] += tau * w;
@@ -312,7 +297,7 @@ __device__ __forceinline__ double fluid_stage(const StageArgs<R> &a, const Bufs<
     rk_update<3 * N, R, KEEP, POL>(a, B, boff, y, kv, nw, uk, dk, shot);
     const R *np = nw, *nmx = nw + N, *nmy = nw + 2 * N;
     if (STORE) store_recompute<K, NF, 3 * N, R, NF, 1>(a, lk, boff, y, kv, fv);
-    fluid_traces<K, NF, R, POL>(a, B, tb, nF, lk, boff, np, nmx, nmy, tau);
+    fluid_traces<K, NF, R, POL, PK>(a, B, T, lk, boff, np, nmx, nmy, tau);
     double energy = 0.0;
     if (a.last) {
         if (want_e) {
@@ -344,25 +329,20 @@ __device__ __forceinline__ double fluid_stage(const StageArgs<R> &a, const Bufs<
 }
 
 // ------------------------------------------------------------------------- solid cells
-template <int K, int NF, typename R, bool STORE, int POL>
-__device__ __forceinline__ double solid_stage(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
-                                              const LaneInfo &L, bool want_e) {
+template <int K, int NF, typename R, bool STORE, int POL, bool PK>
+__device__ __forceinline__ double solid_stage(const StageArgs<R> &a, const Bufs<R> &B, const Tab<K, R, PK> &T,
+                                              int nF, const LaneInfo &L, bool want_e) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
     const int nic = a.n_ic, ic = L.ic, shot = L.shot;
     const unsigned boff = L.boff, coff = L.coff;
     const R r2 = R(kRsqrt2);
-    const HHO_CONST R *Bx = tb;
-    const HHO_CONST R *By = tb + N * N;
-    const HHO_CONST R *Sm = tb + 2 * N * N;
-    const HHO_CONST R *Gt = tb + 3 * N * N;
-    const HHO_CONST R *nr = Gt + nF * N * F;
     int lk[NF];
     R cc[NF], rn[NF][2][F];
     R fv[STORE ? NF : 1][2][F];  // face values, kept for the recompute stores
     load_links<NF, R>(B, nF, ic, lk, cc);
     constexpr bool KEEP = keep_in_registers<K, R>();
     R y[5 * N], uk[KEEP ? 5 * N : 1], dk[KEEP ? 5 * N : 1];
-    load_state<5 * N, R, KEEP, POL>(a, B, boff, y, uk, dk);
+    load_state<5 * N, R, KEEP>(a, B, boff, y, uk, dk);
     const R *vx = y, *vy = y + N, *s1 = y + 2 * N, *s2 = y + 3 * N, *s3 = y + 4 * N;
     load_incoming<K, NF, R>(B, kSolid, a.S, shot, lk, rn);
     const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
@@ -383,15 +363,15 @@ __device__ __forceinline__ double solid_stage(const StageArgs<R> &a, const Bufs<
         R a1 = 0, a2 = 0, a3 = 0, bx = 0, by = 0;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            const R srb = Sm[r * N + b];
+            const R srb = T.s(r, b);
             if (b_nonzero(r, b)) {
-                const R bxrb = Bx[r * N + b], byrb = By[r * N + b];
+                const R bxrb = T.bx(r, b), byrb = T.by(r, b);
                 a1 += bxrb * vx[b];
                 a2 += byrb * vy[b];
                 a3 += byrb * vx[b] + bxrb * vy[b];
             }
             if (b_nonzero(b, r)) {
-                const R bxbr = Bx[b * N + r], bybr = By[b * N + r];
+                const R bxbr = T.bx(b, r), bybr = T.by(b, r);
                 bx += bxbr * s1[b] + bybr * hs3[b];
                 by += bybr * s2[b] + bxbr * hs3[b];
             }
@@ -407,7 +387,7 @@ __device__ __forceinline__ double solid_stage(const StageArgs<R> &a, const Bufs<
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         if (lk[j] < 0) continue;  // boundary face: v_F = 0 (homogeneous Dirichlet)
-        const R nx = nr[2 * j], ny = nr[2 * j + 1];
+        const R nx = T.n(j, 0), ny = T.n(j, 1);
         R rx[F], ry[F];
 #pragma unroll
         for (int i = 0; i < F; ++i) rx[i] = ry[i] = R(0);
@@ -418,8 +398,8 @@ __device__ __forceinline__ double solid_stage(const StageArgs<R> &a, const Bufs<
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 if (!g_nonzero(b, i)) continue;
-                rx[i] += Gt[(j * N + b) * F + i] * qx;
-                ry[i] += Gt[(j * N + b) * F + i] * qy;
+                rx[i] += T.g(j, b, i) * qx;
+                ry[i] += T.g(j, b, i) * qy;
             }
         }
         R vFx[F], vFy[F];
@@ -451,8 +431,8 @@ __device__ __forceinline__ double solid_stage(const StageArgs<R> &a, const Bufs<
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 if (!g_nonzero(b, i)) continue;
-                wx += Gt[(j * N + b) * F + i] * vFx[i];
-                wy += Gt[(j * N + b) * F + i] * vFy[i];
+                wx += T.g(j, b, i) * vFx[i];
+                wy += T.g(j, b, i) * vFy[i];
             }
             rs1[b] += nx * wx;
             rs2[b] += ny * wy;
@@ -500,7 +480,7 @@ __device__ __forceinline__ double solid_stage(const StageArgs<R> &a, const Bufs<
     rk_update<5 * N, R, KEEP, POL>(a, B, boff, y, kv, nw, uk, dk, shot);
     const R *nvx = nw, *nvy = nw + N, *ns1 = nw + 2 * N, *ns2 = nw + 3 * N, *ns3 = nw + 4 * N;
     if (STORE) store_recompute<K, NF, 5 * N, R, NF, 2>(a, lk, boff, y, kv, fv);
-    solid_traces<K, NF, R, POL>(a, B, tb, nF, lk, boff, nvx, nvy, ns1, ns2, ns3, tau, itau);
+    solid_traces<K, NF, R, POL, PK>(a, B, T, lk, boff, nvx, nvy, ns1, ns2, ns3, tau, itau);
     double energy = 0.0;
     if (a.last) {
         if (want_e) {
@@ -540,10 +520,10 @@ __device__ __forceinline__ double solid_stage(const StageArgs<R> &a, const Bufs<
 // One lane's stage; returns its energy (the last stage with energy recording), else 0.
 template <int K, int NF, typename R, bool STORE, int POL, bool POOLED>
 __device__ __forceinline__ double stage_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L, bool want_e) {
-    const HHO_CONST R *tb = class_table<POOLED>(a, G, L.ic);
+    const Tab<K, R, POOLED> T{class_table<POOLED>(a, G, L.ic), G.nF};
     const Bufs<R> B = make_bufs(a);
-    if (G.medium == kFluid) return fluid_stage<K, NF, R, STORE, POL>(a, B, tb, G.nF, L, want_e);
-    return solid_stage<K, NF, R, STORE, POL>(a, B, tb, G.nF, L, want_e);
+    if (G.medium == kFluid) return fluid_stage<K, NF, R, STORE, POL, POOLED>(a, B, T, G.nF, L, want_e);
+    return solid_stage<K, NF, R, STORE, POL, POOLED>(a, B, T, G.nF, L, want_e);
 }
 
 // With pooled groups a stage is two launches over the same grid: the one for the ordinary groups
@@ -568,14 +548,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(stage_wa
         if (G.nF <= 4) e = stage_body<K, 4, R, STORE, POL, POOLED>(a, G, L, want_e);
         else e = stage_body<K, kMaxFaces, R, STORE, POL, POOLED>(a, G, L, want_e);
     }
-    if (want_e) block_energy(e, a.S, a.cpb, a.e_part);
+    if (want_e) block_energy(e, a.S, a.cpb, energy_slot(a));
 }
 
 // Outgoing trace contributions of the state in a.Yin (used once after the state is set).
 template <int K, int NF, typename R, bool POOLED>
 __device__ __forceinline__ void traces_body(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L) {
     constexpr int N = Dim<K>::N;
-    const HHO_CONST R *tb = class_table<POOLED>(a, G, L.ic);
+    const Tab<K, R, POOLED> T{class_table<POOLED>(a, G, L.ic), G.nF};
     const Bufs<R> B = make_bufs(a);
     int lk[NF];
     load_links<NF, R>(B, G.nF, L.ic, lk, (R *)nullptr);
@@ -588,9 +568,9 @@ __device__ __forceinline__ void traces_body(const StageArgs<R> &a, const GroupDe
 #pragma unroll
         for (int b = 0; b < N; ++b) v[q][b] = q < nb ? bld<R>(B.r, L.boff, B.yin + (q * N + b) * B.rowb) : R(0);
     if (G.medium == kFluid)
-        fluid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.boff, v[0], v[1], v[2], tau);
+        fluid_traces<K, NF, R, 0, POOLED>(a, B, T, lk, L.boff, v[0], v[1], v[2], tau);
     else
-        solid_traces<K, NF, R>(a, B, tb, G.nF, lk, L.boff, v[0], v[1], v[2], v[3], v[4], tau, itau);
+        solid_traces<K, NF, R, 0, POOLED>(a, B, T, lk, L.boff, v[0], v[1], v[2], v[3], v[4], tau, itau);
 }
 
 template <int K, typename R, bool POOLED = false>
@@ -670,6 +650,32 @@ __global__ __launch_bounds__(kReduceBlock) void energy_reduce_kernel(const doubl
     }
 }
 
+// History of several steps: workgroup (s, j) sums the partials of step clock->step - j, shot s.
+__global__ __launch_bounds__(kReduceBlock) void energy_reduce_steps_kernel(const double *part, int n_blocks, int S,
+                                                                           long long stride, int slots, double *out,
+                                                                           const Clock *clock, int cap) {
+    __shared__ double buf[kReduceBlock / 64];
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int m = clock->step - (int)blockIdx.y;
+    if (m < 0 || m >= cap) return;  // uniform over the workgroup
+    const double *p = part + (long long)(m % slots) * stride;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int b = tid;
+    for (; b + 3 * kReduceBlock < n_blocks; b += 4 * kReduceBlock)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += p[(long long)(b + u * kReduceBlock) * S + s];
+    for (; b < n_blocks; b += kReduceBlock) acc[0] += p[(long long)b * S + s];
+    double v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((tid & 63) == 0) buf[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kReduceBlock / 64; ++w) t += buf[w];
+        out[(long long)m * S + s] = t;
+    }
+}
+
 template <typename R>
 __global__ void scatter_kernel(const double *ext, const int64_t *map, long long n, int shot, R *state) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -740,6 +746,12 @@ hipError_t launch_energy_reduce(const double *part, int n_blocks, int S, double 
     return hipGetLastError();
 }
 
+hipError_t launch_energy_reduce_steps(const double *part, int n_blocks, int S, long long stride, int slots,
+                                      double *out, const Clock *clock, int count, int cap, hipStream_t st) {
+    hipLaunchKernelGGL(energy_reduce_steps_kernel, dim3(S, count), dim3(kReduceBlock), 0, st, part, n_blocks, S,
+                       stride, slots, out, clock, cap);
+    return hipGetLastError();
+}
 
 template <typename R>
 hipError_t launch_scatter(const double *ext, const int64_t *map, long long n, int shot, R *state, hipStream_t st) {

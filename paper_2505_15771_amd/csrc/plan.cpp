@@ -414,11 +414,28 @@ std::string build_plan(int nv, const double *xy, int nc, const int32_t *cell_ptr
             }
         }
         ci.offset = (int)P.tables.size();
-        P.tables.insert(P.tables.end(), Bx.begin(), Bx.end());
-        P.tables.insert(P.tables.end(), By.begin(), By.end());
-        P.tables.insert(P.tables.end(), Ssum.begin(), Ssum.end());
-        P.tables.insert(P.tables.end(), G.begin(), G.end());
-        P.tables.insert(P.tables.end(), nrm.begin(), nrm.end());
+        if (!ci.pooled) {
+            P.tables.insert(P.tables.end(), Bx.begin(), Bx.end());
+            P.tables.insert(P.tables.end(), By.begin(), By.end());
+            P.tables.insert(P.tables.end(), Ssum.begin(), Ssum.end());
+            P.tables.insert(P.tables.end(), G.begin(), G.end());
+            P.tables.insert(P.tables.end(), nrm.begin(), nrm.end());
+        } else {
+            // packed (read per lane): the structurally nonzero entries of B_x and B_y, the upper
+            // triangle of the symmetric S, the structurally nonzero entries of every G_j, the normals
+            const int deg[10] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3};
+            for (const std::vector<double> *Bc : {&Bx, &By})
+                for (int r = 0; r < N; ++r)
+                    for (int b = 0; b < N; ++b)
+                        if (deg[b] < deg[r]) P.tables.push_back((*Bc)[r * N + b]);
+            for (int r = 0; r < N; ++r)
+                for (int b = r; b < N; ++b) P.tables.push_back(Ssum[r * N + b]);
+            for (int j = 0; j < nl; ++j)
+                for (int a2 = 0; a2 < N; ++a2)
+                    for (int i = 0; i < F; ++i)
+                        if (i <= deg[a2]) P.tables.push_back(G[(j * N + a2) * F + i]);
+            P.tables.insert(P.tables.end(), nrm.begin(), nrm.end());
+        }
     }
 
     // per-cell stabilisation weight eta * tau_T (alpha = 0) and elastic constants

@@ -550,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel3(StageArgs<R> a) {
         if (G.nF <= 4) e = stage_body3<K, 4, R, POL, POOLED>(a, G, L, want_e);
         else e = stage_body3<K, 6, R, POL, POOLED>(a, G, L, want_e);
     }
-    if (want_e) block_energy(e, a.S, a.cpb, a.e_part);
+    if (want_e) block_energy(e, a.S, a.cpb, energy_slot(a));
 }
 
 template <int K, int NF, typename R, bool POOLED>

@@ -52,14 +52,6 @@ template <>
 __device__ __forceinline__ double bld<double>(Rsrc r, unsigned voff, unsigned soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
-// Load with a cache policy LPOL (0 = default, 2 = streaming).
-template <typename R, int LPOL>
-__device__ __forceinline__ R bldp(Rsrc r, unsigned voff, unsigned soff) {
-    if constexpr (sizeof(R) == 4)
-        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, LPOL));
-    else
-        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, LPOL));
-}
 // Stores take a cache policy POL: 0 = default, kNonTemporal = streaming (used when the working
 // set of a context is larger than the last-level cache, so that stage outputs go through to
 // memory while the launch runs instead of in one write-back at its end).
@@ -210,6 +202,72 @@ __device__ constexpr bool b_nonzero(int r, int b) { return kBasisDegree[b] < kBa
 // nonzero only when i <= deg(a) (exact zeros in the host plan as well).
 __device__ constexpr bool g_nonzero(int a, int i) { return i <= kBasisDegree[a]; }
 
+// Class tables.  Shared (group) tables are dense: B_x, B_y, S (N x N row-major), then per face G_j
+// (N x F) and n_j (2).  The per-cell tables of pooled groups, read by every lane, are packed
+// without their structural zeros: the entries of B_x and of B_y with deg(b) < deg(r) (row-major),
+// the upper triangle of the symmetric S (r <= b, row-major), per face the entries of G_j with
+// i <= deg(a) (row-major), then the normals.  Tab reads either layout by compile-time indices.
+template <int K>
+struct Packed {
+    static constexpr int N = Dim<K>::N, F = Dim<K>::F;
+    static constexpr int count_b() {
+        int c = 0;
+        for (int r = 0; r < N; ++r)
+            for (int b = 0; b < N; ++b) c += kBasisDegree[b] < kBasisDegree[r];
+        return c;
+    }
+    static constexpr int count_g() {
+        int c = 0;
+        for (int a = 0; a < N; ++a)
+            for (int i = 0; i < F; ++i) c += i <= kBasisDegree[a];
+        return c;
+    }
+    static constexpr int nB = count_b(), nS = N * (N + 1) / 2, nG = count_g();
+    static constexpr int bidx(int r, int b) {
+        int c = 0;
+        for (int rr = 0; rr < N; ++rr)
+            for (int bb = 0; bb < N; ++bb) {
+                if (rr == r && bb == b) return c;
+                c += kBasisDegree[bb] < kBasisDegree[rr];
+            }
+        return -1;
+    }
+    static constexpr int sidx(int r, int b) {
+        const int lo = r < b ? r : b, hi = r < b ? b : r;
+        return lo * N - lo * (lo - 1) / 2 + (hi - lo);
+    }
+    static constexpr int gidx(int a, int i) {
+        int c = 0;
+        for (int aa = 0; aa < N; ++aa)
+            for (int ii = 0; ii < F; ++ii) {
+                if (aa == a && ii == i) return c;
+                c += ii <= kBasisDegree[aa];
+            }
+        return -1;
+    }
+};
+
+template <int K, typename R, bool PACKED>
+struct Tab {
+    static constexpr int N = Dim<K>::N, F = Dim<K>::F;
+    using P = Packed<K>;
+    const HHO_CONST R *t;
+    int nF;  // faces of the table layout
+    __device__ __forceinline__ R bx(int r, int b) const { return PACKED ? t[P::bidx(r, b)] : t[r * N + b]; }
+    __device__ __forceinline__ R by(int r, int b) const {
+        return PACKED ? t[P::nB + P::bidx(r, b)] : t[N * N + r * N + b];
+    }
+    __device__ __forceinline__ R s(int r, int b) const {
+        return PACKED ? t[2 * P::nB + P::sidx(r, b)] : t[2 * N * N + r * N + b];
+    }
+    __device__ __forceinline__ R g(int j, int a, int i) const {
+        return PACKED ? t[2 * P::nB + P::nS + j * P::nG + P::gidx(a, i)] : t[3 * N * N + (j * N + a) * F + i];
+    }
+    __device__ __forceinline__ R n(int j, int c) const {
+        return PACKED ? t[2 * P::nB + P::nS + nF * P::nG + 2 * j + c] : t[3 * N * N + nF * N * F + 2 * j + c];
+    }
+};
+
 struct LaneInfo {
     int ic, shot;
     unsigned boff;   // byte offset of this lane in a [row][lane] array of reals
@@ -289,20 +347,18 @@ __device__ __forceinline__ const HHO_CONST R *class_table(const StageArgs<R> &a,
 }
 
 // ------------------------------------------------------------------------- outgoing traces
-template <int K, int NF, typename R, int POL = 0>
-__device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
+template <int K, int NF, typename R, int POL = 0, bool PK = false>
+__device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const Bufs<R> &B, const Tab<K, R, PK> &T,
                                              const int *lk, unsigned boff, const R *p, const R *mx, const R *my,
                                              R tau) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
-    const HHO_CONST R *Gt = tb + 3 * N * N;
-    const HHO_CONST R *nr = Gt + nF * N * F;
     R tp[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) tp[b] = tau * p[b];
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         if (lk[j] < 0) continue;
-        const R nx = nr[2 * j], ny = nr[2 * j + 1];
+        const R nx = T.n(j, 0), ny = T.n(j, 1);
         R r[F];
 #pragma unroll
         for (int i = 0; i < F; ++i) r[i] = R(0);
@@ -311,7 +367,7 @@ __device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const Bufs<R
             const R q = tp[b] - nx * mx[b] - ny * my[b];
 #pragma unroll
             for (int i = 0; i < F; ++i)
-                if (g_nonzero(b, i)) r[i] += Gt[(j * N + b) * F + i] * q;
+                if (g_nonzero(b, i)) r[i] += T.g(j, b, i) * q;
         }
         R o[F];
 #pragma unroll
@@ -320,14 +376,12 @@ __device__ __forceinline__ void fluid_traces(const StageArgs<R> &a, const Bufs<R
     }
 }
 
-template <int K, int NF, typename R, int POL = 0>
-__device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
+template <int K, int NF, typename R, int POL = 0, bool PK = false>
+__device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R> &B, const Tab<K, R, PK> &T,
                                              const int *lk, unsigned boff, const R *vx, const R *vy, const R *s1,
                                              const R *s2, const R *s3, R tau, R itau) {
     constexpr int N = Dim<K>::N, F = Dim<K>::F;
     const R r2 = R(kRsqrt2);
-    const HHO_CONST R *Gt = tb + 3 * N * N;
-    const HHO_CONST R *nr = Gt + nF * N * F;
     R tvx[N], tvy[N], hs3[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
@@ -338,7 +392,7 @@ __device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         if (lk[j] < 0) continue;
-        const R nx = nr[2 * j], ny = nr[2 * j + 1];
+        const R nx = T.n(j, 0), ny = T.n(j, 1);
         R rx[F], ry[F];
 #pragma unroll
         for (int i = 0; i < F; ++i) rx[i] = ry[i] = R(0);
@@ -349,8 +403,8 @@ __device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 if (!g_nonzero(b, i)) continue;
-                rx[i] += Gt[(j * N + b) * F + i] * qx;
-                ry[i] += Gt[(j * N + b) * F + i] * qy;
+                rx[i] += T.g(j, b, i) * qx;
+                ry[i] += T.g(j, b, i) * qy;
             }
         }
         // across the interface the fluid side needs r_s / tau_s
@@ -364,6 +418,13 @@ __device__ __forceinline__ void solid_traces(const StageArgs<R> &a, const Bufs<R
         bstv<F, R, POL>(B.r, F * boff, B.tout + (j * 2) * F * B.rowb, ox);
         bstv<F, R, POL>(B.r, F * boff, B.tout + (j * 2 + 1) * F * B.rowb, oy);
     }
+}
+
+// Energy partials of the current launch: the step's slot when partials are kept per step.
+template <typename R>
+__device__ __forceinline__ double *energy_slot(const StageArgs<R> &a) {
+    if (a.e_slots <= 1) return a.e_part;
+    return a.e_part + (long long)(uni(a.clock)->step % a.e_slots) * a.e_stride;
 }
 
 // Block reduction of per-lane energies into one partial per shot: lanes are (cell, shot) with the

@@ -15,11 +15,46 @@ import numpy as np
 R2 = 1.0 / np.sqrt(2.0)
 
 
+_DEG = (0, 1, 1, 2, 2, 2, 3, 3, 3, 3)
+
+
+def _unpack_pooled(t, off, N, F, nF):
+    """Dense B_x, B_y, S, G, normals from a pooled (packed) table: the entries of B_x and B_y with
+    deg(b) < deg(r), the upper triangle of S, the entries of G_j with i <= deg(a), the normals."""
+    pos = off
+    B = []
+    for _ in range(2):
+        M = np.zeros((N, N))
+        for r in range(N):
+            for b in range(N):
+                if _DEG[b] < _DEG[r]:
+                    M[r, b] = t[pos]
+                    pos += 1
+        B.append(M)
+    Sm = np.zeros((N, N))
+    for r in range(N):
+        for b in range(r, N):
+            Sm[r, b] = Sm[b, r] = t[pos]
+            pos += 1
+    G = np.zeros((nF, N, F))
+    for j in range(nF):
+        for a in range(N):
+            for i in range(F):
+                if i <= _DEG[a]:
+                    G[j, a, i] = t[pos]
+                    pos += 1
+    nrm = t[pos:pos + 2 * nF].reshape(nF, 2)
+    return B[0], B[1], Sm, G, nrm
+
+
 def _cell_tables(ins, g, ic):
-    """Class tables of internal cell ic in group g (a pooled group's cells each have their own)."""
+    """Class tables of internal cell ic in group g (a pooled group's cells each have their own,
+    packed)."""
     N, F = ins.N, ins.F
     med, nF, off = int(ins.groups[g, 0]), int(ins.groups[g, 1]), int(ins.ic_tab[ic])
     t = ins.tables
+    if ins.pooled[g]:
+        return (med, nF) + _unpack_pooled(t, off, N, F, nF)
     Bx = t[off:off + N * N].reshape(N, N)
     By = t[off + N * N:off + 2 * N * N].reshape(N, N)
     Sm = t[off + 2 * N * N:off + 3 * N * N].reshape(N, N)
