@@ -112,22 +112,24 @@ def moved_bytes_per_step(mesh, k, word, shots):
 
 
 def _faces3d(mesh):
-    """(faces, interior faces, fluid-solid interface faces) of a tetrahedron / hexahedron mesh: a
-    face is the vertex set of a cell's local face, shared by the cells that list it."""
-    tet = np.array([(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)])
-    hexf = np.array([(0, 1, 2, 3), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7)])
+    """(faces, interior faces, fluid-solid interface faces) of a tetrahedron / prism / hexahedron
+    mesh: a face is the vertex set of a cell's local face, shared by the cells that list it."""
+    local = {4: [(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)],
+             6: [(0, 1, 2), (3, 4, 5), (0, 1, 4, 3), (1, 2, 5, 4), (2, 0, 3, 5)],
+             8: [(0, 1, 2, 3), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7)]}
     ptr, vtx, med = np.asarray(mesh["cell_ptr"]), np.asarray(mesh["cell_vtx"]), np.asarray(mesh["medium"])
     keys, owner = [], []
-    for nv, loc in ((4, tet), (8, hexf)):
+    for nv, faces in local.items():
         cells = np.flatnonzero(np.diff(ptr) == nv)
         if len(cells) == 0:
             continue
         cv = vtx[ptr[cells][:, None] + np.arange(nv)[None, :]]
-        kk = np.sort(cv[:, loc], axis=2)          # [cells, faces, 3 or 4] sorted vertex ids
-        if kk.shape[2] == 3:                      # triangles: a fourth id of -1
-            kk = np.concatenate([kk, -np.ones(kk.shape[:2] + (1,), kk.dtype)], axis=2)
-        keys.append(kk.reshape(-1, 4))
-        owner.append(np.repeat(cells, len(loc)))
+        for f in faces:
+            kk = np.sort(cv[:, list(f)], axis=1)          # sorted vertex ids; triangles get a fourth id -1
+            if len(f) == 3:
+                kk = np.concatenate([kk, -np.ones((len(cells), 1), kk.dtype)], axis=1)
+            keys.append(kk)
+            owner.append(cells)
     keys, owner = np.concatenate(keys).astype(np.int64), np.concatenate(owner)
     order = np.lexsort(keys.T[::-1])
     ks = keys[order]
@@ -146,20 +148,21 @@ def algorithmic_bytes_per_step3d(mesh, k, word, shots):
     f = (k + 1) * (k + 2) // 2
     med = np.asarray(mesh["medium"])
     nv = np.diff(mesh["cell_ptr"])
-    nf = np.where(nv == 4, 4, 6)
+    nf = np.where(nv == 4, 4, np.where(nv == 6, 5, 6))
     ndof = int(np.sum(np.where(med == 0, 4, 9))) * N
     n_faces, _, n_interface = _faces3d(mesh)
     meta = int(np.sum(4 * nf + 4 * np.where(med == 0, 3, 4))) + 12 * n_faces + (4 * f) ** 2 * word * n_interface
     return word * 17 * ndof * shots + 4 * meta, ndof
 
 
-def run_3d(n, k, dtype, shots, steps, warmup, tets=True):
-    """Two-material unit cube of n^3 cubes (each cut into six tetrahedra, or kept as hexahedra),
-    solid below z = 1/2, materials perturbed by U[-10 %, 10 %] per cell, random states, RK4 from
-    captured graphs; DOF-stage updates/s and the algorithmic bytes against the HBM peak."""
+def run_3d(n, k, dtype, shots, steps, warmup, kind="tets"):
+    """Two-material unit cube of n^3 cubes (each cut into six tetrahedra; or columns of hexahedra
+    and triangular prisms, kind "hybrid"), solid below z = 1/2, materials perturbed by U[-10 %, 10 %]
+    per cell, random states, RK4 from captured graphs; DOF-stage updates/s and the algorithmic bytes
+    against the HBM peak."""
     import torch
     from paper_2505_15771_amd import Engine
-    mesh = M.with_materials3d(M.unit_cube(n, tets=tets), perturb=0.1, seed=7001)
+    mesh = M.with_materials3d(M.unit_cube(n, kind=kind, seed=7000), perturb=0.1, seed=7001)
     e = Engine(mesh, k, dtype=dtype, n_shots=shots)
     for sh in range(shots):
         e.set_state(M.random_state(e.n_dof, 7100 + sh), shot=sh)
@@ -176,7 +179,8 @@ def run_3d(n, k, dtype, shots, steps, warmup, tets=True):
     ms = ev0.elapsed_time(ev1)
     word = 8 if dtype == "f64" else 4
     bstep, ndof = algorithmic_bytes_per_step3d(mesh, k, word, shots)
-    out = dict(workload="unit cube %d^3 %s, two materials" % (n, "tetrahedra" if tets else "hexahedra"),
+    out = dict(workload="unit cube %d^3 %s, two materials" % (n, "tetrahedra" if kind == "tets" else
+                                                                 "columns of hexahedra and prisms"),
                cells=int(len(mesh["medium"])), k=k, dtype=dtype, shots=shots, steps=steps,
                ms_per_step=ms / steps, launch_us=ms / steps / 4 * 1e3,
                value=ndof * shots * 4 * steps / (ms * 1e-3), bytes_per_step=bstep,
@@ -941,7 +945,8 @@ def main():
     ap.add_argument("--dtype", default="f32")
     ap.add_argument("--shots", type=int, default=1)
     ap.add_argument("--only", choices=("headline", "variant", "adjoint", "basin", "batch", "paper", "cfl",
-                                       "precision", "tableaux", "sdirk", "eta", "geometry", "perturbed", "3d"),
+                                       "precision", "tableaux", "sdirk", "eta", "geometry", "perturbed", "3d",
+                                       "3dhybrid"),
                     default=None,
                     help="run one workload alone and print its JSON line (for profiling)")
     ap.add_argument("--only-steps", type=int, default=200)
@@ -989,6 +994,7 @@ def main():
               "eta": lambda: run_eta_sweep(),
               "perturbed": lambda: run_perturbed(dtype=args.dtype, steps=args.only_steps),
               "3d": lambda: run_3d(48 if args.k == 1 else 32, args.k, args.dtype, args.shots, args.only_steps, 5),
+              "3dhybrid": lambda: run_3d(48, args.k, args.dtype, args.shots, args.only_steps, 5, kind="hybrid"),
               "geometry": lambda: [run_cfl_geometry(), run_cfl_geometry(stab_speed=1)],
               "sdirk": lambda: [run_sdirk_bilayer(k_, steps=args.only_steps,
                                                   erk_traces=run_paper_bilayer(k_, sensors=True)["_traces"])
@@ -1043,13 +1049,14 @@ def main():
             _log("workload", w)
             extras["paper_bilayer_k%d" % k_] = dict(erk4_s=round(v["run_s"], 4), sdirk34_s=round(w["run_s_to_t_final"], 3),
                                                     paper_erk4_cpu_s=v["paper_cpu_s"])
-        for (n_, k_, dt_, sh_) in ((48, 1, "f32", 1), (32, 2, "f32", 1), (32, 2, "f64", 1), (32, 2, "f32", 4)):
-            v = run_3d(n_, k_, dt_, sh_, 200, 5)
+        for (n_, k_, dt_, sh_, kd_) in ((48, 1, "f32", 1, "tets"), (32, 2, "f32", 1, "tets"), (32, 2, "f64", 1, "tets"),
+                                        (32, 2, "f32", 4, "tets"), (48, 2, "f32", 1, "hybrid")):
+            v = run_3d(n_, k_, dt_, sh_, 200, 5, kind=kd_)
             _log("workload", v)
-            extras["cube3d_tets_k%d_%s_%dshot" % (k_, dt_, sh_)] = dict(cells=v["cells"],
-                                                                         us_per_step=round(v["ms_per_step"] * 1e3, 1),
-                                                                         value=round(v["value"], -6),
-                                                                         frac=round(v["frac"], 3))
+            extras["cube3d_%s_k%d_%s_%dshot" % (kd_, k_, dt_, sh_)] = dict(cells=v["cells"],
+                                                                            us_per_step=round(v["ms_per_step"] * 1e3, 1),
+                                                                            value=round(v["value"], -6),
+                                                                            frac=round(v["frac"], 3))
         for k_ in (1, 2, 3):
             _log("workload", run_cfl(k_))
         _log("workload", run_precision())

@@ -107,16 +107,18 @@ typedef struct {
  * upload of SoA buffers.  State starts at zero.  Errors: ARG, MESH, SINGULAR, OOM, DEVICE. */
 hho_status hho_setup(const hho_mesh *mesh, const hho_params *params, hho_ctx **out);
 
-/* Three-dimensional mesh of tetrahedra and hexahedra aligned with the fluid / solid partition
- * (the method of Sec. 2-3 with d = 3; Table tab::DOFS counts its unknowns):
+/* Three-dimensional mesh of tetrahedra, triangular prisms and hexahedra aligned with the fluid /
+ * solid partition (the method of Sec. 2-3 with d = 3; Table tab::DOFS counts its unknowns):
  *   xyz[3*n_vertices]         vertex coordinates (x, y, z)
- *   cell_ptr[n_cells+1]       CSR offsets into cell_vtx: 4 ids (tetrahedron) or 8 ids (hexahedron
- *                             with planar faces: vertices 0-3 around the bottom face, 4-7 above
- *                             vertices 0-3 in the same order); cells must be convex
+ *   cell_ptr[n_cells+1]       CSR offsets into cell_vtx: 4 ids (tetrahedron), 6 ids (triangular
+ *                             prism: vertices 0-2 around the bottom triangle, 3-5 above vertices
+ *                             0-2 in the same order) or 8 ids (hexahedron: vertices 0-3 around the
+ *                             bottom face, 4-7 above vertices 0-3 in the same order); faces must
+ *                             be planar and cells convex
  *   medium, rho, a, b         as in hho_mesh (solid: lambda, mu of 3D isotropic elasticity)
  * Every face (same vertex set) must be shared by at most two cells.  Local faces: tetrahedron
- * face j is opposite vertex j; hexahedron faces (0 1 2 3), (4 5 6 7), (0 1 5 4), (1 2 6 5),
- * (2 3 7 6), (3 0 4 7). */
+ * face j is opposite vertex j; prism faces (0 1 2), (3 4 5), (0 1 4 3), (1 2 5 4), (2 0 3 5);
+ * hexahedron faces (0 1 2 3), (4 5 6 7), (0 1 5 4), (1 2 6 5), (2 3 7 6), (3 0 4 7). */
 typedef struct {
     int32_t n_vertices;
     const double *xyz;

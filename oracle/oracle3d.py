@@ -519,9 +519,10 @@ def ricker(t, f0, t0):
     return (1.0 - 2.0 * a * a) * math.exp(-a * a)
 
 
-def cube_mesh(n, tets=True, medium_of=None, materials=None, L=1.0):
+def cube_mesh(n, tets=True, medium_of=None, materials=None, L=1.0, prisms=False):
     """n^3 cubes of side L / n on [0, L]^3, each split into six tetrahedra around its main diagonal
-    (or kept as hexahedra); medium_of(x, y, z) of the cell centre gives 0 (fluid) / 1 (solid)
+    (or kept as hexahedra, or with prisms cut into two triangular prisms along the diagonal of its
+    base); medium_of(x, y, z) of the cell centre gives 0 (fluid) / 1 (solid)
     (default: solid below z = L / 2); materials (rho_f, c_f, rho_s, lambda, mu), default
     rho = 1, c = 1 in the fluid and rho = 1, lambda = mu = 1 (c_P = sqrt 3, c_S = 1) in the solid."""
     g = np.linspace(0.0, L, n + 1)
@@ -534,7 +535,9 @@ def cube_mesh(n, tets=True, medium_of=None, materials=None, L=1.0):
             for l in range(n):
                 h = (vid(i, j, l), vid(i + 1, j, l), vid(i + 1, j + 1, l), vid(i, j + 1, l),
                      vid(i, j, l + 1), vid(i + 1, j, l + 1), vid(i + 1, j + 1, l + 1), vid(i, j + 1, l + 1))
-                if tets:
+                if prisms:
+                    cells += [(h[0], h[1], h[2], h[4], h[5], h[6]), (h[0], h[2], h[3], h[4], h[6], h[7])]
+                elif tets:
                     cells += [tuple(h[t] for t in tt) for tt in HEX_TETS]
                 else:
                     cells.append(h)
@@ -546,7 +549,7 @@ def cube_mesh(n, tets=True, medium_of=None, materials=None, L=1.0):
     a = np.where(med == FLUID, cf, lam)
     b = np.where(med == FLUID, 0.0, mu)
     # orient every tetrahedron positively
-    cells = [c if len(c) == 8 or np.linalg.det(np.stack([xyz[c[1]] - xyz[c[0]], xyz[c[2]] - xyz[c[0]],
+    cells = [c if len(c) != 4 or np.linalg.det(np.stack([xyz[c[1]] - xyz[c[0]], xyz[c[2]] - xyz[c[0]],
                                                              xyz[c[3]] - xyz[c[0]]])) > 0 else (c[0], c[2], c[1], c[3])
              for c in cells]
     return dict(xyz=xyz, cells=cells, medium=med, rho=rho, a=a, b=b)

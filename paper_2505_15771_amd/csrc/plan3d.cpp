@@ -1,5 +1,5 @@
 // Host-side execution plan of the three-dimensional engine (float64): mesh validation for
-// tetrahedra and hexahedra with planar faces, face matching and tagging, per-shape-class local
+// tetrahedra, triangular prisms and hexahedra with planar faces, face matching and tagging, per-shape-class local
 // operators in orthonormal cell and face bases (Sec. 3.3, eq. rec_a, rec_e, stab in d = 3),
 // materials and stabilisation weights, and the grouping of cells by (medium, shape class) into
 // the same structure-of-arrays layout as the two-dimensional plan.
@@ -36,14 +36,17 @@ double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
 double norm(V3 a) { return std::sqrt(dot(a, a)); }
 
-// Local faces: tetrahedron face j opposite vertex j; hexahedron with vertices 0-3 around the
-// bottom and 4-7 above them (every face listed as a cycle of its vertices).
-const int kTetFace[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+// Local faces, every face a cycle of its vertices: tetrahedron face j opposite vertex j; triangular
+// prism with vertices 0-2 around the bottom and 3-5 above them; hexahedron with vertices 0-3 around
+// the bottom and 4-7 above them.
+const int kTetFace[4][4] = {{1, 2, 3, -1}, {0, 2, 3, -1}, {0, 1, 3, -1}, {0, 1, 2, -1}};
+const int kPrismFace[5][4] = {{0, 1, 2, -1}, {3, 4, 5, -1}, {0, 1, 4, 3}, {1, 2, 5, 4}, {2, 0, 3, 5}};
 const int kHexFace[6][4] = {{0, 1, 2, 3}, {4, 5, 6, 7}, {0, 1, 5, 4}, {1, 2, 6, 5}, {2, 3, 7, 6}, {3, 0, 4, 7}};
 
-int n_local_faces(int nv) { return nv == 4 ? 4 : 6; }
-int face_size(int nv) { return nv == 4 ? 3 : 4; }
-int face_vertex(int nv, int j, int m) { return nv == 4 ? kTetFace[j][m] : kHexFace[j][m]; }
+int n_local_faces(int nv) { return nv == 4 ? 4 : nv == 6 ? 5 : 6; }
+const int *local_face_table(int nv, int j) { return nv == 4 ? kTetFace[j] : nv == 6 ? kPrismFace[j] : kHexFace[j]; }
+int face_size(int nv, int j) { return local_face_table(nv, j)[3] < 0 ? 3 : 4; }
+int face_vertex(int nv, int j, int m) { return local_face_table(nv, j)[m]; }
 
 double factorial(int n) {
     double r = 1.0;
@@ -187,7 +190,7 @@ struct FaceRef {
 
 FaceRef local_face(const int32_t *cv, int nv, int j) {
     FaceRef f;
-    f.nv = face_size(nv);
+    f.nv = face_size(nv, j);
     for (int m = 0; m < f.nv; ++m) f.v[m] = cv[face_vertex(nv, j, m)];
     return f;
 }
@@ -314,9 +317,9 @@ std::string build_plan3d(int nv, const double *xyz, int nc, const int32_t *cell_
     if (cell_ptr[0] != 0) return "cell_ptr[0] must be 0";
     for (int c = 0; c < nc; ++c) {
         const int n = cell_ptr[c + 1] - cell_ptr[c];
-        if (n != 4 && n != 8)
+        if (n != 4 && n != 6 && n != 8)
             return "cell " + std::to_string(c) + " has " + std::to_string(n) +
-                   " vertices (4: tetrahedron, 8: hexahedron)";
+                   " vertices (4: tetrahedron, 6: triangular prism, 8: hexahedron)";
         P.max_nf = std::max(P.max_nf, n_local_faces(n));
     }
     const int ne = cell_ptr[nc];

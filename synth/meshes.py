@@ -437,18 +437,24 @@ def pressure_pulse(mesh, k, center=(0.0, 200.0), sigma=50.0, k_primal=None):
 
 # ----------------------------------------------------------------------------- three dimensions
 # Three-dimensional meshes are dicts with xyz float64 [n_vertices, 3], cell_ptr / cell_vtx (4 ids
-# per tetrahedron, 8 per hexahedron: 0-3 around the bottom face counter-clockwise seen from above,
-# 4-7 above them), medium, and after with_materials3d rho, a, b.
+# per tetrahedron; 6 per triangular prism: 0-2 around the bottom triangle, 3-5 above them; 8 per
+# hexahedron: 0-3 around the bottom face counter-clockwise seen from above, 4-7 above them), medium,
+# and after with_materials3d rho, a, b.
 
 # the six tetrahedra of a cube around its diagonal from corner 0 to corner 6
 _KUHN = ((0, 1, 2, 6), (0, 2, 3, 6), (0, 3, 7, 6), (0, 7, 4, 6), (0, 4, 5, 6), (0, 5, 1, 6))
 
 
-def unit_cube(n, tets=True, jitter=0.0, seed=0, interface_z=0.5, shear=None):
-    """n^3 cubes on [0, 1]^3, solid below z = interface_z and fluid above (cell centres).  tets:
-    every cube cut into six tetrahedra (else kept as a hexahedron).  jitter: interior vertices off
-    the interface plane moved by U[-jitter, jitter] h per coordinate (seeded; tetrahedra only).
-    shear: a 3 x 3 matrix applied to every vertex (hexahedra stay parallelepipeds)."""
+def unit_cube(n, tets=True, jitter=0.0, seed=0, interface_z=0.5, shear=None, kind=None):
+    """n^3 cubes on [0, 1]^3, solid below z = interface_z and fluid above (cell centres).  kind
+    (default "tets" if tets else "hexes"): "tets" cuts every cube into six tetrahedra, "hexes" keeps
+    it, "prisms" cuts it into two triangular prisms along a diagonal of its base (the same diagonal
+    in every cube), "hybrid" keeps every vertical column of cubes as hexahedra or cuts it into prisms
+    along a random diagonal, each with probability 1/2 (seeded).  jitter: interior vertices off the
+    interface plane moved by U[-jitter, jitter] h per coordinate (seeded; tetrahedra only).  shear:
+    a 3 x 3 matrix applied to every vertex (hexahedra and prisms keep planar faces)."""
+    kind = kind or ("tets" if tets else "hexes")
+    tets = kind == "tets"
     g = np.linspace(0.0, 1.0, n + 1)
     X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
     xyz = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
@@ -457,15 +463,32 @@ def unit_cube(n, tets=True, jitter=0.0, seed=0, interface_z=0.5, shear=None):
         return (i * (n + 1) + j) * (n + 1) + l
 
     cells = []
+    col_rng = np.random.default_rng(seed + 7919)
     for i in range(n):
         for j in range(n):
+            # column kind: 0 hexahedra, 1 / 2 prisms cut along the diagonal from base vertex 0 / 1
+            col = {"hexes": 0, "prisms": 1, "tets": 0}.get(kind, 0)
+            if kind == "hybrid":
+                col = 0 if col_rng.random() < 0.5 else 1 + int(col_rng.integers(2))
             for l in range(n):
                 h = (vid(i, j, l), vid(i + 1, j, l), vid(i + 1, j + 1, l), vid(i, j + 1, l),
                      vid(i, j, l + 1), vid(i + 1, j, l + 1), vid(i + 1, j + 1, l + 1), vid(i, j + 1, l + 1))
                 if tets:
                     cells += [tuple(h[t] for t in tt) for tt in _KUHN]
-                else:
+                elif col == 0:
                     cells.append(h)
+                elif col == 1:
+                    cells += [(h[0], h[1], h[2], h[4], h[5], h[6]), (h[0], h[2], h[3], h[4], h[6], h[7])]
+                else:
+                    cells += [(h[0], h[1], h[3], h[4], h[5], h[7]), (h[1], h[2], h[3], h[5], h[6], h[7])]
+    if kind == "hybrid" or kind == "prisms":
+        ptr = np.concatenate([[0], np.cumsum([len(c) for c in cells])]).astype(np.int32)
+        vtx = np.concatenate([np.asarray(c) for c in cells]).astype(np.int32)
+        cent = np.array([xyz[list(c)].mean(axis=0) for c in cells])
+        medium = np.where(cent[:, 2] < interface_z, SOLID, FLUID).astype(np.uint8)
+        if shear is not None:
+            xyz = xyz @ np.asarray(shear, float).T
+        return dict(xyz=xyz, cell_ptr=ptr, cell_vtx=vtx, medium=medium)
     cells = np.array(cells, np.int64)
     cent = xyz[cells].mean(axis=1)
     medium = np.where(cent[:, 2] < interface_z, SOLID, FLUID).astype(np.uint8)

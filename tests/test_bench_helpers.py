@@ -145,7 +145,8 @@ def test_faces3d_counts_match_the_host_plan():
     import bench
     from paper_2505_15771_amd.hho import Inspect
     from synth import meshes as M
-    for mesh in (M.with_materials3d(M.unit_cube(4)), M.with_materials3d(M.unit_cube(3, tets=False))):
+    for mesh in (M.with_materials3d(M.unit_cube(4)), M.with_materials3d(M.unit_cube(3, tets=False)),
+                 M.with_materials3d(M.unit_cube(4, kind="hybrid", seed=2))):
         ins = Inspect(mesh, 1)
         L = ins.link
         n_faces, n_interior, n_interface = bench._faces3d(mesh)

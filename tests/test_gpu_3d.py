@@ -1,6 +1,6 @@
 """GPU parity of the three-dimensional HIP path (hho_setup3d through the C ABI) against the
-three-dimensional FP64 oracle (oracle/oracle3d.py): tetrahedra, parallelepiped hexahedra and
-tetrahedra with moved vertices (pooled class tables), two materials with the fluid-solid
+three-dimensional FP64 oracle (oracle/oracle3d.py): tetrahedra, parallelepiped hexahedra, sheared
+columns of hexahedra and triangular prisms, and tetrahedra with moved vertices (pooled class tables), two materials with the fluid-solid
 interface, k = 1 and 2, ERK(2/3/4), several shots, a batch that mixes a two- and a
 three-dimensional context, and a larger mesh checked through properties that hold at any size.
 
@@ -56,6 +56,8 @@ MESHES = {
     "tets": lambda: (M.with_materials3d(M.unit_cube(4), perturb=0.1, seed=21), 4),
     "hexes": lambda: (M.with_materials3d(M.unit_cube(4, tets=False, shear=SHEAR), perturb=0.1, seed=22), 4),
     "tets-moved": lambda: (M.with_materials3d(M.unit_cube(4, jitter=0.25, seed=23), perturb=0.1, seed=24), 4),
+    "hexes-prisms": lambda: (M.with_materials3d(M.unit_cube(4, kind="hybrid", seed=25, shear=SHEAR), perturb=0.1,
+                                                seed=26), 4),
 }
 
 

@@ -3,8 +3,9 @@
 The stage derivative k = M^{-1}(-K_eff U) that the three-dimensional kernels compute is
 reassembled in NumPy from the exported plan (tests/kernel_model3d.py: class tables in the
 orthonormal bases, face frames fixed by the faces, links, face-solve coefficients, materials) and
-compared with the three-dimensional FP64 oracle's on tetrahedra, sheared hexahedra (parallelepipeds)
-and tetrahedra with moved vertices (every cell its own shape class, pooled tables), k = 1 and 2,
+compared with the three-dimensional FP64 oracle's on tetrahedra, sheared hexahedra (parallelepipeds),
+a sheared mesh of hexahedron and triangular-prism columns, and tetrahedra with moved vertices (every
+cell its own shape class, pooled tables), k = 1 and 2,
 with the fluid-solid interface and perturbed materials.
 """
 import numpy as np
@@ -26,6 +27,8 @@ CASES = {
     "tets": lambda: M.with_materials3d(M.unit_cube(3), rho_f=2.0, c_f=1.5, rho_s=3.0, lam=2.0, mu=0.7),
     "hexes-sheared": lambda: M.with_materials3d(M.unit_cube(3, tets=False, shear=SHEAR), perturb=0.1, seed=5),
     "tets-moved": lambda: M.with_materials3d(M.unit_cube(4, jitter=0.25, seed=3), perturb=0.1, seed=4),
+    "hexes-prisms-sheared": lambda: M.with_materials3d(M.unit_cube(3, kind="hybrid", seed=5, shear=SHEAR),
+                                                       perturb=0.1, seed=6),
 }
 
 

@@ -72,11 +72,11 @@ def test_dof_counts_and_face_shares():
 
 
 @pytest.mark.parametrize("k", [1, 2])
-@pytest.mark.parametrize("hexes", [False, True])
-def test_skew_part_cancels(k, hexes):
+@pytest.mark.parametrize("kind", ["tets", "hexes", "prisms"])
+def test_skew_part_cancels(k, kind):
     """X . A X = stabilisation energy for random cell and face values, on a two-material mesh
     (solid below z = 1/2) with materials varying per cell."""
-    m = cube_mesh(2, tets=not hexes)
+    m = cube_mesh(2, tets=kind == "tets", prisms=kind == "prisms")
     rng = np.random.default_rng(k)
     m["rho"] = m["rho"] * (1 + 0.2 * rng.random(len(m["rho"])))
     m["a"] = m["a"] * (1 + 0.2 * rng.random(len(m["a"])))
@@ -126,8 +126,8 @@ def _with_traces(o, U, fluid_fn, solid_fns):
     return X
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
-def test_polynomial_consistency(k):
+@pytest.mark.parametrize("k,prisms", [(1, False), (2, False), (3, False), (2, True)])
+def test_polynomial_consistency(k, prisms):
     """Interior cells only see polynomial traces: for p in P^k (fluid) and v in P^k(R^3) (solid)
     with face values their traces, the m rows of A X are -(grad p, r)_T and the s rows
     -(grad_sym v, b)_T for every interior cell, and the stabilisation energy of the interior
@@ -137,7 +137,7 @@ def test_polynomial_consistency(k):
     vs = [_Poly(k, rng) for _ in range(3)]
     zero = lambda x, y, z: 0 * x
     for med in (FLUID, SOLID):
-        o = Oracle3D(cube_mesh(3, medium_of=lambda x, y, z, m_=med: m_), k)
+        o = Oracle3D(cube_mesh(3, medium_of=lambda x, y, z, m_=med: m_, prisms=prisms), k)
         U = o.project([p, zero, zero, zero], [vs[0], vs[1], vs[2]] + [zero] * 6)
         X = _with_traces(o, U, p, vs)
         R = o.A @ X
@@ -273,11 +273,11 @@ def _poly_fields(k, rng):
 
 
 @pytest.mark.parametrize("k", [1, 2])
-@pytest.mark.parametrize("tets", [True, False])
-def test_point_load_and_point_values_reproduce_polynomials(tets, k):
+@pytest.mark.parametrize("kind", ["tets", "hexes", "prisms"])
+def test_point_load_and_point_values_reproduce_polynomials(kind, k):
     """Point evaluation is exact on polynomial fields: for U the projection of fields of degree k,
     F . U = d . u(x) for the point-force load F, and the receiver values are u(x), in either medium."""
-    o = Oracle3D(cube_mesh(2, tets=tets), k)
+    o = Oracle3D(cube_mesh(2, tets=kind == "tets", prisms=kind == "prisms"), k)
     rng = np.random.default_rng(41)
     ff, sf = _poly_fields(k, rng)
     U = o.project(ff, sf)
