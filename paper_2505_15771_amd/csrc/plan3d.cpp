@@ -593,9 +593,24 @@ std::string build_plan3d(int nv, const double *xyz, int nc, const int32_t *cell_
             return "cell " + std::to_string(c) + ": local operators lost their degree structure "
                    "(ill-conditioned basis)";
         ci.offset = (int)P.tables.size();
-        for (int d = 0; d < 3; ++d) P.tables.insert(P.tables.end(), B[d].begin(), B[d].end());
-        P.tables.insert(P.tables.end(), Ssum.begin(), Ssum.end());
-        P.tables.insert(P.tables.end(), G.begin(), G.end());
+        if (!ci.pooled) {
+            for (int d = 0; d < 3; ++d) P.tables.insert(P.tables.end(), B[d].begin(), B[d].end());
+            P.tables.insert(P.tables.end(), Ssum.begin(), Ssum.end());
+            P.tables.insert(P.tables.end(), G.begin(), G.end());
+        } else {
+            // packed (read per lane): the structurally nonzero entries of B_x, B_y, B_z, the upper
+            // triangle of the symmetric S, the structurally nonzero entries of every G_j, the normals
+            for (int d = 0; d < 3; ++d)
+                for (int r = 0; r < N; ++r)
+                    for (int b = 0; b < N; ++b)
+                        if (degc[b] < degc[r]) P.tables.push_back(B[d][(size_t)r * N + b]);
+            for (int r = 0; r < N; ++r)
+                for (int b = r; b < N; ++b) P.tables.push_back(Ssum[(size_t)r * N + b]);
+            for (int j = 0; j < nF; ++j)
+                for (int a = 0; a < N; ++a)
+                    for (int i = 0; i < F; ++i)
+                        if (degf[i] <= degc[a]) P.tables.push_back(G[((size_t)j * N + a) * F + i]);
+        }
         P.tables.insert(P.tables.end(), nrm.begin(), nrm.end());
     }
 

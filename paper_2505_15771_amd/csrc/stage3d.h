@@ -44,6 +44,70 @@ constexpr int kDegF3[10] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3};
 __device__ constexpr bool b3_nonzero(int r, int b) { return kDeg3[b] < kDeg3[r]; }
 __device__ constexpr bool g3_nonzero(int a, int i) { return kDegF3[i] <= kDeg3[a]; }
 
+// Class tables: dense for the shared tables (B_x, B_y, B_z, S: N x N row-major; per face G_j
+// N x F and n_j, 3 values), packed for the per-cell tables of pooled groups: the entries of B_x, B_y,
+// B_z with deg(b) < deg(r), the upper triangle of S, per face the entries of G_j with
+// deg(psi_i) <= deg(phi_a), then the normals.  Tab3 reads either layout by compile-time indices.
+template <int K>
+struct Packed3 {
+    static constexpr int N = Dim3<K>::N, F = Dim3<K>::F;
+    static constexpr int count_b() {
+        int c = 0;
+        for (int r = 0; r < N; ++r)
+            for (int b = 0; b < N; ++b) c += kDeg3[b] < kDeg3[r];
+        return c;
+    }
+    static constexpr int count_g() {
+        int c = 0;
+        for (int a = 0; a < N; ++a)
+            for (int i = 0; i < F; ++i) c += kDegF3[i] <= kDeg3[a];
+        return c;
+    }
+    static constexpr int nB = count_b(), nS = N * (N + 1) / 2, nG = count_g();
+    static constexpr int bidx(int r, int b) {
+        int c = 0;
+        for (int rr = 0; rr < N; ++rr)
+            for (int bb = 0; bb < N; ++bb) {
+                if (rr == r && bb == b) return c;
+                c += kDeg3[bb] < kDeg3[rr];
+            }
+        return -1;
+    }
+    static constexpr int sidx(int r, int b) {
+        const int lo = r < b ? r : b, hi = r < b ? b : r;
+        return lo * N - lo * (lo - 1) / 2 + (hi - lo);
+    }
+    static constexpr int gidx(int a, int i) {
+        int c = 0;
+        for (int aa = 0; aa < N; ++aa)
+            for (int ii = 0; ii < F; ++ii) {
+                if (aa == a && ii == i) return c;
+                c += kDegF3[ii] <= kDeg3[aa];
+            }
+        return -1;
+    }
+};
+
+template <int K, typename R, bool PACKED>
+struct Tab3 {
+    static constexpr int N = Dim3<K>::N, F = Dim3<K>::F;
+    using P = Packed3<K>;
+    const HHO_CONST R *t;
+    int nF;  // faces of the table layout
+    __device__ __forceinline__ R b(int d, int r, int c) const {
+        return PACKED ? t[d * P::nB + P::bidx(r, c)] : t[d * N * N + r * N + c];
+    }
+    __device__ __forceinline__ R s(int r, int c) const {
+        return PACKED ? t[3 * P::nB + P::sidx(r, c)] : t[3 * N * N + r * N + c];
+    }
+    __device__ __forceinline__ R g(int j, int a, int i) const {
+        return PACKED ? t[3 * P::nB + P::nS + j * P::nG + P::gidx(a, i)] : t[4 * N * N + (j * N + a) * F + i];
+    }
+    __device__ __forceinline__ R n(int j, int c) const {
+        return PACKED ? t[3 * P::nB + P::nS + nF * P::nG + 3 * j + c] : t[4 * N * N + nF * N * F + 3 * j + c];
+    }
+};
+
 // Stage input Y_i = U^n + D_{i-1} (U^n on the first stage).
 template <int ND, typename R>
 __device__ __forceinline__ void load_state3(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, R *y) {
@@ -109,17 +173,15 @@ __device__ __forceinline__ void gather3(const Bufs<R> &B, int S, int shot, int l
 }
 
 // ------------------------------------------------------------------------- outgoing traces
-template <int K, int NF, typename R, int POL = 0>
-__device__ __forceinline__ void fluid_traces3(const Bufs<R> &B, const HHO_CONST R *tb, int nF, const int *lk,
+template <int K, int NF, typename R, int POL = 0, bool PK = false>
+__device__ __forceinline__ void fluid_traces3(const Bufs<R> &B, const Tab3<K, R, PK> &T, const int *lk,
                                               unsigned boff, const R *p, const R *mx, const R *my, const R *mz,
                                               R tau) {
     constexpr int N = Dim3<K>::N, F = Dim3<K>::F;
-    const HHO_CONST R *Gt = tb + 4 * N * N;
-    const HHO_CONST R *nr = Gt + nF * N * F;
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         if (lk[j] < 0) continue;
-        const R nx = nr[3 * j], ny = nr[3 * j + 1], nz = nr[3 * j + 2];
+        const R nx = T.n(j, 0), ny = T.n(j, 1), nz = T.n(j, 2);
         R o[F];
 #pragma unroll
         for (int i = 0; i < F; ++i) o[i] = R(0);
@@ -128,7 +190,7 @@ __device__ __forceinline__ void fluid_traces3(const Bufs<R> &B, const HHO_CONST 
             const R q = tau * p[b] - nx * mx[b] - ny * my[b] - nz * mz[b];
 #pragma unroll
             for (int i = 0; i < F; ++i)
-                if (g3_nonzero(b, i)) o[i] += Gt[(j * N + b) * F + i] * q;
+                if (g3_nonzero(b, i)) o[i] += T.g(j, b, i) * q;
         }
         bstv<F, R, POL>(B.r, F * boff, B.tout + (j * 3) * F * B.rowb, o);
     }
@@ -144,16 +206,14 @@ __device__ __forceinline__ void stress_n(const R *s, int N, int b, R nx, R ny, R
     tz = sxz * nx + syz * ny + s[2 * N + b] * nz;
 }
 
-template <int K, int NF, typename R, int POL = 0>
-__device__ __forceinline__ void solid_traces3(const Bufs<R> &B, const HHO_CONST R *tb, int nF, const int *lk,
+template <int K, int NF, typename R, int POL = 0, bool PK = false>
+__device__ __forceinline__ void solid_traces3(const Bufs<R> &B, const Tab3<K, R, PK> &T, const int *lk,
                                               unsigned boff, const R *v, const R *s, R tau, R itau) {
     constexpr int N = Dim3<K>::N, F = Dim3<K>::F;
-    const HHO_CONST R *Gt = tb + 4 * N * N;
-    const HHO_CONST R *nr = Gt + nF * N * F;
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         if (lk[j] < 0) continue;
-        const R nx = nr[3 * j], ny = nr[3 * j + 1], nz = nr[3 * j + 2];
+        const R nx = T.n(j, 0), ny = T.n(j, 1), nz = T.n(j, 2);
         R o[3][F];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
@@ -167,7 +227,7 @@ __device__ __forceinline__ void solid_traces3(const Bufs<R> &B, const HHO_CONST 
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 if (!g3_nonzero(b, i)) continue;
-                const R g = Gt[(j * N + b) * F + i];
+                const R g = T.g(j, b, i);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) o[c][i] += g * q[c];
             }
@@ -184,16 +244,12 @@ __device__ __forceinline__ void solid_traces3(const Bufs<R> &B, const HHO_CONST 
 }
 
 // ------------------------------------------------------------------------- fluid cells
-template <int K, int NF, typename R, int POL>
-__device__ __forceinline__ double fluid_stage3(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
+template <int K, int NF, typename R, int POL, bool PK>
+__device__ __forceinline__ double fluid_stage3(const StageArgs<R> &a, const Bufs<R> &B, const Tab3<K, R, PK> &T, int nF,
                                                const LaneInfo &L, bool want_e) {
     constexpr int N = Dim3<K>::N, F = Dim3<K>::F;
     const int nic = a.n_ic, ic = L.ic, shot = L.shot;
     const unsigned boff = L.boff, coff = L.coff;
-    const HHO_CONST R *Bd[3] = {tb, tb + N * N, tb + 2 * N * N};
-    const HHO_CONST R *Sm = tb + 3 * N * N;
-    const HHO_CONST R *Gt = tb + 4 * N * N;
-    const HHO_CONST R *nr = Gt + nF * N * F;
     int lk[NF];
     R cc[NF];
     load_links<NF, R>(B, nF, ic, lk, cc);
@@ -212,20 +268,20 @@ __device__ __forceinline__ double fluid_stage3(const StageArgs<R> &a, const Bufs
             R sx = 0;
 #pragma unroll
             for (int b = 0; b < N; ++b) {
-                if (b3_nonzero(r, b)) sx += Bd[d][r * N + b] * p[b];
-                if (b3_nonzero(b, r)) sd += Bd[d][b * N + r] * m[d][b];
+                if (b3_nonzero(r, b)) sx += T.b(d, r, b) * p[b];
+                if (b3_nonzero(b, r)) sd += T.b(d, b, r) * m[d][b];
             }
             rm[d][r] = sx;
         }
         R st = 0;
 #pragma unroll
-        for (int b = 0; b < N; ++b) st += Sm[r * N + b] * p[b];
+        for (int b = 0; b < N; ++b) st += T.s(r, b) * p[b];
         rp[r] = -sd - tau * st;
     }
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         if (lk[j] < 0) continue;  // boundary face: p_F = 0
-        const R nx = nr[3 * j], ny = nr[3 * j + 1], nz = nr[3 * j + 2];
+        const R nx = T.n(j, 0), ny = T.n(j, 1), nz = T.n(j, 2);
         const bool itf = (lk[j] >> 3) & 1;
         R rn0[F], rn1[F], rn2[F];
         gather3<F, R>(B, a.S, shot, lk[j], 0, rn0);
@@ -241,7 +297,7 @@ __device__ __forceinline__ double fluid_stage3(const StageArgs<R> &a, const Bufs
             const R q = tau * p[b] - nx * m[0][b] - ny * m[1][b] - nz * m[2][b];
 #pragma unroll
             for (int i = 0; i < F; ++i)
-                if (g3_nonzero(b, i)) r[i] += Gt[(j * N + b) * F + i] * q;
+                if (g3_nonzero(b, i)) r[i] += T.g(j, b, i) * q;
         }
         R pF[F];
         if (!itf) {
@@ -257,7 +313,7 @@ __device__ __forceinline__ double fluid_stage3(const StageArgs<R> &a, const Bufs
             R w = 0;
 #pragma unroll
             for (int i = 0; i < F; ++i)
-                if (g3_nonzero(b, i)) w += Gt[(j * N + b) * F + i] * pF[i];
+                if (g3_nonzero(b, i)) w += T.g(j, b, i) * pF[i];
             rm[0][b] += nx * w;
             rm[1][b] += ny * w;
             rm[2][b] += nz * w;
@@ -285,7 +341,7 @@ __device__ __forceinline__ double fluid_stage3(const StageArgs<R> &a, const Bufs
         kv[3 * N + b] = irho * rm[2][b];
     }
     rk_update3<4 * N, R, POL>(a, B, boff, y, kv, nw, shot);
-    fluid_traces3<K, NF, R, POL>(B, tb, nF, lk, boff, nw, nw + N, nw + 2 * N, nw + 3 * N, tau);
+    fluid_traces3<K, NF, R, POL, PK>(B, T, lk, boff, nw, nw + N, nw + 2 * N, nw + 3 * N, tau);
     double energy = 0.0;
     if (a.last && want_e) {
         double sp = 0, sm = 0;
@@ -317,19 +373,13 @@ __device__ __forceinline__ double fluid_stage3(const StageArgs<R> &a, const Bufs
 }
 
 // ------------------------------------------------------------------------- solid cells
-template <int K, int NF, typename R, int POL>
-__device__ __forceinline__ double solid_stage3(const StageArgs<R> &a, const Bufs<R> &B, const HHO_CONST R *tb, int nF,
+template <int K, int NF, typename R, int POL, bool PK>
+__device__ __forceinline__ double solid_stage3(const StageArgs<R> &a, const Bufs<R> &B, const Tab3<K, R, PK> &T, int nF,
                                                const LaneInfo &L, bool want_e) {
     constexpr int N = Dim3<K>::N, F = Dim3<K>::F;
     const int nic = a.n_ic, ic = L.ic, shot = L.shot;
     const unsigned boff = L.boff, coff = L.coff;
     const R r2 = R(kRsqrt2);
-    const HHO_CONST R *Bx = tb;
-    const HHO_CONST R *By = tb + N * N;
-    const HHO_CONST R *Bz = tb + 2 * N * N;
-    const HHO_CONST R *Sm = tb + 3 * N * N;
-    const HHO_CONST R *Gt = tb + 4 * N * N;
-    const HHO_CONST R *nr = Gt + nF * N * F;
     int lk[NF];
     R cc[NF];
     load_links<NF, R>(B, nF, ic, lk, cc);
@@ -351,7 +401,7 @@ __device__ __forceinline__ double solid_stage3(const StageArgs<R> &a, const Bufs
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             if (b3_nonzero(r, b)) {
-                const R X = Bx[r * N + b], Y = By[r * N + b], Z = Bz[r * N + b];
+                const R X = T.b(0, r, b), Y = T.b(1, r, b), Z = T.b(2, r, b);
                 a1 += X * vx[b];
                 a2 += Y * vy[b];
                 a3 += Z * vz[b];
@@ -360,7 +410,7 @@ __device__ __forceinline__ double solid_stage3(const StageArgs<R> &a, const Bufs
                 a6 += Z * vy[b] + Y * vz[b];
             }
             if (b3_nonzero(b, r)) {
-                const R X = Bx[b * N + r], Y = By[b * N + r], Z = Bz[b * N + r];
+                const R X = T.b(0, b, r), Y = T.b(1, b, r), Z = T.b(2, b, r);
                 const R h4 = r2 * s4[b], h5 = r2 * s5[b], h6 = r2 * s6[b];
                 bx += X * s1[b] + Y * h4 + Z * h5;
                 by += X * h4 + Y * s2[b] + Z * h6;
@@ -370,7 +420,7 @@ __device__ __forceinline__ double solid_stage3(const StageArgs<R> &a, const Bufs
         R sx = 0, sy = 0, sz = 0;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            const R w = Sm[r * N + b];
+            const R w = T.s(r, b);
             sx += w * vx[b];
             sy += w * vy[b];
             sz += w * vz[b];
@@ -388,7 +438,7 @@ __device__ __forceinline__ double solid_stage3(const StageArgs<R> &a, const Bufs
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         if (lk[j] < 0) continue;  // boundary face: v_F = 0
-        const R nx = nr[3 * j], ny = nr[3 * j + 1], nz = nr[3 * j + 2];
+        const R nx = T.n(j, 0), ny = T.n(j, 1), nz = T.n(j, 2);
         const bool itf = (lk[j] >> 3) & 1;
         R rn[3][F];
         gather3<F, R>(B, a.S, shot, lk[j], 0, rn[0]);
@@ -409,7 +459,7 @@ __device__ __forceinline__ double solid_stage3(const StageArgs<R> &a, const Bufs
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 if (!g3_nonzero(b, i)) continue;
-                const R g = Gt[(j * N + b) * F + i];
+                const R g = T.g(j, b, i);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) rc[c][i] += g * q[c];
             }
@@ -436,7 +486,7 @@ __device__ __forceinline__ double solid_stage3(const StageArgs<R> &a, const Bufs
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 if (!g3_nonzero(b, i)) continue;
-                const R g = Gt[(j * N + b) * F + i];
+                const R g = T.g(j, b, i);
                 wx += g * vF[0][i];
                 wy += g * vF[1][i];
                 wz += g * vF[2][i];
@@ -485,7 +535,7 @@ __device__ __forceinline__ double solid_stage3(const StageArgs<R> &a, const Bufs
     }
     (void)l2m;
     rk_update3<9 * N, R, POL>(a, B, boff, y, kv, nw, shot);
-    solid_traces3<K, NF, R, POL>(B, tb, nF, lk, boff, nw, nw + 3 * N, tau, itau);
+    solid_traces3<K, NF, R, POL, PK>(B, T, lk, boff, nw, nw + 3 * N, tau, itau);
     double energy = 0.0;
     if (a.last && want_e) {
         const double ca = a.emat[(long long)nic + ic], cb = a.emat[(long long)2 * nic + ic];
@@ -527,10 +577,10 @@ __device__ __forceinline__ double solid_stage3(const StageArgs<R> &a, const Bufs
 
 template <int K, int NF, typename R, int POL, bool POOLED>
 __device__ __forceinline__ double stage_body3(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L, bool want_e) {
-    const HHO_CONST R *tb = class_table<POOLED>(a, G, L.ic);
+    const Tab3<K, R, POOLED> T{class_table<POOLED>(a, G, L.ic), G.nF};
     const Bufs<R> B = make_bufs(a);
-    if (G.medium == kFluid) return fluid_stage3<K, NF, R, POL>(a, B, tb, G.nF, L, want_e);
-    return solid_stage3<K, NF, R, POL>(a, B, tb, G.nF, L, want_e);
+    if (G.medium == kFluid) return fluid_stage3<K, NF, R, POL, POOLED>(a, B, T, G.nF, L, want_e);
+    return solid_stage3<K, NF, R, POL, POOLED>(a, B, T, G.nF, L, want_e);
 }
 
 // Stage launch; with pooled groups two launches over the same grid as in two dimensions.
@@ -556,7 +606,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel3(StageArgs<R> a) {
 template <int K, int NF, typename R, bool POOLED>
 __device__ __forceinline__ void traces_body3(const StageArgs<R> &a, const GroupDev &G, const LaneInfo &L) {
     constexpr int N = Dim3<K>::N;
-    const HHO_CONST R *tb = class_table<POOLED>(a, G, L.ic);
+    const Tab3<K, R, POOLED> T{class_table<POOLED>(a, G, L.ic), G.nF};
     const Bufs<R> B = make_bufs(a);
     int lk[NF];
     load_links<NF, R>(B, G.nF, L.ic, lk, (R *)nullptr);
@@ -565,13 +615,13 @@ __device__ __forceinline__ void traces_body3(const StageArgs<R> &a, const GroupD
         R y[4 * N];
 #pragma unroll
         for (int r = 0; r < 4 * N; ++r) y[r] = bld<R>(B.r, L.boff, B.yin + r * B.rowb);
-        fluid_traces3<K, NF, R>(B, tb, G.nF, lk, L.boff, y, y + N, y + 2 * N, y + 3 * N, tau);
+        fluid_traces3<K, NF, R, 0, POOLED>(B, T, lk, L.boff, y, y + N, y + 2 * N, y + 3 * N, tau);
     } else {
         const R itau = bld<R>(B.r, L.coff, B.mat + kInvTau * B.crowb);
         R y[9 * N];
 #pragma unroll
         for (int r = 0; r < 9 * N; ++r) y[r] = bld<R>(B.r, L.boff, B.yin + r * B.rowb);
-        solid_traces3<K, NF, R>(B, tb, G.nF, lk, L.boff, y, y + 3 * N, tau, itau);
+        solid_traces3<K, NF, R, 0, POOLED>(B, T, lk, L.boff, y, y + 3 * N, tau, itau);
     }
 }
 

@@ -11,10 +11,44 @@ import numpy as np
 R2 = 1.0 / np.sqrt(2.0)
 
 
-def _tables(ins, ic, nF):
+_DEG = (0, 1, 1, 1, 2, 2, 2, 2, 2, 2)
+_DEGF = (0, 1, 1, 2, 2, 2)
+
+
+def _unpack_pooled(t, off, N, F, nF):
+    """Dense tables from a pooled (packed) table: the entries of B_x, B_y, B_z with deg(b) < deg(r),
+    the upper triangle of S, the entries of G_j with deg(psi_i) <= deg(phi_a), the normals."""
+    pos = off
+    B = []
+    for _ in range(3):
+        M = np.zeros((N, N))
+        for r in range(N):
+            for b in range(N):
+                if _DEG[b] < _DEG[r]:
+                    M[r, b] = t[pos]
+                    pos += 1
+        B.append(M)
+    Sm = np.zeros((N, N))
+    for r in range(N):
+        for b in range(r, N):
+            Sm[r, b] = Sm[b, r] = t[pos]
+            pos += 1
+    G = np.zeros((nF, N, F))
+    for j in range(nF):
+        for a in range(N):
+            for i in range(F):
+                if _DEGF[i] <= _DEG[a]:
+                    G[j, a, i] = t[pos]
+                    pos += 1
+    return B, Sm, G, t[pos:pos + 3 * nF].reshape(nF, 3)
+
+
+def _tables(ins, ic, nF, pooled=False):
     N, F = ins.N, ins.F
     off = int(ins.ic_tab[ic])
     t = ins.tables
+    if pooled:
+        return _unpack_pooled(t, off, N, F, nF)
     B = [t[off + d * N * N: off + (d + 1) * N * N].reshape(N, N) for d in range(3)]
     Sm = t[off + 3 * N * N: off + 4 * N * N].reshape(N, N)
     g0 = off + 4 * N * N
@@ -39,9 +73,10 @@ def stage_derivative(ins, mesh, U):
     state, tabs, own = {}, {}, {}
     for c in range(nc):
         ic = ins.ic_of_cell[c]
-        nF = int(ins.groups[group_of_ic[ic], 1])
+        g = group_of_ic[ic]
+        nF = int(ins.groups[g, 1])
         state[ic] = U[off[c]:off[c + 1]].reshape(rows[c], N)
-        tabs[ic] = _tables(ins, ic, nF)
+        tabs[ic] = _tables(ins, ic, nF, bool(ins.pooled[g]))
     tau = ins.mat[2]
     itau = ins.mat[5]
     # outgoing contributions of every cell on its own faces

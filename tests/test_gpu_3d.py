@@ -199,18 +199,18 @@ def test_3d_rejects_two_dimensional_calls():
         assert ex.value.code == 1
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_3d_ricker_sources_and_receivers(dtype):
-    """Two shots on 4^3 cubes of tetrahedra, k = 2: shot 0 a Ricker point force in the solid,
-    shot 1 a Ricker pressure source in the fluid; two receivers per medium recording p or
-    (v_x, v_y, v_z) after every step; 60 steps from rest against the oracle driven by the same
-    point loads."""
+@pytest.mark.parametrize("case,dtype", [("tets", "f64"), ("tets", "f32"), ("hexes-prisms", "f64")])
+def test_3d_ricker_sources_and_receivers(case, dtype):
+    """Two shots on 4^3 cubes (tetrahedra, or sheared hexahedron / prism columns), k = 2: shot 0 a
+    Ricker point force in the solid, shot 1 a Ricker pressure source in the fluid; two receivers per
+    medium recording p or (v_x, v_y, v_z) after every step; 60 steps from rest against the oracle
+    driven by the same point loads."""
     from oracle.oracle3d import ricker
     from paper_2505_15771_amd import Engine
-    mesh, n = MESHES["tets"]()
+    mesh, n = MESHES[case]()
     k = 2
-    say("case: 3d tets k=2 %s, Ricker sources in both media, 4 receivers, 60 steps" % dtype)
-    o = oracle3d(mesh, k, key="tets")
+    say("case: 3d %s k=2 %s, Ricker sources in both media, 4 receivers, 60 steps" % (case, dtype))
+    o = oracle3d(mesh, k, key=case)
     dt = dt_for(mesh, n, k)
     f0, t0, amp = 10.0, 0.12, 1.0
     src = [(np.array([0.41, 0.36, 0.29]), np.array([0.3, -0.2, 1.0])),
