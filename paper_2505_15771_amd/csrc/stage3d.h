@@ -122,44 +122,86 @@ __device__ __forceinline__ void load_state3(const StageArgs<R> &a, const Bufs<R>
 
 // Runge-Kutta combine (eq. ERK) in the increment form of the two-dimensional stage: before the
 // last stage D_i = cY D_{i-1} + ck dt k_i (and the partial sum Q), on the last stage
-// U^{n+1} = U^n + Q + cd D_{s-2} + cb dt k_s.  U^n and D_{i-1} are read again (cache hits).
-template <int ND, typename R, int POL>
+// U^{n+1} = U^n + Q + cd D_{s-2} + cb dt k_s.  CHUNKED (launches with shared tables): U^n is read
+// again in every stage, the first included, so that the stage input is not held in registers
+// through the residual, and the rows are combined a third (solid) or a quarter (fluid) at a
+// time, so that at most that share of U^n, D_{i-1} and Q is in registers at once beside k_i.
+// Otherwise (pooled launches, one wave per SIMD, where the loads of later chunks would wait
+// behind the stores of earlier ones) every row at once, U^n taken from the stage input y on the
+// first stage.
+template <int ND, typename R, int POL, bool CHUNKED>
 __device__ __forceinline__ void rk_update3(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, const R *y,
                                            const R *kv, R *out, int shot) {
     const R dt = R(shot_dt(a, shot));
-    R u[ND], din[ND];
-    if (a.first) {
+    if constexpr (!CHUNKED) {
+        R u[ND], din[ND];
+        if (a.first) {
 #pragma unroll
-        for (int r = 0; r < ND; ++r) {
-            u[r] = y[r];
-            din[r] = R(0);
+            for (int r = 0; r < ND; ++r) {
+                u[r] = y[r];
+                din[r] = R(0);
+            }
+        } else {
+            const bool need_d = a.last ? a.cd != R(0) : (a.cY != R(0) || a.q_write);
+#pragma unroll
+            for (int r = 0; r < ND; ++r) {
+                u[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
+                din[r] = need_d ? bld<R>(B.r, boff, B.yin + r * B.rowb) : R(0);
+            }
+        }
+        if (!a.last) {
+            const R ckdt = a.ck * dt;
+#pragma unroll
+            for (int r = 0; r < ND; ++r) {
+                const R d = a.cY * din[r] + ckdt * kv[r];
+                bst<POL>(B.r, boff, B.yout + r * B.rowb, d);
+                if (a.q_write) bst<POL>(B.r, boff, B.yq + r * B.rowb, a.qa * din[r] + a.qb * d);
+                out[r] = u[r] + d;
+            }
+        } else {
+            R q[ND];
+#pragma unroll
+            for (int r = 0; r < ND; ++r) q[r] = a.q_read ? bld<R>(B.r, boff, B.yq + r * B.rowb) : R(0);
+            const R cb = a.cb * dt;
+#pragma unroll
+            for (int r = 0; r < ND; ++r) {
+                out[r] = u[r] + (q[r] + a.cd * din[r] + cb * kv[r]);
+                bst<POL>(B.r, boff, B.u + r * B.rowb, out[r]);
+            }
         }
     } else {
-        const bool need_d = a.last ? a.cd != R(0) : (a.cY != R(0) || a.q_write);
+        const bool need_d = !a.first && (a.last ? a.cd != R(0) : (a.cY != R(0) || a.q_write));
+        constexpr int CH = ND % 3 == 0 ? ND / 3 : ND / 4;
+        static_assert(ND % CH == 0, "whole chunks");
 #pragma unroll
-        for (int r = 0; r < ND; ++r) {
-            u[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
-            din[r] = need_d ? bld<R>(B.r, boff, B.yin + r * B.rowb) : R(0);
-        }
-    }
-    if (!a.last) {
-        const R ckdt = a.ck * dt;
+        for (int c0 = 0; c0 < ND; c0 += CH) {
+            R u[CH], din[CH];
 #pragma unroll
-        for (int r = 0; r < ND; ++r) {
-            const R d = a.cY * din[r] + ckdt * kv[r];
-            bst<POL>(B.r, boff, B.yout + r * B.rowb, d);
-            if (a.q_write) bst<POL>(B.r, boff, B.yq + r * B.rowb, a.qa * din[r] + a.qb * d);
-            out[r] = u[r] + d;
-        }
-    } else {
-        R q[ND];
+            for (int r = 0; r < CH; ++r) {
+                u[r] = bld<R>(B.r, boff, B.u + (c0 + r) * B.rowb);
+                din[r] = need_d ? bld<R>(B.r, boff, B.yin + (c0 + r) * B.rowb) : R(0);
+            }
+            if (!a.last) {
+                const R ckdt = a.ck * dt;
 #pragma unroll
-        for (int r = 0; r < ND; ++r) q[r] = a.q_read ? bld<R>(B.r, boff, B.yq + r * B.rowb) : R(0);
-        const R cb = a.cb * dt;
+                for (int r = 0; r < CH; ++r) {
+                    const R d = a.cY * din[r] + ckdt * kv[c0 + r];
+                    bst<POL>(B.r, boff, B.yout + (c0 + r) * B.rowb, d);
+                    if (a.q_write) bst<POL>(B.r, boff, B.yq + (c0 + r) * B.rowb, a.qa * din[r] + a.qb * d);
+                    out[c0 + r] = u[r] + d;
+                }
+            } else {
+                R q[CH];
 #pragma unroll
-        for (int r = 0; r < ND; ++r) {
-            out[r] = u[r] + (q[r] + a.cd * din[r] + cb * kv[r]);
-            bst<POL>(B.r, boff, B.u + r * B.rowb, out[r]);
+                for (int r = 0; r < CH; ++r)
+                    q[r] = a.q_read ? bld<R>(B.r, boff, B.yq + (c0 + r) * B.rowb) : R(0);
+                const R cb = a.cb * dt;
+#pragma unroll
+                for (int r = 0; r < CH; ++r) {
+                    out[c0 + r] = u[r] + (q[r] + a.cd * din[r] + cb * kv[c0 + r]);
+                    bst<POL>(B.r, boff, B.u + (c0 + r) * B.rowb, out[c0 + r]);
+                }
+            }
         }
     }
 }
@@ -340,7 +382,7 @@ __device__ __forceinline__ double fluid_stage3(const StageArgs<R> &a, const Bufs
         kv[2 * N + b] = irho * rm[1][b];
         kv[3 * N + b] = irho * rm[2][b];
     }
-    rk_update3<4 * N, R, POL>(a, B, boff, y, kv, nw, shot);
+    rk_update3<4 * N, R, POL, !PK>(a, B, boff, y, kv, nw, shot);
     fluid_traces3<K, NF, R, POL, PK>(B, T, lk, boff, nw, nw + N, nw + 2 * N, nw + 3 * N, tau);
     double energy = 0.0;
     if (a.last && want_e) {
@@ -534,7 +576,7 @@ __device__ __forceinline__ double solid_stage3(const StageArgs<R> &a, const Bufs
         kv[8 * N + b] = tmu * rs[5][b];
     }
     (void)l2m;
-    rk_update3<9 * N, R, POL>(a, B, boff, y, kv, nw, shot);
+    rk_update3<9 * N, R, POL, !PK>(a, B, boff, y, kv, nw, shot);
     solid_traces3<K, NF, R, POL, PK>(B, T, lk, boff, nw, nw + 3 * N, tau, itau);
     double energy = 0.0;
     if (a.last && want_e) {
@@ -584,8 +626,8 @@ __device__ __forceinline__ double stage_body3(const StageArgs<R> &a, const Group
 }
 
 // Stage launch; with pooled groups two launches over the same grid as in two dimensions.
-template <int K, typename R, int POL, bool POOLED = false>
-__global__ __launch_bounds__(kBlock) void stage_kernel3(StageArgs<R> a) {
+template <int K, typename R, int POL, bool POOLED>
+__device__ __forceinline__ void stage_entry3(const StageArgs<R> &a) {
     if ((!POOLED || a.all_pooled) && a.last && a.clock_next && blockIdx.x == 0 && threadIdx.x == 0) {
         Clock c = *a.clock;
         c.step += 1;
@@ -601,6 +643,18 @@ __global__ __launch_bounds__(kBlock) void stage_kernel3(StageArgs<R> a) {
         else e = stage_body3<K, 6, R, POL, POOLED>(a, G, L, want_e);
     }
     if (want_e) block_energy(e, a.S, a.cpb, energy_slot(a));
+}
+
+template <int K, typename R, int POL, bool POOLED = false>
+__global__ __launch_bounds__(kBlock) void stage_kernel3(StageArgs<R> a) {
+    stage_entry3<K, R, POL, POOLED>(a);
+}
+
+// The same stage with a lane's registers (VGPRs and AGPRs together) capped at 256, so that two
+// waves share a SIMD.
+template <int K, typename R, int POL, bool POOLED = false>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void stage_kernel3_w2(StageArgs<R> a) {
+    stage_entry3<K, R, POL, POOLED>(a);
 }
 
 template <int K, int NF, typename R, bool POOLED>
@@ -675,14 +729,23 @@ __global__ __launch_bounds__(kBlock) void energy_kernel3(StageArgs<R> a) {
 
 template <int K, typename R>
 hipError_t launch_stage3(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
+    const dim3 grid(n_blocks), block(a.cpb * a.S);
+    // float32 shared-table launches capped at two waves per SIMD; pooled launches (per-lane tables
+    // in vector registers) and float64 uncapped, where the cap would spill
     if (!a.all_pooled) {
-        if (a.nt_stores)
-            hipLaunchKernelGGL((stage_kernel3<K, R, kNonTemporal>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
-        else
-            hipLaunchKernelGGL((stage_kernel3<K, R, 0>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+        if constexpr (sizeof(R) == 4) {
+            if (a.nt_stores)
+                hipLaunchKernelGGL((stage_kernel3_w2<K, R, kNonTemporal>), grid, block, 0, st, a);
+            else
+                hipLaunchKernelGGL((stage_kernel3_w2<K, R, 0>), grid, block, 0, st, a);
+        } else {
+            if (a.nt_stores)
+                hipLaunchKernelGGL((stage_kernel3<K, R, kNonTemporal>), grid, block, 0, st, a);
+            else
+                hipLaunchKernelGGL((stage_kernel3<K, R, 0>), grid, block, 0, st, a);
+        }
     }
-    if (a.has_pooled)
-        hipLaunchKernelGGL((stage_kernel3<K, R, 0, true>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+    if (a.has_pooled) hipLaunchKernelGGL((stage_kernel3<K, R, 0, true>), grid, block, 0, st, a);
     return hipGetLastError();
 }
 
