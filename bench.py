@@ -725,8 +725,8 @@ def copy_bandwidth(mib=1024, reps=20):
 # over the step's dispatches, each counter scaled by what it reads for an elementwise kernel of
 # known size; valid only for the kernel and host-plan sources with this digest (else null).
 MEASURED_BATCH_TRAFFIC = {
-    "sources_sha256": "11b728f59e0ca49677eb5e04652c90f023dd168761a2c0235b83be96e15330a6",
-    "bytes_per_step": 15502273638,   # FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, 512 dispatches / 8 steps
+    "sources_sha256": "c4b2eecc720d3b99f15dc6657cfa7e485e62b6e3497504ad12ea62f72fcb572e",
+    "bytes_per_step": 15368154752,   # FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, 512 dispatches / 8 steps
 }
 
 
@@ -914,17 +914,17 @@ def summary_line(steps, warmup, head, err, f64_ms, cpu, variants, extras, copy_g
                                "graphs, float64 energy per shot and step" % head["cells"],
                    "shot_dofs": head["shot_dofs"], "meshes": 16, "shots_per_mesh": 4,
                    "path": "graph replays (32/16/8/4/2/1-step graphs)"},
-        "roofline": {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "roofline": {"bound": "hbm", "achieved": round(head["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": head["frac"], "traffic": traffic, "kernel": "stage_kernel (every launch of a step)",
-                     "bytes_per_step": head["bytes_per_step"], "device_us_per_step": head["device_ms_per_step"] * 1e3,
-                     "traffic_unit": "HBM bytes per step", "copy_gbs": copy_gbs,
-                     "frac_of_copy": head["gbs"] / copy_gbs},
+                     "bytes_per_step": head["bytes_per_step"], "device_us_per_step": round(head["device_ms_per_step"] * 1e3, 1),
+                     "traffic_unit": "HBM bytes per step", "copy_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(head["gbs"] / copy_gbs, 4)},
         "cpu_baseline": cpu,
-        "rel_err_vs_oracle": None if err is None else {"max": max(err), "mean": float(np.mean(err)), "steps": 3,
+        "rel_err_vs_oracle": None if err is None else {"max": float("%.3g" % max(err)), "mean": float("%.3g" % np.mean(err)), "steps": 3,
                                                        "what": "shot 0 of each mesh, random state + source"},
         "f64_single_shot_ms_per_step": f64_ms,
         "speedup_vs_f64_single_shot": f64_ms / head["ms_per_step"],
-        "variants": variants,
+        "variants": {"workload": "256x256 hybrid mesh", "runs": variants},
         "extras": extras,
     }
     return json.dumps(out)
@@ -1022,9 +1022,8 @@ def main():
                              (3, "f32", 8)):
             v = run_variant(mesh, k, dt_, sh, max(min(args.steps, 400), 10), 5)
             _log("variant", v)
-            variants.append(dict(workload="256x256 hybrid", k=k, dtype=dt_, shots=sh,
-                                 value=round(v["value"], -6), us_per_step=round(v["ms_per_step"] * 1e3, 2),
-                                 launch_us=round(v["launch_us"], 2), frac=round(v["frac"], 3)))
+            variants.append(dict(k=k, dtype=dt_, shots=sh, us_per_step=round(v["ms_per_step"] * 1e3, 2),
+                                 frac=round(v["frac"], 3)))
 
     # ---- other workloads: one stderr line each, a few figures kept in the summary
     extras = {}
@@ -1052,9 +1051,7 @@ def main():
                                         (32, 1, "f32", 1, "moved")):
             v = run_3d(n_, k_, dt_, sh_, 200, 5, kind=kd_)
             _log("workload", v)
-            extras["cube3d_%s_k%d_%s_%dshot" % (kd_, k_, dt_, sh_)] = dict(cells=v["cells"],
-                                                                            us_per_step=round(v["ms_per_step"] * 1e3, 1),
-                                                                            value=round(v["value"], -6),
+            extras["cube3d_%s_k%d_%s_%dshot" % (kd_, k_, dt_, sh_)] = dict(us_per_step=round(v["ms_per_step"] * 1e3, 1),
                                                                             frac=round(v["frac"], 3))
         for k_ in (1, 2, 3):
             _log("workload", run_cfl(k_))

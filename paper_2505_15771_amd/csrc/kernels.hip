@@ -36,22 +36,30 @@ namespace {
 
 // Register budget of the stage kernel: the least number of waves per SIMD the compiler must leave
 // room for, per degree k = 1, 2, 3 (4 waves leave 128 VGPRs per lane, 3 leave 168, 2 leave 256;
-// 1 sets no budget), for float32 and float64 stepping.
+// 1 sets no budget), for float32 and float64 stepping.  It applies to the plain stage launches
+// (shared tables, no recompute stores); a float64 launch with a budget of two waves also
+// combines its rows in chunks (rk_update), which is what brings it within 256 registers.
 #ifndef HHO_STAGE_WAVES_F32
 #define HHO_STAGE_WAVES_F32 1, 1, 1
 #endif
 #ifndef HHO_STAGE_WAVES_F64
-#define HHO_STAGE_WAVES_F64 1, 1, 1
+#define HHO_STAGE_WAVES_F64 1, 2, 1
 #endif
 // Highest degree whose float32 stage keeps U^n and D_{i-1} in registers for the combine (float64:
 // k = 1 only); the others read them again (cache hits), which costs fewer registers.
 #ifndef HHO_KEEP_MAX_K_F32
 #define HHO_KEEP_MAX_K_F32 2
 #endif
-template <int K, typename R>
+template <int K, typename R, bool STORE = false, bool POOLED = false>
 constexpr int stage_waves() {
     constexpr int w32[3] = {HHO_STAGE_WAVES_F32}, w64[3] = {HHO_STAGE_WAVES_F64};
+    if (STORE || POOLED) return 1;
     return sizeof(R) == 4 ? w32[K - 1] : w64[K - 1];
+}
+// float64 plain launches under a two-wave budget combine their rows in chunks
+template <int K, typename R, bool STORE, bool POOLED>
+constexpr bool chunked_combine() {
+    return sizeof(R) == 8 && stage_waves<K, R, STORE, POOLED>() >= 2;
 }
 template <int K, typename R>
 constexpr bool keep_in_registers() {
@@ -107,9 +115,49 @@ __device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> 
 // residual.  out = the new stage state (Y_{i+1} or U^{n+1}), from which the outgoing traces are
 // formed.  Every load is issued before the first store: the arrays share one buffer resource,
 // so the compiler cannot move a load above an earlier store.
-template <int ND, typename R, bool KEEP, int POL>
+template <int ND, typename R, bool KEEP, int POL, bool CHUNK = false>
 __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, const R *y,
                                           const R *kv, R *out, const R *uk, const R *dk, int shot) {
+    if constexpr (CHUNK) {
+        // U^n read again on every stage (the stage input y is not kept for the first one) and the
+        // rows combined a fifth (or a third) at a time, so that only that share of U^n, D_{i-1}
+        // and Q is in registers beside k_i
+        const R dt = R(shot_dt(a, shot));
+        const bool need_d = !a.first && (a.last ? a.cd != R(0) : (a.cY != R(0) || a.q_write));
+        constexpr int CH = ND % 5 == 0 ? ND / 5 : ND / 3;
+        static_assert(ND % CH == 0, "whole chunks");
+#pragma unroll
+        for (int c0 = 0; c0 < ND; c0 += CH) {
+            R u[CH], din[CH];
+#pragma unroll
+            for (int r = 0; r < CH; ++r) {
+                u[r] = bld<R>(B.r, boff, B.u + (c0 + r) * B.rowb);
+                din[r] = need_d ? bld<R>(B.r, boff, B.yin + (c0 + r) * B.rowb) : R(0);
+            }
+            if (!a.last) {
+                const R ckdt = a.ck * dt;
+#pragma unroll
+                for (int r = 0; r < CH; ++r) {
+                    const R d = a.cY * din[r] + ckdt * kv[c0 + r];
+                    bst<POL>(B.r, boff, B.yout + (c0 + r) * B.rowb, d);
+                    if (a.q_write) bst<POL>(B.r, boff, B.yq + (c0 + r) * B.rowb, a.qa * din[r] + a.qb * d);
+                    out[c0 + r] = u[r] + d;
+                }
+            } else {
+                R q[CH];
+#pragma unroll
+                for (int r = 0; r < CH; ++r)
+                    q[r] = a.q_read ? bld<R>(B.r, boff, B.yq + (c0 + r) * B.rowb) : R(0);
+                const R cb = a.cb * dt;
+#pragma unroll
+                for (int r = 0; r < CH; ++r) {
+                    out[c0 + r] = u[r] + (q[r] + a.cd * din[r] + cb * kv[c0 + r]);
+                    bst<POL>(B.r, boff, B.u + (c0 + r) * B.rowb, out[c0 + r]);
+                }
+            }
+        }
+        return;
+    }
     const R dt = R(shot_dt(a, shot));
     R u[ND], din[ND];
     const bool need_d = a.last ? a.cd != R(0) : (a.cY != R(0) || a.q_write);
@@ -294,7 +342,7 @@ __device__ __forceinline__ double fluid_stage(const StageArgs<R> &a, const Bufs<
         kv[N + b] = irho * rmx[b];
         kv[2 * N + b] = irho * rmy[b];
     }
-    rk_update<3 * N, R, KEEP, POL>(a, B, boff, y, kv, nw, uk, dk, shot);
+    rk_update<3 * N, R, KEEP, POL, chunked_combine<K, R, STORE, PK>()>(a, B, boff, y, kv, nw, uk, dk, shot);
     const R *np = nw, *nmx = nw + N, *nmy = nw + 2 * N;
     if (STORE) store_recompute<K, NF, 3 * N, R, NF, 1>(a, lk, boff, y, kv, fv);
     fluid_traces<K, NF, R, POL, PK>(a, B, T, lk, boff, np, nmx, nmy, tau);
@@ -477,7 +525,7 @@ __device__ __forceinline__ double solid_stage(const StageArgs<R> &a, const Bufs<
         kv[3 * N + b] = lam * rs1[b] + l2m * rs2[b];
         kv[4 * N + b] = tmu * rs3[b];
     }
-    rk_update<5 * N, R, KEEP, POL>(a, B, boff, y, kv, nw, uk, dk, shot);
+    rk_update<5 * N, R, KEEP, POL, chunked_combine<K, R, STORE, PK>()>(a, B, boff, y, kv, nw, uk, dk, shot);
     const R *nvx = nw, *nvy = nw + N, *ns1 = nw + 2 * N, *ns2 = nw + 3 * N, *ns3 = nw + 4 * N;
     if (STORE) store_recompute<K, NF, 5 * N, R, NF, 2>(a, lk, boff, y, kv, fv);
     solid_traces<K, NF, R, POL, PK>(a, B, T, lk, boff, nvx, nvy, ns1, ns2, ns3, tau, itau);
@@ -531,7 +579,7 @@ __device__ __forceinline__ double stage_body(const StageArgs<R> &a, const GroupD
 // workgroup of a launch whose group is of the other kind returns at once.  When every group is
 // pooled only the pooled launch runs, and it advances the clock.
 template <int K, typename R, bool STORE, int POL, bool POOLED = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(stage_waves<K, R>(), 8))) void stage_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(stage_waves<K, R, STORE, POOLED>(), 8))) void stage_kernel(
     StageArgs<R> a) {
     if ((!POOLED || a.all_pooled) && a.last && a.clock_next && blockIdx.x == 0 && threadIdx.x == 0) {
         Clock c = *a.clock;
