@@ -725,8 +725,8 @@ def copy_bandwidth(mib=1024, reps=20):
 # over the step's dispatches, each counter scaled by what it reads for an elementwise kernel of
 # known size; valid only for the kernel and host-plan sources with this digest (else null).
 MEASURED_BATCH_TRAFFIC = {
-    "sources_sha256": "c4b2eecc720d3b99f15dc6657cfa7e485e62b6e3497504ad12ea62f72fcb572e",
-    "bytes_per_step": 15368154752,   # FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, 512 dispatches / 8 steps
+    "sources_sha256": "cd1ec4e5494d0616d238def7cbd6035d035fb10730c2bc583c911d559283bc85",
+    "bytes_per_step": 14783531251,   # FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, 512 dispatches / 8 steps
 }
 
 

@@ -65,6 +65,18 @@ template <int K, typename R>
 constexpr bool keep_in_registers() {
     return sizeof(R) == 4 ? K <= HHO_KEEP_MAX_K_F32 : K <= 1;
 }
+// float32 k = 3 plain launches park D_{i-1} in LDS between the stage's first read and the combine
+// (their registers do not hold it, and read again from memory it misses the L2); one row of
+// blockDim floats per unknown row, each lane reading back only what it wrote
+template <int K, typename R, bool STORE, bool POOLED>
+constexpr bool lds_increment() {
+    return sizeof(R) == 4 && K == 3 && !STORE && !POOLED && !keep_in_registers<K, R>();
+}
+template <int K, typename R>
+constexpr size_t lds_increment_bytes(int lanes) {
+    return lds_increment<K, R, false, false>() ? (size_t)lanes * 5 * Dim<K>::N * sizeof(R) : 0;
+}
+extern __shared__ unsigned char hho_stage_lds[];
 
 // Stage state of one lane.  The stage buffers hold increments D_i = Y_{i+1} - U^n rather than
 // the stage states: the stage input is Y_i = U^n + D_{i-1} (U^n itself on the first stage).
@@ -72,7 +84,7 @@ constexpr bool keep_in_registers() {
 // relative precision in float32 (a stored Y_i would round away the low bits of dt k_i).
 // With KEEP, U^n and D_{i-1} stay in registers (uk, dk) for the combine; otherwise the combine
 // reads them again (cache hits), which keeps the register count of the larger degrees down.
-template <int ND, typename R, bool KEEP>
+template <int ND, typename R, bool KEEP, bool LDSD = false>
 __device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, R *y, R *uk,
                                            R *dk) {
     if (a.first) {
@@ -94,6 +106,11 @@ __device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> 
         }
 #pragma unroll
         for (int r = 0; r < ND; ++r) y[r] = u[r] + d[r];
+        if (LDSD) {
+            R *dl = reinterpret_cast<R *>(hho_stage_lds);
+#pragma unroll
+            for (int r = 0; r < ND; ++r) dl[r * blockDim.x + threadIdx.x] = d[r];
+        }
         if (KEEP) {
 #pragma unroll
             for (int r = 0; r < ND; ++r) {
@@ -115,7 +132,7 @@ __device__ __forceinline__ void load_state(const StageArgs<R> &a, const Bufs<R> 
 // residual.  out = the new stage state (Y_{i+1} or U^{n+1}), from which the outgoing traces are
 // formed.  Every load is issued before the first store: the arrays share one buffer resource,
 // so the compiler cannot move a load above an earlier store.
-template <int ND, typename R, bool KEEP, int POL, bool CHUNK = false>
+template <int ND, typename R, bool KEEP, int POL, bool CHUNK = false, bool LDSD = false>
 __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &B, unsigned boff, const R *y,
                                           const R *kv, R *out, const R *uk, const R *dk, int shot) {
     if constexpr (CHUNK) {
@@ -174,10 +191,11 @@ __device__ __forceinline__ void rk_update(const StageArgs<R> &a, const Bufs<R> &
             din[r] = R(0);
         }
     } else if (need_d) {
+        const R *dl = reinterpret_cast<const R *>(hho_stage_lds);
 #pragma unroll
         for (int r = 0; r < ND; ++r) {
             u[r] = bld<R>(B.r, boff, B.u + r * B.rowb);
-            din[r] = bld<R>(B.r, boff, B.yin + r * B.rowb);
+            din[r] = LDSD ? dl[r * blockDim.x + threadIdx.x] : bld<R>(B.r, boff, B.yin + r * B.rowb);
         }
     } else {
 #pragma unroll
@@ -248,7 +266,7 @@ __device__ __forceinline__ double fluid_stage(const StageArgs<R> &a, const Bufs<
     load_links<NF, R>(B, nF, ic, lk, cc);
     constexpr bool KEEP = keep_in_registers<K, R>();
     R y[3 * N], uk[KEEP ? 3 * N : 1], dk[KEEP ? 3 * N : 1];
-    load_state<3 * N, R, KEEP>(a, B, boff, y, uk, dk);
+    load_state<3 * N, R, KEEP, lds_increment<K, R, STORE, PK>()>(a, B, boff, y, uk, dk);
     const R *p = y, *mx = y + N, *my = y + 2 * N;
     load_incoming<K, NF, R>(B, kFluid, a.S, shot, lk, rn);
     const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
@@ -342,7 +360,8 @@ __device__ __forceinline__ double fluid_stage(const StageArgs<R> &a, const Bufs<
         kv[N + b] = irho * rmx[b];
         kv[2 * N + b] = irho * rmy[b];
     }
-    rk_update<3 * N, R, KEEP, POL, chunked_combine<K, R, STORE, PK>()>(a, B, boff, y, kv, nw, uk, dk, shot);
+    rk_update<3 * N, R, KEEP, POL, chunked_combine<K, R, STORE, PK>(), lds_increment<K, R, STORE, PK>()>(
+        a, B, boff, y, kv, nw, uk, dk, shot);
     const R *np = nw, *nmx = nw + N, *nmy = nw + 2 * N;
     if (STORE) store_recompute<K, NF, 3 * N, R, NF, 1>(a, lk, boff, y, kv, fv);
     fluid_traces<K, NF, R, POL, PK>(a, B, T, lk, boff, np, nmx, nmy, tau);
@@ -390,7 +409,7 @@ __device__ __forceinline__ double solid_stage(const StageArgs<R> &a, const Bufs<
     load_links<NF, R>(B, nF, ic, lk, cc);
     constexpr bool KEEP = keep_in_registers<K, R>();
     R y[5 * N], uk[KEEP ? 5 * N : 1], dk[KEEP ? 5 * N : 1];
-    load_state<5 * N, R, KEEP>(a, B, boff, y, uk, dk);
+    load_state<5 * N, R, KEEP, lds_increment<K, R, STORE, PK>()>(a, B, boff, y, uk, dk);
     const R *vx = y, *vy = y + N, *s1 = y + 2 * N, *s2 = y + 3 * N, *s3 = y + 4 * N;
     load_incoming<K, NF, R>(B, kSolid, a.S, shot, lk, rn);
     const R tau = bld<R>(B.r, coff, B.mat + kTau * B.crowb);
@@ -525,7 +544,8 @@ __device__ __forceinline__ double solid_stage(const StageArgs<R> &a, const Bufs<
         kv[3 * N + b] = lam * rs1[b] + l2m * rs2[b];
         kv[4 * N + b] = tmu * rs3[b];
     }
-    rk_update<5 * N, R, KEEP, POL, chunked_combine<K, R, STORE, PK>()>(a, B, boff, y, kv, nw, uk, dk, shot);
+    rk_update<5 * N, R, KEEP, POL, chunked_combine<K, R, STORE, PK>(), lds_increment<K, R, STORE, PK>()>(
+        a, B, boff, y, kv, nw, uk, dk, shot);
     const R *nvx = nw, *nvy = nw + N, *ns1 = nw + 2 * N, *ns2 = nw + 3 * N, *ns3 = nw + 4 * N;
     if (STORE) store_recompute<K, NF, 5 * N, R, NF, 2>(a, lk, boff, y, kv, fv);
     solid_traces<K, NF, R, POL, PK>(a, B, T, lk, boff, nvx, nvy, ns1, ns2, ns3, tau, itau);
@@ -745,10 +765,11 @@ hipError_t launch_stage(const StageArgs<R> &a, int n_blocks, hipStream_t st) {
         else return hipErrorNotSupported;
     }
     if (!a.all_pooled) {
+        const size_t lds = lds_increment_bytes<K, R>(a.cpb * a.S);
         if (a.nt_stores)
-            hipLaunchKernelGGL((stage_kernel<K, R, false, kNonTemporal>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+            hipLaunchKernelGGL((stage_kernel<K, R, false, kNonTemporal>), dim3(n_blocks), dim3(a.cpb * a.S), lds, st, a);
         else
-            hipLaunchKernelGGL((stage_kernel<K, R, false, 0>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
+            hipLaunchKernelGGL((stage_kernel<K, R, false, 0>), dim3(n_blocks), dim3(a.cpb * a.S), lds, st, a);
     }
     if (a.has_pooled)
         hipLaunchKernelGGL((stage_kernel<K, R, false, 0, true>), dim3(n_blocks), dim3(a.cpb * a.S), 0, st, a);
