@@ -202,16 +202,18 @@ def test_five_shots_every_launch_shape(lanes):
         assert err < 1e-12
 
 
+@pytest.mark.parametrize("k", [2, 3])
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
-def test_every_tuning_combination(dtype, tol):
-    """Every launch shape with both store policies gives the oracle's state and energy;
+def test_every_tuning_combination(dtype, tol, k):
+    """Every launch shape with both store policies gives the oracle's state and energy (k = 3 in
+    float32 keeps D_{i-1} in LDS sized by the workgroup, k = 2 in float64 combines in chunks);
     hho_get_tuning reports what hho_set_tuning set, and unknown flag bits are rejected."""
     from oracle import Oracle
     from paper_2505_15771_amd import Engine, HHOError
     mesh = M.with_materials(M.unit_square(30, p_split=0.5, seed=31), perturb=0.1, seed=32)
-    o = Oracle(mesh, 2)
+    o = Oracle(mesh, k)
     U0 = np.random.default_rng(950).standard_normal(o.ndof)
-    e = Engine(mesh, 2, dtype=dtype, record_energy=True)
+    e = Engine(mesh, k, dtype=dtype, record_energy=True)
     dt = e.dt_cfl(0.5)
     ref = o.erk(U0, 0.0, dt, 6)
     E_ref = o.energy(ref)
@@ -219,7 +221,7 @@ def test_every_tuning_combination(dtype, tol):
         e.set_tuning(64, 2)
     for lanes in (64, 128, 256):
         for flags in range(2):
-            say("case: %s, %d lanes, flags %d" % (dtype, lanes, flags))
+            say("case: k=%d %s, %d lanes, flags %d" % (k, dtype, lanes, flags))
             e.set_tuning(lanes, flags)
             assert e.tuning() == (lanes, flags)
             e.set_state(U0)
