@@ -164,6 +164,7 @@ def run_3d(n, k, dtype, shots, steps, warmup, kind="tets"):
         e.set_state(M.random_state(e.n_dof, 7100 + sh), shot=sh)
     e.autotune()
     dt = (0.1 if k == 1 else 0.05) / n / M.max_wave_speed3d(mesh) * (0.6 if kind == "moved" else 1.0)
+    e.reserve_steps(max(steps, warmup))  # histories sized before the graphs are captured
     e.erk_step(0.0, dt, warmup)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -199,6 +200,7 @@ def run_variant(mesh, k, dtype, shots, steps, warmup):
     eng.autotune()  # launch shape and store cache policy (outside the timed region)
     h = 1.0 / 256
     dt = 0.5 * min(CFL_SQUARE[k], CFL_TRI[k]) * h / M.max_wave_speed(mesh)
+    eng.reserve_steps(max(steps, warmup))  # histories sized before the graphs are captured
     eng.erk_step(0.0, dt, warmup)
     eng.synchronize()
     torch.cuda.synchronize()
@@ -282,6 +284,7 @@ def run_basin(dtype, steps=100, warmup=5):
                       np.ones(64, np.int32))
     dt = eng.dt_cfl(0.5)
     eng.autotune()
+    eng.reserve_steps(max(steps, warmup))  # histories sized before the graphs are captured
     eng.erk_step(0.0, dt, warmup)
     eng.synchronize()
     st = torch.cuda.current_stream()
@@ -350,6 +353,7 @@ def run_perturbed(k=2, dtype="f32", steps=200, n=256):
         e.set_state(1e-3 * np.random.default_rng(7).standard_normal(e.n_dof))
         e.autotune()
         dt = 0.3 * e.dt_cfl(1.0)
+        e.reserve_steps(max(steps, 20))
         e.erk_step(0.0, dt, 20)
         e.synchronize()
         st = torch.cuda.current_stream()
@@ -763,6 +767,7 @@ def run_headline(steps, warmup):
     bstep = sum(algorithmic_bytes_per_step(m, k, 4, 4)[0] for m, k in meshes)
     b = Batch(engines)
     setup_s = time.perf_counter() - t_setup
+    b.reserve_steps(max(steps, warmup, 1))  # histories sized for the timed call: no re-capture in it
     b.erk_step([0.0] * len(engines), dts, max(warmup, 1))  # captures the step graphs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -793,6 +798,7 @@ def run_headline_f64_single(meshes, dts, steps):
         e = Engine(mesh, k, dtype="f64", n_shots=1, record_energy=True)
         e.set_sources(0, [M.shot_positions(4, 4100 + i)[0]], [[0.0, 1.0]], 10.0, 0.12, 1.0)
         e.autotune()
+        e.reserve_steps(max(steps, 4))
         e.erk_step(0.0, dt, 4)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -211,6 +211,13 @@ hho_status hho_receivers(hho_ctx *ctx, int32_t n, const double *xy, const int32_
  * the previous step, or is not finite. */
 hho_status hho_erk_step(hho_ctx *ctx, double t0, double dt, int32_t n_steps);
 
+/* Size the per-call histories of ctx (receiver rows, energies when record_energy = 1) for calls
+ * of up to n_steps steps.  A call longer than every earlier one grows them itself, and with them
+ * the captured graphs are captured again inside that call; reserving first moves that work out of
+ * a timed or latency-sensitive call.  Allocates device and pinned host memory (ERR_DEVICE when
+ * that fails); changes no state; ARG for n_steps < 0. */
+hho_status hho_reserve_steps(hho_ctx *ctx, int32_t n_steps);
+
 /* Wait for all work enqueued by ctx. */
 hho_status hho_synchronize(hho_ctx *ctx);
 

@@ -507,7 +507,9 @@ hho_status autotune_shape(hho_ctx *ctx);
 // Common start of a stepping call: output capacities, device clock, initial energy, traces.
 // With defer, the initial energies are only enqueued (into ctx->h_e0): the caller synchronises
 // the context's stream and reads them with read_initial_energy.
-hho_status begin_steps(hho_ctx *ctx, double t0, double dt, int n_steps, std::vector<double> &E0, bool defer = false) {
+// Per-call histories (receiver rows, energies) sized for calls of up to n_steps steps; growing a
+// device buffer bumps the context version, so that the graphs are captured again with it.
+hho_status reserve_steps(hho_ctx *ctx, int n_steps) {
     const int S = ctx->plan.S;
     hho_status s;
     if (ctx->nrec > 0) {
@@ -534,6 +536,13 @@ hho_status begin_steps(hho_ctx *ctx, double t0, double dt, int n_steps, std::vec
             ctx->h_ehist_cap = need;
         }
     }
+    return HHO_OK;
+}
+
+hho_status begin_steps(hho_ctx *ctx, double t0, double dt, int n_steps, std::vector<double> &E0, bool defer = false) {
+    const int S = ctx->plan.S;
+    hho_status s = reserve_steps(ctx, n_steps);
+    if (s != HHO_OK) return s;
     ctx->h_clock.t0 = t0;
     ctx->h_clock.dt = dt;
     ctx->h_clock.step = 0;
@@ -1585,6 +1594,19 @@ hho_status hho_receivers(hho_ctx *ctx, int32_t n, const double *xy, const int32_
         ctx->nrec = n;
         ctx->version++;
         return HHO_OK;
+    });
+}
+
+hho_status hho_reserve_steps(hho_ctx *ctx, int32_t n_steps) {
+    return guarded(ctx ? &const_cast<hho_ctx *>(ctx)->err : &g_setup_error, [&]() -> hho_status {
+        if (!ctx) return HHO_ERR_ARG;
+        if (n_steps < 0) {
+            ctx->err = "reserve_steps: n_steps >= 0 required";
+            return HHO_ERR_ARG;
+        }
+        hho_status s = set_device(ctx);
+        if (s != HHO_OK) return s;
+        return reserve_steps(ctx, n_steps);
     });
 }
 

@@ -68,6 +68,7 @@ EXPORTS = {
     "hho_set_loads": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "hho_receivers": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "hho_erk_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int32]),
+    "hho_reserve_steps": (C.c_int, [C.c_void_p, C.c_int32]),
     "hho_synchronize": (C.c_int, [C.c_void_p]),
     "hho_get_traces": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "hho_energy": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -319,6 +320,10 @@ class Engine:
         self._call(self.lib.hho_erk_step, float(t0), float(dt), int(n_steps))
         self.last_steps = int(n_steps)
 
+    def reserve_steps(self, n_steps):
+        """Size the receiver and energy histories for calls of up to n_steps (hho_reserve_steps)."""
+        self._call(self.lib.hho_reserve_steps, int(n_steps))
+
     def adjoint(self, t0, dt, n_steps, d_obs=None, ckpt_every=0):
         """Misfit J and dJ/d(materials) [n_cells, 3] by the discrete adjoint (hho_adjoint_step).
 
@@ -488,6 +493,11 @@ class Batch:
         if code != 0:
             msg = self.lib.hho_batch_last_error(self._h).decode()
             raise (Unstable if code == 6 else HHOError)(code, msg)
+
+    def reserve_steps(self, n_steps):
+        """hho_reserve_steps on every engine of the batch."""
+        for e in self.engines:
+            e.reserve_steps(n_steps)
 
     def last_time_ms(self):
         """Device time of the graph replays of the last erk_step call (HIP events), ms."""

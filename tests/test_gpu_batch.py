@@ -232,3 +232,37 @@ def test_every_tuning_combination(dtype, tol, k):
             assert err < tol
             assert dE < (1e-12 if dtype == "f64" else 1e-5)
     e.close()
+
+
+def test_reserve_steps_changes_no_result():
+    """hho_reserve_steps sizes the receiver and energy histories ahead of a call: a 70-step call
+    after a 5-step one (graphs captured before and after the reservation) gives the state, the
+    receiver traces and the energy history of an unreserved run, and of the oracle; a negative
+    count is rejected."""
+    from oracle import Oracle
+    from paper_2505_15771_amd import Engine, HHOError
+    say("case: reserve_steps, k=2 f64, 5 + 70 steps")
+    mesh = M.with_materials(M.unit_square(16, p_split=0.5, seed=41), perturb=0.1, seed=42)
+    o = Oracle(mesh, 2)
+    U0 = np.random.default_rng(43).standard_normal(o.ndof)
+    outs = []
+    for reserve in (0, 70):
+        e = Engine(mesh, 2, dtype="f64", record_energy=True)
+        e.set_receivers([[0.3, 0.75], [0.6, 0.3]], [0, 1])
+        e.set_state(U0)
+        dt = e.dt_cfl(0.5)
+        if reserve:
+            e.reserve_steps(reserve)
+            with pytest.raises(HHOError):
+                e.reserve_steps(-1)
+        e.erk_step(0.0, dt, 5)
+        e.erk_step(5 * dt, dt, 70)
+        outs.append((e.get_state(), e.traces(), e.energy_history()))
+        e.close()
+    ref = o.erk(U0, 0.0, dt, 75)
+    for U, tr, eh in outs:
+        assert rel(U, ref) < 1e-12
+        assert eh.shape[0] == 70 and np.all(np.isfinite(eh))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.allclose(outs[0][2], outs[1][2], rtol=1e-13, atol=0.0)
